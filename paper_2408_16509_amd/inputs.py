@@ -1,0 +1,272 @@
+"""Seeded synthetic inputs shared by the GPU path's tests/benchmark and the oracle's tests.
+
+This module holds no arithmetic of the Flux Reconstruction method itself: it only
+builds meshes (vertex coordinates and element connectivity of periodic boxes),
+draws seeded random numbers, and evaluates initial-condition formulas at
+coordinates the caller supplies.
+
+Meshes
+    * ``hex_box``: a structured periodic grid of 8-node hexahedra on a box, with
+      optional seeded vertex perturbation (periodic images move identically) and a
+      seeded permutation of the element order.
+    * ``kuhn_split``: each hexahedral cell cut into 6 tetrahedra sharing the cell's
+      main diagonal, which stays conforming between neighbouring cells.
+
+Node orders
+    Hexahedra use the VTK corner order, reference corners
+    (-1,-1,-1) (1,-1,-1) (1,1,-1) (-1,1,-1) (-1,-1,1) (1,-1,1) (1,1,1) (-1,1,1).
+    Tetrahedra list their 4 corners in the order of the reference tetrahedron
+    printed with the paper's tetrahedral point sets (Fig. mesh b,c):
+    (-1,-1,-1) (1,-1,-1) (-1,-1,1) (-1,1,-1).
+
+Initial conditions (evaluated at caller-given physical points)
+    * Taylor--Green vortex (Sec. "Accuracy", TGV initial-condition equations),
+      with the reference pressure chosen from the Mach number, p0 = 1/(gamma Ma^2).
+    * Planar Mach-3 shock at a seeded orientation over seeded density noise.
+    * Isentropic vortex (Shu) for convergence tests.
+    * Seeded random smooth/perturbed states for parity tests.
+"""
+from __future__ import annotations
+
+import itertools
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+HEX = 0
+TET = 1
+
+# Reference corners of the two element types (documented above).
+HEX_REF_CORNERS = np.array(
+    [[-1, -1, -1], [1, -1, -1], [1, 1, -1], [-1, 1, -1],
+     [-1, -1, 1], [1, -1, 1], [1, 1, 1], [-1, 1, 1]], dtype=np.float64)
+TET_REF_CORNERS = np.array(
+    [[-1, -1, -1], [1, -1, -1], [-1, -1, 1], [-1, 1, -1]], dtype=np.float64)
+
+
+@dataclass
+class Mesh:
+    """A mixed mesh: vertices, element types and corner lists (padded to 8 with -1)."""
+    xyz: np.ndarray            # [n_vert][3] float64
+    etype: np.ndarray          # [n_elem] int32 (HEX or TET)
+    enodes: np.ndarray         # [n_elem][8] int64, tets use the first 4
+    period: np.ndarray         # [3] float64 box lengths (0 = not periodic)
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_elem(self) -> int:
+        return int(self.etype.shape[0])
+
+    def n_of(self, t: int) -> int:
+        return int(np.count_nonzero(self.etype == t))
+
+    def corners(self, idx) -> np.ndarray:
+        """Corner coordinates [len(idx)][n_corner][3] of elements `idx` (one type)."""
+        idx = np.asarray(idx)
+        t = int(self.etype[idx[0]]) if idx.size else HEX
+        nc = 8 if t == HEX else 4
+        return self.xyz[self.enodes[idx, :nc]]
+
+
+def _grid_vertices(n, lo, hi, perturb, seed):
+    nx, ny, nz = n
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+    h = (hi - lo) / np.array([nx, ny, nz], dtype=np.float64)
+    # canonical (periodic) vertex lattice [k][j][i][3]
+    kk, jj, ii = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    canon = np.stack([lo[0] + ii * h[0], lo[1] + jj * h[1], lo[2] + kk * h[2]], axis=-1)
+    if perturb:
+        rng = np.random.default_rng(seed)
+        canon = canon + rng.uniform(-perturb, perturb, size=canon.shape) * h
+    # full lattice with periodic images on the upper faces
+    K, J, I = np.meshgrid(np.arange(nz + 1), np.arange(ny + 1), np.arange(nx + 1), indexing="ij")
+    xyz = canon[K % nz, J % ny, I % nx].copy()
+    xyz[..., 0] += (I // nx) * (hi[0] - lo[0])
+    xyz[..., 1] += (J // ny) * (hi[1] - lo[1])
+    xyz[..., 2] += (K // nz) * (hi[2] - lo[2])
+    return xyz.reshape(-1, 3), h
+
+
+def _vid(i, j, k, n):
+    nx, ny, _ = n
+    return (k * (ny + 1) + j) * (nx + 1) + i
+
+
+def hex_box(n=(4, 4, 4), lo=(-math.pi,) * 3, hi=(math.pi,) * 3, perturb=0.0,
+            perturb_seed=None, permute_seed=None) -> Mesh:
+    """Periodic box of nx*ny*nz hexahedra (VTK corner order).
+
+    perturb: each canonical vertex coordinate moves by U(-perturb, perturb) * h,
+    drawn with numpy PCG64(perturb_seed) in C order of the canonical lattice
+    [k][j][i][3]; periodic images move identically.
+    permute_seed: if given, element order is PCG64(permute_seed).permutation.
+    """
+    n = tuple(int(v) for v in n)
+    xyz, h = _grid_vertices(n, lo, hi, perturb, perturb_seed)
+    nx, ny, nz = n
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    i, j, k = i.ravel(), j.ravel(), k.ravel()
+    corners = [(0, 0, 0), (1, 0, 0), (1, 1, 0), (0, 1, 0),
+               (0, 0, 1), (1, 0, 1), (1, 1, 1), (0, 1, 1)]
+    en = np.stack([_vid(i + a, j + b, k + c, n) for a, b, c in corners], axis=1).astype(np.int64)
+    if permute_seed is not None:
+        perm = np.random.default_rng(permute_seed).permutation(en.shape[0])
+        en = en[perm]
+    etype = np.full(en.shape[0], HEX, dtype=np.int32)
+    period = np.asarray(hi, dtype=np.float64) - np.asarray(lo, dtype=np.float64)
+    return Mesh(xyz, etype, en, period, {"n": n, "h": h, "kind": "hex_box"})
+
+
+def _tet_signed_volume(c):
+    a = c[..., 1, :] - c[..., 0, :]
+    b = c[..., 3, :] - c[..., 0, :]
+    d = c[..., 2, :] - c[..., 0, :]
+    # reference axes: corner1-corner0 = 2e_x, corner3-corner0 = 2e_y, corner2-corner0 = 2e_z
+    return np.einsum("...i,...i->...", a, np.cross(b, d))
+
+
+def kuhn_split(mesh: Mesh, permute_seed=None) -> Mesh:
+    """Cut every hexahedron into 6 tetrahedra around its corner0-corner6 diagonal.
+
+    For each ordering (a, b, c) of the three axes the tetrahedron is the path
+    corner0 -> +e_a -> +e_a+e_b -> corner6.  All cells use the same diagonal, so
+    the split is conforming between neighbouring cells, including across the
+    periodic boundaries.  Corner order is fixed up so the affine map has J > 0.
+    """
+    # VTK corner index from (dx, dy, dz) bits
+    bit = {(0, 0, 0): 0, (1, 0, 0): 1, (1, 1, 0): 2, (0, 1, 0): 3,
+           (0, 0, 1): 4, (1, 0, 1): 5, (1, 1, 1): 6, (0, 1, 1): 7}
+    tets_local = []
+    for perm in itertools.permutations(range(3)):
+        p = [0, 0, 0]
+        path = [bit[tuple(p)]]
+        for ax in perm:
+            p[ax] = 1
+            path.append(bit[tuple(p)])
+        tets_local.append(path)
+    tets_local = np.array(tets_local)            # [6][4]
+    hexes = mesh.enodes[mesh.etype == HEX, :8]
+    tn = hexes[:, tets_local].reshape(-1, 4)     # [6*nh][4]
+    vol = _tet_signed_volume(mesh.xyz[tn])
+    neg = vol < 0
+    tn[neg] = tn[neg][:, [0, 2, 1, 3]]           # swap two corners to flip orientation
+    if permute_seed is not None:
+        tn = tn[np.random.default_rng(permute_seed).permutation(tn.shape[0])]
+    en = np.full((tn.shape[0], 8), -1, dtype=np.int64)
+    en[:, :4] = tn
+    etype = np.full(tn.shape[0], TET, dtype=np.int32)
+    meta = dict(mesh.meta)
+    meta["kind"] = "kuhn"
+    return Mesh(mesh.xyz.copy(), etype, en, mesh.period.copy(), meta)
+
+
+def concat(meshes, permute_seed=None) -> Mesh:
+    """Several meshes in one element list (they must not share faces)."""
+    xyz, en, et = [], [], []
+    off = 0
+    for m in meshes:
+        xyz.append(m.xyz)
+        e = m.enodes.copy()
+        e[e >= 0] += off
+        en.append(e)
+        et.append(m.etype)
+        off += m.xyz.shape[0]
+    en = np.concatenate(en)
+    et = np.concatenate(et)
+    if permute_seed is not None:
+        perm = np.random.default_rng(permute_seed).permutation(en.shape[0])
+        en, et = en[perm], et[perm]
+    return Mesh(np.concatenate(xyz), et, en, meshes[0].period.copy(), {"kind": "concat"})
+
+
+# ----------------------------------------------------------------------------------
+# Initial conditions.  All take physical coordinates x,y,z (any equal shapes) and
+# return conservative variables stacked on a new leading axis of length 5:
+# (rho, rho*u, rho*v, rho*w, E).
+# ----------------------------------------------------------------------------------
+
+def prim_to_cons(rho, u, v, w, p, gamma=1.4):
+    E = p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v + w * w)
+    return np.stack([rho, rho * u, rho * v, rho * w, E])
+
+
+def tgv(x, y, z, mach=0.1, gamma=1.4):
+    """Taylor--Green vortex with unit velocity/length/density scales, p0 = 1/(gamma Ma^2)."""
+    p0 = 1.0 / (gamma * mach * mach)
+    u = np.sin(x) * np.cos(y) * np.cos(z)
+    v = -np.cos(x) * np.sin(y) * np.cos(z)
+    w = np.zeros_like(u)
+    p = p0 + (np.cos(2 * x) + np.cos(2 * y)) * (2.0 + np.cos(2 * z)) / 16.0
+    rho = p / p0
+    return prim_to_cons(rho, u, v, w, p, gamma)
+
+
+SHOCK_MACH = 3.0
+
+
+def shock_normal(seed=41):
+    v = np.random.default_rng(seed).normal(size=3)
+    return v / np.linalg.norm(v)
+
+
+def shock_states(gamma=1.4, ms=SHOCK_MACH):
+    """Pre/post states of a normal shock moving into gas at rest (rho=1, p=1)."""
+    g = gamma
+    r2 = (g + 1) * ms * ms / ((g - 1) * ms * ms + 2)
+    p2 = 1.0 + 2 * g / (g + 1) * (ms * ms - 1)
+    c1 = math.sqrt(g)
+    u2 = ms * c1 * (1.0 - 1.0 / r2)
+    return (1.0, 1.0), (r2, p2, u2)
+
+
+def shock(x, y, z, gamma=1.4, orient_seed=41, noise_seed=42, noise=0.05):
+    """Planar Mach-3 shock through the origin at a seeded orientation.
+
+    Upstream (n.x > 0): rho = 1 + noise*U(-1,1) i.i.d. per point (PCG64(noise_seed),
+    drawn in the C order of the coordinate arrays), v = 0, p = 1.
+    Downstream: Rankine--Hugoniot state moving along n.
+    """
+    nvec = shock_normal(orient_seed)
+    s = nvec[0] * x + nvec[1] * y + nvec[2] * z
+    (_, _), (r2, p2, u2) = shock_states(gamma)
+    rng = np.random.default_rng(noise_seed)
+    rho1 = 1.0 + noise * rng.uniform(-1.0, 1.0, size=np.shape(x))
+    pre = s > 0
+    rho = np.where(pre, rho1, r2)
+    p = np.where(pre, 1.0, p2)
+    vel = np.where(pre, 0.0, u2)
+    return prim_to_cons(rho, vel * nvec[0], vel * nvec[1], vel * nvec[2], p, gamma)
+
+
+def isentropic_vortex(x, y, z, t=0.0, eps=5.0, u0=1.0, v0=0.0, gamma=1.4, period=20.0):
+    """Shu's isentropic vortex centred at the origin, convected by (u0, v0) for time t.
+
+    The nearest periodic image (period in x and y) of the vortex centre is used.
+    """
+    xc = u0 * t
+    yc = v0 * t
+    dx = x - xc
+    dy = y - yc
+    dx = dx - period * np.round(dx / period)
+    dy = dy - period * np.round(dy / period)
+    r2 = dx * dx + dy * dy
+    f = np.exp(0.5 * (1.0 - r2))
+    du = -eps / (2 * math.pi) * f * dy
+    dv = eps / (2 * math.pi) * f * dx
+    T = 1.0 - (gamma - 1.0) * eps * eps / (8 * gamma * math.pi * math.pi) * f * f
+    rho = T ** (1.0 / (gamma - 1.0))
+    p = rho ** gamma
+    return prim_to_cons(rho, u0 + du, v0 + dv, np.zeros_like(x), p, gamma)
+
+
+def random_state(shape, seed, rho0=1.0, p0=1.0, vel=0.5, amp=0.1, gamma=1.4):
+    """Seeded random positive state: rho, p = base*(1 + amp*U(-1,1)), velocity U(-vel, vel)."""
+    rng = np.random.default_rng(seed)
+    rho = rho0 * (1.0 + amp * rng.uniform(-1, 1, size=shape))
+    u = vel * rng.uniform(-1, 1, size=shape)
+    v = vel * rng.uniform(-1, 1, size=shape)
+    w = vel * rng.uniform(-1, 1, size=shape)
+    p = p0 * (1.0 + amp * rng.uniform(-1, 1, size=shape))
+    return prim_to_cons(rho, u, v, w, p, gamma)

@@ -1,0 +1,629 @@
+// Host-side setup: element operators, periodic connectivity, geometry.
+//
+// Hexahedra (order p): Gauss--Legendre solution points and tensor face flux points;
+// nodal Lagrange basis (barycentric form); DG correction functions of Huynh (the
+// paper's FR reference), i.e. derivatives of the right/left Radau polynomials
+// (P_{p+1} +- P_p)/2 folded into the 1-D derivative operator:
+//     div along a line = Dh f + cp F_plus + cm F_minus,
+//     Dh = D - gR' l(+1)^T - gL' l(-1)^T,  cp = gR',  cm = -gL'.
+// Tetrahedra (order 4): the 35 alpha-optimised points printed in Fig. mesh(c);
+// flux points are the surface solution points (Fig. mesh(b)), so interpolation is
+// a gather; the correction is the DG lifting M^{-1} E with exact simplex integrals.
+// All setup linear algebra is done in long double.
+#include "setup.hpp"
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <map>
+#include <unordered_map>
+
+namespace frmi {
+
+using ld = long double;
+
+// ------------------------------------------------------------------ 1-D tools
+static void legendre_and_deriv(int n, ld x, ld& P, ld& dP) {
+  // three-term recurrence for P_k and P_k'
+  ld p0 = 1, p1 = x, d0 = 0, d1 = 1;
+  if (n == 0) { P = 1; dP = 0; return; }
+  for (int k = 1; k < n; ++k) {
+    ld p2 = ((2 * k + 1) * x * p1 - k * p0) / (k + 1);
+    ld d2 = d0 + (2 * k + 1) * p1;        // P'_{k+1} = P'_{k-1} + (2k+1) P_k
+    p0 = p1; p1 = p2; d0 = d1; d1 = d2;
+  }
+  P = p1; dP = d1;
+}
+
+static void gauss_legendre(int n, ld* x, ld* w) {
+  const ld pi = 3.141592653589793238462643383279502884L;
+  for (int i = 0; i < n; ++i) {
+    ld z = std::cos(pi * (i + 0.75L) / (n + 0.5L));
+    for (int it = 0; it < 100; ++it) {
+      ld P, dP;
+      legendre_and_deriv(n, z, P, dP);
+      ld dz = P / dP;
+      z -= dz;
+      if (std::fabs(dz) < 1e-19L) break;
+    }
+    ld P, dP;
+    legendre_and_deriv(n, z, P, dP);
+    x[n - 1 - i] = z;                       // increasing order
+    w[n - 1 - i] = 2 / ((1 - z * z) * dP * dP);
+  }
+}
+
+void build_hex_ops(int p, HexOps& o) {
+  o = HexOps();
+  o.p = p; o.n1 = p + 1; o.nsp = o.n1 * o.n1 * o.n1; o.nfpf = o.n1 * o.n1; o.nfp = 6 * o.nfpf;
+  const int n = o.n1;
+  ld x[kMaxP + 1], w[kMaxP + 1], bw[kMaxP + 1];
+  gauss_legendre(n, x, w);
+  for (int j = 0; j < n; ++j) {                // barycentric weights
+    bw[j] = 1;
+    for (int m = 0; m < n; ++m) if (m != j) bw[j] /= (x[j] - x[m]);
+  }
+  for (int side = 0; side < 2; ++side) {      // l_j(-1), l_j(+1)
+    ld y = side ? 1.0L : -1.0L, den = 0;
+    for (int m = 0; m < n; ++m) den += bw[m] / (y - x[m]);
+    for (int j = 0; j < n; ++j) (side ? o.lp : o.lm)[j] = (double)(bw[j] / (y - x[j]) / den);
+  }
+  ld D[kMaxP + 1][kMaxP + 1] = {};
+  for (int a = 0; a < n; ++a) {
+    ld s = 0;
+    for (int b = 0; b < n; ++b) if (b != a) { D[a][b] = bw[b] / bw[a] / (x[a] - x[b]); s += D[a][b]; }
+    D[a][a] = -s;
+  }
+  for (int a = 0; a < n; ++a) {
+    ld P1, dP1, P0, dP0;
+    legendre_and_deriv(p + 1, x[a], P1, dP1);
+    legendre_and_deriv(p, x[a], P0, dP0);
+    ld gR = 0.5L * (dP1 + dP0);
+    ld gL = 0.5L * ((p % 2 == 0) ? -1.0L : 1.0L) * (dP1 - dP0);
+    o.cp[a] = (double)gR;
+    o.cm[a] = (double)(-gL);
+    o.x[a] = (double)x[a];
+    o.w[a] = (double)w[a];
+    for (int b = 0; b < n; ++b) {
+      o.D[a][b] = (double)D[a][b];
+      ld lpb = bw[b], lmb = bw[b];
+      (void)lpb; (void)lmb;
+    }
+  }
+  // fold the correction into the derivative (long double)
+  ld lp[kMaxP + 1], lm[kMaxP + 1];
+  for (int side = 0; side < 2; ++side) {
+    ld y = side ? 1.0L : -1.0L, den = 0;
+    for (int m = 0; m < n; ++m) den += bw[m] / (y - x[m]);
+    for (int j = 0; j < n; ++j) (side ? lp : lm)[j] = bw[j] / (y - x[j]) / den;
+  }
+  for (int a = 0; a < n; ++a) {
+    ld P1, dP1, P0, dP0;
+    legendre_and_deriv(p + 1, x[a], P1, dP1);
+    legendre_and_deriv(p, x[a], P0, dP0);
+    ld gR = 0.5L * (dP1 + dP0);
+    ld gL = 0.5L * ((p % 2 == 0) ? -1.0L : 1.0L) * (dP1 - dP0);
+    for (int b = 0; b < n; ++b) o.Dh[a][b] = (double)(D[a][b] - gR * lp[b] - gL * lm[b]);
+  }
+  // orthonormal Legendre Vandermonde and its inverse V^T W (Gauss rule exact)
+  for (int a = 0; a < n; ++a)
+    for (int m = 0; m < n; ++m) {
+      ld P, dP;
+      legendre_and_deriv(m, x[a], P, dP);
+      ld v = std::sqrt((2 * m + 1) / 2.0L) * P;
+      o.Vm[a][m] = (double)v;
+      o.Vmi[m][a] = (double)(v * w[a]);
+    }
+}
+
+// ------------------------------------------------------------------ tetrahedron
+// Fig. mesh(c): fourth-order alpha-optimised solution points (printed order).
+static const double kA = 0.654653670707977, kB = 0.551583572090994, kC = 0.103167144181987;
+static const double kTetPts[35][3] = {
+    {-1, -1, -1}, {-kA, -1, -1}, {0, -1, -1}, {kA, -1, -1}, {1, -1, -1},
+    {-1, -kA, -1}, {-kB, -kB, -1}, {kC, -kB, -1}, {kA, -kA, -1}, {-1, 0, -1},
+    {-kB, kC, -1}, {0, 0, -1}, {-1, kA, -1}, {-kA, kA, -1}, {-1, 1, -1},
+    {-1, -1, -kA}, {-kB, -1, -kB}, {kC, -1, -kB}, {kA, -1, -kA}, {-1, -kB, -kB},
+    {-0.5, -0.5, -0.5}, {kC, -kB, -kB}, {-1, kC, -kB}, {-kB, kC, -kB}, {-1, kA, -kA},
+    {-1, -1, 0}, {-kB, -1, kC}, {0, -1, 0}, {-1, -kB, kC}, {-kB, -kB, kC},
+    {-1, 0, 0}, {-1, -1, kA}, {-kA, -1, kA}, {-1, -kA, kA}, {-1, -1, 1}};
+// reference corners and faces (corner triples), outward unit normals
+static const double kTetCorner[4][3] = {{-1, -1, -1}, {1, -1, -1}, {-1, -1, 1}, {-1, 1, -1}};
+static const int kTetFace[4][3] = {{0, 1, 3}, {0, 1, 2}, {0, 2, 3}, {1, 2, 3}};
+
+static ld factorial(int n) { ld r = 1; for (int i = 2; i <= n; ++i) r *= i; return r; }
+
+template <int N>
+static bool invert(ld (&A)[N][N], int n) {      // Gauss--Jordan, partial pivoting, in place
+  int piv[N];
+  ld B[N][N];
+  for (int i = 0; i < n; ++i) for (int j = 0; j < n; ++j) B[i][j] = (i == j);
+  for (int c = 0; c < n; ++c) {
+    int r = c;
+    for (int i = c + 1; i < n; ++i) if (std::fabs(A[i][c]) > std::fabs(A[r][c])) r = i;
+    if (std::fabs(A[r][c]) < 1e-300L) return false;
+    piv[c] = r;
+    for (int j = 0; j < n; ++j) { std::swap(A[c][j], A[r][j]); std::swap(B[c][j], B[r][j]); }
+    ld d = A[c][c];
+    for (int j = 0; j < n; ++j) { A[c][j] /= d; B[c][j] /= d; }
+    for (int i = 0; i < n; ++i) if (i != c) {
+      ld f = A[i][c];
+      if (f == 0) continue;
+      for (int j = 0; j < n; ++j) { A[i][j] -= f * A[c][j]; B[i][j] -= f * B[c][j]; }
+    }
+  }
+  (void)piv;
+  for (int i = 0; i < n; ++i) for (int j = 0; j < n; ++j) A[i][j] = B[i][j];
+  return true;
+}
+
+// normalised Jacobi polynomial P_n^{(a,0)} (orthonormal with weight (1-x)^a on [-1,1])
+static ld jacobi(ld x, int alpha, int n) {
+  const ld a = alpha, b = 0;
+  std::vector<ld> P(n + 1);
+  ld g0 = std::pow(2.0L, a + b + 1) / (a + b + 1) * std::tgamma(a + 1) * std::tgamma(b + 1) / std::tgamma(a + b + 1);
+  P[0] = 1 / std::sqrt(g0);
+  if (n == 0) return P[0];
+  ld g1 = (a + 1) * (b + 1) / (a + b + 3) * g0;
+  P[1] = ((a + b + 2) * x / 2 + (a - b) / 2) / std::sqrt(g1);
+  ld aold = 2 / (2 + a + b) * std::sqrt((a + 1) * (b + 1) / (a + b + 3));
+  for (int i = 1; i < n; ++i) {
+    ld h1 = 2 * i + a + b;
+    ld anew = 2 / (h1 + 2) * std::sqrt((i + 1) * (i + 1 + a + b) * (i + 1 + a) * (i + 1 + b) / (h1 + 1) / (h1 + 3));
+    ld bnew = -(a * a - b * b) / h1 / (h1 + 2);
+    P[i + 1] = 1 / anew * (-aold * P[i - 1] + (x - bnew) * P[i]);
+    aold = anew;
+  }
+  return P[n];
+}
+
+// orthonormal modal basis of P_4 on the reference tet in collapsed coordinates
+static ld pkd(const double* X, int i, int j, int k) {
+  ld r = X[0], s = X[1], t = X[2];
+  ld a = (std::fabs(s + t) > 1e-14L) ? 2 * (1 + r) / (-s - t) - 1 : -1;
+  ld b = (std::fabs(t - 1) > 1e-14L) ? 2 * (1 + s) / (1 - t) - 1 : -1;
+  ld c = t;
+  return 2 * std::sqrt(2.0L) * jacobi(a, 0, i) * jacobi(b, 2 * i + 1, j) * std::pow(1 - b, i) *
+         jacobi(c, 2 * (i + j) + 2, k) * std::pow(1 - c, i + j);
+}
+
+void build_tet_ops(TetOps& o) {
+  constexpr int N = TetOps::nsp;
+  for (int z = 0; z < N; ++z) for (int d = 0; d < 3; ++d) o.pts[z][d] = kTetPts[z][d];
+  // faces and flux points (face-local order: ascending solution point index)
+  int f_idx = 0;
+  for (int f = 0; f < 4; ++f) {
+    const double* A = kTetCorner[kTetFace[f][0]];
+    const double* B = kTetCorner[kTetFace[f][1]];
+    const double* C = kTetCorner[kTetFace[f][2]];
+    double e1[3], e2[3], nv[3];
+    for (int d = 0; d < 3; ++d) { e1[d] = B[d] - A[d]; e2[d] = C[d] - A[d]; }
+    nv[0] = e1[1] * e2[2] - e1[2] * e2[1];
+    nv[1] = e1[2] * e2[0] - e1[0] * e2[2];
+    nv[2] = e1[0] * e2[1] - e1[1] * e2[0];
+    double nn = std::sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+    // orient outward: away from the centroid (-1/2,-1/2,-1/2)
+    double dotc = 0;
+    for (int d = 0; d < 3; ++d) dotc += nv[d] * (A[d] + 0.5);
+    double sg = dotc > 0 ? 1.0 : -1.0;
+    for (int d = 0; d < 3; ++d) o.nref[f][d] = sg * nv[d] / nn;
+    for (int z = 0; z < N; ++z) {
+      double dist = 0;
+      for (int d = 0; d < 3; ++d) dist += (o.pts[z][d] - A[d]) * o.nref[f][d];
+      if (std::fabs(dist) < 1e-12) { o.fp_src[f_idx] = z; o.fp_face[f_idx] = f; ++f_idx; }
+    }
+  }
+  // monomials u^a v^b w^c of total degree <= 4 in unit-simplex coordinates u = (xi+1)/2
+  std::vector<std::array<int, 3>> ex;
+  for (int dsum = 0; dsum <= 4; ++dsum)
+    for (int c = 0; c <= dsum; ++c)
+      for (int b = 0; b <= dsum - c; ++b) ex.push_back({dsum - b - c, b, c});
+  auto mono = [&](const double* X, int m) {
+    ld u = (X[0] + 1) / 2, v = (X[1] + 1) / 2, w = (X[2] + 1) / 2;
+    return std::pow(u, ex[m][0]) * std::pow(v, ex[m][1]) * std::pow(w, ex[m][2]);
+  };
+  auto dmono = [&](const double* X, int m, int d) {   // d/dxi_d = 1/2 d/du_d
+    ld uu[3] = {(X[0] + 1) / 2.0L, (X[1] + 1) / 2.0L, (X[2] + 1) / 2.0L};
+    int e = ex[m][d];
+    if (e == 0) return (ld)0;
+    ld r = 0.5L * e;
+    for (int q = 0; q < 3; ++q) r *= std::pow(uu[q], q == d ? e - 1 : ex[m][q]);
+    return r;
+  };
+  static ld Vm[N][N];
+  for (int z = 0; z < N; ++z) for (int m = 0; m < N; ++m) Vm[z][m] = mono(o.pts[z], m);
+  invert(Vm, N);                                  // C[m][j]: l_j = sum_m C[m][j] mono_m
+  static ld Cm[N][N];
+  for (int m = 0; m < N; ++m) for (int j = 0; j < N; ++j) Cm[m][j] = Vm[m][j];
+  for (int d = 0; d < 3; ++d)
+    for (int z = 0; z < N; ++z)
+      for (int j = 0; j < N; ++j) {
+        ld s = 0;
+        for (int m = 0; m < N; ++m) s += dmono(o.pts[z], m, d) * Cm[m][j];
+        o.D[d][z][j] = (double)s;
+      }
+  // exact simplex integrals (reference tet = 8 x unit simplex)
+  auto simplex = [&](int a, int b, int c) { return 8 * factorial(a) * factorial(b) * factorial(c) / factorial(a + b + c + 3); };
+  static ld M[N][N];
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) {
+      ld s = 0;
+      for (int m = 0; m < N; ++m)
+        for (int q = 0; q < N; ++q)
+          s += Cm[m][i] * Cm[q][j] * simplex(ex[m][0] + ex[q][0], ex[m][1] + ex[q][1], ex[m][2] + ex[q][2]);
+      M[i][j] = s;
+    }
+  for (int j = 0; j < N; ++j) {
+    ld s = 0;
+    for (int m = 0; m < N; ++m) s += Cm[m][j] * simplex(ex[m][0], ex[m][1], ex[m][2]);
+    o.weights[j] = (double)s;
+  }
+  // face mass matrices: E[src(q)][sigma(r)] = int_face phi_q phi_r dS
+  static ld E[N][TetOps::nfp];
+  for (int i = 0; i < N; ++i) for (int s = 0; s < TetOps::nfp; ++s) E[i][s] = 0;
+  std::vector<std::array<int, 2>> ex2;
+  for (int dsum = 0; dsum <= 4; ++dsum) for (int a = 0; a <= dsum; ++a) ex2.push_back({a, dsum - a});
+  for (int f = 0; f < 4; ++f) {
+    const double* A = kTetCorner[kTetFace[f][0]];
+    const double* B = kTetCorner[kTetFace[f][1]];
+    const double* C = kTetCorner[kTetFace[f][2]];
+    ld e1[3], e2[3];
+    for (int d = 0; d < 3; ++d) { e1[d] = B[d] - A[d]; e2[d] = C[d] - A[d]; }
+    ld cx = e1[1] * e2[2] - e1[2] * e2[1], cy = e1[2] * e2[0] - e1[0] * e2[2], cz = e1[0] * e2[1] - e1[1] * e2[0];
+    ld dA = std::sqrt(cx * cx + cy * cy + cz * cz);
+    int ids[15], nq = 0;
+    for (int s = 0; s < TetOps::nfp; ++s) if (o.fp_face[s] == f) ids[nq++] = s;
+    // (s, t) face coordinates of the points: solve A + s e1 + t e2 = x by least squares (exact)
+    ld st[15][2];
+    ld g11 = 0, g12 = 0, g22 = 0;
+    for (int d = 0; d < 3; ++d) { g11 += e1[d] * e1[d]; g12 += e1[d] * e2[d]; g22 += e2[d] * e2[d]; }
+    ld det = g11 * g22 - g12 * g12;
+    for (int q = 0; q < 15; ++q) {
+      const double* X = o.pts[o.fp_src[ids[q]]];
+      ld r1 = 0, r2 = 0;
+      for (int d = 0; d < 3; ++d) { r1 += (X[d] - A[d]) * e1[d]; r2 += (X[d] - A[d]) * e2[d]; }
+      st[q][0] = (g22 * r1 - g12 * r2) / det;
+      st[q][1] = (g11 * r2 - g12 * r1) / det;
+    }
+    static ld Vf[15][15];
+    for (int q = 0; q < 15; ++q)
+      for (int m = 0; m < 15; ++m) Vf[q][m] = std::pow(st[q][0], ex2[m][0]) * std::pow(st[q][1], ex2[m][1]);
+    invert(Vf, 15);
+    for (int q = 0; q < 15; ++q)
+      for (int r = 0; r < 15; ++r) {
+        ld s = 0;
+        for (int m = 0; m < 15; ++m)
+          for (int n2 = 0; n2 < 15; ++n2) {
+            int a = ex2[m][0] + ex2[n2][0], b = ex2[m][1] + ex2[n2][1];
+            s += Vf[m][q] * Vf[n2][r] * factorial(a) * factorial(b) / factorial(a + b + 2);
+          }
+        E[o.fp_src[ids[q]]][ids[r]] = dA * s;
+      }
+  }
+  invert(M, N);
+  for (int i = 0; i < N; ++i)
+    for (int s = 0; s < TetOps::nfp; ++s) {
+      ld acc = 0;
+      for (int j = 0; j < N; ++j) acc += M[i][j] * E[j][s];
+      o.lift[i][s] = (double)acc;
+    }
+  // orthonormal modal basis (graded by total degree)
+  int m = 0;
+  static ld Vp[N][N];
+  for (int dsum = 0; dsum <= 4; ++dsum)
+    for (int i = 0; i <= dsum; ++i)
+      for (int j = 0; j <= dsum - i; ++j) {
+        int k = dsum - i - j;
+        for (int z = 0; z < N; ++z) Vp[z][m] = pkd(o.pts[z], i, j, k);
+        o.deg[m] = dsum;
+        ++m;
+      }
+  for (int z = 0; z < N; ++z) for (int q = 0; q < N; ++q) o.V[z][q] = (double)Vp[z][q];
+  invert(Vp, N);
+  for (int z = 0; z < N; ++z) for (int q = 0; q < N; ++q) o.Vinv[z][q] = (double)Vp[z][q];
+}
+
+// ------------------------------------------------------------------ geometry
+// Hexahedra: x(xi) = sum_S c_S prod_{d in S} xi_d over the 8 subsets S of {0,1,2}
+// (trilinear map of the VTK corners); coefficients stored as geo[comp*8 + S].
+static const int kHexCorner[8][3] = {{-1, -1, -1}, {1, -1, -1}, {1, 1, -1}, {-1, 1, -1},
+                                     {-1, -1, 1}, {1, -1, 1}, {1, 1, 1}, {-1, 1, 1}};
+static const int kSubset[8] = {0, 1, 2, 4, 3, 5, 6, 7};   // S index -> bitmask: {},{0},{1},{2},{01},{02},{12},{012}
+
+static void hex_coeffs(const double X[8][3], double c[24]) {
+  for (int comp = 0; comp < 3; ++comp)
+    for (int s = 0; s < 8; ++s) {
+      int mask = kSubset[s];
+      ld acc = 0;
+      for (int n = 0; n < 8; ++n) {
+        ld f = 1;
+        for (int d = 0; d < 3; ++d) if (mask >> d & 1) f *= kHexCorner[n][d];
+        acc += f * X[n][comp];
+      }
+      c[comp * 8 + s] = (double)(acc / 8);
+    }
+}
+
+static void hex_map(const double c[24], const double xi[3], double x[3], double g[3][3]) {
+  // g[k] = d x / d xi_k (column k of G)
+  const double a = xi[0], b = xi[1], d = xi[2];
+  for (int comp = 0; comp < 3; ++comp) {
+    const double* q = c + comp * 8;
+    x[comp] = q[0] + q[1] * a + q[2] * b + q[3] * d + q[4] * a * b + q[5] * a * d + q[6] * b * d + q[7] * a * b * d;
+    g[0][comp] = q[1] + q[4] * b + q[5] * d + q[7] * b * d;
+    g[1][comp] = q[2] + q[4] * a + q[6] * d + q[7] * a * d;
+    g[2][comp] = q[3] + q[5] * a + q[6] * b + q[7] * a * b;
+  }
+}
+
+static void cross(const double* u, const double* v, double* w) {
+  w[0] = u[1] * v[2] - u[2] * v[1];
+  w[1] = u[2] * v[0] - u[0] * v[2];
+  w[2] = u[0] * v[1] - u[1] * v[0];
+}
+
+// reference points of hex flux points: face f = 2d + s, local q = t0 + n1 t1 over the
+// two tangential axes in increasing order
+static void hex_fp_ref(const HexOps& o, int f, int q, double xi[3]) {
+  int d = f / 2, s = f % 2;
+  int ta = (d == 0) ? 1 : 0, tb = (d == 2) ? 1 : 2;
+  xi[d] = s ? 1.0 : -1.0;
+  xi[ta] = o.x[q % o.n1];
+  xi[tb] = o.x[q / o.n1];
+}
+
+// ------------------------------------------------------------------ connectivity
+struct Key {
+  int64_t k[3];
+  bool operator==(const Key& o) const { return k[0] == o.k[0] && k[1] == o.k[1] && k[2] == o.k[2]; }
+};
+struct KeyHash {
+  size_t operator()(const Key& a) const {
+    uint64_t h = 1469598103934665603ULL;
+    for (int i = 0; i < 3; ++i) { h ^= (uint64_t)a.k[i] + 0x9e3779b97f4a7c15ULL + (h << 6) + (h >> 2); }
+    return (size_t)h;
+  }
+};
+
+std::string build_setup(int order, int64_t n_vert, const double* xyz, const double* period,
+                        int64_t n_elem, const int32_t* etype, const int64_t* enodes,
+                        int e_align, Setup& out, int& code) {
+  code = 0;
+  out = Setup();
+  if (order < 1 || order > kMaxP) { code = 3; return "hexahedra support orders 1..4"; }
+  bool has[2] = {false, false};
+  for (int64_t e = 0; e < n_elem; ++e) {
+    if (etype[e] != kHex && etype[e] != kTet) { code = 1; return "unknown element type"; }
+    has[etype[e]] = true;
+    int nc = etype[e] == kHex ? 8 : 4;
+    for (int c = 0; c < nc; ++c)
+      if (enodes[e * 8 + c] < 0 || enodes[e * 8 + c] >= n_vert) { code = 1; return "corner index out of range"; }
+  }
+  if (has[kTet] && order != 4) { code = 3; return "tetrahedra are supported at order 4 only (the paper's point set)"; }
+  build_hex_ops(order, out.hex);
+  if (has[kTet]) build_tet_ops(out.tet);
+  const HexOps& H = out.hex;
+  const TetOps& T = out.tet;
+  // blocks
+  int bidx[2] = {-1, -1};
+  for (int t = 0; t < 2; ++t) if (has[t]) {
+    Block b;
+    b.etype = t;
+    for (int64_t e = 0; e < n_elem; ++e) if (etype[e] == t) b.elems.push_back(e);
+    b.n = (int64_t)b.elems.size();
+    b.e_pad = (b.n + e_align - 1) / e_align * e_align;
+    b.nsp = t == kHex ? H.nsp : T.nsp;
+    b.nfp = t == kHex ? H.nfp : T.nfp;
+    b.nfaces = t == kHex ? 6 : 4;
+    b.nfpf = t == kHex ? H.nfpf : T.nfpf;
+    b.ngeo = t == kHex ? 24 : 10;
+    b.geo.assign((size_t)b.ngeo * b.e_pad, 0.0);
+    b.nbr_elem.assign((size_t)b.nfaces * b.e_pad, 0);
+    b.nbr_info.assign((size_t)b.nfaces * b.e_pad, -1);
+    b.sol_xyz.assign((size_t)b.n * b.nsp * 3, 0.0);
+    bidx[t] = (int)out.blocks.size();
+    out.blocks.push_back(std::move(b));
+  }
+  // ---- geometry, Jacobian check, solution points
+  for (auto& b : out.blocks) {
+    for (int64_t le = 0; le < b.e_pad; ++le) {
+      int64_t e = b.elems[le < b.n ? le : 0];
+      if (b.etype == kHex) {
+        double X[8][3], c[24];
+        for (int n = 0; n < 8; ++n) for (int d = 0; d < 3; ++d) X[n][d] = xyz[enodes[e * 8 + n] * 3 + d];
+        hex_coeffs(X, c);
+        for (int g = 0; g < 24; ++g) b.geo[(size_t)g * b.e_pad + le] = c[g];
+        if (le >= b.n) continue;
+        for (int z = 0; z < H.nsp + H.nfp; ++z) {
+          double xi[3], x[3], G[3][3], cr[3];
+          if (z < H.nsp) { xi[0] = H.x[z % H.n1]; xi[1] = H.x[(z / H.n1) % H.n1]; xi[2] = H.x[z / (H.n1 * H.n1)]; }
+          else hex_fp_ref(H, (z - H.nsp) / H.nfpf, (z - H.nsp) % H.nfpf, xi);
+          hex_map(c, xi, x, G);
+          cross(G[1], G[2], cr);
+          double J = G[0][0] * cr[0] + G[0][1] * cr[1] + G[0][2] * cr[2];
+          if (!(J > 0)) { code = 2; return "element with J <= 0"; }
+          if (z < H.nsp) for (int d = 0; d < 3; ++d) b.sol_xyz[((size_t)le * b.nsp + z) * 3 + d] = x[d];
+        }
+      } else {
+        double X[4][3];
+        for (int n = 0; n < 4; ++n) for (int d = 0; d < 3; ++d) X[n][d] = xyz[enodes[e * 8 + n] * 3 + d];
+        double g[3][3];   // columns: xi0 -> corner1, xi1 -> corner3, xi2 -> corner2
+        for (int d = 0; d < 3; ++d) {
+          g[0][d] = 0.5 * (X[1][d] - X[0][d]);
+          g[1][d] = 0.5 * (X[3][d] - X[0][d]);
+          g[2][d] = 0.5 * (X[2][d] - X[0][d]);
+        }
+        double S[3][3];
+        cross(g[1], g[2], S[0]);
+        cross(g[2], g[0], S[1]);
+        cross(g[0], g[1], S[2]);
+        double J = g[0][0] * S[0][0] + g[0][1] * S[0][1] + g[0][2] * S[0][2];
+        if (le < b.n && !(J > 0)) { code = 2; return "element with J <= 0"; }
+        for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) b.geo[(size_t)(i * 3 + j) * b.e_pad + le] = S[i][j];
+        b.geo[(size_t)9 * b.e_pad + le] = J;
+        if (le >= b.n) continue;
+        for (int z = 0; z < T.nsp; ++z)
+          for (int d = 0; d < 3; ++d) {
+            double x = X[0][d];
+            for (int k = 0; k < 3; ++k) x += (T.pts[z][k] + 1.0) * g[k][d];
+            b.sol_xyz[((size_t)le * b.nsp + z) * 3 + d] = x;
+          }
+      }
+    }
+  }
+  // ---- face matching
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  for (int64_t v = 0; v < n_vert; ++v)
+    for (int d = 0; d < 3; ++d) { lo[d] = std::min(lo[d], xyz[v * 3 + d]); hi[d] = std::max(hi[d], xyz[v * 3 + d]); }
+  double span = std::max({hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2], 1e-300});
+  const double scale = 1e-8 * span;
+  static const int kHexFaceCorners[6][4] = {{0, 3, 4, 7}, {1, 2, 5, 6}, {0, 1, 4, 5}, {2, 3, 6, 7}, {0, 1, 2, 3}, {4, 5, 6, 7}};
+  auto face_centroid = [&](const Block& b, int64_t le, int f, double c[3]) {
+    int64_t e = b.elems[le];
+    int nc = b.etype == kHex ? 4 : 3;
+    c[0] = c[1] = c[2] = 0;
+    for (int k = 0; k < nc; ++k) {
+      int corner = b.etype == kHex ? kHexFaceCorners[f][k] : kTetFace[f][k];
+      for (int d = 0; d < 3; ++d) c[d] += xyz[enodes[e * 8 + corner] * 3 + d];
+    }
+    for (int d = 0; d < 3; ++d) c[d] /= nc;
+  };
+  std::unordered_map<Key, std::vector<std::array<int64_t, 3>>, KeyHash> buckets;
+  buckets.reserve((size_t)n_elem * 6);
+  for (int bi = 0; bi < (int)out.blocks.size(); ++bi) {
+    const Block& b = out.blocks[bi];
+    for (int64_t le = 0; le < b.n; ++le)
+      for (int f = 0; f < b.nfaces; ++f) {
+        double c[3];
+        face_centroid(b, le, f, c);
+        Key k;
+        for (int d = 0; d < 3; ++d) {
+          if (period[d] > 0) {
+            double r = std::fmod(c[d], period[d]);
+            if (r < 0) r += period[d];
+            int64_t n = std::llround(period[d] / scale);
+            k.k[d] = std::llround(r / scale) % n;
+          } else {
+            k.k[d] = std::llround(c[d] / scale);
+          }
+        }
+        buckets[k].push_back({bi, le, f});
+      }
+  }
+  // flux point physical coordinates of one face
+  auto face_points = [&](const Block& b, int64_t le, int f, std::vector<std::array<double, 3>>& P) {
+    P.resize(b.nfpf);
+    int64_t e = b.elems[le];
+    for (int q = 0; q < b.nfpf; ++q) {
+      if (b.etype == kHex) {
+        double c[24], xi[3], x[3], G[3][3];
+        for (int g = 0; g < 24; ++g) c[g] = b.geo[(size_t)g * b.e_pad + le];
+        hex_fp_ref(H, f, q, xi);
+        hex_map(c, xi, x, G);
+        P[q] = {x[0], x[1], x[2]};
+      } else {
+        int s = f * 15 + q;
+        const double* xi = T.pts[T.fp_src[s]];
+        double X[4][3];
+        for (int n = 0; n < 4; ++n) for (int d = 0; d < 3; ++d) X[n][d] = xyz[enodes[e * 8 + n] * 3 + d];
+        for (int d = 0; d < 3; ++d)
+          P[q][d] = X[0][d] + 0.5 * (xi[0] + 1) * (X[1][d] - X[0][d]) + 0.5 * (xi[1] + 1) * (X[3][d] - X[0][d]) +
+                    0.5 * (xi[2] + 1) * (X[2][d] - X[0][d]);
+      }
+    }
+  };
+  // outward scaled normal at the reference face centre
+  auto face_normal = [&](const Block& b, int64_t le, int f, double nv[3]) {
+    if (b.etype == kHex) {
+      double c[24], xi[3] = {0, 0, 0}, x[3], G[3][3];
+      for (int g = 0; g < 24; ++g) c[g] = b.geo[(size_t)g * b.e_pad + le];
+      int d = f / 2;
+      xi[d] = (f % 2) ? 1.0 : -1.0;
+      hex_map(c, xi, x, G);
+      cross(G[(d + 1) % 3], G[(d + 2) % 3], nv);
+      double sg = (f % 2) ? 1.0 : -1.0;
+      for (int k = 0; k < 3; ++k) nv[k] *= sg;
+    } else {
+      for (int j = 0; j < 3; ++j) {
+        nv[j] = 0;
+        for (int i = 0; i < 3; ++i) nv[j] += b.geo[(size_t)(i * 3 + j) * b.e_pad + le] * T.nref[f][i];
+      }
+    }
+  };
+  std::map<std::vector<int32_t>, int> perm_ids;
+  std::vector<std::vector<int32_t>> perms;
+  auto perm_id = [&](const std::vector<int32_t>& p) {
+    auto it = perm_ids.find(p);
+    if (it != perm_ids.end()) return it->second;
+    int id = (int)perms.size();
+    perm_ids[p] = id;
+    perms.push_back(p);
+    return id;
+  };
+  std::vector<std::array<double, 3>> PA, PB;
+  for (auto& kv : buckets) {
+    auto& lst = kv.second;
+    if (lst.size() != 2) { code = 2; return "face without exactly one partner (unpaired or non-conforming mesh)"; }
+    Block& A = out.blocks[lst[0][0]];
+    Block& B = out.blocks[lst[1][0]];
+    int64_t ea = lst[0][1], eb = lst[1][1];
+    int fa = (int)lst[0][2], fb = (int)lst[1][2];
+    if (A.etype != B.etype) { code = 3; return "hexahedron-tetrahedron interfaces need pyramids (not supported)"; }
+    face_points(A, ea, fa, PA);
+    face_points(B, eb, fb, PB);
+    double ca[3], cb[3], sh[3];
+    face_centroid(A, ea, fa, ca);
+    face_centroid(B, eb, fb, cb);
+    for (int d = 0; d < 3; ++d) {
+      double dd = ca[d] - cb[d];
+      double w = dd;
+      if (period[d] > 0) w = dd - period[d] * std::nearbyint(dd / period[d]);
+      sh[d] = dd - w;
+    }
+    int nq = A.nfpf;
+    std::vector<int32_t> pa(nq), pb(nq, -1);
+    for (int q = 0; q < nq; ++q) {
+      int best = -1;
+      double bd = 1e300;
+      for (int r = 0; r < nq; ++r) {
+        double d2 = 0;
+        for (int d = 0; d < 3; ++d) { double t = PA[q][d] - PB[r][d] - sh[d]; d2 += t * t; }
+        if (d2 < bd) { bd = d2; best = r; }
+      }
+      if (std::sqrt(bd) > 1e-8 * span || pb[best] != -1) { code = 2; return "flux points of matched faces do not conform"; }
+      pa[q] = best;
+      pb[best] = q;
+    }
+    double nv[3];
+    face_normal(A, ea, fa, nv);
+    double mx = std::max({std::fabs(nv[0]), std::fabs(nv[1]), std::fabs(nv[2])});
+    int dom = 0;
+    while (std::fabs(nv[dom]) < (1 - 1e-6) * mx) ++dom;
+    int a_left = nv[dom] > 0 ? 1 : 0;
+    int oa = perm_id(pa), ob = perm_id(pb);
+    if (oa > 511 || ob > 511) { code = 3; return "too many distinct face orientations"; }
+    A.nbr_elem[(size_t)fa * A.e_pad + ea] = (int32_t)eb;
+    A.nbr_info[(size_t)fa * A.e_pad + ea] = fb | (oa << 3) | (a_left << 12);
+    B.nbr_elem[(size_t)fb * B.e_pad + eb] = (int32_t)ea;
+    B.nbr_info[(size_t)fb * B.e_pad + eb] = fa | (ob << 3) | ((1 - a_left) << 12);
+  }
+  // padding lanes copy element 0's connectivity (in-bounds, results discarded)
+  for (auto& b : out.blocks) {
+    for (int f = 0; f < b.nfaces; ++f)
+      for (int64_t le = 0; le < b.e_pad; ++le) {
+        size_t i = (size_t)f * b.e_pad + le;
+        if (le >= b.n) { b.nbr_elem[i] = b.nbr_elem[(size_t)f * b.e_pad]; b.nbr_info[i] = b.nbr_info[(size_t)f * b.e_pad]; }
+        if (b.nbr_info[i] < 0) { code = 2; return "unpaired face"; }
+      }
+  }
+  out.n_orient = (int)perms.size();
+  out.perm_stride = 0;
+  for (auto& p : perms) out.perm_stride = std::max(out.perm_stride, (int)p.size());
+  out.orient_perm.assign((size_t)std::max(out.n_orient, 1) * std::max(out.perm_stride, 1), 0);
+  for (int i = 0; i < out.n_orient; ++i)
+    for (size_t q = 0; q < perms[i].size(); ++q) out.orient_perm[(size_t)i * out.perm_stride + q] = perms[i][q];
+  (void)bidx;
+  return "";
+}
+
+}  // namespace frmi

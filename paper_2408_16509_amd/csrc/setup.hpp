@@ -1,0 +1,72 @@
+// Host-side setup of the FR right-hand side: element operators, mesh connectivity
+// and geometry, ready to upload.  Plain C++17, no device code.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace frmi {
+
+constexpr int kHex = 0;
+constexpr int kTet = 1;
+constexpr int kMaxP = 4;
+
+// One-dimensional operators of hexahedra of order p (Gauss--Legendre points).
+struct HexOps {
+  int p = 0, n1 = 0, nsp = 0, nfp = 0, nfpf = 0;
+  double x[kMaxP + 1] = {}, w[kMaxP + 1] = {};
+  double lm[kMaxP + 1] = {}, lp[kMaxP + 1] = {};   // l_a(-1), l_a(+1)
+  double D[kMaxP + 1][kMaxP + 1] = {};             // D[a][b] = l_b'(x_a)
+  double Dh[kMaxP + 1][kMaxP + 1] = {};            // D - gR' lp^T - gL' lm^T (correction folded in)
+  double cp[kMaxP + 1] = {}, cm[kMaxP + 1] = {};   // gR'(x_a), -gL'(x_a)
+  double Vm[kMaxP + 1][kMaxP + 1] = {};            // 1-D orthonormal Legendre Vandermonde V[a][m]
+  double Vmi[kMaxP + 1][kMaxP + 1] = {};           // its inverse
+};
+
+// Operators of the order-4 tetrahedron (alpha-optimised points of Fig. mesh).
+struct TetOps {
+  static constexpr int nsp = 35, nfp = 60, nfpf = 15;
+  double pts[nsp][3];
+  int fp_src[nfp];                 // solution point collocated with each flux point
+  int fp_face[nfp];
+  double nref[4][3];               // unit outward reference normals
+  double D[3][nsp][nsp];           // D[i][z][n] = d l_n / d xi_i at x_z
+  double lift[nsp][nfp];           // DG lifting M^{-1} E
+  double weights[nsp];             // integral of l_z
+  double V[nsp][nsp];              // orthonormal modal basis at the points, V[z][m]
+  double Vinv[nsp][nsp];
+  int deg[nsp];                    // total degree of mode m
+};
+
+// A block of elements of one type, in the native (element-fastest) layout.
+struct Block {
+  int etype = kHex;
+  int64_t n = 0, e_pad = 0;
+  int nsp = 0, nfp = 0, nfaces = 0, nfpf = 0;
+  std::vector<int64_t> elems;      // global element ids in block order (mesh order)
+  int ngeo = 0;
+  std::vector<double> geo;         // [ngeo][e_pad]
+  std::vector<int32_t> nbr_elem;   // [nfaces][e_pad] neighbour's local index (same block)
+  std::vector<int32_t> nbr_info;   // [nfaces][e_pad] nbr_face | orient << 3 | is_left << 12
+  std::vector<double> sol_xyz;     // [n][nsp][3] physical solution points (canonical order)
+};
+
+struct Setup {
+  HexOps hex;
+  TetOps tet;
+  std::vector<Block> blocks;
+  int n_orient = 0;
+  std::vector<int32_t> orient_perm;  // [n_orient][max face points]
+  int perm_stride = 0;
+};
+
+// Builders.  Return an empty string on success, else an error message; `code`
+// receives 1 for argument errors, 2 for mesh errors, 3 for unsupported options.
+void build_hex_ops(int p, HexOps& ops);
+void build_tet_ops(TetOps& ops);
+std::string build_setup(int order, int64_t n_vert, const double* xyz, const double* period,
+                        int64_t n_elem, const int32_t* etype, const int64_t* enodes,
+                        int e_align, Setup& out, int& code);
+
+}  // namespace frmi

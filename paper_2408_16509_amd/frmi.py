@@ -1,0 +1,249 @@
+"""Thin ctypes binding of libfrmi.so (the C ABI declared in include/frmi.h).
+
+Argument marshalling only: every step of the right-hand side, the RK update, the
+filter and the MLP run in the library's HIP kernels.  Device buffers are PyTorch
+CUDA tensors (device memory and the stream come from PyTorch).  Importing this
+module raises if the built library is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfrmi.so")
+
+FR_EULER, FR_NAVIER_STOKES = 0, 1
+FR_RUSANOV, FR_HLLC = 0, 1
+FR_FP64, FR_FP32 = 0, 1
+FR_HEX, FR_TET = 0, 1
+STATUS = {0: "FR_OK", 1: "FR_ERR_ARG", 2: "FR_ERR_MESH", 3: "FR_ERR_ALLOC", 4: "FR_ERR_DEVICE",
+          5: "FR_ERR_NONFINITE", 6: "FR_ERR_STATE", 7: "FR_ERR_UNSUPPORTED"}
+
+
+class FrParams(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32), ("system", ctypes.c_int32), ("order", ctypes.c_int32),
+        ("riemann", ctypes.c_int32), ("precision", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+        ("gamma", ctypes.c_double), ("mu", ctypes.c_double), ("prandtl", ctypes.c_double),
+        ("ldg_beta", ctypes.c_double), ("ldg_tau", ctypes.c_double), ("u_ref", ctypes.c_double * 5),
+        ("filt_eps_rho", ctypes.c_double), ("filt_eps_p", ctypes.c_double), ("filt_eps_s", ctypes.c_double),
+        ("filt_zeta_max_coef", ctypes.c_double), ("filt_bits", ctypes.c_int32), ("reserved1", ctypes.c_int32),
+    ]
+
+
+class FrLayout(ctypes.Structure):
+    _fields_ = [
+        ("n_types", ctypes.c_int32), ("etype", ctypes.c_int32 * 2), ("n_elem", ctypes.c_int64 * 2),
+        ("e_pad", ctypes.c_int64 * 2), ("n_sp", ctypes.c_int32 * 2), ("n_fp", ctypes.c_int32 * 2),
+        ("canon_offset", ctypes.c_int64 * 2), ("native_offset", ctypes.c_int64 * 2),
+        ("canon_len", ctypes.c_int64), ("native_len", ctypes.c_int64),
+        ("native_dtype", ctypes.c_int32), ("reserved", ctypes.c_int32),
+    ]
+
+
+class FrFilterStats(ctypes.Structure):
+    _fields_ = [("n_troubled", ctypes.c_int64), ("n_fallback", ctypes.c_int64),
+                ("n_evals", ctypes.c_int64), ("seconds", ctypes.c_double)]
+
+
+class FrKernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
+
+
+EXPORTS = [
+    "fr_default_params", "fr_setup_mesh", "fr_layout", "fr_sol_points", "fr_pack", "fr_unpack",
+    "fr_rhs", "fr_rk_step", "fr_filter", "fr_mlp_set_weights", "fr_mlp_get_weights",
+    "fr_mlp_features", "fr_mlp_forward", "fr_mlp_grad", "fr_mlp_train", "fr_check", "fr_sync",
+    "fr_profile", "fr_profile_read",
+    "fr_destroy", "fr_last_error",
+]
+
+
+def load():
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with python -m paper_2408_16509_amd.build")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    P = ctypes.POINTER
+    sig = {
+        "fr_default_params": (None, [P(FrParams)]),
+        "fr_setup_mesh": (i32, [P(FrParams), i64, vp, vp, i64, vp, vp, vp, P(vp)]),
+        "fr_layout": (i32, [vp, P(FrLayout)]),
+        "fr_sol_points": (i32, [vp, vp]),
+        "fr_pack": (i32, [vp, vp, vp]),
+        "fr_unpack": (i32, [vp, vp, vp]),
+        "fr_rhs": (i32, [vp, vp, vp]),
+        "fr_rk_step": (i32, [vp, vp, dbl, i32, i32]),
+        "fr_filter": (i32, [vp, vp, vp, i32, vp, P(FrFilterStats)]),
+        "fr_mlp_set_weights": (i32, [vp, vp, vp, vp]),
+        "fr_mlp_get_weights": (i32, [vp, vp]),
+        "fr_mlp_features": (i32, [vp, vp, vp, vp, vp, vp, i64, P(i64)]),
+        "fr_mlp_forward": (i32, [vp, vp, i64, vp]),
+        "fr_mlp_grad": (i32, [vp, vp, vp, i64, vp, vp]),
+        "fr_mlp_train": (i32, [vp, vp, vp, i64, vp, i32, i32, ctypes.c_float, ctypes.c_float,
+                               ctypes.c_float, ctypes.c_float, vp]),
+        "fr_check": (i32, [vp, vp]),
+        "fr_sync": (i32, [vp]),
+        "fr_profile": (i32, [vp, i32]),
+        "fr_profile_read": (i32, [vp, vp, i32, P(i32)]),
+        "fr_destroy": (None, [vp]),
+        "fr_last_error": (ctypes.c_char_p, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+_LIB = None
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        _LIB = load()
+    return _LIB
+
+
+class FrError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def default_params(**kw) -> FrParams:
+    p = FrParams()
+    lib().fr_default_params(ctypes.byref(p))
+    for k, v in kw.items():
+        if k == "u_ref":
+            for i in range(5):
+                p.u_ref[i] = float(v[i])
+        else:
+            setattr(p, k, v)
+    return p
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+class Context:
+    """An FR context on one mesh.  `stream` defaults to torch's current stream."""
+
+    def __init__(self, mesh, stream=None, **params):
+        import torch
+        self._torch = torch
+        self.params = default_params(**params)
+        xyz = np.ascontiguousarray(mesh.xyz, dtype=np.float64)
+        per = np.ascontiguousarray(mesh.period, dtype=np.float64)
+        et = np.ascontiguousarray(mesh.etype, dtype=np.int32)
+        en = np.ascontiguousarray(mesh.enodes, dtype=np.int64)
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self.stream = stream
+        h = ctypes.c_void_p()
+        st = lib().fr_setup_mesh(ctypes.byref(self.params), xyz.shape[0], xyz.ctypes.data, per.ctypes.data,
+                                 et.shape[0], et.ctypes.data, en.ctypes.data, ctypes.c_void_p(stream),
+                                 ctypes.byref(h))
+        if st != 0:
+            raise FrError(st, lib().fr_last_error(None).decode())
+        self.h = h
+        lay = FrLayout()
+        self._check(lib().fr_layout(self.h, ctypes.byref(lay)))
+        self.layout = lay
+
+    def _check(self, st):
+        if st != 0:
+            raise FrError(st, lib().fr_last_error(self.h).decode())
+
+    # --------------------------------------------------------------- buffers
+    @property
+    def native_dtype(self):
+        return self._torch.float64 if self.layout.native_dtype == FR_FP64 else self._torch.float32
+
+    def new_native(self, dtype=None):
+        return self._torch.zeros(self.layout.native_len, dtype=dtype or self.native_dtype, device="cuda")
+
+    def new_native64(self):
+        return self._torch.zeros(self.layout.native_len, dtype=self._torch.float64, device="cuda")
+
+    def sol_points(self):
+        n = self.layout.canon_len // 5
+        out = np.empty((n, 3), dtype=np.float64)
+        self._check(lib().fr_sol_points(self.h, out.ctypes.data))
+        return out
+
+    def pack(self, canon, out=None):
+        torch = self._torch
+        c = torch.as_tensor(canon, dtype=torch.float64, device="cuda").contiguous()
+        if out is None:
+            out = self.new_native()
+        self._check(lib().fr_pack(self.h, _ptr(c), _ptr(out)))
+        return out
+
+    def unpack(self, native, out=None):
+        torch = self._torch
+        if out is None:
+            out = torch.empty(self.layout.canon_len, dtype=torch.float64, device="cuda")
+        self._check(lib().fr_unpack(self.h, _ptr(native), _ptr(out)))
+        return out
+
+    # --------------------------------------------------------------- compute
+    def rhs(self, u, r):
+        self._check(lib().fr_rhs(self.h, _ptr(u), _ptr(r)))
+
+    def rk_step(self, u, dt, n_steps=1, filter_mode=-1):
+        self._check(lib().fr_rk_step(self.h, _ptr(u), float(dt), int(n_steps), int(filter_mode)))
+
+    def filter(self, u, u_prev=None, mode=0, k=None, stats=False):
+        s = FrFilterStats() if stats else None
+        self._check(lib().fr_filter(self.h, _ptr(u), _ptr(u if u_prev is None else u_prev), int(mode),
+                                    _ptr(k), ctypes.byref(s) if stats else None))
+        return s
+
+    def check(self, u):
+        st = lib().fr_check(self.h, _ptr(u))
+        if st == 5:
+            return False
+        self._check(st)
+        return True
+
+    def sync(self):
+        self._check(lib().fr_sync(self.h))
+
+    def profile(self, enable=True):
+        self._check(lib().fr_profile(self.h, 1 if enable else 0))
+
+    def profile_read(self):
+        """{kernel family: (launches, total device ms)} from the event timing."""
+        buf = (FrKernelTime * 64)()
+        n = ctypes.c_int32()
+        self._check(lib().fr_profile_read(self.h, buf, 64, ctypes.byref(n)))
+        return {buf[i].name.decode(): (int(buf[i].launches), float(buf[i].total_ms)) for i in range(n.value)}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().fr_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # canonical helpers (host numpy <-> device)
+    def split_canon(self, flat):
+        """Canonical flat array -> list of per-block [n][5][nsp] arrays."""
+        out = []
+        for i in range(self.layout.n_types):
+            o, n, s = self.layout.canon_offset[i], self.layout.n_elem[i], self.layout.n_sp[i]
+            out.append(flat[o:o + n * 5 * s].reshape(n, 5, s))
+        return out
+
+    def join_canon(self, blocks):
+        return np.concatenate([np.asarray(b, dtype=np.float64).ravel() for b in blocks])

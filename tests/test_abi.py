@@ -1,0 +1,84 @@
+"""The C-ABI library loads and exports every symbol include/frmi.h declares; host-side
+argument checks (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "frmi.h")
+LIB = os.path.join(ROOT, "paper_2408_16509_amd", "libfrmi.so")
+
+
+def declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(fr_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_header_declares_the_four_entry_points():
+    names = declared()
+    for n in ("fr_setup_mesh", "fr_rhs", "fr_rk_step", "fr_filter"):
+        assert n in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libfrmi.so not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libfrmi.so not built")
+def test_binding_covers_header_and_argument_errors():
+    from paper_2408_16509_amd import frmi
+    assert set(frmi.EXPORTS) == set(declared())
+    p = frmi.default_params()
+    assert p.struct_size == ctypes.sizeof(frmi.FrParams) and p.order == 3 and abs(p.gamma - 1.4) < 1e-15
+    lib = frmi.lib()
+    h = ctypes.c_void_p()
+    # NULL arrays -> FR_ERR_ARG before any device work
+    assert lib.fr_setup_mesh(ctypes.byref(p), 0, None, None, 0, None, None, None, ctypes.byref(h)) == 1
+    assert b"empty" in lib.fr_last_error(None)
+    bad = frmi.default_params()
+    bad.struct_size = 3
+    assert lib.fr_setup_mesh(ctypes.byref(bad), 1, None, None, 1, None, None, None, ctypes.byref(h)) == 1
+    # NULL context calls fail cleanly
+    assert lib.fr_rhs(None, None, None) == 1
+    assert lib.fr_sync(None) == 1
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libfrmi.so not built")
+def test_mesh_errors_are_reported_before_device_work():
+    from paper_2408_16509_amd import frmi, inputs
+    lib = frmi.lib()
+
+    def setup(m, **kw):
+        p = frmi.default_params(**kw)
+        h = ctypes.c_void_p()
+        xyz = np.ascontiguousarray(m.xyz)
+        per = np.ascontiguousarray(m.period, dtype=np.float64)
+        et = np.ascontiguousarray(m.etype, dtype=np.int32)
+        en = np.ascontiguousarray(m.enodes, dtype=np.int64)
+        st = lib.fr_setup_mesh(ctypes.byref(p), xyz.shape[0], xyz.ctypes.data, per.ctypes.data, et.shape[0],
+                               et.ctypes.data, en.ctypes.data, None, ctypes.byref(h))
+        return st, lib.fr_last_error(None).decode()
+
+    m = inputs.hex_box((2, 2, 2))
+    m.period = np.zeros(3)                       # not periodic -> boundary faces unpaired
+    st, msg = setup(m)
+    assert st == 2 and "partner" in msg
+    m = inputs.hex_box((2, 2, 2))
+    m.enodes[0] = m.enodes[0][[1, 0, 3, 2, 5, 4, 7, 6]]   # mirrored element: J < 0
+    st, msg = setup(m)
+    assert st == 2 and "J <= 0" in msg
+    st, msg = setup(inputs.hex_box((2, 2, 2)), order=5)
+    assert st == 7
+    st, msg = setup(inputs.kuhn_split(inputs.hex_box((1, 1, 1))), order=3)
+    assert st == 7 and "order 4" in msg
+    m = inputs.hex_box((2, 2, 2))
+    m.enodes[0, 0] = 10 ** 6
+    st, msg = setup(m)
+    assert st == 1

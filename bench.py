@@ -38,18 +38,25 @@ CONFIGS = {
 
 
 def kernel_bytes_per_elem(name, nsp, nfp):
-    """Compulsory HBM bytes per element of each kernel family (each value touched once)."""
-    d = 8
-    geo_conn = 24 * d + 6 * 2 * 4
+    """Compulsory HBM bytes per element of each kernel family (each value touched once).
+
+    NS uses the one-sided LDG switch (beta = 1/2): the gradient kernel reads the
+    neighbour's trace only on faces where the element is the right side and stores
+    gradient traces only there; the divergence kernel reads a neighbour's gradient
+    trace only where the element is the left side (half of the faces each)."""
     fam = name.rsplit("_p", 1)[0]
+    d = 8
+    if fam.endswith("_f32"):
+        fam, d = fam[:-4], 4
+    geo_conn = 24 * d + 6 * 2 * 4
     if fam == "hex_trace":
         return d * 5 * (nsp + nfp)
     if fam == "hex_div_euler":
         return d * (5 * nsp + 5 * nfp + 5 * nsp) + geo_conn
     if fam == "hex_grad":
-        return d * (5 * nsp + 5 * nfp + 15 * nsp + 15 * nfp) + geo_conn
+        return d * (5 * nsp + 5 * nfp // 2 + 15 * nsp + 15 * nfp // 2) + geo_conn
     if fam == "hex_div_ns":
-        return d * (5 * nsp + 15 * nsp + 5 * nfp + 15 * nfp + 15 * nfp + 5 * nsp) + geo_conn
+        return d * (5 * nsp + 15 * nsp + 5 * nfp + 15 * nfp // 2 + 5 * nsp) + geo_conn
     return None
 
 
@@ -98,12 +105,49 @@ def cpu_baseline(mesh, cfg, u_canon_fn):
             "sample": f"1 FP64 oracle RHS over the full mesh ({dof} points), mesh setup excluded, {dt:.1f} s"}, u, R
 
 
+def run_form(form, cfg, mesh, ic, args, torch, np, frmi):
+    """Time `args.steps` RK4 steps of one precision form; per-kernel event timing."""
+    kw = dict(system=cfg["system"], order=cfg["order"], riemann=cfg["riemann"])
+    if form == "fp32":
+        p0 = 1.0 / (1.4 * cfg["mach"] ** 2)
+        kw.update(precision=frmi.FR_FP32, u_ref=(1.0, 0.0, 0.0, 0.0, p0 / 0.4))
+    ctx = frmi.Context(mesh, **kw)
+    lay = ctx.layout
+    E, nsp, nfp = lay.n_elem[0], lay.n_sp[0], lay.n_fp[0]
+    x = ctx.sol_points().reshape(E, nsp, 3)
+    u0 = ctx.pack64(ic(x).ravel())
+    u = u0.clone()
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        ctx.rk_step(u, cfg["dt"], 1)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    wall0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        ctx.rk_step(u, cfg["dt"], 1)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms = ev0.elapsed_time(ev1) / args.steps
+    res = {"ctx": ctx, "ms": ms, "wall": wall, "finite": ctx.check(u), "E": E, "nsp": nsp, "nfp": nfp}
+    if not args.no_kernel_timing:
+        uk = u0.clone()
+        ctx.profile(True)
+        for _ in range(2):
+            ctx.rk_step(uk, cfg["dt"], 1)
+        res["times"] = ctx.profile_read()
+        ctx.profile(False)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="ns_tgv_hex32_p3", choices=sorted(CONFIGS))
+    ap.add_argument("--forms", default="fp32,fp64", help="precision forms to time; the first is the headline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
     args = ap.parse_args()
@@ -121,51 +165,30 @@ def main():
     torch.cuda.set_device(0)
     mesh = inputs.hex_box(cfg["n"], perturb=cfg.get("perturb", 0.0), perturb_seed=cfg.get("perturb_seed"),
                           permute_seed=cfg.get("permute_seed"))
-    ctx = frmi.Context(mesh, system=cfg["system"], order=cfg["order"], riemann=cfg["riemann"])
-    lay = ctx.layout
-    E, nsp, nfp = lay.n_elem[0], lay.n_sp[0], lay.n_fp[0]
 
     def ic(xsol):
         s = inputs.tgv(xsol[..., 0], xsol[..., 1], xsol[..., 2], mach=cfg["mach"])
         return np.moveaxis(s, 0, 1).copy()
 
-    x = ctx.sol_points().reshape(E, nsp, 3)
-    u0 = ctx.pack(ic(x).ravel())
-    u = u0.clone()
-    stream = torch.cuda.current_stream()
-    for _ in range(args.warmup):
-        ctx.rk_step(u, cfg["dt"], 1)
-    torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    wall0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        ctx.rk_step(u, cfg["dt"], 1)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    ms = ev0.elapsed_time(ev1) / args.steps
-    ok = ctx.check(u)
+    forms = [f.strip() for f in args.forms.split(",") if f.strip()]
+    runs = {f: run_form(f, cfg, mesh, ic, args, torch, np, frmi) for f in forms}
+    head = runs[forms[0]]
+    E, nsp, nfp = head["E"], head["nsp"], head["nfp"]
     dof = E * nsp
-    value = 4 * dof / (ms * 1e-3) / 1e9
-
+    gdofs = {f: 4 * dof / (r["ms"] * 1e-3) / 1e9 for f, r in runs.items()}
     out = {
         "metric": "RHS GDoF/s (FP32/learned vs FP64 plain) at stated L2 error; % HBM roofline",
-        "value": round(value, 4), "unit": "GDoF/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic",
+        "value": round(gdofs[forms[0]], 4), "unit": "GDoF/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(head["ms"], 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32" if forms[0] == "fp32" else "f64", "data": "synthetic",
         "config": {"workload": args.config, "elements": int(E), "order": cfg["order"], "points_per_elem": int(nsp),
-                   "dof": int(dof), "rhs_per_step": 4, "form": "fp64", "state_finite_after": bool(ok),
-                   "wall_s_timed": round(wall, 3)},
+                   "dof": int(dof), "rhs_per_step": 4, "form": forms[0],
+                   "rk_accumulation": "f64", "state_finite_after": bool(head["finite"]),
+                   "wall_s_timed": round(head["wall"], 3)},
+        "forms": {f: {"gdof_s": round(gdofs[f], 4), "ms_per_step": round(runs[f]["ms"], 4)} for f in forms},
     }
-    # --- dominant kernel, timed with HIP events on the context stream
     if not args.no_kernel_timing:
-        uk = u0.clone()
-        ctx.profile(True)
-        for _ in range(2):
-            ctx.rk_step(uk, cfg["dt"], 1)
-        times = ctx.profile_read()
-        ctx.profile(False)
+        times = head["times"]
         fam = {k: v for k, v in times.items() if kernel_bytes_per_elem(k, nsp, nfp) is not None}
         dom = max(fam, key=lambda k: fam[k][1])
         launches, tot = fam[dom]
@@ -176,18 +199,22 @@ def main():
         out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                            "kernel": dom, "avg_launch_ms": round(avg_ms, 4), "bytes_per_launch": int(by)}
-        out["kernels_ms_per_step"] = {k: round(v[1] / 2, 4) for k, v in sorted(times.items())}
-        out["rhs_m0_fraction"] = round(4 * dof * 80 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
-    # --- CPU oracle baseline on the host (rank 0, N = 1)
+        for f in forms:
+            out["forms"][f]["kernels_ms_per_step"] = {k: round(v[1] / 2, 4) for k, v in sorted(runs[f]["times"].items())}
+            bpd = 80 if f == "fp64" else 40
+            out["forms"][f]["rhs_m0_fraction"] = round(4 * dof * bpd / (runs[f]["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
     if not args.no_cpu_baseline:
         base, uo, Ro = cpu_baseline(mesh, cfg, ic)
         out["cpu_baseline"] = base
-        # parity of the same RHS on the GPU (the state comes from the oracle's points)
-        ug = ctx.pack(uo[0].ravel())
-        rg = ctx.new_native()
-        ctx.rhs(ug, rg)
-        got = ctx.unpack(rg).cpu().numpy().reshape(Ro[0].shape)
-        out["config"]["rhs_rel_l2_vs_oracle"] = float(np.linalg.norm(got - Ro[0]) / np.linalg.norm(Ro[0]))
+        for f in forms:
+            ctx = runs[f]["ctx"]
+            ug = ctx.pack(uo[0].ravel())
+            rg = ctx.new_native()
+            ctx.rhs(ug, rg)
+            got = ctx.unpack_rhs(rg).cpu().numpy().reshape(Ro[0].shape)
+            err = np.sqrt(((got - Ro[0]) ** 2).sum(axis=(0, 2)) / (Ro[0] ** 2).sum(axis=(0, 2)))
+            out["forms"][f]["rhs_rel_l2_vs_oracle"] = float(np.linalg.norm(got - Ro[0]) / np.linalg.norm(Ro[0]))
+            out["forms"][f]["rhs_rel_l2_per_var"] = [float(v) for v in err]
     print(json.dumps(out), flush=True)
 
 

@@ -135,6 +135,15 @@ fr_status fr_sol_points(fr_ctx ctx, double* xyz);
 fr_status fr_pack(fr_ctx ctx, const double* canon_dev, void* native_dev);
 fr_status fr_unpack(fr_ctx ctx, const void* native_dev, double* canon_dev);
 
+/* Canonical FP64 state (device) <-> FP64 native state (device): the layout of the
+ * state that fr_rk_step, fr_filter and fr_check work on, in both precisions. */
+fr_status fr_pack64(fr_ctx ctx, const double* canon_dev, double* native_dev);
+fr_status fr_unpack64(fr_ctx ctx, const double* native_dev, double* canon_dev);
+
+/* A native right-hand side (fr_rhs output, native dtype) -> canonical FP64 values
+ * (no reference state is added in the FP32 form: R is not a deviation). */
+fr_status fr_unpack_rhs(fr_ctx ctx, const void* r_dev, double* canon_dev);
+
 /* r = du/dt of the FR scheme (steps 1-4 of Sec. "Flux Reconstruction", with
  * R = -(div f~)/J from the transformed equation).  Native layout; dtype as
  * fr_layout().native_dtype.  u and r must not alias. */

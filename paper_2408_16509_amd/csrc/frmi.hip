@@ -23,12 +23,17 @@ struct DevBlock {
   int64_t n = 0, E = 0;
   int nsp = 0, nfp = 0, nfaces = 0;
   int64_t canon_off = 0, native_off = 0;
-  double* geo = nullptr;
+  double* geo = nullptr;    // FP64 geometry
+  void* geo_t = nullptr;    // geometry in the kernels' arithmetic type (== geo for FP64)
   int32_t* nbr_elem = nullptr;
   int32_t* nbr_info = nullptr;
-  double* uf = nullptr;     // [nfp][5][E]
-  double* grad = nullptr;   // [nsp][15][E]
-  double* gradf = nullptr;  // [nfp][15][E]
+  void* uf = nullptr;       // [nfp][5][E]
+  void* grad = nullptr;     // [nsp][15][E]
+  void* gradf = nullptr;    // [nfp][15][E]
+};
+
+struct RefVec {
+  double v[5];
 };
 
 }  // namespace
@@ -39,12 +44,11 @@ struct fr_ctx_s {
   Setup host;
   std::vector<DevBlock> blocks;
   int32_t* perm = nullptr;
-  HexK hexk;
   int64_t canon_len = 0, native_len = 0;
-  // RK workspace (FP64 native states)
-  double* rk_stage = nullptr;
+  // RK workspace: stage state and increment in the native dtype, FP64 accumulator
+  void* rk_stage = nullptr;
   double* rk_acc = nullptr;
-  double* rk_k = nullptr;
+  void* rk_k = nullptr;
   int* flag = nullptr;
   std::string err;
   // per-kernel event timing
@@ -180,6 +184,59 @@ int grid_for(int64_t n, int threads) {
   return (int)g;
 }
 
+// ------------------------------------------------------------ FP32-form kernels
+// Deviation of the FP64 state from the reference state, rounded to FP32.
+__global__ void k_to_dev(const double* __restrict__ u, float* __restrict__ w, int64_t n, int64_t E, RefVec ref) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    w[i] = (float)(u[i] - ref.v[(i / E) % 5]);
+}
+__global__ void k_pack32(const double* __restrict__ canon, float* __restrict__ nat, int64_t n, int64_t E, int nsp,
+                         RefVec ref) {
+  const int64_t total = (int64_t)nsp * 5 * E;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = i % E;
+    const int64_t pv = i / E;
+    const int v = (int)(pv % 5), pt = (int)(pv / 5);
+    nat[i] = e < n ? (float)(canon[(e * 5 + v) * nsp + pt] - ref.v[v]) : 0.0f;
+  }
+}
+__global__ void k_unpack32(const float* __restrict__ nat, double* __restrict__ canon, int64_t n, int64_t E, int nsp,
+                           RefVec ref, int add_ref) {
+  const int64_t total = n * 5 * nsp;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int pt = (int)(i % nsp);
+    const int64_t ev = i / nsp;
+    const int v = (int)(ev % 5);
+    const int64_t e = ev / 5;
+    canon[i] = (double)nat[((int64_t)pt * 5 + v) * E + e] + (add_ref ? ref.v[v] : 0.0);
+  }
+}
+// RK stages of the FP32 form: FP64 state and accumulator, FP32 increments and stage deviations.
+__global__ void k_rk32_first(const double* __restrict__ u, const float* __restrict__ k, double* __restrict__ acc,
+                             float* __restrict__ st, int64_t n, int64_t E, double b, double c, RefVec ref) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double ui = u[i], ki = (double)k[i];
+    acc[i] = ui + b * ki;
+    st[i] = (float)(ui + c * ki - ref.v[(i / E) % 5]);
+  }
+}
+__global__ void k_rk32_mid(const double* __restrict__ u, const float* __restrict__ k, double* __restrict__ acc,
+                           float* __restrict__ st, int64_t n, int64_t E, double b, double c, RefVec ref) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double ki = (double)k[i];
+    acc[i] += b * ki;
+    st[i] = (float)(u[i] + c * ki - ref.v[(i / E) % 5]);
+  }
+}
+__global__ void k_rk32_last(double* __restrict__ u, const float* __restrict__ k, const double* __restrict__ acc,
+                            float* __restrict__ st, int64_t n, int64_t E, double b, RefVec ref) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double un = acc[i] + b * (double)k[i];
+    u[i] = un;
+    st[i] = (float)(un - ref.v[(i / E) % 5]);
+  }
+}
+
 // ------------------------------------------------------------ hex dispatch
 template <int P>
 struct HexCfg;
@@ -188,27 +245,59 @@ template <> struct HexCfg<2> { static constexpr int NE = 32; };
 template <> struct HexCfg<3> { static constexpr int NE = 16; };
 template <> struct HexCfg<4> { static constexpr int NE = 8; };
 
-template <int P>
-fr_status hex_rhs_p(fr_ctx c, DevBlock& b, const double* u, double* r) {
+template <typename T>
+HexK<T> hexk_of(const HexOps& H) {
+  HexK<T> k;
+  for (int a = 0; a < 5; ++a) {
+    k.x[a] = (T)H.x[a]; k.lm[a] = (T)H.lm[a]; k.lp[a] = (T)H.lp[a];
+    k.cp[a] = (T)H.cp[a]; k.cm[a] = (T)H.cm[a];
+    for (int b = 0; b < 5; ++b) k.Dh[a][b] = (T)H.Dh[a][b];
+  }
+  return k;
+}
+
+template <typename T>
+RefState<T> ref_of(const fr_params& p) {
+  RefState<T> R;
+  R.rho0 = (T)p.u_ref[0];
+  R.E0 = (T)p.u_ref[4];
+  R.p0 = (T)((p.gamma - 1.0) * p.u_ref[4]);
+  R.H0 = (T)(p.u_ref[4] + (p.gamma - 1.0) * p.u_ref[4]);
+  return R;
+}
+
+int side_mode_of(double beta) { return beta == 0.5 ? 1 : (beta == -0.5 ? -1 : 0); }
+
+template <typename T, bool DEV, int P>
+fr_status hex_rhs_p(fr_ctx c, DevBlock& b, const T* u, T* r) {
   constexpr int N1 = P + 1, NE = HexCfg<P>::NE, NT = NE * N1 * N1;
   Conn C{b.nbr_elem, b.nbr_info, c->perm, c->host.perm_stride};
-  const Phys ph = phys_of(c->prm);
+  const fr_params& p = c->prm;
+  const HexK<T> K = hexk_of<T>(c->host.hex);
+  const RefState<T> R = ref_of<T>(p);
+  const T* geo = (const T*)b.geo_t;
+  T* uf = (T*)b.uf;
+  T* grad = (T*)b.grad;
+  T* gradf = (T*)b.gradf;
+  const int sm = side_mode_of(p.ldg_beta);
   const int64_t trace_threads = b.E * 3 * N1 * N1;
-  static const std::string sfx = "_p" + std::to_string(P);
+  static const std::string sfx = std::string(sizeof(T) == 8 ? "" : "_f32") + "_p" + std::to_string(P);
   int pk = c->prof_begin(("hex_trace" + sfx).c_str());
-  hex_trace<P><<<(unsigned)((trace_threads + 255) / 256), 256, 0, c->stream>>>(u, b.uf, b.E, c->hexk);
+  hex_trace<T, P><<<(unsigned)((trace_threads + 255) / 256), 256, 0, c->stream>>>(u, uf, b.E, K);
   c->prof_end(pk);
   const unsigned nblk = (unsigned)(b.E / NE);
-  if (c->prm.system == FR_EULER) {
+  if (p.system == FR_EULER) {
     pk = c->prof_begin(("hex_div_euler" + sfx).c_str());
-    hex_div_euler<P, NE><<<nblk, NT, 0, c->stream>>>(u, b.uf, b.geo, C, r, b.E, b.n, c->hexk, ph);
+    hex_div_euler<T, DEV, P, NE><<<nblk, NT, 0, c->stream>>>(u, uf, geo, C, r, b.E, b.n, K, (T)p.gamma, p.riemann, R);
     c->prof_end(pk);
   } else {
     pk = c->prof_begin(("hex_grad" + sfx).c_str());
-    hex_grad<P, NE><<<nblk, NT, 0, c->stream>>>(u, b.uf, b.geo, C, b.grad, b.gradf, b.E, c->hexk, ph);
+    hex_grad<T, P, NE><<<nblk, NT, 0, c->stream>>>(u, uf, geo, C, grad, gradf, b.E, K, (T)p.ldg_beta, sm);
     c->prof_end(pk);
     pk = c->prof_begin(("hex_div_ns" + sfx).c_str());
-    hex_div_ns<P, NE><<<nblk, NT, 0, c->stream>>>(u, b.uf, b.grad, b.gradf, b.geo, C, r, b.E, b.n, c->hexk, ph);
+    hex_div_ns<T, DEV, P, NE><<<nblk, NT, 0, c->stream>>>(u, uf, grad, gradf, geo, C, r, b.E, b.n, K, (T)p.gamma,
+                                                          (T)p.mu, (T)p.prandtl, (T)p.ldg_beta, (T)p.ldg_tau,
+                                                          p.riemann, sm, R);
     c->prof_end(pk);
   }
   hipError_t e = hipGetLastError();
@@ -216,17 +305,18 @@ fr_status hex_rhs_p(fr_ctx c, DevBlock& b, const double* u, double* r) {
   return FR_OK;
 }
 
-fr_status rhs_fp64(fr_ctx c, const double* u, double* r) {
+template <typename T, bool DEV>
+fr_status rhs_t(fr_ctx c, const T* u, T* r) {
   for (auto& b : c->blocks) {
-    const double* ub = u + b.native_off;
-    double* rb = r + b.native_off;
+    const T* ub = u + b.native_off;
+    T* rb = r + b.native_off;
     fr_status s = FR_OK;
     if (b.etype == FR_HEX) {
       switch (c->prm.order) {
-        case 1: s = hex_rhs_p<1>(c, b, ub, rb); break;
-        case 2: s = hex_rhs_p<2>(c, b, ub, rb); break;
-        case 3: s = hex_rhs_p<3>(c, b, ub, rb); break;
-        case 4: s = hex_rhs_p<4>(c, b, ub, rb); break;
+        case 1: s = hex_rhs_p<T, DEV, 1>(c, b, ub, rb); break;
+        case 2: s = hex_rhs_p<T, DEV, 2>(c, b, ub, rb); break;
+        case 3: s = hex_rhs_p<T, DEV, 3>(c, b, ub, rb); break;
+        case 4: s = hex_rhs_p<T, DEV, 4>(c, b, ub, rb); break;
         default: s = fail(c, FR_ERR_UNSUPPORTED, "order");
       }
     } else {
@@ -235,6 +325,18 @@ fr_status rhs_fp64(fr_ctx c, const double* u, double* r) {
     if (s != FR_OK) return s;
   }
   return FR_OK;
+}
+
+// RHS of the context's precision on its native state.
+fr_status rhs_native(fr_ctx c, const void* u, void* r) {
+  if (c->prm.precision == FR_FP32) return rhs_t<float, true>(c, (const float*)u, (float*)r);
+  return rhs_t<double, false>(c, (const double*)u, (double*)r);
+}
+
+RefVec refvec(const fr_params& p) {
+  RefVec r;
+  for (int i = 0; i < 5; ++i) r.v[i] = p.u_ref[i];
+  return r;
 }
 
 }  // namespace
@@ -270,6 +372,7 @@ void fr_destroy(fr_ctx c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   for (auto& b : c->blocks) {
+    if (b.geo_t && b.geo_t != b.geo) (void)hipFree(b.geo_t);
     (void)hipFree(b.geo); (void)hipFree(b.nbr_elem); (void)hipFree(b.nbr_info);
     (void)hipFree(b.uf); (void)hipFree(b.grad); (void)hipFree(b.gradf);
   }
@@ -289,7 +392,10 @@ fr_status fr_setup_mesh(const fr_params* p, int64_t n_vert, const double* xyz, c
   if (!xyz || !period || !etype || !enodes || n_vert <= 0 || n_elem <= 0) return fail(nullptr, FR_ERR_ARG, "empty mesh or NULL array");
   if (p->system != FR_EULER && p->system != FR_NAVIER_STOKES) return fail(nullptr, FR_ERR_ARG, "system");
   if (p->riemann != FR_RUSANOV && p->riemann != FR_HLLC) return fail(nullptr, FR_ERR_ARG, "riemann");
-  if (p->precision != FR_FP64) return fail(nullptr, FR_ERR_UNSUPPORTED, "precision");
+  if (p->precision != FR_FP64 && p->precision != FR_FP32) return fail(nullptr, FR_ERR_ARG, "precision");
+  if (p->precision == FR_FP32 && (p->u_ref[1] != 0 || p->u_ref[2] != 0 || p->u_ref[3] != 0 ||
+                                  !(p->u_ref[0] > 0) || !(p->u_ref[4] > 0)))
+    return fail(nullptr, FR_ERR_ARG, "the FP32 form needs a reference state at rest with rho > 0, E > 0");
   if (!(p->gamma > 1.0)) return fail(nullptr, FR_ERR_ARG, "gamma must exceed 1");
   if (p->filt_bits < 1 || p->filt_bits > 30) return fail(nullptr, FR_ERR_ARG, "filt_bits must be in 1..30");
   fr_ctx c = new (std::nothrow) fr_ctx_s();
@@ -309,12 +415,7 @@ fr_status fr_setup_mesh(const fr_params* p, int64_t n_vert, const double* xyz, c
     delete c;
     return fail(nullptr, s, msg);
   }
-  const HexOps& H = c->host.hex;
-  for (int a = 0; a < 5; ++a) {
-    c->hexk.x[a] = H.x[a]; c->hexk.lm[a] = H.lm[a]; c->hexk.lp[a] = H.lp[a];
-    c->hexk.cp[a] = H.cp[a]; c->hexk.cm[a] = H.cm[a];
-    for (int b = 0; b < 5; ++b) c->hexk.Dh[a][b] = H.Dh[a][b];
-  }
+  const size_t tsz = p->precision == FR_FP32 ? sizeof(float) : sizeof(double);
   int64_t canon = 0, native = 0;
   auto bail = [&](fr_status s) { std::string m = c->err; fr_destroy(c); return fail(nullptr, s, m); };
   for (auto& hb : c->host.blocks) {
@@ -326,11 +427,21 @@ fr_status fr_setup_mesh(const fr_params* p, int64_t n_vert, const double* xyz, c
     c->blocks.push_back(b);
     DevBlock& d = c->blocks.back();
     if (dalloc(c, &d.geo, hb.geo.size()) || dalloc(c, &d.nbr_elem, hb.nbr_elem.size()) ||
-        dalloc(c, &d.nbr_info, hb.nbr_info.size()) || dalloc(c, &d.uf, (size_t)d.nfp * 5 * d.E))
+        dalloc(c, &d.nbr_info, hb.nbr_info.size()) || dalloc(c, (char**)&d.uf, (size_t)d.nfp * 5 * d.E * tsz))
       return bail(FR_ERR_ALLOC);
     if (p->system == FR_NAVIER_STOKES &&
-        (dalloc(c, &d.grad, (size_t)d.nsp * 15 * d.E) || dalloc(c, &d.gradf, (size_t)d.nfp * 15 * d.E)))
+        (dalloc(c, (char**)&d.grad, (size_t)d.nsp * 15 * d.E * tsz) ||
+         dalloc(c, (char**)&d.gradf, (size_t)d.nfp * 15 * d.E * tsz)))
       return bail(FR_ERR_ALLOC);
+    d.geo_t = d.geo;
+    if (tsz == sizeof(float)) {
+      std::vector<float> g32(hb.geo.begin(), hb.geo.end());
+      if (dalloc(c, (float**)&d.geo_t, g32.size())) return bail(FR_ERR_ALLOC);
+      if (hipMemcpy(d.geo_t, g32.data(), g32.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
+        c->err = "upload failed";
+        return bail(FR_ERR_DEVICE);
+      }
+    }
     if (hipMemcpy(d.geo, hb.geo.data(), hb.geo.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(d.nbr_elem, hb.nbr_elem.data(), hb.nbr_elem.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(d.nbr_info, hb.nbr_info.data(), hb.nbr_info.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
@@ -374,11 +485,32 @@ fr_status fr_sol_points(fr_ctx c, double* xyz) {
   return FR_OK;
 }
 
-fr_status fr_pack(fr_ctx c, const double* canon, void* native) {
-  if (!c || !canon || !native) return fail(c, FR_ERR_ARG, "NULL argument");
+static fr_status pack64(fr_ctx c, const double* canon, double* native) {
   for (auto& b : c->blocks) {
     const int64_t tot = (int64_t)b.nsp * 5 * b.E;
-    k_pack<<<grid_for(tot, 256), 256, 0, c->stream>>>(canon + b.canon_off, (double*)native + b.native_off, b.n, b.E, b.nsp);
+    k_pack<<<grid_for(tot, 256), 256, 0, c->stream>>>(canon + b.canon_off, native + b.native_off, b.n, b.E, b.nsp);
+  }
+  HIP_TRY(c, hipGetLastError());
+  return FR_OK;
+}
+
+static fr_status unpack64(fr_ctx c, const double* native, double* canon) {
+  for (auto& b : c->blocks) {
+    const int64_t tot = b.n * 5 * b.nsp;
+    k_unpack<<<grid_for(tot, 256), 256, 0, c->stream>>>(native + b.native_off, canon + b.canon_off, b.n, b.E, b.nsp);
+  }
+  HIP_TRY(c, hipGetLastError());
+  return FR_OK;
+}
+
+fr_status fr_pack(fr_ctx c, const double* canon, void* native) {
+  if (!c || !canon || !native) return fail(c, FR_ERR_ARG, "NULL argument");
+  if (c->prm.precision == FR_FP64) return pack64(c, canon, (double*)native);
+  const RefVec ref = refvec(c->prm);
+  for (auto& b : c->blocks) {
+    const int64_t tot = (int64_t)b.nsp * 5 * b.E;
+    k_pack32<<<grid_for(tot, 256), 256, 0, c->stream>>>(canon + b.canon_off, (float*)native + b.native_off, b.n, b.E,
+                                                        b.nsp, ref);
   }
   HIP_TRY(c, hipGetLastError());
   return FR_OK;
@@ -386,18 +518,44 @@ fr_status fr_pack(fr_ctx c, const double* canon, void* native) {
 
 fr_status fr_unpack(fr_ctx c, const void* native, double* canon) {
   if (!c || !canon || !native) return fail(c, FR_ERR_ARG, "NULL argument");
+  if (c->prm.precision == FR_FP64) return unpack64(c, (const double*)native, canon);
+  const RefVec ref = refvec(c->prm);
   for (auto& b : c->blocks) {
     const int64_t tot = b.n * 5 * b.nsp;
-    k_unpack<<<grid_for(tot, 256), 256, 0, c->stream>>>((const double*)native + b.native_off, canon + b.canon_off, b.n, b.E, b.nsp);
+    k_unpack32<<<grid_for(tot, 256), 256, 0, c->stream>>>((const float*)native + b.native_off, canon + b.canon_off,
+                                                          b.n, b.E, b.nsp, ref, 1);
   }
   HIP_TRY(c, hipGetLastError());
   return FR_OK;
 }
 
+fr_status fr_unpack_rhs(fr_ctx c, const void* r, double* canon) {
+  if (!c || !canon || !r) return fail(c, FR_ERR_ARG, "NULL argument");
+  if (c->prm.precision == FR_FP64) return unpack64(c, (const double*)r, canon);
+  const RefVec ref = refvec(c->prm);
+  for (auto& b : c->blocks) {
+    const int64_t tot = b.n * 5 * b.nsp;
+    k_unpack32<<<grid_for(tot, 256), 256, 0, c->stream>>>((const float*)r + b.native_off, canon + b.canon_off, b.n,
+                                                          b.E, b.nsp, ref, 0);
+  }
+  HIP_TRY(c, hipGetLastError());
+  return FR_OK;
+}
+
+fr_status fr_pack64(fr_ctx c, const double* canon, double* native) {
+  if (!c || !canon || !native) return fail(c, FR_ERR_ARG, "NULL argument");
+  return pack64(c, canon, native);
+}
+
+fr_status fr_unpack64(fr_ctx c, const double* native, double* canon) {
+  if (!c || !canon || !native) return fail(c, FR_ERR_ARG, "NULL argument");
+  return unpack64(c, native, canon);
+}
+
 fr_status fr_rhs(fr_ctx c, const void* u, void* r) {
   if (!c || !u || !r) return fail(c, FR_ERR_ARG, "NULL argument");
   if (u == r) return fail(c, FR_ERR_ARG, "u and r must not alias");
-  return rhs_fp64(c, (const double*)u, (double*)r);
+  return rhs_native(c, u, r);
 }
 
 fr_status fr_rk_step(fr_ctx c, void* u_, double dt, int32_t n_steps, int32_t filter_mode) {
@@ -406,33 +564,66 @@ fr_status fr_rk_step(fr_ctx c, void* u_, double dt, int32_t n_steps, int32_t fil
   if (filter_mode != -1) return fail(c, FR_ERR_UNSUPPORTED, "filter not yet available");
   double* u = (double*)u_;
   const int64_t n = c->native_len;
+  const bool f32 = c->prm.precision == FR_FP32;
+  const size_t tsz = f32 ? sizeof(float) : sizeof(double);
   if (!c->rk_stage) {
-    if (dalloc(c, &c->rk_stage, n) || dalloc(c, &c->rk_acc, n) || dalloc(c, &c->rk_k, n)) return FR_ERR_ALLOC;
+    if (dalloc(c, (char**)&c->rk_stage, n * tsz) || dalloc(c, &c->rk_acc, n) || dalloc(c, (char**)&c->rk_k, n * tsz))
+      return FR_ERR_ALLOC;
     // padding lanes are never written by the RHS: keep them defined (zero increments)
-    HIP_TRY(c, hipMemsetAsync(c->rk_k, 0, n * sizeof(double), c->stream));
-    HIP_TRY(c, hipMemsetAsync(c->rk_stage, 0, n * sizeof(double), c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->rk_k, 0, n * tsz, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->rk_stage, 0, n * tsz, c->stream));
     HIP_TRY(c, hipMemsetAsync(c->rk_acc, 0, n * sizeof(double), c->stream));
   }
   const int g = grid_for(n, 256);
-  for (int s = 0; s < n_steps; ++s) {
-    fr_status st;
-    int pk;
-    if ((st = rhs_fp64(c, u, c->rk_k))) return st;
-    pk = c->prof_begin("rk4_update");
-    k_rk_first<<<g, 256, 0, c->stream>>>(u, c->rk_k, c->rk_acc, c->rk_stage, n, dt / 6.0, dt / 2.0);
-    c->prof_end(pk);
-    if ((st = rhs_fp64(c, c->rk_stage, c->rk_k))) return st;
-    pk = c->prof_begin("rk4_update");
-    k_rk_mid<<<g, 256, 0, c->stream>>>(u, c->rk_k, c->rk_acc, c->rk_stage, n, dt / 3.0, dt / 2.0);
-    c->prof_end(pk);
-    if ((st = rhs_fp64(c, c->rk_stage, c->rk_k))) return st;
-    pk = c->prof_begin("rk4_update");
-    k_rk_mid<<<g, 256, 0, c->stream>>>(u, c->rk_k, c->rk_acc, c->rk_stage, n, dt / 3.0, dt);
-    c->prof_end(pk);
-    if ((st = rhs_fp64(c, c->rk_stage, c->rk_k))) return st;
-    pk = c->prof_begin("rk4_update");
-    k_rk_last<<<g, 256, 0, c->stream>>>(u, c->rk_k, c->rk_acc, n, dt / 6.0);
-    c->prof_end(pk);
+  const double b1 = dt / 6.0, b2 = dt / 3.0, c2 = dt / 2.0;
+  fr_status st;
+  int pk;
+  if (!f32) {
+    double *K = (double*)c->rk_k, *S = (double*)c->rk_stage;
+    for (int s = 0; s < n_steps; ++s) {
+      if ((st = rhs_native(c, u, K))) return st;
+      pk = c->prof_begin("rk4_update");
+      k_rk_first<<<g, 256, 0, c->stream>>>(u, K, c->rk_acc, S, n, b1, c2);
+      c->prof_end(pk);
+      if ((st = rhs_native(c, S, K))) return st;
+      pk = c->prof_begin("rk4_update");
+      k_rk_mid<<<g, 256, 0, c->stream>>>(u, K, c->rk_acc, S, n, b2, c2);
+      c->prof_end(pk);
+      if ((st = rhs_native(c, S, K))) return st;
+      pk = c->prof_begin("rk4_update");
+      k_rk_mid<<<g, 256, 0, c->stream>>>(u, K, c->rk_acc, S, n, b2, dt);
+      c->prof_end(pk);
+      if ((st = rhs_native(c, S, K))) return st;
+      pk = c->prof_begin("rk4_update");
+      k_rk_last<<<g, 256, 0, c->stream>>>(u, K, c->rk_acc, n, b1);
+      c->prof_end(pk);
+    }
+  } else {
+    float *K = (float*)c->rk_k, *S = (float*)c->rk_stage;
+    const RefVec ref = refvec(c->prm);
+    // the FP32 deviation of u_n; later steps get it from the previous step's last update
+    for (auto& b : c->blocks) {
+      const int64_t nb = (int64_t)b.nsp * 5 * b.E;
+      k_to_dev<<<grid_for(nb, 256), 256, 0, c->stream>>>(u + b.native_off, S + b.native_off, nb, b.E, ref);
+    }
+    for (int s = 0; s < n_steps; ++s) {
+      for (int stage = 0; stage < 4; ++stage) {
+        if ((st = rhs_native(c, S, K))) return st;
+        pk = c->prof_begin("rk4_update_f32");
+        for (auto& b : c->blocks) {
+          const int64_t nb = (int64_t)b.nsp * 5 * b.E, o = b.native_off;
+          const int gb = grid_for(nb, 256);
+          if (stage == 0)
+            k_rk32_first<<<gb, 256, 0, c->stream>>>(u + o, K + o, c->rk_acc + o, S + o, nb, b.E, b1, c2, ref);
+          else if (stage < 3)
+            k_rk32_mid<<<gb, 256, 0, c->stream>>>(u + o, K + o, c->rk_acc + o, S + o, nb, b.E, b2,
+                                                  stage == 1 ? c2 : dt, ref);
+          else
+            k_rk32_last<<<gb, 256, 0, c->stream>>>(u + o, K + o, c->rk_acc + o, S + o, nb, b.E, b1, ref);
+        }
+        c->prof_end(pk);
+      }
+    }
   }
   HIP_TRY(c, hipGetLastError());
   return FR_OK;

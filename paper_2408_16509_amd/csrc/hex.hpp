@@ -1,4 +1,4 @@
-// Hexahedral FR kernels (order P, Gauss--Legendre points), FP64.
+// Hexahedral FR kernels (order P, Gauss--Legendre points).
 //
 // Native layout: state u[(pt*5 + v)*E + e] (element fastest, E = padded count),
 // traces uf[(fp*5 + v)*E + e], gradients grad[(pt*15 + v*3 + j)*E + e] and
@@ -15,7 +15,14 @@
 // normal flux at the ends never needs forming.  Each thread owns one line of one
 // element per direction pass; the three directions' contributions meet in LDS.
 // The geometric map is trilinear and evaluated on the fly from its 24 monomial
-// coefficients (metric terms of linear elements computed from the corners).
+// coefficients (metric terms of linear elements computed from the corners),
+// staged per block in LDS.
+//
+// Arithmetic type T: double (the plain form) or float.  In the float form the
+// state is the deviation du = u - u_ref from a constant state at rest and every
+// flux is evaluated as f(u) - f(u_ref) in cancellation-free form (Flux<T, DEV>);
+// this changes nothing in exact arithmetic because the transformed flux of a
+// constant state has zero discrete divergence and zero interface jump.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -24,30 +31,132 @@
 
 namespace frmi {
 
+template <typename T>
 struct HexK {
-  double x[5], lm[5], lp[5], Dh[5][5], cp[5], cm[5];
+  T x[5], lm[5], lp[5], Dh[5][5], cp[5], cm[5];
+};
+
+// Reference state of the deviation form (at rest): rho0, E0, p0 = (gamma-1)E0, H0 = E0 + p0.
+template <typename T>
+struct RefState {
+  T rho0, E0, p0, H0;
 };
 
 struct Conn {
-  const int32_t* nbr_elem;   // [6][E]
-  const int32_t* nbr_info;   // [6][E] nbr_face | orient << 3 | is_left << 12
+  const int32_t* nbr_elem;   // [nfaces][E]
+  const int32_t* nbr_info;   // [nfaces][E] nbr_face | orient << 3 | is_left << 12
   const int32_t* perm;       // [n_orient][stride]
   int32_t perm_stride;
 };
 
+// Inviscid flux along s and the quantities the Riemann solvers need.  DEV: the
+// state holds du and the flux returned is f(u).s - f(u_ref).s.
+template <typename T, bool DEV>
+struct Flux {
+  __device__ __forceinline__ static void eval(const T w[5], T sx, T sy, T sz, T gm1, const RefState<T>& R,
+                                              T f[5], T& vs, T& p_full) {
+    if constexpr (!DEV) {
+      flux_dir(w, sx, sy, sz, gm1, f, vs, p_full);
+    } else {
+      const T rho = R.rho0 + w[0];
+      const T ir = T(1) / rho;
+      const T vx = w[1] * ir, vy = w[2] * ir, vz = w[3] * ir;
+      const T dp = gm1 * (w[4] - T(0.5) * (w[1] * vx + w[2] * vy + w[3] * vz));
+      vs = vx * sx + vy * sy + vz * sz;
+      f[0] = w[1] * sx + w[2] * sy + w[3] * sz;
+      f[1] = w[1] * vs + dp * sx;
+      f[2] = w[2] * vs + dp * sy;
+      f[3] = w[3] * vs + dp * sz;
+      f[4] = (R.H0 + w[4] + dp) * vs;
+      p_full = R.p0 + dp;
+    }
+  }
+  __device__ __forceinline__ static T rho(const T w[5], const RefState<T>& R) {
+    if constexpr (DEV) return R.rho0 + w[0];
+    else return w[0];
+  }
+};
+
+// Rusanov / HLLC on (possibly deviation) states.  In the deviation form the
+// constant f(u_ref).n is subtracted, which leaves every solver's formula intact
+// because solvers are consistent (𝔉(u, u, n) = f(u).n).
+template <typename T, bool DEV>
+__device__ __forceinline__ void common_inviscid(int kind, const T uL[5], const T uR[5], const T n[3], T gamma,
+                                                const RefState<T>& R, T F[5]) {
+  const T gm1 = gamma - T(1);
+  T fL[5], fR[5], vnL, vnR, pL, pR;
+  Flux<T, DEV>::eval(uL, n[0], n[1], n[2], gm1, R, fL, vnL, pL);
+  Flux<T, DEV>::eval(uR, n[0], n[1], n[2], gm1, R, fR, vnR, pR);
+  const T rL = Flux<T, DEV>::rho(uL, R), rR = Flux<T, DEV>::rho(uR, R);
+  const T cL = sqrt(gamma * pL / rL), cR = sqrt(gamma * pR / rR);
+  if (kind != 1) {
+    const T lam = fmax(fabs(vnL) + cL, fabs(vnR) + cR);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) F[v] = T(0.5) * (fL[v] + fR[v]) - T(0.5) * lam * (uR[v] - uL[v]);
+    return;
+  }
+  const T SL = fmin(vnL - cL, vnR - cR);
+  const T SR = fmax(vnL + cL, vnR + cR);
+  // pR - pL from the deviation pressures in the float form (same value in exact arithmetic)
+  const T dpLR = pR - pL;
+  const T Ss = (dpLR + rL * vnL * (SL - vnL) - rR * vnR * (SR - vnR)) / (rL * (SL - vnL) - rR * (SR - vnR));
+  if (T(0) <= SL) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) F[v] = fL[v];
+    return;
+  }
+  const bool left = T(0) <= Ss;
+  if (!left && !(T(0) < SR)) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) F[v] = fR[v];
+    return;
+  }
+  const T* wK = left ? uL : uR;
+  const T* fK = left ? fL : fR;
+  const T S = left ? SL : SR, vn = left ? vnL : vnR, p = left ? pL : pR, r = left ? rL : rR;
+  // U*_K - U_K written without forming U*_K (no cancellation of the total energy):
+  //   mass: r (Ss - vn)/(S - Ss); momentum: that times v + fac (Ss - vn) n;
+  //   energy: (Ss - vn)/(S - Ss) [r (S - vn) Ss + p + E]
+  const T fac = r * (S - vn) / (S - Ss);
+  const T q = (Ss - vn) / (S - Ss);
+  const T E = DEV ? R.E0 + wK[4] : wK[4];
+  T dU[5];
+  dU[0] = r * q;
+  dU[1] = wK[1] * q + fac * (Ss - vn) * n[0];
+  dU[2] = wK[2] * q + fac * (Ss - vn) * n[1];
+  dU[3] = wK[3] * q + fac * (Ss - vn) * n[2];
+  dU[4] = q * (r * (S - vn) * Ss + p + E);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) F[v] = fK[v] + S * dU[v];
+}
+
+// Viscous flux along s from (possibly deviation) state and its gradient.
+template <typename T, bool DEV>
+__device__ __forceinline__ void viscous(const T w[5], const T g[15], T sx, T sy, T sz, T gamma, T mu, T pr,
+                                        const RefState<T>& R, T fv[5]) {
+  T u[5] = {w[0], w[1], w[2], w[3], w[4]};
+  if constexpr (DEV) { u[0] += R.rho0; u[4] += R.E0; }
+  viscous_dir(u, g, sx, sy, sz, gamma, mu, pr, fv);
+}
+
 // Columns of G = dx/dxi at reference point (a, b, d) of a trilinear map with
-// monomial coefficients c[comp*8 + S], S in {1, a, b, d, ab, ad, bd, abd}.
-__device__ __forceinline__ void hex_cols(const double* c, double a, double b, double d, double g[3][3]) {
+// monomial coefficients c[comp*8 + S], S in {1, a, b, d, ab, ad, bd, abd}; c is
+// read through the stride `cs` (LDS staging).
+template <typename T>
+__device__ __forceinline__ void hex_cols(const T* c, int cs, T a, T b, T d, T g[3][3]) {
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    const double* q = c + k * 8;
-    g[0][k] = q[1] + q[4] * b + q[5] * d + q[7] * b * d;
-    g[1][k] = q[2] + q[4] * a + q[6] * d + q[7] * a * d;
-    g[2][k] = q[3] + q[5] * a + q[6] * b + q[7] * a * b;
+    const T* q = c + k * 8 * cs;
+    const T q1 = q[1 * cs], q2 = q[2 * cs], q3 = q[3 * cs], q4 = q[4 * cs];
+    const T q5 = q[5 * cs], q6 = q[6 * cs], q7 = q[7 * cs];
+    g[0][k] = q1 + q4 * b + q5 * d + q7 * b * d;
+    g[1][k] = q2 + q4 * a + q6 * d + q7 * a * d;
+    g[2][k] = q3 + q5 * a + q6 * b + q7 * a * b;
   }
 }
 
-__device__ __forceinline__ void cross3(const double* u, const double* v, double* w) {
+template <typename T>
+__device__ __forceinline__ void cross3(const T* u, const T* v, T* w) {
   w[0] = u[1] * v[2] - u[2] * v[1];
   w[1] = u[2] * v[0] - u[0] * v[2];
   w[2] = u[0] * v[1] - u[1] * v[0];
@@ -58,52 +167,68 @@ __device__ __forceinline__ int line_pt(int d, int a, int t0, int t1) {
   return d == 0 ? a + N1 * (t0 + N1 * t1) : (d == 1 ? t0 + N1 * (a + N1 * t1) : t0 + N1 * (t1 + N1 * a));
 }
 
-template <int N1>
-__device__ __forceinline__ void line_xi(const HexK& K, int d, int a, int t0, int t1, double xi[3]) {
-  const double ta = K.x[t0], tb = K.x[t1], xa = K.x[a];
+template <typename T>
+__device__ __forceinline__ void line_xi(const HexK<T>& K, int d, int a, int t0, int t1, T xi[3]) {
+  const T ta = K.x[t0], tb = K.x[t1], xa = K.x[a];
   xi[0] = d == 0 ? xa : ta;
   xi[1] = d == 0 ? ta : (d == 1 ? xa : tb);
   xi[2] = d == 2 ? xa : tb;
 }
 
-template <int N1>
-__device__ __forceinline__ void end_xi(const HexK& K, int d, int s, int t0, int t1, double xi[3]) {
-  const double ta = K.x[t0], tb = K.x[t1], xe = s ? 1.0 : -1.0;
+template <typename T>
+__device__ __forceinline__ void end_xi(const HexK<T>& K, int d, int s, int t0, int t1, T xi[3]) {
+  const T ta = K.x[t0], tb = K.x[t1], xe = s ? T(1) : T(-1);
   xi[0] = d == 0 ? xe : ta;
   xi[1] = d == 0 ? ta : (d == 1 ? xe : tb);
   xi[2] = d == 2 ? xe : tb;
 }
 
 // S row d = g_{d+1} x g_{d+2}: row d of J G^{-1}.
-__device__ __forceinline__ void srow(const double g[3][3], int d, double s[3]) {
+template <typename T>
+__device__ __forceinline__ void srow(const T g[3][3], int d, T s[3]) {
   if (d == 0) cross3(g[1], g[2], s);
   else if (d == 1) cross3(g[2], g[0], s);
   else cross3(g[0], g[1], s);
 }
 
-// Neighbour flux-point slot of end s of line (d, q) of element e.
+template <typename T>
+__device__ __forceinline__ T det_cols(const T g[3][3]) {
+  T cr[3];
+  cross3(g[1], g[2], cr);
+  return g[0][0] * cr[0] + g[0][1] * cr[1] + g[0][2] * cr[2];
+}
+
+// Neighbour flux-point slot of end `face` / face-local point q of element e.
 struct NbrSlot {
   int64_t elem;
   int fp;
   bool left;
 };
 
-template <int N1>
+template <int NFPF>
 __device__ __forceinline__ NbrSlot nbr_slot(const Conn& C, int64_t E, int64_t e, int face, int q) {
   const int info = C.nbr_info[(int64_t)face * E + e];
   NbrSlot s;
   s.elem = C.nbr_elem[(int64_t)face * E + e];
   const int nf = info & 7, orient = (info >> 3) & 511;
   s.left = (info >> 12) & 1;
-  s.fp = nf * N1 * N1 + C.perm[orient * C.perm_stride + q];
+  s.fp = nf * NFPF + C.perm[orient * C.perm_stride + q];
   return s;
+}
+
+// Stage the block's geometry coefficients into LDS: G[g*NE + el].
+template <typename T, int NE, int NT>
+__device__ __forceinline__ void stage_geo(const T* __restrict__ geo, int64_t E, int64_t e0, T* G) {
+  for (int i = threadIdx.x; i < 24 * NE; i += NT) {
+    const int g = i / NE, el = i % NE;
+    G[i] = geo[(int64_t)g * E + e0 + el];
+  }
 }
 
 // ---------------------------------------------------------------------------
 // Step 1 (eq:disu) at the flux points: traces of u at both ends of every line.
-template <int P>
-__global__ void __launch_bounds__(256) hex_trace(const double* __restrict__ u, double* __restrict__ uf,
-                                                 int64_t E, HexK K) {
+template <typename T, int P>
+__global__ void __launch_bounds__(256) hex_trace(const T* __restrict__ u, T* __restrict__ uf, int64_t E, HexK<T> K) {
   constexpr int N1 = P + 1, NL = 3 * N1 * N1;
   const int64_t gtid = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t wave = gtid >> 6;
@@ -113,13 +238,13 @@ __global__ void __launch_bounds__(256) hex_trace(const double* __restrict__ u, d
   const int64_t e = tile * 64 + lane;
   if (e >= E) return;
   const int d = l / (N1 * N1), q = l % (N1 * N1), t0 = q % N1, t1 = q / N1;
-  double m[5] = {0, 0, 0, 0, 0}, p[5] = {0, 0, 0, 0, 0};
+  T m[5] = {0, 0, 0, 0, 0}, p[5] = {0, 0, 0, 0, 0};
 #pragma unroll
   for (int a = 0; a < N1; ++a) {
     const int pt = line_pt<N1>(d, a, t0, t1);
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-      const double val = u[((int64_t)pt * 5 + v) * E + e];
+      const T val = u[((int64_t)pt * 5 + v) * E + e];
       m[v] += K.lm[a] * val;
       p[v] += K.lp[a] * val;
     }
@@ -132,161 +257,179 @@ __global__ void __launch_bounds__(256) hex_trace(const double* __restrict__ u, d
   }
 }
 
+// Accumulate one direction's divergence contribution into LDS and, in the last
+// pass, write R = -div / J.
+template <typename T, int N1, int NE>
+__device__ __forceinline__ void accumulate_div(int d, const T (&ft)[5][N1], const T (&Fc)[2][5], const HexK<T>& K,
+                                               T* DIV, const T* G, int el, int t0, int t1, int64_t e, int64_t n,
+                                               int64_t E, T* __restrict__ r) {
+  constexpr int NSP = N1 * N1 * N1;
+#pragma unroll
+  for (int a = 0; a < N1; ++a) {
+    const int pt = line_pt<N1>(d, a, t0, t1);
+    T div[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      T acc = K.cp[a] * Fc[1][v] + K.cm[a] * Fc[0][v];
+#pragma unroll
+      for (int b = 0; b < N1; ++b) acc += K.Dh[a][b] * ft[v][b];
+      div[v] = acc;
+    }
+    T* D = DIV + (pt * NE + el);
+    if (d == 0) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) D[v * NSP * NE] = div[v];
+    } else if (d == 1) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) D[v * NSP * NE] += div[v];
+    } else {
+      T xi[3], g[3][3];
+      line_xi(K, d, a, t0, t1, xi);
+      hex_cols(G + el, NE, xi[0], xi[1], xi[2], g);
+      const T iJ = T(-1) / det_cols(g);
+      if (e < n) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) r[((int64_t)pt * 5 + v) * E + e] = (D[v * NSP * NE] + div[v]) * iJ;
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Steps 2-4 for Euler, fused: per line, own traces, neighbour traces, common flux
 // (eq:comm_flux) at both ends, transformed flux at the line points and the
 // corrected divergence (eq:FRfinal); R = -div / J.
-template <int P, int NE>
+template <typename T, bool DEV, int P, int NE>
 __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_div_euler(
-    const double* __restrict__ u, const double* __restrict__ uf, const double* __restrict__ geo,
-    Conn C, double* __restrict__ r, int64_t E, int64_t n, HexK K, Phys ph) {
-  constexpr int N1 = P + 1, NSP = N1 * N1 * N1;
-  __shared__ double DIV[5 * NSP * NE];
+    const T* __restrict__ u, const T* __restrict__ uf, const T* __restrict__ geo,
+    Conn C, T* __restrict__ r, int64_t E, int64_t n, HexK<T> K, T gamma, int riemann, RefState<T> R) {
+  constexpr int N1 = P + 1, NSP = N1 * N1 * N1, NF = N1 * N1, NT = NE * N1 * N1;
+  __shared__ T DIV[5 * NSP * NE];
+  __shared__ T G[24 * NE];
   const int el = threadIdx.x % NE, l = threadIdx.x / NE;
-  const int64_t e = (int64_t)blockIdx.x * NE + el;
+  const int64_t e0 = (int64_t)blockIdx.x * NE, e = e0 + el;
   const int t0 = l % N1, t1 = l / N1;
-  double c[24];
-#pragma unroll
-  for (int g = 0; g < 24; ++g) c[g] = geo[(int64_t)g * E + e];
-  const double gam = ph.gamma, gm1 = ph.gamma - 1.0;
+  stage_geo<T, NE, NT>(geo, E, e0, G);
+  __syncthreads();
+  const T gm1 = gamma - T(1);
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    double ft[5][N1], tm[5] = {0, 0, 0, 0, 0}, tp[5] = {0, 0, 0, 0, 0};
+    T ft[5][N1], tm[5] = {0, 0, 0, 0, 0}, tp[5] = {0, 0, 0, 0, 0};
 #pragma unroll
     for (int a = 0; a < N1; ++a) {
       const int pt = line_pt<N1>(d, a, t0, t1);
-      double uu[5];
+      T uu[5];
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
         uu[v] = u[((int64_t)pt * 5 + v) * E + e];
         tm[v] += K.lm[a] * uu[v];
         tp[v] += K.lp[a] * uu[v];
       }
-      double xi[3], g[3][3], s[3], f[5], vs, pr;
-      line_xi<N1>(K, d, a, t0, t1, xi);
-      hex_cols(c, xi[0], xi[1], xi[2], g);
+      T xi[3], g[3][3], s[3], f[5], vs, pr;
+      line_xi(K, d, a, t0, t1, xi);
+      hex_cols(G + el, NE, xi[0], xi[1], xi[2], g);
       srow(g, d, s);
-      flux_dir(uu, s[0], s[1], s[2], gm1, f, vs, pr);
+      Flux<T, DEV>::eval(uu, s[0], s[1], s[2], gm1, R, f, vs, pr);
 #pragma unroll
       for (int v = 0; v < 5; ++v) ft[v][a] = f[v];
     }
-    double Fc[2][5];
+    T Fc[2][5];
 #pragma unroll
     for (int sd = 0; sd < 2; ++sd) {
-      double xi[3], g[3][3], nv[3];
-      end_xi<N1>(K, d, sd, t0, t1, xi);
-      hex_cols(c, xi[0], xi[1], xi[2], g);
+      T xi[3], g[3][3], nv[3];
+      end_xi(K, d, sd, t0, t1, xi);
+      hex_cols(G + el, NE, xi[0], xi[1], xi[2], g);
       srow(g, d, nv);
-      const double sg = sd ? 1.0 : -1.0;
-      const double mag = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
-      const int face = 2 * d + sd;
-      const NbrSlot ns = nbr_slot<N1>(C, E, e, face, l);
-      double un[5];
+      const T sg = sd ? T(1) : T(-1);
+      const T mag = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+      const NbrSlot ns = nbr_slot<NF>(C, E, e, 2 * d + sd, l);
+      T un[5];
 #pragma unroll
       for (int v = 0; v < 5; ++v) un[v] = uf[((int64_t)ns.fp * 5 + v) * E + ns.elem];
-      const double* own = sd ? tp : tm;
-      double uL[5], uR[5], nL[3], F[5];
+      const T* own = sd ? tp : tm;
+      T uL[5], uR[5], nL[3], F[5];
 #pragma unroll
       for (int v = 0; v < 5; ++v) { uL[v] = ns.left ? own[v] : un[v]; uR[v] = ns.left ? un[v] : own[v]; }
-      const double sl = (ns.left ? sg : -sg) / mag;
+      const T sl = (ns.left ? sg : -sg) / mag;
 #pragma unroll
       for (int k = 0; k < 3; ++k) nL[k] = nv[k] * sl;
-      riemann(ph.riemann, uL, uR, nL, gam, F);
-      const double fs = ns.left ? mag : -mag;
+      common_inviscid<T, DEV>(riemann, uL, uR, nL, gamma, R, F);
+      const T fs = ns.left ? mag : -mag;
 #pragma unroll
       for (int v = 0; v < 5; ++v) Fc[sd][v] = fs * F[v];
     }
-#pragma unroll
-    for (int a = 0; a < N1; ++a) {
-      const int pt = line_pt<N1>(d, a, t0, t1);
-      double div[5];
-#pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        double acc = K.cp[a] * Fc[1][v] + K.cm[a] * Fc[0][v];
-#pragma unroll
-        for (int b = 0; b < N1; ++b) acc += K.Dh[a][b] * ft[v][b];
-        div[v] = acc;
-      }
-      double* D = DIV + (pt * NE + el);
-      if (d == 0) {
-#pragma unroll
-        for (int v = 0; v < 5; ++v) D[v * NSP * NE] = div[v];
-      } else if (d == 1) {
-#pragma unroll
-        for (int v = 0; v < 5; ++v) D[v * NSP * NE] += div[v];
-      } else {
-        double xi[3], g[3][3], s[3];
-        line_xi<N1>(K, d, a, t0, t1, xi);
-        hex_cols(c, xi[0], xi[1], xi[2], g);
-        cross3(g[1], g[2], s);
-        const double iJ = -1.0 / (g[0][0] * s[0] + g[0][1] * s[1] + g[0][2] * s[2]);
-        if (e < n) {
-#pragma unroll
-          for (int v = 0; v < 5; ++v) r[((int64_t)pt * 5 + v) * E + e] = (D[v * NSP * NE] + div[v]) * iJ;
-        }
-      }
-    }
+    accumulate_div<T, N1, NE>(d, ft, Fc, K, DIV, G, el, t0, t1, e, n, E, r);
     if (d < 2) __syncthreads();
   }
 }
 
 // ---------------------------------------------------------------------------
-// Navier--Stokes phase 1: corrected gradient (LDG common solution u^ at the
-// flux points), physical gradient at the solution points, and its traces.
-template <int P, int NE>
+// Navier--Stokes phase 1: corrected gradient (LDG common solution u^ at the flux
+// points), physical gradient at the solution points, and its traces at the flux
+// points that the viscous common flux will read.  side_mode: +1 when beta = +1/2
+// (u^ = u_L, the viscous common flux takes the right side only: the left side's
+// jump vanishes and only right-side traces are stored), -1 for beta = -1/2 (the
+// mirror case), 0 in general.
+template <typename T, int P, int NE>
 __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_grad(
-    const double* __restrict__ u, const double* __restrict__ uf, const double* __restrict__ geo,
-    Conn C, double* __restrict__ grad, double* __restrict__ gradf, int64_t E, HexK K, Phys ph) {
-  constexpr int N1 = P + 1, NSP = N1 * N1 * N1, NF = N1 * N1;
-  __shared__ double GR[3 * NSP * NE];
+    const T* __restrict__ u, const T* __restrict__ uf, const T* __restrict__ geo,
+    Conn C, T* __restrict__ grad, T* __restrict__ gradf, int64_t E, HexK<T> K, T beta, int side_mode) {
+  constexpr int N1 = P + 1, NSP = N1 * N1 * N1, NF = N1 * N1, NT = NE * N1 * N1;
+  __shared__ T GR[3 * NSP * NE];
+  __shared__ T G[24 * NE];
   const int el = threadIdx.x % NE, l = threadIdx.x / NE;
-  const int64_t e = (int64_t)blockIdx.x * NE + el;
+  const int64_t e0 = (int64_t)blockIdx.x * NE, e = e0 + el;
   const int t0 = l % N1, t1 = l / N1;
-  double c[24];
+  stage_geo<T, NE, NT>(geo, E, e0, G);
+  // connectivity of this thread's 6 line ends
+  NbrSlot ns[3][2];
 #pragma unroll
-  for (int g = 0; g < 24; ++g) c[g] = geo[(int64_t)g * E + e];
-  const double beta = ph.beta;
+  for (int d = 0; d < 3; ++d)
+#pragma unroll
+    for (int sd = 0; sd < 2; ++sd) ns[d][sd] = nbr_slot<NF>(C, E, e, 2 * d + sd, l);
+  __syncthreads();
   for (int v = 0; v < 5; ++v) {
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      double uv[N1], tm = 0, tp = 0;
+      T uv[N1], tm = 0, tp = 0;
 #pragma unroll
       for (int a = 0; a < N1; ++a) {
         uv[a] = u[((int64_t)line_pt<N1>(d, a, t0, t1) * 5 + v) * E + e];
         tm += K.lm[a] * uv[a];
         tp += K.lp[a] * uv[a];
       }
-      double uh[2];
+      T uh[2];
 #pragma unroll
       for (int sd = 0; sd < 2; ++sd) {
-        const NbrSlot ns = nbr_slot<N1>(C, E, e, 2 * d + sd, l);
-        const double un = uf[((int64_t)ns.fp * 5 + v) * E + ns.elem];
-        const double own = sd ? tp : tm;
-        const double uL = ns.left ? own : un, uR = ns.left ? un : own;
-        uh[sd] = 0.5 * (uL + uR) + beta * (uL - uR);
+        const NbrSlot& s = ns[d][sd];
+        const T own = sd ? tp : tm;
+        // the common value equals the own trace when the switch points at this side
+        const bool need = side_mode == 0 || (side_mode > 0 ? !s.left : s.left);
+        T un = own;
+        if (need) un = uf[((int64_t)s.fp * 5 + v) * E + s.elem];
+        const T uL = s.left ? own : un, uR = s.left ? un : own;
+        uh[sd] = need ? T(0.5) * (uL + uR) + beta * (uL - uR) : own;
       }
 #pragma unroll
       for (int a = 0; a < N1; ++a) {
-        double gt = K.cp[a] * uh[1] - K.cm[a] * uh[0];
+        T gt = K.cp[a] * uh[1] - K.cm[a] * uh[0];
 #pragma unroll
         for (int b = 0; b < N1; ++b) gt += K.Dh[a][b] * uv[b];
-        double xi[3], g[3][3], s[3], cr[3];
-        line_xi<N1>(K, d, a, t0, t1, xi);
-        hex_cols(c, xi[0], xi[1], xi[2], g);
+        T xi[3], g[3][3], s[3];
+        line_xi(K, d, a, t0, t1, xi);
+        hex_cols(G + el, NE, xi[0], xi[1], xi[2], g);
         srow(g, d, s);
-        cross3(g[1], g[2], cr);
-        const double sc = gt / (g[0][0] * cr[0] + g[0][1] * cr[1] + g[0][2] * cr[2]);
+        const T sc = gt / det_cols(g);
         const int pt = line_pt<N1>(d, a, t0, t1);
-        double* G = GR + (pt * NE + el);
+        T* Gp = GR + (pt * NE + el);
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-          if (d == 0) G[j * NSP * NE] = s[j] * sc;
-          else G[j * NSP * NE] += s[j] * sc;
+          if (d == 0) Gp[j * NSP * NE] = s[j] * sc;
+          else Gp[j * NSP * NE] += s[j] * sc;
         }
       }
       __syncthreads();
     }
-    // gradient at the solution points of this thread's column, then traces
 #pragma unroll
     for (int a = 0; a < N1; ++a) {
       const int pt = line_pt<N1>(2, a, t0, t1);
@@ -295,22 +438,25 @@ __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_grad(
     }
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      double gm[3] = {0, 0, 0}, gp[3] = {0, 0, 0};
+      T gm[3] = {0, 0, 0}, gp[3] = {0, 0, 0};
 #pragma unroll
       for (int a = 0; a < N1; ++a) {
         const int pt = line_pt<N1>(d, a, t0, t1);
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-          const double val = GR[(j * NSP + pt) * NE + el];
+          const T val = GR[(j * NSP + pt) * NE + el];
           gm[j] += K.lm[a] * val;
           gp[j] += K.lp[a] * val;
         }
       }
-      const int fm = 2 * d * NF + l, fp = (2 * d + 1) * NF + l;
 #pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        gradf[((int64_t)fm * 15 + v * 3 + j) * E + e] = gm[j];
-        gradf[((int64_t)fp * 15 + v * 3 + j) * E + e] = gp[j];
+      for (int sd = 0; sd < 2; ++sd) {
+        // stored only where a neighbour will read it
+        const bool keep = side_mode == 0 || (side_mode > 0 ? !ns[d][sd].left : ns[d][sd].left);
+        if (!keep) continue;
+        const int f = (2 * d + sd) * NF + l;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) gradf[((int64_t)f * 15 + v * 3 + j) * E + e] = sd ? gp[j] : gm[j];
       }
     }
     __syncthreads();
@@ -320,28 +466,30 @@ __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_grad(
 // ---------------------------------------------------------------------------
 // Navier--Stokes phase 2: f = f_inv - f_v at the solution points, LDG common
 // flux (inviscid Riemann flux minus the switched viscous flux plus the penalty)
-// at the line ends, corrected divergence.
-template <int P, int NE>
+// at the line ends, corrected divergence.  The own side's gradient trace at a
+// line end comes from the line's own solution-point gradients.
+template <typename T, bool DEV, int P, int NE>
 __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_div_ns(
-    const double* __restrict__ u, const double* __restrict__ uf, const double* __restrict__ grad,
-    const double* __restrict__ gradf, const double* __restrict__ geo, Conn C, double* __restrict__ r,
-    int64_t E, int64_t n, HexK K, Phys ph) {
-  constexpr int N1 = P + 1, NSP = N1 * N1 * N1;
-  __shared__ double DIV[5 * NSP * NE];
+    const T* __restrict__ u, const T* __restrict__ uf, const T* __restrict__ grad,
+    const T* __restrict__ gradf, const T* __restrict__ geo, Conn C, T* __restrict__ r,
+    int64_t E, int64_t n, HexK<T> K, T gamma, T mu, T pr, T beta, T tau, int riemann, int side_mode,
+    RefState<T> R) {
+  constexpr int N1 = P + 1, NSP = N1 * N1 * N1, NF = N1 * N1, NT = NE * N1 * N1;
+  __shared__ T DIV[5 * NSP * NE];
+  __shared__ T G[24 * NE];
   const int el = threadIdx.x % NE, l = threadIdx.x / NE;
-  const int64_t e = (int64_t)blockIdx.x * NE + el;
+  const int64_t e0 = (int64_t)blockIdx.x * NE, e = e0 + el;
   const int t0 = l % N1, t1 = l / N1;
-  double c[24];
-#pragma unroll
-  for (int g = 0; g < 24; ++g) c[g] = geo[(int64_t)g * E + e];
-  const double gam = ph.gamma, gm1 = ph.gamma - 1.0, mu = ph.mu, pr = ph.prandtl;
+  stage_geo<T, NE, NT>(geo, E, e0, G);
+  __syncthreads();
+  const T gm1 = gamma - T(1);
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    double ft[5][N1], tm[5] = {0, 0, 0, 0, 0}, tp[5] = {0, 0, 0, 0, 0};
+    T ft[5][N1], tm[5] = {0, 0, 0, 0, 0}, tp[5] = {0, 0, 0, 0, 0};
 #pragma unroll
     for (int a = 0; a < N1; ++a) {
       const int pt = line_pt<N1>(d, a, t0, t1);
-      double uu[5], gg[15];
+      T uu[5], gg[15];
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
         uu[v] = u[((int64_t)pt * 5 + v) * E + e];
@@ -350,84 +498,70 @@ __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_div_ns(
       }
 #pragma unroll
       for (int k = 0; k < 15; ++k) gg[k] = grad[((int64_t)pt * 15 + k) * E + e];
-      double xi[3], g[3][3], s[3], f[5], fv[5], vs, prs;
-      line_xi<N1>(K, d, a, t0, t1, xi);
-      hex_cols(c, xi[0], xi[1], xi[2], g);
+      T xi[3], g[3][3], s[3], f[5], fv[5], vs, prs;
+      line_xi(K, d, a, t0, t1, xi);
+      hex_cols(G + el, NE, xi[0], xi[1], xi[2], g);
       srow(g, d, s);
-      flux_dir(uu, s[0], s[1], s[2], gm1, f, vs, prs);
-      viscous_dir(uu, gg, s[0], s[1], s[2], gam, mu, pr, fv);
+      Flux<T, DEV>::eval(uu, s[0], s[1], s[2], gm1, R, f, vs, prs);
+      viscous<T, DEV>(uu, gg, s[0], s[1], s[2], gamma, mu, pr, R, fv);
 #pragma unroll
       for (int v = 0; v < 5; ++v) ft[v][a] = f[v] - fv[v];
     }
-    double Fc[2][5];
+    T Fc[2][5];
 #pragma unroll
     for (int sd = 0; sd < 2; ++sd) {
-      double xi[3], g[3][3], nv[3];
-      end_xi<N1>(K, d, sd, t0, t1, xi);
-      hex_cols(c, xi[0], xi[1], xi[2], g);
+      T xi[3], g[3][3], nv[3];
+      end_xi(K, d, sd, t0, t1, xi);
+      hex_cols(G + el, NE, xi[0], xi[1], xi[2], g);
       srow(g, d, nv);
-      const double sg = sd ? 1.0 : -1.0;
-      const double mag = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
-      const int face = 2 * d + sd;
-      const int fown = face * N1 * N1 + l;
-      const NbrSlot ns = nbr_slot<N1>(C, E, e, face, l);
-      double un[5], gn[15], go[15];
+      const T sg = sd ? T(1) : T(-1);
+      const T mag = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+      const NbrSlot ns = nbr_slot<NF>(C, E, e, 2 * d + sd, l);
+      T un[5];
 #pragma unroll
       for (int v = 0; v < 5; ++v) un[v] = uf[((int64_t)ns.fp * 5 + v) * E + ns.elem];
-#pragma unroll
-      for (int k = 0; k < 15; ++k) {
-        gn[k] = gradf[((int64_t)ns.fp * 15 + k) * E + ns.elem];
-        go[k] = gradf[((int64_t)fown * 15 + k) * E + e];
-      }
-      const double* own = sd ? tp : tm;
-      double uL[5], uR[5], gL[15], gR[15], nL[3], F[5], fvL[5], fvR[5];
+      const T* own = sd ? tp : tm;
+      T uL[5], uR[5], nL[3], F[5];
 #pragma unroll
       for (int v = 0; v < 5; ++v) { uL[v] = ns.left ? own[v] : un[v]; uR[v] = ns.left ? un[v] : own[v]; }
-#pragma unroll
-      for (int k = 0; k < 15; ++k) { gL[k] = ns.left ? go[k] : gn[k]; gR[k] = ns.left ? gn[k] : go[k]; }
-      const double sl = (ns.left ? sg : -sg) / mag;
+      const T sl = (ns.left ? sg : -sg) / mag;
 #pragma unroll
       for (int k = 0; k < 3; ++k) nL[k] = nv[k] * sl;
-      riemann(ph.riemann, uL, uR, nL, gam, F);
-      viscous_dir(uL, gL, nL[0], nL[1], nL[2], gam, mu, pr, fvL);
-      viscous_dir(uR, gR, nL[0], nL[1], nL[2], gam, mu, pr, fvR);
-      const double fs = ns.left ? mag : -mag;
+      common_inviscid<T, DEV>(riemann, uL, uR, nL, gamma, R, F);
+      // viscous common flux: wL fv(L) + wR fv(R), wL = 1/2 - beta, wR = 1/2 + beta
+      const T wL = T(0.5) - beta, wR = T(0.5) + beta;
+      const T w_own = ns.left ? wL : wR, w_nbr = ns.left ? wR : wL;
+      T fvc[5] = {0, 0, 0, 0, 0};
+      if (side_mode == 0 || w_own != T(0)) {
+        T go[15];
 #pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        const double fvc = 0.5 * (fvL[v] + fvR[v]) - ph.beta * (fvL[v] - fvR[v]);
-        Fc[sd][v] = fs * (F[v] - fvc + ph.tau * (uL[v] - uR[v]));
-      }
-    }
+        for (int k = 0; k < 15; ++k) go[k] = T(0);
 #pragma unroll
-    for (int a = 0; a < N1; ++a) {
-      const int pt = line_pt<N1>(d, a, t0, t1);
-      double div[5];
+        for (int a = 0; a < N1; ++a) {
+          const T la = sd ? K.lp[a] : K.lm[a];
+          const int pt = line_pt<N1>(d, a, t0, t1);
 #pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        double acc = K.cp[a] * Fc[1][v] + K.cm[a] * Fc[0][v];
-#pragma unroll
-        for (int b = 0; b < N1; ++b) acc += K.Dh[a][b] * ft[v][b];
-        div[v] = acc;
-      }
-      double* D = DIV + (pt * NE + el);
-      if (d == 0) {
-#pragma unroll
-        for (int v = 0; v < 5; ++v) D[v * NSP * NE] = div[v];
-      } else if (d == 1) {
-#pragma unroll
-        for (int v = 0; v < 5; ++v) D[v * NSP * NE] += div[v];
-      } else {
-        double xi[3], g[3][3], s[3];
-        line_xi<N1>(K, d, a, t0, t1, xi);
-        hex_cols(c, xi[0], xi[1], xi[2], g);
-        cross3(g[1], g[2], s);
-        const double iJ = -1.0 / (g[0][0] * s[0] + g[0][1] * s[1] + g[0][2] * s[2]);
-        if (e < n) {
-#pragma unroll
-          for (int v = 0; v < 5; ++v) r[((int64_t)pt * 5 + v) * E + e] = (D[v * NSP * NE] + div[v]) * iJ;
+          for (int k = 0; k < 15; ++k) go[k] += la * grad[((int64_t)pt * 15 + k) * E + e];
         }
+        T fv[5];
+        viscous<T, DEV>(own, go, nL[0], nL[1], nL[2], gamma, mu, pr, R, fv);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) fvc[v] += w_own * fv[v];
       }
+      if (side_mode == 0 || w_nbr != T(0)) {
+        T gn[15];
+#pragma unroll
+        for (int k = 0; k < 15; ++k) gn[k] = gradf[((int64_t)ns.fp * 15 + k) * E + ns.elem];
+        T fv[5];
+        viscous<T, DEV>(un, gn, nL[0], nL[1], nL[2], gamma, mu, pr, R, fv);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) fvc[v] += w_nbr * fv[v];
+      }
+      const T fs = ns.left ? mag : -mag;
+#pragma unroll
+      for (int v = 0; v < 5; ++v) Fc[sd][v] = fs * (F[v] - fvc[v] + tau * (uL[v] - uR[v]));
     }
+    accumulate_div<T, N1, NE>(d, ft, Fc, K, DIV, G, el, t0, t1, e, n, E, r);
     if (d < 2) __syncthreads();
   }
 }

@@ -55,6 +55,7 @@ class FrKernelTime(ctypes.Structure):
 
 EXPORTS = [
     "fr_default_params", "fr_setup_mesh", "fr_layout", "fr_sol_points", "fr_pack", "fr_unpack",
+    "fr_pack64", "fr_unpack64", "fr_unpack_rhs",
     "fr_rhs", "fr_rk_step", "fr_filter", "fr_mlp_set_weights", "fr_mlp_get_weights",
     "fr_mlp_features", "fr_mlp_forward", "fr_mlp_grad", "fr_mlp_train", "fr_check", "fr_sync",
     "fr_profile", "fr_profile_read",
@@ -75,6 +76,9 @@ def load():
         "fr_sol_points": (i32, [vp, vp]),
         "fr_pack": (i32, [vp, vp, vp]),
         "fr_unpack": (i32, [vp, vp, vp]),
+        "fr_pack64": (i32, [vp, vp, vp]),
+        "fr_unpack64": (i32, [vp, vp, vp]),
+        "fr_unpack_rhs": (i32, [vp, vp, vp]),
         "fr_rhs": (i32, [vp, vp, vp]),
         "fr_rk_step": (i32, [vp, vp, dbl, i32, i32]),
         "fr_filter": (i32, [vp, vp, vp, i32, vp, P(FrFilterStats)]),
@@ -190,6 +194,30 @@ class Context:
         if out is None:
             out = torch.empty(self.layout.canon_len, dtype=torch.float64, device="cuda")
         self._check(lib().fr_unpack(self.h, _ptr(native), _ptr(out)))
+        return out
+
+    def pack64(self, canon, out=None):
+        """Canonical FP64 -> FP64 native state (what rk_step / filter / check use)."""
+        torch = self._torch
+        c = torch.as_tensor(canon, dtype=torch.float64, device="cuda").contiguous()
+        if out is None:
+            out = self.new_native64()
+        self._check(lib().fr_pack64(self.h, _ptr(c), _ptr(out)))
+        return out
+
+    def unpack64(self, native, out=None):
+        torch = self._torch
+        if out is None:
+            out = torch.empty(self.layout.canon_len, dtype=torch.float64, device="cuda")
+        self._check(lib().fr_unpack64(self.h, _ptr(native), _ptr(out)))
+        return out
+
+    def unpack_rhs(self, r, out=None):
+        """Native right-hand side -> canonical FP64 (no reference state added)."""
+        torch = self._torch
+        if out is None:
+            out = torch.empty(self.layout.canon_len, dtype=torch.float64, device="cuda")
+        self._check(lib().fr_unpack_rhs(self.h, _ptr(r), _ptr(out)))
         return out
 
     # --------------------------------------------------------------- compute

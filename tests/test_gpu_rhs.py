@@ -31,7 +31,7 @@ def gpu_rhs(mesh, u_blocks, **kw):
     u = ctx.pack(ctx.join_canon(u_blocks))
     r = ctx.new_native()
     ctx.rhs(u, r)
-    out = ctx.unpack(r).cpu().numpy()
+    out = ctx.unpack_rhs(r).cpu().numpy()
     ctx.close()
     return [b.copy() for b in _split(out, u_blocks)]
 
@@ -106,9 +106,9 @@ def test_rhs_parity_config1_and_rk4_10_steps():
     check(gpu_rhs(mesh, u, system=0, order=2, riemann=0), Ro, floor_=fl)
     uo = ork.rk4(lambda s: ofr.rhs(bl, s, prm), u, 1e-3, 10)
     ctx = _ctx(mesh, system=0, order=2, riemann=0)
-    ug = ctx.pack(ctx.join_canon(u))
+    ug = ctx.pack64(ctx.join_canon(u))
     ctx.rk_step(ug, 1e-3, 10)
-    got = _split(ctx.unpack(ug).cpu().numpy(), u)
+    got = _split(ctx.unpack64(ug).cpu().numpy(), u)
     # compare the change over the 10 steps (the state itself is O(p0))
     du_g = [g - a for g, a in zip(got, u)]
     du_o = [o - a for o, a in zip(uo, u)]
@@ -145,7 +145,7 @@ def test_check_detects_nonfinite():
     bl = oracle_blocks(mesh, 2)
     u = state_for(bl, "random")
     ctx = _ctx(mesh, order=2)
-    ug = ctx.pack(ctx.join_canon(u))
+    ug = ctx.pack64(ctx.join_canon(u))
     assert ctx.check(ug)
     ug[5] = float("nan")
     assert not ctx.check(ug)

@@ -177,6 +177,15 @@ fr_status fr_mlp_get_weights(fr_ctx ctx, float* w);
 fr_status fr_mlp_features(fr_ctx ctx, const void* u_dev, const void* u_prev_dev,
                           float* x_dev, int32_t* elem_dev, int32_t* k_dev, int64_t cap, int64_t* n);
 
+/* Training data from the plain filter: n_steps filtered RK4 steps of size dt on
+ * the FP64 native state u (in place, plain filter on every stage state and the new
+ * state); at every filter application the raw features (x_dev [cap][16]) and the
+ * plain search's dyadic index (k_dev [cap], -1 = fallback) of each element that
+ * fails the checks are recorded before it is filtered.  *n (host) receives the
+ * number of rows written (at most cap).  Synchronises after every filter call. */
+fr_status fr_mlp_collect(fr_ctx ctx, void* u_dev, double dt, int32_t n_steps, float* x_dev, int32_t* k_dev,
+                         int64_t cap, int64_t* n);
+
 /* Predictions y_dev [n] for raw features x_dev [n][16] with the current weights. */
 fr_status fr_mlp_forward(fr_ctx ctx, const float* x_dev, int64_t n, float* y_dev);
 

@@ -1,0 +1,422 @@
+// Entropy-bounded modal filter for hexahedra (Sec. "Numerical Stability": modal
+// filtering, applied per element only where density, pressure or a minimum-entropy
+// bound is violated, with the strength found iteratively so as to filter as
+// little as possible).  FP64 throughout.
+//
+//   modes      u^ = V^{-1} u, tensor Legendre modes (i, j, k)
+//   filter     u^_ijk <- exp(-zeta (i^2 + j^2 + k^2) / p^2) u^_ijk  (separable in i, j, k)
+//   checks     at the solution points and the 6 (p+1)^2 face flux points:
+//              rho >= eps_rho, p >= eps_p, s = p rho^-gamma >= s_min - eps_s |s_min|
+//   s_min      min of s over the check points of the element and of its face
+//              neighbours, taken from the state at the start of the step
+//   search     k in [0, 2^n], zeta = k zeta_max / 2^n; G(0) -> untouched; not G(2^n)
+//              -> zeta_max (fallback, k = -1); else bisection keeping G(lo) false and
+//              G(hi) true, result hi.  A predicted k^ (learned warm start) replaces the
+//              starting bracket by [floor(k^/2), ceil(2 k^)] and the search continues in
+//              whichever bracket keeps that invariant.
+//
+// One 64-lane block per element.  A constraint evaluation at strength zeta is three
+// 1-D passes through LDS with the filtered evaluation matrix
+//     W[r][m] = P~_m(x_r) exp(-zeta m^2 / p^2),   r = nodes 0..p, then xi = -1, +1,
+// so a check point (r1, r2, r3) with at most one end row covers both solution and
+// flux points.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace frmi {
+
+struct FiltK {
+  double Vm[5][5];    // P~_m(x_a) (rows nodes, cols modes)
+  double Vmi[5][5];   // inverse: modes from nodal values
+  double Pe[2][5];    // P~_m(-1), P~_m(+1)
+  double lm[5], lp[5];
+};
+
+struct FiltPrm {
+  double gamma, eps_rho, eps_p, eps_s, zeta_max;
+  int n_bits;
+};
+
+__device__ __forceinline__ double entropy_of(double rho, double p, double gamma) {
+  return rho > 0 ? p * pow(rho, -gamma) : -INFINITY;
+}
+
+__device__ __forceinline__ bool admissible(const double w[5], double smin, const FiltPrm& F) {
+  const double rho = w[0];
+  const double p = (F.gamma - 1.0) * (w[4] - 0.5 * (w[1] * w[1] + w[2] * w[2] + w[3] * w[3]) / rho);
+  const double s = entropy_of(rho, p, F.gamma);
+  return rho >= F.eps_rho && p >= F.eps_p && s >= smin - F.eps_s * fabs(smin);
+}
+
+// Minimum entropy of each element over its check points (thread per element).
+template <int P>
+__global__ void __launch_bounds__(256) hex_sown(const double* __restrict__ u, double* __restrict__ sown, int64_t E,
+                                                int64_t n, FiltK K, double gamma) {
+  constexpr int N1 = P + 1, NSP = N1 * N1 * N1;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n) return;
+  double smin = INFINITY;
+  for (int pt = 0; pt < NSP; ++pt) {
+    double w[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) w[v] = u[((int64_t)pt * 5 + v) * E + e];
+    const double p = (gamma - 1.0) * (w[4] - 0.5 * (w[1] * w[1] + w[2] * w[2] + w[3] * w[3]) / w[0]);
+    smin = fmin(smin, entropy_of(w[0], p, gamma));
+  }
+  for (int d = 0; d < 3; ++d)
+    for (int q = 0; q < N1 * N1; ++q) {
+      const int t0 = q % N1, t1 = q / N1;
+      double m[5] = {0, 0, 0, 0, 0}, pl[5] = {0, 0, 0, 0, 0};
+      for (int a = 0; a < N1; ++a) {
+        const int pt = d == 0 ? a + N1 * (t0 + N1 * t1) : (d == 1 ? t0 + N1 * (a + N1 * t1) : t0 + N1 * (t1 + N1 * a));
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+          const double val = u[((int64_t)pt * 5 + v) * E + e];
+          m[v] += K.lm[a] * val;
+          pl[v] += K.lp[a] * val;
+        }
+      }
+      const double pm = (gamma - 1.0) * (m[4] - 0.5 * (m[1] * m[1] + m[2] * m[2] + m[3] * m[3]) / m[0]);
+      const double pp = (gamma - 1.0) * (pl[4] - 0.5 * (pl[1] * pl[1] + pl[2] * pl[2] + pl[3] * pl[3]) / pl[0]);
+      smin = fmin(smin, fmin(entropy_of(m[0], pm, gamma), entropy_of(pl[0], pp, gamma)));
+    }
+  sown[e] = smin;
+}
+
+// s_min over the element and its face neighbours.
+__global__ void __launch_bounds__(256) elem_smin(const double* __restrict__ sown, const int32_t* __restrict__ nbr_elem,
+                                                 int nfaces, double* __restrict__ smin, int64_t E, int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n) return;
+  double s = sown[e];
+  for (int f = 0; f < nfaces; ++f) s = fmin(s, sown[nbr_elem[(int64_t)f * E + e]]);
+  smin[e] = s;
+}
+
+template <int P>
+struct HexFiltSmem {
+  static constexpr int N1 = P + 1, NR = N1 + 2;
+  double U[5][N1 * N1 * N1];           // modal coefficients u^[v][i + N1 j + N1^2 k]
+  double T1[5][N1 * N1 * NR];          // [v][i + N1 j][r3]
+  double T2[5][N1 * NR * NR];          // [v][i][r2][r3]
+  double W[NR][N1];                    // filtered evaluation matrix
+  int flag;
+};
+
+// Check-point evaluation at the strength held in S.W: returns (block-uniformly)
+// whether every check point is admissible.  When `store` is non-null the nodal
+// values at the solution points are written there ([pt][5][E] layout).
+template <int P>
+__device__ bool hex_eval_checks(HexFiltSmem<P>& S, double smin, const FiltPrm& F, double* __restrict__ store,
+                                int64_t E, int64_t e) {
+  constexpr int N1 = P + 1, NR = N1 + 2, NSP = N1 * N1 * N1, NFP = 6 * N1 * N1;
+  const int t = threadIdx.x;
+  // pass over k: T1[v][i + N1 j][r3]
+  for (int o = t; o < 5 * N1 * N1 * NR; o += 64) {
+    const int v = o / (N1 * N1 * NR), rem = o % (N1 * N1 * NR), ij = rem / NR, r3 = rem % NR;
+    double acc = 0;
+#pragma unroll
+    for (int k = 0; k < N1; ++k) acc += S.W[r3][k] * S.U[v][ij + N1 * N1 * k];
+    S.T1[v][rem] = acc;
+  }
+  __syncthreads();
+  // pass over j: T2[v][i][r2][r3]
+  for (int o = t; o < 5 * N1 * NR * NR; o += 64) {
+    const int v = o / (N1 * NR * NR), rem = o % (N1 * NR * NR);
+    const int i = rem / (NR * NR), r2 = (rem / NR) % NR, r3 = rem % NR;
+    double acc = 0;
+#pragma unroll
+    for (int j = 0; j < N1; ++j) acc += S.W[r2][j] * S.T1[v][(i + N1 * j) * NR + r3];
+    S.T2[v][rem] = acc;
+  }
+  __syncthreads();
+  // pass over i at every check point
+  bool ok = true;
+  for (int c = t; c < NSP + NFP; c += 64) {
+    int r1, r2, r3;
+    if (c < NSP) {
+      r1 = c % N1; r2 = (c / N1) % N1; r3 = c / (N1 * N1);
+    } else {
+      const int f = (c - NSP) / (N1 * N1), q = (c - NSP) % (N1 * N1), d = f / 2, s = f % 2;
+      const int ta = q % N1, tb = q / N1, end = N1 + s;
+      r1 = d == 0 ? end : ta;
+      r2 = d == 0 ? ta : (d == 1 ? end : tb);
+      r3 = d == 2 ? end : tb;
+    }
+    double w[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      double acc = 0;
+#pragma unroll
+      for (int i = 0; i < N1; ++i) acc += S.W[r1][i] * S.T2[v][(i * NR + r2) * NR + r3];
+      w[v] = acc;
+    }
+    ok = ok && admissible(w, smin, F);
+    if (store && c < NSP) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) store[((int64_t)c * 5 + v) * E + e] = w[v];
+    }
+  }
+  return __syncthreads_and(ok ? 1 : 0) != 0;
+}
+
+template <int P>
+__device__ __forceinline__ void hex_set_w(HexFiltSmem<P>& S, const FiltK& K, double zeta) {
+  constexpr int N1 = P + 1, NR = N1 + 2;
+  const int t = threadIdx.x;
+  if (t < NR * N1) {
+    const int r = t / N1, m = t % N1;
+    const double sig = exp(-zeta * (double)(m * m) / (double)(P * P));
+    const double pm = r < N1 ? K.Vm[r][m] : K.Pe[r - N1][m];
+    S.W[r][m] = pm * sig;
+  }
+  __syncthreads();
+}
+
+// Nodal values of nv variables (X, [v][pt]) -> modal coefficients (into `out`),
+// three 1-D passes with V^{-1}; Y is scratch of the same size.
+template <int P>
+__device__ void hex_to_modal(double* X, double* Y, double* out, int nv, const FiltK& K) {
+  constexpr int N1 = P + 1, NSP = N1 * N1 * N1;
+  const int t = threadIdx.x;
+  for (int o = t; o < nv * NSP; o += 64) {
+    const int v = o / NSP, pt = o % NSP, ij = pt % (N1 * N1), m = pt / (N1 * N1);
+    double acc = 0;
+#pragma unroll
+    for (int k = 0; k < N1; ++k) acc += K.Vmi[m][k] * X[v * NSP + ij + N1 * N1 * k];
+    Y[o] = acc;
+  }
+  __syncthreads();
+  for (int o = t; o < nv * NSP; o += 64) {
+    const int v = o / NSP, pt = o % NSP, i = pt % N1, m = (pt / N1) % N1, kk = pt / (N1 * N1);
+    double acc = 0;
+#pragma unroll
+    for (int j = 0; j < N1; ++j) acc += K.Vmi[m][j] * Y[v * NSP + i + N1 * j + N1 * N1 * kk];
+    X[o] = acc;
+  }
+  __syncthreads();
+  for (int o = t; o < nv * NSP; o += 64) {
+    const int v = o / NSP, pt = o % NSP, m = pt % N1, rest = pt / N1;
+    double acc = 0;
+#pragma unroll
+    for (int i = 0; i < N1; ++i) acc += K.Vmi[m][i] * X[v * NSP + i + N1 * rest];
+    out[o] = acc;
+  }
+  __syncthreads();
+}
+
+template <int P>
+__device__ void hex_load_modal(HexFiltSmem<P>& S, const double* __restrict__ u, int64_t E, int64_t e,
+                               const FiltK& K) {
+  constexpr int N1 = P + 1, NSP = N1 * N1 * N1;
+  double* X = &S.T1[0][0];
+  double* Y = &S.T2[0][0];
+  for (int o = threadIdx.x; o < 5 * NSP; o += 64) {
+    const int v = o / NSP, pt = o % NSP;
+    X[o] = u[((int64_t)pt * 5 + v) * E + e];
+  }
+  __syncthreads();
+  hex_to_modal<P>(X, Y, &S.U[0][0], 5, K);
+}
+
+// One 64-lane block per element: detection, search (mode 0 plain, 1 warm start
+// from khat[e]) and application of the filter.
+template <int P>
+__global__ void __launch_bounds__(64) hex_filter(double* __restrict__ u, const double* __restrict__ smin_a,
+                                                 int64_t E, int64_t n, FiltK K, FiltPrm F, int mode,
+                                                 const float* __restrict__ khat, int32_t* __restrict__ k_out,
+                                                 int32_t* __restrict__ evals_out) {
+  __shared__ HexFiltSmem<P> S;
+  const int64_t e = blockIdx.x;
+  if (e >= n) return;
+  const int t = threadIdx.x;
+  const double smin = smin_a[e];
+  hex_load_modal<P>(S, u, E, e, K);
+  hex_set_w<P>(S, K, 0.0);
+  const bool ok0 = hex_eval_checks<P>(S, smin, F, nullptr, E, e);
+  int evals = 1;
+  if (ok0) {
+    if (t == 0) {
+      if (k_out) k_out[e] = 0;
+      if (evals_out) evals_out[e] = evals;
+    }
+    return;
+  }
+  const int64_t N = (int64_t)1 << F.n_bits;
+  const double dz = F.zeta_max / (double)N;
+  auto G = [&](int64_t k) {
+    hex_set_w<P>(S, K, (double)k * dz);
+    ++evals;
+    return hex_eval_checks<P>(S, smin, F, nullptr, E, e);
+  };
+  int64_t lo = 0, hi = N;
+  bool fallback = false;
+  if (mode == 1) {
+    double kh = (double)khat[e];
+    kh = fmin(fmax(kh, 1.0), (double)N);
+    const int64_t blo = (int64_t)floor(kh / 2), bhi = min((int64_t)ceil(2 * kh), N);
+    const bool g_hi = G(bhi);
+    if (g_hi) {
+      bool g_lo = false;
+      if (blo > 0) g_lo = G(blo);
+      if (g_lo) { lo = 0; hi = blo; }
+      else { lo = blo; hi = bhi; }
+    } else {
+      lo = bhi; hi = N;
+      fallback = bhi >= N ? true : !G(N);
+    }
+  } else {
+    fallback = !G(N);
+  }
+  if (!fallback) {
+    while (hi - lo > 1) {
+      const int64_t mid = (lo + hi) / 2;
+      if (G(mid)) hi = mid;
+      else lo = mid;
+    }
+  }
+  const double zeta = fallback ? F.zeta_max : (double)hi * dz;
+  hex_set_w<P>(S, K, zeta);
+  (void)hex_eval_checks<P>(S, smin, F, u, E, e);
+  if (t == 0) {
+    if (k_out) k_out[e] = fallback ? -1 : (int32_t)hi;
+    if (evals_out) evals_out[e] = evals;
+  }
+}
+
+// Block reductions over 64 lanes through LDS.
+__device__ __forceinline__ double block_min64(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = 32; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+__device__ __forceinline__ double block_max64(double v, double* red) { return -block_min64(-v, red); }
+__device__ __forceinline__ double block_sum64(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = 32; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// The 16 per-element features of the learned warm start, for elements that fail
+// the checks at zeta = 0 (flag[e] = 1; others get flag 0 and no features):
+//   0-8   log10 of the modal energy of rho, E, p in the shells max(i,j,k) = 1, 2, >= 3,
+//         relative to the mean mode's energy (floored at 1e-30)
+//   9     min rho / rho_mean - 1        10  min p / p_mean - 1
+//   11    (min s - s_min) / |s_min| clipped to [-10, 10]
+//   12    fraction of violating check points
+//   13    max |rho - rho_mean| / rho_mean
+//   14    log10(s_mean / s_min)         15  |v_mean| / c_mean
+// (mean = element mean state; its pressure, entropy and sound speed.)
+template <int P>
+__global__ void __launch_bounds__(64) hex_features(const double* __restrict__ u, const double* __restrict__ smin_a,
+                                                   int64_t E, int64_t n, FiltK K, FiltPrm F,
+                                                   int32_t* __restrict__ flag, float* __restrict__ feat) {
+  constexpr int N1 = P + 1, NR = N1 + 2, NSP = N1 * N1 * N1, NFP = 6 * N1 * N1;
+  __shared__ HexFiltSmem<P> S;
+  __shared__ double red[64];
+  __shared__ double PM[NSP];
+  const int64_t e = blockIdx.x;
+  if (e >= n) return;
+  const int t = threadIdx.x;
+  const double smin = smin_a[e];
+  const double g = F.gamma;
+  hex_load_modal<P>(S, u, E, e, K);
+  hex_set_w<P>(S, K, 0.0);
+  const bool ok0 = hex_eval_checks<P>(S, smin, F, nullptr, E, e);
+  if (ok0) {
+    if (t == 0) flag[e] = 0;
+    return;
+  }
+  // mean state from the (0,0,0) mode: mean = u^_000 P~_0^3 = u^_000 / (2 sqrt 2)
+  const double c0 = 1.0 / (2.0 * sqrt(2.0));
+  const double rb = S.U[0][0] * c0, mx = S.U[1][0] * c0, my = S.U[2][0] * c0, mz = S.U[3][0] * c0;
+  const double Eb = S.U[4][0] * c0;
+  const double vx = mx / rb, vy = my / rb, vz = mz / rb;
+  const double pb = (g - 1.0) * (Eb - 0.5 * rb * (vx * vx + vy * vy + vz * vz));
+  const double pbc = fmax(pb, 1e-300);
+  const double cb = sqrt(g * pbc / rb);
+  const double sb = pbc * pow(rb, -g);
+  // check-point statistics at zeta = 0 (T2 holds the passes of the last evaluation)
+  double mrho = INFINITY, mp = INFINITY, ms = INFINITY, mdr = 0, nbad = 0;
+  for (int c = t; c < NSP + NFP; c += 64) {
+    int r1, r2, r3;
+    if (c < NSP) {
+      r1 = c % N1; r2 = (c / N1) % N1; r3 = c / (N1 * N1);
+    } else {
+      const int f = (c - NSP) / (N1 * N1), q = (c - NSP) % (N1 * N1), d = f / 2, s = f % 2;
+      const int ta = q % N1, tb = q / N1, end = N1 + s;
+      r1 = d == 0 ? end : ta;
+      r2 = d == 0 ? ta : (d == 1 ? end : tb);
+      r3 = d == 2 ? end : tb;
+    }
+    double w[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      double acc = 0;
+#pragma unroll
+      for (int i = 0; i < N1; ++i) acc += S.W[r1][i] * S.T2[v][(i * NR + r2) * NR + r3];
+      w[v] = acc;
+    }
+    const double p = (g - 1.0) * (w[4] - 0.5 * (w[1] * w[1] + w[2] * w[2] + w[3] * w[3]) / w[0]);
+    double s = entropy_of(w[0], p, g);
+    if (!isfinite(s)) s = -1e30;
+    mrho = fmin(mrho, w[0]);
+    mp = fmin(mp, p);
+    ms = fmin(ms, s);
+    mdr = fmax(mdr, fabs(w[0] - rb));
+    nbad += admissible(w, smin, F) ? 0.0 : 1.0;
+    if (c < NSP) PM[c] = p;
+  }
+  mrho = block_min64(mrho, red);
+  mp = block_min64(mp, red);
+  ms = block_min64(ms, red);
+  mdr = block_max64(mdr, red);
+  nbad = block_sum64(nbad, red);
+  // modal coefficients of the nodal pressure
+  double* X = &S.T1[0][0];
+  double* Y = &S.T2[0][0];
+  for (int o = t; o < NSP; o += 64) X[o] = PM[o];
+  __syncthreads();
+  hex_to_modal<P>(X, Y, PM, 1, K);
+  // shell energies of rho (U[0]), E (U[4]), p (PM)
+  double en[3][3];
+  for (int fi = 0; fi < 3; ++fi) {
+    const double* c = fi == 0 ? S.U[0] : (fi == 1 ? S.U[4] : PM);
+    double sh[3] = {0, 0, 0};
+    for (int m = t; m < NSP; m += 64) {
+      const int i = m % N1, j = (m / N1) % N1, k = m / (N1 * N1);
+      const int shell = max(i, max(j, k));
+      if (shell >= 1) sh[min(shell, 3) - 1] += c[m] * c[m];
+    }
+    const double e0 = c[0] * c[0] + 1e-300;
+    for (int q = 0; q < 3; ++q) en[fi][q] = block_sum64(sh[q], red) / e0;
+  }
+  if (t == 0) {
+    float* x = feat + e * 16;
+    for (int fi = 0; fi < 3; ++fi)
+      for (int q = 0; q < 3; ++q) x[3 * fi + q] = (float)log10(fmax(en[fi][q], 1e-30));
+    x[9] = (float)(mrho / rb - 1.0);
+    x[10] = (float)(mp / pb - 1.0);
+    x[11] = (float)fmin(fmax((ms - smin) / fmax(fabs(smin), 1e-300), -10.0), 10.0);
+    x[12] = (float)(nbad / (double)(NSP + NFP));
+    x[13] = (float)(mdr / rb);
+    x[14] = (float)log10(fmax(sb / fmax(smin, 1e-300), 1e-30));
+    x[15] = (float)(sqrt(vx * vx + vy * vy + vz * vz) / cb);
+    flag[e] = 1;
+  }
+}
+
+}  // namespace frmi

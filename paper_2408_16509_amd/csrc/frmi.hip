@@ -9,7 +9,9 @@
 #include <vector>
 
 #include "../../include/frmi.h"
+#include "filter.hpp"
 #include "hex.hpp"
+#include "mlp.hpp"
 #include "setup.hpp"
 
 using namespace frmi;
@@ -30,6 +32,9 @@ struct DevBlock {
   void* uf = nullptr;       // [nfp][5][E]
   void* grad = nullptr;     // [nsp][15][E]
   void* gradf = nullptr;    // [nfp][15][E]
+  int64_t elem_off = 0;     // offset of the block in canonical element order
+  double* sown = nullptr;   // entropy filter: own min entropy [E]
+  double* smin = nullptr;   // entropy filter: neighbourhood min entropy [E]
 };
 
 struct RefVec {
@@ -51,6 +56,30 @@ struct fr_ctx_s {
   void* rk_k = nullptr;
   int* flag = nullptr;
   std::string err;
+  // entropy filter / MLP workspace (canonical element order)
+  int64_t n_elem_total = 0;
+  int32_t* f_k = nullptr;
+  int32_t* f_evals = nullptr;
+  int32_t* f_flag = nullptr;
+  float* f_feat = nullptr;
+  float* f_khat = nullptr;
+  double* f_copy = nullptr;     // FP64 native state copy (training targets)
+  float* m_w = nullptr;         // MLP parameters, Adam moments, gradient, input scaling
+  float* m_m = nullptr;
+  float* m_v = nullptr;
+  float* m_g = nullptr;
+  float* m_scale = nullptr;
+  float* m_loss = nullptr;
+  float* m_scratch = nullptr;
+  float* m_sqerr = nullptr;
+  int32_t* m_idx = nullptr;
+  int m_batch_cap = 0;
+  bool mlp_ready = false;
+  // training-data collection during filtered RK steps (fr_mlp_collect)
+  bool collecting = false;
+  float* col_x = nullptr;
+  int32_t* col_k = nullptr;
+  int64_t col_cap = 0, col_n = 0, col_seen = 0;
   // per-kernel event timing
   bool prof = false;
   struct ProfEv { int id; hipEvent_t a, b; };
@@ -339,6 +368,185 @@ RefVec refvec(const fr_params& p) {
   return r;
 }
 
+
+// ------------------------------------------------------------ entropy filter
+FiltK filtk_of(const HexOps& H) {
+  FiltK k;
+  std::memset(&k, 0, sizeof(k));
+  for (int a = 0; a < 5; ++a) {
+    k.lm[a] = H.lm[a];
+    k.lp[a] = H.lp[a];
+    for (int m = 0; m < 5; ++m) { k.Vm[a][m] = H.Vm[a][m]; k.Vmi[a][m] = H.Vmi[a][m]; }
+  }
+  for (int m = 0; m < H.n1; ++m) {
+    const double nm = std::sqrt((2.0 * m + 1.0) / 2.0);
+    k.Pe[0][m] = nm * ((m % 2) ? -1.0 : 1.0);
+    k.Pe[1][m] = nm;
+  }
+  return k;
+}
+
+FiltPrm filtprm_of(const fr_params& p, int order) {
+  FiltPrm f;
+  f.gamma = p.gamma;
+  f.eps_rho = p.filt_eps_rho;
+  f.eps_p = p.filt_eps_p;
+  f.eps_s = p.filt_eps_s;
+  f.zeta_max = p.filt_zeta_max_coef * order * order;
+  f.n_bits = p.filt_bits;
+  return f;
+}
+
+fr_status filter_alloc(fr_ctx c) {
+  if (c->f_k) return FR_OK;
+  const int64_t n = c->n_elem_total;
+  for (auto& b : c->blocks)
+    if (dalloc(c, &b.sown, b.E) || dalloc(c, &b.smin, b.E)) return FR_ERR_ALLOC;
+  if (dalloc(c, &c->f_k, n) || dalloc(c, &c->f_evals, n) || dalloc(c, &c->f_flag, n) ||
+      dalloc(c, &c->f_feat, n * 16) || dalloc(c, &c->f_khat, n))
+    return FR_ERR_ALLOC;
+  return FR_OK;
+}
+
+template <int P>
+void hex_smin_p(fr_ctx c, DevBlock& b, const double* uprev) {
+  const FiltK K = filtk_of(c->host.hex);
+  const int g = (int)((b.n + 255) / 256);
+  int pk = c->prof_begin("filter_smin");
+  hex_sown<P><<<g, 256, 0, c->stream>>>(uprev + b.native_off, b.sown, b.E, b.n, K, c->prm.gamma);
+  elem_smin<<<g, 256, 0, c->stream>>>(b.sown, b.nbr_elem, b.nfaces, b.smin, b.E, b.n);
+  c->prof_end(pk);
+}
+
+template <int P>
+void hex_filter_p(fr_ctx c, DevBlock& b, double* u, int mode) {
+  const FiltK K = filtk_of(c->host.hex);
+  const FiltPrm F = filtprm_of(c->prm, P);
+  const int64_t o = b.elem_off;
+  int pk;
+  if (mode == 1) {
+    pk = c->prof_begin("filter_features_mlp");
+    hex_features<P><<<(unsigned)b.n, 64, 0, c->stream>>>(u + b.native_off, b.smin, b.E, b.n, K, F, c->f_flag + o,
+                                                         c->f_feat + o * 16);
+    mlp_forward<<<(unsigned)((b.n + 255) / 256), 256, 0, c->stream>>>(c->m_w, c->m_scale, c->f_feat + o * 16,
+                                                                      c->f_flag + o, b.n, F.n_bits, c->f_khat + o);
+    c->prof_end(pk);
+  }
+  pk = c->prof_begin(mode == 1 ? "filter_search_warm" : "filter_search_plain");
+  hex_filter<P><<<(unsigned)b.n, 64, 0, c->stream>>>(u + b.native_off, b.smin, b.E, b.n, K, F, mode,
+                                                     c->f_khat + o, c->f_k + o, c->f_evals + o);
+  c->prof_end(pk);
+}
+
+fr_status compute_smin(fr_ctx c, const double* uprev) {
+  for (auto& b : c->blocks) {
+    if (b.etype != FR_HEX) return fail(c, FR_ERR_UNSUPPORTED, "entropy filter: tetrahedra not yet available");
+    switch (c->prm.order) {
+      case 1: hex_smin_p<1>(c, b, uprev); break;
+      case 2: hex_smin_p<2>(c, b, uprev); break;
+      case 3: hex_smin_p<3>(c, b, uprev); break;
+      case 4: hex_smin_p<4>(c, b, uprev); break;
+    }
+  }
+  HIP_TRY(c, hipGetLastError());
+  return FR_OK;
+}
+
+fr_status collect_rows(fr_ctx c, const double* u);
+
+fr_status apply_filter(fr_ctx c, double* u, int mode) {
+  if (c->collecting) {
+    fr_status st = collect_rows(c, u);
+    if (st) return st;
+  }
+  for (auto& b : c->blocks) {
+    if (b.etype != FR_HEX) return fail(c, FR_ERR_UNSUPPORTED, "entropy filter: tetrahedra not yet available");
+    switch (c->prm.order) {
+      case 1: hex_filter_p<1>(c, b, u, mode); break;
+      case 2: hex_filter_p<2>(c, b, u, mode); break;
+      case 3: hex_filter_p<3>(c, b, u, mode); break;
+      case 4: hex_filter_p<4>(c, b, u, mode); break;
+    }
+  }
+  HIP_TRY(c, hipGetLastError());
+  return FR_OK;
+}
+
+template <int P>
+void hex_features_p(fr_ctx c, DevBlock& b, const double* u) {
+  const FiltK K = filtk_of(c->host.hex);
+  const FiltPrm F = filtprm_of(c->prm, P);
+  const int64_t o = b.elem_off;
+  hex_features<P><<<(unsigned)b.n, 64, 0, c->stream>>>(u + b.native_off, b.smin, b.E, b.n, K, F, c->f_flag + o,
+                                                       c->f_feat + o * 16);
+}
+
+template <int P>
+void hex_features_p(fr_ctx c, DevBlock& b, const double* u);
+
+__global__ void k_gather_features(const float* __restrict__ feat, const int32_t* __restrict__ kk,
+                                  const int32_t* __restrict__ idx, int64_t n, float* __restrict__ x,
+                                  int32_t* __restrict__ elem, int32_t* __restrict__ kout) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t e = idx[i];
+  for (int f = 0; f < 16; ++f) x[i * 16 + f] = feat[(int64_t)e * 16 + f];
+  if (elem) elem[i] = e;
+  if (kout) kout[i] = kk[e];
+}
+
+// Features and plain-search targets of the troubled elements of u (entropy bound
+// from the current s_min), appended to the collection buffers.
+fr_status collect_rows(fr_ctx c, const double* u) {
+  for (auto& b : c->blocks) {
+    switch (c->prm.order) {
+      case 1: hex_features_p<1>(c, b, u); break;
+      case 2: hex_features_p<2>(c, b, u); break;
+      case 3: hex_features_p<3>(c, b, u); break;
+      case 4: hex_features_p<4>(c, b, u); break;
+    }
+  }
+  HIP_TRY(c, hipMemcpyAsync(c->f_copy, u, c->native_len * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  c->collecting = false;
+  fr_status st = apply_filter(c, c->f_copy, 0);
+  c->collecting = true;
+  if (st) return st;
+  std::vector<int32_t> flag(c->n_elem_total);
+  HIP_TRY(c, hipMemcpyAsync(flag.data(), c->f_flag, flag.size() * 4, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  std::vector<int32_t> idx;
+  for (size_t i = 0; i < flag.size(); ++i) if (flag[i]) idx.push_back((int32_t)i);
+  c->col_seen += (int64_t)idx.size();
+  const int64_t m = std::min<int64_t>((int64_t)idx.size(), c->col_cap - c->col_n);
+  if (m > 0) {
+    int32_t* didx = nullptr;
+    if (dalloc(c, &didx, m)) return FR_ERR_ALLOC;
+    HIP_TRY(c, hipMemcpyAsync(didx, idx.data(), m * 4, hipMemcpyHostToDevice, c->stream));
+    k_gather_features<<<(unsigned)((m + 255) / 256), 256, 0, c->stream>>>(c->f_feat, c->f_k, didx, m,
+                                                                          c->col_x + c->col_n * 16, nullptr,
+                                                                          c->col_k + c->col_n);
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    (void)hipFree(didx);
+    c->col_n += m;
+  }
+  return FR_OK;
+}
+
+fr_status mlp_alloc(fr_ctx c, int batch) {
+  if (!c->m_w) {
+    if (dalloc(c, &c->m_w, MLP_NP) || dalloc(c, &c->m_m, MLP_NP) || dalloc(c, &c->m_v, MLP_NP) ||
+        dalloc(c, &c->m_g, MLP_NP) || dalloc(c, &c->m_scale, 2 * MLP_IN) || dalloc(c, &c->m_loss, 1))
+      return FR_ERR_ALLOC;
+  }
+  if (batch > c->m_batch_cap) {
+    (void)hipFree(c->m_scratch);
+    (void)hipFree(c->m_sqerr);
+    if (dalloc(c, &c->m_scratch, (size_t)batch * MLP_SS) || dalloc(c, &c->m_sqerr, batch)) return FR_ERR_ALLOC;
+    c->m_batch_cap = batch;
+  }
+  return FR_OK;
+}
+
 }  // namespace
 
 // =============================================================================
@@ -379,6 +587,11 @@ void fr_destroy(fr_ctx c) {
   (void)hipFree(c->perm);
   (void)hipFree(c->rk_stage); (void)hipFree(c->rk_acc); (void)hipFree(c->rk_k);
   (void)hipFree(c->flag);
+  for (auto& b : c->blocks) { (void)hipFree(b.sown); (void)hipFree(b.smin); }
+  for (void* q : {(void*)c->f_k, (void*)c->f_evals, (void*)c->f_flag, (void*)c->f_feat, (void*)c->f_khat,
+                  (void*)c->f_copy, (void*)c->m_w, (void*)c->m_m, (void*)c->m_v, (void*)c->m_g, (void*)c->m_scale,
+                  (void*)c->m_loss, (void*)c->m_scratch, (void*)c->m_sqerr, (void*)c->m_idx})
+    (void)hipFree(q);
   c->prof_clear();
   delete c;
 }
@@ -422,6 +635,8 @@ fr_status fr_setup_mesh(const fr_params* p, int64_t n_vert, const double* xyz, c
     DevBlock b;
     b.etype = hb.etype; b.n = hb.n; b.E = hb.e_pad; b.nsp = hb.nsp; b.nfp = hb.nfp; b.nfaces = hb.nfaces;
     b.canon_off = canon; b.native_off = native;
+    b.elem_off = c->n_elem_total;
+    c->n_elem_total += b.n;
     canon += b.n * 5 * b.nsp;
     native += b.E * 5 * b.nsp;
     c->blocks.push_back(b);
@@ -561,7 +776,14 @@ fr_status fr_rhs(fr_ctx c, const void* u, void* r) {
 fr_status fr_rk_step(fr_ctx c, void* u_, double dt, int32_t n_steps, int32_t filter_mode) {
   if (!c || !u_) return fail(c, FR_ERR_ARG, "NULL argument");
   if (n_steps < 0 || !std::isfinite(dt)) return fail(c, FR_ERR_ARG, "n_steps or dt");
-  if (filter_mode != -1) return fail(c, FR_ERR_UNSUPPORTED, "filter not yet available");
+  if (filter_mode < -1 || filter_mode > 1) return fail(c, FR_ERR_ARG, "filter_mode must be -1, 0 or 1");
+  if (filter_mode >= 0 && c->prm.precision != FR_FP64)
+    return fail(c, FR_ERR_UNSUPPORTED, "the entropy filter runs on the FP64 form");
+  if (filter_mode == 1 && !c->mlp_ready) return fail(c, FR_ERR_STATE, "MLP weights not set");
+  if (filter_mode >= 0) {
+    fr_status fs = filter_alloc(c);
+    if (fs) return fs;
+  }
   double* u = (double*)u_;
   const int64_t n = c->native_len;
   const bool f32 = c->prm.precision == FR_FP32;
@@ -580,23 +802,30 @@ fr_status fr_rk_step(fr_ctx c, void* u_, double dt, int32_t n_steps, int32_t fil
   int pk;
   if (!f32) {
     double *K = (double*)c->rk_k, *S = (double*)c->rk_stage;
+    const bool filt = filter_mode >= 0;
     for (int s = 0; s < n_steps; ++s) {
+      // entropy bound of this step from u_n; every later stage state and u_{n+1} is filtered
+      if (filt && (st = compute_smin(c, u))) return st;
       if ((st = rhs_native(c, u, K))) return st;
       pk = c->prof_begin("rk4_update");
       k_rk_first<<<g, 256, 0, c->stream>>>(u, K, c->rk_acc, S, n, b1, c2);
       c->prof_end(pk);
+      if (filt && (st = apply_filter(c, S, filter_mode))) return st;
       if ((st = rhs_native(c, S, K))) return st;
       pk = c->prof_begin("rk4_update");
       k_rk_mid<<<g, 256, 0, c->stream>>>(u, K, c->rk_acc, S, n, b2, c2);
       c->prof_end(pk);
+      if (filt && (st = apply_filter(c, S, filter_mode))) return st;
       if ((st = rhs_native(c, S, K))) return st;
       pk = c->prof_begin("rk4_update");
       k_rk_mid<<<g, 256, 0, c->stream>>>(u, K, c->rk_acc, S, n, b2, dt);
       c->prof_end(pk);
+      if (filt && (st = apply_filter(c, S, filter_mode))) return st;
       if ((st = rhs_native(c, S, K))) return st;
       pk = c->prof_begin("rk4_update");
       k_rk_last<<<g, 256, 0, c->stream>>>(u, K, c->rk_acc, n, b1);
       c->prof_end(pk);
+      if (filt && (st = apply_filter(c, u, filter_mode))) return st;
     }
   } else {
     float *K = (float*)c->rk_k, *S = (float*)c->rk_stage;
@@ -675,19 +904,158 @@ fr_status fr_sync(fr_ctx c) {
   return FR_OK;
 }
 
-fr_status fr_filter(fr_ctx c, void*, const void*, int32_t, int32_t*, fr_filter_stats*) {
-  return fail(c, FR_ERR_UNSUPPORTED, "filter not yet available");
+fr_status fr_filter(fr_ctx c, void* u_, const void* uprev_, int32_t mode, int32_t* k_dev, fr_filter_stats* stats) {
+  if (!c || !u_ || !uprev_) return fail(c, FR_ERR_ARG, "NULL argument");
+  if (mode != 0 && mode != 1) return fail(c, FR_ERR_ARG, "mode must be 0 (plain) or 1 (MLP warm start)");
+  if (mode == 1 && !c->mlp_ready) return fail(c, FR_ERR_STATE, "MLP weights not set");
+  fr_status st;
+  if ((st = filter_alloc(c))) return st;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (stats) {
+    HIP_TRY(c, hipEventCreate(&e0));
+    HIP_TRY(c, hipEventCreate(&e1));
+    HIP_TRY(c, hipEventRecord(e0, c->stream));
+  }
+  if ((st = compute_smin(c, (const double*)uprev_))) return st;
+  if ((st = apply_filter(c, (double*)u_, mode))) return st;
+  if (k_dev) HIP_TRY(c, hipMemcpyAsync(k_dev, c->f_k, c->n_elem_total * 4, hipMemcpyDeviceToDevice, c->stream));
+  if (stats) {
+    HIP_TRY(c, hipEventRecord(e1, c->stream));
+    std::vector<int32_t> k(c->n_elem_total), ev(c->n_elem_total);
+    HIP_TRY(c, hipMemcpyAsync(k.data(), c->f_k, k.size() * 4, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(ev.data(), c->f_evals, ev.size() * 4, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    float ms = 0;
+    HIP_TRY(c, hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    std::memset(stats, 0, sizeof(*stats));
+    for (size_t i = 0; i < k.size(); ++i) {
+      if (k[i] != 0) { stats->n_troubled++; stats->n_evals += ev[i]; }
+      if (k[i] < 0) stats->n_fallback++;
+    }
+    stats->seconds = ms * 1e-3;
+  }
+  return FR_OK;
 }
-fr_status fr_mlp_set_weights(fr_ctx c, const float*, const float*, const float*) { return fail(c, FR_ERR_UNSUPPORTED, "mlp"); }
-fr_status fr_mlp_get_weights(fr_ctx c, float*) { return fail(c, FR_ERR_UNSUPPORTED, "mlp"); }
-fr_status fr_mlp_features(fr_ctx c, const void*, const void*, float*, int32_t*, int32_t*, int64_t, int64_t*) {
-  return fail(c, FR_ERR_UNSUPPORTED, "mlp");
+
+fr_status fr_mlp_set_weights(fr_ctx c, const float* w, const float* xm, const float* xs) {
+  if (!c || !w || !xm || !xs) return fail(c, FR_ERR_ARG, "NULL argument");
+  for (int i = 0; i < MLP_IN; ++i)
+    if (!(xs[i] > 0)) return fail(c, FR_ERR_ARG, "x_std must be positive");
+  fr_status st;
+  if ((st = mlp_alloc(c, 1))) return st;
+  std::vector<float> sc(2 * MLP_IN);
+  for (int i = 0; i < MLP_IN; ++i) { sc[i] = xm[i]; sc[MLP_IN + i] = xs[i]; }
+  HIP_TRY(c, hipMemcpyAsync(c->m_w, w, MLP_NP * sizeof(float), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->m_scale, sc.data(), sc.size() * sizeof(float), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->mlp_ready = true;
+  return FR_OK;
 }
-fr_status fr_mlp_forward(fr_ctx c, const float*, int64_t, float*) { return fail(c, FR_ERR_UNSUPPORTED, "mlp"); }
-fr_status fr_mlp_grad(fr_ctx c, const float*, const float*, int64_t, float*, float*) { return fail(c, FR_ERR_UNSUPPORTED, "mlp"); }
-fr_status fr_mlp_train(fr_ctx c, const float*, const float*, int64_t, const int32_t*, int32_t, int32_t, float, float,
-                       float, float, float*) {
-  return fail(c, FR_ERR_UNSUPPORTED, "mlp");
+
+fr_status fr_mlp_get_weights(fr_ctx c, float* w) {
+  if (!c || !w) return fail(c, FR_ERR_ARG, "NULL argument");
+  if (!c->mlp_ready) return fail(c, FR_ERR_STATE, "MLP weights not set");
+  HIP_TRY(c, hipMemcpyAsync(w, c->m_w, MLP_NP * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return FR_OK;
+}
+
+fr_status fr_mlp_features(fr_ctx c, const void* u_, const void* uprev_, float* x, int32_t* elem, int32_t* kout,
+                          int64_t cap, int64_t* n) {
+  if (!c || !u_ || !uprev_ || !n || (cap > 0 && !x)) return fail(c, FR_ERR_ARG, "NULL argument");
+  fr_status st;
+  if ((st = filter_alloc(c))) return st;
+  if (!c->f_copy && dalloc(c, &c->f_copy, c->native_len)) return FR_ERR_ALLOC;
+  if ((st = compute_smin(c, (const double*)uprev_))) return st;
+  for (auto& b : c->blocks) {
+    switch (c->prm.order) {
+      case 1: hex_features_p<1>(c, b, (const double*)u_); break;
+      case 2: hex_features_p<2>(c, b, (const double*)u_); break;
+      case 3: hex_features_p<3>(c, b, (const double*)u_); break;
+      case 4: hex_features_p<4>(c, b, (const double*)u_); break;
+    }
+  }
+  // training targets: the plain search on a copy of the state
+  HIP_TRY(c, hipMemcpyAsync(c->f_copy, u_, c->native_len * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  if ((st = apply_filter(c, c->f_copy, 0))) return st;
+  std::vector<int32_t> flag(c->n_elem_total);
+  HIP_TRY(c, hipMemcpyAsync(flag.data(), c->f_flag, flag.size() * 4, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  std::vector<int32_t> idx;
+  for (size_t i = 0; i < flag.size(); ++i) if (flag[i]) idx.push_back((int32_t)i);
+  *n = (int64_t)idx.size();
+  const int64_t m = std::min<int64_t>(cap, *n);
+  if (m > 0) {
+    int32_t* didx = nullptr;
+    if (dalloc(c, &didx, m)) return FR_ERR_ALLOC;
+    HIP_TRY(c, hipMemcpyAsync(didx, idx.data(), m * 4, hipMemcpyHostToDevice, c->stream));
+    k_gather_features<<<(unsigned)((m + 255) / 256), 256, 0, c->stream>>>(c->f_feat, c->f_k, didx, m, x, elem, kout);
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    (void)hipFree(didx);
+  }
+  return FR_OK;
+}
+
+fr_status fr_mlp_collect(fr_ctx c, void* u, double dt, int32_t n_steps, float* x, int32_t* k, int64_t cap,
+                         int64_t* n) {
+  if (!c || !u || !n || cap < 0 || (cap > 0 && (!x || !k))) return fail(c, FR_ERR_ARG, "bad argument");
+  fr_status st;
+  if ((st = filter_alloc(c))) return st;
+  if (!c->f_copy && dalloc(c, &c->f_copy, c->native_len)) return FR_ERR_ALLOC;
+  c->collecting = true;
+  c->col_x = x;
+  c->col_k = k;
+  c->col_cap = cap;
+  c->col_n = 0;
+  c->col_seen = 0;
+  st = fr_rk_step(c, u, dt, n_steps, 0);
+  c->collecting = false;
+  *n = c->col_n;
+  return st;
+}
+
+fr_status fr_mlp_forward(fr_ctx c, const float* x, int64_t n, float* y) {
+  if (!c || (n > 0 && (!x || !y)) || n < 0) return fail(c, FR_ERR_ARG, "bad argument");
+  if (!c->mlp_ready) return fail(c, FR_ERR_STATE, "MLP weights not set");
+  if (n == 0) return FR_OK;
+  mlp_forward<<<(unsigned)((n + 255) / 256), 256, 0, c->stream>>>(c->m_w, c->m_scale, x, nullptr, n, 0, y);
+  HIP_TRY(c, hipGetLastError());
+  return FR_OK;
+}
+
+fr_status fr_mlp_grad(fr_ctx c, const float* x, const float* y, int64_t n, float* grad, float* loss) {
+  if (!c || !x || !y || !grad || !loss || n <= 0 || n > (1 << 20)) return fail(c, FR_ERR_ARG, "bad argument");
+  if (!c->mlp_ready) return fail(c, FR_ERR_STATE, "MLP weights not set");
+  fr_status st;
+  if ((st = mlp_alloc(c, (int)n))) return st;
+  mlp_fwd_bwd<<<(unsigned)((n + 255) / 256), 256, 0, c->stream>>>(c->m_w, c->m_scale, x, y, nullptr, (int)n,
+                                                                   c->m_scratch, c->m_sqerr);
+  mlp_grad_reduce<<<(MLP_NP + 1 + 255) / 256, 256, 0, c->stream>>>(c->m_scratch, (int)n, c->m_sqerr, grad, loss);
+  HIP_TRY(c, hipGetLastError());
+  return FR_OK;
+}
+
+fr_status fr_mlp_train(fr_ctx c, const float* x, const float* y, int64_t n, const int32_t* perm, int32_t n_steps,
+                       int32_t batch, float lr, float b1, float b2, float eps, float* loss_hist) {
+  if (!c || !x || !y || !perm || n <= 0 || n_steps < 0 || batch <= 0 || batch > (1 << 16))
+    return fail(c, FR_ERR_ARG, "bad argument");
+  if (!c->mlp_ready) return fail(c, FR_ERR_STATE, "MLP weights not set");
+  fr_status st;
+  if ((st = mlp_alloc(c, batch))) return st;
+  HIP_TRY(c, hipMemsetAsync(c->m_m, 0, MLP_NP * sizeof(float), c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->m_v, 0, MLP_NP * sizeof(float), c->stream));
+  for (int t = 1; t <= n_steps; ++t) {
+    mlp_fwd_bwd<<<(unsigned)((batch + 255) / 256), 256, 0, c->stream>>>(c->m_w, c->m_scale, x, y,
+                                                                         perm + (int64_t)(t - 1) * batch, batch,
+                                                                         c->m_scratch, c->m_sqerr);
+    mlp_grad_reduce<<<(MLP_NP + 1 + 255) / 256, 256, 0, c->stream>>>(c->m_scratch, batch, c->m_sqerr, c->m_g,
+                                                                      loss_hist ? loss_hist + (t - 1) : c->m_loss);
+    mlp_adam<<<(MLP_NP + 255) / 256, 256, 0, c->stream>>>(c->m_w, c->m_g, c->m_m, c->m_v, t, lr, b1, b2, eps);
+  }
+  HIP_TRY(c, hipGetLastError());
+  return FR_OK;
 }
 
 }  // extern "C"

@@ -57,7 +57,7 @@ EXPORTS = [
     "fr_default_params", "fr_setup_mesh", "fr_layout", "fr_sol_points", "fr_pack", "fr_unpack",
     "fr_pack64", "fr_unpack64", "fr_unpack_rhs",
     "fr_rhs", "fr_rk_step", "fr_filter", "fr_mlp_set_weights", "fr_mlp_get_weights",
-    "fr_mlp_features", "fr_mlp_forward", "fr_mlp_grad", "fr_mlp_train", "fr_check", "fr_sync",
+    "fr_mlp_features", "fr_mlp_collect", "fr_mlp_forward", "fr_mlp_grad", "fr_mlp_train", "fr_check", "fr_sync",
     "fr_profile", "fr_profile_read",
     "fr_destroy", "fr_last_error",
 ]
@@ -85,6 +85,7 @@ def load():
         "fr_mlp_set_weights": (i32, [vp, vp, vp, vp]),
         "fr_mlp_get_weights": (i32, [vp, vp]),
         "fr_mlp_features": (i32, [vp, vp, vp, vp, vp, vp, i64, P(i64)]),
+        "fr_mlp_collect": (i32, [vp, vp, dbl, i32, vp, vp, i64, P(i64)]),
         "fr_mlp_forward": (i32, [vp, vp, i64, vp]),
         "fr_mlp_grad": (i32, [vp, vp, vp, i64, vp, vp]),
         "fr_mlp_train": (i32, [vp, vp, vp, i64, vp, i32, i32, ctypes.c_float, ctypes.c_float,
@@ -232,6 +233,58 @@ class Context:
         self._check(lib().fr_filter(self.h, _ptr(u), _ptr(u if u_prev is None else u_prev), int(mode),
                                     _ptr(k), ctypes.byref(s) if stats else None))
         return s
+
+    # --------------------------------------------------------------- learned warm start
+    def mlp_set_weights(self, w, x_mean, x_std):
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        xm = np.ascontiguousarray(x_mean, dtype=np.float32)
+        xs = np.ascontiguousarray(x_std, dtype=np.float32)
+        self._check(lib().fr_mlp_set_weights(self.h, w.ctypes.data, xm.ctypes.data, xs.ctypes.data))
+
+    def mlp_get_weights(self):
+        w = np.empty(5313, dtype=np.float32)
+        self._check(lib().fr_mlp_get_weights(self.h, w.ctypes.data))
+        return w
+
+    def mlp_features(self, u, u_prev, cap):
+        torch = self._torch
+        x = torch.zeros((max(cap, 1), 16), dtype=torch.float32, device="cuda")
+        el = torch.zeros(max(cap, 1), dtype=torch.int32, device="cuda")
+        k = torch.zeros(max(cap, 1), dtype=torch.int32, device="cuda")
+        n = ctypes.c_int64()
+        self._check(lib().fr_mlp_features(self.h, _ptr(u), _ptr(u_prev), _ptr(x), _ptr(el), _ptr(k), int(cap),
+                                          ctypes.byref(n)))
+        m = min(n.value, cap)
+        return x[:m], el[:m], k[:m], n.value
+
+    def mlp_collect(self, u, dt, n_steps, cap):
+        torch = self._torch
+        x = torch.zeros((max(cap, 1), 16), dtype=torch.float32, device="cuda")
+        k = torch.zeros(max(cap, 1), dtype=torch.int32, device="cuda")
+        n = ctypes.c_int64()
+        self._check(lib().fr_mlp_collect(self.h, _ptr(u), float(dt), int(n_steps), _ptr(x), _ptr(k), int(cap),
+                                         ctypes.byref(n)))
+        return x[:n.value], k[:n.value]
+
+    def mlp_forward(self, x):
+        torch = self._torch
+        y = torch.empty(x.shape[0], dtype=torch.float32, device="cuda")
+        self._check(lib().fr_mlp_forward(self.h, _ptr(x), int(x.shape[0]), _ptr(y)))
+        return y
+
+    def mlp_grad(self, x, y):
+        torch = self._torch
+        g = torch.empty(5313, dtype=torch.float32, device="cuda")
+        loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        self._check(lib().fr_mlp_grad(self.h, _ptr(x), _ptr(y), int(x.shape[0]), _ptr(g), _ptr(loss)))
+        return g, loss
+
+    def mlp_train(self, x, y, perm, n_steps, batch, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        torch = self._torch
+        hist = torch.empty(max(n_steps, 1), dtype=torch.float32, device="cuda")
+        self._check(lib().fr_mlp_train(self.h, _ptr(x), _ptr(y), int(x.shape[0]), _ptr(perm), int(n_steps),
+                                       int(batch), lr, beta1, beta2, eps, _ptr(hist)))
+        return hist[:n_steps]
 
     def check(self, u):
         st = lib().fr_check(self.h, _ptr(u))

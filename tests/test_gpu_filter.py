@@ -1,0 +1,200 @@
+"""GPU entropy filter, MLP features and MLP kernels against the FP64 oracle.
+
+Filter decisions: the dyadic index k of every element must equal the oracle's
+(the bisection ends where the constraints flip, so its margins are far above
+rounding); filtered states agree to 1e-12 relative; untouched elements stay
+bit-identical; every check point of the result satisfies the bounds (checked by
+the oracle in FP64).  Features are stored in FP32 (1e-5).  MLP: FP32 kernels
+against the FP64 oracle (forward 1e-5, gradient 1e-4 relative).
+"""
+import numpy as np
+import pytest
+
+from oracle import entropy_filter as ef
+from oracle import fr as ofr
+from oracle import mlp as omlp
+from oracle import rk as ork
+from paper_2408_16509_amd import inputs
+
+from helpers import oracle_blocks
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+FP = ef.FilterParams()
+
+
+def shock_case(n=4, order=3, dt=2e-2, orient_seed=41, noise_seed=42):
+    """(mesh, blocks, u0, u1): u0 = filtered shock IC; u1 = one RK4 step from u0 with the
+    filter on the stage states only (u1 itself unfiltered)."""
+    mesh = inputs.hex_box((n, n, n))
+    bl = oracle_blocks(mesh, order)
+    x = bl[0].xsol
+    ic = np.moveaxis(inputs.shock(x[..., 0], x[..., 1], x[..., 2], orient_seed=orient_seed,
+                                  noise_seed=noise_seed), 0, 1).copy()
+    u0 = ef.entropy_filter(bl, [ic], [ic], FP)[0][0]
+    smin0 = ef.smin_neighbourhood(bl, [u0], FP)
+    stage = lambda s: [ef.filter_block(b, ss, sm, FP)[0] for b, ss, sm in zip(bl, s, smin0)]
+    prm = ofr.Params(riemann=1)
+    u1 = ork.rk4_step(lambda s: ofr.rhs(bl, stage(s), prm), [u0], dt)[0]
+    return mesh, bl, u0, u1
+
+
+@pytest.fixture(scope="module")
+def case():
+    return shock_case()
+
+
+def _ctx(mesh, order=3):
+    from paper_2408_16509_amd import frmi
+    return frmi.Context(mesh, system=0, order=order, riemann=1)
+
+
+def test_filter_matches_oracle(case):
+    mesh, bl, u0, u1 = case
+    b = bl[0]
+    smin = ef.smin_neighbourhood(bl, [u0], FP)[0]
+    uo, ko, evo = ef.filter_block(b, u1, smin, FP)
+    ctx = _ctx(mesh)
+    ug = ctx.pack64(u1.ravel())
+    up = ctx.pack64(u0.ravel())
+    k = torch.zeros(len(b.elems), dtype=torch.int32, device="cuda")
+    st = ctx.filter(ug, up, mode=0, k=k, stats=True)
+    kg = k.cpu().numpy()
+    got = ctx.unpack64(ug).cpu().numpy().reshape(u1.shape)
+    print(f"troubled {st.n_troubled} fallback {st.n_fallback} evals {st.n_evals} oracle troubled {(ko != 0).sum()}"
+          f" evals {evo[ko != 0].sum()}")
+    assert np.array_equal(kg, ko)
+    assert st.n_troubled == (ko != 0).sum() and st.n_evals == evo[ko != 0].sum()
+    assert np.array_equal(got[ko == 0], u1[ko == 0])
+    sel = ko != 0
+    err = np.linalg.norm(got[sel] - uo[sel]) / np.linalg.norm(uo[sel])
+    assert err <= 1e-12
+    assert ef.admissible(b, got, smin, FP)[0].all()
+    # element means are unchanged (conservative)
+    np.testing.assert_allclose(got @ b.ops.weights, u1 @ b.ops.weights, rtol=1e-13)
+
+
+def test_features_match_oracle(case):
+    mesh, bl, u0, u1 = case
+    b = bl[0]
+    smin = ef.smin_neighbourhood(bl, [u0], FP)[0]
+    Fo = ef.features(b, u1, smin, FP)
+    ok0 = ef.admissible(b, u1, smin, FP)[0]
+    ctx = _ctx(mesh)
+    x, el, k, n = ctx.mlp_features(ctx.pack64(u1.ravel()), ctx.pack64(u0.ravel()), cap=len(b.elems))
+    el = el.cpu().numpy()
+    assert n == (~ok0).sum() and np.array_equal(el, np.nonzero(~ok0)[0])
+    Fg = x.cpu().numpy()
+    ref = Fo[el]
+    np.testing.assert_allclose(Fg, ref, rtol=2e-5, atol=2e-5)
+    # the targets are the plain filter's k
+    _, ko, _ = ef.filter_block(b, u1, smin, FP)
+    assert np.array_equal(k.cpu().numpy(), ko[el])
+
+
+def test_mlp_forward_grad_train_match_oracle():
+    from paper_2408_16509_amd import frmi
+    rng = np.random.default_rng(11)
+    X = rng.normal(size=(512, 16))
+    y = np.tanh(X[:, 0] - 0.3 * X[:, 5]) * 0.4 + 0.5
+    xm, xs = X.mean(axis=0), X.std(axis=0)
+    w0 = omlp.glorot_init(43) + 0.01 * rng.normal(size=omlp.N_PARAMS)
+    ctx = _ctx(inputs.hex_box((1, 1, 1)), order=2)
+    ctx.mlp_set_weights(w0, xm, xs)
+    assert np.array_equal(ctx.mlp_get_weights(), w0.astype(np.float32))
+    Xs = (X - xm) / xs
+    xd = torch.tensor(X, dtype=torch.float32, device="cuda")
+    yd = torch.tensor(y, dtype=torch.float32, device="cuda")
+    yo = omlp.forward(w0.astype(np.float32).astype(np.float64), Xs)
+    yg = ctx.mlp_forward(xd).cpu().numpy()
+    np.testing.assert_allclose(yg, yo, rtol=1e-5, atol=1e-5)
+    g, loss = ctx.mlp_grad(xd[:256], yd[:256])
+    lo, go = omlp.loss_and_grad(w0.astype(np.float32).astype(np.float64), Xs[:256], y[:256])
+    gg = g.cpu().numpy()
+    assert abs(loss.item() - lo) <= 1e-5 * abs(lo)
+    assert np.linalg.norm(gg - go) <= 1e-4 * np.linalg.norm(go)
+    # 200 Adam steps on the same minibatch sequence as the oracle
+    steps = 200
+    idx = np.concatenate(omlp.batches(512, 128, steps, seed=44)).astype(np.int32)
+    perm = torch.tensor(idx, dtype=torch.int32, device="cuda")
+    hist = ctx.mlp_train(xd, yd, perm, steps, 128).cpu().numpy()
+    wo, ho = omlp.train(w0.astype(np.float32).astype(np.float64), Xs, y, steps, batch=128, seed=44)
+    wg = ctx.mlp_get_weights()
+    print(f"loss start {hist[0]:.4e} end {hist[-1]:.4e}; oracle end {ho[-1]:.4e}; "
+          f"weights rel diff {np.linalg.norm(wg - wo) / np.linalg.norm(wo):.2e}")
+    assert hist[-1] < 0.3 * hist[0]
+    np.testing.assert_allclose(hist, ho, rtol=2e-3, atol=1e-6)
+    assert np.linalg.norm(wg - wo) <= 1e-3 * np.linalg.norm(wo)
+
+
+def test_filtered_rk_step_matches_oracle():
+    """One RK4 step with the plain filter on every stage state and the new state."""
+    mesh, bl, u0, _ = shock_case()
+    b = bl[0]
+    smin0 = ef.smin_neighbourhood(bl, [u0], FP)
+    post = lambda s: [ef.filter_block(bb, ss, sm, FP)[0] for bb, ss, sm in zip(bl, s, smin0)]
+    prm = ofr.Params(riemann=1)
+    uo = ork.rk4_step(lambda s: ofr.rhs(bl, s, prm), [u0], 2e-2, stage_post=post)[0]
+    ctx = _ctx(mesh)
+    ug = ctx.pack64(u0.ravel())
+    ctx.rk_step(ug, 2e-2, 1, filter_mode=0)
+    got = ctx.unpack64(ug).cpu().numpy().reshape(uo.shape)
+    err = np.linalg.norm(got - uo) / np.linalg.norm(uo - u0)
+    print(f"filtered RK4 step: relative error of the increment {err:.2e}")
+    assert err <= 1e-10
+    assert ctx.check(ug)
+
+
+def test_warm_start_gain_after_training():
+    """Train the MLP on plain-filter data from held-out shock draws, then filter an
+    unseen draw: identical k, fewer constraint evaluations per troubled element."""
+    from paper_2408_16509_amd import frmi
+    mesh = inputs.hex_box((6, 6, 6))
+    ctx = _ctx(mesh)
+    lay = ctx.layout
+    xs, ks = [], []
+    for seed in range(101, 105):
+        bl = oracle_blocks(mesh, 3)
+        x = bl[0].xsol
+        ic = np.moveaxis(inputs.shock(x[..., 0], x[..., 1], x[..., 2], orient_seed=seed, noise_seed=seed + 100),
+                         0, 1).copy()
+        u = ctx.pack64(ic.ravel())
+        ctx.filter(u, u, mode=0)
+        X, K = ctx.mlp_collect(u, 1e-2, 3, cap=20000)
+        xs.append(X)
+        ks.append(K)
+    X = torch.cat(xs)
+    K = torch.cat(ks)
+    keep = K > 0
+    X, K = X[keep], K[keep]
+    y = torch.log2(K.double()) / 20.0
+    Xn = X.cpu().numpy().astype(np.float64)
+    xm, xsd = Xn.mean(axis=0), Xn.std(axis=0) + 1e-6
+    ctx.mlp_set_weights(omlp.glorot_init(43), xm, xsd)
+    steps = 1500
+    idx = np.concatenate(omlp.batches(X.shape[0], 256, steps, seed=44)).astype(np.int32)
+    hist = ctx.mlp_train(X.contiguous(), y.float().contiguous(), torch.tensor(idx, device="cuda"), steps, 256)
+    h = hist.cpu().numpy()
+    print(f"training rows {X.shape[0]}, loss {h[:10].mean():.3e} -> {h[-10:].mean():.3e}")
+    assert h[-10:].mean() < 0.5 * h[:10].mean()
+    # unseen draw
+    bl = oracle_blocks(mesh, 3)
+    x = bl[0].xsol
+    ic = np.moveaxis(inputs.shock(x[..., 0], x[..., 1], x[..., 2], orient_seed=109, noise_seed=209), 0, 1).copy()
+    u = ctx.pack64(ic.ravel())
+    ctx.filter(u, u, mode=0)
+    ctx.rk_step(u, 1e-2, 1, filter_mode=0)
+    u_prev = u.clone()
+    ctx.rk_step(u, 5e-3, 1, filter_mode=-1)          # unfiltered step: creates troubled elements
+    assert ctx.check(u)
+    res = {}
+    for mode in (0, 1):
+        uu = u.clone()
+        k = torch.zeros(lay.n_elem[0], dtype=torch.int32, device="cuda")
+        st = ctx.filter(uu, u_prev, mode=mode, k=k, stats=True)
+        res[mode] = (k.cpu().numpy(), st.n_evals / max(st.n_troubled, 1), st.n_troubled)
+    print(f"troubled {res[0][2]}: evals per troubled element plain {res[0][1]:.2f}, warm {res[1][1]:.2f}")
+    assert res[0][2] > 0
+    assert np.array_equal(res[0][0], res[1][0])
+    assert res[1][1] < res[0][1]

@@ -160,42 +160,72 @@ def hex_ops(p: int) -> ElementOps:
 
 @lru_cache(maxsize=None)
 def tet_ops(p: int = 4) -> ElementOps:
+    """Tet operators from the same definitions, assembled in extended precision
+    (mpmath, tet.MP_DPS digits) and rounded to FP64 once."""
+    import mpmath
     if p != 4:
         raise ValueError("tetrahedra are supported at p = 4 only (the paper's printed point set)")
+    mpmath.mp.dps = tet.MP_DPS
     sol = tet.SOL_PTS_P4.copy()
     nsp = sol.shape[0]
-    fpts, fface, fnorm, fsrc = [], [], [], []
+    fpts, fface, fnorm = [], [], []
     for f in range(4):
         ids = tet.face_point_ids(f)
         st = tet.face_coords(f, sol[ids])
-        # order the face's points by (t, s) so that the listing is deterministic
         order = np.lexsort((st[:, 0], st[:, 1]))
         for q in ids[order]:
             fpts.append(sol[q])
             fface.append(f)
             fnorm.append(tet.FACES[f][1])
-            fsrc.append(q)
     fpts, fface, fnorm = np.array(fpts), np.array(fface), np.array(fnorm)
     nfp = fpts.shape[0]
-    interp = tet.lagrange(sol, fpts, p)
-    G = tet.lagrange_grad(sol, sol, p)                 # [x][j][d]
-    deriv = np.transpose(G, (2, 0, 1)).copy()         # [d][zeta][nu]
-    # mass matrix and face matrix by quadrature
-    qp, qw = tet.quad_tet(p + 3)
-    Lq = tet.lagrange(sol, qp, p)
-    M = Lq.T @ (qw[:, None] * Lq)
-    weights = Lq.T @ qw
-    E = np.zeros((nsp, nfp))
-    tq, tw = tet.quad_tri(p + 3)
+    # Lagrange coefficients: l_j = sum_m C[m, j] mono_m
+    V = mpmath.matrix([tet.mp_mono_row(x, p) for x in sol])
+    C = V ** -1
+    to_np = lambda A: np.array([[float(A[i, j]) for j in range(A.cols)] for i in range(A.rows)])
+
+    def lag(xs):
+        return mpmath.matrix([tet.mp_mono_row(x, p) for x in xs]) * C
+
+    interp = to_np(lag(fpts))
+    deriv = np.stack([to_np(mpmath.matrix([tet.mp_mono_row(x, p, deriv=d) for x in sol]) * C) for d in range(3)])
+    # mass matrix, weights and face matrices by extended-precision quadrature
+    qp, qw = tet.mp_quad_tet(p + 3)
+    Lq = lag(qp)
+    M = mpmath.matrix(nsp, nsp)
+    wts = mpmath.matrix(nsp, 1)
+    for q in range(len(qw)):
+        for a in range(nsp):
+            la = Lq[q, a] * qw[q]
+            wts[a] += la
+            for b in range(nsp):
+                M[a, b] += la * Lq[q, b]
+    E = mpmath.matrix(nsp, nfp)
+    tq, tw = tet.mp_quad_tri(p + 3)
     for f in range(4):
-        X0, e1, e2, dA = tet.face_param(f)
-        xq = X0 + tq[:, :1] * e1 + tq[:, 1:] * e2
+        i0, i1, i2 = tet.FACES[f][0]
+        X0, X1, X2 = [[mpmath.mpf(float(v)) for v in tet.CORNERS[i]] for i in (i0, i1, i2)]
+        e1 = [X1[k] - X0[k] for k in range(3)]
+        e2 = [X2[k] - X0[k] for k in range(3)]
+        cr = [e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]]
+        dA = mpmath.sqrt(cr[0] ** 2 + cr[1] ** 2 + cr[2] ** 2)
         cols = np.nonzero(fface == f)[0]
         fst = tet.face_coords(f, fpts[cols])
-        phi = tet.tri_monomials(tq, p) @ np.linalg.inv(tet.tri_monomials(fst, p))   # face Lagrange
-        Lf = tet.lagrange(sol, xq, p)
-        E[:, cols] = Lf.T @ ((tw * dA)[:, None] * phi)
-    lift = np.linalg.solve(M, E)
+        tri = lambda st: [st[0] ** a * st[1] ** (d - a) for d in range(p + 1) for a in range(d + 1)]
+        Cf = mpmath.matrix([tri([mpmath.mpf(float(v)) for v in s_]) for s_ in fst]) ** -1
+        xq = [[X0[k] + s_[0] * e1[k] + s_[1] * e2[k] for k in range(3)] for s_ in tq]
+        Lf = lag(xq)
+        phi = mpmath.matrix([tri(s_) for s_ in tq]) * Cf
+        for q in range(len(tw)):
+            wq = tw[q] * dA
+            for a in range(nsp):
+                la = Lf[q, a] * wq
+                if la == 0:
+                    continue
+                for c_, s_ in enumerate(cols):
+                    E[a, int(s_)] += la * phi[q, c_]
+    lift = to_np(M ** -1 * E)
+    weights = np.array([float(wts[a]) for a in range(nsp)])
     modal_V = tet.ortho_basis(sol, p)
     modal_deg = tet.ortho_degrees(p)
     return ElementOps(TET, p, sol, fpts, fface, fnorm, interp, deriv, lift, weights,

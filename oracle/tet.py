@@ -18,9 +18,12 @@ from __future__ import annotations
 import math
 from functools import lru_cache
 
+import mpmath
 import numpy as np
 
 from . import polys
+
+MP_DPS = 40          # digits of the extended-precision operator construction
 
 A = 0.654653670707977      # printed digits; equals sqrt(3/7)
 B = 0.551583572090994
@@ -192,3 +195,82 @@ def face_coords(f, pts):
 def tri_monomials(st, p):
     st = np.atleast_2d(st)
     return np.stack([st[:, 0] ** a * st[:, 1] ** (d - a) for d in range(p + 1) for a in range(d + 1)], axis=1)
+
+
+# ---------------------- extended-precision construction (mpmath) -------------------
+# The tetrahedral operators are assembled in MP_DPS-digit arithmetic from the same
+# definitions (monomial Lagrange coefficients, Gauss rules, mass and face matrices)
+# and rounded to FP64 once, so the oracle's operators carry no construction error
+# beyond that final rounding.
+
+def mp_gauss_legendre(n):
+    """n-point Gauss--Legendre rule on [-1, 1], Newton-refined in mpmath."""
+    mp = mpmath.mp
+    x0, _ = polys.gauss_legendre(n)
+    xs, ws = [], []
+    for z in x0:
+        z = mp.mpf(float(z))
+        for _ in range(60):
+            p0, p1 = mp.mpf(1), z
+            for k in range(1, n):
+                p0, p1 = p1, ((2 * k + 1) * z * p1 - k * p0) / (k + 1)
+            dp = n * (z * p1 - p0) / (z * z - 1)
+            dz = p1 / dp
+            z -= dz
+            if abs(dz) < mp.mpf(10) ** (-(MP_DPS - 5)):
+                break
+        p0, p1 = mp.mpf(1), z
+        for k in range(1, n):
+            p0, p1 = p1, ((2 * k + 1) * z * p1 - k * p0) / (k + 1)
+        dp = n * (z * p1 - p0) / (z * z - 1)
+        xs.append(z)
+        ws.append(2 / ((1 - z * z) * dp * dp))
+    return xs, ws
+
+
+def mp_mono_row(x, p, deriv=None):
+    """Centred monomial values (or one partial derivative) at a point, as mpf list."""
+    c = [mpmath.mpf(float(v)) - mpmath.mpf(-0.5) for v in x] if not isinstance(x[0], mpmath.mpf) else \
+        [v + mpmath.mpf(0.5) for v in x]
+    out = []
+    for a, b, cc in exponents(p):
+        e = [a, b, cc]
+        if deriv is None:
+            out.append(c[0] ** a * c[1] ** b * c[2] ** cc)
+        else:
+            if e[deriv] == 0:
+                out.append(mpmath.mpf(0))
+                continue
+            f = mpmath.mpf(e[deriv])
+            for k in range(3):
+                f *= c[k] ** (e[k] - 1 if k == deriv else e[k])
+            out.append(f)
+    return out
+
+
+def mp_quad_tet(n):
+    g, w = mp_gauss_legendre(n)
+    g = [(v + 1) / 2 for v in g]
+    w = [v / 2 for v in w]
+    P, W = [], []
+    for i in range(n):
+        for j in range(n):
+            for k in range(n):
+                s3 = g[k]
+                s2 = g[j] * (1 - s3)
+                s1 = g[i] * (1 - g[j]) * (1 - s3)
+                P.append([2 * s1 - 1, 2 * s2 - 1, 2 * s3 - 1])
+                W.append(8 * w[i] * w[j] * w[k] * (1 - g[j]) * (1 - s3) ** 2)
+    return P, W
+
+
+def mp_quad_tri(n):
+    g, w = mp_gauss_legendre(n)
+    g = [(v + 1) / 2 for v in g]
+    w = [v / 2 for v in w]
+    P, W = [], []
+    for i in range(n):
+        for j in range(n):
+            P.append([g[i] * (1 - g[j]), g[j]])
+            W.append(w[i] * w[j] * (1 - g[j]))
+    return P, W

@@ -13,6 +13,7 @@
 #include "hex.hpp"
 #include "mlp.hpp"
 #include "setup.hpp"
+#include "tet.hpp"
 
 using namespace frmi;
 
@@ -75,6 +76,10 @@ struct fr_ctx_s {
   int32_t* m_idx = nullptr;
   int m_batch_cap = 0;
   bool mlp_ready = false;
+  // tetrahedral operators on the device (arithmetic type of the context)
+  void* tet_Dh = nullptr;
+  void* tet_L = nullptr;
+  int32_t* tet_src = nullptr;
   // training-data collection during filtered RK steps (fr_mlp_collect)
   bool collecting = false;
   float* col_x = nullptr;
@@ -335,6 +340,41 @@ fr_status hex_rhs_p(fr_ctx c, DevBlock& b, const T* u, T* r) {
 }
 
 template <typename T, bool DEV>
+fr_status tet_rhs(fr_ctx c, DevBlock& b, const T* u, T* r) {
+  constexpr int NE = sizeof(T) == 8 ? 32 : 64, NG = 256 / NE;
+  Conn C{b.nbr_elem, b.nbr_info, c->perm, c->host.perm_stride};
+  const fr_params& p = c->prm;
+  TetDev<T> O;
+  O.Dh = (const T*)c->tet_Dh;
+  O.L = (const T*)c->tet_L;
+  O.src = c->tet_src;
+  for (int f = 0; f < 4; ++f)
+    for (int k = 0; k < 3; ++k) O.nref[f][k] = (T)c->host.tet.nref[f][k];
+  const RefState<T> R = ref_of<T>(p);
+  const T* geo = (const T*)b.geo_t;
+  const unsigned nblk = (unsigned)(b.E / NE);
+  static const std::string sfx = sizeof(T) == 8 ? "" : "_f32";
+  int pk;
+  if (p.system == FR_EULER) {
+    pk = c->prof_begin(("tet_div_euler" + sfx).c_str());
+    tet_div_euler<T, DEV, NE, NG><<<nblk, NE * NG, 0, c->stream>>>(u, geo, C, O, r, b.E, b.n, (T)p.gamma, p.riemann, R);
+    c->prof_end(pk);
+  } else {
+    pk = c->prof_begin(("tet_grad" + sfx).c_str());
+    tet_grad<T, NE, NG><<<nblk, NE * NG, 0, c->stream>>>(u, geo, C, O, (T*)b.grad, b.E, (T)p.ldg_beta);
+    c->prof_end(pk);
+    pk = c->prof_begin(("tet_div_ns" + sfx).c_str());
+    tet_div_ns<T, DEV, NE, NG><<<nblk, NE * NG, 0, c->stream>>>(u, (const T*)b.grad, geo, C, O, r, b.E, b.n,
+                                                               (T)p.gamma, (T)p.mu, (T)p.prandtl, (T)p.ldg_beta,
+                                                               (T)p.ldg_tau, p.riemann, R);
+    c->prof_end(pk);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(c, FR_ERR_DEVICE, std::string("tet kernel launch: ") + hipGetErrorString(e));
+  return FR_OK;
+}
+
+template <typename T, bool DEV>
 fr_status rhs_t(fr_ctx c, const T* u, T* r) {
   for (auto& b : c->blocks) {
     const T* ub = u + b.native_off;
@@ -349,7 +389,7 @@ fr_status rhs_t(fr_ctx c, const T* u, T* r) {
         default: s = fail(c, FR_ERR_UNSUPPORTED, "order");
       }
     } else {
-      s = fail(c, FR_ERR_UNSUPPORTED, "tetrahedra not yet available");
+      s = tet_rhs<T, DEV>(c, b, ub, rb);
     }
     if (s != FR_OK) return s;
   }
@@ -587,6 +627,7 @@ void fr_destroy(fr_ctx c) {
   (void)hipFree(c->perm);
   (void)hipFree(c->rk_stage); (void)hipFree(c->rk_acc); (void)hipFree(c->rk_k);
   (void)hipFree(c->flag);
+  (void)hipFree(c->tet_Dh); (void)hipFree(c->tet_L); (void)hipFree(c->tet_src);
   for (auto& b : c->blocks) { (void)hipFree(b.sown); (void)hipFree(b.smin); }
   for (void* q : {(void*)c->f_k, (void*)c->f_evals, (void*)c->f_flag, (void*)c->f_feat, (void*)c->f_khat,
                   (void*)c->f_copy, (void*)c->m_w, (void*)c->m_m, (void*)c->m_v, (void*)c->m_g, (void*)c->m_scale,
@@ -670,6 +711,30 @@ fr_status fr_setup_mesh(const fr_params* p, int64_t n_vert, const double* xyz, c
   if (hipMemcpy(c->perm, c->host.orient_perm.data(), c->host.orient_perm.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
     c->err = "upload failed";
     return bail(FR_ERR_DEVICE);
+  }
+  bool has_tet = false;
+  for (auto& b : c->blocks) has_tet = has_tet || b.etype == FR_TET;
+  if (has_tet) {
+    const TetOps& T = c->host.tet;
+    std::vector<double> dh(&T.Dh[0][0][0], &T.Dh[0][0][0] + 3 * 35 * 35), L(&T.lift[0][0], &T.lift[0][0] + 35 * 60);
+    std::vector<int32_t> src(T.fp_src, T.fp_src + 60);
+    const size_t bytes_dh = dh.size() * tsz, bytes_l = L.size() * tsz;
+    std::vector<char> bdh(bytes_dh), bl(bytes_l);
+    if (tsz == sizeof(float)) {
+      for (size_t i = 0; i < dh.size(); ++i) ((float*)bdh.data())[i] = (float)dh[i];
+      for (size_t i = 0; i < L.size(); ++i) ((float*)bl.data())[i] = (float)L[i];
+    } else {
+      std::memcpy(bdh.data(), dh.data(), bytes_dh);
+      std::memcpy(bl.data(), L.data(), bytes_l);
+    }
+    if (dalloc(c, (char**)&c->tet_Dh, bytes_dh) || dalloc(c, (char**)&c->tet_L, bytes_l) || dalloc(c, &c->tet_src, 60))
+      return bail(FR_ERR_ALLOC);
+    if (hipMemcpy(c->tet_Dh, bdh.data(), bytes_dh, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->tet_L, bl.data(), bytes_l, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->tet_src, src.data(), 60 * 4, hipMemcpyHostToDevice) != hipSuccess) {
+      c->err = "upload failed";
+      return bail(FR_ERR_DEVICE);
+    }
   }
   *out = c;
   return FR_OK;

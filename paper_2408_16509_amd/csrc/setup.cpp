@@ -84,11 +84,7 @@ void build_hex_ops(int p, HexOps& o) {
     o.cm[a] = (double)(-gL);
     o.x[a] = (double)x[a];
     o.w[a] = (double)w[a];
-    for (int b = 0; b < n; ++b) {
-      o.D[a][b] = (double)D[a][b];
-      ld lpb = bw[b], lmb = bw[b];
-      (void)lpb; (void)lmb;
-    }
+    for (int b = 0; b < n; ++b) o.D[a][b] = (double)D[a][b];
   }
   // fold the correction into the derivative (long double)
   ld lp[kMaxP + 1], lm[kMaxP + 1];
@@ -307,6 +303,16 @@ void build_tet_ops(TetOps& o) {
       for (int j = 0; j < N; ++j) acc += M[i][j] * E[j][s];
       o.lift[i][s] = (double)acc;
     }
+  // fold the collocated normal trace into the derivative:
+  //   Dh_i[z][nu] = D_i[z][nu] - sum_{sigma: src(sigma) = nu} lift[z][sigma] n~_{face(sigma), i}
+  for (int d = 0; d < 3; ++d)
+    for (int z = 0; z < N; ++z)
+      for (int nu = 0; nu < N; ++nu) {
+        ld acc = o.D[d][z][nu];
+        for (int sg = 0; sg < TetOps::nfp; ++sg)
+          if (o.fp_src[sg] == nu) acc -= (ld)o.lift[z][sg] * o.nref[o.fp_face[sg]][d];
+        o.Dh[d][z][nu] = (double)acc;
+      }
   // orthonormal modal basis (graded by total degree)
   int m = 0;
   static ld Vp[N][N];

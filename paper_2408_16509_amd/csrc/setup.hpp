@@ -33,6 +33,8 @@ struct TetOps {
   double nref[4][3];               // unit outward reference normals
   double D[3][nsp][nsp];           // D[i][z][n] = d l_n / d xi_i at x_z
   double lift[nsp][nfp];           // DG lifting M^{-1} E
+  double Dh[3][nsp][nsp];          // D_i - lift * (n~_i at the collocated flux points): the
+                                   // normal trace of f~ folded into the derivative
   double weights[nsp];             // integral of l_z
   double V[nsp][nsp];              // orthonormal modal basis at the points, V[z][m]
   double Vinv[nsp][nsp];

@@ -67,6 +67,18 @@ def test_fp32_rhs_random(order, system, riemann):
     assert g <= 1e-5
 
 
+@pytest.mark.parametrize("system", [0, 1])
+def test_fp32_rhs_random_tets(system):
+    mesh = inputs.kuhn_split(inputs.hex_box((2, 2, 2), perturb=0.1, perturb_seed=6), permute_seed=3)
+    bl = oracle_blocks(mesh, 4)
+    u = state_for(bl, "random", seed=8)
+    Ro = ofr.rhs(bl, u, oracle_params(system, 0))
+    Rg = gpu_rhs32(mesh, u, system=system, order=4, u_ref=UREF_RANDOM)
+    g, pv = rel_err(Rg, Ro)
+    print(f"fp32 tets sys={system}: global {g:.2e} per-var {np.array2string(pv, precision=2)}")
+    assert g <= 1e-5
+
+
 def test_fp32_reference_state_is_exact():
     mesh = inputs.hex_box((3, 3, 3), perturb=0.1, perturb_seed=2)
     bl = oracle_blocks(mesh, 3)

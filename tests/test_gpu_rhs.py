@@ -74,6 +74,14 @@ CASES = [
     ("hex111", 3, 1, 0, "random"),
     ("hex444", 2, 0, 0, "tgv"),
     ("hex444", 3, 1, 0, "tgv"),
+    ("tet1", 4, 0, 0, "random"),
+    ("tet1", 4, 0, 1, "random"),
+    ("tetpert", 4, 0, 0, "random"),
+    ("tetpert", 4, 1, 0, "random"),
+    ("tet1", 4, 1, 1, "random"),
+    ("tetpert", 4, 0, 1, "tgv"),
+    ("mixed", 4, 0, 0, "random"),
+    ("mixed", 4, 1, 0, "random"),
 ]
 
 MESHES = {
@@ -82,6 +90,14 @@ MESHES = {
     "hex111": lambda: inputs.hex_box((1, 1, 1)),
     "hex211": lambda: inputs.hex_box((2, 1, 1)),
     "hexpert": lambda: inputs.hex_box((3, 4, 3), perturb=0.1, perturb_seed=31, permute_seed=32),
+    "tet1": lambda: inputs.kuhn_split(inputs.hex_box((1, 1, 1))),
+    "tetpert": lambda: inputs.kuhn_split(inputs.hex_box((2, 3, 2), perturb=0.1, perturb_seed=51), permute_seed=53),
+    # a hex box and a tet box (shifted so no face of one lies on a face of the other) in one context
+    "mixed": lambda: inputs.concat([
+        inputs.hex_box((2, 2, 2), perturb=0.1, perturb_seed=5),
+        inputs.kuhn_split(inputs.hex_box((2, 2, 2), lo=(-3.0, -3.1, -3.2),
+                                         hi=(-3.0 + 2 * np.pi, -3.1 + 2 * np.pi, -3.2 + 2 * np.pi))),
+    ], permute_seed=7),
 }
 
 

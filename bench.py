@@ -40,29 +40,34 @@ CONFIGS = {
 def kernel_bytes_per_elem(name, nsp, nfp):
     """Compulsory HBM bytes per element of each kernel family (each value touched once).
 
-    NS uses the one-sided LDG switch (beta = 1/2): the gradient kernel reads the
-    neighbour's trace only on faces where the element is the right side and stores
-    gradient traces only there; the divergence kernel reads a neighbour's gradient
-    trace only where the element is the left side (half of the faces each)."""
-    fam = name.rsplit("_p", 1)[0]
+    d is the word size; geometry is 24 words per hexahedron (the 8 corners) and 10
+    per tetrahedron (the affine map), connectivity 2 int32 per face.  NS uses the
+    one-sided LDG switch (beta = 1/2): the gradient kernel reads the neighbour's
+    solution trace only on faces where the element is the right side and stores
+    gradient traces only there (half of the flux points); the face kernel reads one
+    gradient trace per flux point pair, i.e. the stored half."""
+    fam = name.rsplit("_p", 1)[0] if "_p" in name else name
     d = 8
     if fam.endswith("_f32"):
         fam, d = fam[:-4], 4
-    geo_conn = 24 * d + 6 * 2 * 4
-    if fam == "hex_trace":
-        return d * 5 * (nsp + nfp)
-    if fam == "hex_div_euler":
-        return d * (5 * nsp + 5 * nfp + 5 * nsp) + geo_conn
-    if fam == "hex_grad":
-        return d * (5 * nsp + 5 * nfp // 2 + 15 * nsp + 15 * nfp // 2) + geo_conn
-    if fam == "hex_div_ns":
-        return d * (5 * nsp + 15 * nsp + 5 * nfp + 15 * nfp // 2 + 5 * nsp) + geo_conn
-    return None
+    hex_geo, hex_conn = 24 * d, 6 * 2 * 4
+    tet_gc = 10 * d + 4 * 2 * 4
+    table = {
+        "hex_trace": d * 5 * (nsp + nfp),
+        "hex_div_euler": d * (5 * nsp + 5 * nfp + 5 * nsp) + hex_geo + hex_conn,
+        "hex_grad": d * (5 * nsp + 5 * nfp // 2 + 15 * nsp + 15 * nfp // 2) + hex_geo + hex_conn,
+        "hex_face_ns": d * (5 * nfp + 15 * nfp // 2 + 5 * nfp) + hex_geo + hex_conn,
+        "hex_div_ns": d * (5 * nsp + 15 * nsp + 5 * nfp + 5 * nsp) + hex_geo,
+        "tet_div_euler": d * (5 * nsp + 5 * nsp) + tet_gc,
+        "tet_grad": d * (5 * nsp + 15 * nsp) + tet_gc,
+        "tet_div_ns": d * (5 * nsp + 15 * nsp + 5 * nsp) + tet_gc,
+    }
+    return table.get(fam)
 
 
 def source_hash():
     h = hashlib.sha256()
-    for f in ("hex.hpp", "physics.hpp", "frmi.hip"):
+    for f in ("hex.hpp", "tet.hpp", "physics.hpp", "filter.hpp", "frmi.hip"):
         with open(os.path.join(ROOT, "paper_2408_16509_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -33,6 +33,7 @@ struct DevBlock {
   void* uf = nullptr;       // [nfp][5][E]
   void* grad = nullptr;     // [nsp][15][E]
   void* gradf = nullptr;    // [nfp][15][E]
+  void* fc = nullptr;       // [nfp][5][E] common fluxes (Navier--Stokes)
   int64_t elem_off = 0;     // offset of the block in canonical element order
   double* sown = nullptr;   // entropy filter: own min entropy [E]
   double* smin = nullptr;   // entropy filter: neighbourhood min entropy [E]
@@ -278,6 +279,9 @@ template <> struct HexCfg<1> { static constexpr int NE = 64; };
 template <> struct HexCfg<2> { static constexpr int NE = 32; };
 template <> struct HexCfg<3> { static constexpr int NE = 16; };
 template <> struct HexCfg<4> { static constexpr int NE = 8; };
+// element tile of the NS divergence (its LDS holds 15 values per point and element)
+template <typename T, int P>
+struct DivNsCfg { static constexpr int NE = (sizeof(T) == 8 ? 8 : 16) / (P == 4 ? 2 : 1) * (P <= 2 ? 2 : 1); };
 
 template <typename T>
 HexK<T> hexk_of(const HexOps& H) {
@@ -328,10 +332,16 @@ fr_status hex_rhs_p(fr_ctx c, DevBlock& b, const T* u, T* r) {
     pk = c->prof_begin(("hex_grad" + sfx).c_str());
     hex_grad<T, P, NE><<<nblk, NT, 0, c->stream>>>(u, uf, geo, C, grad, gradf, b.E, K, (T)p.ldg_beta, sm);
     c->prof_end(pk);
+    T* fc = (T*)b.fc;
+    const int64_t face_threads = b.E * 6 * N1 * N1;
+    pk = c->prof_begin(("hex_face_ns" + sfx).c_str());
+    hex_face_ns<T, DEV, P><<<(unsigned)((face_threads + 255) / 256), 256, 0, c->stream>>>(
+        uf, gradf, geo, C, fc, b.E, K, (T)p.gamma, (T)p.mu, (T)p.prandtl, (T)p.ldg_beta, (T)p.ldg_tau, p.riemann, sm, R);
+    c->prof_end(pk);
+    constexpr int NE2 = DivNsCfg<T, P>::NE;
     pk = c->prof_begin(("hex_div_ns" + sfx).c_str());
-    hex_div_ns<T, DEV, P, NE><<<nblk, NT, 0, c->stream>>>(u, uf, grad, gradf, geo, C, r, b.E, b.n, K, (T)p.gamma,
-                                                          (T)p.mu, (T)p.prandtl, (T)p.ldg_beta, (T)p.ldg_tau,
-                                                          p.riemann, sm, R);
+    hex_div_ns<T, DEV, P, NE2><<<(unsigned)(b.E / NE2), NE2 * N1 * N1, 0, c->stream>>>(
+        u, grad, fc, geo, r, b.E, b.n, K, (T)p.gamma, (T)p.mu, (T)p.prandtl, R);
     c->prof_end(pk);
   }
   hipError_t e = hipGetLastError();
@@ -622,7 +632,7 @@ void fr_destroy(fr_ctx c) {
   for (auto& b : c->blocks) {
     if (b.geo_t && b.geo_t != b.geo) (void)hipFree(b.geo_t);
     (void)hipFree(b.geo); (void)hipFree(b.nbr_elem); (void)hipFree(b.nbr_info);
-    (void)hipFree(b.uf); (void)hipFree(b.grad); (void)hipFree(b.gradf);
+    (void)hipFree(b.uf); (void)hipFree(b.grad); (void)hipFree(b.gradf); (void)hipFree(b.fc);
   }
   (void)hipFree(c->perm);
   (void)hipFree(c->rk_stage); (void)hipFree(c->rk_acc); (void)hipFree(c->rk_k);
@@ -687,7 +697,8 @@ fr_status fr_setup_mesh(const fr_params* p, int64_t n_vert, const double* xyz, c
       return bail(FR_ERR_ALLOC);
     if (p->system == FR_NAVIER_STOKES &&
         (dalloc(c, (char**)&d.grad, (size_t)d.nsp * 15 * d.E * tsz) ||
-         dalloc(c, (char**)&d.gradf, (size_t)d.nfp * 15 * d.E * tsz)))
+         dalloc(c, (char**)&d.gradf, (size_t)d.nfp * 15 * d.E * tsz) ||
+         dalloc(c, (char**)&d.fc, (size_t)d.nfp * 5 * d.E * tsz)))
       return bail(FR_ERR_ALLOC);
     d.geo_t = d.geo;
     if (tsz == sizeof(float)) {

@@ -464,105 +464,131 @@ __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_grad(
 }
 
 // ---------------------------------------------------------------------------
-// Navier--Stokes phase 2: f = f_inv - f_v at the solution points, LDG common
-// flux (inviscid Riemann flux minus the switched viscous flux plus the penalty)
-// at the line ends, corrected divergence.  The own side's gradient trace at a
-// line end comes from the line's own solution-point gradients.
+// Navier--Stokes phase 2a: the LDG common flux at every flux point of every element
+// (eq:comm_flux with the viscous terms): inviscid Riemann flux along the left
+// side's normal, minus the switched viscous flux, plus the penalty; entering this
+// element as +-|S^T n~| times it.  One thread per (element, flux point), lanes over
+// elements.  With a one-sided switch only the contributing side's gradient trace
+// is read (stored by hex_grad in that side's slot).
+template <typename T, bool DEV, int P>
+__global__ void __launch_bounds__(256) hex_face_ns(const T* __restrict__ uf, const T* __restrict__ gradf,
+                                                   const T* __restrict__ geo, Conn C, T* __restrict__ fc, int64_t E,
+                                                   HexK<T> K, T gamma, T mu, T pr, T beta, T tau, int riemann,
+                                                   int side_mode, RefState<T> R) {
+  constexpr int N1 = P + 1, NF = N1 * N1, NFP = 6 * NF;
+  const int64_t gtid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t wave = gtid >> 6;
+  const int lane = (int)(gtid & 63);
+  const int64_t tile = wave / NFP;
+  const int fp = (int)(wave % NFP);
+  const int64_t e = tile * 64 + lane;
+  if (e >= E) return;
+  const int face = fp / NF, q = fp % NF, d = face / 2, sd = face % 2, t0 = q % N1, t1 = q / N1;
+  T c[24];
+#pragma unroll
+  for (int g = 0; g < 24; ++g) c[g] = geo[(int64_t)g * E + e];
+  T xi[3], g[3][3], nv[3];
+  end_xi(K, d, sd, t0, t1, xi);
+  hex_cols(c, 1, xi[0], xi[1], xi[2], g);
+  srow(g, d, nv);
+  const T mag = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+  const NbrSlot ns = nbr_slot<NF>(C, E, e, face, q);
+  T own[5], un[5], uL[5], uR[5], nL[3], F[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    own[v] = uf[((int64_t)fp * 5 + v) * E + e];
+    un[v] = uf[((int64_t)ns.fp * 5 + v) * E + ns.elem];
+  }
+  const T sg = sd ? T(1) : T(-1);
+  const T sl = (ns.left ? sg : -sg) / mag;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) nL[k] = nv[k] * sl;
+#pragma unroll
+  for (int v = 0; v < 5; ++v) { uL[v] = ns.left ? own[v] : un[v]; uR[v] = ns.left ? un[v] : own[v]; }
+  common_inviscid<T, DEV>(riemann, uL, uR, nL, gamma, R, F);
+  const T wL = T(0.5) - beta, wR = T(0.5) + beta;
+  const T w_own = ns.left ? wL : wR, w_nbr = ns.left ? wR : wL;
+  T fvc[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+    const T wgt = side == 0 ? w_own : w_nbr;
+    if (side_mode != 0 && wgt == T(0)) continue;
+    const int64_t gs = side == 0 ? (int64_t)fp : (int64_t)ns.fp;
+    const int64_t ge = side == 0 ? e : ns.elem;
+    T gk[15], fv[5];
+#pragma unroll
+    for (int k = 0; k < 15; ++k) gk[k] = gradf[(gs * 15 + k) * E + ge];
+    viscous<T, DEV>(side == 0 ? own : un, gk, nL[0], nL[1], nL[2], gamma, mu, pr, R, fv);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) fvc[v] += wgt * fv[v];
+  }
+  const T fs = ns.left ? mag : -mag;
+#pragma unroll
+  for (int v = 0; v < 5; ++v) fc[((int64_t)fp * 5 + v) * E + e] = fs * (F[v] - fvc[v] + tau * (uL[v] - uR[v]));
+}
+
+// ---------------------------------------------------------------------------
+// Navier--Stokes phase 2b: f = f_inv - f_v at the solution points and the
+// corrected divergence with the common fluxes of hex_face_ns at the line ends.
+// Each thread owns one column (i, j) of one element: it evaluates the transformed
+// flux of all three directions at its column's points once (every u and grad u
+// value is read once) into LDS, then gathers, for each of its points, the three
+// line contractions through that point from LDS.
 template <typename T, bool DEV, int P, int NE>
 __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_div_ns(
-    const T* __restrict__ u, const T* __restrict__ uf, const T* __restrict__ grad,
-    const T* __restrict__ gradf, const T* __restrict__ geo, Conn C, T* __restrict__ r,
-    int64_t E, int64_t n, HexK<T> K, T gamma, T mu, T pr, T beta, T tau, int riemann, int side_mode,
-    RefState<T> R) {
+    const T* __restrict__ u, const T* __restrict__ grad, const T* __restrict__ fc, const T* __restrict__ geo,
+    T* __restrict__ r, int64_t E, int64_t n, HexK<T> K, T gamma, T mu, T pr, RefState<T> R) {
   constexpr int N1 = P + 1, NSP = N1 * N1 * N1, NF = N1 * N1, NT = NE * N1 * N1;
-  __shared__ T DIV[5 * NSP * NE];
+  __shared__ T FT[3 * 5 * NSP * NE];       // [d][v][pt][el]
   __shared__ T G[24 * NE];
   const int el = threadIdx.x % NE, l = threadIdx.x / NE;
   const int64_t e0 = (int64_t)blockIdx.x * NE, e = e0 + el;
-  const int t0 = l % N1, t1 = l / N1;
+  const int ci = l % N1, cj = l / N1;
   stage_geo<T, NE, NT>(geo, E, e0, G);
   __syncthreads();
   const T gm1 = gamma - T(1);
+  T iJ[N1];
 #pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    T ft[5][N1], tm[5] = {0, 0, 0, 0, 0}, tp[5] = {0, 0, 0, 0, 0};
+  for (int k = 0; k < N1; ++k) {
+    const int pt = ci + N1 * (cj + N1 * k);
+    T uu[5], gg[15];
 #pragma unroll
-    for (int a = 0; a < N1; ++a) {
-      const int pt = line_pt<N1>(d, a, t0, t1);
-      T uu[5], gg[15];
+    for (int v = 0; v < 5; ++v) uu[v] = u[((int64_t)pt * 5 + v) * E + e];
 #pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        uu[v] = u[((int64_t)pt * 5 + v) * E + e];
-        tm[v] += K.lm[a] * uu[v];
-        tp[v] += K.lp[a] * uu[v];
-      }
+    for (int q = 0; q < 15; ++q) gg[q] = grad[((int64_t)pt * 15 + q) * E + e];
+    T g[3][3];
+    hex_cols(G + el, NE, K.x[ci], K.x[cj], K.x[k], g);
+    iJ[k] = T(-1) / det_cols(g);
 #pragma unroll
-      for (int k = 0; k < 15; ++k) gg[k] = grad[((int64_t)pt * 15 + k) * E + e];
-      T xi[3], g[3][3], s[3], f[5], fv[5], vs, prs;
-      line_xi(K, d, a, t0, t1, xi);
-      hex_cols(G + el, NE, xi[0], xi[1], xi[2], g);
+    for (int d = 0; d < 3; ++d) {
+      T s[3], f[5], fv[5], vs, prs;
       srow(g, d, s);
       Flux<T, DEV>::eval(uu, s[0], s[1], s[2], gm1, R, f, vs, prs);
       viscous<T, DEV>(uu, gg, s[0], s[1], s[2], gamma, mu, pr, R, fv);
 #pragma unroll
-      for (int v = 0; v < 5; ++v) ft[v][a] = f[v] - fv[v];
+      for (int v = 0; v < 5; ++v) FT[((d * 5 + v) * NSP + pt) * NE + el] = f[v] - fv[v];
     }
-    T Fc[2][5];
+  }
+  __syncthreads();
 #pragma unroll
-    for (int sd = 0; sd < 2; ++sd) {
-      T xi[3], g[3][3], nv[3];
-      end_xi(K, d, sd, t0, t1, xi);
-      hex_cols(G + el, NE, xi[0], xi[1], xi[2], g);
-      srow(g, d, nv);
-      const T sg = sd ? T(1) : T(-1);
-      const T mag = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
-      const NbrSlot ns = nbr_slot<NF>(C, E, e, 2 * d + sd, l);
-      T un[5];
+  for (int k = 0; k < N1; ++k) {
+    const int pt = ci + N1 * (cj + N1 * k);
+    // line coordinates of this point in each direction: (position a, face-local q)
+    const int a0 = ci, q0 = cj + N1 * k, a1 = cj, q1 = ci + N1 * k, a2 = k, q2 = ci + N1 * cj;
 #pragma unroll
-      for (int v = 0; v < 5; ++v) un[v] = uf[((int64_t)ns.fp * 5 + v) * E + ns.elem];
-      const T* own = sd ? tp : tm;
-      T uL[5], uR[5], nL[3], F[5];
+    for (int v = 0; v < 5; ++v) {
+      T acc = T(0);
 #pragma unroll
-      for (int v = 0; v < 5; ++v) { uL[v] = ns.left ? own[v] : un[v]; uR[v] = ns.left ? un[v] : own[v]; }
-      const T sl = (ns.left ? sg : -sg) / mag;
-#pragma unroll
-      for (int k = 0; k < 3; ++k) nL[k] = nv[k] * sl;
-      common_inviscid<T, DEV>(riemann, uL, uR, nL, gamma, R, F);
-      // viscous common flux: wL fv(L) + wR fv(R), wL = 1/2 - beta, wR = 1/2 + beta
-      const T wL = T(0.5) - beta, wR = T(0.5) + beta;
-      const T w_own = ns.left ? wL : wR, w_nbr = ns.left ? wR : wL;
-      T fvc[5] = {0, 0, 0, 0, 0};
-      if (side_mode == 0 || w_own != T(0)) {
-        T go[15];
-#pragma unroll
-        for (int k = 0; k < 15; ++k) go[k] = T(0);
-#pragma unroll
-        for (int a = 0; a < N1; ++a) {
-          const T la = sd ? K.lp[a] : K.lm[a];
-          const int pt = line_pt<N1>(d, a, t0, t1);
-#pragma unroll
-          for (int k = 0; k < 15; ++k) go[k] += la * grad[((int64_t)pt * 15 + k) * E + e];
-        }
-        T fv[5];
-        viscous<T, DEV>(own, go, nL[0], nL[1], nL[2], gamma, mu, pr, R, fv);
-#pragma unroll
-        for (int v = 0; v < 5; ++v) fvc[v] += w_own * fv[v];
+      for (int b = 0; b < N1; ++b) {
+        acc += K.Dh[a0][b] * FT[((0 * 5 + v) * NSP + (b + N1 * (cj + N1 * k))) * NE + el];
+        acc += K.Dh[a1][b] * FT[((1 * 5 + v) * NSP + (ci + N1 * (b + N1 * k))) * NE + el];
+        acc += K.Dh[a2][b] * FT[((2 * 5 + v) * NSP + (ci + N1 * (cj + N1 * b))) * NE + el];
       }
-      if (side_mode == 0 || w_nbr != T(0)) {
-        T gn[15];
-#pragma unroll
-        for (int k = 0; k < 15; ++k) gn[k] = gradf[((int64_t)ns.fp * 15 + k) * E + ns.elem];
-        T fv[5];
-        viscous<T, DEV>(un, gn, nL[0], nL[1], nL[2], gamma, mu, pr, R, fv);
-#pragma unroll
-        for (int v = 0; v < 5; ++v) fvc[v] += w_nbr * fv[v];
-      }
-      const T fs = ns.left ? mag : -mag;
-#pragma unroll
-      for (int v = 0; v < 5; ++v) Fc[sd][v] = fs * (F[v] - fvc[v] + tau * (uL[v] - uR[v]));
+      acc += K.cp[a0] * fc[(((int64_t)1 * NF + q0) * 5 + v) * E + e] + K.cm[a0] * fc[(((int64_t)0 * NF + q0) * 5 + v) * E + e];
+      acc += K.cp[a1] * fc[(((int64_t)3 * NF + q1) * 5 + v) * E + e] + K.cm[a1] * fc[(((int64_t)2 * NF + q1) * 5 + v) * E + e];
+      acc += K.cp[a2] * fc[(((int64_t)5 * NF + q2) * 5 + v) * E + e] + K.cm[a2] * fc[(((int64_t)4 * NF + q2) * 5 + v) * E + e];
+      if (e < n) r[((int64_t)pt * 5 + v) * E + e] = acc * iJ[k];
     }
-    accumulate_div<T, N1, NE>(d, ft, Fc, K, DIV, G, el, t0, t1, e, n, E, r);
-    if (d < 2) __syncthreads();
   }
 }
 

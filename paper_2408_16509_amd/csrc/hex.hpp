@@ -31,6 +31,17 @@
 
 namespace frmi {
 
+// Workgroups of a launch are dispatched round-robin over the 8 XCDs, each with its
+// own L2.  Renumber them so that every XCD works through one contiguous range of
+// logical blocks: blocks that read the same cache lines (neighbouring element tiles,
+// the lines of one tile) then meet in the same L2 instead of fetching from HBM once
+// per XCD.  A bijection on [0, gridDim.x).
+__device__ __forceinline__ int64_t xcd_block() {
+  const uint32_t b = blockIdx.x, nb = gridDim.x;
+  const uint32_t x = b & 7u, i = b >> 3, q = nb >> 3, r = nb & 7u;
+  return (int64_t)x * q + (x < r ? x : r) + i;
+}
+
 template <typename T>
 struct HexK {
   T x[5], lm[5], lp[5], Dh[5][5], cp[5], cm[5];
@@ -230,7 +241,7 @@ __device__ __forceinline__ void stage_geo(const T* __restrict__ geo, int64_t E, 
 template <typename T, int P>
 __global__ void __launch_bounds__(256) hex_trace(const T* __restrict__ u, T* __restrict__ uf, int64_t E, HexK<T> K) {
   constexpr int N1 = P + 1, NL = 3 * N1 * N1;
-  const int64_t gtid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t gtid = xcd_block() * 256 + threadIdx.x;
   const int64_t wave = gtid >> 6;
   const int lane = (int)(gtid & 63);
   const int64_t tile = wave / NL;
@@ -307,7 +318,7 @@ __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_div_euler(
   __shared__ T DIV[5 * NSP * NE];
   __shared__ T G[24 * NE];
   const int el = threadIdx.x % NE, l = threadIdx.x / NE;
-  const int64_t e0 = (int64_t)blockIdx.x * NE, e = e0 + el;
+  const int64_t e0 = xcd_block() * NE, e = e0 + el;
   const int t0 = l % N1, t1 = l / N1;
   stage_geo<T, NE, NT>(geo, E, e0, G);
   __syncthreads();
@@ -378,7 +389,7 @@ __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_grad(
   __shared__ T GR[3 * NSP * NE];
   __shared__ T G[24 * NE];
   const int el = threadIdx.x % NE, l = threadIdx.x / NE;
-  const int64_t e0 = (int64_t)blockIdx.x * NE, e = e0 + el;
+  const int64_t e0 = xcd_block() * NE, e = e0 + el;
   const int t0 = l % N1, t1 = l / N1;
   stage_geo<T, NE, NT>(geo, E, e0, G);
   // connectivity of this thread's 6 line ends
@@ -476,7 +487,7 @@ __global__ void __launch_bounds__(256) hex_face_ns(const T* __restrict__ uf, con
                                                    HexK<T> K, T gamma, T mu, T pr, T beta, T tau, int riemann,
                                                    int side_mode, RefState<T> R) {
   constexpr int N1 = P + 1, NF = N1 * N1, NFP = 6 * NF;
-  const int64_t gtid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t gtid = xcd_block() * 256 + threadIdx.x;
   const int64_t wave = gtid >> 6;
   const int lane = (int)(gtid & 63);
   const int64_t tile = wave / NFP;
@@ -542,7 +553,7 @@ __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_div_ns(
   __shared__ T FT[3 * 5 * NSP * NE];       // [d][v][pt][el]
   __shared__ T G[24 * NE];
   const int el = threadIdx.x % NE, l = threadIdx.x / NE;
-  const int64_t e0 = (int64_t)blockIdx.x * NE, e = e0 + el;
+  const int64_t e0 = xcd_block() * NE, e = e0 + el;
   const int ci = l % N1, cj = l / N1;
   stage_geo<T, NE, NT>(geo, E, e0, G);
   __syncthreads();

@@ -68,7 +68,7 @@ __global__ void __launch_bounds__(NE * NG) tet_div_euler(const T* __restrict__ u
                                                          int64_t n, T gamma, int riemann, RefState<T> R) {
   __shared__ T B[(3 * TET_NSP + TET_NFP) * NE];
   const int el = threadIdx.x % NE, g = threadIdx.x / NE;
-  const int64_t e = (int64_t)blockIdx.x * NE + el;
+  const int64_t e = xcd_block() * NE + el;
   T S[9], J;
   tet_geo(geo, E, e, S, J);
   const T gm1 = gamma - T(1);
@@ -121,7 +121,7 @@ __global__ void __launch_bounds__(NE * NG) tet_grad(const T* __restrict__ u, con
                                                     TetDev<T> O, T* __restrict__ grad, int64_t E, T beta) {
   __shared__ T B[(TET_NSP + TET_NFP) * NE];
   const int el = threadIdx.x % NE, g = threadIdx.x / NE;
-  const int64_t e = (int64_t)blockIdx.x * NE + el;
+  const int64_t e = xcd_block() * NE + el;
   T S[9], J;
   tet_geo(geo, E, e, S, J);
   for (int v = 0; v < 5; ++v) {
@@ -163,7 +163,7 @@ __global__ void __launch_bounds__(NE * NG) tet_div_ns(const T* __restrict__ u, c
                                                       T beta, T tau, int riemann, RefState<T> R) {
   __shared__ T B[(3 * TET_NSP + TET_NFP) * NE];
   const int el = threadIdx.x % NE, g = threadIdx.x / NE;
-  const int64_t e = (int64_t)blockIdx.x * NE + el;
+  const int64_t e = xcd_block() * NE + el;
   T S[9], J;
   tet_geo(geo, E, e, S, J);
   const T gm1 = gamma - T(1);

@@ -30,11 +30,36 @@ HBM_PEAK_GBS = 8000.0
 
 CONFIGS = {
     # name: mesh cells, order, system, riemann, Mach, dt
-    "ns_tgv_hex32_p3": dict(n=(32, 32, 32), order=3, system=1, riemann=0, mach=0.1, dt=4e-4),
-    "euler_tgv_hex4_p2": dict(n=(4, 4, 4), order=2, system=0, riemann=0, mach=0.1, dt=1e-3),
+    "ns_tgv_hex32_p3": dict(n=(32, 32, 32), order=3, system=1, riemann=0, mach=0.1, dt=4e-4, oracle_ok=True),
+    "euler_tgv_hex4_p2": dict(n=(4, 4, 4), order=2, system=0, riemann=0, mach=0.1, dt=1e-3, oracle_ok=True),
     "ns_tgv_hex48pert_p4": dict(n=(48, 48, 48), order=4, system=1, riemann=0, mach=0.1, dt=1.5e-4,
                                 perturb=0.1, perturb_seed=31, permute_seed=32),
+    # 32x64x64 cells twice, +-10 % perturbed (seed 51): p = 4 hexahedra, and the same
+    # cells as 6 p = 4 tetrahedra each (917,504 elements), element order seed 53
+    "ns_tgv_mixed_c5split_p4": dict(kind="mixed", n=(32, 64, 64), order=4, system=1, riemann=0, mach=0.1,
+                                    dt=7.5e-5, perturb=0.1, perturb_seed=51, permute_seed=53),
+    # Mach-3 shock (orientation seed 41, density noise seed 42), Euler + HLLC, entropy
+    # filter on every RK stage: plain bisection vs the learned warm start, the MLP
+    # trained on the plain filter's data from held-out draws (seeds 101-108 / 201-208)
+    "euler_shock_hex48_p3": dict(n=(48, 48, 48), order=3, system=0, riemann=1, dt=5e-4, filter=True,
+                                 orient_seed=41, noise_seed=42, train_seeds=tuple(range(101, 109)),
+                                 train_steps=50, val_seed=109, train_iters=4000),
 }
+
+
+def build_mesh(cfg, inputs):
+    if cfg.get("kind") == "mixed":
+        # two conforming periodic boxes in one context: hexahedra, and the same cells
+        # cut into 6 tetrahedra each (the tet box offset in x so the two never pair)
+        n = cfg["n"]
+        lo_b = (3.0, -3.141592653589793, -3.141592653589793)
+        hi_b = tuple(v + 2 * 3.141592653589793 for v in lo_b)
+        a = inputs.hex_box(n, perturb=cfg["perturb"], perturb_seed=cfg["perturb_seed"])
+        b = inputs.kuhn_split(inputs.hex_box(n, lo=lo_b, hi=hi_b, perturb=cfg["perturb"],
+                                             perturb_seed=cfg["perturb_seed"]))
+        return inputs.concat([a, b], permute_seed=cfg["permute_seed"])
+    return inputs.hex_box(cfg["n"], perturb=cfg.get("perturb", 0.0), perturb_seed=cfg.get("perturb_seed"),
+                          permute_seed=cfg.get("permute_seed"))
 
 
 def kernel_bytes_per_elem(name, nsp, nfp):
@@ -118,9 +143,14 @@ def run_form(form, cfg, mesh, ic, args, torch, np, frmi):
         kw.update(precision=frmi.FR_FP32, u_ref=(1.0, 0.0, 0.0, 0.0, p0 / 0.4))
     ctx = frmi.Context(mesh, **kw)
     lay = ctx.layout
-    E, nsp, nfp = lay.n_elem[0], lay.n_sp[0], lay.n_fp[0]
-    x = ctx.sol_points().reshape(E, nsp, 3)
-    u0 = ctx.pack64(ic(x).ravel())
+    x = ctx.sol_points()
+    canon, off, blocks = [], 0, {}
+    for i in range(lay.n_types):
+        n, s = lay.n_elem[i], lay.n_sp[i]
+        canon.append(ic(x[off:off + n * s].reshape(n, s, 3)).ravel())
+        off += n * s
+        blocks["hex" if lay.etype[i] == frmi.FR_HEX else "tet"] = (int(n), int(s), int(lay.n_fp[i]))
+    u0 = ctx.pack64(np.concatenate(canon))
     u = u0.clone()
     stream = torch.cuda.current_stream()
     for _ in range(args.warmup):
@@ -135,7 +165,7 @@ def run_form(form, cfg, mesh, ic, args, torch, np, frmi):
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     ms = ev0.elapsed_time(ev1) / args.steps
-    res = {"ctx": ctx, "ms": ms, "wall": wall, "finite": ctx.check(u), "E": E, "nsp": nsp, "nfp": nfp}
+    res = {"ctx": ctx, "ms": ms, "wall": wall, "finite": ctx.check(u), "blocks": blocks}
     if not args.no_kernel_timing:
         uk = u0.clone()
         ctx.profile(True)
@@ -144,6 +174,130 @@ def run_form(form, cfg, mesh, ic, args, torch, np, frmi):
         res["times"] = ctx.profile_read()
         ctx.profile(False)
     return res
+
+
+def run_filter_workload(cfg, args, torch, np, frmi, inputs):
+    """Shock workload with the entropy filter (FP64 form): train the warm-start MLP on
+    held-out draws, then time filtered RK4 steps with the plain and the learned search
+    on the measured draw; compare the dyadic indices both searches return and count
+    constraint evaluations per troubled element."""
+    mesh = inputs.hex_box(cfg["n"])
+    ctx = frmi.Context(mesh, system=cfg["system"], order=cfg["order"], riemann=cfg["riemann"])
+    lay = ctx.layout
+    E, nsp, nfp = lay.n_elem[0], lay.n_sp[0], lay.n_fp[0]
+    x = ctx.sol_points().reshape(E, nsp, 3)
+
+    def ic(o_seed, n_seed):
+        s_ = inputs.shock(x[..., 0], x[..., 1], x[..., 2], orient_seed=o_seed, noise_seed=n_seed)
+        u = ctx.pack64(np.moveaxis(s_, 0, 1).copy().ravel())
+        ctx.filter(u, u, mode=0)
+        return u
+
+    dt = cfg["dt"]
+    # training data: the plain filter's (features, dyadic index) rows from held-out draws
+    t0 = time.perf_counter()
+    xs, ks = [], []
+    for sd in cfg["train_seeds"]:
+        X, K = ctx.mlp_collect(ic(sd, sd + 100), dt, cfg["train_steps"], cap=4_000_000)
+        xs.append(X[K > 0])
+        ks.append(K[K > 0])
+    X = torch.cat(xs).contiguous()
+    y = (torch.log2(torch.cat(ks).double()) / 20.0).float().contiguous()
+    Xv, Kv = ctx.mlp_collect(ic(cfg["val_seed"], cfg["val_seed"] + 100), dt, 10, cap=1_000_000)
+    Xv, yv = Xv[Kv > 0].contiguous(), (torch.log2(Kv[Kv > 0].double()) / 20.0).float()
+    Xn = X.double()
+    ctx.mlp_set_weights(inputs.mlp_glorot(43), Xn.mean(0).cpu().numpy(), (Xn.std(0) + 1e-6).cpu().numpy())
+    iters = cfg["train_iters"]
+    rows = torch.tensor(inputs.minibatch_rows(X.shape[0], 256, iters, 44), device="cuda")
+    hist = ctx.mlp_train(X, y, rows, iters, 256).cpu().numpy()
+    val = float(((ctx.mlp_forward(Xv) - yv) ** 2).mean()) if Xv.shape[0] else None
+    train_s = time.perf_counter() - t0
+    # measured draw
+    u0 = ic(cfg["orient_seed"], cfg["noise_seed"])
+    for _ in range(args.warmup):
+        ctx.rk_step(u0, dt, 1, filter_mode=0)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    runs = {}
+    for mode, name in ((0, "plain"), (1, "mlp")):
+        u = u0.clone()
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(args.steps):
+            ctx.rk_step(u, dt, 1, filter_mode=mode)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / args.steps
+        uk = u0.clone()
+        ctx.profile(True)
+        for _ in range(2):
+            ctx.rk_step(uk, dt, 1, filter_mode=mode)
+        times = ctx.profile_read()
+        ctx.profile(False)
+        runs[name] = {"ms": ms, "u": u, "times": times, "finite": ctx.check(u)}
+    # filter statistics on stage-like states: one unfiltered step from points of the trajectory
+    probe = {"plain": [0, 0, 0], "mlp": [0, 0, 0]}
+    k_equal, k_total, filt_ms = 0, 0, {"plain": [], "mlp": []}
+    u = u0.clone()
+    for i in range(5):
+        for _ in range(max(1, args.steps // 5)):
+            ctx.rk_step(u, dt, 1, filter_mode=0)
+        us = u.clone()
+        ctx.rk_step(us, dt, 1, filter_mode=-1)
+        kk = {}
+        for mode, name in ((0, "plain"), (1, "mlp")):
+            uu = us.clone()
+            k = torch.zeros(E, dtype=torch.int32, device="cuda")
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            ev0.record(stream)
+            ctx.filter(uu, u, mode=mode, k=k)
+            ev1.record(stream)
+            st = ctx.filter(us.clone(), u, mode=mode, stats=True)
+            filt_ms[name].append(ev0.elapsed_time(ev1))
+            probe[name][0] += st.n_troubled
+            probe[name][1] += st.n_evals
+            probe[name][2] += st.n_fallback
+            kk[name] = k
+        touched = (kk["plain"] != 0) | (kk["mlp"] != 0)
+        k_equal += int(((kk["plain"] == kk["mlp"]) & touched).sum())
+        k_total += int(touched.sum())
+    dof = E * nsp
+    gd = {n: 4 * dof / (r["ms"] * 1e-3) / 1e9 for n, r in runs.items()}
+    out = {
+        "metric": "RHS GDoF/s (FP32/learned vs FP64 plain) at stated L2 error; % HBM roofline",
+        "value": round(gd["mlp"], 4), "unit": "GDoF/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(runs["mlp"]["ms"], 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": args.config, "elements": int(E), "order": cfg["order"], "points_per_elem": int(nsp),
+                   "dof": int(dof), "rhs_per_step": 4, "form": "fp64, entropy filter on every stage, learned warm start",
+                   "state_finite_after": bool(runs["mlp"]["finite"] and runs["plain"]["finite"])},
+        "forms": {},
+        "filter": {
+            "train_rows": int(X.shape[0]), "train_iters": iters, "train_s": round(train_s, 2),
+            "loss_first_last": [float(hist[:20].mean()), float(hist[-20:].mean())], "val_mse": val,
+            "k_identical_fraction_troubled": k_equal / max(k_total, 1),
+        },
+    }
+    for n, r in runs.items():
+        out["forms"][f"fp64_filter_{n}"] = {
+            "gdof_s": round(gd[n], 4), "ms_per_step": round(r["ms"], 4),
+            "kernels_ms_per_step": {k: round(v[1] / 2, 4) for k, v in sorted(r["times"].items())}}
+        tr, ev, fb = probe[n]
+        out["filter"][n] = {"troubled_per_call": tr / 5, "evals_per_troubled": round(ev / max(tr, 1), 3),
+                            "fallback_per_call": fb / 5, "filter_call_ms": round(float(np.mean(filt_ms[n])), 4)}
+    times = runs["mlp"]["times"]
+    fam = {k: v for k, v in times.items() if kernel_bytes_per_elem(k, nsp, nfp) is not None}
+    dom = max(fam, key=lambda k: fam[k][1])
+    launches, tot = fam[dom]
+    avg_ms = tot / launches
+    by = kernel_bytes_per_elem(dom, nsp, nfp) * E
+    achieved = by / (avg_ms * 1e-3) / 1e9
+    out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": load_traffic(dom, args.config),
+                       "kernel": dom, "avg_launch_ms": round(avg_ms, 4), "bytes_per_launch": int(by)}
+    return out
 
 
 def main():
@@ -181,8 +335,10 @@ def main():
 
     cfg = CONFIGS[args.config]
     torch.cuda.set_device(0)
-    mesh = inputs.hex_box(cfg["n"], perturb=cfg.get("perturb", 0.0), perturb_seed=cfg.get("perturb_seed"),
-                          permute_seed=cfg.get("permute_seed"))
+    if cfg.get("filter"):
+        print(json.dumps(run_filter_workload(cfg, args, torch, np, frmi, inputs)), flush=True)
+        return
+    mesh = build_mesh(cfg, inputs)
 
     def ic(xsol):
         s = inputs.tgv(xsol[..., 0], xsol[..., 1], xsol[..., 2], mach=cfg["mach"])
@@ -191,15 +347,25 @@ def main():
     forms = [f.strip() for f in args.forms.split(",") if f.strip()]
     runs = {f: run_form(f, cfg, mesh, ic, args, torch, np, frmi) for f in forms}
     head = runs[forms[0]]
-    E, nsp, nfp = head["E"], head["nsp"], head["nfp"]
-    dof = E * nsp
+    blocks = head["blocks"]
+    E = sum(b[0] for b in blocks.values())
+    dof = sum(b[0] * b[1] for b in blocks.values())
+    nsp = blocks["hex"][1] if "hex" in blocks else blocks["tet"][1]
+
+    def kbytes(k):
+        b = blocks.get(k.split("_", 1)[0])
+        if b is None:
+            return None
+        per = kernel_bytes_per_elem(k, b[1], b[2])
+        return None if per is None else per * b[0]
     gdofs = {f: 4 * dof / (r["ms"] * 1e-3) / 1e9 for f, r in runs.items()}
     out = {
         "metric": "RHS GDoF/s (FP32/learned vs FP64 plain) at stated L2 error; % HBM roofline",
         "value": round(gdofs[forms[0]], 4), "unit": "GDoF/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(head["ms"], 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32" if forms[0] == "fp32" else "f64", "data": "synthetic",
-        "config": {"workload": args.config, "elements": int(E), "order": cfg["order"], "points_per_elem": int(nsp),
+        "config": {"workload": args.config, "elements": int(E), "order": cfg["order"],
+                   "blocks": {k: {"elements": v[0], "points_per_elem": v[1]} for k, v in blocks.items()},
                    "dof": int(dof), "rhs_per_step": 4, "form": forms[0],
                    "rk_accumulation": "f64", "state_finite_after": bool(head["finite"]),
                    "wall_s_timed": round(head["wall"], 3)},
@@ -207,11 +373,11 @@ def main():
     }
     if not args.no_kernel_timing:
         times = head["times"]
-        fam = {k: v for k, v in times.items() if kernel_bytes_per_elem(k, nsp, nfp) is not None}
+        fam = {k: v for k, v in times.items() if kbytes(k) is not None}
         dom = max(fam, key=lambda k: fam[k][1])
         launches, tot = fam[dom]
         avg_ms = tot / launches
-        by = kernel_bytes_per_elem(dom, nsp, nfp) * E
+        by = kbytes(dom)
         achieved = by / (avg_ms * 1e-3) / 1e9
         traffic = load_traffic(dom, args.config)
         out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -221,7 +387,11 @@ def main():
             out["forms"][f]["kernels_ms_per_step"] = {k: round(v[1] / 2, 4) for k, v in sorted(runs[f]["times"].items())}
             bpd = 80 if f == "fp64" else 40
             out["forms"][f]["rhs_m0_fraction"] = round(4 * dof * bpd / (runs[f]["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not cfg.get("oracle_ok", False):
+        out["cpu_baseline"] = None
+        out["cpu_baseline_note"] = ("the FP64 oracle on this workload takes minutes and tens of GB; "
+                                    "it is timed on the default workload")
+    elif not args.no_cpu_baseline:
         base, uo, Ro = cpu_baseline(mesh, cfg, ic)
         out["cpu_baseline"] = base
         for f in forms:

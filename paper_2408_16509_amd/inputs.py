@@ -270,3 +270,34 @@ def random_state(shape, seed, rho0=1.0, p0=1.0, vel=0.5, amp=0.1, gamma=1.4):
     w = vel * rng.uniform(-1, 1, size=shape)
     p = p0 * (1.0 + amp * rng.uniform(-1, 1, size=shape))
     return prim_to_cons(rho, u, v, w, p, gamma)
+
+
+# ----------------------------------------------------------------- learned warm start
+MLP_SHAPES = ((64, 16), (64,), (64, 64), (64,), (64,), (1,))   # W1 b1 W2 b2 w3 b3, flat in this order
+
+
+def mlp_glorot(seed=43):
+    """Initial MLP parameters (flat FP32, 5,313): Glorot-uniform weights drawn from
+    PCG64(seed) in the order W1, W2, w3; zero biases."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for shape, fan in zip(MLP_SHAPES, ((16, 64), None, (64, 64), None, (64, 1), None)):
+        if fan is None:
+            parts.append(np.zeros(shape))
+        else:
+            a = math.sqrt(6.0 / (fan[0] + fan[1]))
+            parts.append(rng.uniform(-a, a, size=shape))
+    return np.concatenate([p.ravel() for p in parts]).astype(np.float32)
+
+
+def minibatch_rows(n, batch, steps, seed=44):
+    """Row ids of `steps` minibatches (flat int32): epochs of PCG64(seed) permutations,
+    a batch never straddling two epochs."""
+    rng = np.random.default_rng(seed)
+    out, perm, pos = [], rng.permutation(n), 0
+    for _ in range(steps):
+        if pos + batch > n:
+            perm, pos = rng.permutation(n), 0
+        out.append(perm[pos:pos + batch])
+        pos += batch
+    return np.concatenate(out).astype(np.int32)

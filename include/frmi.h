@@ -30,8 +30,9 @@
  *   first reference axis, Gauss--Legendre nodes increasing.  Tet solution points
  *   in the printed order of Fig. mesh(c).
  * Native layout (what fr_rhs / fr_rk_step / fr_filter operate on)
- *   Internal: per type block [sol_pt][var][E_pad] (element fastest).  Sizes come
- *   from fr_layout; do not rely on them beyond allocation.
+ *   Internal: per type block [sol_pt][var][E_pad] (element fastest), elements in
+ *   the native order (see fr_params.elem_order).  Sizes come from fr_layout; do
+ *   not rely on them beyond allocation.
  */
 #ifndef FRMI_H
 #define FRMI_H
@@ -68,7 +69,10 @@ typedef struct {
   int32_t riemann;         /* FR_RUSANOV or FR_HLLC (common flux of eq:comm_flux)    */
   int32_t precision;       /* FR_FP64, or FR_FP32: FP32 kernels on deviation
                               variables du = u - u_ref (FP64 RK accumulation)      */
-  int32_t reserved0;
+  int32_t elem_order;      /* native element order: 0 renumbers each type block along
+                              a Morton curve of the element centroids (neighbours
+                              share tiles and cache lines), 1 keeps the input order.
+                              Canonical arrays always follow the input order.       */
   double gamma;            /* ratio of specific heats                                */
   double mu;               /* constant dynamic viscosity (Navier--Stokes)           */
   double prandtl;          /* Prandtl number                                         */
@@ -152,7 +156,10 @@ fr_status fr_rhs(fr_ctx ctx, const void* u_dev, void* r_dev);
 /* n_steps classical RK4 steps of size dt on the FP64 native state u (in place).
  * filter_mode: -1 no filter; 0 plain entropy filter; 1 MLP warm-started filter.
  * The filter is applied to every stage state and to the new state, with the
- * entropy bound taken from the state at the start of the step. */
+ * entropy bound taken from the state at the start of the step.  In the FP32 form
+ * the right-hand sides run on FP32 deviations while the stage states, the
+ * accumulation and the filter (with its checks) stay FP64.  Hexahedra only for
+ * filter_mode >= 0 (FR_ERR_UNSUPPORTED with tetrahedra). */
 fr_status fr_rk_step(fr_ctx ctx, void* u_dev, double dt, int32_t n_steps, int32_t filter_mode);
 
 /* Entropy-bounded modal filter (Sec. "Numerical Stability", entropy filtering)

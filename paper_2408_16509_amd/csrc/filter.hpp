@@ -24,6 +24,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "hex.hpp"
+
 namespace frmi {
 
 struct FiltK {
@@ -220,16 +222,13 @@ __device__ void hex_load_modal(HexFiltSmem<P>& S, const double* __restrict__ u, 
   hex_to_modal<P>(X, Y, &S.U[0][0], 5, K);
 }
 
-// One 64-lane block per element: detection, search (mode 0 plain, 1 warm start
-// from khat[e]) and application of the filter.
+// One element on a 64-lane block: exact check at zeta = 0, search (mode 0 plain,
+// 1 warm start from khat[e]) and application of the filter.
 template <int P>
-__global__ void __launch_bounds__(64) hex_filter(double* __restrict__ u, const double* __restrict__ smin_a,
-                                                 int64_t E, int64_t n, FiltK K, FiltPrm F, int mode,
-                                                 const float* __restrict__ khat, int32_t* __restrict__ k_out,
-                                                 int32_t* __restrict__ evals_out) {
-  __shared__ HexFiltSmem<P> S;
-  const int64_t e = blockIdx.x;
-  if (e >= n) return;
+__device__ void hex_filter_elem(HexFiltSmem<P>& S, double* __restrict__ u, const double* __restrict__ smin_a,
+                                int64_t E, int64_t e, const FiltK& K, const FiltPrm& F, int mode,
+                                const float* __restrict__ khat, int32_t* __restrict__ k_out,
+                                int32_t* __restrict__ evals_out) {
   const int t = threadIdx.x;
   const double smin = smin_a[e];
   hex_load_modal<P>(S, u, E, e, K);
@@ -285,6 +284,124 @@ __global__ void __launch_bounds__(64) hex_filter(double* __restrict__ u, const d
   }
 }
 
+// The candidates list[0 .. *count) (from the detection), one block looping over them.
+template <int P>
+__global__ void __launch_bounds__(64) hex_filter(double* __restrict__ u, const double* __restrict__ smin_a, int64_t E,
+                                                 const int32_t* __restrict__ list, const int32_t* __restrict__ count,
+                                                 FiltK K, FiltPrm F, int mode, const float* __restrict__ khat,
+                                                 int32_t* __restrict__ k_out, int32_t* __restrict__ evals_out) {
+  __shared__ HexFiltSmem<P> S;
+  const int32_t m = *count;
+  for (int32_t i = blockIdx.x; i < m; i += gridDim.x) {
+    hex_filter_elem<P>(S, u, smin_a, E, list[i], K, F, mode, khat, k_out, evals_out);
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Detection: elements that may fail the checks at zeta = 0.  One wave per (tile of
+// 64 elements, line of solution points), as the trace kernel: the line's two end
+// values are flux-point check points, and the lines along xi_1 also check their
+// solution points.  The test is pessimistic by a relative 1e-10 in rho, E and
+// |m|^2 (far above the rounding of either evaluation), so every element the exact
+// check of the search rejects is flagged; the search re-checks and leaves false
+// positives untouched.  flag must be cleared before.
+__device__ __forceinline__ bool maybe_violates(const double w[5], double sbound, const FiltPrm& F) {
+  constexpr double dl = 1e-10;
+  const double rho = w[0];
+  const double rlo = rho - dl * fabs(rho), rhi = rho + dl * fabs(rho);
+  if (!(rlo >= F.eps_rho)) return true;
+  const double m2 = (w[1] * w[1] + w[2] * w[2] + w[3] * w[3]) * (1.0 + dl);
+  const double plo = (F.gamma - 1.0) * (w[4] - dl * fabs(w[4]) - 0.5 * m2 / rlo);
+  if (!(plo >= F.eps_p)) return true;
+  const double slo = plo * pow(rhi, -F.gamma);
+  return !(slo >= sbound + dl * fabs(sbound));
+}
+
+template <int P>
+__global__ void __launch_bounds__(256) hex_filter_detect(const double* __restrict__ u, const double* __restrict__ smin_a,
+                                                         int64_t E, int64_t n, FiltK K, FiltPrm F,
+                                                         int32_t* __restrict__ flag) {
+  constexpr int N1 = P + 1, NL = 3 * N1 * N1;
+  const int64_t gtid = xcd_block() * 256 + threadIdx.x;
+  const int64_t wave = gtid >> 6;
+  const int lane = (int)(gtid & 63);
+  const int64_t tile = wave / NL;
+  const int l = (int)(wave % NL);
+  const int64_t e = tile * 64 + lane;
+  if (e >= n) return;
+  const int d = l / (N1 * N1), q = l % (N1 * N1), t0 = q % N1, t1 = q / N1;
+  const double smin = smin_a[e];
+  const double sb = smin - F.eps_s * fabs(smin);
+  double m[5] = {0, 0, 0, 0, 0}, pl[5] = {0, 0, 0, 0, 0};
+  bool bad = false;
+#pragma unroll
+  for (int a = 0; a < N1; ++a) {
+    const int pt = line_pt<N1>(d, a, t0, t1);
+    double w[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      w[v] = u[((int64_t)pt * 5 + v) * E + e];
+      m[v] += K.lm[a] * w[v];
+      pl[v] += K.lp[a] * w[v];
+    }
+    if (d == 0) bad = bad || maybe_violates(w, sb, F);
+  }
+  bad = bad || maybe_violates(m, sb, F) || maybe_violates(pl, sb, F);
+  if (bad) flag[e] = 1;
+}
+
+__global__ void k_fill_i32(int32_t* __restrict__ a, int64_t n, int32_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    a[i] = v;
+}
+
+// Ordered compaction of the flagged elements into a list: per-256 counts, one
+// block scanning the counts (count[nb] receives the total), scatter.
+__global__ void __launch_bounds__(256) k_flag_count(const int32_t* __restrict__ flag, int64_t n,
+                                                    int32_t* __restrict__ counts) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int c = __syncthreads_count(e < n && flag[e] != 0);
+  if (threadIdx.x == 0) counts[blockIdx.x] = c;
+}
+
+__global__ void __launch_bounds__(1024) k_scan_counts(int32_t* __restrict__ counts, int nb) {
+  __shared__ int32_t part[1024];
+  const int t = threadIdx.x;
+  const int chunk = (nb + 1023) / 1024, lo = min(t * chunk, nb), hi = min(lo + chunk, nb);
+  int32_t s = 0;
+  for (int i = lo; i < hi; ++i) s += counts[i];
+  part[t] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {      // inclusive scan (Hillis--Steele)
+    const int32_t v = t >= off ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int32_t run = t > 0 ? part[t - 1] : 0;
+  for (int i = lo; i < hi; ++i) {
+    const int32_t c = counts[i];
+    counts[i] = run;
+    run += c;
+  }
+  if (t == 1023) counts[nb] = part[1023];
+}
+
+__global__ void __launch_bounds__(256) k_flag_scatter(const int32_t* __restrict__ flag, int64_t n,
+                                                      const int32_t* __restrict__ offsets, int32_t* __restrict__ list) {
+  __shared__ int32_t wsum[4];
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const bool f = e < n && flag[e] != 0;
+  const uint64_t mask = __ballot(f);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) wsum[w] = __popcll(mask);
+  __syncthreads();
+  int32_t base = offsets[blockIdx.x];
+  for (int i = 0; i < w; ++i) base += wsum[i];
+  if (f) list[base + __popcll(mask & ((1ull << lane) - 1ull))] = (int32_t)e;
+}
+
 // Block reductions over 64 lanes through LDS.
 __device__ __forceinline__ double block_min64(double v, double* red) {
   red[threadIdx.x] = v;
@@ -321,15 +438,10 @@ __device__ __forceinline__ double block_sum64(double v, double* red) {
 //   14    log10(s_mean / s_min)         15  |v_mean| / c_mean
 // (mean = element mean state; its pressure, entropy and sound speed.)
 template <int P>
-__global__ void __launch_bounds__(64) hex_features(const double* __restrict__ u, const double* __restrict__ smin_a,
-                                                   int64_t E, int64_t n, FiltK K, FiltPrm F,
-                                                   int32_t* __restrict__ flag, float* __restrict__ feat) {
+__device__ void hex_features_elem(HexFiltSmem<P>& S, double* red, double* PM, const double* __restrict__ u,
+                                  const double* __restrict__ smin_a, int64_t E, int64_t e, const FiltK& K,
+                                  const FiltPrm& F, int32_t* __restrict__ flag, float* __restrict__ feat) {
   constexpr int N1 = P + 1, NR = N1 + 2, NSP = N1 * N1 * N1, NFP = 6 * N1 * N1;
-  __shared__ HexFiltSmem<P> S;
-  __shared__ double red[64];
-  __shared__ double PM[NSP];
-  const int64_t e = blockIdx.x;
-  if (e >= n) return;
   const int t = threadIdx.x;
   const double smin = smin_a[e];
   const double g = F.gamma;
@@ -416,6 +528,23 @@ __global__ void __launch_bounds__(64) hex_features(const double* __restrict__ u,
     x[14] = (float)log10(fmax(sb / fmax(smin, 1e-300), 1e-30));
     x[15] = (float)(sqrt(vx * vx + vy * vy + vz * vz) / cb);
     flag[e] = 1;
+  }
+}
+
+// Features of the candidates list[0 .. *count), one block looping over them.
+template <int P>
+__global__ void __launch_bounds__(64) hex_features(const double* __restrict__ u, const double* __restrict__ smin_a,
+                                                   int64_t E, const int32_t* __restrict__ list,
+                                                   const int32_t* __restrict__ count, FiltK K, FiltPrm F,
+                                                   int32_t* __restrict__ flag, float* __restrict__ feat) {
+  constexpr int N1 = P + 1, NSP = N1 * N1 * N1;
+  __shared__ HexFiltSmem<P> S;
+  __shared__ double red[64];
+  __shared__ double PM[NSP];
+  const int32_t m = *count;
+  for (int32_t i = blockIdx.x; i < m; i += gridDim.x) {
+    hex_features_elem<P>(S, red, PM, u, smin_a, E, list[i], K, F, flag, feat);
+    __syncthreads();
   }
 }
 

@@ -1,6 +1,7 @@
 // C ABI of the MI355X-native FR right-hand side (declared in include/frmi.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -34,9 +35,14 @@ struct DevBlock {
   void* grad = nullptr;     // [nsp][15][E]
   void* gradf = nullptr;    // [nfp][15][E]
   void* fc = nullptr;       // [nfp][5][E] common fluxes (Navier--Stokes)
-  int64_t elem_off = 0;     // offset of the block in canonical element order
+  int64_t elem_off = 0;     // offset of the block in the element numbering (both orders)
+  int32_t* cpos = nullptr;  // native index -> canonical index within the block [E] (-1: padding)
+  int32_t* npos = nullptr;  // canonical index -> native index within the block [n]
   double* sown = nullptr;   // entropy filter: own min entropy [E]
   double* smin = nullptr;   // entropy filter: neighbourhood min entropy [E]
+  int32_t* f_det = nullptr;   // entropy filter: detection flags [n]
+  int32_t* f_list = nullptr;  // candidates of the search, native ids [n]
+  int32_t* f_cnt = nullptr;   // per-256 offsets [nb], then the candidate count
 };
 
 struct RefVec {
@@ -51,6 +57,8 @@ struct fr_ctx_s {
   Setup host;
   std::vector<DevBlock> blocks;
   int32_t* perm = nullptr;
+  int32_t* g_npos = nullptr;          // canonical -> native element index, all blocks [n_elem_total]
+  std::vector<int32_t> h_cpos;        // native -> canonical element index, all blocks (host)
   int64_t canon_len = 0, native_len = 0;
   // RK workspace: stage state and increment in the native dtype, FP64 accumulator
   void* rk_stage = nullptr;
@@ -79,6 +87,8 @@ struct fr_ctx_s {
   bool mlp_ready = false;
   // tetrahedral operators on the device (arithmetic type of the context)
   void* tet_Dh = nullptr;
+  void* tet_opT = nullptr;
+  double* rk_s64 = nullptr;   // FP64 stage state of the filtered FP32 form    // [TET_KP][TET_MP] transposed divergence operator
   void* tet_L = nullptr;
   int32_t* tet_src = nullptr;
   // training-data collection during filtered RK steps (fr_mlp_collect)
@@ -147,51 +157,65 @@ Phys phys_of(const fr_params& p) {
 }
 
 // ------------------------------------------------------------ layout kernels
-__global__ void k_pack(const double* __restrict__ canon, double* __restrict__ nat, int64_t n, int64_t E, int nsp) {
+// Canonical [elem][var][pt] (input element order) <-> native [pt][var][E] (native
+// element order, cpos / npos map between the two).
+__global__ void k_pack(const double* __restrict__ canon, double* __restrict__ nat, const int32_t* __restrict__ cpos,
+                       int64_t n, int64_t E, int nsp) {
   const int64_t total = (int64_t)nsp * 5 * E;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t e = i % E;
     const int64_t pv = i / E;
     const int v = (int)(pv % 5), pt = (int)(pv / 5);
-    nat[i] = e < n ? canon[(e * 5 + v) * nsp + pt] : (v == 0 || v == 4 ? 1.0 : 0.0);
+    nat[i] = e < n ? canon[((int64_t)cpos[e] * 5 + v) * nsp + pt] : (v == 0 || v == 4 ? 1.0 : 0.0);
   }
 }
 
-__global__ void k_unpack(const double* __restrict__ nat, double* __restrict__ canon, int64_t n, int64_t E, int nsp) {
+__global__ void k_unpack(const double* __restrict__ nat, double* __restrict__ canon, const int32_t* __restrict__ npos,
+                         int64_t n, int64_t E, int nsp) {
   const int64_t total = n * 5 * nsp;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
     const int pt = (int)(i % nsp);
     const int64_t ev = i / nsp;
     const int v = (int)(ev % 5);
     const int64_t e = ev / 5;
-    canon[i] = nat[((int64_t)pt * 5 + v) * E + e];
+    canon[i] = nat[((int64_t)pt * 5 + v) * E + npos[e]];
   }
 }
 
+// Per-element values from native to canonical element order (both global numberings).
+__global__ void k_elem_to_canon(const int32_t* __restrict__ src, const int32_t* __restrict__ npos, int64_t n,
+                                int32_t* __restrict__ dst) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[npos[i]];
+}
+
 // ------------------------------------------------------------ RK4 kernels
-// stage 1: acc = u + dt/6 k ; st = u + dt/2 k
-__global__ void k_rk_first(const double* __restrict__ u, const double* __restrict__ k, double* __restrict__ acc,
+// stage 1: acc = u + dt/6 k ; st = u + dt/2 k  (FP64 state; increments FP64 or FP32)
+template <typename KT>
+__global__ void k_rk_first(const double* __restrict__ u, const KT* __restrict__ k, double* __restrict__ acc,
                            double* __restrict__ st, int64_t n, double b, double c) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const double ui = u[i], ki = k[i];
+    const double ui = u[i], ki = (double)k[i];
     acc[i] = ui + b * ki;
     st[i] = ui + c * ki;
   }
 }
 // middle stages: acc += b k ; st = u + c k
-__global__ void k_rk_mid(const double* __restrict__ u, const double* __restrict__ k, double* __restrict__ acc,
+template <typename KT>
+__global__ void k_rk_mid(const double* __restrict__ u, const KT* __restrict__ k, double* __restrict__ acc,
                          double* __restrict__ st, int64_t n, double b, double c) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const double ki = k[i];
+    const double ki = (double)k[i];
     acc[i] += b * ki;
     st[i] = u[i] + c * ki;
   }
 }
 // last: u = acc + b k
-__global__ void k_rk_last(double* __restrict__ u, const double* __restrict__ k, const double* __restrict__ acc,
+template <typename KT>
+__global__ void k_rk_last(double* __restrict__ u, const KT* __restrict__ k, const double* __restrict__ acc,
                           int64_t n, double b) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    u[i] = acc[i] + b * k[i];
+    u[i] = acc[i] + b * (double)k[i];
 }
 
 // ------------------------------------------------------------ check kernel
@@ -225,25 +249,25 @@ __global__ void k_to_dev(const double* __restrict__ u, float* __restrict__ w, in
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     w[i] = (float)(u[i] - ref.v[(i / E) % 5]);
 }
-__global__ void k_pack32(const double* __restrict__ canon, float* __restrict__ nat, int64_t n, int64_t E, int nsp,
-                         RefVec ref) {
+__global__ void k_pack32(const double* __restrict__ canon, float* __restrict__ nat, const int32_t* __restrict__ cpos,
+                         int64_t n, int64_t E, int nsp, RefVec ref) {
   const int64_t total = (int64_t)nsp * 5 * E;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t e = i % E;
     const int64_t pv = i / E;
     const int v = (int)(pv % 5), pt = (int)(pv / 5);
-    nat[i] = e < n ? (float)(canon[(e * 5 + v) * nsp + pt] - ref.v[v]) : 0.0f;
+    nat[i] = e < n ? (float)(canon[((int64_t)cpos[e] * 5 + v) * nsp + pt] - ref.v[v]) : 0.0f;
   }
 }
-__global__ void k_unpack32(const float* __restrict__ nat, double* __restrict__ canon, int64_t n, int64_t E, int nsp,
-                           RefVec ref, int add_ref) {
+__global__ void k_unpack32(const float* __restrict__ nat, double* __restrict__ canon, const int32_t* __restrict__ npos,
+                           int64_t n, int64_t E, int nsp, RefVec ref, int add_ref) {
   const int64_t total = n * 5 * nsp;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
     const int pt = (int)(i % nsp);
     const int64_t ev = i / nsp;
     const int v = (int)(ev % 5);
     const int64_t e = ev / 5;
-    canon[i] = (double)nat[((int64_t)pt * 5 + v) * E + e] + (add_ref ? ref.v[v] : 0.0);
+    canon[i] = (double)nat[((int64_t)pt * 5 + v) * E + npos[e]] + (add_ref ? ref.v[v] : 0.0);
   }
 }
 // RK stages of the FP32 form: FP64 state and accumulator, FP32 increments and stage deviations.
@@ -364,19 +388,35 @@ fr_status tet_rhs(fr_ctx c, DevBlock& b, const T* u, T* r) {
   const T* geo = (const T*)b.geo_t;
   const unsigned nblk = (unsigned)(b.E / NE);
   static const std::string sfx = sizeof(T) == 8 ? "" : "_f32";
+  const int sm = side_mode_of(p.ldg_beta);
+  const int64_t face_threads = b.E * TET_NFP;
+  const unsigned face_grid = (unsigned)((face_threads + 255) / 256);
+  // persistent divergence grid: a few resident blocks per CU, each over a tile range
+  const unsigned div_grid = (unsigned)std::min<int64_t>(b.E / TDIV_NE, sizeof(T) == 8 ? 256 : 512);
+  const T* opT = (const T*)c->tet_opT;
+  T* fc = (T*)b.fc;
   int pk;
   if (p.system == FR_EULER) {
+    pk = c->prof_begin(("tet_face_euler" + sfx).c_str());
+    tet_face<T, DEV, false><<<face_grid, 256, 0, c->stream>>>(u, nullptr, geo, C, O, fc, b.E, (T)p.gamma, (T)0, (T)0,
+                                                              (T)0, (T)0, p.riemann, 0, R);
+    c->prof_end(pk);
     pk = c->prof_begin(("tet_div_euler" + sfx).c_str());
-    tet_div_euler<T, DEV, NE, NG><<<nblk, NE * NG, 0, c->stream>>>(u, geo, C, O, r, b.E, b.n, (T)p.gamma, p.riemann, R);
+    tet_div<T, DEV, false><<<div_grid, TDIV_NT, 0, c->stream>>>(u, nullptr, fc, geo, opT, r, b.E, b.n, (T)p.gamma,
+                                                                (T)0, (T)0, R);
     c->prof_end(pk);
   } else {
     pk = c->prof_begin(("tet_grad" + sfx).c_str());
     tet_grad<T, NE, NG><<<nblk, NE * NG, 0, c->stream>>>(u, geo, C, O, (T*)b.grad, b.E, (T)p.ldg_beta);
     c->prof_end(pk);
+    pk = c->prof_begin(("tet_face_ns" + sfx).c_str());
+    tet_face<T, DEV, true><<<face_grid, 256, 0, c->stream>>>(u, (const T*)b.grad, geo, C, O, fc, b.E, (T)p.gamma,
+                                                             (T)p.mu, (T)p.prandtl, (T)p.ldg_beta, (T)p.ldg_tau,
+                                                             p.riemann, sm, R);
+    c->prof_end(pk);
     pk = c->prof_begin(("tet_div_ns" + sfx).c_str());
-    tet_div_ns<T, DEV, NE, NG><<<nblk, NE * NG, 0, c->stream>>>(u, (const T*)b.grad, geo, C, O, r, b.E, b.n,
-                                                               (T)p.gamma, (T)p.mu, (T)p.prandtl, (T)p.ldg_beta,
-                                                               (T)p.ldg_tau, p.riemann, R);
+    tet_div<T, DEV, true><<<div_grid, TDIV_NT, 0, c->stream>>>(u, (const T*)b.grad, fc, geo, opT, r, b.E, b.n,
+                                                               (T)p.gamma, (T)p.mu, (T)p.prandtl, R);
     c->prof_end(pk);
   }
   hipError_t e = hipGetLastError();
@@ -451,7 +491,9 @@ fr_status filter_alloc(fr_ctx c) {
   if (c->f_k) return FR_OK;
   const int64_t n = c->n_elem_total;
   for (auto& b : c->blocks)
-    if (dalloc(c, &b.sown, b.E) || dalloc(c, &b.smin, b.E)) return FR_ERR_ALLOC;
+    if (dalloc(c, &b.sown, b.E) || dalloc(c, &b.smin, b.E) || dalloc(c, &b.f_det, b.n) ||
+        dalloc(c, &b.f_list, b.n) || dalloc(c, &b.f_cnt, (b.n + 255) / 256 + 1))
+      return FR_ERR_ALLOC;
   if (dalloc(c, &c->f_k, n) || dalloc(c, &c->f_evals, n) || dalloc(c, &c->f_flag, n) ||
       dalloc(c, &c->f_feat, n * 16) || dalloc(c, &c->f_khat, n))
     return FR_ERR_ALLOC;
@@ -468,22 +510,60 @@ void hex_smin_p(fr_ctx c, DevBlock& b, const double* uprev) {
   c->prof_end(pk);
 }
 
+// Candidates of the search: detection at zeta = 0 and ordered compaction into
+// b.f_list / count b.f_cnt[nb]; untouched elements get k = 0 and one evaluation.
+template <int P>
+void hex_candidates_p(fr_ctx c, DevBlock& b, const double* u) {
+  constexpr int N1 = P + 1;
+  const FiltK K = filtk_of(c->host.hex);
+  const FiltPrm F = filtprm_of(c->prm, P);
+  const int64_t o = b.elem_off;
+  const int nb = (int)((b.n + 255) / 256);
+  const int gf = grid_for(b.n, 256);
+  int pk = c->prof_begin("filter_detect");
+  k_fill_i32<<<gf, 256, 0, c->stream>>>(b.f_det, b.n, 0);
+  k_fill_i32<<<gf, 256, 0, c->stream>>>(c->f_k + o, b.n, 0);
+  k_fill_i32<<<gf, 256, 0, c->stream>>>(c->f_evals + o, b.n, 1);
+  const int64_t threads = b.E * 3 * N1 * N1;
+  hex_filter_detect<P><<<(unsigned)((threads + 255) / 256), 256, 0, c->stream>>>(u + b.native_off, b.smin, b.E, b.n,
+                                                                                  K, F, b.f_det);
+  k_flag_count<<<nb, 256, 0, c->stream>>>(b.f_det, b.n, b.f_cnt);
+  k_scan_counts<<<1, 1024, 0, c->stream>>>(b.f_cnt, nb);
+  k_flag_scatter<<<nb, 256, 0, c->stream>>>(b.f_det, b.n, b.f_cnt, b.f_list);
+  c->prof_end(pk);
+}
+
+inline unsigned list_grid(const DevBlock& b) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b.n, 2048)); }
+
+// Features (and the exact troubled flag) of the candidates of b.
+template <int P>
+void hex_features_p(fr_ctx c, DevBlock& b, const double* u) {
+  const FiltK K = filtk_of(c->host.hex);
+  const FiltPrm F = filtprm_of(c->prm, P);
+  const int64_t o = b.elem_off;
+  const int nb = (int)((b.n + 255) / 256);
+  k_fill_i32<<<grid_for(b.n, 256), 256, 0, c->stream>>>(c->f_flag + o, b.n, 0);
+  hex_features<P><<<list_grid(b), 64, 0, c->stream>>>(u + b.native_off, b.smin, b.E, b.f_list, b.f_cnt + nb, K, F,
+                                                       c->f_flag + o, c->f_feat + o * 16);
+}
+
 template <int P>
 void hex_filter_p(fr_ctx c, DevBlock& b, double* u, int mode) {
   const FiltK K = filtk_of(c->host.hex);
   const FiltPrm F = filtprm_of(c->prm, P);
   const int64_t o = b.elem_off;
+  const int nb = (int)((b.n + 255) / 256);
+  hex_candidates_p<P>(c, b, u);
   int pk;
   if (mode == 1) {
     pk = c->prof_begin("filter_features_mlp");
-    hex_features<P><<<(unsigned)b.n, 64, 0, c->stream>>>(u + b.native_off, b.smin, b.E, b.n, K, F, c->f_flag + o,
-                                                         c->f_feat + o * 16);
-    mlp_forward<<<(unsigned)((b.n + 255) / 256), 256, 0, c->stream>>>(c->m_w, c->m_scale, c->f_feat + o * 16,
-                                                                      c->f_flag + o, b.n, F.n_bits, c->f_khat + o);
+    hex_features_p<P>(c, b, u);
+    mlp_forward_list<<<(unsigned)std::min<int64_t>((b.n + 255) / 256, 256), 256, 0, c->stream>>>(
+        c->m_w, c->m_scale, c->f_feat + o * 16, c->f_flag + o, b.f_list, b.f_cnt + nb, F.n_bits, c->f_khat + o);
     c->prof_end(pk);
   }
   pk = c->prof_begin(mode == 1 ? "filter_search_warm" : "filter_search_plain");
-  hex_filter<P><<<(unsigned)b.n, 64, 0, c->stream>>>(u + b.native_off, b.smin, b.E, b.n, K, F, mode,
+  hex_filter<P><<<list_grid(b), 64, 0, c->stream>>>(u + b.native_off, b.smin, b.E, b.f_list, b.f_cnt + nb, K, F, mode,
                                                      c->f_khat + o, c->f_k + o, c->f_evals + o);
   c->prof_end(pk);
 }
@@ -522,18 +602,6 @@ fr_status apply_filter(fr_ctx c, double* u, int mode) {
   return FR_OK;
 }
 
-template <int P>
-void hex_features_p(fr_ctx c, DevBlock& b, const double* u) {
-  const FiltK K = filtk_of(c->host.hex);
-  const FiltPrm F = filtprm_of(c->prm, P);
-  const int64_t o = b.elem_off;
-  hex_features<P><<<(unsigned)b.n, 64, 0, c->stream>>>(u + b.native_off, b.smin, b.E, b.n, K, F, c->f_flag + o,
-                                                       c->f_feat + o * 16);
-}
-
-template <int P>
-void hex_features_p(fr_ctx c, DevBlock& b, const double* u);
-
 __global__ void k_gather_features(const float* __restrict__ feat, const int32_t* __restrict__ kk,
                                   const int32_t* __restrict__ idx, int64_t n, float* __restrict__ x,
                                   int32_t* __restrict__ elem, int32_t* __restrict__ kout) {
@@ -547,15 +615,28 @@ __global__ void k_gather_features(const float* __restrict__ feat, const int32_t*
 
 // Features and plain-search targets of the troubled elements of u (entropy bound
 // from the current s_min), appended to the collection buffers.
-fr_status collect_rows(fr_ctx c, const double* u) {
+template <int P>
+void hex_candidate_features_p(fr_ctx c, DevBlock& b, const double* u) {
+  hex_candidates_p<P>(c, b, u);
+  hex_features_p<P>(c, b, u);
+}
+
+fr_status candidate_features(fr_ctx c, const double* u) {
   for (auto& b : c->blocks) {
     switch (c->prm.order) {
-      case 1: hex_features_p<1>(c, b, u); break;
-      case 2: hex_features_p<2>(c, b, u); break;
-      case 3: hex_features_p<3>(c, b, u); break;
-      case 4: hex_features_p<4>(c, b, u); break;
+      case 1: hex_candidate_features_p<1>(c, b, u); break;
+      case 2: hex_candidate_features_p<2>(c, b, u); break;
+      case 3: hex_candidate_features_p<3>(c, b, u); break;
+      case 4: hex_candidate_features_p<4>(c, b, u); break;
     }
   }
+  HIP_TRY(c, hipGetLastError());
+  return FR_OK;
+}
+
+fr_status collect_rows(fr_ctx c, const double* u) {
+  fr_status cs = candidate_features(c, u);
+  if (cs) return cs;
   HIP_TRY(c, hipMemcpyAsync(c->f_copy, u, c->native_len * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   c->collecting = false;
   fr_status st = apply_filter(c, c->f_copy, 0);
@@ -633,12 +714,17 @@ void fr_destroy(fr_ctx c) {
     if (b.geo_t && b.geo_t != b.geo) (void)hipFree(b.geo_t);
     (void)hipFree(b.geo); (void)hipFree(b.nbr_elem); (void)hipFree(b.nbr_info);
     (void)hipFree(b.uf); (void)hipFree(b.grad); (void)hipFree(b.gradf); (void)hipFree(b.fc);
+    (void)hipFree(b.cpos); (void)hipFree(b.npos);
   }
   (void)hipFree(c->perm);
-  (void)hipFree(c->rk_stage); (void)hipFree(c->rk_acc); (void)hipFree(c->rk_k);
+  (void)hipFree(c->g_npos);
+  (void)hipFree(c->rk_stage); (void)hipFree(c->rk_acc); (void)hipFree(c->rk_k); (void)hipFree(c->rk_s64);
   (void)hipFree(c->flag);
-  (void)hipFree(c->tet_Dh); (void)hipFree(c->tet_L); (void)hipFree(c->tet_src);
-  for (auto& b : c->blocks) { (void)hipFree(b.sown); (void)hipFree(b.smin); }
+  (void)hipFree(c->tet_Dh); (void)hipFree(c->tet_L); (void)hipFree(c->tet_src); (void)hipFree(c->tet_opT);
+  for (auto& b : c->blocks) {
+    (void)hipFree(b.sown); (void)hipFree(b.smin);
+    (void)hipFree(b.f_det); (void)hipFree(b.f_list); (void)hipFree(b.f_cnt);
+  }
   for (void* q : {(void*)c->f_k, (void*)c->f_evals, (void*)c->f_flag, (void*)c->f_feat, (void*)c->f_khat,
                   (void*)c->f_copy, (void*)c->m_w, (void*)c->m_m, (void*)c->m_v, (void*)c->m_g, (void*)c->m_scale,
                   (void*)c->m_loss, (void*)c->m_scratch, (void*)c->m_sqerr, (void*)c->m_idx})
@@ -662,6 +748,7 @@ fr_status fr_setup_mesh(const fr_params* p, int64_t n_vert, const double* xyz, c
     return fail(nullptr, FR_ERR_ARG, "the FP32 form needs a reference state at rest with rho > 0, E > 0");
   if (!(p->gamma > 1.0)) return fail(nullptr, FR_ERR_ARG, "gamma must exceed 1");
   if (p->filt_bits < 1 || p->filt_bits > 30) return fail(nullptr, FR_ERR_ARG, "filt_bits must be in 1..30");
+  if (p->elem_order != 0 && p->elem_order != 1) return fail(nullptr, FR_ERR_ARG, "elem_order must be 0 or 1");
   fr_ctx c = new (std::nothrow) fr_ctx_s();
   if (!c) return fail(nullptr, FR_ERR_ALLOC, "context allocation");
   c->prm = *p;
@@ -669,7 +756,7 @@ fr_status fr_setup_mesh(const fr_params* p, int64_t n_vert, const double* xyz, c
   int code = 0;
   std::string msg;
   try {
-    msg = build_setup(p->order, n_vert, xyz, period, n_elem, etype, enodes, 64, c->host, code);
+    msg = build_setup(p->order, n_vert, xyz, period, n_elem, etype, enodes, 64, p->elem_order, c->host, code);
   } catch (const std::exception& ex) {
     msg = ex.what();
     code = 3;
@@ -692,13 +779,25 @@ fr_status fr_setup_mesh(const fr_params* p, int64_t n_vert, const double* xyz, c
     native += b.E * 5 * b.nsp;
     c->blocks.push_back(b);
     DevBlock& d = c->blocks.back();
+    {
+      std::vector<int32_t> cp((size_t)d.E, -1), np_((size_t)d.n);
+      for (int64_t i = 0; i < d.n; ++i) { cp[i] = hb.canon_pos[i]; np_[hb.canon_pos[i]] = (int32_t)i; }
+      if (dalloc(c, &d.cpos, cp.size()) || dalloc(c, &d.npos, np_.size())) return bail(FR_ERR_ALLOC);
+      if (hipMemcpy(d.cpos, cp.data(), cp.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+          hipMemcpy(d.npos, np_.data(), np_.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
+        c->err = "upload failed";
+        return bail(FR_ERR_DEVICE);
+      }
+    }
     if (dalloc(c, &d.geo, hb.geo.size()) || dalloc(c, &d.nbr_elem, hb.nbr_elem.size()) ||
         dalloc(c, &d.nbr_info, hb.nbr_info.size()) || dalloc(c, (char**)&d.uf, (size_t)d.nfp * 5 * d.E * tsz))
       return bail(FR_ERR_ALLOC);
+    const bool is_tet = d.etype == FR_TET;
     if (p->system == FR_NAVIER_STOKES &&
         (dalloc(c, (char**)&d.grad, (size_t)d.nsp * 15 * d.E * tsz) ||
-         dalloc(c, (char**)&d.gradf, (size_t)d.nfp * 15 * d.E * tsz) ||
-         dalloc(c, (char**)&d.fc, (size_t)d.nfp * 5 * d.E * tsz)))
+         (!is_tet && dalloc(c, (char**)&d.gradf, (size_t)d.nfp * 15 * d.E * tsz))))
+      return bail(FR_ERR_ALLOC);
+    if ((p->system == FR_NAVIER_STOKES || is_tet) && dalloc(c, (char**)&d.fc, (size_t)d.nfp * 5 * d.E * tsz))
       return bail(FR_ERR_ALLOC);
     d.geo_t = d.geo;
     if (tsz == sizeof(float)) {
@@ -718,6 +817,23 @@ fr_status fr_setup_mesh(const fr_params* p, int64_t n_vert, const double* xyz, c
   }
   c->canon_len = canon;
   c->native_len = native;
+  {
+    std::vector<int32_t> gn((size_t)c->n_elem_total);
+    c->h_cpos.assign((size_t)c->n_elem_total, 0);
+    for (size_t bi = 0; bi < c->blocks.size(); ++bi) {
+      const Block& hb = c->host.blocks[bi];
+      const int64_t o = c->blocks[bi].elem_off;
+      for (int64_t i = 0; i < hb.n; ++i) {
+        c->h_cpos[o + i] = (int32_t)(o + hb.canon_pos[i]);
+        gn[o + hb.canon_pos[i]] = (int32_t)(o + i);
+      }
+    }
+    if (dalloc(c, &c->g_npos, gn.size())) return bail(FR_ERR_ALLOC);
+    if (hipMemcpy(c->g_npos, gn.data(), gn.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
+      c->err = "upload failed";
+      return bail(FR_ERR_DEVICE);
+    }
+  }
   if (dalloc(c, &c->perm, c->host.orient_perm.size()) || dalloc(c, &c->flag, 1)) return bail(FR_ERR_ALLOC);
   if (hipMemcpy(c->perm, c->host.orient_perm.data(), c->host.orient_perm.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
     c->err = "upload failed";
@@ -729,6 +845,20 @@ fr_status fr_setup_mesh(const fr_params* p, int64_t n_vert, const double* xyz, c
     const TetOps& T = c->host.tet;
     std::vector<double> dh(&T.Dh[0][0][0], &T.Dh[0][0][0] + 3 * 35 * 35), L(&T.lift[0][0], &T.lift[0][0] + 35 * 60);
     std::vector<int32_t> src(T.fp_src, T.fp_src + 60);
+    // transposed, zero-padded divergence operator [Dh_0 Dh_1 Dh_2 L] of the matrix-core contraction
+    std::vector<double> opT((size_t)TET_KP * TET_MP, 0.0);
+    for (int k = 0; k < 105; ++k)
+      for (int pt = 0; pt < 35; ++pt) opT[(size_t)k * TET_MP + pt] = T.Dh[k / 35][pt][k % 35];
+    for (int sg = 0; sg < 60; ++sg)
+      for (int pt = 0; pt < 35; ++pt) opT[(size_t)(TET_KA + sg) * TET_MP + pt] = T.lift[pt][sg];
+    std::vector<char> bop(opT.size() * tsz);
+    if (tsz == sizeof(float)) for (size_t i = 0; i < opT.size(); ++i) ((float*)bop.data())[i] = (float)opT[i];
+    else std::memcpy(bop.data(), opT.data(), bop.size());
+    if (dalloc(c, (char**)&c->tet_opT, bop.size()) ||
+        hipMemcpy(c->tet_opT, bop.data(), bop.size(), hipMemcpyHostToDevice) != hipSuccess) {
+      c->err = "tet operator upload failed";
+      return bail(FR_ERR_DEVICE);
+    }
     const size_t bytes_dh = dh.size() * tsz, bytes_l = L.size() * tsz;
     std::vector<char> bdh(bytes_dh), bl(bytes_l);
     if (tsz == sizeof(float)) {
@@ -779,7 +909,8 @@ fr_status fr_sol_points(fr_ctx c, double* xyz) {
 static fr_status pack64(fr_ctx c, const double* canon, double* native) {
   for (auto& b : c->blocks) {
     const int64_t tot = (int64_t)b.nsp * 5 * b.E;
-    k_pack<<<grid_for(tot, 256), 256, 0, c->stream>>>(canon + b.canon_off, native + b.native_off, b.n, b.E, b.nsp);
+    k_pack<<<grid_for(tot, 256), 256, 0, c->stream>>>(canon + b.canon_off, native + b.native_off, b.cpos, b.n, b.E,
+                                                      b.nsp);
   }
   HIP_TRY(c, hipGetLastError());
   return FR_OK;
@@ -788,7 +919,8 @@ static fr_status pack64(fr_ctx c, const double* canon, double* native) {
 static fr_status unpack64(fr_ctx c, const double* native, double* canon) {
   for (auto& b : c->blocks) {
     const int64_t tot = b.n * 5 * b.nsp;
-    k_unpack<<<grid_for(tot, 256), 256, 0, c->stream>>>(native + b.native_off, canon + b.canon_off, b.n, b.E, b.nsp);
+    k_unpack<<<grid_for(tot, 256), 256, 0, c->stream>>>(native + b.native_off, canon + b.canon_off, b.npos, b.n, b.E,
+                                                        b.nsp);
   }
   HIP_TRY(c, hipGetLastError());
   return FR_OK;
@@ -800,8 +932,8 @@ fr_status fr_pack(fr_ctx c, const double* canon, void* native) {
   const RefVec ref = refvec(c->prm);
   for (auto& b : c->blocks) {
     const int64_t tot = (int64_t)b.nsp * 5 * b.E;
-    k_pack32<<<grid_for(tot, 256), 256, 0, c->stream>>>(canon + b.canon_off, (float*)native + b.native_off, b.n, b.E,
-                                                        b.nsp, ref);
+    k_pack32<<<grid_for(tot, 256), 256, 0, c->stream>>>(canon + b.canon_off, (float*)native + b.native_off, b.cpos,
+                                                        b.n, b.E, b.nsp, ref);
   }
   HIP_TRY(c, hipGetLastError());
   return FR_OK;
@@ -814,7 +946,7 @@ fr_status fr_unpack(fr_ctx c, const void* native, double* canon) {
   for (auto& b : c->blocks) {
     const int64_t tot = b.n * 5 * b.nsp;
     k_unpack32<<<grid_for(tot, 256), 256, 0, c->stream>>>((const float*)native + b.native_off, canon + b.canon_off,
-                                                          b.n, b.E, b.nsp, ref, 1);
+                                                          b.npos, b.n, b.E, b.nsp, ref, 1);
   }
   HIP_TRY(c, hipGetLastError());
   return FR_OK;
@@ -826,8 +958,8 @@ fr_status fr_unpack_rhs(fr_ctx c, const void* r, double* canon) {
   const RefVec ref = refvec(c->prm);
   for (auto& b : c->blocks) {
     const int64_t tot = b.n * 5 * b.nsp;
-    k_unpack32<<<grid_for(tot, 256), 256, 0, c->stream>>>((const float*)r + b.native_off, canon + b.canon_off, b.n,
-                                                          b.E, b.nsp, ref, 0);
+    k_unpack32<<<grid_for(tot, 256), 256, 0, c->stream>>>((const float*)r + b.native_off, canon + b.canon_off,
+                                                          b.npos, b.n, b.E, b.nsp, ref, 0);
   }
   HIP_TRY(c, hipGetLastError());
   return FR_OK;
@@ -853,8 +985,6 @@ fr_status fr_rk_step(fr_ctx c, void* u_, double dt, int32_t n_steps, int32_t fil
   if (!c || !u_) return fail(c, FR_ERR_ARG, "NULL argument");
   if (n_steps < 0 || !std::isfinite(dt)) return fail(c, FR_ERR_ARG, "n_steps or dt");
   if (filter_mode < -1 || filter_mode > 1) return fail(c, FR_ERR_ARG, "filter_mode must be -1, 0 or 1");
-  if (filter_mode >= 0 && c->prm.precision != FR_FP64)
-    return fail(c, FR_ERR_UNSUPPORTED, "the entropy filter runs on the FP64 form");
   if (filter_mode == 1 && !c->mlp_ready) return fail(c, FR_ERR_STATE, "MLP weights not set");
   if (filter_mode >= 0) {
     fr_status fs = filter_alloc(c);
@@ -884,49 +1014,75 @@ fr_status fr_rk_step(fr_ctx c, void* u_, double dt, int32_t n_steps, int32_t fil
       if (filt && (st = compute_smin(c, u))) return st;
       if ((st = rhs_native(c, u, K))) return st;
       pk = c->prof_begin("rk4_update");
-      k_rk_first<<<g, 256, 0, c->stream>>>(u, K, c->rk_acc, S, n, b1, c2);
+      k_rk_first<double><<<g, 256, 0, c->stream>>>(u, K, c->rk_acc, S, n, b1, c2);
       c->prof_end(pk);
       if (filt && (st = apply_filter(c, S, filter_mode))) return st;
       if ((st = rhs_native(c, S, K))) return st;
       pk = c->prof_begin("rk4_update");
-      k_rk_mid<<<g, 256, 0, c->stream>>>(u, K, c->rk_acc, S, n, b2, c2);
+      k_rk_mid<double><<<g, 256, 0, c->stream>>>(u, K, c->rk_acc, S, n, b2, c2);
       c->prof_end(pk);
       if (filt && (st = apply_filter(c, S, filter_mode))) return st;
       if ((st = rhs_native(c, S, K))) return st;
       pk = c->prof_begin("rk4_update");
-      k_rk_mid<<<g, 256, 0, c->stream>>>(u, K, c->rk_acc, S, n, b2, dt);
+      k_rk_mid<double><<<g, 256, 0, c->stream>>>(u, K, c->rk_acc, S, n, b2, dt);
       c->prof_end(pk);
       if (filt && (st = apply_filter(c, S, filter_mode))) return st;
       if ((st = rhs_native(c, S, K))) return st;
       pk = c->prof_begin("rk4_update");
-      k_rk_last<<<g, 256, 0, c->stream>>>(u, K, c->rk_acc, n, b1);
+      k_rk_last<double><<<g, 256, 0, c->stream>>>(u, K, c->rk_acc, n, b1);
       c->prof_end(pk);
       if (filt && (st = apply_filter(c, u, filter_mode))) return st;
     }
   } else {
     float *K = (float*)c->rk_k, *S = (float*)c->rk_stage;
     const RefVec ref = refvec(c->prm);
+    auto to_dev = [&](const double* src) {
+      for (auto& b : c->blocks) {
+        const int64_t nb = (int64_t)b.nsp * 5 * b.E;
+        k_to_dev<<<grid_for(nb, 256), 256, 0, c->stream>>>(src + b.native_off, S + b.native_off, nb, b.E, ref);
+      }
+    };
     // the FP32 deviation of u_n; later steps get it from the previous step's last update
-    for (auto& b : c->blocks) {
-      const int64_t nb = (int64_t)b.nsp * 5 * b.E;
-      k_to_dev<<<grid_for(nb, 256), 256, 0, c->stream>>>(u + b.native_off, S + b.native_off, nb, b.E, ref);
-    }
-    for (int s = 0; s < n_steps; ++s) {
-      for (int stage = 0; stage < 4; ++stage) {
-        if ((st = rhs_native(c, S, K))) return st;
-        pk = c->prof_begin("rk4_update_f32");
-        for (auto& b : c->blocks) {
-          const int64_t nb = (int64_t)b.nsp * 5 * b.E, o = b.native_off;
-          const int gb = grid_for(nb, 256);
-          if (stage == 0)
-            k_rk32_first<<<gb, 256, 0, c->stream>>>(u + o, K + o, c->rk_acc + o, S + o, nb, b.E, b1, c2, ref);
-          else if (stage < 3)
-            k_rk32_mid<<<gb, 256, 0, c->stream>>>(u + o, K + o, c->rk_acc + o, S + o, nb, b.E, b2,
-                                                  stage == 1 ? c2 : dt, ref);
-          else
-            k_rk32_last<<<gb, 256, 0, c->stream>>>(u + o, K + o, c->rk_acc + o, S + o, nb, b.E, b1, ref);
+    to_dev(u);
+    if (filter_mode >= 0) {
+      // filtered: every stage state is formed in FP64, filtered with FP64 checks, then
+      // rounded to the FP32 deviation the kernels read
+      if (!c->rk_s64 && dalloc(c, &c->rk_s64, n)) return FR_ERR_ALLOC;
+      double* S64 = c->rk_s64;
+      for (int s = 0; s < n_steps; ++s) {
+        if ((st = compute_smin(c, u))) return st;
+        for (int stage = 0; stage < 4; ++stage) {
+          if ((st = rhs_native(c, S, K))) return st;
+          pk = c->prof_begin("rk4_update_f32");
+          if (stage == 0) k_rk_first<float><<<g, 256, 0, c->stream>>>(u, K, c->rk_acc, S64, n, b1, c2);
+          else if (stage < 3) k_rk_mid<float><<<g, 256, 0, c->stream>>>(u, K, c->rk_acc, S64, n, b2, stage == 1 ? c2 : dt);
+          else k_rk_last<float><<<g, 256, 0, c->stream>>>(u, K, c->rk_acc, n, b1);
+          c->prof_end(pk);
+          double* tgt = stage < 3 ? S64 : u;
+          if ((st = apply_filter(c, tgt, filter_mode))) return st;
+          pk = c->prof_begin("rk4_update_f32");
+          to_dev(tgt);
+          c->prof_end(pk);
         }
-        c->prof_end(pk);
+      }
+    } else {
+      for (int s = 0; s < n_steps; ++s) {
+        for (int stage = 0; stage < 4; ++stage) {
+          if ((st = rhs_native(c, S, K))) return st;
+          pk = c->prof_begin("rk4_update_f32");
+          for (auto& b : c->blocks) {
+            const int64_t nb = (int64_t)b.nsp * 5 * b.E, o = b.native_off;
+            const int gb = grid_for(nb, 256);
+            if (stage == 0)
+              k_rk32_first<<<gb, 256, 0, c->stream>>>(u + o, K + o, c->rk_acc + o, S + o, nb, b.E, b1, c2, ref);
+            else if (stage < 3)
+              k_rk32_mid<<<gb, 256, 0, c->stream>>>(u + o, K + o, c->rk_acc + o, S + o, nb, b.E, b2,
+                                                    stage == 1 ? c2 : dt, ref);
+            else
+              k_rk32_last<<<gb, 256, 0, c->stream>>>(u + o, K + o, c->rk_acc + o, S + o, nb, b.E, b1, ref);
+          }
+          c->prof_end(pk);
+        }
       }
     }
   }
@@ -994,7 +1150,8 @@ fr_status fr_filter(fr_ctx c, void* u_, const void* uprev_, int32_t mode, int32_
   }
   if ((st = compute_smin(c, (const double*)uprev_))) return st;
   if ((st = apply_filter(c, (double*)u_, mode))) return st;
-  if (k_dev) HIP_TRY(c, hipMemcpyAsync(k_dev, c->f_k, c->n_elem_total * 4, hipMemcpyDeviceToDevice, c->stream));
+  if (k_dev)
+    k_elem_to_canon<<<grid_for(c->n_elem_total, 256), 256, 0, c->stream>>>(c->f_k, c->g_npos, c->n_elem_total, k_dev);
   if (stats) {
     HIP_TRY(c, hipEventRecord(e1, c->stream));
     std::vector<int32_t> k(c->n_elem_total), ev(c->n_elem_total);
@@ -1045,29 +1202,28 @@ fr_status fr_mlp_features(fr_ctx c, const void* u_, const void* uprev_, float* x
   if ((st = filter_alloc(c))) return st;
   if (!c->f_copy && dalloc(c, &c->f_copy, c->native_len)) return FR_ERR_ALLOC;
   if ((st = compute_smin(c, (const double*)uprev_))) return st;
-  for (auto& b : c->blocks) {
-    switch (c->prm.order) {
-      case 1: hex_features_p<1>(c, b, (const double*)u_); break;
-      case 2: hex_features_p<2>(c, b, (const double*)u_); break;
-      case 3: hex_features_p<3>(c, b, (const double*)u_); break;
-      case 4: hex_features_p<4>(c, b, (const double*)u_); break;
-    }
-  }
+  if ((st = candidate_features(c, (const double*)u_))) return st;
   // training targets: the plain search on a copy of the state
   HIP_TRY(c, hipMemcpyAsync(c->f_copy, u_, c->native_len * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   if ((st = apply_filter(c, c->f_copy, 0))) return st;
   std::vector<int32_t> flag(c->n_elem_total);
   HIP_TRY(c, hipMemcpyAsync(flag.data(), c->f_flag, flag.size() * 4, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  std::vector<int32_t> idx;
-  for (size_t i = 0; i < flag.size(); ++i) if (flag[i]) idx.push_back((int32_t)i);
+  // rows in canonical element order
+  std::vector<std::pair<int32_t, int32_t>> sel;
+  for (size_t i = 0; i < flag.size(); ++i) if (flag[i]) sel.push_back({c->h_cpos[i], (int32_t)i});
+  std::sort(sel.begin(), sel.end());
+  std::vector<int32_t> idx(sel.size()), cid(sel.size());
+  for (size_t i = 0; i < sel.size(); ++i) { cid[i] = sel[i].first; idx[i] = sel[i].second; }
   *n = (int64_t)idx.size();
   const int64_t m = std::min<int64_t>(cap, *n);
   if (m > 0) {
     int32_t* didx = nullptr;
     if (dalloc(c, &didx, m)) return FR_ERR_ALLOC;
     HIP_TRY(c, hipMemcpyAsync(didx, idx.data(), m * 4, hipMemcpyHostToDevice, c->stream));
-    k_gather_features<<<(unsigned)((m + 255) / 256), 256, 0, c->stream>>>(c->f_feat, c->f_k, didx, m, x, elem, kout);
+    k_gather_features<<<(unsigned)((m + 255) / 256), 256, 0, c->stream>>>(c->f_feat, c->f_k, didx, m, x, nullptr,
+                                                                          kout);
+    if (elem) HIP_TRY(c, hipMemcpyAsync(elem, cid.data(), m * 4, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     (void)hipFree(didx);
   }

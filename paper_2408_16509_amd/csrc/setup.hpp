@@ -46,7 +46,8 @@ struct Block {
   int etype = kHex;
   int64_t n = 0, e_pad = 0;
   int nsp = 0, nfp = 0, nfaces = 0, nfpf = 0;
-  std::vector<int64_t> elems;      // global element ids in block order (mesh order)
+  std::vector<int64_t> elems;      // global element ids in native order
+  std::vector<int32_t> canon_pos;  // native index -> canonical index (input order within the type)
   int ngeo = 0;
   std::vector<double> geo;         // [ngeo][e_pad]
   std::vector<int32_t> nbr_elem;   // [nfaces][e_pad] neighbour's local index (same block)
@@ -69,6 +70,6 @@ void build_hex_ops(int p, HexOps& ops);
 void build_tet_ops(TetOps& ops);
 std::string build_setup(int order, int64_t n_vert, const double* xyz, const double* period,
                         int64_t n_elem, const int32_t* etype, const int64_t* enodes,
-                        int e_align, Setup& out, int& code);
+                        int e_align, int elem_order, Setup& out, int& code);
 
 }  // namespace frmi

@@ -8,11 +8,10 @@
 // and the LDG corrected reference gradient is gt_i = Dh_i u + L diag(n~_i) u^.
 // Affine elements: S = J G^{-1} and J are constant per element (geo[10][E]).
 //
-// Work mapping: lane = element (NE per block), point groups over the block's waves.
-// For each variable the block stages the panel B = [f~_0; f~_1; f~_2; F^C] (165
-// rows, or [u; u^] for the gradient) in LDS and contracts it with the dense
-// operator rows; flux and Riemann evaluations are redone per variable, which costs
-// flops but keeps the per-thread state small.
+// Kernels: the gradient (lane = element, for each variable the panel [u; u^] staged
+// in LDS and contracted with the dense operator rows), the common fluxes (thread
+// per element and flux point), and the divergence as one dense contraction per
+// block of elements on the matrix cores.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -61,58 +60,6 @@ __device__ __forceinline__ T tet_dot(const T* __restrict__ A, int nk, const T* B
 }
 
 // ---------------------------------------------------------------------------
-// Euler: R = -(sum_i Dh_i f~_i + L F^C) / J.
-template <typename T, bool DEV, int NE, int NG>
-__global__ void __launch_bounds__(NE * NG) tet_div_euler(const T* __restrict__ u, const T* __restrict__ geo,
-                                                         Conn C, TetDev<T> O, T* __restrict__ r, int64_t E,
-                                                         int64_t n, T gamma, int riemann, RefState<T> R) {
-  __shared__ T B[(3 * TET_NSP + TET_NFP) * NE];
-  const int el = threadIdx.x % NE, g = threadIdx.x / NE;
-  const int64_t e = xcd_block() * NE + el;
-  T S[9], J;
-  tet_geo(geo, E, e, S, J);
-  const T gm1 = gamma - T(1);
-#pragma unroll
-  for (int v = 0; v < 5; ++v) {
-    for (int pt = g; pt < TET_NSP; pt += NG) {
-      T w[5], f[5], vs, pr;
-      tet_load(u, E, e, pt, w);
-#pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        Flux<T, DEV>::eval(w, S[3 * i], S[3 * i + 1], S[3 * i + 2], gm1, R, f, vs, pr);
-        B[(i * TET_NSP + pt) * NE + el] = f[v];
-      }
-    }
-    for (int sg = g; sg < TET_NFP; sg += NG) {
-      const int face = sg / TET_NFPF, q = sg % TET_NFPF;
-      const NbrSlot ns = nbr_slot<TET_NFPF>(C, E, e, face, q);
-      T own[5], un[5], nv[3], nL[3], uL[5], uR[5], F[5];
-      tet_load(u, E, e, O.src[sg], own);
-      tet_load(u, E, ns.elem, O.src[ns.fp], un);
-      tet_normal(S, O, face, nv);
-      const T mag = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
-      const T sl = (ns.left ? T(1) : T(-1)) / mag;
-#pragma unroll
-      for (int k = 0; k < 3; ++k) nL[k] = nv[k] * sl;
-#pragma unroll
-      for (int c = 0; c < 5; ++c) { uL[c] = ns.left ? own[c] : un[c]; uR[c] = ns.left ? un[c] : own[c]; }
-      common_inviscid<T, DEV>(riemann, uL, uR, nL, gamma, R, F);
-      B[(3 * TET_NSP + sg) * NE + el] = (ns.left ? mag : -mag) * F[v];
-    }
-    __syncthreads();
-    const T iJ = T(-1) / J;
-    for (int pt = g; pt < TET_NSP; pt += NG) {
-      T acc = T(0);
-#pragma unroll
-      for (int i = 0; i < 3; ++i) acc += tet_dot<T, NE>(O.Dh + (i * TET_NSP + pt) * TET_NSP, TET_NSP, B + i * TET_NSP * NE, el);
-      acc += tet_dot<T, NE>(O.L + pt * TET_NFP, TET_NFP, B + 3 * TET_NSP * NE, el);
-      if (e < n) r[((int64_t)pt * 5 + v) * E + e] = acc * iJ;
-    }
-    __syncthreads();
-  }
-}
-
-// ---------------------------------------------------------------------------
 // Navier--Stokes phase 1: physical gradient at the solution points,
 // grad = G^{-T} (Dh u + L n~ u^)   (G^{-T} = S^T / J).  Flux-point gradients are
 // the collocated solution-point values, so no trace array is needed.
@@ -154,70 +101,175 @@ __global__ void __launch_bounds__(NE * NG) tet_grad(const T* __restrict__ u, con
 }
 
 // ---------------------------------------------------------------------------
-// Navier--Stokes phase 2: f = f_inv - f_v at the solution points, LDG common flux
-// at the flux points from the collocated values of both sides, corrected divergence.
-template <typename T, bool DEV, int NE, int NG>
-__global__ void __launch_bounds__(NE * NG) tet_div_ns(const T* __restrict__ u, const T* __restrict__ grad,
-                                                      const T* __restrict__ geo, Conn C, TetDev<T> O,
-                                                      T* __restrict__ r, int64_t E, int64_t n, T gamma, T mu, T pr,
-                                                      T beta, T tau, int riemann, RefState<T> R) {
-  __shared__ T B[(3 * TET_NSP + TET_NFP) * NE];
-  const int el = threadIdx.x % NE, g = threadIdx.x / NE;
-  const int64_t e = xcd_block() * NE + el;
+// Common fluxes at the flux points (eq:comm_flux, with the LDG viscous part for
+// Navier--Stokes): one thread per (element, flux point), lanes over 64 consecutive
+// elements.  Both sides' states are collocated solution-point values; with a
+// one-sided switch only the contributing side's gradient is read.
+// fc[s][v][E] = +-|S^T n~| times the common normal flux (sign of the element's side).
+template <typename T, bool DEV, bool NS>
+__global__ void __launch_bounds__(256) tet_face(const T* __restrict__ u, const T* __restrict__ grad,
+                                                const T* __restrict__ geo, Conn C, TetDev<T> O, T* __restrict__ fc,
+                                                int64_t E, T gamma, T mu, T pr, T beta, T tau, int riemann,
+                                                int side_mode, RefState<T> R) {
+  const int64_t gtid = xcd_block() * 256 + threadIdx.x;
+  const int64_t wave = gtid >> 6;
+  const int lane = (int)(gtid & 63);
+  const int64_t tile = wave / TET_NFP;
+  const int sg = (int)(wave % TET_NFP);
+  const int64_t e = tile * 64 + lane;
+  if (e >= E) return;
+  const int face = sg / TET_NFPF, q = sg % TET_NFPF;
   T S[9], J;
   tet_geo(geo, E, e, S, J);
+  const NbrSlot ns = nbr_slot<TET_NFPF>(C, E, e, face, q);
+  const int so = O.src[sg], sn = O.src[ns.fp];
+  T own[5], un[5], nv[3], nL[3], uL[5], uR[5], F[5];
+  tet_load(u, E, e, so, own);
+  tet_load(u, E, ns.elem, sn, un);
+  tet_normal(S, O, face, nv);
+  const T mag = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+  const T sl = (ns.left ? T(1) : T(-1)) / mag;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) nL[k] = nv[k] * sl;
+#pragma unroll
+  for (int c = 0; c < 5; ++c) { uL[c] = ns.left ? own[c] : un[c]; uR[c] = ns.left ? un[c] : own[c]; }
+  common_inviscid<T, DEV>(riemann, uL, uR, nL, gamma, R, F);
+  if constexpr (NS) {
+    const T wL = T(0.5) - beta, wR = T(0.5) + beta;
+    const T w_own = ns.left ? wL : wR, w_nbr = ns.left ? wR : wL;
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const T wgt = side == 0 ? w_own : w_nbr;
+      if (side_mode != 0 && wgt == T(0)) continue;
+      const int64_t gp = side == 0 ? so : sn, ge = side == 0 ? e : ns.elem;
+      T gk[15], fv[5];
+#pragma unroll
+      for (int k = 0; k < 15; ++k) gk[k] = grad[(gp * 15 + k) * E + ge];
+      viscous<T, DEV>(side == 0 ? own : un, gk, nL[0], nL[1], nL[2], gamma, mu, pr, R, fv);
+#pragma unroll
+      for (int c = 0; c < 5; ++c) F[c] -= wgt * fv[c];
+    }
+#pragma unroll
+    for (int c = 0; c < 5; ++c) F[c] += tau * (uL[c] - uR[c]);
+  }
+  const T fs = ns.left ? mag : -mag;
+#pragma unroll
+  for (int c = 0; c < 5; ++c) fc[((int64_t)sg * 5 + c) * E + e] = fs * F[c];
+}
+
+// 16x16x4 matrix-core products: D = A B + C with A 16x4 (lane l: A[l % 16][l / 16]),
+// B 4x16 (lane l: B[l / 16][l % 16]) and D 16x16, lane l holding column l % 16 in four
+// registers q: rows 4 (l / 16) + q for FP32, rows l / 16 + 4 q for FP64 (both checked
+// on gfx950 by a one-wave product of known matrices).
+typedef float tet_f4 __attribute__((ext_vector_type(4)));
+typedef double tet_d4 __attribute__((ext_vector_type(4)));
+template <typename T>
+struct Mma16;
+template <>
+struct Mma16<float> {
+  using V = tet_f4;
+  __device__ __forceinline__ static V run(float a, float b, V c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ __forceinline__ static int row(int lane, int q) { return 4 * (lane / 16) + q; }
+};
+template <>
+struct Mma16<double> {
+  using V = tet_d4;
+  __device__ __forceinline__ static V run(double a, double b, V c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ __forceinline__ static int row(int lane, int q) { return lane / 16 + 4 * q; }
+};
+
+// Contraction layout: K rows 0..104 are the transformed fluxes f~_i at the solution
+// points (k = 35 i + point), 105..107 zero, 108..167 the common fluxes at the flux
+// points; output rows are the 35 solution points padded to 48.  opT[k][pt] holds
+// Op = [Dh_0 Dh_1 Dh_2 L] transposed and zero-padded.
+constexpr int TET_KA = 108, TET_KB = 60, TET_KP = TET_KA + TET_KB, TET_MP = 48;
+constexpr int TDIV_NE = 16, TDIV_NT = 5 * 64;
+
+// Corrected divergence (eq:FRfinal) on the matrix cores: per block of 16 elements,
+// R^T = -(1/J) Op P with the panel P = [f~_0; f~_1; f~_2; F^C] (K x 5*16).  The block
+// stages Op once in LDS and loops over a contiguous range of element tiles; for each
+// tile its 5 waves evaluate the fluxes into the panel (two K chunks through LDS),
+// then wave v multiplies the 16 columns of variable v by the three 16-row tiles of Op.
+template <typename T, bool DEV, bool NS>
+__global__ void __launch_bounds__(TDIV_NT) tet_div(const T* __restrict__ u, const T* __restrict__ grad,
+                                                   const T* __restrict__ fc, const T* __restrict__ geo,
+                                                   const T* __restrict__ opT, T* __restrict__ r, int64_t E, int64_t n,
+                                                   T gamma, T mu, T pr, RefState<T> R) {
+  constexpr int NE = TDIV_NE, NT = TDIV_NT;
+  __shared__ T OP[TET_KP * TET_MP];
+  __shared__ T PAN[TET_KA * 5 * NE];     // [k][v][el]; the second K chunk reuses it
+  __shared__ T SJ[10 * NE];
+  const int t = threadIdx.x;
+  const int v = t / 64, lane = t % 64, kr = lane / 16, col = lane % 16;
   const T gm1 = gamma - T(1);
-  const T wL = T(0.5) - beta, wR = T(0.5) + beta;
-#pragma unroll
-  for (int v = 0; v < 5; ++v) {
-    for (int pt = g; pt < TET_NSP; pt += NG) {
-      T w[5], gg[15], f[5], fv[5], vs, prs;
+  for (int i = t; i < TET_KP * TET_MP; i += NT) OP[i] = opT[i];
+  const int64_t ntile = E / NE, b = xcd_block(), nb = gridDim.x;
+  const int64_t tb = b * ntile / nb, te = (b + 1) * ntile / nb;
+  for (int64_t tile = tb; tile < te; ++tile) {
+    const int64_t e0 = tile * NE;
+    __syncthreads();
+    for (int i = t; i < 10 * NE; i += NT) SJ[i] = geo[(int64_t)(i / NE) * E + e0 + i % NE];
+    for (int i = t; i < 3 * 5 * NE; i += NT) PAN[105 * 5 * NE + i] = T(0);
+    __syncthreads();
+    // K chunk 1: transformed fluxes at the solution points
+    for (int it = t; it < NE * TET_NSP; it += NT) {
+      const int el = it % NE, pt = it / NE;
+      const int64_t e = e0 + el;
+      T w[5], gg[15];
       tet_load(u, E, e, pt, w);
+      if constexpr (NS) {
 #pragma unroll
-      for (int k = 0; k < 15; ++k) gg[k] = grad[((int64_t)pt * 15 + k) * E + e];
+        for (int k = 0; k < 15; ++k) gg[k] = grad[((int64_t)pt * 15 + k) * E + e];
+      }
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
-        Flux<T, DEV>::eval(w, S[3 * i], S[3 * i + 1], S[3 * i + 2], gm1, R, f, vs, prs);
-        viscous<T, DEV>(w, gg, S[3 * i], S[3 * i + 1], S[3 * i + 2], gamma, mu, pr, R, fv);
-        B[(i * TET_NSP + pt) * NE + el] = f[v] - fv[v];
+        const T sx = SJ[(3 * i) * NE + el], sy = SJ[(3 * i + 1) * NE + el], sz = SJ[(3 * i + 2) * NE + el];
+        T f[5], vs, prs;
+        Flux<T, DEV>::eval(w, sx, sy, sz, gm1, R, f, vs, prs);
+        if constexpr (NS) {
+          T fv[5];
+          viscous<T, DEV>(w, gg, sx, sy, sz, gamma, mu, pr, R, fv);
+#pragma unroll
+          for (int c = 0; c < 5; ++c) f[c] -= fv[c];
+        }
+#pragma unroll
+        for (int c = 0; c < 5; ++c) PAN[((i * TET_NSP + pt) * 5 + c) * NE + el] = f[c];
       }
     }
-    for (int sg = g; sg < TET_NFP; sg += NG) {
-      const int face = sg / TET_NFPF, q = sg % TET_NFPF;
-      const NbrSlot ns = nbr_slot<TET_NFPF>(C, E, e, face, q);
-      const int so = O.src[sg], sn = O.src[ns.fp];
-      T own[5], un[5], nv[3], nL[3], uL[5], uR[5], F[5], go[15], gn[15], fvo[5], fvn[5];
-      tet_load(u, E, e, so, own);
-      tet_load(u, E, ns.elem, sn, un);
+    __syncthreads();
+    typename Mma16<T>::V acc[3];
 #pragma unroll
-      for (int k = 0; k < 15; ++k) {
-        go[k] = grad[((int64_t)so * 15 + k) * E + e];
-        gn[k] = grad[((int64_t)sn * 15 + k) * E + ns.elem];
-      }
-      tet_normal(S, O, face, nv);
-      const T mag = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
-      const T sl = (ns.left ? T(1) : T(-1)) / mag;
+    for (int mt = 0; mt < 3; ++mt) acc[mt] = typename Mma16<T>::V{0, 0, 0, 0};
+    for (int k0 = 0; k0 < TET_KA; k0 += 4) {
+      const T bop = PAN[((k0 + kr) * 5 + v) * NE + col];
 #pragma unroll
-      for (int k = 0; k < 3; ++k) nL[k] = nv[k] * sl;
-#pragma unroll
-      for (int c = 0; c < 5; ++c) { uL[c] = ns.left ? own[c] : un[c]; uR[c] = ns.left ? un[c] : own[c]; }
-      common_inviscid<T, DEV>(riemann, uL, uR, nL, gamma, R, F);
-      viscous<T, DEV>(own, go, nL[0], nL[1], nL[2], gamma, mu, pr, R, fvo);
-      viscous<T, DEV>(un, gn, nL[0], nL[1], nL[2], gamma, mu, pr, R, fvn);
-      const T w_own = ns.left ? wL : wR, w_nbr = ns.left ? wR : wL;
-      const T fvc = w_own * fvo[v] + w_nbr * fvn[v];
-      B[(3 * TET_NSP + sg) * NE + el] = (ns.left ? mag : -mag) * (F[v] - fvc + tau * (uL[v] - uR[v]));
+      for (int mt = 0; mt < 3; ++mt) acc[mt] = Mma16<T>::run(OP[(k0 + kr) * TET_MP + mt * 16 + col], bop, acc[mt]);
     }
     __syncthreads();
-    const T iJ = T(-1) / J;
-    for (int pt = g; pt < TET_NSP; pt += NG) {
-      T acc = T(0);
-#pragma unroll
-      for (int i = 0; i < 3; ++i) acc += tet_dot<T, NE>(O.Dh + (i * TET_NSP + pt) * TET_NSP, TET_NSP, B + i * TET_NSP * NE, el);
-      acc += tet_dot<T, NE>(O.L + pt * TET_NFP, TET_NFP, B + 3 * TET_NSP * NE, el);
-      if (e < n) r[((int64_t)pt * 5 + v) * E + e] = acc * iJ;
-    }
+    // K chunk 2: common fluxes at the flux points
+    for (int i = t; i < TET_KB * 5 * NE; i += NT) PAN[i] = fc[(int64_t)(i / NE) * E + e0 + i % NE];
     __syncthreads();
+    for (int k0 = 0; k0 < TET_KB; k0 += 4) {
+      const T bop = PAN[((k0 + kr) * 5 + v) * NE + col];
+#pragma unroll
+      for (int mt = 0; mt < 3; ++mt)
+        acc[mt] = Mma16<T>::run(OP[(TET_KA + k0 + kr) * TET_MP + mt * 16 + col], bop, acc[mt]);
+    }
+    const int64_t e = e0 + col;
+    const T iJ = T(-1) / SJ[9 * NE + col];
+    if (e < n) {
+#pragma unroll
+      for (int mt = 0; mt < 3; ++mt)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int pt = mt * 16 + Mma16<T>::row(lane, q);
+          if (pt < TET_NSP) r[((int64_t)pt * 5 + v) * E + e] = acc[mt][q] * iJ;
+        }
+    }
   }
 }
 

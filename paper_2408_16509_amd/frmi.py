@@ -26,7 +26,7 @@ STATUS = {0: "FR_OK", 1: "FR_ERR_ARG", 2: "FR_ERR_MESH", 3: "FR_ERR_ALLOC", 4: "
 class FrParams(ctypes.Structure):
     _fields_ = [
         ("struct_size", ctypes.c_uint32), ("system", ctypes.c_int32), ("order", ctypes.c_int32),
-        ("riemann", ctypes.c_int32), ("precision", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+        ("riemann", ctypes.c_int32), ("precision", ctypes.c_int32), ("elem_order", ctypes.c_int32),
         ("gamma", ctypes.c_double), ("mu", ctypes.c_double), ("prandtl", ctypes.c_double),
         ("ldg_beta", ctypes.c_double), ("ldg_tau", ctypes.c_double), ("u_ref", ctypes.c_double * 5),
         ("filt_eps_rho", ctypes.c_double), ("filt_eps_p", ctypes.c_double), ("filt_eps_s", ctypes.c_double),

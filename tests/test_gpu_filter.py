@@ -146,6 +146,31 @@ def test_filtered_rk_step_matches_oracle():
     assert ctx.check(ug)
 
 
+def test_filtered_rk_step_fp32_form():
+    """The same step in the FP32 deviation form (about the pre-shock state): FP32
+    right-hand sides, FP64 stage states, accumulation and filter.  Stated bound: the
+    increment within 1e-4 of the FP64 oracle's (FP32 rounding of the right-hand side,
+    plus filter strengths that may move by a dyadic step where a stage state sits on a
+    bound); the result satisfies every bound at every check point (oracle's check)."""
+    from paper_2408_16509_amd import frmi
+    mesh, bl, u0, _ = shock_case()
+    smin0 = ef.smin_neighbourhood(bl, [u0], FP)
+    post = lambda s: [ef.filter_block(bb, ss, sm, FP)[0] for bb, ss, sm in zip(bl, s, smin0)]
+    prm = ofr.Params(riemann=1)
+    uo = ork.rk4_step(lambda s: ofr.rhs(bl, s, prm), [u0], 2e-2, stage_post=post)[0]
+    ctx = frmi.Context(mesh, system=0, order=3, riemann=1, precision=frmi.FR_FP32,
+                       u_ref=(1.0, 0.0, 0.0, 0.0, 1.0 / 0.4))
+    ug = ctx.pack64(u0.ravel())
+    ctx.rk_step(ug, 2e-2, 1, filter_mode=0)
+    got = ctx.unpack64(ug).cpu().numpy().reshape(uo.shape)
+    err = np.linalg.norm(got - uo) / np.linalg.norm(uo - u0)
+    ok, _ = ef.admissible(bl[0], got, smin0[0], FP)
+    print(f"filtered RK4 step, FP32 form: relative error of the increment {err:.2e}; "
+          f"elements within bounds {ok.mean():.4f}")
+    assert err <= 1e-4
+    assert ok.all()
+
+
 def test_warm_start_gain_after_training():
     """Train the MLP on plain-filter data from held-out shock draws, then filter an
     unseen draw: identical k, fewer constraint evaluations per troubled element."""

@@ -83,11 +83,9 @@ def kernel_bytes_per_elem(name, nsp, nfp):
         "hex_grad": d * (5 * nsp + 5 * nfp // 2 + 15 * nsp + 15 * nfp // 2) + hex_geo + hex_conn,
         "hex_face_ns": d * (5 * nfp + 15 * nfp // 2 + 5 * nfp) + hex_geo + hex_conn,
         "hex_div_ns": d * (5 * nsp + 15 * nsp + 5 * nfp + 5 * nsp) + hex_geo,
-        "tet_face_euler": d * (5 * nsp + 5 * nfp) + tet_gc,
-        "tet_div_euler": d * (5 * nsp + 5 * nfp + 5 * nsp) + 10 * d,
+        "tet_div_euler": d * (5 * nsp + 5 * nsp) + tet_gc,
         "tet_grad": d * (5 * nsp + 15 * nsp) + tet_gc,
-        "tet_face_ns": d * (5 * nsp + 15 * nsp + 5 * nfp) + tet_gc,
-        "tet_div_ns": d * (5 * nsp + 15 * nsp + 5 * nfp + 5 * nsp) + 10 * d,
+        "tet_div_ns": d * (5 * nsp + 15 * nsp + 5 * nsp) + tet_gc,
     }
     return table.get(fam)
 

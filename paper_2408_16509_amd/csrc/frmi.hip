@@ -86,10 +86,9 @@ struct fr_ctx_s {
   int m_batch_cap = 0;
   bool mlp_ready = false;
   // tetrahedral operators on the device (arithmetic type of the context)
-  void* tet_Dh = nullptr;
-  void* tet_opT = nullptr;
+  void* tet_opT = nullptr;    // [TET_KP][TET_MP] transposed divergence operator
+  void* tet_ogT = nullptr;    // [TGR_K][TGR_M] transposed stacked gradient operator
   double* rk_s64 = nullptr;   // FP64 stage state of the filtered FP32 form    // [TET_KP][TET_MP] transposed divergence operator
-  void* tet_L = nullptr;
   int32_t* tet_src = nullptr;
   // training-data collection during filtered RK steps (fr_mlp_collect)
   bool collecting = false;
@@ -375,48 +374,33 @@ fr_status hex_rhs_p(fr_ctx c, DevBlock& b, const T* u, T* r) {
 
 template <typename T, bool DEV>
 fr_status tet_rhs(fr_ctx c, DevBlock& b, const T* u, T* r) {
-  constexpr int NE = sizeof(T) == 8 ? 32 : 64, NG = 256 / NE;
   Conn C{b.nbr_elem, b.nbr_info, c->perm, c->host.perm_stride};
   const fr_params& p = c->prm;
   TetDev<T> O;
-  O.Dh = (const T*)c->tet_Dh;
-  O.L = (const T*)c->tet_L;
   O.src = c->tet_src;
   for (int f = 0; f < 4; ++f)
     for (int k = 0; k < 3; ++k) O.nref[f][k] = (T)c->host.tet.nref[f][k];
   const RefState<T> R = ref_of<T>(p);
   const T* geo = (const T*)b.geo_t;
-  const unsigned nblk = (unsigned)(b.E / NE);
   static const std::string sfx = sizeof(T) == 8 ? "" : "_f32";
   const int sm = side_mode_of(p.ldg_beta);
-  const int64_t face_threads = b.E * TET_NFP;
-  const unsigned face_grid = (unsigned)((face_threads + 255) / 256);
-  // persistent divergence grid: a few resident blocks per CU, each over a tile range
-  const unsigned div_grid = (unsigned)std::min<int64_t>(b.E / TDIV_NE, sizeof(T) == 8 ? 256 : 512);
+  const unsigned div_grid = (unsigned)(b.E / TDIV_NE);   // one 16-element tile per block
   const T* opT = (const T*)c->tet_opT;
-  T* fc = (T*)b.fc;
   int pk;
   if (p.system == FR_EULER) {
-    pk = c->prof_begin(("tet_face_euler" + sfx).c_str());
-    tet_face<T, DEV, false><<<face_grid, 256, 0, c->stream>>>(u, nullptr, geo, C, O, fc, b.E, (T)p.gamma, (T)0, (T)0,
-                                                              (T)0, (T)0, p.riemann, 0, R);
-    c->prof_end(pk);
     pk = c->prof_begin(("tet_div_euler" + sfx).c_str());
-    tet_div<T, DEV, false><<<div_grid, TDIV_NT, 0, c->stream>>>(u, nullptr, fc, geo, opT, r, b.E, b.n, (T)p.gamma,
-                                                                (T)0, (T)0, R);
+    tet_div<T, DEV, false><<<div_grid, TDIV_NT, 0, c->stream>>>(u, nullptr, geo, C, O, opT, r, b.E, b.n, (T)p.gamma,
+                                                                (T)0, (T)0, (T)0, (T)0, p.riemann, 0, R);
     c->prof_end(pk);
   } else {
     pk = c->prof_begin(("tet_grad" + sfx).c_str());
-    tet_grad<T, NE, NG><<<nblk, NE * NG, 0, c->stream>>>(u, geo, C, O, (T*)b.grad, b.E, (T)p.ldg_beta);
-    c->prof_end(pk);
-    pk = c->prof_begin(("tet_face_ns" + sfx).c_str());
-    tet_face<T, DEV, true><<<face_grid, 256, 0, c->stream>>>(u, (const T*)b.grad, geo, C, O, fc, b.E, (T)p.gamma,
-                                                             (T)p.mu, (T)p.prandtl, (T)p.ldg_beta, (T)p.ldg_tau,
-                                                             p.riemann, sm, R);
+    tet_grad_mma<T><<<div_grid, TDIV_NT, 0, c->stream>>>(u, geo, C, O, (const T*)c->tet_ogT, (T*)b.grad, b.E, b.n,
+                                                          (T)p.ldg_beta);
     c->prof_end(pk);
     pk = c->prof_begin(("tet_div_ns" + sfx).c_str());
-    tet_div<T, DEV, true><<<div_grid, TDIV_NT, 0, c->stream>>>(u, (const T*)b.grad, fc, geo, opT, r, b.E, b.n,
-                                                               (T)p.gamma, (T)p.mu, (T)p.prandtl, R);
+    tet_div<T, DEV, true><<<div_grid, TDIV_NT, 0, c->stream>>>(u, (const T*)b.grad, geo, C, O, opT, r, b.E, b.n,
+                                                               (T)p.gamma, (T)p.mu, (T)p.prandtl, (T)p.ldg_beta,
+                                                               (T)p.ldg_tau, p.riemann, sm, R);
     c->prof_end(pk);
   }
   hipError_t e = hipGetLastError();
@@ -720,7 +704,7 @@ void fr_destroy(fr_ctx c) {
   (void)hipFree(c->g_npos);
   (void)hipFree(c->rk_stage); (void)hipFree(c->rk_acc); (void)hipFree(c->rk_k); (void)hipFree(c->rk_s64);
   (void)hipFree(c->flag);
-  (void)hipFree(c->tet_Dh); (void)hipFree(c->tet_L); (void)hipFree(c->tet_src); (void)hipFree(c->tet_opT);
+  (void)hipFree(c->tet_src); (void)hipFree(c->tet_opT); (void)hipFree(c->tet_ogT);
   for (auto& b : c->blocks) {
     (void)hipFree(b.sown); (void)hipFree(b.smin);
     (void)hipFree(b.f_det); (void)hipFree(b.f_list); (void)hipFree(b.f_cnt);
@@ -797,7 +781,7 @@ fr_status fr_setup_mesh(const fr_params* p, int64_t n_vert, const double* xyz, c
         (dalloc(c, (char**)&d.grad, (size_t)d.nsp * 15 * d.E * tsz) ||
          (!is_tet && dalloc(c, (char**)&d.gradf, (size_t)d.nfp * 15 * d.E * tsz))))
       return bail(FR_ERR_ALLOC);
-    if ((p->system == FR_NAVIER_STOKES || is_tet) && dalloc(c, (char**)&d.fc, (size_t)d.nfp * 5 * d.E * tsz))
+    if (p->system == FR_NAVIER_STOKES && !is_tet && dalloc(c, (char**)&d.fc, (size_t)d.nfp * 5 * d.E * tsz))
       return bail(FR_ERR_ALLOC);
     d.geo_t = d.geo;
     if (tsz == sizeof(float)) {
@@ -843,7 +827,6 @@ fr_status fr_setup_mesh(const fr_params* p, int64_t n_vert, const double* xyz, c
   for (auto& b : c->blocks) has_tet = has_tet || b.etype == FR_TET;
   if (has_tet) {
     const TetOps& T = c->host.tet;
-    std::vector<double> dh(&T.Dh[0][0][0], &T.Dh[0][0][0] + 3 * 35 * 35), L(&T.lift[0][0], &T.lift[0][0] + 35 * 60);
     std::vector<int32_t> src(T.fp_src, T.fp_src + 60);
     // transposed, zero-padded divergence operator [Dh_0 Dh_1 Dh_2 L] of the matrix-core contraction
     std::vector<double> opT((size_t)TET_KP * TET_MP, 0.0);
@@ -854,25 +837,25 @@ fr_status fr_setup_mesh(const fr_params* p, int64_t n_vert, const double* xyz, c
     std::vector<char> bop(opT.size() * tsz);
     if (tsz == sizeof(float)) for (size_t i = 0; i < opT.size(); ++i) ((float*)bop.data())[i] = (float)opT[i];
     else std::memcpy(bop.data(), opT.data(), bop.size());
-    if (dalloc(c, (char**)&c->tet_opT, bop.size()) ||
-        hipMemcpy(c->tet_opT, bop.data(), bop.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    // stacked, transposed gradient operator [[Dh_i, L diag(n~_i)]] (i = 0, 1, 2)
+    std::vector<double> ogT((size_t)TGR_K * TGR_M, 0.0);
+    for (int i = 0; i < 3; ++i)
+      for (int pt = 0; pt < 35; ++pt) {
+        for (int k = 0; k < 35; ++k) ogT[(size_t)k * TGR_M + TET_MP * i + pt] = T.Dh[i][pt][k];
+        for (int sg = 0; sg < 60; ++sg)
+          ogT[(size_t)(35 + sg) * TGR_M + TET_MP * i + pt] = T.lift[pt][sg] * T.nref[T.fp_face[sg]][i];
+      }
+    std::vector<char> bog(ogT.size() * tsz);
+    if (tsz == sizeof(float)) for (size_t i = 0; i < ogT.size(); ++i) ((float*)bog.data())[i] = (float)ogT[i];
+    else std::memcpy(bog.data(), ogT.data(), bog.size());
+    if (dalloc(c, (char**)&c->tet_opT, bop.size()) || dalloc(c, (char**)&c->tet_ogT, bog.size()) ||
+        hipMemcpy(c->tet_opT, bop.data(), bop.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->tet_ogT, bog.data(), bog.size(), hipMemcpyHostToDevice) != hipSuccess) {
       c->err = "tet operator upload failed";
       return bail(FR_ERR_DEVICE);
     }
-    const size_t bytes_dh = dh.size() * tsz, bytes_l = L.size() * tsz;
-    std::vector<char> bdh(bytes_dh), bl(bytes_l);
-    if (tsz == sizeof(float)) {
-      for (size_t i = 0; i < dh.size(); ++i) ((float*)bdh.data())[i] = (float)dh[i];
-      for (size_t i = 0; i < L.size(); ++i) ((float*)bl.data())[i] = (float)L[i];
-    } else {
-      std::memcpy(bdh.data(), dh.data(), bytes_dh);
-      std::memcpy(bl.data(), L.data(), bytes_l);
-    }
-    if (dalloc(c, (char**)&c->tet_Dh, bytes_dh) || dalloc(c, (char**)&c->tet_L, bytes_l) || dalloc(c, &c->tet_src, 60))
-      return bail(FR_ERR_ALLOC);
-    if (hipMemcpy(c->tet_Dh, bdh.data(), bytes_dh, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(c->tet_L, bl.data(), bytes_l, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(c->tet_src, src.data(), 60 * 4, hipMemcpyHostToDevice) != hipSuccess) {
+    if (dalloc(c, &c->tet_src, 60)) return bail(FR_ERR_ALLOC);
+    if (hipMemcpy(c->tet_src, src.data(), 60 * 4, hipMemcpyHostToDevice) != hipSuccess) {
       c->err = "upload failed";
       return bail(FR_ERR_DEVICE);
     }

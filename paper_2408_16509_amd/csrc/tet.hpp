@@ -8,10 +8,9 @@
 // and the LDG corrected reference gradient is gt_i = Dh_i u + L diag(n~_i) u^.
 // Affine elements: S = J G^{-1} and J are constant per element (geo[10][E]).
 //
-// Kernels: the gradient (lane = element, for each variable the panel [u; u^] staged
-// in LDS and contracted with the dense operator rows), the common fluxes (thread
-// per element and flux point), and the divergence as one dense contraction per
-// block of elements on the matrix cores.
+// Kernels: the gradient and the divergence, each one dense contraction per block of
+// 16 elements on the matrix cores, with the panel ([u; u^], or the transformed and
+// common fluxes) evaluated into LDS by the same block.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -25,8 +24,6 @@ constexpr int TET_NSP = 35, TET_NFP = 60, TET_NFPF = 15;
 
 template <typename T>
 struct TetDev {
-  const T* Dh;          // [3][35][35]
-  const T* L;           // [35][60]
   const int32_t* src;   // [60] collocated solution point of each flux point
   T nref[4][3];         // unit outward reference normals of the faces
 };
@@ -51,79 +48,20 @@ __device__ __forceinline__ void tet_load(const T* __restrict__ u, int64_t E, int
   for (int v = 0; v < 5; ++v) w[v] = u[((int64_t)pt * 5 + v) * E + e];
 }
 
-// One row of the contraction: sum_k A[row][k] B[k][el] over nk rows of the panel.
-template <typename T, int NE>
-__device__ __forceinline__ T tet_dot(const T* __restrict__ A, int nk, const T* B, int el) {
-  T acc = T(0);
-  for (int k = 0; k < nk; ++k) acc += A[k] * B[k * NE + el];
-  return acc;
-}
-
 // ---------------------------------------------------------------------------
-// Navier--Stokes phase 1: physical gradient at the solution points,
-// grad = G^{-T} (Dh u + L n~ u^)   (G^{-T} = S^T / J).  Flux-point gradients are
-// the collocated solution-point values, so no trace array is needed.
-template <typename T, int NE, int NG>
-__global__ void __launch_bounds__(NE * NG) tet_grad(const T* __restrict__ u, const T* __restrict__ geo, Conn C,
-                                                    TetDev<T> O, T* __restrict__ grad, int64_t E, T beta) {
-  __shared__ T B[(TET_NSP + TET_NFP) * NE];
-  const int el = threadIdx.x % NE, g = threadIdx.x / NE;
-  const int64_t e = xcd_block() * NE + el;
-  T S[9], J;
-  tet_geo(geo, E, e, S, J);
-  for (int v = 0; v < 5; ++v) {
-    for (int pt = g; pt < TET_NSP; pt += NG) B[pt * NE + el] = u[((int64_t)pt * 5 + v) * E + e];
-    for (int sg = g; sg < TET_NFP; sg += NG) {
-      const int face = sg / TET_NFPF, q = sg % TET_NFPF;
-      const NbrSlot ns = nbr_slot<TET_NFPF>(C, E, e, face, q);
-      const T own = u[((int64_t)O.src[sg] * 5 + v) * E + e];
-      const T un = u[((int64_t)O.src[ns.fp] * 5 + v) * E + ns.elem];
-      const T uL = ns.left ? own : un, uR = ns.left ? un : own;
-      B[(TET_NSP + sg) * NE + el] = T(0.5) * (uL + uR) + beta * (uL - uR);
-    }
-    __syncthreads();
-    const T iJ = T(1) / J;
-    for (int pt = g; pt < TET_NSP; pt += NG) {
-      T gt[3];
-#pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        T acc = tet_dot<T, NE>(O.Dh + (i * TET_NSP + pt) * TET_NSP, TET_NSP, B, el);
-        const T* Lr = O.L + pt * TET_NFP;
-        for (int sg = 0; sg < TET_NFP; ++sg) acc += Lr[sg] * O.nref[sg / TET_NFPF][i] * B[(TET_NSP + sg) * NE + el];
-        gt[i] = acc;
-      }
-#pragma unroll
-      for (int j = 0; j < 3; ++j)
-        grad[((int64_t)pt * 15 + v * 3 + j) * E + e] = (S[j] * gt[0] + S[3 + j] * gt[1] + S[6 + j] * gt[2]) * iJ;
-    }
-    __syncthreads();
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Common fluxes at the flux points (eq:comm_flux, with the LDG viscous part for
-// Navier--Stokes): one thread per (element, flux point), lanes over 64 consecutive
-// elements.  Both sides' states are collocated solution-point values; with a
-// one-sided switch only the contributing side's gradient is read.
-// fc[s][v][E] = +-|S^T n~| times the common normal flux (sign of the element's side).
+// Common normal flux at flux point sg of element e (eq:comm_flux, with the LDG viscous
+// part for Navier--Stokes), times +-|S^T n~| (the sign of the element's side).  Both
+// sides' states are collocated solution-point values; with a one-sided switch only
+// the contributing side's gradient is read.
 template <typename T, bool DEV, bool NS>
-__global__ void __launch_bounds__(256) tet_face(const T* __restrict__ u, const T* __restrict__ grad,
-                                                const T* __restrict__ geo, Conn C, TetDev<T> O, T* __restrict__ fc,
-                                                int64_t E, T gamma, T mu, T pr, T beta, T tau, int riemann,
-                                                int side_mode, RefState<T> R) {
-  const int64_t gtid = xcd_block() * 256 + threadIdx.x;
-  const int64_t wave = gtid >> 6;
-  const int lane = (int)(gtid & 63);
-  const int64_t tile = wave / TET_NFP;
-  const int sg = (int)(wave % TET_NFP);
-  const int64_t e = tile * 64 + lane;
-  if (e >= E) return;
+__device__ __forceinline__ void tet_common_flux(const T* __restrict__ u, const T* __restrict__ grad, const T S[9],
+                                                const Conn& C, const TetDev<T>& O, int64_t E, int64_t e, int sg,
+                                                T gamma, T mu, T pr, T beta, T tau, int riemann, int side_mode,
+                                                const RefState<T>& R, T out[5]) {
   const int face = sg / TET_NFPF, q = sg % TET_NFPF;
-  T S[9], J;
-  tet_geo(geo, E, e, S, J);
   const NbrSlot ns = nbr_slot<TET_NFPF>(C, E, e, face, q);
   const int so = O.src[sg], sn = O.src[ns.fp];
-  T own[5], un[5], nv[3], nL[3], uL[5], uR[5], F[5];
+  T own[5], un[5], nv[3], nL[3], uL[5], uR[5];
   tet_load(u, E, e, so, own);
   tet_load(u, E, ns.elem, sn, un);
   tet_normal(S, O, face, nv);
@@ -133,7 +71,7 @@ __global__ void __launch_bounds__(256) tet_face(const T* __restrict__ u, const T
   for (int k = 0; k < 3; ++k) nL[k] = nv[k] * sl;
 #pragma unroll
   for (int c = 0; c < 5; ++c) { uL[c] = ns.left ? own[c] : un[c]; uR[c] = ns.left ? un[c] : own[c]; }
-  common_inviscid<T, DEV>(riemann, uL, uR, nL, gamma, R, F);
+  common_inviscid<T, DEV>(riemann, uL, uR, nL, gamma, R, out);
   if constexpr (NS) {
     const T wL = T(0.5) - beta, wR = T(0.5) + beta;
     const T w_own = ns.left ? wL : wR, w_nbr = ns.left ? wR : wL;
@@ -147,14 +85,14 @@ __global__ void __launch_bounds__(256) tet_face(const T* __restrict__ u, const T
       for (int k = 0; k < 15; ++k) gk[k] = grad[(gp * 15 + k) * E + ge];
       viscous<T, DEV>(side == 0 ? own : un, gk, nL[0], nL[1], nL[2], gamma, mu, pr, R, fv);
 #pragma unroll
-      for (int c = 0; c < 5; ++c) F[c] -= wgt * fv[c];
+      for (int c = 0; c < 5; ++c) out[c] -= wgt * fv[c];
     }
 #pragma unroll
-    for (int c = 0; c < 5; ++c) F[c] += tau * (uL[c] - uR[c]);
+    for (int c = 0; c < 5; ++c) out[c] += tau * (uL[c] - uR[c]);
   }
   const T fs = ns.left ? mag : -mag;
 #pragma unroll
-  for (int c = 0; c < 5; ++c) fc[((int64_t)sg * 5 + c) * E + e] = fs * F[c];
+  for (int c = 0; c < 5; ++c) out[c] *= fs;
 }
 
 // 16x16x4 matrix-core products: D = A B + C with A 16x4 (lane l: A[l % 16][l / 16]),
@@ -190,28 +128,25 @@ constexpr int TET_KA = 108, TET_KB = 60, TET_KP = TET_KA + TET_KB, TET_MP = 48;
 constexpr int TDIV_NE = 16, TDIV_NT = 5 * 64;
 
 // Corrected divergence (eq:FRfinal) on the matrix cores: per block of 16 elements,
-// R^T = -(1/J) Op P with the panel P = [f~_0; f~_1; f~_2; F^C] (K x 5*16).  The block
-// stages Op once in LDS and loops over a contiguous range of element tiles; for each
-// tile its 5 waves evaluate the fluxes into the panel (two K chunks through LDS),
-// then wave v multiplies the 16 columns of variable v by the three 16-row tiles of Op.
+// R^T = -(1/J) Op P with the panel P = [f~_0; f~_1; f~_2; F^C] (K x 5*16).  A block
+// takes one tile of elements: its 5 waves evaluate the transformed fluxes at the
+// solution points, then the common fluxes at the flux points, into the panel (two K
+// chunks through LDS), and wave v multiplies the 16 columns of variable v by the
+// three 16-row tiles of Op (read through the caches).
 template <typename T, bool DEV, bool NS>
 __global__ void __launch_bounds__(TDIV_NT) tet_div(const T* __restrict__ u, const T* __restrict__ grad,
-                                                   const T* __restrict__ fc, const T* __restrict__ geo,
+                                                   const T* __restrict__ geo, Conn C, TetDev<T> O,
                                                    const T* __restrict__ opT, T* __restrict__ r, int64_t E, int64_t n,
-                                                   T gamma, T mu, T pr, RefState<T> R) {
+                                                   T gamma, T mu, T pr, T beta, T tau, int riemann, int side_mode,
+                                                   RefState<T> R) {
   constexpr int NE = TDIV_NE, NT = TDIV_NT;
-  __shared__ T OP[TET_KP * TET_MP];
   __shared__ T PAN[TET_KA * 5 * NE];     // [k][v][el]; the second K chunk reuses it
   __shared__ T SJ[10 * NE];
   const int t = threadIdx.x;
   const int v = t / 64, lane = t % 64, kr = lane / 16, col = lane % 16;
   const T gm1 = gamma - T(1);
-  for (int i = t; i < TET_KP * TET_MP; i += NT) OP[i] = opT[i];
-  const int64_t ntile = E / NE, b = xcd_block(), nb = gridDim.x;
-  const int64_t tb = b * ntile / nb, te = (b + 1) * ntile / nb;
-  for (int64_t tile = tb; tile < te; ++tile) {
-    const int64_t e0 = tile * NE;
-    __syncthreads();
+  const int64_t e0 = xcd_block() * NE;
+  {
     for (int i = t; i < 10 * NE; i += NT) SJ[i] = geo[(int64_t)(i / NE) * E + e0 + i % NE];
     for (int i = t; i < 3 * 5 * NE; i += NT) PAN[105 * 5 * NE + i] = T(0);
     __syncthreads();
@@ -244,20 +179,30 @@ __global__ void __launch_bounds__(TDIV_NT) tet_div(const T* __restrict__ u, cons
     typename Mma16<T>::V acc[3];
 #pragma unroll
     for (int mt = 0; mt < 3; ++mt) acc[mt] = typename Mma16<T>::V{0, 0, 0, 0};
+#pragma unroll 2
     for (int k0 = 0; k0 < TET_KA; k0 += 4) {
       const T bop = PAN[((k0 + kr) * 5 + v) * NE + col];
 #pragma unroll
-      for (int mt = 0; mt < 3; ++mt) acc[mt] = Mma16<T>::run(OP[(k0 + kr) * TET_MP + mt * 16 + col], bop, acc[mt]);
+      for (int mt = 0; mt < 3; ++mt) acc[mt] = Mma16<T>::run(opT[(k0 + kr) * TET_MP + mt * 16 + col], bop, acc[mt]);
     }
     __syncthreads();
     // K chunk 2: common fluxes at the flux points
-    for (int i = t; i < TET_KB * 5 * NE; i += NT) PAN[i] = fc[(int64_t)(i / NE) * E + e0 + i % NE];
+    for (int it = t; it < NE * TET_NFP; it += NT) {
+      const int el = it % NE, sg = it / NE;
+      T S[9], F[5];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) S[k] = SJ[k * NE + el];
+      tet_common_flux<T, DEV, NS>(u, grad, S, C, O, E, e0 + el, sg, gamma, mu, pr, beta, tau, riemann, side_mode, R, F);
+#pragma unroll
+      for (int c = 0; c < 5; ++c) PAN[(sg * 5 + c) * NE + el] = F[c];
+    }
     __syncthreads();
+#pragma unroll 2
     for (int k0 = 0; k0 < TET_KB; k0 += 4) {
       const T bop = PAN[((k0 + kr) * 5 + v) * NE + col];
 #pragma unroll
       for (int mt = 0; mt < 3; ++mt)
-        acc[mt] = Mma16<T>::run(OP[(TET_KA + k0 + kr) * TET_MP + mt * 16 + col], bop, acc[mt]);
+        acc[mt] = Mma16<T>::run(opT[(TET_KA + k0 + kr) * TET_MP + mt * 16 + col], bop, acc[mt]);
     }
     const int64_t e = e0 + col;
     const T iJ = T(-1) / SJ[9 * NE + col];
@@ -268,6 +213,78 @@ __global__ void __launch_bounds__(TDIV_NT) tet_div(const T* __restrict__ u, cons
         for (int q = 0; q < 4; ++q) {
           const int pt = mt * 16 + Mma16<T>::row(lane, q);
           if (pt < TET_NSP) r[((int64_t)pt * 5 + v) * E + e] = acc[mt][q] * iJ;
+        }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Navier--Stokes gradient on the matrix cores.  Per element and variable the
+// reference gradient is gt_i = Dh_i u + L diag(n~_i) u^ (i = 0, 1, 2): one product of
+// the stacked operator G = [[Dh_0, L n~_0], [Dh_1, L n~_1], [Dh_2, L n~_2]] (3 x 35 rows
+// padded to 3 x 48, K = 35 + 60 padded to 96; stored transposed, ogT[k][48 i + pt])
+// with the panel [u; u^] of a block of 16 elements.  Wave v holds the nine 16x16
+// output tiles of variable v, so the three gt_i of a point meet in one lane, where
+// the physical gradient S^T gt / J is formed and stored.
+constexpr int TGR_K = 96, TGR_M = 3 * TET_MP;
+
+template <typename T>
+__global__ void __launch_bounds__(TDIV_NT) tet_grad_mma(const T* __restrict__ u, const T* __restrict__ geo, Conn C,
+                                                        TetDev<T> O, const T* __restrict__ ogT, T* __restrict__ grad,
+                                                        int64_t E, int64_t n, T beta) {
+  constexpr int NE = TDIV_NE, NT = TDIV_NT;
+  __shared__ T PAN[TGR_K * 5 * NE];      // [k][v][el]: u at the 35 points, u^ at the 60 flux points, 0
+  __shared__ T SJ[10 * NE];
+  const int t = threadIdx.x;
+  const int v = t / 64, lane = t % 64, kr = lane / 16, col = lane % 16;
+  const int64_t e0 = xcd_block() * NE;
+  {
+    for (int i = t; i < 10 * NE; i += NT) SJ[i] = geo[(int64_t)(i / NE) * E + e0 + i % NE];
+    for (int i = t; i < 5 * NE; i += NT) PAN[(TGR_K - 1) * 5 * NE + i] = T(0);
+    for (int i = t; i < TET_NSP * 5 * NE; i += NT) PAN[i] = u[(int64_t)(i / NE) * E + e0 + i % NE];
+    __syncthreads();
+    for (int it = t; it < TET_NFP * NE; it += NT) {
+      const int el = it % NE, sg = it / NE;
+      const int64_t e = e0 + el;
+      const int face = sg / TET_NFPF, q = sg % TET_NFPF;
+      const NbrSlot ns = nbr_slot<TET_NFPF>(C, E, e, face, q);
+      const int so = O.src[sg];
+      T un[5];
+      tet_load(u, E, ns.elem, O.src[ns.fp], un);
+#pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        const T own = PAN[(so * 5 + c) * NE + el];
+        const T uL = ns.left ? own : un[c], uR = ns.left ? un[c] : own;
+        PAN[((TET_NSP + sg) * 5 + c) * NE + el] = T(0.5) * (uL + uR) + beta * (uL - uR);
+      }
+    }
+    __syncthreads();
+    typename Mma16<T>::V acc[9];
+#pragma unroll
+    for (int m = 0; m < 9; ++m) acc[m] = typename Mma16<T>::V{0, 0, 0, 0};
+#pragma unroll 2
+    for (int k0 = 0; k0 < TGR_K; k0 += 4) {
+      const T bop = PAN[((k0 + kr) * 5 + v) * NE + col];
+      const T* arow = ogT + (k0 + kr) * TGR_M + col;
+#pragma unroll
+      for (int m = 0; m < 9; ++m) acc[m] = Mma16<T>::run(arow[m * 16], bop, acc[m]);
+    }
+    const int64_t e = e0 + col;
+    if (e < n) {
+      T S[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) S[k] = SJ[k * NE + col];
+      const T iJ = T(1) / SJ[9 * NE + col];
+#pragma unroll
+      for (int mt = 0; mt < 3; ++mt)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int pt = mt * 16 + Mma16<T>::row(lane, q);
+          if (pt >= TET_NSP) continue;
+          const T g0 = acc[mt][q], g1 = acc[3 + mt][q], g2 = acc[6 + mt][q];
+#pragma unroll
+          for (int j = 0; j < 3; ++j)
+            grad[((int64_t)pt * 15 + v * 3 + j) * E + e] = (S[j] * g0 + S[3 + j] * g1 + S[6 + j] * g2) * iJ;
         }
     }
   }

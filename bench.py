@@ -245,7 +245,7 @@ def run_filter_workload(cfg, args, torch, np, frmi, inputs):
     for k_, r_ in runs.items():
         r_["sol_rel_l2_vs_fp64_plain"] = float(torch.linalg.norm(r_["u"] - ref_u) / torch.linalg.norm(ref_u))
     # filter statistics on stage-like states: one unfiltered step from points of the trajectory
-    probe = {"plain": [0, 0, 0], "mlp": [0, 0, 0]}
+    probe = {"plain": [0, 0, 0, 0], "mlp": [0, 0, 0, 0]}
     k_equal, k_total, filt_ms = 0, 0, {"plain": [], "mlp": []}
     u = u0.clone()
     for i in range(5):
@@ -267,6 +267,7 @@ def run_filter_workload(cfg, args, torch, np, frmi, inputs):
             probe[name][0] += st.n_troubled
             probe[name][1] += st.n_evals
             probe[name][2] += st.n_fallback
+            probe[name][3] += st.n_candidates
             kk[name] = k
         touched = (kk["plain"] != 0) | (kk["mlp"] != 0)
         k_equal += int(((kk["plain"] == kk["mlp"]) & touched).sum())
@@ -298,8 +299,9 @@ def run_filter_workload(cfg, args, torch, np, frmi, inputs):
             "solution_rel_l2_vs_fp64_plain_after_steps": r["sol_rel_l2_vs_fp64_plain"],
             "kernels_ms_per_step": {k: round(v[1] / 2, 4) for k, v in sorted(r["times"].items())}}
     for n in ("plain", "mlp"):
-        tr, ev, fb = probe[n]
-        out["filter"][n] = {"troubled_per_call": tr / 5, "evals_per_troubled": round(ev / max(tr, 1), 3),
+        tr, ev, fb, cand = probe[n]
+        out["filter"][n] = {"troubled_per_call": tr / 5, "candidates_per_call": cand / 5,
+                            "evals_per_troubled": round(ev / max(tr, 1), 3),
                             "fallback_per_call": fb / 5, "filter_call_ms": round(float(np.mean(filt_ms[n])), 4)}
     times = head["times"]
     fam = {k: v for k, v in times.items() if kernel_bytes_per_elem(k, nsp, nfp) is not None}

@@ -69,10 +69,13 @@ typedef struct {
   int32_t riemann;         /* FR_RUSANOV or FR_HLLC (common flux of eq:comm_flux)    */
   int32_t precision;       /* FR_FP64, or FR_FP32: FP32 kernels on deviation
                               variables du = u - u_ref (FP64 RK accumulation)      */
-  int32_t elem_order;      /* native element order: 0 renumbers each type block along
-                              a Morton curve of the element centroids (neighbours
-                              share tiles and cache lines), 1 keeps the input order.
-                              Canonical arrays always follow the input order.       */
+  int32_t elem_order;      /* native element order of each type block: 1 keeps the
+                              input order, 2 renumbers along a Morton curve of the
+                              element centroids (face neighbours share tiles and
+                              cache lines), 0 (default) takes whichever of the two
+                              spreads the face neighbours of a 64-element tile over
+                              fewer tiles.  Canonical arrays always follow the input
+                              order.                                                 */
   double gamma;            /* ratio of specific heats                                */
   double mu;               /* constant dynamic viscosity (Navier--Stokes)           */
   double prandtl;          /* Prandtl number                                         */
@@ -107,6 +110,7 @@ typedef struct {
   int64_t n_fallback;      /* elements filtered at zeta_max because no k satisfied   */
   int64_t n_evals;         /* constraint evaluations over troubled elements          */
   double  seconds;         /* device time of the call                                */
+  int64_t n_candidates;    /* elements the detection passed to the exact search      */
 } fr_filter_stats;
 
 /* Fill p with defaults: Euler, order 3, Rusanov, FP64, gamma 1.4, mu 1/1600,

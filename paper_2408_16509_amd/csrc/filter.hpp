@@ -15,7 +15,7 @@
 //              starting bracket by [floor(k^/2), ceil(2 k^)] and the search continues in
 //              whichever bracket keeps that invariant.
 //
-// One 64-lane block per element.  A constraint evaluation at strength zeta is three
+// One 256-lane block per element.  A constraint evaluation at strength zeta is three
 // 1-D passes through LDS with the filtered evaluation matrix
 //     W[r][m] = P~_m(x_r) exp(-zeta m^2 / p^2),   r = nodes 0..p, then xi = -1, +1,
 // so a check point (r1, r2, r3) with at most one end row covers both solution and
@@ -27,6 +27,8 @@
 #include "hex.hpp"
 
 namespace frmi {
+
+constexpr int FNT = 256;   // threads of the per-element filter blocks
 
 struct FiltK {
   double Vm[5][5];    // P~_m(x_a) (rows nodes, cols modes)
@@ -51,48 +53,67 @@ __device__ __forceinline__ bool admissible(const double w[5], double smin, const
   return rho >= F.eps_rho && p >= F.eps_p && s >= smin - F.eps_s * fabs(smin);
 }
 
-// Minimum entropy of each element over its check points (thread per element).
+// Doubles as unsigned integers with the same order (for an atomic minimum).
+__device__ __forceinline__ unsigned long long ord_bits(double x) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  return (b >> 63) ? ~b : (b | 0x8000000000000000ULL);
+}
+__device__ __forceinline__ double ord_val(unsigned long long o) {
+  return __longlong_as_double((long long)((o >> 63) ? (o & 0x7FFFFFFFFFFFFFFFULL) : ~o));
+}
+
+__global__ void k_fill_u64(unsigned long long* __restrict__ a, int64_t n, unsigned long long v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    a[i] = v;
+}
+
+// Minimum entropy of each element over its check points: one wave per (tile of 64
+// elements, line), as the detection; the solution points are taken on the lines
+// along xi_1, the flux points at every line's ends; NaN values are ignored (as fmin
+// does).  sown holds the minimum in ord_bits form and must start at ord_bits(+inf).
 template <int P>
-__global__ void __launch_bounds__(256) hex_sown(const double* __restrict__ u, double* __restrict__ sown, int64_t E,
-                                                int64_t n, FiltK K, double gamma) {
-  constexpr int N1 = P + 1, NSP = N1 * N1 * N1;
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+__global__ void __launch_bounds__(256) hex_sown(const double* __restrict__ u, unsigned long long* __restrict__ sown,
+                                                int64_t E, int64_t n, FiltK K, double gamma) {
+  constexpr int N1 = P + 1, NL = 3 * N1 * N1;
+  const int64_t gtid = xcd_block() * 256 + threadIdx.x;
+  const int64_t wave = gtid >> 6;
+  const int lane = (int)(gtid & 63);
+  const int64_t tile = wave / NL;
+  const int l = (int)(wave % NL);
+  const int64_t e = tile * 64 + lane;
   if (e >= n) return;
+  const int d = l / (N1 * N1), q = l % (N1 * N1), t0 = q % N1, t1 = q / N1;
+  double m[5] = {0, 0, 0, 0, 0}, pl[5] = {0, 0, 0, 0, 0};
   double smin = INFINITY;
-  for (int pt = 0; pt < NSP; ++pt) {
+#pragma unroll
+  for (int a = 0; a < N1; ++a) {
+    const int pt = line_pt<N1>(d, a, t0, t1);
     double w[5];
 #pragma unroll
-    for (int v = 0; v < 5; ++v) w[v] = u[((int64_t)pt * 5 + v) * E + e];
-    const double p = (gamma - 1.0) * (w[4] - 0.5 * (w[1] * w[1] + w[2] * w[2] + w[3] * w[3]) / w[0]);
-    smin = fmin(smin, entropy_of(w[0], p, gamma));
-  }
-  for (int d = 0; d < 3; ++d)
-    for (int q = 0; q < N1 * N1; ++q) {
-      const int t0 = q % N1, t1 = q / N1;
-      double m[5] = {0, 0, 0, 0, 0}, pl[5] = {0, 0, 0, 0, 0};
-      for (int a = 0; a < N1; ++a) {
-        const int pt = d == 0 ? a + N1 * (t0 + N1 * t1) : (d == 1 ? t0 + N1 * (a + N1 * t1) : t0 + N1 * (t1 + N1 * a));
-#pragma unroll
-        for (int v = 0; v < 5; ++v) {
-          const double val = u[((int64_t)pt * 5 + v) * E + e];
-          m[v] += K.lm[a] * val;
-          pl[v] += K.lp[a] * val;
-        }
-      }
-      const double pm = (gamma - 1.0) * (m[4] - 0.5 * (m[1] * m[1] + m[2] * m[2] + m[3] * m[3]) / m[0]);
-      const double pp = (gamma - 1.0) * (pl[4] - 0.5 * (pl[1] * pl[1] + pl[2] * pl[2] + pl[3] * pl[3]) / pl[0]);
-      smin = fmin(smin, fmin(entropy_of(m[0], pm, gamma), entropy_of(pl[0], pp, gamma)));
+    for (int v = 0; v < 5; ++v) {
+      w[v] = u[((int64_t)pt * 5 + v) * E + e];
+      m[v] += K.lm[a] * w[v];
+      pl[v] += K.lp[a] * w[v];
     }
-  sown[e] = smin;
+    if (d == 0) {
+      const double p = (gamma - 1.0) * (w[4] - 0.5 * (w[1] * w[1] + w[2] * w[2] + w[3] * w[3]) / w[0]);
+      smin = fmin(smin, entropy_of(w[0], p, gamma));
+    }
+  }
+  const double pm = (gamma - 1.0) * (m[4] - 0.5 * (m[1] * m[1] + m[2] * m[2] + m[3] * m[3]) / m[0]);
+  const double pp = (gamma - 1.0) * (pl[4] - 0.5 * (pl[1] * pl[1] + pl[2] * pl[2] + pl[3] * pl[3]) / pl[0]);
+  smin = fmin(smin, fmin(entropy_of(m[0], pm, gamma), entropy_of(pl[0], pp, gamma)));
+  if (!isnan(smin)) atomicMin(sown + e, ord_bits(smin));
 }
 
 // s_min over the element and its face neighbours.
-__global__ void __launch_bounds__(256) elem_smin(const double* __restrict__ sown, const int32_t* __restrict__ nbr_elem,
-                                                 int nfaces, double* __restrict__ smin, int64_t E, int64_t n) {
+__global__ void __launch_bounds__(256) elem_smin(const unsigned long long* __restrict__ sown,
+                                                 const int32_t* __restrict__ nbr_elem, int nfaces,
+                                                 double* __restrict__ smin, int64_t E, int64_t n) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= n) return;
-  double s = sown[e];
-  for (int f = 0; f < nfaces; ++f) s = fmin(s, sown[nbr_elem[(int64_t)f * E + e]]);
+  double s = ord_val(sown[e]);
+  for (int f = 0; f < nfaces; ++f) s = fmin(s, ord_val(sown[nbr_elem[(int64_t)f * E + e]]));
   smin[e] = s;
 }
 
@@ -115,7 +136,7 @@ __device__ bool hex_eval_checks(HexFiltSmem<P>& S, double smin, const FiltPrm& F
   constexpr int N1 = P + 1, NR = N1 + 2, NSP = N1 * N1 * N1, NFP = 6 * N1 * N1;
   const int t = threadIdx.x;
   // pass over k: T1[v][i + N1 j][r3]
-  for (int o = t; o < 5 * N1 * N1 * NR; o += 64) {
+  for (int o = t; o < 5 * N1 * N1 * NR; o += FNT) {
     const int v = o / (N1 * N1 * NR), rem = o % (N1 * N1 * NR), ij = rem / NR, r3 = rem % NR;
     double acc = 0;
 #pragma unroll
@@ -124,7 +145,7 @@ __device__ bool hex_eval_checks(HexFiltSmem<P>& S, double smin, const FiltPrm& F
   }
   __syncthreads();
   // pass over j: T2[v][i][r2][r3]
-  for (int o = t; o < 5 * N1 * NR * NR; o += 64) {
+  for (int o = t; o < 5 * N1 * NR * NR; o += FNT) {
     const int v = o / (N1 * NR * NR), rem = o % (N1 * NR * NR);
     const int i = rem / (NR * NR), r2 = (rem / NR) % NR, r3 = rem % NR;
     double acc = 0;
@@ -135,7 +156,7 @@ __device__ bool hex_eval_checks(HexFiltSmem<P>& S, double smin, const FiltPrm& F
   __syncthreads();
   // pass over i at every check point
   bool ok = true;
-  for (int c = t; c < NSP + NFP; c += 64) {
+  for (int c = t; c < NSP + NFP; c += FNT) {
     int r1, r2, r3;
     if (c < NSP) {
       r1 = c % N1; r2 = (c / N1) % N1; r3 = c / (N1 * N1);
@@ -182,7 +203,7 @@ template <int P>
 __device__ void hex_to_modal(double* X, double* Y, double* out, int nv, const FiltK& K) {
   constexpr int N1 = P + 1, NSP = N1 * N1 * N1;
   const int t = threadIdx.x;
-  for (int o = t; o < nv * NSP; o += 64) {
+  for (int o = t; o < nv * NSP; o += FNT) {
     const int v = o / NSP, pt = o % NSP, ij = pt % (N1 * N1), m = pt / (N1 * N1);
     double acc = 0;
 #pragma unroll
@@ -190,7 +211,7 @@ __device__ void hex_to_modal(double* X, double* Y, double* out, int nv, const Fi
     Y[o] = acc;
   }
   __syncthreads();
-  for (int o = t; o < nv * NSP; o += 64) {
+  for (int o = t; o < nv * NSP; o += FNT) {
     const int v = o / NSP, pt = o % NSP, i = pt % N1, m = (pt / N1) % N1, kk = pt / (N1 * N1);
     double acc = 0;
 #pragma unroll
@@ -198,7 +219,7 @@ __device__ void hex_to_modal(double* X, double* Y, double* out, int nv, const Fi
     X[o] = acc;
   }
   __syncthreads();
-  for (int o = t; o < nv * NSP; o += 64) {
+  for (int o = t; o < nv * NSP; o += FNT) {
     const int v = o / NSP, pt = o % NSP, m = pt % N1, rest = pt / N1;
     double acc = 0;
 #pragma unroll
@@ -214,7 +235,7 @@ __device__ void hex_load_modal(HexFiltSmem<P>& S, const double* __restrict__ u, 
   constexpr int N1 = P + 1, NSP = N1 * N1 * N1;
   double* X = &S.T1[0][0];
   double* Y = &S.T2[0][0];
-  for (int o = threadIdx.x; o < 5 * NSP; o += 64) {
+  for (int o = threadIdx.x; o < 5 * NSP; o += FNT) {
     const int v = o / NSP, pt = o % NSP;
     X[o] = u[((int64_t)pt * 5 + v) * E + e];
   }
@@ -222,18 +243,22 @@ __device__ void hex_load_modal(HexFiltSmem<P>& S, const double* __restrict__ u, 
   hex_to_modal<P>(X, Y, &S.U[0][0], 5, K);
 }
 
-// One element on a 64-lane block: exact check at zeta = 0, search (mode 0 plain,
-// 1 warm start from khat[e]) and application of the filter.
+// One element on a block: exact check at zeta = 0, search (mode 0 plain,
+// 1 warm start from the predicted index kh) and application of the filter.  With
+// `preloaded` the modal coefficients are already in S.U and the check at zeta = 0
+// has failed (the learned path, whose feature pass did both).
 template <int P>
 __device__ void hex_filter_elem(HexFiltSmem<P>& S, double* __restrict__ u, const double* __restrict__ smin_a,
-                                int64_t E, int64_t e, const FiltK& K, const FiltPrm& F, int mode,
-                                const float* __restrict__ khat, int32_t* __restrict__ k_out,
-                                int32_t* __restrict__ evals_out) {
+                                int64_t E, int64_t e, const FiltK& K, const FiltPrm& F, int mode, float kh_in,
+                                bool preloaded, int32_t* __restrict__ k_out, int32_t* __restrict__ evals_out) {
   const int t = threadIdx.x;
   const double smin = smin_a[e];
-  hex_load_modal<P>(S, u, E, e, K);
-  hex_set_w<P>(S, K, 0.0);
-  const bool ok0 = hex_eval_checks<P>(S, smin, F, nullptr, E, e);
+  bool ok0 = false;
+  if (!preloaded) {
+    hex_load_modal<P>(S, u, E, e, K);
+    hex_set_w<P>(S, K, 0.0);
+    ok0 = hex_eval_checks<P>(S, smin, F, nullptr, E, e);
+  }
   int evals = 1;
   if (ok0) {
     if (t == 0) {
@@ -252,7 +277,7 @@ __device__ void hex_filter_elem(HexFiltSmem<P>& S, double* __restrict__ u, const
   int64_t lo = 0, hi = N;
   bool fallback = false;
   if (mode == 1) {
-    double kh = (double)khat[e];
+    double kh = (double)kh_in;
     kh = fmin(fmax(kh, 1.0), (double)N);
     const int64_t blo = (int64_t)floor(kh / 2), bhi = min((int64_t)ceil(2 * kh), N);
     const bool g_hi = G(bhi);
@@ -286,14 +311,15 @@ __device__ void hex_filter_elem(HexFiltSmem<P>& S, double* __restrict__ u, const
 
 // The candidates list[0 .. *count) (from the detection), one block looping over them.
 template <int P>
-__global__ void __launch_bounds__(64) hex_filter(double* __restrict__ u, const double* __restrict__ smin_a, int64_t E,
+__global__ void __launch_bounds__(FNT) hex_filter(double* __restrict__ u, const double* __restrict__ smin_a, int64_t E,
                                                  const int32_t* __restrict__ list, const int32_t* __restrict__ count,
                                                  FiltK K, FiltPrm F, int mode, const float* __restrict__ khat,
                                                  int32_t* __restrict__ k_out, int32_t* __restrict__ evals_out) {
   __shared__ HexFiltSmem<P> S;
   const int32_t m = *count;
   for (int32_t i = blockIdx.x; i < m; i += gridDim.x) {
-    hex_filter_elem<P>(S, u, smin_a, E, list[i], K, F, mode, khat, k_out, evals_out);
+    const int32_t e = list[i];
+    hex_filter_elem<P>(S, u, smin_a, E, e, K, F, mode, khat ? khat[e] : 0.0f, false, k_out, evals_out);
     __syncthreads();
   }
 }
@@ -306,7 +332,9 @@ __global__ void __launch_bounds__(64) hex_filter(double* __restrict__ u, const d
 // |m|^2 (far above the rounding of either evaluation), so every element the exact
 // check of the search rejects is flagged; the search re-checks and leaves false
 // positives untouched.  flag must be cleared before.
-__device__ __forceinline__ bool maybe_violates(const double w[5], double sbound, const FiltPrm& F) {
+// lsb = log(bound + dl |bound|) of the entropy bound, or -inf when that is <= 0
+// (then any state with positive density and pressure passes the entropy check).
+__device__ __forceinline__ bool maybe_violates(const double w[5], double lsb, const FiltPrm& F) {
   constexpr double dl = 1e-10;
   const double rho = w[0];
   const double rlo = rho - dl * fabs(rho), rhi = rho + dl * fabs(rho);
@@ -314,8 +342,7 @@ __device__ __forceinline__ bool maybe_violates(const double w[5], double sbound,
   const double m2 = (w[1] * w[1] + w[2] * w[2] + w[3] * w[3]) * (1.0 + dl);
   const double plo = (F.gamma - 1.0) * (w[4] - dl * fabs(w[4]) - 0.5 * m2 / rlo);
   if (!(plo >= F.eps_p)) return true;
-  const double slo = plo * pow(rhi, -F.gamma);
-  return !(slo >= sbound + dl * fabs(sbound));
+  return !(log(plo) - F.gamma * log(rhi) >= lsb);
 }
 
 template <int P>
@@ -333,6 +360,8 @@ __global__ void __launch_bounds__(256) hex_filter_detect(const double* __restric
   const int d = l / (N1 * N1), q = l % (N1 * N1), t0 = q % N1, t1 = q / N1;
   const double smin = smin_a[e];
   const double sb = smin - F.eps_s * fabs(smin);
+  const double sbm = sb + 1e-10 * fabs(sb);
+  const double lsb = sbm > 0 ? log(sbm) : -INFINITY;
   double m[5] = {0, 0, 0, 0, 0}, pl[5] = {0, 0, 0, 0, 0};
   bool bad = false;
 #pragma unroll
@@ -345,15 +374,25 @@ __global__ void __launch_bounds__(256) hex_filter_detect(const double* __restric
       m[v] += K.lm[a] * w[v];
       pl[v] += K.lp[a] * w[v];
     }
-    if (d == 0) bad = bad || maybe_violates(w, sb, F);
+    if (d == 0) bad = bad || maybe_violates(w, lsb, F);
   }
-  bad = bad || maybe_violates(m, sb, F) || maybe_violates(pl, sb, F);
+  bad = bad || maybe_violates(m, lsb, F) || maybe_violates(pl, lsb, F);
   if (bad) flag[e] = 1;
 }
 
 __global__ void k_fill_i32(int32_t* __restrict__ a, int64_t n, int32_t v) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     a[i] = v;
+}
+
+// Reset of a filter call: no candidates flagged, k = 0 and one evaluation everywhere.
+__global__ void k_filter_reset(int32_t* __restrict__ det, int32_t* __restrict__ k, int32_t* __restrict__ evals,
+                               int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    det[i] = 0;
+    k[i] = 0;
+    evals[i] = 1;
+  }
 }
 
 // Ordered compaction of the flagged elements into a list: per-256 counts, one
@@ -402,11 +441,11 @@ __global__ void __launch_bounds__(256) k_flag_scatter(const int32_t* __restrict_
   if (f) list[base + __popcll(mask & ((1ull << lane) - 1ull))] = (int32_t)e;
 }
 
-// Block reductions over 64 lanes through LDS.
-__device__ __forceinline__ double block_min64(double v, double* red) {
+// Block reductions over the FNT lanes of a filter block through LDS (red[FNT]).
+__device__ __forceinline__ double block_min(double v, double* red) {
   red[threadIdx.x] = v;
   __syncthreads();
-  for (int s = 32; s > 0; s >>= 1) {
+  for (int s = FNT / 2; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + s]);
     __syncthreads();
   }
@@ -414,11 +453,11 @@ __device__ __forceinline__ double block_min64(double v, double* red) {
   __syncthreads();
   return r;
 }
-__device__ __forceinline__ double block_max64(double v, double* red) { return -block_min64(-v, red); }
-__device__ __forceinline__ double block_sum64(double v, double* red) {
+__device__ __forceinline__ double block_max(double v, double* red) { return -block_min(-v, red); }
+__device__ __forceinline__ double block_sum(double v, double* red) {
   red[threadIdx.x] = v;
   __syncthreads();
-  for (int s = 32; s > 0; s >>= 1) {
+  for (int s = FNT / 2; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
     __syncthreads();
   }
@@ -437,10 +476,13 @@ __device__ __forceinline__ double block_sum64(double v, double* red) {
 //   13    max |rho - rho_mean| / rho_mean
 //   14    log10(s_mean / s_min)         15  |v_mean| / c_mean
 // (mean = element mean state; its pressure, entropy and sound speed.)
+// Returns (block-uniformly) whether the element fails the checks at zeta = 0; the
+// features go to feat[e] and/or xs (LDS), the flag to flag[e] (each may be null).
 template <int P>
-__device__ void hex_features_elem(HexFiltSmem<P>& S, double* red, double* PM, const double* __restrict__ u,
+__device__ bool hex_features_elem(HexFiltSmem<P>& S, double* red, double* PM, const double* __restrict__ u,
                                   const double* __restrict__ smin_a, int64_t E, int64_t e, const FiltK& K,
-                                  const FiltPrm& F, int32_t* __restrict__ flag, float* __restrict__ feat) {
+                                  const FiltPrm& F, int32_t* __restrict__ flag, float* __restrict__ feat,
+                                  float* xs) {
   constexpr int N1 = P + 1, NR = N1 + 2, NSP = N1 * N1 * N1, NFP = 6 * N1 * N1;
   const int t = threadIdx.x;
   const double smin = smin_a[e];
@@ -449,8 +491,8 @@ __device__ void hex_features_elem(HexFiltSmem<P>& S, double* red, double* PM, co
   hex_set_w<P>(S, K, 0.0);
   const bool ok0 = hex_eval_checks<P>(S, smin, F, nullptr, E, e);
   if (ok0) {
-    if (t == 0) flag[e] = 0;
-    return;
+    if (t == 0 && flag) flag[e] = 0;
+    return false;
   }
   // mean state from the (0,0,0) mode: mean = u^_000 P~_0^3 = u^_000 / (2 sqrt 2)
   const double c0 = 1.0 / (2.0 * sqrt(2.0));
@@ -463,7 +505,7 @@ __device__ void hex_features_elem(HexFiltSmem<P>& S, double* red, double* PM, co
   const double sb = pbc * pow(rb, -g);
   // check-point statistics at zeta = 0 (T2 holds the passes of the last evaluation)
   double mrho = INFINITY, mp = INFINITY, ms = INFINITY, mdr = 0, nbad = 0;
-  for (int c = t; c < NSP + NFP; c += 64) {
+  for (int c = t; c < NSP + NFP; c += FNT) {
     int r1, r2, r3;
     if (c < NSP) {
       r1 = c % N1; r2 = (c / N1) % N1; r3 = c / (N1 * N1);
@@ -492,15 +534,15 @@ __device__ void hex_features_elem(HexFiltSmem<P>& S, double* red, double* PM, co
     nbad += admissible(w, smin, F) ? 0.0 : 1.0;
     if (c < NSP) PM[c] = p;
   }
-  mrho = block_min64(mrho, red);
-  mp = block_min64(mp, red);
-  ms = block_min64(ms, red);
-  mdr = block_max64(mdr, red);
-  nbad = block_sum64(nbad, red);
+  mrho = block_min(mrho, red);
+  mp = block_min(mp, red);
+  ms = block_min(ms, red);
+  mdr = block_max(mdr, red);
+  nbad = block_sum(nbad, red);
   // modal coefficients of the nodal pressure
   double* X = &S.T1[0][0];
   double* Y = &S.T2[0][0];
-  for (int o = t; o < NSP; o += 64) X[o] = PM[o];
+  for (int o = t; o < NSP; o += FNT) X[o] = PM[o];
   __syncthreads();
   hex_to_modal<P>(X, Y, PM, 1, K);
   // shell energies of rho (U[0]), E (U[4]), p (PM)
@@ -508,16 +550,16 @@ __device__ void hex_features_elem(HexFiltSmem<P>& S, double* red, double* PM, co
   for (int fi = 0; fi < 3; ++fi) {
     const double* c = fi == 0 ? S.U[0] : (fi == 1 ? S.U[4] : PM);
     double sh[3] = {0, 0, 0};
-    for (int m = t; m < NSP; m += 64) {
+    for (int m = t; m < NSP; m += FNT) {
       const int i = m % N1, j = (m / N1) % N1, k = m / (N1 * N1);
       const int shell = max(i, max(j, k));
       if (shell >= 1) sh[min(shell, 3) - 1] += c[m] * c[m];
     }
     const double e0 = c[0] * c[0] + 1e-300;
-    for (int q = 0; q < 3; ++q) en[fi][q] = block_sum64(sh[q], red) / e0;
+    for (int q = 0; q < 3; ++q) en[fi][q] = block_sum(sh[q], red) / e0;
   }
   if (t == 0) {
-    float* x = feat + e * 16;
+    float x[16];
     for (int fi = 0; fi < 3; ++fi)
       for (int q = 0; q < 3; ++q) x[3 * fi + q] = (float)log10(fmax(en[fi][q], 1e-30));
     x[9] = (float)(mrho / rb - 1.0);
@@ -527,23 +569,71 @@ __device__ void hex_features_elem(HexFiltSmem<P>& S, double* red, double* PM, co
     x[13] = (float)(mdr / rb);
     x[14] = (float)log10(fmax(sb / fmax(smin, 1e-300), 1e-30));
     x[15] = (float)(sqrt(vx * vx + vy * vy + vz * vz) / cb);
-    flag[e] = 1;
+    for (int k = 0; k < 16; ++k) {
+      if (feat) feat[e * 16 + k] = x[k];
+      if (xs) xs[k] = x[k];
+    }
+    if (flag) flag[e] = 1;
   }
+  return true;
 }
 
 // Features of the candidates list[0 .. *count), one block looping over them.
 template <int P>
-__global__ void __launch_bounds__(64) hex_features(const double* __restrict__ u, const double* __restrict__ smin_a,
+__global__ void __launch_bounds__(FNT) hex_features(const double* __restrict__ u, const double* __restrict__ smin_a,
                                                    int64_t E, const int32_t* __restrict__ list,
                                                    const int32_t* __restrict__ count, FiltK K, FiltPrm F,
                                                    int32_t* __restrict__ flag, float* __restrict__ feat) {
   constexpr int N1 = P + 1, NSP = N1 * N1 * N1;
   __shared__ HexFiltSmem<P> S;
-  __shared__ double red[64];
+  __shared__ double red[FNT];
   __shared__ double PM[NSP];
   const int32_t m = *count;
   for (int32_t i = blockIdx.x; i < m; i += gridDim.x) {
-    hex_features_elem<P>(S, red, PM, u, smin_a, E, list[i], K, F, flag, feat);
+    (void)hex_features_elem<P>(S, red, PM, u, smin_a, E, list[i], K, F, flag, feat, nullptr);
+    __syncthreads();
+  }
+}
+
+// The learned warm start in one pass per candidate: the feature pass (which also
+// loads the modal coefficients and checks zeta = 0), the MLP forward (lane j holds
+// hidden unit j of both layers, lanes 0..63; the flat weights W1[64][16] b1 W2[64][64] b2 w3 b3
+// and the input scaling [mean; std] are read through the caches), then the search
+// bracketed around the predicted index 2^(n y).
+template <int P>
+__global__ void __launch_bounds__(FNT, 4) hex_filter_learned(double* __restrict__ u, const double* __restrict__ smin_a,
+                                                         int64_t E, const int32_t* __restrict__ list,
+                                                         const int32_t* __restrict__ count, FiltK K, FiltPrm F,
+                                                         const float* __restrict__ w, const float* __restrict__ scale,
+                                                         int32_t* __restrict__ k_out, int32_t* __restrict__ evals_out) {
+  constexpr int N1 = P + 1, NSP = N1 * N1 * N1;
+  __shared__ HexFiltSmem<P> S;
+  __shared__ double red[FNT];
+  __shared__ double PM[NSP];
+  __shared__ float xs[16], h1[64];
+  const int t = threadIdx.x;
+  const int32_t m = *count;
+  for (int32_t i = blockIdx.x; i < m; i += gridDim.x) {
+    const int32_t e = list[i];
+    const bool troubled = hex_features_elem<P>(S, red, PM, u, smin_a, E, e, K, F, nullptr, nullptr, xs);
+    __syncthreads();
+    if (!troubled) continue;
+    if (t < 64) {
+      float a = w[64 * 16 + t];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) a += w[t * 16 + k] * ((xs[k] - scale[k]) / scale[16 + k]);
+      h1[t] = tanhf(a);
+    }
+    __syncthreads();
+    double contrib = 0.0;
+    if (t < 64) {
+      float b = w[64 * 16 + 64 + 64 * 64 + t];
+      for (int k = 0; k < 64; ++k) b += w[64 * 16 + 64 + t * 64 + k] * h1[k];
+      contrib = (double)(w[64 * 16 + 64 + 64 * 64 + 64 + t] * tanhf(b));
+    }
+    const double y = block_sum(contrib, red) + (double)w[64 * 16 + 64 + 64 * 64 + 64 + 64];
+    const float kh = exp2f((float)F.n_bits * (float)y);
+    hex_filter_elem<P>(S, u, smin_a, E, e, K, F, 1, kh, true, k_out, evals_out);
     __syncthreads();
   }
 }

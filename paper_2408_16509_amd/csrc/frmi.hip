@@ -487,10 +487,15 @@ fr_status filter_alloc(fr_ctx c) {
 template <int P>
 void hex_smin_p(fr_ctx c, DevBlock& b, const double* uprev) {
   const FiltK K = filtk_of(c->host.hex);
+  constexpr int N1 = P + 1;
   const int g = (int)((b.n + 255) / 256);
+  const int64_t threads = b.E * 3 * N1 * N1;
+  unsigned long long* sown = (unsigned long long*)b.sown;
   int pk = c->prof_begin("filter_smin");
-  hex_sown<P><<<g, 256, 0, c->stream>>>(uprev + b.native_off, b.sown, b.E, b.n, K, c->prm.gamma);
-  elem_smin<<<g, 256, 0, c->stream>>>(b.sown, b.nbr_elem, b.nfaces, b.smin, b.E, b.n);
+  k_fill_u64<<<grid_for(b.n, 256), 256, 0, c->stream>>>(sown, b.n, 0xFFF0000000000000ULL);   // ord_bits(+inf)
+  hex_sown<P><<<(unsigned)((threads + 255) / 256), 256, 0, c->stream>>>(uprev + b.native_off, sown, b.E, b.n, K,
+                                                                          c->prm.gamma);
+  elem_smin<<<g, 256, 0, c->stream>>>(sown, b.nbr_elem, b.nfaces, b.smin, b.E, b.n);
   c->prof_end(pk);
 }
 
@@ -505,9 +510,7 @@ void hex_candidates_p(fr_ctx c, DevBlock& b, const double* u) {
   const int nb = (int)((b.n + 255) / 256);
   const int gf = grid_for(b.n, 256);
   int pk = c->prof_begin("filter_detect");
-  k_fill_i32<<<gf, 256, 0, c->stream>>>(b.f_det, b.n, 0);
-  k_fill_i32<<<gf, 256, 0, c->stream>>>(c->f_k + o, b.n, 0);
-  k_fill_i32<<<gf, 256, 0, c->stream>>>(c->f_evals + o, b.n, 1);
+  k_filter_reset<<<gf, 256, 0, c->stream>>>(b.f_det, c->f_k + o, c->f_evals + o, b.n);
   const int64_t threads = b.E * 3 * N1 * N1;
   hex_filter_detect<P><<<(unsigned)((threads + 255) / 256), 256, 0, c->stream>>>(u + b.native_off, b.smin, b.E, b.n,
                                                                                   K, F, b.f_det);
@@ -527,7 +530,7 @@ void hex_features_p(fr_ctx c, DevBlock& b, const double* u) {
   const int64_t o = b.elem_off;
   const int nb = (int)((b.n + 255) / 256);
   k_fill_i32<<<grid_for(b.n, 256), 256, 0, c->stream>>>(c->f_flag + o, b.n, 0);
-  hex_features<P><<<list_grid(b), 64, 0, c->stream>>>(u + b.native_off, b.smin, b.E, b.f_list, b.f_cnt + nb, K, F,
+  hex_features<P><<<list_grid(b), FNT, 0, c->stream>>>(u + b.native_off, b.smin, b.E, b.f_list, b.f_cnt + nb, K, F,
                                                        c->f_flag + o, c->f_feat + o * 16);
 }
 
@@ -540,15 +543,14 @@ void hex_filter_p(fr_ctx c, DevBlock& b, double* u, int mode) {
   hex_candidates_p<P>(c, b, u);
   int pk;
   if (mode == 1) {
-    pk = c->prof_begin("filter_features_mlp");
-    hex_features_p<P>(c, b, u);
-    mlp_forward_list<<<(unsigned)std::min<int64_t>((b.n + 255) / 256, 256), 256, 0, c->stream>>>(
-        c->m_w, c->m_scale, c->f_feat + o * 16, c->f_flag + o, b.f_list, b.f_cnt + nb, F.n_bits, c->f_khat + o);
-    c->prof_end(pk);
+    pk = c->prof_begin("filter_search_learned");
+    hex_filter_learned<P><<<list_grid(b), FNT, 0, c->stream>>>(u + b.native_off, b.smin, b.E, b.f_list, b.f_cnt + nb,
+                                                              K, F, c->m_w, c->m_scale, c->f_k + o, c->f_evals + o);
+  } else {
+    pk = c->prof_begin("filter_search_plain");
+    hex_filter<P><<<list_grid(b), FNT, 0, c->stream>>>(u + b.native_off, b.smin, b.E, b.f_list, b.f_cnt + nb, K, F,
+                                                       0, nullptr, c->f_k + o, c->f_evals + o);
   }
-  pk = c->prof_begin(mode == 1 ? "filter_search_warm" : "filter_search_plain");
-  hex_filter<P><<<list_grid(b), 64, 0, c->stream>>>(u + b.native_off, b.smin, b.E, b.f_list, b.f_cnt + nb, K, F, mode,
-                                                     c->f_khat + o, c->f_k + o, c->f_evals + o);
   c->prof_end(pk);
 }
 
@@ -732,7 +734,7 @@ fr_status fr_setup_mesh(const fr_params* p, int64_t n_vert, const double* xyz, c
     return fail(nullptr, FR_ERR_ARG, "the FP32 form needs a reference state at rest with rho > 0, E > 0");
   if (!(p->gamma > 1.0)) return fail(nullptr, FR_ERR_ARG, "gamma must exceed 1");
   if (p->filt_bits < 1 || p->filt_bits > 30) return fail(nullptr, FR_ERR_ARG, "filt_bits must be in 1..30");
-  if (p->elem_order != 0 && p->elem_order != 1) return fail(nullptr, FR_ERR_ARG, "elem_order must be 0 or 1");
+  if (p->elem_order < 0 || p->elem_order > 2) return fail(nullptr, FR_ERR_ARG, "elem_order must be 0, 1 or 2");
   fr_ctx c = new (std::nothrow) fr_ctx_s();
   if (!c) return fail(nullptr, FR_ERR_ALLOC, "context allocation");
   c->prm = *p;
@@ -1151,6 +1153,11 @@ fr_status fr_filter(fr_ctx c, void* u_, const void* uprev_, int32_t mode, int32_
       if (k[i] < 0) stats->n_fallback++;
     }
     stats->seconds = ms * 1e-3;
+    for (auto& b : c->blocks) {
+      int32_t m = 0;
+      HIP_TRY(c, hipMemcpy(&m, b.f_cnt + (b.n + 255) / 256, 4, hipMemcpyDeviceToHost));
+      stats->n_candidates += m;
+    }
   }
   return FR_OK;
 }

@@ -126,6 +126,7 @@ static const double kTetPts[35][3] = {
 // reference corners and faces (corner triples), outward unit normals
 static const double kTetCorner[4][3] = {{-1, -1, -1}, {1, -1, -1}, {-1, -1, 1}, {-1, 1, -1}};
 static const int kTetFace[4][3] = {{0, 1, 3}, {0, 1, 2}, {0, 2, 3}, {1, 2, 3}};
+static const int kHexFaceCorners[6][4] = {{0, 3, 4, 7}, {1, 2, 5, 6}, {0, 1, 4, 5}, {2, 3, 6, 7}, {0, 1, 2, 3}, {4, 5, 6, 7}};
 
 static ld factorial(int n) { ld r = 1; for (int i = 2; i <= n; ++i) r *= i; return r; }
 
@@ -402,6 +403,43 @@ static uint64_t spread3(uint64_t v) {
   return v;
 }
 
+// Locality of a native order: over the 64-element tiles, the number of distinct tiles
+// that hold the face neighbours of a tile's elements (faces matched by their corner
+// ids; periodic pairs, whose corners are distinct images, are left out).
+static int64_t tile_spread(const Block& b, int nc, const int64_t* enodes) {
+  const int nf = nc == 8 ? 6 : 4, nfc = nc == 8 ? 4 : 3;
+  std::unordered_map<Key, std::array<int64_t, 2>, KeyHash> faces;
+  faces.reserve((size_t)b.n * nf);
+  std::vector<std::vector<int64_t>> nbr((size_t)b.n);
+  for (int64_t i = 0; i < b.n; ++i) {
+    const int64_t e = b.elems[i];
+    for (int f = 0; f < nf; ++f) {
+      int64_t c[4] = {-1, -1, -1, -1};
+      for (int k = 0; k < nfc; ++k) c[k] = enodes[e * 8 + (nc == 8 ? kHexFaceCorners[f][k] : kTetFace[f][k])];
+      std::sort(c, c + nfc);
+      Key key;   // distinct faces of a conforming mesh share at most two corners
+      key.k[0] = c[0]; key.k[1] = c[1]; key.k[2] = c[2];
+      auto it = faces.find(key);
+      if (it == faces.end()) faces.emplace(key, std::array<int64_t, 2>{i, -1});
+      else if (it->second[1] < 0) {
+        it->second[1] = i;
+        nbr[i].push_back(it->second[0]);
+        nbr[it->second[0]].push_back(i);
+      }
+    }
+  }
+  int64_t total = 0;
+  std::vector<int64_t> seen;
+  for (int64_t t0 = 0; t0 < b.n; t0 += 64) {
+    seen.clear();
+    for (int64_t i = t0; i < std::min(b.n, t0 + 64); ++i)
+      for (int64_t j : nbr[i]) seen.push_back(j / 64);
+    std::sort(seen.begin(), seen.end());
+    total += (int64_t)(std::unique(seen.begin(), seen.end()) - seen.begin());
+  }
+  return total;
+}
+
 // Renumber a block along the Morton (Z-order) curve of its element centroids, each
 // coordinate quantised to 21 bits over the centroids' bounding box; ties keep the
 // input order.  Elements that share faces then mostly share 64-element tiles, so
@@ -465,7 +503,17 @@ std::string build_setup(int order, int64_t n_vert, const double* xyz, const doub
     b.n = (int64_t)b.elems.size();
     b.canon_pos.resize(b.n);
     for (int64_t i = 0; i < b.n; ++i) b.canon_pos[i] = (int32_t)i;
-    if (elem_order == 0) morton_order(b, t == kHex ? 8 : 4, xyz, enodes);
+    if (elem_order == 0 || elem_order == 2) {
+      const int nc = t == kHex ? 8 : 4;
+      Block keep;
+      if (elem_order == 0) { keep.n = b.n; keep.elems = b.elems; keep.canon_pos = b.canon_pos; }
+      morton_order(b, nc, xyz, enodes);
+      // automatic: keep the input order when its tiles are at least as compact
+      if (elem_order == 0 && tile_spread(keep, nc, enodes) <= tile_spread(b, nc, enodes)) {
+        b.elems.swap(keep.elems);
+        b.canon_pos.swap(keep.canon_pos);
+      }
+    }
     b.e_pad = (b.n + e_align - 1) / e_align * e_align;
     b.nsp = t == kHex ? H.nsp : T.nsp;
     b.nfp = t == kHex ? H.nfp : T.nfp;
@@ -533,7 +581,6 @@ std::string build_setup(int order, int64_t n_vert, const double* xyz, const doub
     for (int d = 0; d < 3; ++d) { lo[d] = std::min(lo[d], xyz[v * 3 + d]); hi[d] = std::max(hi[d], xyz[v * 3 + d]); }
   double span = std::max({hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2], 1e-300});
   const double scale = 1e-8 * span;
-  static const int kHexFaceCorners[6][4] = {{0, 3, 4, 7}, {1, 2, 5, 6}, {0, 1, 4, 5}, {2, 3, 6, 7}, {0, 1, 2, 3}, {4, 5, 6, 7}};
   auto face_centroid = [&](const Block& b, int64_t le, int f, double c[3]) {
     int64_t e = b.elems[le];
     int nc = b.etype == kHex ? 4 : 3;

@@ -46,7 +46,7 @@ class FrLayout(ctypes.Structure):
 
 class FrFilterStats(ctypes.Structure):
     _fields_ = [("n_troubled", ctypes.c_int64), ("n_fallback", ctypes.c_int64),
-                ("n_evals", ctypes.c_int64), ("seconds", ctypes.c_double)]
+                ("n_evals", ctypes.c_int64), ("seconds", ctypes.c_double), ("n_candidates", ctypes.c_int64)]
 
 
 class FrKernelTime(ctypes.Structure):

@@ -353,7 +353,10 @@ fr_status hex_rhs_p(fr_ctx c, DevBlock& b, const T* u, T* r) {
     c->prof_end(pk);
   } else {
     pk = c->prof_begin(("hex_grad" + sfx).c_str());
-    hex_grad<T, P, NE><<<nblk, NT, 0, c->stream>>>(u, uf, geo, C, grad, gradf, b.E, K, (T)p.ldg_beta, sm);
+    if constexpr (P <= 3)
+      hex_grad<T, P, NE><<<nblk, NT, 0, c->stream>>>(u, uf, geo, C, grad, gradf, b.E, K, (T)p.ldg_beta, sm);
+    else
+      hex_grad_lines<T, P, NE><<<nblk, NT, 0, c->stream>>>(u, uf, geo, C, grad, gradf, b.E, K, (T)p.ldg_beta, sm);
     c->prof_end(pk);
     T* fc = (T*)b.fc;
     const int64_t face_threads = b.E * 6 * N1 * N1;

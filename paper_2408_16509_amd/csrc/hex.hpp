@@ -374,6 +374,17 @@ __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_div_euler(
   }
 }
 
+// LDS slot of point pt in the gradient kernel's [component][point][element] buffer.
+// With 4 points per line and 16 FP32 elements a point row is 16 banks, and the rows
+// a wave touches on a line along xi_1 are 4 apart (same 16 banks of 64): the XOR of
+// the point's low two bits with the next two spreads the four rows of every line
+// direction over different bank groups.  A bijection on [0, 64).
+template <typename T, int N1, int NE>
+__device__ __forceinline__ int gr_slot(int pt) {
+  if constexpr (N1 == 4 && NE * sizeof(T) == 64) return pt ^ ((pt >> 2) & 3);
+  else return pt;
+}
+
 // ---------------------------------------------------------------------------
 // Navier--Stokes phase 1: corrected gradient (LDG common solution u^ at the flux
 // points), physical gradient at the solution points, and its traces at the flux
@@ -383,6 +394,127 @@ __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_div_euler(
 // mirror case), 0 in general.
 template <typename T, int P, int NE>
 __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_grad(
+    const T* __restrict__ u, const T* __restrict__ uf, const T* __restrict__ geo,
+    Conn C, T* __restrict__ grad, T* __restrict__ gradf, int64_t E, HexK<T> K, T beta, int side_mode) {
+  constexpr int N1 = P + 1, NSP = N1 * N1 * N1, NF = N1 * N1, NT = NE * N1 * N1;
+  __shared__ T GR[3 * NSP * NE];
+  __shared__ T U[5 * NSP * NE];       // the block's state, [pt*5 + v][el]
+  __shared__ T G[24 * NE];
+  const int el = threadIdx.x % NE, l = threadIdx.x / NE;
+  const int64_t e0 = xcd_block() * NE, e = e0 + el;
+  const int t0 = l % N1, t1 = l / N1;
+  // the global reads up front: geometry, the block's state and the neighbour traces at
+  // this thread's 6 line ends (only where the common value is not the own trace)
+  stage_geo<T, NE, NT>(geo, E, e0, G);
+  for (int i = threadIdx.x; i < 5 * NSP * NE; i += NT) U[i] = u[(int64_t)(i / NE) * E + e0 + i % NE];
+  auto uval = [&](int pt, int v) -> T { return U[(pt * 5 + v) * NE + el]; };
+  T uh[3][2][5];
+  bool need[3][2], left[3][2];
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+#pragma unroll
+    for (int sd = 0; sd < 2; ++sd) {
+      const NbrSlot s = nbr_slot<NF>(C, E, e, 2 * d + sd, l);
+      left[d][sd] = s.left;
+      need[d][sd] = side_mode == 0 || (side_mode > 0 ? !s.left : s.left);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) uh[d][sd][v] = need[d][sd] ? uf[((int64_t)s.fp * 5 + v) * E + s.elem] : T(0);
+    }
+  __syncthreads();
+  // metric of this thread's line points, once for all five variables: row d of S over J
+  T sJ[3][N1][3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+#pragma unroll
+    for (int a = 0; a < N1; ++a) {
+      T xi[3], g[3][3], s[3];
+      line_xi(K, d, a, t0, t1, xi);
+      hex_cols(G + el, NE, xi[0], xi[1], xi[2], g);
+      srow(g, d, s);
+      const T iJ = T(1) / det_cols(g);
+#pragma unroll
+      for (int j = 0; j < 3; ++j) sJ[d][a][j] = s[j] * iJ;
+    }
+  // common solution values u^ (LDG) at the 6 line ends
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      T tm = 0, tp = 0;
+#pragma unroll
+      for (int a = 0; a < N1; ++a) {
+        const T x = uval(line_pt<N1>(d, a, t0, t1), v);
+        tm += K.lm[a] * x;
+        tp += K.lp[a] * x;
+      }
+#pragma unroll
+      for (int sd = 0; sd < 2; ++sd) {
+        const T own = sd ? tp : tm, un = uh[d][sd][v];
+        const T uL = left[d][sd] ? own : un, uR = left[d][sd] ? un : own;
+        uh[d][sd][v] = need[d][sd] ? T(0.5) * (uL + uR) + beta * (uL - uR) : own;
+      }
+    }
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      T uv[N1];
+#pragma unroll
+      for (int a = 0; a < N1; ++a) uv[a] = uval(line_pt<N1>(d, a, t0, t1), v);
+#pragma unroll
+      for (int a = 0; a < N1; ++a) {
+        T gt = K.cp[a] * uh[d][1][v] - K.cm[a] * uh[d][0][v];
+#pragma unroll
+        for (int b = 0; b < N1; ++b) gt += K.Dh[a][b] * uv[b];
+        const int pt = line_pt<N1>(d, a, t0, t1);
+        T* Gp = GR + (gr_slot<T, N1, NE>(pt) * NE + el);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          if (d == 0) Gp[j * NSP * NE] = sJ[d][a][j] * gt;
+          else Gp[j * NSP * NE] += sJ[d][a][j] * gt;
+        }
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < N1; ++a) {
+      const int pt = line_pt<N1>(2, a, t0, t1);
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        grad[((int64_t)pt * 15 + v * 3 + j) * E + e] = GR[(j * NSP + gr_slot<T, N1, NE>(pt)) * NE + el];
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      T gm[3] = {0, 0, 0}, gp[3] = {0, 0, 0};
+#pragma unroll
+      for (int a = 0; a < N1; ++a) {
+        const int pt = line_pt<N1>(d, a, t0, t1);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          const T val = GR[(j * NSP + gr_slot<T, N1, NE>(pt)) * NE + el];
+          gm[j] += K.lm[a] * val;
+          gp[j] += K.lp[a] * val;
+        }
+      }
+#pragma unroll
+      for (int sd = 0; sd < 2; ++sd) {
+        // stored only where a neighbour will read it
+        const bool keep = side_mode == 0 || (side_mode > 0 ? !left[d][sd] : left[d][sd]);
+        if (!keep) continue;
+        const int f = (2 * d + sd) * NF + l;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) gradf[((int64_t)f * 15 + v * 3 + j) * E + e] = sd ? gp[j] : gm[j];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Variant for p = 4: the state is read from global memory (L2) per line and variable
+// instead of being staged, which keeps the LDS and registers of the 125-point element
+// within an occupancy of 3-4 waves per SIMD.
+template <typename T, int P, int NE>
+__global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_grad_lines(
     const T* __restrict__ u, const T* __restrict__ uf, const T* __restrict__ geo,
     Conn C, T* __restrict__ grad, T* __restrict__ gradf, int64_t E, HexK<T> K, T beta, int side_mode) {
   constexpr int N1 = P + 1, NSP = N1 * N1 * N1, NF = N1 * N1, NT = NE * N1 * N1;
@@ -399,6 +531,20 @@ __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_grad(
 #pragma unroll
     for (int sd = 0; sd < 2; ++sd) ns[d][sd] = nbr_slot<NF>(C, E, e, 2 * d + sd, l);
   __syncthreads();
+  // metric of this thread's line points, once for all five variables: row d of S over J
+  T sJ[3][N1][3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+#pragma unroll
+    for (int a = 0; a < N1; ++a) {
+      T xi[3], g[3][3], s[3];
+      line_xi(K, d, a, t0, t1, xi);
+      hex_cols(G + el, NE, xi[0], xi[1], xi[2], g);
+      srow(g, d, s);
+      const T iJ = T(1) / det_cols(g);
+#pragma unroll
+      for (int j = 0; j < 3; ++j) sJ[d][a][j] = s[j] * iJ;
+    }
   for (int v = 0; v < 5; ++v) {
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -426,17 +572,12 @@ __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_grad(
         T gt = K.cp[a] * uh[1] - K.cm[a] * uh[0];
 #pragma unroll
         for (int b = 0; b < N1; ++b) gt += K.Dh[a][b] * uv[b];
-        T xi[3], g[3][3], s[3];
-        line_xi(K, d, a, t0, t1, xi);
-        hex_cols(G + el, NE, xi[0], xi[1], xi[2], g);
-        srow(g, d, s);
-        const T sc = gt / det_cols(g);
         const int pt = line_pt<N1>(d, a, t0, t1);
-        T* Gp = GR + (pt * NE + el);
+        T* Gp = GR + (gr_slot<T, N1, NE>(pt) * NE + el);
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-          if (d == 0) Gp[j * NSP * NE] = s[j] * sc;
-          else Gp[j * NSP * NE] += s[j] * sc;
+          if (d == 0) Gp[j * NSP * NE] = sJ[d][a][j] * gt;
+          else Gp[j * NSP * NE] += sJ[d][a][j] * gt;
         }
       }
       __syncthreads();
@@ -445,7 +586,8 @@ __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_grad(
     for (int a = 0; a < N1; ++a) {
       const int pt = line_pt<N1>(2, a, t0, t1);
 #pragma unroll
-      for (int j = 0; j < 3; ++j) grad[((int64_t)pt * 15 + v * 3 + j) * E + e] = GR[(j * NSP + pt) * NE + el];
+      for (int j = 0; j < 3; ++j)
+        grad[((int64_t)pt * 15 + v * 3 + j) * E + e] = GR[(j * NSP + gr_slot<T, N1, NE>(pt)) * NE + el];
     }
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -455,7 +597,7 @@ __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_grad(
         const int pt = line_pt<N1>(d, a, t0, t1);
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-          const T val = GR[(j * NSP + pt) * NE + el];
+          const T val = GR[(j * NSP + gr_slot<T, N1, NE>(pt)) * NE + el];
           gm[j] += K.lm[a] * val;
           gp[j] += K.lp[a] * val;
         }

@@ -302,7 +302,7 @@ template <> struct HexCfg<1> { static constexpr int NE = 64; };
 template <> struct HexCfg<2> { static constexpr int NE = 32; };
 template <> struct HexCfg<3> { static constexpr int NE = 16; };
 template <> struct HexCfg<4> { static constexpr int NE = 8; };
-// element tile of the NS divergence (its LDS holds 15 values per point and element)
+// element tile of the NS divergence (its LDS holds 10 or 15 values per point and element)
 template <typename T, int P>
 struct DivNsCfg { static constexpr int NE = (sizeof(T) == 8 ? 8 : 16) / (P == 4 ? 2 : 1) * (P <= 2 ? 2 : 1); };
 
@@ -366,8 +366,12 @@ fr_status hex_rhs_p(fr_ctx c, DevBlock& b, const T* u, T* r) {
     c->prof_end(pk);
     constexpr int NE2 = DivNsCfg<T, P>::NE;
     pk = c->prof_begin(("hex_div_ns" + sfx).c_str());
-    hex_div_ns<T, DEV, P, NE2><<<(unsigned)(b.E / NE2), NE2 * N1 * N1, 0, c->stream>>>(
-        u, grad, fc, geo, r, b.E, b.n, K, (T)p.gamma, (T)p.mu, (T)p.prandtl, R);
+    if constexpr (sizeof(T) == 4 && P <= 3)
+      hex_div_ns<T, DEV, P, NE2><<<(unsigned)(b.E / NE2), NE2 * N1 * N1, 0, c->stream>>>(
+          u, grad, fc, geo, r, b.E, b.n, K, (T)p.gamma, (T)p.mu, (T)p.prandtl, R);
+    else
+      hex_div_ns_lds<T, DEV, P, NE2><<<(unsigned)(b.E / NE2), NE2 * N1 * N1, 0, c->stream>>>(
+          u, grad, fc, geo, r, b.E, b.n, K, (T)p.gamma, (T)p.mu, (T)p.prandtl, R);
     c->prof_end(pk);
   }
   hipError_t e = hipGetLastError();

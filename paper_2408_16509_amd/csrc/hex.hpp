@@ -692,6 +692,78 @@ __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_div_ns(
     const T* __restrict__ u, const T* __restrict__ grad, const T* __restrict__ fc, const T* __restrict__ geo,
     T* __restrict__ r, int64_t E, int64_t n, HexK<T> K, T gamma, T mu, T pr, RefState<T> R) {
   constexpr int N1 = P + 1, NSP = N1 * N1 * N1, NF = N1 * N1, NT = NE * N1 * N1;
+  // f~ along xi_1 and xi_2 go through LDS ([d][v][pt][el]); along xi_3 the line is the
+  // thread's own column, so f~_3 and its common fluxes stay in registers
+  __shared__ T FT[2 * 5 * NSP * NE];
+  __shared__ T G[24 * NE];
+  const int el = threadIdx.x % NE, l = threadIdx.x / NE;
+  const int64_t e0 = xcd_block() * NE, e = e0 + el;
+  const int ci = l % N1, cj = l / N1;
+  stage_geo<T, NE, NT>(geo, E, e0, G);
+  __syncthreads();
+  const T gm1 = gamma - T(1);
+  T iJ[N1], f3[N1][5];
+#pragma unroll
+  for (int k = 0; k < N1; ++k) {
+    const int pt = ci + N1 * (cj + N1 * k);
+    T uu[5], gg[15];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) uu[v] = u[((int64_t)pt * 5 + v) * E + e];
+#pragma unroll
+    for (int q = 0; q < 15; ++q) gg[q] = grad[((int64_t)pt * 15 + q) * E + e];
+    T g[3][3];
+    hex_cols(G + el, NE, K.x[ci], K.x[cj], K.x[k], g);
+    iJ[k] = T(-1) / det_cols(g);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      T s[3], f[5], fv[5], vs, prs;
+      srow(g, d, s);
+      Flux<T, DEV>::eval(uu, s[0], s[1], s[2], gm1, R, f, vs, prs);
+      viscous<T, DEV>(uu, gg, s[0], s[1], s[2], gamma, mu, pr, R, fv);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        if (d < 2) FT[((d * 5 + v) * NSP + pt) * NE + el] = f[v] - fv[v];
+        else f3[k][v] = f[v] - fv[v];
+      }
+    }
+  }
+  // own column: common fluxes at its two xi_3 ends
+  const int q2 = ci + N1 * cj;
+  T F4[5], F5[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    F4[v] = fc[(((int64_t)4 * NF + q2) * 5 + v) * E + e];
+    F5[v] = fc[(((int64_t)5 * NF + q2) * 5 + v) * E + e];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < N1; ++k) {
+    const int pt = ci + N1 * (cj + N1 * k);
+    // line coordinates of this point in each direction: (position a, face-local q)
+    const int a0 = ci, q0 = cj + N1 * k, a1 = cj, q1 = ci + N1 * k;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      T acc = K.cp[k] * F5[v] + K.cm[k] * F4[v];
+#pragma unroll
+      for (int b = 0; b < N1; ++b) {
+        acc += K.Dh[a0][b] * FT[((0 * 5 + v) * NSP + (b + N1 * (cj + N1 * k))) * NE + el];
+        acc += K.Dh[a1][b] * FT[((1 * 5 + v) * NSP + (ci + N1 * (b + N1 * k))) * NE + el];
+        acc += K.Dh[k][b] * f3[b][v];
+      }
+      acc += K.cp[a0] * fc[(((int64_t)1 * NF + q0) * 5 + v) * E + e] + K.cm[a0] * fc[(((int64_t)0 * NF + q0) * 5 + v) * E + e];
+      acc += K.cp[a1] * fc[(((int64_t)3 * NF + q1) * 5 + v) * E + e] + K.cm[a1] * fc[(((int64_t)2 * NF + q1) * 5 + v) * E + e];
+      if (e < n) r[((int64_t)pt * 5 + v) * E + e] = acc * iJ[k];
+    }
+  }
+}
+
+// Variant with all three directions' f~ in LDS (the register budget of FP64 and of
+// p = 4 does not hold f~_3 of a whole column).
+template <typename T, bool DEV, int P, int NE>
+__global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_div_ns_lds(
+    const T* __restrict__ u, const T* __restrict__ grad, const T* __restrict__ fc, const T* __restrict__ geo,
+    T* __restrict__ r, int64_t E, int64_t n, HexK<T> K, T gamma, T mu, T pr, RefState<T> R) {
+  constexpr int N1 = P + 1, NSP = N1 * N1 * N1, NF = N1 * N1, NT = NE * N1 * N1;
   __shared__ T FT[3 * 5 * NSP * NE];       // [d][v][pt][el]
   __shared__ T G[24 * NE];
   const int el = threadIdx.x % NE, l = threadIdx.x / NE;

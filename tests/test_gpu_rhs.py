@@ -175,3 +175,45 @@ def test_rhs_parity_config2_full_size():
     fl, Ro = oracle_floor(mesh, 3, u, oracle_params(1, 0))
     Rg = gpu_rhs(mesh, u, system=1, order=3, riemann=0)
     check(Rg, Ro, floor_=fl)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_native_order_does_not_change_results(precision):
+    """The native element order (input order, Morton renumbering, automatic) only moves
+    data: the canonical right-hand side of a permuted mixed hex + tet mesh is bit-identical."""
+    from paper_2408_16509_amd import frmi
+    mesh = inputs.concat([inputs.hex_box((4, 4, 4), perturb=0.1, perturb_seed=3),
+                          inputs.kuhn_split(inputs.hex_box((3, 3, 3), lo=(3.0, -3.0, -3.0),
+                                                           hi=(3.0 + 2 * np.pi, -3.0 + 2 * np.pi, -3.0 + 2 * np.pi)))],
+                         permute_seed=5)
+    kw = dict(system=1, order=4, riemann=0)
+    if precision:
+        kw.update(precision=frmi.FR_FP32, u_ref=(1.0, 0.0, 0.0, 0.0, 2.5))
+    out = []
+    for order in (1, 2, 0):
+        ctx = _ctx(mesh, elem_order=order, **kw)
+        x = ctx.sol_points()
+        n = x.shape[0]
+        rng = np.random.default_rng(7)
+        rho = 1.0 + 0.1 * rng.uniform(-1, 1, n)
+        vel = 0.3 * rng.uniform(-1, 1, (3, n))
+        p = 1.0 + 0.1 * rng.uniform(-1, 1, n)
+        st = np.stack([rho, rho * vel[0], rho * vel[1], rho * vel[2], p / 0.4 + 0.5 * rho * (vel ** 2).sum(0)])
+        canon = np.concatenate([np.moveaxis(st[:, o:o + m * s].reshape(5, m, s), 0, 1).ravel()
+                                for o, m, s in _blocks_of(ctx)])
+        u = ctx.pack(canon)
+        r = ctx.new_native()
+        ctx.rhs(u, r)
+        out.append(ctx.unpack_rhs(r).cpu().numpy())
+        ctx.close()
+    assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])
+
+
+def _blocks_of(ctx):
+    lay = ctx.layout
+    res, o = [], 0
+    for i in range(lay.n_types):
+        m, s = lay.n_elem[i], lay.n_sp[i]
+        res.append((o, m, s))
+        o += m * s
+    return res

@@ -362,7 +362,8 @@ fr_status hex_rhs_p(fr_ctx c, DevBlock& b, const T* u, T* r) {
     const int64_t face_threads = b.E * 6 * N1 * N1;
     pk = c->prof_begin(("hex_face_ns" + sfx).c_str());
     hex_face_ns<T, DEV, P><<<(unsigned)((face_threads + 255) / 256), 256, 0, c->stream>>>(
-        uf, gradf, geo, C, fc, b.E, K, (T)p.gamma, (T)p.mu, (T)p.prandtl, (T)p.ldg_beta, (T)p.ldg_tau, p.riemann, sm, R);
+        uf, gradf, geo, C, fc, b.E, b.n, K, (T)p.gamma, (T)p.mu, (T)p.prandtl, (T)p.ldg_beta, (T)p.ldg_tau,
+        p.riemann, sm, R);
     c->prof_end(pk);
     constexpr int NE2 = DivNsCfg<T, P>::NE;
     pk = c->prof_begin(("hex_div_ns" + sfx).c_str());

@@ -617,17 +617,18 @@ __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_grad_lines(
 }
 
 // ---------------------------------------------------------------------------
-// Navier--Stokes phase 2a: the LDG common flux at every flux point of every element
-// (eq:comm_flux with the viscous terms): inviscid Riemann flux along the left
-// side's normal, minus the switched viscous flux, plus the penalty; entering this
-// element as +-|S^T n~| times it.  One thread per (element, flux point), lanes over
-// elements.  With a one-sided switch only the contributing side's gradient trace
-// is read (stored by hex_grad in that side's slot).
+// Navier--Stokes phase 2a: the LDG common flux at every flux-point pair (eq:comm_flux
+// with the viscous terms): inviscid Riemann flux along the left side's normal, minus
+// the switched viscous flux, plus the penalty.  Threads over (element, flux point),
+// lanes over elements; the left side of each pair computes it once and writes
+// +|S^T n~| times it into its own slot and the negative into the right side's slot
+// (conservative by construction).  With a one-sided switch only the contributing
+// side's gradient trace is read (stored by hex_grad in that side's slot).
 template <typename T, bool DEV, int P>
 __global__ void __launch_bounds__(256) hex_face_ns(const T* __restrict__ uf, const T* __restrict__ gradf,
                                                    const T* __restrict__ geo, Conn C, T* __restrict__ fc, int64_t E,
-                                                   HexK<T> K, T gamma, T mu, T pr, T beta, T tau, int riemann,
-                                                   int side_mode, RefState<T> R) {
+                                                   int64_t n, HexK<T> K, T gamma, T mu, T pr, T beta, T tau,
+                                                   int riemann, int side_mode, RefState<T> R) {
   constexpr int N1 = P + 1, NF = N1 * N1, NFP = 6 * NF;
   const int64_t gtid = xcd_block() * 256 + threadIdx.x;
   const int64_t wave = gtid >> 6;
@@ -635,7 +636,7 @@ __global__ void __launch_bounds__(256) hex_face_ns(const T* __restrict__ uf, con
   const int64_t tile = wave / NFP;
   const int fp = (int)(wave % NFP);
   const int64_t e = tile * 64 + lane;
-  if (e >= E) return;
+  if (e >= n) return;
   const int face = fp / NF, q = fp % NF, d = face / 2, sd = face % 2, t0 = q % N1, t1 = q / N1;
   T c[24];
 #pragma unroll
@@ -646,6 +647,8 @@ __global__ void __launch_bounds__(256) hex_face_ns(const T* __restrict__ uf, con
   srow(g, d, nv);
   const T mag = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
   const NbrSlot ns = nbr_slot<NF>(C, E, e, face, q);
+  // each flux-point pair once: the left side computes it and writes both slots
+  if (!ns.left) return;
   T own[5], un[5], uL[5], uR[5], nL[3], F[5];
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
@@ -675,9 +678,12 @@ __global__ void __launch_bounds__(256) hex_face_ns(const T* __restrict__ uf, con
 #pragma unroll
     for (int v = 0; v < 5; ++v) fvc[v] += wgt * fv[v];
   }
-  const T fs = ns.left ? mag : -mag;
 #pragma unroll
-  for (int v = 0; v < 5; ++v) fc[((int64_t)fp * 5 + v) * E + e] = fs * (F[v] - fvc[v] + tau * (uL[v] - uR[v]));
+  for (int v = 0; v < 5; ++v) {
+    const T fn = mag * (F[v] - fvc[v] + tau * (uL[v] - uR[v]));
+    fc[((int64_t)fp * 5 + v) * E + e] = fn;
+    fc[((int64_t)ns.fp * 5 + v) * E + ns.elem] = -fn;
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -355,8 +355,12 @@ fr_status hex_rhs_p(fr_ctx c, DevBlock& b, const T* u, T* r) {
     pk = c->prof_begin(("hex_grad" + sfx).c_str());
     if constexpr (P <= 3)
       hex_grad<T, P, NE><<<nblk, NT, 0, c->stream>>>(u, uf, geo, C, grad, gradf, b.E, K, (T)p.ldg_beta, sm);
-    else
-      hex_grad_lines<T, P, NE><<<nblk, NT, 0, c->stream>>>(u, uf, geo, C, grad, gradf, b.E, K, (T)p.ldg_beta, sm);
+    else {
+      // 16 FP32 elements per tile (64-byte rows); FP64 keeps 8 (64-byte rows as well)
+      constexpr int NEg = sizeof(T) == 4 ? 16 : NE;
+      hex_grad_lines<T, P, NEg><<<(unsigned)(b.E / NEg), NEg * N1 * N1, 0, c->stream>>>(
+          u, uf, geo, C, grad, gradf, b.E, K, (T)p.ldg_beta, sm);
+    }
     c->prof_end(pk);
     T* fc = (T*)b.fc;
     const int64_t face_threads = b.E * 6 * N1 * N1;

@@ -42,6 +42,13 @@ struct FiltPrm {
   int n_bits;
 };
 
+// Optional FP32 copy of a filtered state: the deviation (u - ref) in the native layout
+// of the FP32 form (p null: none).
+struct Dev32 {
+  float* p;
+  double ref[5];
+};
+
 __device__ __forceinline__ double entropy_of(double rho, double p, double gamma) {
   return rho > 0 ? p * pow(rho, -gamma) : -INFINITY;
 }
@@ -132,7 +139,7 @@ struct HexFiltSmem {
 // values at the solution points are written there ([pt][5][E] layout).
 template <int P>
 __device__ bool hex_eval_checks(HexFiltSmem<P>& S, double smin, const FiltPrm& F, double* __restrict__ store,
-                                int64_t E, int64_t e) {
+                                const Dev32& s32, int64_t E, int64_t e) {
   constexpr int N1 = P + 1, NR = N1 + 2, NSP = N1 * N1 * N1, NFP = 6 * N1 * N1;
   const int t = threadIdx.x;
   // pass over k: T1[v][i + N1 j][r3]
@@ -178,7 +185,10 @@ __device__ bool hex_eval_checks(HexFiltSmem<P>& S, double smin, const FiltPrm& F
     ok = ok && admissible(w, smin, F);
     if (store && c < NSP) {
 #pragma unroll
-      for (int v = 0; v < 5; ++v) store[((int64_t)c * 5 + v) * E + e] = w[v];
+      for (int v = 0; v < 5; ++v) {
+        store[((int64_t)c * 5 + v) * E + e] = w[v];
+        if (s32.p) s32.p[((int64_t)c * 5 + v) * E + e] = (float)(w[v] - s32.ref[v]);
+      }
     }
   }
   return __syncthreads_and(ok ? 1 : 0) != 0;
@@ -250,14 +260,15 @@ __device__ void hex_load_modal(HexFiltSmem<P>& S, const double* __restrict__ u, 
 template <int P>
 __device__ void hex_filter_elem(HexFiltSmem<P>& S, double* __restrict__ u, const double* __restrict__ smin_a,
                                 int64_t E, int64_t e, const FiltK& K, const FiltPrm& F, int mode, float kh_in,
-                                bool preloaded, int32_t* __restrict__ k_out, int32_t* __restrict__ evals_out) {
+                                bool preloaded, int32_t* __restrict__ k_out, int32_t* __restrict__ evals_out,
+                                const Dev32& s32) {
   const int t = threadIdx.x;
   const double smin = smin_a[e];
   bool ok0 = false;
   if (!preloaded) {
     hex_load_modal<P>(S, u, E, e, K);
     hex_set_w<P>(S, K, 0.0);
-    ok0 = hex_eval_checks<P>(S, smin, F, nullptr, E, e);
+    ok0 = hex_eval_checks<P>(S, smin, F, nullptr, Dev32{}, E, e);
   }
   int evals = 1;
   if (ok0) {
@@ -272,7 +283,7 @@ __device__ void hex_filter_elem(HexFiltSmem<P>& S, double* __restrict__ u, const
   auto G = [&](int64_t k) {
     hex_set_w<P>(S, K, (double)k * dz);
     ++evals;
-    return hex_eval_checks<P>(S, smin, F, nullptr, E, e);
+    return hex_eval_checks<P>(S, smin, F, nullptr, Dev32{}, E, e);
   };
   int64_t lo = 0, hi = N;
   bool fallback = false;
@@ -302,7 +313,7 @@ __device__ void hex_filter_elem(HexFiltSmem<P>& S, double* __restrict__ u, const
   }
   const double zeta = fallback ? F.zeta_max : (double)hi * dz;
   hex_set_w<P>(S, K, zeta);
-  (void)hex_eval_checks<P>(S, smin, F, u, E, e);
+  (void)hex_eval_checks<P>(S, smin, F, u, s32, E, e);
   if (t == 0) {
     if (k_out) k_out[e] = fallback ? -1 : (int32_t)hi;
     if (evals_out) evals_out[e] = evals;
@@ -314,12 +325,13 @@ template <int P>
 __global__ void __launch_bounds__(FNT) hex_filter(double* __restrict__ u, const double* __restrict__ smin_a, int64_t E,
                                                  const int32_t* __restrict__ list, const int32_t* __restrict__ count,
                                                  FiltK K, FiltPrm F, int mode, const float* __restrict__ khat,
-                                                 int32_t* __restrict__ k_out, int32_t* __restrict__ evals_out) {
+                                                 int32_t* __restrict__ k_out, int32_t* __restrict__ evals_out,
+                                                 Dev32 s32) {
   __shared__ HexFiltSmem<P> S;
   const int32_t m = *count;
   for (int32_t i = blockIdx.x; i < m; i += gridDim.x) {
     const int32_t e = list[i];
-    hex_filter_elem<P>(S, u, smin_a, E, e, K, F, mode, khat ? khat[e] : 0.0f, false, k_out, evals_out);
+    hex_filter_elem<P>(S, u, smin_a, E, e, K, F, mode, khat ? khat[e] : 0.0f, false, k_out, evals_out, s32);
     __syncthreads();
   }
 }
@@ -489,7 +501,7 @@ __device__ bool hex_features_elem(HexFiltSmem<P>& S, double* red, double* PM, co
   const double g = F.gamma;
   hex_load_modal<P>(S, u, E, e, K);
   hex_set_w<P>(S, K, 0.0);
-  const bool ok0 = hex_eval_checks<P>(S, smin, F, nullptr, E, e);
+  const bool ok0 = hex_eval_checks<P>(S, smin, F, nullptr, Dev32{}, E, e);
   if (ok0) {
     if (t == 0 && flag) flag[e] = 0;
     return false;
@@ -605,7 +617,8 @@ __global__ void __launch_bounds__(FNT, 4) hex_filter_learned(double* __restrict_
                                                          int64_t E, const int32_t* __restrict__ list,
                                                          const int32_t* __restrict__ count, FiltK K, FiltPrm F,
                                                          const float* __restrict__ w, const float* __restrict__ scale,
-                                                         int32_t* __restrict__ k_out, int32_t* __restrict__ evals_out) {
+                                                         int32_t* __restrict__ k_out, int32_t* __restrict__ evals_out,
+                                                         Dev32 s32) {
   constexpr int N1 = P + 1, NSP = N1 * N1 * N1;
   __shared__ HexFiltSmem<P> S;
   __shared__ double red[FNT];
@@ -633,7 +646,7 @@ __global__ void __launch_bounds__(FNT, 4) hex_filter_learned(double* __restrict_
     }
     const double y = block_sum(contrib, red) + (double)w[64 * 16 + 64 + 64 * 64 + 64 + 64];
     const float kh = exp2f((float)F.n_bits * (float)y);
-    hex_filter_elem<P>(S, u, smin_a, E, e, K, F, 1, kh, true, k_out, evals_out);
+    hex_filter_elem<P>(S, u, smin_a, E, e, K, F, 1, kh, true, k_out, evals_out, s32);
     __syncthreads();
   }
 }

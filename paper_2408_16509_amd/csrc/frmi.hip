@@ -295,6 +295,20 @@ __global__ void k_rk32_last(double* __restrict__ u, const float* __restrict__ k,
   }
 }
 
+// Filtered FP32 form: the stage state in FP64 (for the filter) and its FP32 deviation
+// (for the right-hand side) in one pass; acc = (first ? u : acc) + b k.
+__global__ void k_rk32f_stage(const double* __restrict__ u, const float* __restrict__ k, double* __restrict__ acc,
+                              double* __restrict__ s64, float* __restrict__ s32, int64_t n, int64_t E, double b,
+                              double c, RefVec ref, int first) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double ui = u[i], ki = (double)k[i];
+    acc[i] = (first ? ui : acc[i]) + b * ki;
+    const double si = ui + c * ki;
+    s64[i] = si;
+    s32[i] = (float)(si - ref.v[(i / E) % 5]);
+  }
+}
+
 // ------------------------------------------------------------ hex dispatch
 template <int P>
 struct HexCfg;
@@ -547,21 +561,24 @@ void hex_features_p(fr_ctx c, DevBlock& b, const double* u) {
 }
 
 template <int P>
-void hex_filter_p(fr_ctx c, DevBlock& b, double* u, int mode) {
+void hex_filter_p(fr_ctx c, DevBlock& b, double* u, int mode, float* u32) {
   const FiltK K = filtk_of(c->host.hex);
   const FiltPrm F = filtprm_of(c->prm, P);
   const int64_t o = b.elem_off;
   const int nb = (int)((b.n + 255) / 256);
+  Dev32 s32{u32 ? u32 + b.native_off : nullptr, {0, 0, 0, 0, 0}};
+  for (int v = 0; v < 5; ++v) s32.ref[v] = c->prm.u_ref[v];
   hex_candidates_p<P>(c, b, u);
   int pk;
   if (mode == 1) {
     pk = c->prof_begin("filter_search_learned");
     hex_filter_learned<P><<<list_grid(b), FNT, 0, c->stream>>>(u + b.native_off, b.smin, b.E, b.f_list, b.f_cnt + nb,
-                                                              K, F, c->m_w, c->m_scale, c->f_k + o, c->f_evals + o);
+                                                              K, F, c->m_w, c->m_scale, c->f_k + o, c->f_evals + o,
+                                                              s32);
   } else {
     pk = c->prof_begin("filter_search_plain");
     hex_filter<P><<<list_grid(b), FNT, 0, c->stream>>>(u + b.native_off, b.smin, b.E, b.f_list, b.f_cnt + nb, K, F,
-                                                       0, nullptr, c->f_k + o, c->f_evals + o);
+                                                       0, nullptr, c->f_k + o, c->f_evals + o, s32);
   }
   c->prof_end(pk);
 }
@@ -581,8 +598,11 @@ fr_status compute_smin(fr_ctx c, const double* uprev) {
 }
 
 fr_status collect_rows(fr_ctx c, const double* u);
+fr_status apply_filter(fr_ctx c, double* u, int mode, float* u32 = nullptr);
 
-fr_status apply_filter(fr_ctx c, double* u, int mode) {
+// Filter the FP64 native state u in place; with u32 (the FP32 form's stage buffer) the
+// filtered elements' FP32 deviations are rewritten there as well.
+fr_status apply_filter(fr_ctx c, double* u, int mode, float* u32) {
   if (c->collecting) {
     fr_status st = collect_rows(c, u);
     if (st) return st;
@@ -590,10 +610,10 @@ fr_status apply_filter(fr_ctx c, double* u, int mode) {
   for (auto& b : c->blocks) {
     if (b.etype != FR_HEX) return fail(c, FR_ERR_UNSUPPORTED, "entropy filter: tetrahedra not yet available");
     switch (c->prm.order) {
-      case 1: hex_filter_p<1>(c, b, u, mode); break;
-      case 2: hex_filter_p<2>(c, b, u, mode); break;
-      case 3: hex_filter_p<3>(c, b, u, mode); break;
-      case 4: hex_filter_p<4>(c, b, u, mode); break;
+      case 1: hex_filter_p<1>(c, b, u, mode, u32); break;
+      case 2: hex_filter_p<2>(c, b, u, mode, u32); break;
+      case 3: hex_filter_p<3>(c, b, u, mode, u32); break;
+      case 4: hex_filter_p<4>(c, b, u, mode, u32); break;
     }
   }
   HIP_TRY(c, hipGetLastError());
@@ -1051,15 +1071,18 @@ fr_status fr_rk_step(fr_ctx c, void* u_, double dt, int32_t n_steps, int32_t fil
         for (int stage = 0; stage < 4; ++stage) {
           if ((st = rhs_native(c, S, K))) return st;
           pk = c->prof_begin("rk4_update_f32");
-          if (stage == 0) k_rk_first<float><<<g, 256, 0, c->stream>>>(u, K, c->rk_acc, S64, n, b1, c2);
-          else if (stage < 3) k_rk_mid<float><<<g, 256, 0, c->stream>>>(u, K, c->rk_acc, S64, n, b2, stage == 1 ? c2 : dt);
-          else k_rk_last<float><<<g, 256, 0, c->stream>>>(u, K, c->rk_acc, n, b1);
+          for (auto& b : c->blocks) {
+            const int64_t nb = (int64_t)b.nsp * 5 * b.E, o = b.native_off;
+            const int gb = grid_for(nb, 256);
+            if (stage < 3)
+              k_rk32f_stage<<<gb, 256, 0, c->stream>>>(u + o, K + o, c->rk_acc + o, S64 + o, S + o, nb, b.E,
+                                                        stage == 0 ? b1 : b2, stage == 2 ? dt : c2, ref, stage == 0);
+            else
+              k_rk32_last<<<gb, 256, 0, c->stream>>>(u + o, K + o, c->rk_acc + o, S + o, nb, b.E, b1, ref);
+          }
           c->prof_end(pk);
-          double* tgt = stage < 3 ? S64 : u;
-          if ((st = apply_filter(c, tgt, filter_mode))) return st;
-          pk = c->prof_begin("rk4_update_f32");
-          to_dev(tgt);
-          c->prof_end(pk);
+          // the filter rewrites the FP32 deviation of every element it changes
+          if ((st = apply_filter(c, stage < 3 ? S64 : u, filter_mode, S))) return st;
         }
       }
     } else {

@@ -1053,17 +1053,14 @@ fr_status fr_rk_step(fr_ctx c, void* u_, double dt, int32_t n_steps, int32_t fil
   } else {
     float *K = (float*)c->rk_k, *S = (float*)c->rk_stage;
     const RefVec ref = refvec(c->prm);
-    auto to_dev = [&](const double* src) {
-      for (auto& b : c->blocks) {
-        const int64_t nb = (int64_t)b.nsp * 5 * b.E;
-        k_to_dev<<<grid_for(nb, 256), 256, 0, c->stream>>>(src + b.native_off, S + b.native_off, nb, b.E, ref);
-      }
-    };
     // the FP32 deviation of u_n; later steps get it from the previous step's last update
-    to_dev(u);
+    for (auto& b : c->blocks) {
+      const int64_t nb = (int64_t)b.nsp * 5 * b.E;
+      k_to_dev<<<grid_for(nb, 256), 256, 0, c->stream>>>(u + b.native_off, S + b.native_off, nb, b.E, ref);
+    }
     if (filter_mode >= 0) {
-      // filtered: every stage state is formed in FP64, filtered with FP64 checks, then
-      // rounded to the FP32 deviation the kernels read
+      // filtered: every stage state is formed in FP64 (for the filter and its FP64
+      // checks) together with the FP32 deviation the kernels read
       if (!c->rk_s64 && dalloc(c, &c->rk_s64, n)) return FR_ERR_ALLOC;
       double* S64 = c->rk_s64;
       for (int s = 0; s < n_steps; ++s) {

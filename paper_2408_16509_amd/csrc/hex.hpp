@@ -12,8 +12,10 @@
 // of eq:FRfinal with the DG correction reduces to
 //     div_d = Dh f~_d + cp F^C(+) + cm F^C(-)
 // (Dh = D - gR' l(+1)^T - gL' l(-1)^T, cp = gR', cm = -gL'), so the discontinuous
-// normal flux at the ends never needs forming.  Each thread owns one line of one
-// element per direction pass; the three directions' contributions meet in LDS.
+// normal flux at the ends never needs forming.  In the trace, Euler and gradient
+// kernels each thread owns one line of one element per direction pass and the three
+// directions' contributions meet in LDS; the NS divergence gives each thread one
+// column of points and pulls the three line contractions through its points from LDS.
 // The geometric map is trilinear and evaluated on the fly from its 24 monomial
 // coefficients (metric terms of linear elements computed from the corners),
 // staged per block in LDS.

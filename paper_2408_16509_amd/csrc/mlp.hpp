@@ -60,26 +60,6 @@ __global__ void __launch_bounds__(256) mlp_forward(const float* __restrict__ w, 
   y[r] = n_bits > 0 ? exp2f((float)n_bits * out) : out;
 }
 
-// Predictions for the troubled elements among the candidates list[0 .. *count)
-// (flag[e] = 1), written to y[e].
-__global__ void __launch_bounds__(256) mlp_forward_list(const float* __restrict__ w, const float* __restrict__ scale,
-                                                        const float* __restrict__ x, const int32_t* __restrict__ flag,
-                                                        const int32_t* __restrict__ list,
-                                                        const int32_t* __restrict__ count, int n_bits,
-                                                        float* __restrict__ y) {
-  __shared__ float W[MLP_NP];
-  __shared__ float sc[2 * MLP_IN];
-  mlp_stage(w, scale, W, sc);
-  const int32_t m = *count;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t e = list[i];
-    if (flag[e] == 0) continue;
-    float h1[MLP_H];
-    const float out = mlp_eval(W, sc, x + e * MLP_IN, h1, nullptr);
-    y[e] = n_bits > 0 ? exp2f((float)n_bits * out) : out;
-  }
-}
-
 // Per-sample forward and backward quantities of one batch (rows idx[0..B)).
 // Scratch per sample s: xs[16] | h1[64] | h2[64] | d1[64] | d2[64] | dy
 constexpr int MLP_SS = MLP_IN + 4 * MLP_H + 1;

@@ -138,9 +138,10 @@ def cpu_baseline(mesh, cfg, u_canon_fn):
 def run_form(form, cfg, mesh, ic, args, torch, np, frmi):
     """Time `args.steps` RK4 steps of one precision form; per-kernel event timing."""
     kw = dict(system=cfg["system"], order=cfg["order"], riemann=cfg["riemann"])
-    if form == "fp32":
+    if form in ("fp32", "bf16x3"):
         p0 = 1.0 / (1.4 * cfg["mach"] ** 2)
-        kw.update(precision=frmi.FR_FP32, u_ref=(1.0, 0.0, 0.0, 0.0, p0 / 0.4))
+        kw.update(precision=frmi.FR_FP32 if form == "fp32" else frmi.FR_FP32_BF16X3,
+                  u_ref=(1.0, 0.0, 0.0, 0.0, p0 / 0.4))
     ctx = frmi.Context(mesh, **kw)
     lay = ctx.layout
     x = ctx.sol_points()
@@ -322,7 +323,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="ns_tgv_hex32_p3", choices=sorted(CONFIGS))
-    ap.add_argument("--forms", default="fp32,fp64", help="precision forms to time; the first is the headline")
+    ap.add_argument("--forms", default="fp32,fp64",
+                    help="precision forms to time (fp32, fp64, bf16x3); the first is the headline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -379,7 +381,7 @@ def main():
         "metric": "RHS GDoF/s (FP32/learned vs FP64 plain) at stated L2 error; % HBM roofline",
         "value": round(gdofs[forms[0]], 4), "unit": "GDoF/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(head["ms"], 4), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32" if forms[0] == "fp32" else "f64", "data": "synthetic",
+        "vs_baseline": None, "dtype": {"fp32": "f32", "bf16x3": "f32+bf16x3"}.get(forms[0], "f64"), "data": "synthetic",
         "config": {"workload": args.config, "elements": int(E), "order": cfg["order"],
                    "blocks": {k: {"elements": v[0], "points_per_elem": v[1]} for k, v in blocks.items()},
                    "dof": int(dof), "rhs_per_step": 4, "form": forms[0],

@@ -58,7 +58,7 @@ typedef enum {
 
 enum { FR_EULER = 0, FR_NAVIER_STOKES = 1 };
 enum { FR_RUSANOV = 0, FR_HLLC = 1 };
-enum { FR_FP64 = 0, FR_FP32 = 1 };
+enum { FR_FP64 = 0, FR_FP32 = 1, FR_FP32_BF16X3 = 2 };
 enum { FR_HEX = 0, FR_TET = 1 };
 
 /* Solver parameters.  struct_size must be sizeof(fr_params). */
@@ -68,7 +68,11 @@ typedef struct {
   int32_t order;           /* hexahedra: 1..4; tetrahedra need 4                     */
   int32_t riemann;         /* FR_RUSANOV or FR_HLLC (common flux of eq:comm_flux)    */
   int32_t precision;       /* FR_FP64, or FR_FP32: FP32 kernels on deviation
-                              variables du = u - u_ref (FP64 RK accumulation)      */
+                              variables du = u - u_ref (FP64 RK accumulation), or
+                              FR_FP32_BF16X3: as FR_FP32 with the dense tetrahedral
+                              operator products done as BF16x3 split products
+                              (hi*hi + hi*lo + lo*hi, FP32 accumulation; hexahedra
+                              unchanged)                                            */
   int32_t elem_order;      /* native element order of each type block: 1 keeps the
                               input order, 2 renumbers along a Morton curve of the
                               element centroids (face neighbours share tiles and

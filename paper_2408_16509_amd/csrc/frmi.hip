@@ -22,6 +22,22 @@ namespace {
 
 thread_local std::string g_thread_err;
 
+// x rounded to FP32, then split into bf16 hi = rne(x) and lo = rne(x - hi) (bit patterns).
+uint16_t bf16_rne(float f) {
+  uint32_t b;
+  std::memcpy(&b, &f, 4);
+  b += 0x7FFFu + ((b >> 16) & 1u);
+  return (uint16_t)(b >> 16);
+}
+void bf16_split_host(double x, uint16_t& hi, uint16_t& lo) {
+  const float xf = (float)x;
+  hi = bf16_rne(xf);
+  const uint32_t hb = (uint32_t)hi << 16;
+  float hf;
+  std::memcpy(&hf, &hb, 4);
+  lo = bf16_rne(xf - hf);
+}
+
 struct DevBlock {
   int etype = 0;
   int64_t n = 0, E = 0;
@@ -88,6 +104,8 @@ struct fr_ctx_s {
   // tetrahedral operators on the device (arithmetic type of the context)
   void* tet_opT = nullptr;    // [TET_KP][TET_MP] transposed divergence operator
   void* tet_ogT = nullptr;    // [TGR_K][TGR_M] transposed stacked gradient operator
+  void* tet_opH = nullptr;    // BF16x3 split of the divergence operator: hi [TET_MP][TET_KP16], then lo
+  void* tet_ogH = nullptr;    // BF16x3 split of the gradient operator: hi [TGR_M][TGR_K], then lo
   double* rk_s64 = nullptr;   // FP64 stage state of the filtered FP32 form    // [TET_KP][TET_MP] transposed divergence operator
   int32_t* tet_src = nullptr;
   // training-data collection during filtered RK steps (fr_mlp_collect)
@@ -412,21 +430,39 @@ fr_status tet_rhs(fr_ctx c, DevBlock& b, const T* u, T* r) {
   const int sm = side_mode_of(p.ldg_beta);
   const unsigned div_grid = (unsigned)(b.E / TDIV_NE);   // one 16-element tile per block
   const T* opT = (const T*)c->tet_opT;
+  const tet_s4 *opH = (const tet_s4*)c->tet_opH, *opL = opH ? opH + TET_MP * TET_KP16 / 4 : nullptr;
+  const tet_s4 *ogH = (const tet_s4*)c->tet_ogH, *ogL = ogH ? ogH + TGR_M * TGR_K / 4 : nullptr;
+  // BF16x3 contractions: only in the FP32 form (T = float) when asked for
+  constexpr bool can_bf3 = sizeof(T) == 4;
+  const bool bf3 = can_bf3 && c->prm.precision == FR_FP32_BF16X3;
   int pk;
   if (p.system == FR_EULER) {
     pk = c->prof_begin(("tet_div_euler" + sfx).c_str());
-    tet_div<T, DEV, false><<<div_grid, TDIV_NT, 0, c->stream>>>(u, nullptr, geo, C, O, opT, r, b.E, b.n, (T)p.gamma,
-                                                                (T)0, (T)0, (T)0, (T)0, p.riemann, 0, R);
+    if (bf3)
+      tet_div<T, DEV, false, can_bf3><<<div_grid, TDIV_NT, 0, c->stream>>>(
+          u, nullptr, geo, C, O, opT, opH, opL, r, b.E, b.n, (T)p.gamma, (T)0, (T)0, (T)0, (T)0, p.riemann, 0, R);
+    else
+      tet_div<T, DEV, false, false><<<div_grid, TDIV_NT, 0, c->stream>>>(
+          u, nullptr, geo, C, O, opT, opH, opL, r, b.E, b.n, (T)p.gamma, (T)0, (T)0, (T)0, (T)0, p.riemann, 0, R);
     c->prof_end(pk);
   } else {
     pk = c->prof_begin(("tet_grad" + sfx).c_str());
-    tet_grad_mma<T><<<div_grid, TDIV_NT, 0, c->stream>>>(u, geo, C, O, (const T*)c->tet_ogT, (T*)b.grad, b.E, b.n,
-                                                          (T)p.ldg_beta);
+    if (bf3)
+      tet_grad_mma<T, can_bf3><<<div_grid, TDIV_NT, 0, c->stream>>>(u, geo, C, O, (const T*)c->tet_ogT, ogH, ogL,
+                                                                     (T*)b.grad, b.E, b.n, (T)p.ldg_beta);
+    else
+      tet_grad_mma<T, false><<<div_grid, TDIV_NT, 0, c->stream>>>(u, geo, C, O, (const T*)c->tet_ogT, ogH, ogL,
+                                                                   (T*)b.grad, b.E, b.n, (T)p.ldg_beta);
     c->prof_end(pk);
     pk = c->prof_begin(("tet_div_ns" + sfx).c_str());
-    tet_div<T, DEV, true><<<div_grid, TDIV_NT, 0, c->stream>>>(u, (const T*)b.grad, geo, C, O, opT, r, b.E, b.n,
-                                                               (T)p.gamma, (T)p.mu, (T)p.prandtl, (T)p.ldg_beta,
-                                                               (T)p.ldg_tau, p.riemann, sm, R);
+    if (bf3)
+      tet_div<T, DEV, true, can_bf3><<<div_grid, TDIV_NT, 0, c->stream>>>(
+          u, (const T*)b.grad, geo, C, O, opT, opH, opL, r, b.E, b.n, (T)p.gamma, (T)p.mu, (T)p.prandtl,
+          (T)p.ldg_beta, (T)p.ldg_tau, p.riemann, sm, R);
+    else
+      tet_div<T, DEV, true, false><<<div_grid, TDIV_NT, 0, c->stream>>>(
+          u, (const T*)b.grad, geo, C, O, opT, opH, opL, r, b.E, b.n, (T)p.gamma, (T)p.mu, (T)p.prandtl,
+          (T)p.ldg_beta, (T)p.ldg_tau, p.riemann, sm, R);
     c->prof_end(pk);
   }
   hipError_t e = hipGetLastError();
@@ -458,7 +494,7 @@ fr_status rhs_t(fr_ctx c, const T* u, T* r) {
 
 // RHS of the context's precision on its native state.
 fr_status rhs_native(fr_ctx c, const void* u, void* r) {
-  if (c->prm.precision == FR_FP32) return rhs_t<float, true>(c, (const float*)u, (float*)r);
+  if (c->prm.precision != FR_FP64) return rhs_t<float, true>(c, (const float*)u, (float*)r);
   return rhs_t<double, false>(c, (const double*)u, (double*)r);
 }
 
@@ -739,6 +775,7 @@ void fr_destroy(fr_ctx c) {
   (void)hipFree(c->rk_stage); (void)hipFree(c->rk_acc); (void)hipFree(c->rk_k); (void)hipFree(c->rk_s64);
   (void)hipFree(c->flag);
   (void)hipFree(c->tet_src); (void)hipFree(c->tet_opT); (void)hipFree(c->tet_ogT);
+  (void)hipFree(c->tet_opH); (void)hipFree(c->tet_ogH);
   for (auto& b : c->blocks) {
     (void)hipFree(b.sown); (void)hipFree(b.smin);
     (void)hipFree(b.f_det); (void)hipFree(b.f_list); (void)hipFree(b.f_cnt);
@@ -760,8 +797,9 @@ fr_status fr_setup_mesh(const fr_params* p, int64_t n_vert, const double* xyz, c
   if (!xyz || !period || !etype || !enodes || n_vert <= 0 || n_elem <= 0) return fail(nullptr, FR_ERR_ARG, "empty mesh or NULL array");
   if (p->system != FR_EULER && p->system != FR_NAVIER_STOKES) return fail(nullptr, FR_ERR_ARG, "system");
   if (p->riemann != FR_RUSANOV && p->riemann != FR_HLLC) return fail(nullptr, FR_ERR_ARG, "riemann");
-  if (p->precision != FR_FP64 && p->precision != FR_FP32) return fail(nullptr, FR_ERR_ARG, "precision");
-  if (p->precision == FR_FP32 && (p->u_ref[1] != 0 || p->u_ref[2] != 0 || p->u_ref[3] != 0 ||
+  if (p->precision != FR_FP64 && p->precision != FR_FP32 && p->precision != FR_FP32_BF16X3)
+    return fail(nullptr, FR_ERR_ARG, "precision");
+  if (p->precision != FR_FP64 && (p->u_ref[1] != 0 || p->u_ref[2] != 0 || p->u_ref[3] != 0 ||
                                   !(p->u_ref[0] > 0) || !(p->u_ref[4] > 0)))
     return fail(nullptr, FR_ERR_ARG, "the FP32 form needs a reference state at rest with rho > 0, E > 0");
   if (!(p->gamma > 1.0)) return fail(nullptr, FR_ERR_ARG, "gamma must exceed 1");
@@ -784,7 +822,7 @@ fr_status fr_setup_mesh(const fr_params* p, int64_t n_vert, const double* xyz, c
     delete c;
     return fail(nullptr, s, msg);
   }
-  const size_t tsz = p->precision == FR_FP32 ? sizeof(float) : sizeof(double);
+  const size_t tsz = p->precision != FR_FP64 ? sizeof(float) : sizeof(double);
   int64_t canon = 0, native = 0;
   auto bail = [&](fr_status s) { std::string m = c->err; fr_destroy(c); return fail(nullptr, s, m); };
   for (auto& hb : c->host.blocks) {
@@ -882,6 +920,27 @@ fr_status fr_setup_mesh(const fr_params* p, int64_t n_vert, const double* xyz, c
     std::vector<char> bog(ogT.size() * tsz);
     if (tsz == sizeof(float)) for (size_t i = 0; i < ogT.size(); ++i) ((float*)bog.data())[i] = (float)ogT[i];
     else std::memcpy(bog.data(), ogT.data(), bog.size());
+    if (p->precision == FR_FP32_BF16X3) {
+      // [M][K] row-major (k contiguous), hi then lo, K padded to multiples of 16
+      std::vector<uint16_t> dh((size_t)2 * TET_MP * TET_KP16, 0), gh((size_t)2 * TGR_M * TGR_K, 0);
+      const size_t dlo = (size_t)TET_MP * TET_KP16, glo = (size_t)TGR_M * TGR_K;
+      for (int m = 0; m < TET_MP; ++m) {
+        for (int k = 0; k < 105; ++k) bf16_split_host(opT[(size_t)k * TET_MP + m], dh[(size_t)m * TET_KP16 + k],
+                                                      dh[dlo + (size_t)m * TET_KP16 + k]);
+        for (int s2 = 0; s2 < 60; ++s2)
+          bf16_split_host(opT[(size_t)(TET_KA + s2) * TET_MP + m], dh[(size_t)m * TET_KP16 + TET_KA16 + s2],
+                          dh[dlo + (size_t)m * TET_KP16 + TET_KA16 + s2]);
+      }
+      for (int m = 0; m < TGR_M; ++m)
+        for (int k = 0; k < TGR_K; ++k)
+          bf16_split_host(ogT[(size_t)k * TGR_M + m], gh[(size_t)m * TGR_K + k], gh[glo + (size_t)m * TGR_K + k]);
+      if (dalloc(c, (char**)&c->tet_opH, dh.size() * 2) || dalloc(c, (char**)&c->tet_ogH, gh.size() * 2) ||
+          hipMemcpy(c->tet_opH, dh.data(), dh.size() * 2, hipMemcpyHostToDevice) != hipSuccess ||
+          hipMemcpy(c->tet_ogH, gh.data(), gh.size() * 2, hipMemcpyHostToDevice) != hipSuccess) {
+        c->err = "tet operator upload failed";
+        return bail(FR_ERR_DEVICE);
+      }
+    }
     if (dalloc(c, (char**)&c->tet_opT, bop.size()) || dalloc(c, (char**)&c->tet_ogT, bog.size()) ||
         hipMemcpy(c->tet_opT, bop.data(), bop.size(), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(c->tet_ogT, bog.data(), bog.size(), hipMemcpyHostToDevice) != hipSuccess) {
@@ -909,7 +968,7 @@ fr_status fr_layout(fr_ctx c, fr_layout_t* o) {
   }
   o->canon_len = c->canon_len;
   o->native_len = c->native_len;
-  o->native_dtype = c->prm.precision;
+  o->native_dtype = c->prm.precision == FR_FP64 ? FR_FP64 : FR_FP32;
   return FR_OK;
 }
 
@@ -1009,7 +1068,7 @@ fr_status fr_rk_step(fr_ctx c, void* u_, double dt, int32_t n_steps, int32_t fil
   }
   double* u = (double*)u_;
   const int64_t n = c->native_len;
-  const bool f32 = c->prm.precision == FR_FP32;
+  const bool f32 = c->prm.precision != FR_FP64;
   const size_t tsz = f32 ? sizeof(float) : sizeof(double);
   if (!c->rk_stage) {
     if (dalloc(c, (char**)&c->rk_stage, n * tsz) || dalloc(c, &c->rk_acc, n) || dalloc(c, (char**)&c->rk_k, n * tsz))

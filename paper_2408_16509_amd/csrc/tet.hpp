@@ -120,11 +120,66 @@ struct Mma16<double> {
   __device__ __forceinline__ static int row(int lane, int q) { return lane / 16 + 4 * q; }
 };
 
+// BF16x3 split products: x = hi + lo with hi = bf16(x), lo = bf16(x - hi) (round to
+// nearest even), a b ~ a_hi b_hi + a_hi b_lo + a_lo b_hi accumulated in FP32 by the
+// 16x16x16 bf16 matrix-core product (lane l holds 4 consecutive k of row / column
+// l % 16; output layout as the FP32 product, checked on gfx950 like it).
+typedef short tet_s4 __attribute__((ext_vector_type(4)));
+typedef __bf16 tet_b4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void bf16_split4(const float x[4], tet_s4& hi, tet_s4& lo) {
+  tet_b4 h, l;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    h[t] = (__bf16)x[t];
+    l[t] = (__bf16)(x[t] - (float)h[t]);
+  }
+  hi = __builtin_bit_cast(tet_s4, h);
+  lo = __builtin_bit_cast(tet_s4, l);
+}
+
+// acc[m] += Op[16 m .. 16 m + 15][k] P[k][v][col] over nk rows of the LDS panel starting at
+// panel row pk, operator rows starting at column ko.  FP path: opT[k][ldm] (k-major, FP32 or
+// FP64), steps of 4.  BF16x3 path: opH / opL [M][ldk] bf16 (k contiguous), steps of 16.
+template <typename T, bool BF3, int NM, int NE>
+__device__ __forceinline__ void tet_contract(typename Mma16<T>::V (&acc)[NM], const T* PAN, int pk, int nk, int v,
+                                             int lane, const T* __restrict__ opT, int ko, int ldm,
+                                             const tet_s4* __restrict__ opH, const tet_s4* __restrict__ opL, int ldk) {
+  const int kr = lane / 16, col = lane % 16;
+  if constexpr (!BF3) {
+#pragma unroll 2
+    for (int k0 = 0; k0 < nk; k0 += 4) {
+      const T bop = PAN[((pk + k0 + kr) * 5 + v) * NE + col];
+      const T* arow = opT + (ko + k0 + kr) * ldm + col;
+#pragma unroll
+      for (int m = 0; m < NM; ++m) acc[m] = Mma16<T>::run(arow[m * 16], bop, acc[m]);
+    }
+  } else {
+    for (int k0 = 0; k0 < nk; k0 += 16) {
+      float x[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) x[t] = PAN[((pk + k0 + 4 * kr + t) * 5 + v) * NE + col];
+      tet_s4 bh, bl;
+      bf16_split4(x, bh, bl);
+#pragma unroll
+      for (int m = 0; m < NM; ++m) {
+        const int a = ((m * 16 + col) * ldk + ko + k0 + 4 * kr) / 4;
+        const tet_s4 ah = opH[a], al = opL[a];
+        acc[m] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc[m], 0, 0, 0);
+        acc[m] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc[m], 0, 0, 0);
+        acc[m] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc[m], 0, 0, 0);
+      }
+    }
+  }
+}
+
 // Contraction layout: K rows 0..104 are the transformed fluxes f~_i at the solution
 // points (k = 35 i + point), 105..107 zero, 108..167 the common fluxes at the flux
 // points; output rows are the 35 solution points padded to 48.  opT[k][pt] holds
 // Op = [Dh_0 Dh_1 Dh_2 L] transposed and zero-padded.
 constexpr int TET_KA = 108, TET_KB = 60, TET_KP = TET_KA + TET_KB, TET_MP = 48;
+// the BF16x3 path pads both K chunks to multiples of 16: [0, 112) and [112, 176)
+constexpr int TET_KA16 = 112, TET_KB16 = 64, TET_KP16 = TET_KA16 + TET_KB16;
 constexpr int TDIV_NE = 16, TDIV_NT = 5 * 64;
 
 // Corrected divergence (eq:FRfinal) on the matrix cores: per block of 16 elements,
@@ -133,22 +188,24 @@ constexpr int TDIV_NE = 16, TDIV_NT = 5 * 64;
 // solution points, then the common fluxes at the flux points, into the panel (two K
 // chunks through LDS), and wave v multiplies the 16 columns of variable v by the
 // three 16-row tiles of Op (read through the caches).
-template <typename T, bool DEV, bool NS>
+template <typename T, bool DEV, bool NS, bool BF3>
 __global__ void __launch_bounds__(TDIV_NT) tet_div(const T* __restrict__ u, const T* __restrict__ grad,
                                                    const T* __restrict__ geo, Conn C, TetDev<T> O,
-                                                   const T* __restrict__ opT, T* __restrict__ r, int64_t E, int64_t n,
-                                                   T gamma, T mu, T pr, T beta, T tau, int riemann, int side_mode,
-                                                   RefState<T> R) {
+                                                   const T* __restrict__ opT, const tet_s4* __restrict__ opH,
+                                                   const tet_s4* __restrict__ opL, T* __restrict__ r, int64_t E,
+                                                   int64_t n, T gamma, T mu, T pr, T beta, T tau, int riemann,
+                                                   int side_mode, RefState<T> R) {
   constexpr int NE = TDIV_NE, NT = TDIV_NT;
-  __shared__ T PAN[TET_KA * 5 * NE];     // [k][v][el]; the second K chunk reuses it
+  constexpr int KA = BF3 ? TET_KA16 : TET_KA, KB = BF3 ? TET_KB16 : TET_KB;
+  __shared__ T PAN[KA * 5 * NE];          // [k][v][el]; the second K chunk reuses it
   __shared__ T SJ[10 * NE];
   const int t = threadIdx.x;
-  const int v = t / 64, lane = t % 64, kr = lane / 16, col = lane % 16;
+  const int v = t / 64, lane = t % 64, col = lane % 16;
   const T gm1 = gamma - T(1);
   const int64_t e0 = xcd_block() * NE;
   {
     for (int i = t; i < 10 * NE; i += NT) SJ[i] = geo[(int64_t)(i / NE) * E + e0 + i % NE];
-    for (int i = t; i < 3 * 5 * NE; i += NT) PAN[105 * 5 * NE + i] = T(0);
+    for (int i = t; i < (KA - 105) * 5 * NE; i += NT) PAN[105 * 5 * NE + i] = T(0);
     __syncthreads();
     // K chunk 1: transformed fluxes at the solution points
     for (int it = t; it < NE * TET_NSP; it += NT) {
@@ -179,14 +236,11 @@ __global__ void __launch_bounds__(TDIV_NT) tet_div(const T* __restrict__ u, cons
     typename Mma16<T>::V acc[3];
 #pragma unroll
     for (int mt = 0; mt < 3; ++mt) acc[mt] = typename Mma16<T>::V{0, 0, 0, 0};
-#pragma unroll 2
-    for (int k0 = 0; k0 < TET_KA; k0 += 4) {
-      const T bop = PAN[((k0 + kr) * 5 + v) * NE + col];
-#pragma unroll
-      for (int mt = 0; mt < 3; ++mt) acc[mt] = Mma16<T>::run(opT[(k0 + kr) * TET_MP + mt * 16 + col], bop, acc[mt]);
-    }
+    tet_contract<T, BF3, 3, NE>(acc, PAN, 0, KA, v, lane, opT, 0, TET_MP, opH, opL, TET_KP16);
     __syncthreads();
-    // K chunk 2: common fluxes at the flux points
+    // K chunk 2: common fluxes at the flux points (rows past 60 zero)
+    if constexpr (KB > TET_NFP)
+      for (int i = t; i < (KB - TET_NFP) * 5 * NE; i += NT) PAN[TET_NFP * 5 * NE + i] = T(0);
     for (int it = t; it < NE * TET_NFP; it += NT) {
       const int el = it % NE, sg = it / NE;
       T S[9], F[5];
@@ -197,13 +251,7 @@ __global__ void __launch_bounds__(TDIV_NT) tet_div(const T* __restrict__ u, cons
       for (int c = 0; c < 5; ++c) PAN[(sg * 5 + c) * NE + el] = F[c];
     }
     __syncthreads();
-#pragma unroll 2
-    for (int k0 = 0; k0 < TET_KB; k0 += 4) {
-      const T bop = PAN[((k0 + kr) * 5 + v) * NE + col];
-#pragma unroll
-      for (int mt = 0; mt < 3; ++mt)
-        acc[mt] = Mma16<T>::run(opT[(TET_KA + k0 + kr) * TET_MP + mt * 16 + col], bop, acc[mt]);
-    }
+    tet_contract<T, BF3, 3, NE>(acc, PAN, 0, KB, v, lane, opT, BF3 ? TET_KA16 : TET_KA, TET_MP, opH, opL, TET_KP16);
     const int64_t e = e0 + col;
     const T iJ = T(-1) / SJ[9 * NE + col];
     if (e < n) {
@@ -228,15 +276,16 @@ __global__ void __launch_bounds__(TDIV_NT) tet_div(const T* __restrict__ u, cons
 // the physical gradient S^T gt / J is formed and stored.
 constexpr int TGR_K = 96, TGR_M = 3 * TET_MP;
 
-template <typename T>
+template <typename T, bool BF3>
 __global__ void __launch_bounds__(TDIV_NT) tet_grad_mma(const T* __restrict__ u, const T* __restrict__ geo, Conn C,
-                                                        TetDev<T> O, const T* __restrict__ ogT, T* __restrict__ grad,
-                                                        int64_t E, int64_t n, T beta) {
+                                                        TetDev<T> O, const T* __restrict__ ogT,
+                                                        const tet_s4* __restrict__ ogH, const tet_s4* __restrict__ ogL,
+                                                        T* __restrict__ grad, int64_t E, int64_t n, T beta) {
   constexpr int NE = TDIV_NE, NT = TDIV_NT;
   __shared__ T PAN[TGR_K * 5 * NE];      // [k][v][el]: u at the 35 points, u^ at the 60 flux points, 0
   __shared__ T SJ[10 * NE];
   const int t = threadIdx.x;
-  const int v = t / 64, lane = t % 64, kr = lane / 16, col = lane % 16;
+  const int v = t / 64, lane = t % 64, col = lane % 16;
   const int64_t e0 = xcd_block() * NE;
   {
     for (int i = t; i < 10 * NE; i += NT) SJ[i] = geo[(int64_t)(i / NE) * E + e0 + i % NE];
@@ -262,13 +311,7 @@ __global__ void __launch_bounds__(TDIV_NT) tet_grad_mma(const T* __restrict__ u,
     typename Mma16<T>::V acc[9];
 #pragma unroll
     for (int m = 0; m < 9; ++m) acc[m] = typename Mma16<T>::V{0, 0, 0, 0};
-#pragma unroll 2
-    for (int k0 = 0; k0 < TGR_K; k0 += 4) {
-      const T bop = PAN[((k0 + kr) * 5 + v) * NE + col];
-      const T* arow = ogT + (k0 + kr) * TGR_M + col;
-#pragma unroll
-      for (int m = 0; m < 9; ++m) acc[m] = Mma16<T>::run(arow[m * 16], bop, acc[m]);
-    }
+    tet_contract<T, BF3, 9, NE>(acc, PAN, 0, TGR_K, v, lane, ogT, 0, TGR_M, ogH, ogL, TGR_K);
     const int64_t e = e0 + col;
     if (e < n) {
       T S[9];

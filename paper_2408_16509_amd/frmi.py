@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libfrmi.so")
 
 FR_EULER, FR_NAVIER_STOKES = 0, 1
 FR_RUSANOV, FR_HLLC = 0, 1
-FR_FP64, FR_FP32 = 0, 1
+FR_FP64, FR_FP32, FR_FP32_BF16X3 = 0, 1, 2
 FR_HEX, FR_TET = 0, 1
 STATUS = {0: "FR_OK", 1: "FR_ERR_ARG", 2: "FR_ERR_MESH", 3: "FR_ERR_ALLOC", 4: "FR_ERR_DEVICE",
           5: "FR_ERR_NONFINITE", 6: "FR_ERR_STATE", 7: "FR_ERR_UNSUPPORTED"}

@@ -79,6 +79,29 @@ def test_fp32_rhs_random_tets(system):
     assert g <= 1e-5
 
 
+@pytest.mark.parametrize("system", [0, 1])
+def test_bf16x3_rhs_random_tets(system):
+    """FP32 form with the tetrahedral operator products as BF16x3 split products
+    (FP32 accumulation).  Stated bound for well-conditioned states: 1e-4 relative L2
+    (each product keeps ~16 significant bits of both factors: a relative 2^-16 per
+    term, times the cancellation of the contraction)."""
+    from paper_2408_16509_amd import frmi
+    mesh = inputs.kuhn_split(inputs.hex_box((2, 2, 2), perturb=0.1, perturb_seed=6), permute_seed=3)
+    bl = oracle_blocks(mesh, 4)
+    u = state_for(bl, "random", seed=8)
+    Ro = ofr.rhs(bl, u, oracle_params(system, 0))
+    ctx = frmi.Context(mesh, precision=frmi.FR_FP32_BF16X3, u_ref=UREF_RANDOM, system=system, order=4)
+    ug = ctx.pack(ctx.join_canon(u))
+    r = ctx.new_native()
+    ctx.rhs(ug, r)
+    Rg = _split(ctx.unpack_rhs(r).cpu().numpy(), u)
+    ctx.close()
+    g, pv = rel_err(Rg, Ro)
+    g32, _ = rel_err(gpu_rhs32(mesh, u, system=system, order=4, u_ref=UREF_RANDOM), Ro)
+    print(f"bf16x3 tets sys={system}: global {g:.2e} (fp32 form {g32:.2e}) per-var {np.array2string(pv, precision=2)}")
+    assert g <= 1e-4
+
+
 def test_fp32_reference_state_is_exact():
     mesh = inputs.hex_box((3, 3, 3), perturb=0.1, perturb_seed=2)
     bl = oracle_blocks(mesh, 3)

@@ -36,8 +36,10 @@ CONFIGS = {
                                 perturb=0.1, perturb_seed=31, permute_seed=32),
     # 32x64x64 cells twice, +-10 % perturbed (seed 51): p = 4 hexahedra, and the same
     # cells as 6 p = 4 tetrahedra each (917,504 elements), element order seed 53
+    # timed forms: FP32 + learned filter (headline), FP64 + plain filter, and both unfiltered
     "ns_tgv_mixed_c5split_p4": dict(kind="mixed", n=(32, 64, 64), order=4, system=1, riemann=0, mach=0.1,
-                                    dt=7.5e-5, perturb=0.1, perturb_seed=51, permute_seed=53),
+                                    dt=7.5e-5, perturb=0.1, perturb_seed=51, permute_seed=53,
+                                    forms="fp32:learned,fp64:plain,fp32,fp64"),
     # Mach-3 shock (orientation seed 41, density noise seed 42), Euler + HLLC, entropy
     # filter on every RK stage: plain bisection vs the learned warm start, the MLP
     # trained on the plain filter's data from held-out draws (seeds 101-108 / 201-208)
@@ -135,12 +137,20 @@ def cpu_baseline(mesh, cfg, u_canon_fn):
             "sample": f"1 FP64 oracle RHS over the full mesh ({dof} points), mesh setup excluded, {dt:.1f} s"}, u, R
 
 
-def run_form(form, cfg, mesh, ic, args, torch, np, frmi):
-    """Time `args.steps` RK4 steps of one precision form; per-kernel event timing."""
+FILTER_MODES = {"": -1, "plain": 0, "learned": 1}
+
+
+def run_form(form, cfg, mesh, ic, args, torch, np, frmi, inputs):
+    """Time `args.steps` RK4 steps of one form "<precision>[:plain|:learned]" (the suffix
+    turns the entropy filter on every stage state and new state on); per-kernel event
+    timing.  The learned filter uses the initial (Glorot, seed 43) MLP with identity
+    input scaling unless trained weights are given."""
+    prec, _, fmode = form.partition(":")
+    filter_mode = FILTER_MODES[fmode]
     kw = dict(system=cfg["system"], order=cfg["order"], riemann=cfg["riemann"])
-    if form in ("fp32", "bf16x3"):
+    if prec in ("fp32", "bf16x3"):
         p0 = 1.0 / (1.4 * cfg["mach"] ** 2)
-        kw.update(precision=frmi.FR_FP32 if form == "fp32" else frmi.FR_FP32_BF16X3,
+        kw.update(precision=frmi.FR_FP32 if prec == "fp32" else frmi.FR_FP32_BF16X3,
                   u_ref=(1.0, 0.0, 0.0, 0.0, p0 / 0.4))
     ctx = frmi.Context(mesh, **kw)
     lay = ctx.layout
@@ -152,26 +162,34 @@ def run_form(form, cfg, mesh, ic, args, torch, np, frmi):
         off += n * s
         blocks["hex" if lay.etype[i] == frmi.FR_HEX else "tet"] = (int(n), int(s), int(lay.n_fp[i]))
     u0 = ctx.pack64(np.concatenate(canon))
+    if filter_mode == 1:
+        ctx.mlp_set_weights(inputs.mlp_glorot(43), np.zeros(16), np.ones(16))
     u = u0.clone()
     stream = torch.cuda.current_stream()
     for _ in range(args.warmup):
-        ctx.rk_step(u, cfg["dt"], 1)
+        ctx.rk_step(u, cfg["dt"], 1, filter_mode=filter_mode)
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     wall0 = time.perf_counter()
     ev0.record(stream)
     for _ in range(args.steps):
-        ctx.rk_step(u, cfg["dt"], 1)
+        ctx.rk_step(u, cfg["dt"], 1, filter_mode=filter_mode)
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     ms = ev0.elapsed_time(ev1) / args.steps
     res = {"ctx": ctx, "ms": ms, "wall": wall, "finite": ctx.check(u), "blocks": blocks}
+    if filter_mode >= 0:
+        # the filter on the final state (entropy bound from itself): how many elements it treats
+        uf = u.clone()
+        st = ctx.filter(uf, u, mode=filter_mode, stats=True)
+        res["filter"] = {"mode": fmode, "candidates": int(st.n_candidates), "troubled": int(st.n_troubled),
+                         "evals": int(st.n_evals)}
     if not args.no_kernel_timing:
         uk = u0.clone()
         ctx.profile(True)
         for _ in range(2):
-            ctx.rk_step(uk, cfg["dt"], 1)
+            ctx.rk_step(uk, cfg["dt"], 1, filter_mode=filter_mode)
         res["times"] = ctx.profile_read()
         ctx.profile(False)
     return res
@@ -323,8 +341,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="ns_tgv_hex32_p3", choices=sorted(CONFIGS))
-    ap.add_argument("--forms", default="fp32,fp64",
-                    help="precision forms to time (fp32, fp64, bf16x3); the first is the headline")
+    ap.add_argument("--forms", default=None,
+                    help="forms to time: fp32, fp64 or bf16x3, each optionally with :plain or :learned "
+                         "(entropy filter on); the first is the headline (default: the workload's own)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -362,8 +381,8 @@ def main():
         s = inputs.tgv(xsol[..., 0], xsol[..., 1], xsol[..., 2], mach=cfg["mach"])
         return np.moveaxis(s, 0, 1).copy()
 
-    forms = [f.strip() for f in args.forms.split(",") if f.strip()]
-    runs = {f: run_form(f, cfg, mesh, ic, args, torch, np, frmi) for f in forms}
+    forms = [f.strip() for f in (args.forms or cfg.get("forms", "fp32,fp64")).split(",") if f.strip()]
+    runs = {f: run_form(f, cfg, mesh, ic, args, torch, np, frmi, inputs) for f in forms}
     head = runs[forms[0]]
     blocks = head["blocks"]
     E = sum(b[0] for b in blocks.values())
@@ -381,7 +400,7 @@ def main():
         "metric": "RHS GDoF/s (FP32/learned vs FP64 plain) at stated L2 error; % HBM roofline",
         "value": round(gdofs[forms[0]], 4), "unit": "GDoF/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(head["ms"], 4), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": {"fp32": "f32", "bf16x3": "f32+bf16x3"}.get(forms[0], "f64"), "data": "synthetic",
+        "vs_baseline": None, "dtype": {"fp32": "f32", "bf16x3": "f32+bf16x3"}.get(forms[0].split(":")[0], "f64"), "data": "synthetic",
         "config": {"workload": args.config, "elements": int(E), "order": cfg["order"],
                    "blocks": {k: {"elements": v[0], "points_per_elem": v[1]} for k, v in blocks.items()},
                    "dof": int(dof), "rhs_per_step": 4, "form": forms[0],
@@ -389,6 +408,9 @@ def main():
                    "wall_s_timed": round(head["wall"], 3)},
         "forms": {f: {"gdof_s": round(gdofs[f], 4), "ms_per_step": round(runs[f]["ms"], 4)} for f in forms},
     }
+    for f in forms:
+        if "filter" in runs[f]:
+            out["forms"][f]["filter_on_final_state"] = runs[f]["filter"]
     if not args.no_kernel_timing:
         times = head["times"]
         fam = {k: v for k, v in times.items() if kbytes(k) is not None}
@@ -403,7 +425,7 @@ def main():
                            "kernel": dom, "avg_launch_ms": round(avg_ms, 4), "bytes_per_launch": int(by)}
         for f in forms:
             out["forms"][f]["kernels_ms_per_step"] = {k: round(v[1] / 2, 4) for k, v in sorted(runs[f]["times"].items())}
-            bpd = 80 if f == "fp64" else 40
+            bpd = 80 if f.startswith("fp64") else 40
             out["forms"][f]["rhs_m0_fraction"] = round(4 * dof * bpd / (runs[f]["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
     if not args.no_cpu_baseline and not cfg.get("oracle_ok", False):
         out["cpu_baseline"] = None

@@ -166,8 +166,8 @@ fr_status fr_rhs(fr_ctx ctx, const void* u_dev, void* r_dev);
  * The filter is applied to every stage state and to the new state, with the
  * entropy bound taken from the state at the start of the step.  In the FP32 form
  * the right-hand sides run on FP32 deviations while the stage states, the
- * accumulation and the filter (with its checks) stay FP64.  Hexahedra only for
- * filter_mode >= 0 (FR_ERR_UNSUPPORTED with tetrahedra). */
+ * accumulation and the filter (with its checks) stay FP64.  Both element types
+ * (the filter treats each block with its own modal basis). */
 fr_status fr_rk_step(fr_ctx ctx, void* u_dev, double dt, int32_t n_steps, int32_t filter_mode);
 
 /* Entropy-bounded modal filter (Sec. "Numerical Stability", entropy filtering)
@@ -175,7 +175,11 @@ fr_status fr_rk_step(fr_ctx ctx, void* u_dev, double dt, int32_t n_steps, int32_
  * neighbourhood is taken from u_prev (may equal u).  mode 0 plain bisection,
  * 1 MLP warm start (weights must be set).  k_dev (device, [sum n_elem] int32,
  * canonical element order, or NULL) receives the dyadic strength index
- * (0 untouched, -1 fallback).  stats (host, or NULL) synchronises. */
+ * (0 untouched, -1 fallback).  stats (host, or NULL) synchronises.
+ * Modes: tensor Legendre (hexahedra, exponent (i^2 + j^2 + k^2) / p^2) or the
+ * orthonormal basis graded by total degree d (tetrahedra, exponent (d / p)^2).
+ * Check points: solution and flux points (on the tetrahedra the flux points
+ * coincide with solution points). */
 fr_status fr_filter(fr_ctx ctx, void* u_dev, const void* u_prev_dev, int32_t mode,
                     int32_t* k_dev, fr_filter_stats* stats);
 

@@ -253,6 +253,44 @@ __device__ void hex_load_modal(HexFiltSmem<P>& S, const double* __restrict__ u, 
   hex_to_modal<P>(X, Y, &S.U[0][0], 5, K);
 }
 
+// The search shared by the element types, for an element that fails the checks at
+// zeta = 0.  G(k) evaluates the checks at zeta = k zeta_max / 2^n (block-uniform).
+// Plain (mode 0): G(2^n) false -> fallback, else bisection on [0, 2^n] keeping G(lo)
+// false and G(hi) true.  Warm start (mode 1): the predicted index kh gives the bracket
+// [floor(kh / 2), ceil(2 kh)]; its ends are evaluated and the bisection continues in
+// whichever bracket keeps that invariant.  Returns hi (meaningless with fallback).
+template <typename Gf>
+__device__ int64_t dyadic_search(const FiltPrm& F, int mode, float kh_in, Gf& G, bool& fallback) {
+  const int64_t N = (int64_t)1 << F.n_bits;
+  int64_t lo = 0, hi = N;
+  fallback = false;
+  if (mode == 1) {
+    double kh = (double)kh_in;
+    kh = fmin(fmax(kh, 1.0), (double)N);
+    const int64_t blo = (int64_t)floor(kh / 2), bhi = min((int64_t)ceil(2 * kh), N);
+    const bool g_hi = G(bhi);
+    if (g_hi) {
+      bool g_lo = false;
+      if (blo > 0) g_lo = G(blo);
+      if (g_lo) { lo = 0; hi = blo; }
+      else { lo = blo; hi = bhi; }
+    } else {
+      lo = bhi; hi = N;
+      fallback = bhi >= N ? true : !G(N);
+    }
+  } else {
+    fallback = !G(N);
+  }
+  if (!fallback) {
+    while (hi - lo > 1) {
+      const int64_t mid = (lo + hi) / 2;
+      if (G(mid)) hi = mid;
+      else lo = mid;
+    }
+  }
+  return hi;
+}
+
 // One element on a block: exact check at zeta = 0, search (mode 0 plain,
 // 1 warm start from the predicted index kh) and application of the filter.  With
 // `preloaded` the modal coefficients are already in S.U and the check at zeta = 0
@@ -278,39 +316,14 @@ __device__ void hex_filter_elem(HexFiltSmem<P>& S, double* __restrict__ u, const
     }
     return;
   }
-  const int64_t N = (int64_t)1 << F.n_bits;
-  const double dz = F.zeta_max / (double)N;
+  const double dz = F.zeta_max / (double)((int64_t)1 << F.n_bits);
   auto G = [&](int64_t k) {
     hex_set_w<P>(S, K, (double)k * dz);
     ++evals;
     return hex_eval_checks<P>(S, smin, F, nullptr, Dev32{}, E, e);
   };
-  int64_t lo = 0, hi = N;
   bool fallback = false;
-  if (mode == 1) {
-    double kh = (double)kh_in;
-    kh = fmin(fmax(kh, 1.0), (double)N);
-    const int64_t blo = (int64_t)floor(kh / 2), bhi = min((int64_t)ceil(2 * kh), N);
-    const bool g_hi = G(bhi);
-    if (g_hi) {
-      bool g_lo = false;
-      if (blo > 0) g_lo = G(blo);
-      if (g_lo) { lo = 0; hi = blo; }
-      else { lo = blo; hi = bhi; }
-    } else {
-      lo = bhi; hi = N;
-      fallback = bhi >= N ? true : !G(N);
-    }
-  } else {
-    fallback = !G(N);
-  }
-  if (!fallback) {
-    while (hi - lo > 1) {
-      const int64_t mid = (lo + hi) / 2;
-      if (G(mid)) hi = mid;
-      else lo = mid;
-    }
-  }
+  const int64_t hi = dyadic_search(F, mode, kh_in, G, fallback);
   const double zeta = fallback ? F.zeta_max : (double)hi * dz;
   hex_set_w<P>(S, K, zeta);
   (void)hex_eval_checks<P>(S, smin, F, u, s32, E, e);

@@ -11,6 +11,7 @@
 
 #include "../../include/frmi.h"
 #include "filter.hpp"
+#include "filter_tet.hpp"
 #include "hex.hpp"
 #include "mlp.hpp"
 #include "setup.hpp"
@@ -108,6 +109,7 @@ struct fr_ctx_s {
   void* tet_ogH = nullptr;    // BF16x3 split of the gradient operator: hi [TGR_M][TGR_K], then lo
   double* rk_s64 = nullptr;   // FP64 stage state of the filtered FP32 form    // [TET_KP][TET_MP] transposed divergence operator
   int32_t* tet_src = nullptr;
+  double* tet_ftab = nullptr; // entropy filter on tetrahedra: modal operators, weights, multiplicities
   // training-data collection during filtered RK steps (fr_mlp_collect)
   bool collecting = false;
   float* col_x = nullptr;
@@ -535,6 +537,29 @@ FiltPrm filtprm_of(const fr_params& p, int order) {
 
 fr_status filter_alloc(fr_ctx c) {
   if (c->f_k) return FR_OK;
+  bool has_tet = false;
+  for (auto& b : c->blocks) has_tet = has_tet || b.etype == FR_TET;
+  if (has_tet && !c->tet_ftab) {
+    // V^T, V^{-1} transposed, normalised weights, check-point multiplicities
+    const TetOps& T = c->host.tet;
+    std::vector<double> tab(TF_LEN);
+    double wsum = 0;
+    for (int z = 0; z < TF_NSP; ++z) wsum += T.weights[z];
+    for (int m = 0; m < TF_NSP; ++m) {
+      if (T.deg[m] != tet_mode_deg(m)) return fail(c, FR_ERR_STATE, "tetrahedral modes not graded by degree");
+      for (int z = 0; z < TF_NSP; ++z) {
+        tab[TF_VT + m * TF_NSP + z] = T.V[z][m];
+        tab[TF_VIT + z * TF_NSP + m] = T.Vinv[m][z];
+      }
+    }
+    for (int z = 0; z < TF_NSP; ++z) {
+      tab[TF_W + z] = T.weights[z] / wsum;
+      tab[TF_MULT + z] = 1.0;
+    }
+    for (int f = 0; f < TetOps::nfp; ++f) tab[TF_MULT + T.fp_src[f]] += 1.0;
+    if (dalloc(c, &c->tet_ftab, TF_LEN)) return FR_ERR_ALLOC;
+    HIP_TRY(c, hipMemcpy(c->tet_ftab, tab.data(), TF_LEN * sizeof(double), hipMemcpyHostToDevice));
+  }
   const int64_t n = c->n_elem_total;
   for (auto& b : c->blocks)
     if (dalloc(c, &b.sown, b.E) || dalloc(c, &b.smin, b.E) || dalloc(c, &b.f_det, b.n) ||
@@ -619,9 +644,68 @@ void hex_filter_p(fr_ctx c, DevBlock& b, double* u, int mode, float* u32) {
   c->prof_end(pk);
 }
 
+inline unsigned wave_list_grid(const DevBlock& b) {
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>((b.n + 3) / 4, 2048));
+}
+
+void tet_smin(fr_ctx c, DevBlock& b, const double* uprev) {
+  const int g = (int)((b.n + 255) / 256);
+  unsigned long long* sown = (unsigned long long*)b.sown;
+  int pk = c->prof_begin("filter_smin");
+  tet_sown<<<g, 256, 0, c->stream>>>(uprev + b.native_off, sown, b.E, b.n, c->prm.gamma);
+  elem_smin<<<g, 256, 0, c->stream>>>(sown, b.nbr_elem, b.nfaces, b.smin, b.E, b.n);
+  c->prof_end(pk);
+}
+
+void tet_candidates(fr_ctx c, DevBlock& b, const double* u) {
+  const FiltPrm F = filtprm_of(c->prm, c->prm.order);
+  const int64_t o = b.elem_off;
+  const int nb = (int)((b.n + 255) / 256);
+  int pk = c->prof_begin("filter_detect");
+  k_filter_reset<<<grid_for(b.n, 256), 256, 0, c->stream>>>(b.f_det, c->f_k + o, c->f_evals + o, b.n);
+  tet_filter_detect<<<nb, 256, 0, c->stream>>>(u + b.native_off, b.smin, b.E, b.n, F, b.f_det);
+  k_flag_count<<<nb, 256, 0, c->stream>>>(b.f_det, b.n, b.f_cnt);
+  k_scan_counts<<<1, 1024, 0, c->stream>>>(b.f_cnt, nb);
+  k_flag_scatter<<<nb, 256, 0, c->stream>>>(b.f_det, b.n, b.f_cnt, b.f_list);
+  c->prof_end(pk);
+}
+
+void tet_features_b(fr_ctx c, DevBlock& b, const double* u) {
+  const FiltPrm F = filtprm_of(c->prm, c->prm.order);
+  const int64_t o = b.elem_off;
+  const int nb = (int)((b.n + 255) / 256);
+  k_fill_i32<<<grid_for(b.n, 256), 256, 0, c->stream>>>(c->f_flag + o, b.n, 0);
+  tet_features<<<wave_list_grid(b), 256, 0, c->stream>>>(u + b.native_off, b.smin, b.E, b.f_list, b.f_cnt + nb,
+                                                         c->tet_ftab, F, c->f_flag + o, c->f_feat + o * 16);
+}
+
+void tet_filter_b(fr_ctx c, DevBlock& b, double* u, int mode, float* u32) {
+  const FiltPrm F = filtprm_of(c->prm, c->prm.order);
+  const int64_t o = b.elem_off;
+  const int nb = (int)((b.n + 255) / 256);
+  Dev32 s32{u32 ? u32 + b.native_off : nullptr, {0, 0, 0, 0, 0}};
+  for (int v = 0; v < 5; ++v) s32.ref[v] = c->prm.u_ref[v];
+  tet_candidates(c, b, u);
+  int pk;
+  if (mode == 1) {
+    pk = c->prof_begin("filter_search_learned");
+    tet_filter_learned<<<wave_list_grid(b), 256, 0, c->stream>>>(u + b.native_off, b.smin, b.E, b.f_list,
+                                                                 b.f_cnt + nb, c->tet_ftab, F, c->m_w, c->m_scale,
+                                                                 c->f_k + o, c->f_evals + o, s32);
+  } else {
+    pk = c->prof_begin("filter_search_plain");
+    tet_filter<<<wave_list_grid(b), 256, 0, c->stream>>>(u + b.native_off, b.smin, b.E, b.f_list, b.f_cnt + nb,
+                                                         c->tet_ftab, F, c->f_k + o, c->f_evals + o, s32);
+  }
+  c->prof_end(pk);
+}
+
 fr_status compute_smin(fr_ctx c, const double* uprev) {
   for (auto& b : c->blocks) {
-    if (b.etype != FR_HEX) return fail(c, FR_ERR_UNSUPPORTED, "entropy filter: tetrahedra not yet available");
+    if (b.etype == FR_TET) {
+      tet_smin(c, b, uprev);
+      continue;
+    }
     switch (c->prm.order) {
       case 1: hex_smin_p<1>(c, b, uprev); break;
       case 2: hex_smin_p<2>(c, b, uprev); break;
@@ -644,7 +728,10 @@ fr_status apply_filter(fr_ctx c, double* u, int mode, float* u32) {
     if (st) return st;
   }
   for (auto& b : c->blocks) {
-    if (b.etype != FR_HEX) return fail(c, FR_ERR_UNSUPPORTED, "entropy filter: tetrahedra not yet available");
+    if (b.etype == FR_TET) {
+      tet_filter_b(c, b, u, mode, u32);
+      continue;
+    }
     switch (c->prm.order) {
       case 1: hex_filter_p<1>(c, b, u, mode, u32); break;
       case 2: hex_filter_p<2>(c, b, u, mode, u32); break;
@@ -677,6 +764,11 @@ void hex_candidate_features_p(fr_ctx c, DevBlock& b, const double* u) {
 
 fr_status candidate_features(fr_ctx c, const double* u) {
   for (auto& b : c->blocks) {
+    if (b.etype == FR_TET) {
+      tet_candidates(c, b, u);
+      tet_features_b(c, b, u);
+      continue;
+    }
     switch (c->prm.order) {
       case 1: hex_candidate_features_p<1>(c, b, u); break;
       case 2: hex_candidate_features_p<2>(c, b, u); break;
@@ -775,7 +867,7 @@ void fr_destroy(fr_ctx c) {
   (void)hipFree(c->rk_stage); (void)hipFree(c->rk_acc); (void)hipFree(c->rk_k); (void)hipFree(c->rk_s64);
   (void)hipFree(c->flag);
   (void)hipFree(c->tet_src); (void)hipFree(c->tet_opT); (void)hipFree(c->tet_ogT);
-  (void)hipFree(c->tet_opH); (void)hipFree(c->tet_ogH);
+  (void)hipFree(c->tet_opH); (void)hipFree(c->tet_ogH); (void)hipFree(c->tet_ftab);
   for (auto& b : c->blocks) {
     (void)hipFree(b.sown); (void)hipFree(b.smin);
     (void)hipFree(b.f_det); (void)hipFree(b.f_list); (void)hipFree(b.f_cnt);

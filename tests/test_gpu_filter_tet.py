@@ -1,0 +1,256 @@
+"""GPU entropy filter on order-4 tetrahedra (and on a mixed hexahedral + tetrahedral
+context) against the FP64 oracle, with the bars of the hexahedral filter tests:
+every dyadic index k equals the oracle's, filtered states agree to 1e-12 relative,
+untouched elements stay bit-identical, every check point of the result satisfies the
+bounds (oracle's check), element means are kept; features to 2e-5 (stored in FP32).
+
+Workload: 3^3 periodic cells cut into 6 tetrahedra each (element order seed 5), the
+Mach-3 shock of the shock workload at the oracle's solution points, filtered, then one
+RK4 step (Euler, HLLC) with the filter on the stage states; the step's result holds
+the elements the filter must treat.
+"""
+import numpy as np
+import pytest
+
+from oracle import entropy_filter as ef
+from oracle import fr as ofr
+from oracle import mlp as omlp
+from oracle import rk as ork
+from paper_2408_16509_amd import inputs
+
+from helpers import oracle_blocks
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+FP = ef.FilterParams()
+DT = 1e-2
+
+
+def tet_mesh(n=3):
+    return inputs.kuhn_split(inputs.hex_box((n, n, n)), permute_seed=5)
+
+
+MIXED_SHIFT = 3.0 + np.pi     # x offset of the tetrahedral box's centre
+
+
+def mixed_mesh(n=3):
+    """A hexahedral box and, offset in x, the same cells as tetrahedra (no shared faces)."""
+    a = inputs.hex_box((n, n, n))
+    lo = (MIXED_SHIFT - np.pi, -np.pi, -np.pi)
+    b = inputs.kuhn_split(inputs.hex_box((n, n, n), lo=lo, hi=tuple(v + 2 * np.pi for v in lo)))
+    return inputs.concat([a, b], permute_seed=7)
+
+
+def shock_states(mesh, order, fp=FP, dt=DT, shifts=None):
+    """(blocks, u0, u1): u0 = filtered shock state; u1 = one RK4 step from u0 with the
+    filter on the stage states (u1 itself unfiltered), per block.  shifts[i]: x offset
+    of block i's shock plane (each box gets the shock through its own centre)."""
+    bl = oracle_blocks(mesh, order)
+    sh = shifts or [0.0] * len(bl)
+    ic = [np.moveaxis(inputs.shock(b.xsol[..., 0] - d, b.xsol[..., 1], b.xsol[..., 2]), 0, 1).copy()
+          for b, d in zip(bl, sh)]
+    u0 = ef.entropy_filter(bl, ic, ic, fp)[0]
+    smin0 = ef.smin_neighbourhood(bl, u0, fp)
+    stage = lambda s: [ef.filter_block(b, ss, sm, fp)[0] for b, ss, sm in zip(bl, s, smin0)]
+    prm = ofr.Params(riemann=1)
+    u1 = ork.rk4_step(lambda s: ofr.rhs(bl, stage(s), prm), u0, dt)
+    return bl, u0, u1
+
+
+@pytest.fixture(scope="module")
+def case():
+    mesh = tet_mesh()
+    return (mesh,) + shock_states(mesh, 4)
+
+
+def _ctx(mesh, **kw):
+    from paper_2408_16509_amd import frmi
+    return frmi.Context(mesh, system=0, order=4, riemann=1, **kw)
+
+
+def _flat(blocks_u):
+    return np.concatenate([u.ravel() for u in blocks_u])
+
+
+def _split(flat, like):
+    out, o = [], 0
+    for u in like:
+        out.append(flat[o:o + u.size].reshape(u.shape))
+        o += u.size
+    return out
+
+
+def _check_filtered(bl, got, u1, uo, ko, smin, fp=FP):
+    for b, g, u, r, k, sm in zip(bl, got, u1, uo, ko, smin):
+        assert np.array_equal(g[k == 0], u[k == 0])
+        sel = k != 0
+        if np.any(sel):
+            err = np.linalg.norm(g[sel] - r[sel]) / np.linalg.norm(r[sel])
+            assert err <= 1e-12, err
+        assert ef.admissible(b, g, sm, fp)[0].all()
+        np.testing.assert_allclose(g @ b.ops.weights, u @ b.ops.weights, rtol=1e-13)
+
+
+def test_tet_filter_matches_oracle(case):
+    mesh, bl, u0, u1 = case
+    smin = ef.smin_neighbourhood(bl, u0, FP)
+    uo, ko, evo = ef.filter_block(bl[0], u1[0], smin[0], FP)
+    ctx = _ctx(mesh)
+    ug = ctx.pack64(u1[0].ravel())
+    up = ctx.pack64(u0[0].ravel())
+    k = torch.zeros(len(bl[0].elems), dtype=torch.int32, device="cuda")
+    st = ctx.filter(ug, up, mode=0, k=k, stats=True)
+    kg = k.cpu().numpy()
+    got = ctx.unpack64(ug).cpu().numpy().reshape(u1[0].shape)
+    print(f"tets {len(kg)}: troubled {st.n_troubled} (oracle {(ko != 0).sum()}), candidates {st.n_candidates}, "
+          f"evals {st.n_evals} (oracle {evo[ko != 0].sum()})", flush=True)
+    assert (ko != 0).sum() > 20
+    assert np.array_equal(kg, ko)
+    assert st.n_troubled == (ko != 0).sum() and st.n_evals == evo[ko != 0].sum()
+    _check_filtered(bl, [got], u1, [uo], [ko], smin)
+
+
+def test_tet_filter_fallback_matches_oracle(case):
+    """A strength cap too low to restore the bounds: every troubled element takes the
+    capped strength (k = -1), as in the oracle."""
+    mesh, bl, u0, u1 = case
+    fp = ef.FilterParams(zeta_max_coef=0.02)
+    smin = ef.smin_neighbourhood(bl, u0, fp)
+    uo, ko, evo = ef.filter_block(bl[0], u1[0], smin[0], fp)
+    ctx = _ctx(mesh, filt_zeta_max_coef=0.02)
+    ug = ctx.pack64(u1[0].ravel())
+    k = torch.zeros(len(bl[0].elems), dtype=torch.int32, device="cuda")
+    st = ctx.filter(ug, ctx.pack64(u0[0].ravel()), mode=0, k=k, stats=True)
+    kg = k.cpu().numpy()
+    got = ctx.unpack64(ug).cpu().numpy().reshape(u1[0].shape)
+    print(f"fallback {st.n_fallback} of {st.n_troubled} (oracle {(ko < 0).sum()} of {(ko != 0).sum()})", flush=True)
+    assert (ko < 0).sum() > 0
+    assert np.array_equal(kg, ko)
+    sel = ko != 0
+    assert np.array_equal(got[~sel], u1[0][~sel])
+    assert np.linalg.norm(got[sel] - uo[sel]) <= 1e-12 * np.linalg.norm(uo[sel])
+
+
+def test_tet_features_match_oracle(case):
+    mesh, bl, u0, u1 = case
+    smin = ef.smin_neighbourhood(bl, u0, FP)[0]
+    Fo = ef.features(bl[0], u1[0], smin, FP)
+    ok0 = ef.admissible(bl[0], u1[0], smin, FP)[0]
+    ctx = _ctx(mesh)
+    x, el, k, n = ctx.mlp_features(ctx.pack64(u1[0].ravel()), ctx.pack64(u0[0].ravel()), cap=len(bl[0].elems))
+    el = el.cpu().numpy()
+    assert n == (~ok0).sum() and np.array_equal(el, np.nonzero(~ok0)[0])
+    np.testing.assert_allclose(x.cpu().numpy(), Fo[el], rtol=2e-5, atol=2e-5)
+    _, ko, _ = ef.filter_block(bl[0], u1[0], smin, FP)
+    assert np.array_equal(k.cpu().numpy(), ko[el])
+
+
+def _ambiguous(khat, n_bits, rel=4e-6):
+    """Elements whose warm-start bracket ends floor(k^/2), ceil(2 k^) could move under a
+    relative change rel of k^ (the GPU's FP32 forward pass against the oracle's FP64);
+    k^ is clipped to [1, 2^n] on both sides, so values clear of those ends by more than
+    rel clip alike."""
+    N = 2.0 ** n_bits
+    kh = np.clip(khat, 1.0, N)
+    out = np.abs(khat - 1.0) <= rel
+    out |= np.abs(khat - N) <= rel * N
+    inner = (khat > 1.0) & (khat < N)
+    for a in (kh / 2, 2 * kh):
+        out |= inner & (np.abs(a - np.round(a)) <= rel * a)
+    return out
+
+
+def test_tet_learned_filter_matches_oracle(case):
+    """Warm start from fixed MLP weights (Glorot, output layer scaled by 0.1 and its bias
+    set so that the predicted index spreads around 16): the oracle, given its own
+    features and its FP64 forward pass, takes the same brackets; k and the evaluation
+    counts agree wherever a bracket end is not within a relative 4e-6 of an integer
+    boundary (about 5 times the FP32 forward pass's error on this case; elsewhere the
+    bracket may differ, and with it k where the checks are not monotone in zeta; those
+    results must still satisfy the bounds)."""
+    mesh, bl, u0, u1 = case
+    smin = ef.smin_neighbourhood(bl, u0, FP)[0]
+    Fo = ef.features(bl[0], u1[0], smin, FP)
+    w = omlp.glorot_init(43)
+    omlp.unpack(w)["w3"][...] *= 0.1
+    w[-1] = 4.0 / FP.n_bits
+    xm, xs = Fo.mean(axis=0), Fo.std(axis=0) + 1e-3
+    w32 = w.astype(np.float32).astype(np.float64)
+    y = omlp.forward(w32, (Fo - xm.astype(np.float32)) / xs.astype(np.float32))
+    khat = 2.0 ** (FP.n_bits * y)
+    uo, ko, evo = ef.filter_block(bl[0], u1[0], smin, FP, khat=khat)
+    amb = _ambiguous(khat, FP.n_bits) & (ko != 0)
+    ctx = _ctx(mesh)
+    ctx.mlp_set_weights(w, xm, xs)
+    ug = ctx.pack64(u1[0].ravel())
+    k = torch.zeros(len(bl[0].elems), dtype=torch.int32, device="cuda")
+    st = ctx.filter(ug, ctx.pack64(u0[0].ravel()), mode=1, k=k, stats=True)
+    got = ctx.unpack64(ug).cpu().numpy().reshape(u1[0].shape)
+    kg = k.cpu().numpy()
+    print(f"learned: evals {st.n_evals} (oracle {evo[ko != 0].sum()}), troubled {st.n_troubled}, "
+          f"ambiguous brackets {amb.sum()}, k differing there {(kg != ko)[amb].sum()}", flush=True)
+    assert amb.sum() <= 0.1 * (ko != 0).sum()
+    assert np.array_equal(kg[~amb], ko[~amb])
+    assert st.n_troubled == (ko != 0).sum()
+    if not amb.any():
+        assert st.n_evals == evo[ko != 0].sum()
+    keep = ~amb
+    _check_filtered(bl, [np.where(keep[:, None, None], got, uo)], u1, [uo], [ko], [smin])
+    assert ef.admissible(bl[0], got, smin, FP)[0].all()
+
+
+def test_tet_filtered_rk_step_matches_oracle(case):
+    """One RK4 step with the plain filter on every stage state and on the new state."""
+    mesh, bl, u0, _ = case
+    smin0 = ef.smin_neighbourhood(bl, u0, FP)
+    post = lambda s: [ef.filter_block(b, ss, sm, FP)[0] for b, ss, sm in zip(bl, s, smin0)]
+    uo = ork.rk4_step(lambda s: ofr.rhs(bl, s, ofr.Params(riemann=1)), u0, DT, stage_post=post)[0]
+    ctx = _ctx(mesh)
+    ug = ctx.pack64(u0[0].ravel())
+    ctx.rk_step(ug, DT, 1, filter_mode=0)
+    got = ctx.unpack64(ug).cpu().numpy().reshape(uo.shape)
+    err = np.linalg.norm(got - uo) / np.linalg.norm(uo - u0[0])
+    print(f"filtered RK4 step on tets: relative error of the increment {err:.2e}", flush=True)
+    assert err <= 1e-10
+    assert ctx.check(ug)
+
+
+def test_tet_filtered_rk_step_fp32_form(case):
+    """The same step in the FP32 deviation form; bound as for hexahedra (1e-4 of the
+    increment, every check point within the bounds)."""
+    from paper_2408_16509_amd import frmi
+    mesh, bl, u0, _ = case
+    smin0 = ef.smin_neighbourhood(bl, u0, FP)
+    post = lambda s: [ef.filter_block(b, ss, sm, FP)[0] for b, ss, sm in zip(bl, s, smin0)]
+    uo = ork.rk4_step(lambda s: ofr.rhs(bl, s, ofr.Params(riemann=1)), u0, DT, stage_post=post)[0]
+    ctx = _ctx(mesh, precision=frmi.FR_FP32, u_ref=(1.0, 0.0, 0.0, 0.0, 1.0 / 0.4))
+    ug = ctx.pack64(u0[0].ravel())
+    ctx.rk_step(ug, DT, 1, filter_mode=0)
+    got = ctx.unpack64(ug).cpu().numpy().reshape(uo.shape)
+    err = np.linalg.norm(got - uo) / np.linalg.norm(uo - u0[0])
+    ok, _ = ef.admissible(bl[0], got, smin0[0], FP)
+    print(f"filtered RK4 step on tets, FP32 form: relative error of the increment {err:.2e}", flush=True)
+    assert err <= 1e-4
+    assert ok.all()
+
+
+def test_mixed_context_filter_matches_oracle():
+    """Both blocks of a hexahedral + tetrahedral context filtered in one call."""
+    mesh = mixed_mesh()
+    bl, u0, u1 = shock_states(mesh, 4, shifts=[0.0, MIXED_SHIFT])
+    smin = ef.smin_neighbourhood(bl, u0, FP)
+    res = [ef.filter_block(b, u, sm, FP) for b, u, sm in zip(bl, u1, smin)]
+    ko = [r[1] for r in res]
+    ctx = _ctx(mesh)
+    lay = ctx.layout
+    assert [lay.etype[i] for i in range(lay.n_types)] == [b.etype for b in bl]
+    ug = ctx.pack64(_flat(u1))
+    k = torch.zeros(sum(len(b.elems) for b in bl), dtype=torch.int32, device="cuda")
+    st = ctx.filter(ug, ctx.pack64(_flat(u0)), mode=0, k=k, stats=True)
+    got = _split(ctx.unpack64(ug).cpu().numpy(), u1)
+    kg = k.cpu().numpy()
+    print(f"mixed: troubled {st.n_troubled} (oracle hex {(ko[0] != 0).sum()}, tet {(ko[1] != 0).sum()})", flush=True)
+    assert all((kk != 0).sum() > 0 for kk in ko)
+    assert np.array_equal(kg, np.concatenate(ko))
+    _check_filtered(bl, got, u1, [r[0] for r in res], ko, smin)

@@ -89,6 +89,12 @@ def kernel_bytes_per_elem(name, nsp, nfp):
         "tet_grad": d * (5 * nsp + 15 * nsp) + tet_gc,
         "tet_div_ns": d * (5 * nsp + 15 * nsp + 5 * nsp) + tet_gc,
     }
+    if d == 4:
+        # FP32 form, one-sided LDG: the gradient kernel also stores the common flux of
+        # each flux-point pair once (half of the flux points), the divergence kernel
+        # reads it for all of its flux points
+        table["tet_grad"] += d * 5 * nfp // 2
+        table["tet_div_ns"] += d * 5 * nfp
     return table.get(fam)
 
 

@@ -424,6 +424,7 @@ fr_status tet_rhs(fr_ctx c, DevBlock& b, const T* u, T* r) {
   const fr_params& p = c->prm;
   TetDev<T> O;
   O.src = c->tet_src;
+  O.pfp = c->tet_src + 60;
   for (int f = 0; f < 4; ++f)
     for (int k = 0; k < 3; ++k) O.nref[f][k] = (T)c->host.tet.nref[f][k];
   const RefState<T> R = ref_of<T>(p);
@@ -438,33 +439,49 @@ fr_status tet_rhs(fr_ctx c, DevBlock& b, const T* u, T* r) {
   constexpr bool can_bf3 = sizeof(T) == 4;
   const bool bf3 = can_bf3 && c->prm.precision == FR_FP32_BF16X3;
   int pk;
+  const T zero = T(0);
   if (p.system == FR_EULER) {
     pk = c->prof_begin(("tet_div_euler" + sfx).c_str());
     if (bf3)
-      tet_div<T, DEV, false, can_bf3><<<div_grid, TDIV_NT, 0, c->stream>>>(
-          u, nullptr, geo, C, O, opT, opH, opL, r, b.E, b.n, (T)p.gamma, (T)0, (T)0, (T)0, (T)0, p.riemann, 0, R);
+      tet_div<T, DEV, false, can_bf3, false><<<div_grid, TDIV_NT, 0, c->stream>>>(
+          u, nullptr, nullptr, geo, C, O, opT, opH, opL, r, b.E, b.n, (T)p.gamma, zero, zero, zero, zero, p.riemann, 0,
+          R);
     else
-      tet_div<T, DEV, false, false><<<div_grid, TDIV_NT, 0, c->stream>>>(
-          u, nullptr, geo, C, O, opT, opH, opL, r, b.E, b.n, (T)p.gamma, (T)0, (T)0, (T)0, (T)0, p.riemann, 0, R);
+      tet_div<T, DEV, false, false, false><<<div_grid, TDIV_NT, 0, c->stream>>>(
+          u, nullptr, nullptr, geo, C, O, opT, opH, opL, r, b.E, b.n, (T)p.gamma, zero, zero, zero, zero, p.riemann, 0,
+          R);
     c->prof_end(pk);
   } else {
+    // one-sided LDG (beta = +-1/2), FP32 form: the gradient kernel also forms the common
+    // fluxes (in FP64 the extra registers cost that kernel more than the divergence saves)
+    constexpr bool can_fc = sizeof(T) == 4;
+    const bool fc = sm != 0 && can_fc;
+    T* fcb = (T*)b.fc;
+    const T gam = (T)p.gamma, mu = (T)p.mu, pr = (T)p.prandtl, beta = (T)p.ldg_beta, tau = (T)p.ldg_tau;
+    const T* ogT = (const T*)c->tet_ogT;
     pk = c->prof_begin(("tet_grad" + sfx).c_str());
-    if (bf3)
-      tet_grad_mma<T, can_bf3><<<div_grid, TDIV_NT, 0, c->stream>>>(u, geo, C, O, (const T*)c->tet_ogT, ogH, ogL,
-                                                                     (T*)b.grad, b.E, b.n, (T)p.ldg_beta);
-    else
-      tet_grad_mma<T, false><<<div_grid, TDIV_NT, 0, c->stream>>>(u, geo, C, O, (const T*)c->tet_ogT, ogH, ogL,
-                                                                   (T*)b.grad, b.E, b.n, (T)p.ldg_beta);
+#define FR_TET_GRAD(BF, FCX)                                                                                   \
+  tet_grad_mma<T, DEV, BF, FCX><<<div_grid, TDIV_NT, 0, c->stream>>>(u, geo, C, O, ogT, ogH, ogL, (T*)b.grad, fcb, \
+                                                                    b.E, b.n, beta, sm, gam, mu, pr, tau,       \
+                                                                    p.riemann, R)
+    if (bf3) {
+      if (fc) FR_TET_GRAD(can_bf3, can_fc); else FR_TET_GRAD(can_bf3, false);
+    } else {
+      if (fc) FR_TET_GRAD(false, can_fc); else FR_TET_GRAD(false, false);
+    }
+#undef FR_TET_GRAD
     c->prof_end(pk);
     pk = c->prof_begin(("tet_div_ns" + sfx).c_str());
-    if (bf3)
-      tet_div<T, DEV, true, can_bf3><<<div_grid, TDIV_NT, 0, c->stream>>>(
-          u, (const T*)b.grad, geo, C, O, opT, opH, opL, r, b.E, b.n, (T)p.gamma, (T)p.mu, (T)p.prandtl,
-          (T)p.ldg_beta, (T)p.ldg_tau, p.riemann, sm, R);
-    else
-      tet_div<T, DEV, true, false><<<div_grid, TDIV_NT, 0, c->stream>>>(
-          u, (const T*)b.grad, geo, C, O, opT, opH, opL, r, b.E, b.n, (T)p.gamma, (T)p.mu, (T)p.prandtl,
-          (T)p.ldg_beta, (T)p.ldg_tau, p.riemann, sm, R);
+#define FR_TET_DIV(BF, FCX)                                                                                     \
+  tet_div<T, DEV, true, BF, FCX><<<div_grid, TDIV_NT, 0, c->stream>>>(u, (const T*)b.grad, fcb, geo, C, O, opT, opH, \
+                                                                     opL, r, b.E, b.n, gam, mu, pr, beta, tau,   \
+                                                                     p.riemann, sm, R)
+    if (bf3) {
+      if (fc) FR_TET_DIV(can_bf3, can_fc); else FR_TET_DIV(can_bf3, false);
+    } else {
+      if (fc) FR_TET_DIV(false, can_fc); else FR_TET_DIV(false, false);
+    }
+#undef FR_TET_DIV
     c->prof_end(pk);
   }
   hipError_t e = hipGetLastError();
@@ -945,7 +962,7 @@ fr_status fr_setup_mesh(const fr_params* p, int64_t n_vert, const double* xyz, c
         (dalloc(c, (char**)&d.grad, (size_t)d.nsp * 15 * d.E * tsz) ||
          (!is_tet && dalloc(c, (char**)&d.gradf, (size_t)d.nfp * 15 * d.E * tsz))))
       return bail(FR_ERR_ALLOC);
-    if (p->system == FR_NAVIER_STOKES && !is_tet && dalloc(c, (char**)&d.fc, (size_t)d.nfp * 5 * d.E * tsz))
+    if (p->system == FR_NAVIER_STOKES && dalloc(c, (char**)&d.fc, (size_t)d.nfp * 5 * d.E * tsz))
       return bail(FR_ERR_ALLOC);
     d.geo_t = d.geo;
     if (tsz == sizeof(float)) {
@@ -991,7 +1008,14 @@ fr_status fr_setup_mesh(const fr_params* p, int64_t n_vert, const double* xyz, c
   for (auto& b : c->blocks) has_tet = has_tet || b.etype == FR_TET;
   if (has_tet) {
     const TetOps& T = c->host.tet;
+    // flux point -> collocated solution point, then per solution point its flux points
     std::vector<int32_t> src(T.fp_src, T.fp_src + 60);
+    src.resize(60 + 35 * 4, 0);
+    for (int sg = 0; sg < 60; ++sg) {
+      int32_t* row = &src[60 + 4 * T.fp_src[sg]];
+      if (row[0] >= 3) { c->err = "a solution point collocated with more than 3 flux points"; return bail(FR_ERR_STATE); }
+      row[1 + row[0]++] = sg;
+    }
     // transposed, zero-padded divergence operator [Dh_0 Dh_1 Dh_2 L] of the matrix-core contraction
     std::vector<double> opT((size_t)TET_KP * TET_MP, 0.0);
     for (int k = 0; k < 105; ++k)
@@ -1039,8 +1063,8 @@ fr_status fr_setup_mesh(const fr_params* p, int64_t n_vert, const double* xyz, c
       c->err = "tet operator upload failed";
       return bail(FR_ERR_DEVICE);
     }
-    if (dalloc(c, &c->tet_src, 60)) return bail(FR_ERR_ALLOC);
-    if (hipMemcpy(c->tet_src, src.data(), 60 * 4, hipMemcpyHostToDevice) != hipSuccess) {
+    if (dalloc(c, &c->tet_src, src.size())) return bail(FR_ERR_ALLOC);
+    if (hipMemcpy(c->tet_src, src.data(), src.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
       c->err = "upload failed";
       return bail(FR_ERR_DEVICE);
     }

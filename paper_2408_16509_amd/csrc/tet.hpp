@@ -25,6 +25,7 @@ constexpr int TET_NSP = 35, TET_NFP = 60, TET_NFPF = 15;
 template <typename T>
 struct TetDev {
   const int32_t* src;   // [60] collocated solution point of each flux point
+  const int32_t* pfp;   // [35][4]: number of flux points at solution point z (0..3), then their indices
   T nref[4][3];         // unit outward reference normals of the faces
 };
 
@@ -138,36 +139,49 @@ __device__ __forceinline__ void bf16_split4(const float x[4], tet_s4& hi, tet_s4
   lo = __builtin_bit_cast(tet_s4, l);
 }
 
-// acc[m] += Op[16 m .. 16 m + 15][k] P[k][v][col] over nk rows of the LDS panel starting at
-// panel row pk, operator rows starting at column ko.  FP path: opT[k][ldm] (k-major, FP32 or
+// acc[i][v] += Op[16 mt[i] .. 16 mt[i] + 15][k] P[k][v][col] over the nk rows of the LDS
+// panel, operator rows starting at column ko, for all five variables v: each operator
+// value the wave loads serves five products.  FP path: opT[k][ldm] (k-major, FP32 or
 // FP64), steps of 4.  BF16x3 path: opH / opL [M][ldk] bf16 (k contiguous), steps of 16.
-template <typename T, bool BF3, int NM, int NE>
-__device__ __forceinline__ void tet_contract(typename Mma16<T>::V (&acc)[NM], const T* PAN, int pk, int nk, int v,
-                                             int lane, const T* __restrict__ opT, int ko, int ldm,
+template <typename T, bool BF3, int NW, int NE>
+__device__ __forceinline__ void tet_contract(typename Mma16<T>::V (&acc)[NW][5], const T* PAN, int nk, int lane,
+                                             const T* __restrict__ opT, int ko, int ldm, const int (&mt)[NW],
                                              const tet_s4* __restrict__ opH, const tet_s4* __restrict__ opL, int ldk) {
   const int kr = lane / 16, col = lane % 16;
   if constexpr (!BF3) {
 #pragma unroll 2
     for (int k0 = 0; k0 < nk; k0 += 4) {
-      const T bop = PAN[((pk + k0 + kr) * 5 + v) * NE + col];
+      T b[5];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) b[v] = PAN[((k0 + kr) * 5 + v) * NE + col];
       const T* arow = opT + (ko + k0 + kr) * ldm + col;
 #pragma unroll
-      for (int m = 0; m < NM; ++m) acc[m] = Mma16<T>::run(arow[m * 16], bop, acc[m]);
+      for (int i = 0; i < NW; ++i) {
+        const T a = arow[mt[i] * 16];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) acc[i][v] = Mma16<T>::run(a, b[v], acc[i][v]);
+      }
     }
   } else {
     for (int k0 = 0; k0 < nk; k0 += 16) {
-      float x[4];
+      tet_s4 bh[5], bl[5];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) x[t] = PAN[((pk + k0 + 4 * kr + t) * 5 + v) * NE + col];
-      tet_s4 bh, bl;
-      bf16_split4(x, bh, bl);
+      for (int v = 0; v < 5; ++v) {
+        float x[4];
 #pragma unroll
-      for (int m = 0; m < NM; ++m) {
-        const int a = ((m * 16 + col) * ldk + ko + k0 + 4 * kr) / 4;
+        for (int t = 0; t < 4; ++t) x[t] = PAN[((k0 + 4 * kr + t) * 5 + v) * NE + col];
+        bf16_split4(x, bh[v], bl[v]);
+      }
+#pragma unroll
+      for (int i = 0; i < NW; ++i) {
+        const int a = ((mt[i] * 16 + col) * ldk + ko + k0 + 4 * kr) / 4;
         const tet_s4 ah = opH[a], al = opL[a];
-        acc[m] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc[m], 0, 0, 0);
-        acc[m] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc[m], 0, 0, 0);
-        acc[m] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc[m], 0, 0, 0);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+          acc[i][v] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh[v], acc[i][v], 0, 0, 0);
+          acc[i][v] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl[v], acc[i][v], 0, 0, 0);
+          acc[i][v] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh[v], acc[i][v], 0, 0, 0);
+        }
       }
     }
   }
@@ -186,10 +200,15 @@ constexpr int TDIV_NE = 16, TDIV_NT = 5 * 64;
 // R^T = -(1/J) Op P with the panel P = [f~_0; f~_1; f~_2; F^C] (K x 5*16).  A block
 // takes one tile of elements: its 5 waves evaluate the transformed fluxes at the
 // solution points, then the common fluxes at the flux points, into the panel (two K
-// chunks through LDS), and wave v multiplies the 16 columns of variable v by the
-// three 16-row tiles of Op (read through the caches).
-template <typename T, bool DEV, bool NS, bool BF3>
+// chunks through LDS), and waves 0..2 each multiply one 16-row tile of Op (read
+// through the caches, once per block) by the panel columns of all five variables.
+// FCIN: the common fluxes (unit normal, left-to-right orientation) were already
+// formed once per flux-point pair by the gradient kernel and stored in the slot of the
+// side that formed them; here each flux point reads its pair's value and scales it by
+// the element's own +-|S^T n~|.
+template <typename T, bool DEV, bool NS, bool BF3, bool FCIN>
 __global__ void __launch_bounds__(TDIV_NT) tet_div(const T* __restrict__ u, const T* __restrict__ grad,
+                                                   const T* __restrict__ fcin,
                                                    const T* __restrict__ geo, Conn C, TetDev<T> O,
                                                    const T* __restrict__ opT, const tet_s4* __restrict__ opH,
                                                    const tet_s4* __restrict__ opL, T* __restrict__ r, int64_t E,
@@ -200,7 +219,8 @@ __global__ void __launch_bounds__(TDIV_NT) tet_div(const T* __restrict__ u, cons
   __shared__ T PAN[KA * 5 * NE];          // [k][v][el]; the second K chunk reuses it
   __shared__ T SJ[10 * NE];
   const int t = threadIdx.x;
-  const int v = t / 64, lane = t % 64, col = lane % 16;
+  const int w = t / 64, lane = t % 64, col = lane % 16;
+  const int mt[1] = {w};
   const T gm1 = gamma - T(1);
   const int64_t e0 = xcd_block() * NE;
   {
@@ -233,10 +253,10 @@ __global__ void __launch_bounds__(TDIV_NT) tet_div(const T* __restrict__ u, cons
       }
     }
     __syncthreads();
-    typename Mma16<T>::V acc[3];
+    typename Mma16<T>::V acc[1][5];
 #pragma unroll
-    for (int mt = 0; mt < 3; ++mt) acc[mt] = typename Mma16<T>::V{0, 0, 0, 0};
-    tet_contract<T, BF3, 3, NE>(acc, PAN, 0, KA, v, lane, opT, 0, TET_MP, opH, opL, TET_KP16);
+    for (int v = 0; v < 5; ++v) acc[0][v] = typename Mma16<T>::V{0, 0, 0, 0};
+    if (w < 3) tet_contract<T, BF3, 1, NE>(acc, PAN, KA, lane, opT, 0, TET_MP, mt, opH, opL, TET_KP16);
     __syncthreads();
     // K chunk 2: common fluxes at the flux points (rows past 60 zero)
     if constexpr (KB > TET_NFP)
@@ -246,22 +266,41 @@ __global__ void __launch_bounds__(TDIV_NT) tet_div(const T* __restrict__ u, cons
       T S[9], F[5];
 #pragma unroll
       for (int k = 0; k < 9; ++k) S[k] = SJ[k * NE + el];
-      tet_common_flux<T, DEV, NS>(u, grad, S, C, O, E, e0 + el, sg, gamma, mu, pr, beta, tau, riemann, side_mode, R, F);
+      if constexpr (FCIN) {
+        const int face = sg / TET_NFPF;
+        const int64_t e = e0 + el;
+        const NbrSlot ns = nbr_slot<TET_NFPF>(C, E, e, face, sg % TET_NFPF);
+        // the slot of the side that formed the flux: own, or the partner's
+        const bool own = ns.left != (side_mode > 0);
+        const int64_t fe = own ? e : ns.elem;
+        const int fp = own ? sg : ns.fp;
+        T nv[3];
+        tet_normal(S, O, face, nv);
+        const T mag = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+        const T fs = ns.left ? mag : -mag;
+#pragma unroll
+        for (int c = 0; c < 5; ++c) F[c] = fcin[((int64_t)fp * 5 + c) * E + fe] * fs;
+      } else {
+        tet_common_flux<T, DEV, NS>(u, grad, S, C, O, E, e0 + el, sg, gamma, mu, pr, beta, tau, riemann, side_mode,
+                                    R, F);
+      }
 #pragma unroll
       for (int c = 0; c < 5; ++c) PAN[(sg * 5 + c) * NE + el] = F[c];
     }
     __syncthreads();
-    tet_contract<T, BF3, 3, NE>(acc, PAN, 0, KB, v, lane, opT, BF3 ? TET_KA16 : TET_KA, TET_MP, opH, opL, TET_KP16);
+    if (w >= 3) return;
+    tet_contract<T, BF3, 1, NE>(acc, PAN, KB, lane, opT, BF3 ? TET_KA16 : TET_KA, TET_MP, mt, opH, opL, TET_KP16);
     const int64_t e = e0 + col;
     const T iJ = T(-1) / SJ[9 * NE + col];
     if (e < n) {
 #pragma unroll
-      for (int mt = 0; mt < 3; ++mt)
+      for (int q = 0; q < 4; ++q) {
+        const int pt = w * 16 + Mma16<T>::row(lane, q);
+        if (pt < TET_NSP) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int pt = mt * 16 + Mma16<T>::row(lane, q);
-          if (pt < TET_NSP) r[((int64_t)pt * 5 + v) * E + e] = acc[mt][q] * iJ;
+          for (int v = 0; v < 5; ++v) r[((int64_t)pt * 5 + v) * E + e] = acc[0][v][q] * iJ;
         }
+      }
     }
   }
 }
@@ -271,26 +310,41 @@ __global__ void __launch_bounds__(TDIV_NT) tet_div(const T* __restrict__ u, cons
 // reference gradient is gt_i = Dh_i u + L diag(n~_i) u^ (i = 0, 1, 2): one product of
 // the stacked operator G = [[Dh_0, L n~_0], [Dh_1, L n~_1], [Dh_2, L n~_2]] (3 x 35 rows
 // padded to 3 x 48, K = 35 + 60 padded to 96; stored transposed, ogT[k][48 i + pt])
-// with the panel [u; u^] of a block of 16 elements.  Wave v holds the nine 16x16
-// output tiles of variable v, so the three gt_i of a point meet in one lane, where
-// the physical gradient S^T gt / J is formed and stored.
+// with the panel [u; u^] of a block of 16 elements.  Wave w (0..2) holds the output
+// tiles of point tile w in the three directions for all five variables, so the three
+// gt_i of a point meet in one lane, where the physical gradient S^T gt / J is formed
+// and stored; each operator value the wave loads serves five products.
+//
+// FC (one-sided LDG, beta = +-1/2, side_mode = sign of beta): the common flux of
+// every flux-point pair is formed here, once, by the element whose gradient the
+// viscous part takes (the right side for beta = 1/2).  That lane holds the full
+// gradient at the collocated solution point, its own state, and (as u^) the partner's
+// state, so it evaluates eq:comm_flux with the LDG viscous part and penalty in the
+// left-to-right unit normal and stores it in its own slot of fc; the divergence
+// kernel reads it from there for both sides and scales it by its own +-|S^T n~|.
 constexpr int TGR_K = 96, TGR_M = 3 * TET_MP;
 
-template <typename T, bool BF3>
-__global__ void __launch_bounds__(TDIV_NT) tet_grad_mma(const T* __restrict__ u, const T* __restrict__ geo, Conn C,
+template <typename T, bool DEV, bool BF3, bool FC>
+__global__ void __launch_bounds__(TDIV_NT) __attribute__((amdgpu_waves_per_eu(4))) tet_grad_mma(const T* __restrict__ u, const T* __restrict__ geo, Conn C,
                                                         TetDev<T> O, const T* __restrict__ ogT,
                                                         const tet_s4* __restrict__ ogH, const tet_s4* __restrict__ ogL,
-                                                        T* __restrict__ grad, int64_t E, int64_t n, T beta) {
+                                                        T* __restrict__ grad, T* __restrict__ fc, int64_t E, int64_t n,
+                                                        T beta, int side_mode, T gamma, T mu, T pr, T tau, int riemann,
+                                                        RefState<T> R) {
   constexpr int NE = TDIV_NE, NT = TDIV_NT;
   __shared__ T PAN[TGR_K * 5 * NE];      // [k][v][el]: u at the 35 points, u^ at the 60 flux points, 0
   __shared__ T SJ[10 * NE];
+  __shared__ uint8_t SIDE[FC ? TET_NFP * NE : 1];   // bit 0: element is the left side; bit 1: it forms the flux
+  __shared__ int32_t PFP[FC ? TET_NSP * 4 : 1];
   const int t = threadIdx.x;
-  const int v = t / 64, lane = t % 64, col = lane % 16;
+  const int w = t / 64, lane = t % 64, col = lane % 16;
   const int64_t e0 = xcd_block() * NE;
   {
     for (int i = t; i < 10 * NE; i += NT) SJ[i] = geo[(int64_t)(i / NE) * E + e0 + i % NE];
     for (int i = t; i < 5 * NE; i += NT) PAN[(TGR_K - 1) * 5 * NE + i] = T(0);
     for (int i = t; i < TET_NSP * 5 * NE; i += NT) PAN[i] = u[(int64_t)(i / NE) * E + e0 + i % NE];
+    if constexpr (FC)
+      for (int i = t; i < TET_NSP * 4; i += NT) PFP[i] = O.pfp[i];
     __syncthreads();
     for (int it = t; it < TET_NFP * NE; it += NT) {
       const int el = it % NE, sg = it / NE;
@@ -300,18 +354,25 @@ __global__ void __launch_bounds__(TDIV_NT) tet_grad_mma(const T* __restrict__ u,
       const int so = O.src[sg];
       T un[5];
       tet_load(u, E, ns.elem, O.src[ns.fp], un);
+      if constexpr (FC) SIDE[sg * NE + el] = (ns.left ? 1 : 0) | (ns.left != (side_mode > 0) ? 2 : 0);
 #pragma unroll
       for (int c = 0; c < 5; ++c) {
         const T own = PAN[(so * 5 + c) * NE + el];
         const T uL = ns.left ? own : un[c], uR = ns.left ? un[c] : own;
-        PAN[((TET_NSP + sg) * 5 + c) * NE + el] = T(0.5) * (uL + uR) + beta * (uL - uR);
+        // one-sided: u^ is exactly the state of the side named by beta
+        PAN[((TET_NSP + sg) * 5 + c) * NE + el] =
+            side_mode > 0 ? uL : (side_mode < 0 ? uR : T(0.5) * (uL + uR) + beta * (uL - uR));
       }
     }
     __syncthreads();
-    typename Mma16<T>::V acc[9];
+    if (w >= 3) return;
+    typename Mma16<T>::V acc[3][5];
 #pragma unroll
-    for (int m = 0; m < 9; ++m) acc[m] = typename Mma16<T>::V{0, 0, 0, 0};
-    tet_contract<T, BF3, 9, NE>(acc, PAN, 0, TGR_K, v, lane, ogT, 0, TGR_M, ogH, ogL, TGR_K);
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int v = 0; v < 5; ++v) acc[i][v] = typename Mma16<T>::V{0, 0, 0, 0};
+    const int mt[3] = {w, 3 + w, 6 + w};
+    tet_contract<T, BF3, 3, NE>(acc, PAN, TGR_K, lane, ogT, 0, TGR_M, mt, ogH, ogL, TGR_K);
     const int64_t e = e0 + col;
     if (e < n) {
       T S[9];
@@ -319,16 +380,50 @@ __global__ void __launch_bounds__(TDIV_NT) tet_grad_mma(const T* __restrict__ u,
       for (int k = 0; k < 9; ++k) S[k] = SJ[k * NE + col];
       const T iJ = T(1) / SJ[9 * NE + col];
 #pragma unroll
-      for (int mt = 0; mt < 3; ++mt)
+      for (int q = 0; q < 4; ++q) {
+        const int pt = w * 16 + Mma16<T>::row(lane, q);
+        if (pt >= TET_NSP) continue;
+        T gp[15];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int pt = mt * 16 + Mma16<T>::row(lane, q);
-          if (pt >= TET_NSP) continue;
-          const T g0 = acc[mt][q], g1 = acc[3 + mt][q], g2 = acc[6 + mt][q];
+        for (int v = 0; v < 5; ++v) {
+          const T g0 = acc[0][v][q], g1 = acc[1][v][q], g2 = acc[2][v][q];
 #pragma unroll
-          for (int j = 0; j < 3; ++j)
-            grad[((int64_t)pt * 15 + v * 3 + j) * E + e] = (S[j] * g0 + S[3 + j] * g1 + S[6 + j] * g2) * iJ;
+          for (int j = 0; j < 3; ++j) {
+            gp[v * 3 + j] = (S[j] * g0 + S[3 + j] * g1 + S[6 + j] * g2) * iJ;
+            grad[((int64_t)pt * 15 + v * 3 + j) * E + e] = gp[v * 3 + j];
+          }
         }
+        if constexpr (FC) {
+          const int nf = PFP[pt * 4];
+          for (int i = 0; i < nf; ++i) {
+            const int sg = PFP[pt * 4 + 1 + i];
+            const int face = sg / TET_NFPF;
+            const int side = SIDE[sg * NE + col];
+            if (!(side & 2)) continue;                      // the partner's gradient contributes
+            const NbrSlot ns{0, 0, (side & 1) != 0};
+            T own[5], nb[5], uL[5], uR[5], nv[3], nL[3], F[5], fv[5];
+#pragma unroll
+            for (int c = 0; c < 5; ++c) {
+              own[c] = PAN[(pt * 5 + c) * NE + col];
+              nb[c] = PAN[((TET_NSP + sg) * 5 + c) * NE + col];
+              uL[c] = ns.left ? own[c] : nb[c];
+              uR[c] = ns.left ? nb[c] : own[c];
+            }
+            tet_normal(S, O, face, nv);
+            const T mag = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+            const T sl = (ns.left ? T(1) : T(-1)) / mag;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) nL[k] = nv[k] * sl;
+            common_inviscid<T, DEV>(riemann, uL, uR, nL, gamma, R, F);
+            viscous<T, DEV>(own, gp, nL[0], nL[1], nL[2], gamma, mu, pr, R, fv);
+#pragma unroll
+            for (int c = 0; c < 5; ++c) {
+              F[c] = (F[c] - fv[c]) + tau * (uL[c] - uR[c]);
+              fc[((int64_t)sg * 5 + c) * E + e] = F[c];
+            }
+          }
+        }
+      }
     }
   }
 }

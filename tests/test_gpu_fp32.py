@@ -79,6 +79,20 @@ def test_fp32_rhs_random_tets(system):
     assert g <= 1e-5
 
 
+@pytest.mark.parametrize("beta", [-0.5, 0.3])
+def test_fp32_rhs_random_tets_ldg_beta(beta):
+    """FP32 form, Navier--Stokes on tets with the other one-sided switch and with a
+    two-sided weighting (the common fluxes then come from the divergence kernel)."""
+    mesh = inputs.kuhn_split(inputs.hex_box((2, 2, 2), perturb=0.1, perturb_seed=6), permute_seed=3)
+    bl = oracle_blocks(mesh, 4)
+    u = state_for(bl, "random", seed=8)
+    Ro = ofr.rhs(bl, u, oracle_params(1, 0, ldg_beta=beta))
+    Rg = gpu_rhs32(mesh, u, system=1, order=4, u_ref=UREF_RANDOM, ldg_beta=beta)
+    g, pv = rel_err(Rg, Ro)
+    print(f"fp32 tets NS beta={beta}: global {g:.2e} per-var {np.array2string(pv, precision=2)}")
+    assert g <= 1e-5
+
+
 @pytest.mark.parametrize("system", [0, 1])
 def test_bf16x3_rhs_random_tets(system):
     """FP32 form with the tetrahedral operator products as BF16x3 split products

@@ -112,6 +112,20 @@ def test_rhs_parity_small(mname, order, system, riemann, state):
     check(Rg, Ro, floor_=fl)
 
 
+@pytest.mark.parametrize("mname", ["mixed", "tetpert"])
+@pytest.mark.parametrize("beta", [-0.5, 0.3])
+def test_rhs_parity_ldg_beta(mname, beta):
+    """Navier--Stokes with the other one-sided switch (beta = -1/2: the left side's
+    gradient and state) and a two-sided weighting (beta = 0.3: both gradients)."""
+    print(f"case {mname} NS beta={beta}", flush=True)
+    mesh = MESHES[mname]()
+    bl = oracle_blocks(mesh, 4)
+    u = state_for(bl, "random", seed=3)
+    fl, Ro = oracle_floor(mesh, 4, u, oracle_params(1, 0, ldg_beta=beta))
+    Rg = gpu_rhs(mesh, u, system=1, order=4, riemann=0, ldg_beta=beta)
+    check(Rg, Ro, floor_=fl)
+
+
 def test_rhs_parity_config1_and_rk4_10_steps():
     """4^3 straight hexes, p = 2, Euler TGV Ma 0.1, Rusanov: RHS and 10 RK4 steps, dt = 1e-3."""
     mesh = inputs.hex_box((4, 4, 4))

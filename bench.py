@@ -98,9 +98,14 @@ def kernel_bytes_per_elem(name, nsp, nfp):
     return table.get(fam)
 
 
-def source_hash():
+def source_hash(kernel=""):
+    """Hash of the sources a kernel family is built from (its header, the shared
+    physics, and the library file that launches it)."""
+    files = ("hex.hpp", "physics.hpp", "frmi.hip")
+    if kernel.startswith("tet_"):
+        files = ("tet.hpp",) + files
     h = hashlib.sha256()
-    for f in ("hex.hpp", "tet.hpp", "physics.hpp", "filter.hpp", "frmi.hip"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_2408_16509_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -115,7 +120,7 @@ def load_traffic(kernel, workload):
         with open(path) as fh:
             db = json.load(fh)
         rec = db.get(f"{workload}:{kernel}")
-        if rec and rec.get("source_hash") == source_hash():
+        if rec and rec.get("source_hash") == source_hash(kernel):
             return rec.get("bytes_per_launch")
     except Exception:
         return None

@@ -39,7 +39,7 @@ CONFIGS = {
     # timed forms: FP32 + learned filter (headline), FP64 + plain filter, and both unfiltered
     "ns_tgv_mixed_c5split_p4": dict(kind="mixed", n=(32, 64, 64), order=4, system=1, riemann=0, mach=0.1,
                                     dt=7.5e-5, perturb=0.1, perturb_seed=51, permute_seed=53,
-                                    forms="fp32:learned,fp64:plain,fp32,fp64"),
+                                    forms="fp32:learned,fp64:plain,fp32,bf16x3:learned,fp64"),
     # Mach-3 shock (orientation seed 41, density noise seed 42), Euler + HLLC, entropy
     # filter on every RK stage: plain bisection vs the learned warm start, the MLP
     # trained on the plain filter's data from held-out draws (seeds 101-108 / 201-208)
@@ -189,7 +189,12 @@ def run_form(form, cfg, mesh, ic, args, torch, np, frmi, inputs):
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     ms = ev0.elapsed_time(ev1) / args.steps
-    res = {"ctx": ctx, "ms": ms, "wall": wall, "finite": ctx.check(u), "blocks": blocks}
+    res = {"ctx": ctx, "ms": ms, "wall": wall, "finite": ctx.check(u), "blocks": blocks,
+           "u_final": ctx.unpack64(u), "steps_total": args.warmup + args.steps}
+    # the right-hand side of the initial state (canonical FP64), for the form-to-form comparison
+    r = ctx.new_native()
+    ctx.rhs(ctx.pack(ctx.unpack64(u0)), r)
+    res["rhs0"] = ctx.unpack_rhs(r)
     if filter_mode >= 0:
         # the filter on the final state (entropy bound from itself): how many elements it treats
         uf = u.clone()
@@ -346,6 +351,24 @@ def run_filter_workload(cfg, args, torch, np, frmi, inputs):
     return out
 
 
+def _per_var_err(a, b, blocks, torch):
+    """Relative L2 error per conservative variable of canonical arrays (blocks of
+    [n][5][nsp], in block order)."""
+    num = torch.zeros(5, dtype=torch.float64, device=a.device)
+    den = torch.zeros(5, dtype=torch.float64, device=a.device)
+    o = 0
+    for key in ("hex", "tet"):
+        if key not in blocks:
+            continue
+        n, s, _ = blocks[key]
+        x = a[o:o + n * 5 * s].view(n, 5, s)
+        y = b[o:o + n * 5 * s].view(n, 5, s)
+        num += ((x - y) ** 2).sum(dim=(0, 2))
+        den += (y ** 2).sum(dim=(0, 2))
+        o += n * 5 * s
+    return [float(v) for v in torch.sqrt(num / den).cpu()]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -422,6 +445,21 @@ def main():
     for f in forms:
         if "filter" in runs[f]:
             out["forms"][f]["filter_on_final_state"] = runs[f]["filter"]
+    # each reduced-precision form against the first FP64 form of the same run (the FP64 form
+    # is the one the parity tests pin to the oracle): the RHS of the initial state, and the
+    # solution after the same number of RK4 steps
+    ref = next((f for f in forms if f.split(":")[0] == "fp64"), None)
+    if ref is not None:
+        r64, u64 = runs[ref]["rhs0"], runs[ref]["u_final"]
+        for f in forms:
+            if f.split(":")[0] == "fp64":
+                continue
+            rr, uu = runs[f]["rhs0"], runs[f]["u_final"]
+            out["forms"][f]["rhs_rel_l2_vs_fp64_form"] = float(torch.linalg.norm(rr - r64) / torch.linalg.norm(r64))
+            out["forms"][f]["rhs_rel_l2_vs_fp64_form_per_var"] = _per_var_err(rr, r64, runs[f]["blocks"], torch)
+            out["forms"][f]["solution_rel_l2_vs_fp64_form"] = {
+                "against": ref, "steps": runs[f]["steps_total"],
+                "value": float(torch.linalg.norm(uu - u64) / torch.linalg.norm(u64))}
     if not args.no_kernel_timing:
         times = head["times"]
         fam = {k: v for k, v in times.items() if kbytes(k) is not None}

@@ -15,8 +15,9 @@
 //              starting bracket by [floor(k^/2), ceil(2 k^)] and the search continues in
 //              whichever bracket keeps that invariant.
 //
-// One 256-lane block per element.  A constraint evaluation at strength zeta is three
-// 1-D passes through LDS with the filtered evaluation matrix
+// One wave per candidate element (several per block, each with its own LDS region; no
+// block barriers, decisions are wave votes).  A constraint evaluation at strength zeta
+// is three 1-D passes through the wave's LDS with the filtered evaluation matrix
 //     W[r][m] = P~_m(x_r) exp(-zeta m^2 / p^2),   r = nodes 0..p, then xi = -1, +1,
 // so a check point (r1, r2, r3) with at most one end row covers both solution and
 // flux points.
@@ -28,7 +29,7 @@
 
 namespace frmi {
 
-constexpr int FNT = 256;   // threads of the per-element filter blocks
+constexpr int FNT = 256;   // threads of the filter blocks
 
 struct FiltK {
   double Vm[5][5];    // P~_m(x_a) (rows nodes, cols modes)
@@ -58,6 +59,26 @@ __device__ __forceinline__ bool admissible(const double w[5], double smin, const
   const double p = (F.gamma - 1.0) * (w[4] - 0.5 * (w[1] * w[1] + w[2] * w[2] + w[3] * w[3]) / rho);
   const double s = entropy_of(rho, p, F.gamma);
   return rho >= F.eps_rho && p >= F.eps_p && s >= smin - F.eps_s * fabs(smin);
+}
+
+// The same decision as admissible(), with the entropy test screened in FP32 logarithms:
+// log2 p - gamma log2 rho - log2 s_b is formed from FP32 values (each log2f within a few
+// ulp, so the computed value is within about 1e-4 of the exact one for the magnitudes
+// admitted below); only when it lies within 2^-8 of zero is the exact FP64 power formed.
+// Points far from the entropy bound (nearly all of them) skip the FP64 pow.
+__device__ __forceinline__ bool admissible_screened(const double w[5], double smin, const FiltPrm& F) {
+  const double rho = w[0];
+  const double p = (F.gamma - 1.0) * (w[4] - 0.5 * (w[1] * w[1] + w[2] * w[2] + w[3] * w[3]) / rho);
+  if (!(rho >= F.eps_rho) || !(p >= F.eps_p)) return false;
+  const double sb = smin - F.eps_s * fabs(smin);
+  if (sb <= 0.0) return true;                   // s > 0 here
+  const float pf = (float)p, rf = (float)rho, bf = (float)sb;
+  if (pf >= 1e-30f && pf <= 1e30f && rf >= 1e-30f && rf <= 1e30f && bf >= 1e-30f && bf <= 1e30f) {
+    const float L = log2f(pf) - (float)F.gamma * log2f(rf) - log2f(bf);
+    if (L > 0.00390625f) return true;
+    if (L < -0.00390625f) return false;
+  }
+  return p * pow(rho, -F.gamma) >= sb;
 }
 
 // Doubles as unsigned integers with the same order (for an atomic minimum).
@@ -124,35 +145,71 @@ __global__ void __launch_bounds__(256) elem_smin(const unsigned long long* __res
   smin[e] = s;
 }
 
+// Wave-level synchronisation of LDS traffic between the lanes of one wave.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Butterfly reductions over the 64 lanes; every lane receives the same bits.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int s = 32; s >= 1; s >>= 1) v += __shfl_xor(v, s);
+  return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+  for (int s = 32; s >= 1; s >>= 1) v = fmin(v, __shfl_xor(v, s));
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) { return -wave_min(-v); }
+__device__ __forceinline__ float rl_f(float x, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+
+// Waves (candidates) per filter block: the LDS of one wave grows as (p + 1)^3.
 template <int P>
-struct HexFiltSmem {
-  static constexpr int N1 = P + 1, NR = N1 + 2;
-  double U[5][N1 * N1 * N1];           // modal coefficients u^[v][i + N1 j + N1^2 k]
+struct HexFW { static constexpr int value = P <= 3 ? 4 : 2; };
+
+template <int P>
+struct HexWaveSmem {
+  static constexpr int N1 = P + 1, NR = N1 + 2, NSP = N1 * N1 * N1;
+  double U[5][NSP];                    // modal coefficients u^[v][i + N1 j + N1^2 k]
   double T1[5][N1 * N1 * NR];          // [v][i + N1 j][r3]
   double T2[5][N1 * NR * NR];          // [v][i][r2][r3]
   double W[NR][N1];                    // filtered evaluation matrix
-  int flag;
+  double PM[NSP];                      // nodal, then modal pressure (features)
 };
 
-// Check-point evaluation at the strength held in S.W: returns (block-uniformly)
-// whether every check point is admissible.  When `store` is non-null the nodal
-// values at the solution points are written there ([pt][5][E] layout).
+// Check point c (solution points, then the 6 faces' flux points) as evaluation rows.
+template <int N1>
+__device__ __forceinline__ void hex_check_rows(int c, int& r1, int& r2, int& r3) {
+  constexpr int NSP = N1 * N1 * N1;
+  if (c < NSP) {
+    r1 = c % N1; r2 = (c / N1) % N1; r3 = c / (N1 * N1);
+  } else {
+    const int f = (c - NSP) / (N1 * N1), q = (c - NSP) % (N1 * N1), d = f / 2, s = f % 2;
+    const int ta = q % N1, tb = q / N1, end = N1 + s;
+    r1 = d == 0 ? end : ta;
+    r2 = d == 0 ? ta : (d == 1 ? end : tb);
+    r3 = d == 2 ? end : tb;
+  }
+}
+
+// The first two passes of an evaluation at the strength held in S.W (into T1, T2).
 template <int P>
-__device__ bool hex_eval_checks(HexFiltSmem<P>& S, double smin, const FiltPrm& F, double* __restrict__ store,
-                                const Dev32& s32, int64_t E, int64_t e) {
-  constexpr int N1 = P + 1, NR = N1 + 2, NSP = N1 * N1 * N1, NFP = 6 * N1 * N1;
-  const int t = threadIdx.x;
-  // pass over k: T1[v][i + N1 j][r3]
-  for (int o = t; o < 5 * N1 * N1 * NR; o += FNT) {
+__device__ void hex_wave_passes(HexWaveSmem<P>& S, int lane) {
+  constexpr int N1 = P + 1, NR = N1 + 2;
+  for (int o = lane; o < 5 * N1 * N1 * NR; o += 64) {      // over k: T1[v][i + N1 j][r3]
     const int v = o / (N1 * N1 * NR), rem = o % (N1 * N1 * NR), ij = rem / NR, r3 = rem % NR;
     double acc = 0;
 #pragma unroll
     for (int k = 0; k < N1; ++k) acc += S.W[r3][k] * S.U[v][ij + N1 * N1 * k];
     S.T1[v][rem] = acc;
   }
-  __syncthreads();
-  // pass over j: T2[v][i][r2][r3]
-  for (int o = t; o < 5 * N1 * NR * NR; o += FNT) {
+  wave_sync();
+  for (int o = lane; o < 5 * N1 * NR * NR; o += 64) {      // over j: T2[v][i][r2][r3]
     const int v = o / (N1 * NR * NR), rem = o % (N1 * NR * NR);
     const int i = rem / (NR * NR), r2 = (rem / NR) % NR, r3 = rem % NR;
     double acc = 0;
@@ -160,29 +217,37 @@ __device__ bool hex_eval_checks(HexFiltSmem<P>& S, double smin, const FiltPrm& F
     for (int j = 0; j < N1; ++j) acc += S.W[r2][j] * S.T1[v][(i + N1 * j) * NR + r3];
     S.T2[v][rem] = acc;
   }
-  __syncthreads();
-  // pass over i at every check point
+  wave_sync();
+}
+
+// The state at check point (r1, r2, r3) after the passes (the last pass, over i).
+template <int P>
+__device__ __forceinline__ void hex_wave_point(const HexWaveSmem<P>& S, int r1, int r2, int r3, double w[5]) {
+  constexpr int N1 = P + 1, NR = N1 + 2;
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    double acc = 0;
+#pragma unroll
+    for (int i = 0; i < N1; ++i) acc += S.W[r1][i] * S.T2[v][(i * NR + r2) * NR + r3];
+    w[v] = acc;
+  }
+}
+
+// Check-point evaluation at the strength held in S.W: returns (wave-uniformly) whether
+// every check point is admissible.  When `store` is non-null the nodal values at the
+// solution points are written there ([pt][5][E] layout).
+template <int P>
+__device__ bool hex_wave_checks(HexWaveSmem<P>& S, int lane, double smin, const FiltPrm& F,
+                                double* __restrict__ store, const Dev32& s32, int64_t E, int64_t e) {
+  constexpr int N1 = P + 1, NSP = N1 * N1 * N1, NFP = 6 * N1 * N1;
+  hex_wave_passes<P>(S, lane);
   bool ok = true;
-  for (int c = t; c < NSP + NFP; c += FNT) {
+  for (int c = lane; c < NSP + NFP; c += 64) {
     int r1, r2, r3;
-    if (c < NSP) {
-      r1 = c % N1; r2 = (c / N1) % N1; r3 = c / (N1 * N1);
-    } else {
-      const int f = (c - NSP) / (N1 * N1), q = (c - NSP) % (N1 * N1), d = f / 2, s = f % 2;
-      const int ta = q % N1, tb = q / N1, end = N1 + s;
-      r1 = d == 0 ? end : ta;
-      r2 = d == 0 ? ta : (d == 1 ? end : tb);
-      r3 = d == 2 ? end : tb;
-    }
+    hex_check_rows<N1>(c, r1, r2, r3);
     double w[5];
-#pragma unroll
-    for (int v = 0; v < 5; ++v) {
-      double acc = 0;
-#pragma unroll
-      for (int i = 0; i < N1; ++i) acc += S.W[r1][i] * S.T2[v][(i * NR + r2) * NR + r3];
-      w[v] = acc;
-    }
-    ok = ok && admissible(w, smin, F);
+    hex_wave_point<P>(S, r1, r2, r3, w);
+    ok = ok && admissible_screened(w, smin, F);
     if (store && c < NSP) {
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
@@ -191,66 +256,64 @@ __device__ bool hex_eval_checks(HexFiltSmem<P>& S, double smin, const FiltPrm& F
       }
     }
   }
-  return __syncthreads_and(ok ? 1 : 0) != 0;
+  return __all(ok) != 0;
 }
 
 template <int P>
-__device__ __forceinline__ void hex_set_w(HexFiltSmem<P>& S, const FiltK& K, double zeta) {
+__device__ __forceinline__ void hex_wave_set_w(HexWaveSmem<P>& S, const FiltK& K, double zeta, int lane) {
   constexpr int N1 = P + 1, NR = N1 + 2;
-  const int t = threadIdx.x;
-  if (t < NR * N1) {
-    const int r = t / N1, m = t % N1;
+  if (lane < NR * N1) {
+    const int r = lane / N1, m = lane % N1;
     const double sig = exp(-zeta * (double)(m * m) / (double)(P * P));
     const double pm = r < N1 ? K.Vm[r][m] : K.Pe[r - N1][m];
     S.W[r][m] = pm * sig;
   }
-  __syncthreads();
+  wave_sync();
 }
 
 // Nodal values of nv variables (X, [v][pt]) -> modal coefficients (into `out`),
 // three 1-D passes with V^{-1}; Y is scratch of the same size.
 template <int P>
-__device__ void hex_to_modal(double* X, double* Y, double* out, int nv, const FiltK& K) {
+__device__ void hex_wave_to_modal(double* X, double* Y, double* out, int nv, const FiltK& K, int lane) {
   constexpr int N1 = P + 1, NSP = N1 * N1 * N1;
-  const int t = threadIdx.x;
-  for (int o = t; o < nv * NSP; o += FNT) {
+  for (int o = lane; o < nv * NSP; o += 64) {
     const int v = o / NSP, pt = o % NSP, ij = pt % (N1 * N1), m = pt / (N1 * N1);
     double acc = 0;
 #pragma unroll
     for (int k = 0; k < N1; ++k) acc += K.Vmi[m][k] * X[v * NSP + ij + N1 * N1 * k];
     Y[o] = acc;
   }
-  __syncthreads();
-  for (int o = t; o < nv * NSP; o += FNT) {
+  wave_sync();
+  for (int o = lane; o < nv * NSP; o += 64) {
     const int v = o / NSP, pt = o % NSP, i = pt % N1, m = (pt / N1) % N1, kk = pt / (N1 * N1);
     double acc = 0;
 #pragma unroll
     for (int j = 0; j < N1; ++j) acc += K.Vmi[m][j] * Y[v * NSP + i + N1 * j + N1 * N1 * kk];
     X[o] = acc;
   }
-  __syncthreads();
-  for (int o = t; o < nv * NSP; o += FNT) {
+  wave_sync();
+  for (int o = lane; o < nv * NSP; o += 64) {
     const int v = o / NSP, pt = o % NSP, m = pt % N1, rest = pt / N1;
     double acc = 0;
 #pragma unroll
     for (int i = 0; i < N1; ++i) acc += K.Vmi[m][i] * X[v * NSP + i + N1 * rest];
     out[o] = acc;
   }
-  __syncthreads();
+  wave_sync();
 }
 
 template <int P>
-__device__ void hex_load_modal(HexFiltSmem<P>& S, const double* __restrict__ u, int64_t E, int64_t e,
-                               const FiltK& K) {
+__device__ void hex_wave_load_modal(HexWaveSmem<P>& S, const double* __restrict__ u, int64_t E, int64_t e,
+                                    const FiltK& K, int lane) {
   constexpr int N1 = P + 1, NSP = N1 * N1 * N1;
   double* X = &S.T1[0][0];
   double* Y = &S.T2[0][0];
-  for (int o = threadIdx.x; o < 5 * NSP; o += FNT) {
+  for (int o = lane; o < 5 * NSP; o += 64) {
     const int v = o / NSP, pt = o % NSP;
     X[o] = u[((int64_t)pt * 5 + v) * E + e];
   }
-  __syncthreads();
-  hex_to_modal<P>(X, Y, &S.U[0][0], 5, K);
+  wave_sync();
+  hex_wave_to_modal<P>(X, Y, &S.U[0][0], 5, K, lane);
 }
 
 // The search shared by the element types, for an element that fails the checks at
@@ -291,61 +354,50 @@ __device__ int64_t dyadic_search(const FiltPrm& F, int mode, float kh_in, Gf& G,
   return hi;
 }
 
-// One element on a block: exact check at zeta = 0, search (mode 0 plain,
-// 1 warm start from the predicted index kh) and application of the filter.  With
-// `preloaded` the modal coefficients are already in S.U and the check at zeta = 0
-// has failed (the learned path, whose feature pass did both).
+// Search (mode 0 plain, 1 warm start from the predicted index kh) and application of
+// the filter for an element whose modal coefficients are in S.U and whose check at
+// zeta = 0 has failed.
 template <int P>
-__device__ void hex_filter_elem(HexFiltSmem<P>& S, double* __restrict__ u, const double* __restrict__ smin_a,
-                                int64_t E, int64_t e, const FiltK& K, const FiltPrm& F, int mode, float kh_in,
-                                bool preloaded, int32_t* __restrict__ k_out, int32_t* __restrict__ evals_out,
-                                const Dev32& s32) {
-  const int t = threadIdx.x;
-  const double smin = smin_a[e];
-  bool ok0 = false;
-  if (!preloaded) {
-    hex_load_modal<P>(S, u, E, e, K);
-    hex_set_w<P>(S, K, 0.0);
-    ok0 = hex_eval_checks<P>(S, smin, F, nullptr, Dev32{}, E, e);
-  }
+__device__ void hex_wave_search(HexWaveSmem<P>& S, int lane, double* __restrict__ u, double smin, int64_t E,
+                                int64_t e, const FiltK& K, const FiltPrm& F, int mode, float kh_in,
+                                int32_t* __restrict__ k_out, int32_t* __restrict__ evals_out, const Dev32& s32) {
   int evals = 1;
-  if (ok0) {
-    if (t == 0) {
-      if (k_out) k_out[e] = 0;
-      if (evals_out) evals_out[e] = evals;
-    }
-    return;
-  }
   const double dz = F.zeta_max / (double)((int64_t)1 << F.n_bits);
   auto G = [&](int64_t k) {
-    hex_set_w<P>(S, K, (double)k * dz);
+    hex_wave_set_w<P>(S, K, (double)k * dz, lane);
     ++evals;
-    return hex_eval_checks<P>(S, smin, F, nullptr, Dev32{}, E, e);
+    return hex_wave_checks<P>(S, lane, smin, F, nullptr, Dev32{}, E, e);
   };
   bool fallback = false;
   const int64_t hi = dyadic_search(F, mode, kh_in, G, fallback);
   const double zeta = fallback ? F.zeta_max : (double)hi * dz;
-  hex_set_w<P>(S, K, zeta);
-  (void)hex_eval_checks<P>(S, smin, F, u, s32, E, e);
-  if (t == 0) {
+  hex_wave_set_w<P>(S, K, zeta, lane);
+  (void)hex_wave_checks<P>(S, lane, smin, F, u, s32, E, e);
+  if (lane == 0) {
     if (k_out) k_out[e] = fallback ? -1 : (int32_t)hi;
     if (evals_out) evals_out[e] = evals;
   }
 }
 
-// The candidates list[0 .. *count) (from the detection), one block looping over them.
+// The candidates list[0 .. *count) (from the detection), one wave per candidate:
+// modal transform, exact check at zeta = 0, then the plain search.
 template <int P>
-__global__ void __launch_bounds__(FNT) hex_filter(double* __restrict__ u, const double* __restrict__ smin_a, int64_t E,
-                                                 const int32_t* __restrict__ list, const int32_t* __restrict__ count,
-                                                 FiltK K, FiltPrm F, int mode, const float* __restrict__ khat,
-                                                 int32_t* __restrict__ k_out, int32_t* __restrict__ evals_out,
-                                                 Dev32 s32) {
-  __shared__ HexFiltSmem<P> S;
+__global__ void __launch_bounds__(64 * HexFW<P>::value) hex_filter(
+    double* __restrict__ u, const double* __restrict__ smin_a, int64_t E, const int32_t* __restrict__ list,
+    const int32_t* __restrict__ count, FiltK K, FiltPrm F, int32_t* __restrict__ k_out,
+    int32_t* __restrict__ evals_out, Dev32 s32) {
+  constexpr int FW = HexFW<P>::value;
+  __shared__ HexWaveSmem<P> SM[FW];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  HexWaveSmem<P>& S = SM[wv];
   const int32_t m = *count;
-  for (int32_t i = blockIdx.x; i < m; i += gridDim.x) {
+  for (int32_t i = blockIdx.x * FW + wv; i < m; i += gridDim.x * FW) {
     const int32_t e = list[i];
-    hex_filter_elem<P>(S, u, smin_a, E, e, K, F, mode, khat ? khat[e] : 0.0f, false, k_out, evals_out, s32);
-    __syncthreads();
+    const double smin = smin_a[e];
+    hex_wave_load_modal<P>(S, u, E, e, K, lane);
+    hex_wave_set_w<P>(S, K, 0.0, lane);
+    if (hex_wave_checks<P>(S, lane, smin, F, nullptr, Dev32{}, E, e)) continue;   // k = 0 (set by the reset)
+    hex_wave_search<P>(S, lane, u, smin, E, e, K, F, 0, 0.0f, k_out, evals_out, s32);
   }
 }
 
@@ -466,33 +518,9 @@ __global__ void __launch_bounds__(256) k_flag_scatter(const int32_t* __restrict_
   if (f) list[base + __popcll(mask & ((1ull << lane) - 1ull))] = (int32_t)e;
 }
 
-// Block reductions over the FNT lanes of a filter block through LDS (red[FNT]).
-__device__ __forceinline__ double block_min(double v, double* red) {
-  red[threadIdx.x] = v;
-  __syncthreads();
-  for (int s = FNT / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + s]);
-    __syncthreads();
-  }
-  const double r = red[0];
-  __syncthreads();
-  return r;
-}
-__device__ __forceinline__ double block_max(double v, double* red) { return -block_min(-v, red); }
-__device__ __forceinline__ double block_sum(double v, double* red) {
-  red[threadIdx.x] = v;
-  __syncthreads();
-  for (int s = FNT / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-    __syncthreads();
-  }
-  const double r = red[0];
-  __syncthreads();
-  return r;
-}
-
-// The 16 per-element features of the learned warm start, for elements that fail
-// the checks at zeta = 0 (flag[e] = 1; others get flag 0 and no features):
+// The 16 per-element features of the learned warm start, for an element whose modal
+// coefficients are in S.U and whose check at zeta = 0 (evaluated with S.W at zeta = 0,
+// so T2 holds its passes) has failed:
 //   0-8   log10 of the modal energy of rho, E, p in the shells max(i,j,k) = 1, 2, >= 3,
 //         relative to the mean mode's energy (floored at 1e-30)
 //   9     min rho / rho_mean - 1        10  min p / p_mean - 1
@@ -500,25 +528,13 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 //   12    fraction of violating check points
 //   13    max |rho - rho_mean| / rho_mean
 //   14    log10(s_mean / s_min)         15  |v_mean| / c_mean
-// (mean = element mean state; its pressure, entropy and sound speed.)
-// Returns (block-uniformly) whether the element fails the checks at zeta = 0; the
-// features go to feat[e] and/or xs (LDS), the flag to flag[e] (each may be null).
+// (mean = element mean state; its pressure, entropy and sound speed.)  The result is
+// wave-uniform.
 template <int P>
-__device__ bool hex_features_elem(HexFiltSmem<P>& S, double* red, double* PM, const double* __restrict__ u,
-                                  const double* __restrict__ smin_a, int64_t E, int64_t e, const FiltK& K,
-                                  const FiltPrm& F, int32_t* __restrict__ flag, float* __restrict__ feat,
-                                  float* xs) {
-  constexpr int N1 = P + 1, NR = N1 + 2, NSP = N1 * N1 * N1, NFP = 6 * N1 * N1;
-  const int t = threadIdx.x;
-  const double smin = smin_a[e];
+__device__ void hex_wave_features(HexWaveSmem<P>& S, int lane, double smin, const FiltK& K, const FiltPrm& F,
+                                  float x[16]) {
+  constexpr int N1 = P + 1, NSP = N1 * N1 * N1, NFP = 6 * N1 * N1;
   const double g = F.gamma;
-  hex_load_modal<P>(S, u, E, e, K);
-  hex_set_w<P>(S, K, 0.0);
-  const bool ok0 = hex_eval_checks<P>(S, smin, F, nullptr, Dev32{}, E, e);
-  if (ok0) {
-    if (t == 0 && flag) flag[e] = 0;
-    return false;
-  }
   // mean state from the (0,0,0) mode: mean = u^_000 P~_0^3 = u^_000 / (2 sqrt 2)
   const double c0 = 1.0 / (2.0 * sqrt(2.0));
   const double rb = S.U[0][0] * c0, mx = S.U[1][0] * c0, my = S.U[2][0] * c0, mz = S.U[3][0] * c0;
@@ -528,139 +544,155 @@ __device__ bool hex_features_elem(HexFiltSmem<P>& S, double* red, double* PM, co
   const double pbc = fmax(pb, 1e-300);
   const double cb = sqrt(g * pbc / rb);
   const double sb = pbc * pow(rb, -g);
-  // check-point statistics at zeta = 0 (T2 holds the passes of the last evaluation)
-  double mrho = INFINITY, mp = INFINITY, ms = INFINITY, mdr = 0, nbad = 0;
-  for (int c = t; c < NSP + NFP; c += FNT) {
+  // check-point statistics at zeta = 0
+  // the minimum entropy: each lane ranks its points by an FP32 estimate of log2 s and
+  // forms s exactly (FP64 pow) for its lowest one only
+  double mrho = INFINITY, mp = INFINITY, mdr = 0, nbad = 0;
+  double arho = 1.0, ap = 1.0;
+  float al = INFINITY;
+  bool nonfinite = false;
+  for (int c = lane; c < NSP + NFP; c += 64) {
     int r1, r2, r3;
-    if (c < NSP) {
-      r1 = c % N1; r2 = (c / N1) % N1; r3 = c / (N1 * N1);
-    } else {
-      const int f = (c - NSP) / (N1 * N1), q = (c - NSP) % (N1 * N1), d = f / 2, s = f % 2;
-      const int ta = q % N1, tb = q / N1, end = N1 + s;
-      r1 = d == 0 ? end : ta;
-      r2 = d == 0 ? ta : (d == 1 ? end : tb);
-      r3 = d == 2 ? end : tb;
-    }
+    hex_check_rows<N1>(c, r1, r2, r3);
     double w[5];
-#pragma unroll
-    for (int v = 0; v < 5; ++v) {
-      double acc = 0;
-#pragma unroll
-      for (int i = 0; i < N1; ++i) acc += S.W[r1][i] * S.T2[v][(i * NR + r2) * NR + r3];
-      w[v] = acc;
-    }
+    hex_wave_point<P>(S, r1, r2, r3, w);
     const double p = (g - 1.0) * (w[4] - 0.5 * (w[1] * w[1] + w[2] * w[2] + w[3] * w[3]) / w[0]);
-    double s = entropy_of(w[0], p, g);
-    if (!isfinite(s)) s = -1e30;
+    if (!(w[0] > 0.0) || !isfinite(p)) {
+      nonfinite = true;
+    } else {
+      const float l = log2f(fmaxf((float)fabs(p), 1e-37f)) - (float)g * log2f((float)w[0]);
+      const bool lower = p < 0.0 ? (ap >= 0.0 || l > al) : (ap >= 0.0 && l < al);
+      if (lower) { al = l; arho = w[0]; ap = p; }
+    }
     mrho = fmin(mrho, w[0]);
     mp = fmin(mp, p);
-    ms = fmin(ms, s);
     mdr = fmax(mdr, fabs(w[0] - rb));
-    nbad += admissible(w, smin, F) ? 0.0 : 1.0;
-    if (c < NSP) PM[c] = p;
+    nbad += admissible_screened(w, smin, F) ? 0.0 : 1.0;
+    if (c < NSP) S.PM[c] = p;
   }
-  mrho = block_min(mrho, red);
-  mp = block_min(mp, red);
-  ms = block_min(ms, red);
-  mdr = block_max(mdr, red);
-  nbad = block_sum(nbad, red);
+  double ms = al < INFINITY ? entropy_of(arho, ap, g) : INFINITY;
+  if (!isfinite(ms)) ms = -1e30;
+  if (nonfinite) ms = -1e30;
+  mrho = wave_min(mrho);
+  mp = wave_min(mp);
+  ms = wave_min(ms);
+  mdr = wave_max(mdr);
+  nbad = wave_sum(nbad);
+  wave_sync();
   // modal coefficients of the nodal pressure
   double* X = &S.T1[0][0];
   double* Y = &S.T2[0][0];
-  for (int o = t; o < NSP; o += FNT) X[o] = PM[o];
-  __syncthreads();
-  hex_to_modal<P>(X, Y, PM, 1, K);
+  for (int o = lane; o < NSP; o += 64) X[o] = S.PM[o];
+  wave_sync();
+  hex_wave_to_modal<P>(X, Y, S.PM, 1, K, lane);
   // shell energies of rho (U[0]), E (U[4]), p (PM)
-  double en[3][3];
+#pragma unroll
   for (int fi = 0; fi < 3; ++fi) {
-    const double* c = fi == 0 ? S.U[0] : (fi == 1 ? S.U[4] : PM);
+    const double* c = fi == 0 ? S.U[0] : (fi == 1 ? S.U[4] : S.PM);
     double sh[3] = {0, 0, 0};
-    for (int m = t; m < NSP; m += FNT) {
+    for (int m = lane; m < NSP; m += 64) {
       const int i = m % N1, j = (m / N1) % N1, k = m / (N1 * N1);
       const int shell = max(i, max(j, k));
       if (shell >= 1) sh[min(shell, 3) - 1] += c[m] * c[m];
     }
     const double e0 = c[0] * c[0] + 1e-300;
-    for (int q = 0; q < 3; ++q) en[fi][q] = block_sum(sh[q], red) / e0;
-  }
-  if (t == 0) {
-    float x[16];
-    for (int fi = 0; fi < 3; ++fi)
-      for (int q = 0; q < 3; ++q) x[3 * fi + q] = (float)log10(fmax(en[fi][q], 1e-30));
-    x[9] = (float)(mrho / rb - 1.0);
-    x[10] = (float)(mp / pb - 1.0);
-    x[11] = (float)fmin(fmax((ms - smin) / fmax(fabs(smin), 1e-300), -10.0), 10.0);
-    x[12] = (float)(nbad / (double)(NSP + NFP));
-    x[13] = (float)(mdr / rb);
-    x[14] = (float)log10(fmax(sb / fmax(smin, 1e-300), 1e-30));
-    x[15] = (float)(sqrt(vx * vx + vy * vy + vz * vz) / cb);
-    for (int k = 0; k < 16; ++k) {
-      if (feat) feat[e * 16 + k] = x[k];
-      if (xs) xs[k] = x[k];
-    }
-    if (flag) flag[e] = 1;
-  }
-  return true;
-}
-
-// Features of the candidates list[0 .. *count), one block looping over them.
-template <int P>
-__global__ void __launch_bounds__(FNT) hex_features(const double* __restrict__ u, const double* __restrict__ smin_a,
-                                                   int64_t E, const int32_t* __restrict__ list,
-                                                   const int32_t* __restrict__ count, FiltK K, FiltPrm F,
-                                                   int32_t* __restrict__ flag, float* __restrict__ feat) {
-  constexpr int N1 = P + 1, NSP = N1 * N1 * N1;
-  __shared__ HexFiltSmem<P> S;
-  __shared__ double red[FNT];
-  __shared__ double PM[NSP];
-  const int32_t m = *count;
-  for (int32_t i = blockIdx.x; i < m; i += gridDim.x) {
-    (void)hex_features_elem<P>(S, red, PM, u, smin_a, E, list[i], K, F, flag, feat, nullptr);
-    __syncthreads();
-  }
-}
-
-// The learned warm start in one pass per candidate: the feature pass (which also
-// loads the modal coefficients and checks zeta = 0), the MLP forward (lane j holds
-// hidden unit j of both layers, lanes 0..63; the flat weights W1[64][16] b1 W2[64][64] b2 w3 b3
-// and the input scaling [mean; std] are read through the caches), then the search
-// bracketed around the predicted index 2^(n y).
-template <int P>
-__global__ void __launch_bounds__(FNT, 4) hex_filter_learned(double* __restrict__ u, const double* __restrict__ smin_a,
-                                                         int64_t E, const int32_t* __restrict__ list,
-                                                         const int32_t* __restrict__ count, FiltK K, FiltPrm F,
-                                                         const float* __restrict__ w, const float* __restrict__ scale,
-                                                         int32_t* __restrict__ k_out, int32_t* __restrict__ evals_out,
-                                                         Dev32 s32) {
-  constexpr int N1 = P + 1, NSP = N1 * N1 * N1;
-  __shared__ HexFiltSmem<P> S;
-  __shared__ double red[FNT];
-  __shared__ double PM[NSP];
-  __shared__ float xs[16], h1[64];
-  const int t = threadIdx.x;
-  const int32_t m = *count;
-  for (int32_t i = blockIdx.x; i < m; i += gridDim.x) {
-    const int32_t e = list[i];
-    const bool troubled = hex_features_elem<P>(S, red, PM, u, smin_a, E, e, K, F, nullptr, nullptr, xs);
-    __syncthreads();
-    if (!troubled) continue;
-    if (t < 64) {
-      float a = w[64 * 16 + t];
 #pragma unroll
-      for (int k = 0; k < 16; ++k) a += w[t * 16 + k] * ((xs[k] - scale[k]) / scale[16 + k]);
-      h1[t] = tanhf(a);
+    for (int q = 0; q < 3; ++q) x[3 * fi + q] = (float)log10(fmax(wave_sum(sh[q]) / e0, 1e-30));
+  }
+  x[9] = (float)(mrho / rb - 1.0);
+  x[10] = (float)(mp / pb - 1.0);
+  x[11] = (float)fmin(fmax((ms - smin) / fmax(fabs(smin), 1e-300), -10.0), 10.0);
+  x[12] = (float)(nbad / (double)(NSP + NFP));
+  x[13] = (float)(mdr / rb);
+  x[14] = (float)log10(fmax(sb / fmax(smin, 1e-300), 1e-30));
+  x[15] = (float)(sqrt(vx * vx + vy * vy + vz * vz) / cb);
+}
+
+// Features of the candidates list[0 .. *count), one wave per candidate: flag[e] = 1 and
+// feat[e] for the elements failing the check at zeta = 0, flag[e] = 0 for the others.
+template <int P>
+__global__ void __launch_bounds__(64 * HexFW<P>::value) hex_features(
+    const double* __restrict__ u, const double* __restrict__ smin_a, int64_t E, const int32_t* __restrict__ list,
+    const int32_t* __restrict__ count, FiltK K, FiltPrm F, int32_t* __restrict__ flag, float* __restrict__ feat) {
+  constexpr int FW = HexFW<P>::value;
+  __shared__ HexWaveSmem<P> SM[FW];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  HexWaveSmem<P>& S = SM[wv];
+  const int32_t m = *count;
+  for (int32_t i = blockIdx.x * FW + wv; i < m; i += gridDim.x * FW) {
+    const int32_t e = list[i];
+    const double smin = smin_a[e];
+    hex_wave_load_modal<P>(S, u, E, e, K, lane);
+    hex_wave_set_w<P>(S, K, 0.0, lane);
+    if (hex_wave_checks<P>(S, lane, smin, F, nullptr, Dev32{}, E, e)) {
+      if (lane == 0) flag[e] = 0;
+      continue;
     }
-    __syncthreads();
-    double contrib = 0.0;
-    if (t < 64) {
-      float b = w[64 * 16 + 64 + 64 * 64 + t];
-      for (int k = 0; k < 64; ++k) b += w[64 * 16 + 64 + t * 64 + k] * h1[k];
-      contrib = (double)(w[64 * 16 + 64 + 64 * 64 + 64 + t] * tanhf(b));
+    float x[16];
+    hex_wave_features<P>(S, lane, smin, K, F, x);
+    if (lane < 16) {
+      float xv = x[0];
+#pragma unroll
+      for (int k = 1; k < 16; ++k) xv = lane == k ? x[k] : xv;
+      feat[(int64_t)e * 16 + lane] = xv;
     }
-    const double y = block_sum(contrib, red) + (double)w[64 * 16 + 64 + 64 * 64 + 64 + 64];
-    const float kh = exp2f((float)F.n_bits * (float)y);
-    hex_filter_elem<P>(S, u, smin_a, E, e, K, F, 1, kh, true, k_out, evals_out, s32);
-    __syncthreads();
+    if (lane == 0) flag[e] = 1;
+    wave_sync();
+  }
+}
+
+// The warm-start index 2^(n y) from the MLP forward pass on features x (wave-uniform):
+// lane t holds hidden unit t of both layers and reads its rows of the flat weights
+// W1[64][16] b1 W2[64][64] b2 w3 b3 (and the input scaling [mean; std]) through the
+// caches, 16 bytes at a time.
+__device__ __forceinline__ float mlp_wave_khat(const float* __restrict__ wm, const float* __restrict__ scale,
+                                               const float x[16], int lane, int n_bits) {
+  const float4* r1 = reinterpret_cast<const float4*>(wm + lane * 16);
+  float a = wm[64 * 16 + lane];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const float4 c = r1[q];
+    a += c.x * ((x[4 * q] - scale[4 * q]) / scale[16 + 4 * q]);
+    a += c.y * ((x[4 * q + 1] - scale[4 * q + 1]) / scale[16 + 4 * q + 1]);
+    a += c.z * ((x[4 * q + 2] - scale[4 * q + 2]) / scale[16 + 4 * q + 2]);
+    a += c.w * ((x[4 * q + 3] - scale[4 * q + 3]) / scale[16 + 4 * q + 3]);
+  }
+  const float h1 = tanhf(a);
+  const float4* r2 = reinterpret_cast<const float4*>(wm + 64 * 16 + 64 + lane * 64);
+  float b = wm[64 * 16 + 64 + 64 * 64 + lane];
+#pragma unroll 4
+  for (int q = 0; q < 16; ++q) {
+    const float4 c = r2[q];
+    b += c.x * rl_f(h1, 4 * q) + c.y * rl_f(h1, 4 * q + 1) + c.z * rl_f(h1, 4 * q + 2) + c.w * rl_f(h1, 4 * q + 3);
+  }
+  const double contrib = (double)(wm[64 * 16 + 64 + 64 * 64 + 64 + lane] * tanhf(b));
+  const double y = wave_sum(contrib) + (double)wm[64 * 16 + 64 + 64 * 64 + 64 + 64];
+  return exp2f((float)n_bits * (float)y);
+}
+
+// The learned warm start in one pass per candidate (one wave each): modal transform,
+// exact check at zeta = 0, features, the MLP forward, then the search bracketed around
+// the predicted index.
+template <int P>
+__global__ void __launch_bounds__(64 * HexFW<P>::value) hex_filter_learned(
+    double* __restrict__ u, const double* __restrict__ smin_a, int64_t E, const int32_t* __restrict__ list,
+    const int32_t* __restrict__ count, FiltK K, FiltPrm F, const float* __restrict__ w,
+    const float* __restrict__ scale, int32_t* __restrict__ k_out, int32_t* __restrict__ evals_out, Dev32 s32) {
+  constexpr int FW = HexFW<P>::value;
+  __shared__ HexWaveSmem<P> SM[FW];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  HexWaveSmem<P>& S = SM[wv];
+  const int32_t m = *count;
+  for (int32_t i = blockIdx.x * FW + wv; i < m; i += gridDim.x * FW) {
+    const int32_t e = list[i];
+    const double smin = smin_a[e];
+    hex_wave_load_modal<P>(S, u, E, e, K, lane);
+    hex_wave_set_w<P>(S, K, 0.0, lane);
+    if (hex_wave_checks<P>(S, lane, smin, F, nullptr, Dev32{}, E, e)) continue;
+    float x[16];
+    hex_wave_features<P>(S, lane, smin, K, F, x);
+    const float kh = mlp_wave_khat(w, scale, x, lane, F.n_bits);
+    hex_wave_search<P>(S, lane, u, smin, E, e, K, F, 1, kh, k_out, evals_out, s32);
   }
 }
 

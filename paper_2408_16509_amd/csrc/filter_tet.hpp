@@ -45,29 +45,13 @@ __device__ __forceinline__ double rl_d(double x, int l) {
   const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
   return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
-__device__ __forceinline__ float rl_f(float x, int l) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
-}
-
-// Butterfly reductions over the 64 lanes; every lane receives the same bits.
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int s = 32; s >= 1; s >>= 1) v += __shfl_xor(v, s);
-  return v;
-}
-__device__ __forceinline__ double wave_min(double v) {
-#pragma unroll
-  for (int s = 32; s >= 1; s >>= 1) v = fmin(v, __shfl_xor(v, s));
-  return v;
-}
-__device__ __forceinline__ double wave_max(double v) { return -wave_min(-v); }
-
 struct TetFiltWave {
   double x[5];      // nodal state at point z = lane (lanes >= 35: point 0, never checked)
   double uh[5];     // modal coefficient m = lane
   double Q[5][5];   // per-degree parts [d][v] at point z = lane
 };
 
+// Nodal state and modal coefficients of element e.
 __device__ __forceinline__ void tet_wave_load(const double* __restrict__ tab, const double* __restrict__ u, int64_t E,
                                               int64_t e, int lane, TetFiltWave& W) {
   const int z = lane < TF_NSP ? lane : 0;
@@ -82,6 +66,11 @@ __device__ __forceinline__ void tet_wave_load(const double* __restrict__ tab, co
 #pragma unroll
     for (int v = 0; v < 5; ++v) W.uh[v] += vi * rl_d(W.x[v], q);
   }
+}
+
+// The per-degree parts Q of the lane's point (from the modal coefficients).
+__device__ __forceinline__ void tet_wave_parts(const double* __restrict__ tab, int lane, TetFiltWave& W) {
+  const int z = lane < TF_NSP ? lane : 0;
 #pragma unroll
   for (int d = 0; d < 5; ++d) {
 #pragma unroll
@@ -110,7 +99,7 @@ __device__ __forceinline__ bool tet_wave_check(const TetFiltWave& W, double zeta
     for (int d = 1; d < 5; ++d) a += s[d] * W.Q[d][v];
     w[v] = a;
   }
-  return __all(lane >= TF_NSP || admissible(w, smin, F)) != 0;
+  return __all(lane >= TF_NSP || admissible_screened(w, smin, F)) != 0;
 }
 
 __device__ __forceinline__ bool tet_wave_ok0(const TetFiltWave& W, double smin, const FiltPrm& F, int lane) {
@@ -252,6 +241,7 @@ __global__ void __launch_bounds__(256) tet_filter(double* __restrict__ u, const 
     TetFiltWave W;
     tet_wave_load(tab, u, E, e, lane, W);
     if (tet_wave_ok0(W, smin, F, lane)) continue;   // k = 0, one evaluation (set by the reset)
+    tet_wave_parts(tab, lane, W);
     tet_filter_wave(W, u, smin, E, e, lane, F, 0, 0.0f, k_out, evals_out, s32);
   }
 }
@@ -285,10 +275,8 @@ __global__ void __launch_bounds__(256) tet_features(const double* __restrict__ u
   }
 }
 
-// The learned warm start in one pass per candidate: features, the MLP forward (lane t
-// holds hidden unit t of both layers; flat weights W1[64][16] b1 W2[64][64] b2 w3 b3
-// and the input scaling [mean; std] through the caches), then the search bracketed
-// around the predicted index 2^(n y).
+// The learned warm start in one pass per candidate: features, the MLP forward
+// (mlp_wave_khat), then the search bracketed around the predicted index 2^(n y).
 __global__ void __launch_bounds__(256) tet_filter_learned(double* __restrict__ u, const double* __restrict__ smin_a,
                                                           int64_t E, const int32_t* __restrict__ list,
                                                           const int32_t* __restrict__ count,
@@ -306,16 +294,8 @@ __global__ void __launch_bounds__(256) tet_filter_learned(double* __restrict__ u
     if (tet_wave_ok0(W, smin, F, lane)) continue;
     float x[16];
     tet_wave_features(W, tab, smin, F, lane, x);
-    float a = wm[64 * 16 + lane];
-#pragma unroll
-    for (int k = 0; k < 16; ++k) a += wm[lane * 16 + k] * ((x[k] - scale[k]) / scale[16 + k]);
-    const float h1 = tanhf(a);
-    float b = wm[64 * 16 + 64 + 64 * 64 + lane];
-#pragma unroll 8
-    for (int k = 0; k < 64; ++k) b += wm[64 * 16 + 64 + lane * 64 + k] * rl_f(h1, k);
-    const double contrib = (double)(wm[64 * 16 + 64 + 64 * 64 + 64 + lane] * tanhf(b));
-    const double y = wave_sum(contrib) + (double)wm[64 * 16 + 64 + 64 * 64 + 64 + 64];
-    const float kh = exp2f((float)F.n_bits * (float)y);
+    const float kh = mlp_wave_khat(wm, scale, x, lane, F.n_bits);
+    tet_wave_parts(tab, lane, W);
     tet_filter_wave(W, u, smin, E, e, lane, F, 1, kh, k_out, evals_out, s32);
   }
 }

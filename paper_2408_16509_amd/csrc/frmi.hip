@@ -624,7 +624,10 @@ void hex_candidates_p(fr_ctx c, DevBlock& b, const double* u) {
   c->prof_end(pk);
 }
 
-inline unsigned list_grid(const DevBlock& b) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b.n, 2048)); }
+// Grid of the per-candidate filter kernels: FW candidates (waves) per block.
+inline unsigned list_grid(const DevBlock& b, int fw) {
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>((b.n + fw - 1) / fw, 2048));
+}
 
 // Features (and the exact troubled flag) of the candidates of b.
 template <int P>
@@ -634,12 +637,14 @@ void hex_features_p(fr_ctx c, DevBlock& b, const double* u) {
   const int64_t o = b.elem_off;
   const int nb = (int)((b.n + 255) / 256);
   k_fill_i32<<<grid_for(b.n, 256), 256, 0, c->stream>>>(c->f_flag + o, b.n, 0);
-  hex_features<P><<<list_grid(b), FNT, 0, c->stream>>>(u + b.native_off, b.smin, b.E, b.f_list, b.f_cnt + nb, K, F,
+  constexpr int FW = HexFW<P>::value;
+  hex_features<P><<<list_grid(b, FW), 64 * FW, 0, c->stream>>>(u + b.native_off, b.smin, b.E, b.f_list, b.f_cnt + nb, K, F,
                                                        c->f_flag + o, c->f_feat + o * 16);
 }
 
 template <int P>
 void hex_filter_p(fr_ctx c, DevBlock& b, double* u, int mode, float* u32) {
+  constexpr int FW = HexFW<P>::value;
   const FiltK K = filtk_of(c->host.hex);
   const FiltPrm F = filtprm_of(c->prm, P);
   const int64_t o = b.elem_off;
@@ -650,20 +655,17 @@ void hex_filter_p(fr_ctx c, DevBlock& b, double* u, int mode, float* u32) {
   int pk;
   if (mode == 1) {
     pk = c->prof_begin("filter_search_learned");
-    hex_filter_learned<P><<<list_grid(b), FNT, 0, c->stream>>>(u + b.native_off, b.smin, b.E, b.f_list, b.f_cnt + nb,
-                                                              K, F, c->m_w, c->m_scale, c->f_k + o, c->f_evals + o,
-                                                              s32);
+    hex_filter_learned<P><<<list_grid(b, FW), 64 * FW, 0, c->stream>>>(
+        u + b.native_off, b.smin, b.E, b.f_list, b.f_cnt + nb, K, F, c->m_w, c->m_scale, c->f_k + o,
+        c->f_evals + o, s32);
   } else {
     pk = c->prof_begin("filter_search_plain");
-    hex_filter<P><<<list_grid(b), FNT, 0, c->stream>>>(u + b.native_off, b.smin, b.E, b.f_list, b.f_cnt + nb, K, F,
-                                                       0, nullptr, c->f_k + o, c->f_evals + o, s32);
+    hex_filter<P><<<list_grid(b, FW), 64 * FW, 0, c->stream>>>(u + b.native_off, b.smin, b.E, b.f_list,
+                                                               b.f_cnt + nb, K, F, c->f_k + o, c->f_evals + o, s32);
   }
   c->prof_end(pk);
 }
 
-inline unsigned wave_list_grid(const DevBlock& b) {
-  return (unsigned)std::max<int64_t>(1, std::min<int64_t>((b.n + 3) / 4, 2048));
-}
 
 void tet_smin(fr_ctx c, DevBlock& b, const double* uprev) {
   const int g = (int)((b.n + 255) / 256);
@@ -692,7 +694,7 @@ void tet_features_b(fr_ctx c, DevBlock& b, const double* u) {
   const int64_t o = b.elem_off;
   const int nb = (int)((b.n + 255) / 256);
   k_fill_i32<<<grid_for(b.n, 256), 256, 0, c->stream>>>(c->f_flag + o, b.n, 0);
-  tet_features<<<wave_list_grid(b), 256, 0, c->stream>>>(u + b.native_off, b.smin, b.E, b.f_list, b.f_cnt + nb,
+  tet_features<<<list_grid(b, 4), 256, 0, c->stream>>>(u + b.native_off, b.smin, b.E, b.f_list, b.f_cnt + nb,
                                                          c->tet_ftab, F, c->f_flag + o, c->f_feat + o * 16);
 }
 
@@ -706,12 +708,12 @@ void tet_filter_b(fr_ctx c, DevBlock& b, double* u, int mode, float* u32) {
   int pk;
   if (mode == 1) {
     pk = c->prof_begin("filter_search_learned");
-    tet_filter_learned<<<wave_list_grid(b), 256, 0, c->stream>>>(u + b.native_off, b.smin, b.E, b.f_list,
+    tet_filter_learned<<<list_grid(b, 4), 256, 0, c->stream>>>(u + b.native_off, b.smin, b.E, b.f_list,
                                                                  b.f_cnt + nb, c->tet_ftab, F, c->m_w, c->m_scale,
                                                                  c->f_k + o, c->f_evals + o, s32);
   } else {
     pk = c->prof_begin("filter_search_plain");
-    tet_filter<<<wave_list_grid(b), 256, 0, c->stream>>>(u + b.native_off, b.smin, b.E, b.f_list, b.f_cnt + nb,
+    tet_filter<<<list_grid(b, 4), 256, 0, c->stream>>>(u + b.native_off, b.smin, b.E, b.f_list, b.f_cnt + nb,
                                                          c->tet_ftab, F, c->f_k + o, c->f_evals + o, s32);
   }
   c->prof_end(pk);

@@ -1,7 +1,8 @@
 """Pins of the oracle's entropy filter and MLP.
 
 Filter: sigma_0 = 1 keeps element means; zeta = 0 is the identity; the hex filter is
-the tensor product of 1-D filters; after filtering every check point satisfies the
+the tensor product of 1-D filters; the tet filter damps polynomial states shell by
+shell in closed form; after filtering every check point satisfies the
 bounds; untouched elements stay bit-identical; the bisection result is minimal on
 the dyadic grid; the warm-started search returns the plain result.
 MLP: analytic gradient vs central differences; Adam's first step in closed form;
@@ -54,6 +55,35 @@ def test_filter_operator_properties():
             F1 = V1 @ np.diag(np.exp(-z * np.arange(p + 1) ** 2 / p ** 2)) @ np.linalg.inv(V1)
             F = np.kron(np.kron(F1, F1), F1)
             np.testing.assert_allclose(ef.filtered(b, u[:1], np.array([z]))[0], u[0] @ F.T, atol=1e-13)
+
+
+def test_tet_filter_shells_closed_form():
+    """The tetrahedral filter damps each total-degree shell by exp(-zeta (d/p)^2),
+    whatever orthonormal basis spans it: a state of degree <= 1 becomes its mean plus
+    exp(-zeta/p^2) times the rest; a state of degree <= 2 is A + exp(-zeta/p^2) B +
+    exp(-4 zeta/p^2) C for fixed fields A, B, C (fitted at three strengths, checked at
+    a fourth), with A its mean."""
+    ops = elements.ops_for(1, 4)
+
+    class B:
+        pass
+    b = B()
+    b.ops, b.etype = ops, 1
+    X = ops.sol_pts
+    w = ops.weights / ops.weights.sum()
+    lin = 0.3 + 1.2 * X[:, 0] - 0.7 * X[:, 1] + 0.4 * X[:, 2]
+    mean = lin @ w
+    for z in (0.5, 3.0, 40.0):
+        got = ef.filtered(b, np.tile(lin, (1, 5, 1)), np.array([z]))[0]
+        np.testing.assert_allclose(got, np.tile(mean + np.exp(-z / 16) * (lin - mean), (5, 1)), atol=1e-12)
+    quad = lin + 0.5 * X[:, 0] * X[:, 1] - 0.8 * X[:, 2] ** 2 + 0.2 * X[:, 1]
+    fz = lambda z: ef.filtered(b, np.tile(quad, (1, 1, 1)), np.array([z]))[0, 0]
+    zs = (0.0, 2.0, 7.0)
+    M = np.array([[1.0, np.exp(-z / 16), np.exp(-z / 4)] for z in zs])
+    ABC = np.linalg.solve(M, np.stack([fz(z) for z in zs]))
+    z4 = 13.0
+    np.testing.assert_allclose(fz(z4), np.array([1.0, np.exp(-z4 / 16), np.exp(-z4 / 4)]) @ ABC, atol=1e-11)
+    np.testing.assert_allclose(ABC[0], np.full(ops.nsp, quad @ w), atol=1e-12)
 
 
 def test_filter_bounds_minimality_and_warm_start(shock_case):

@@ -254,3 +254,52 @@ def test_mixed_context_filter_matches_oracle():
     assert all((kk != 0).sum() > 0 for kk in ko)
     assert np.array_equal(kg, np.concatenate(ko))
     _check_filtered(bl, got, u1, [r[0] for r in res], ko, smin)
+
+
+def test_filter_leaves_smooth_state_untouched():
+    """Degenerate case: a smooth state (Taylor--Green vortex) in a mixed context has no
+    candidate at all; the filter returns k = 0 everywhere and leaves u bit-identical,
+    in both modes."""
+    mesh = mixed_mesh(2)
+    bl = oracle_blocks(mesh, 4)
+    u = [np.moveaxis(inputs.tgv(b.xsol[..., 0], b.xsol[..., 1], b.xsol[..., 2], mach=0.1), 0, 1).copy() for b in bl]
+    smin = ef.smin_neighbourhood(bl, u, FP)
+    assert all(ef.filter_block(b, ub, sm, FP)[1].max() == 0 for b, ub, sm in zip(bl, u, smin))
+    ctx = _ctx(mesh)
+    ctx.mlp_set_weights(omlp.glorot_init(43), np.zeros(16), np.ones(16))
+    for mode in (0, 1):
+        ug = ctx.pack64(_flat(u))
+        before = ug.clone()
+        k = torch.full((sum(len(b.elems) for b in bl),), 7, dtype=torch.int32, device="cuda")
+        st = ctx.filter(ug, ug.clone(), mode=mode, k=k, stats=True)
+        assert st.n_candidates == 0 and st.n_troubled == 0 and st.n_evals == 0
+        assert int(k.abs().max()) == 0
+        assert torch.equal(ug, before)
+
+
+def test_hex_filter_fallback_and_single_element():
+    """Hexahedral fallback on a one-element periodic mesh (every face neighbour is the
+    element itself): the entropy reference comes from a uniform state of twice the
+    pre-shock entropy, which no filter strength can reach from the shock state, so the
+    element takes the strongest filter (k = -1), as in the oracle, for both caps."""
+    from paper_2408_16509_amd import frmi
+    mesh = inputs.hex_box((1, 1, 1))
+    bl = oracle_blocks(mesh, 3)
+    x = bl[0].xsol
+    ic = np.moveaxis(inputs.shock(x[..., 0], x[..., 1], x[..., 2]), 0, 1).copy()
+    ref = np.zeros_like(ic)
+    ref[:, 0], ref[:, 4] = 1.0, 2.0 / 0.4                 # rho = 1, v = 0, p = 2
+    for coef in (40.0, 0.05):
+        fp = ef.FilterParams(zeta_max_coef=coef)
+        smin = ef.smin_neighbourhood(bl, [ref], fp)
+        uo, ko, _ = ef.filter_block(bl[0], ic, smin[0], fp)
+        ctx = frmi.Context(mesh, system=0, order=3, riemann=1, filt_zeta_max_coef=coef)
+        ug = ctx.pack64(ic.ravel())
+        k = torch.zeros(1, dtype=torch.int32, device="cuda")
+        st = ctx.filter(ug, ctx.pack64(ref.ravel()), mode=0, k=k, stats=True)
+        got = ctx.unpack64(ug).cpu().numpy().reshape(ic.shape)
+        print(f"one hexahedron, zeta_max coefficient {coef}: k {int(k[0])} (oracle {int(ko[0])}), "
+              f"fallback {st.n_fallback}", flush=True)
+        assert ko[0] == -1 and st.n_fallback == 1
+        assert np.array_equal(k.cpu().numpy(), ko)
+        assert np.linalg.norm(got - uo) <= 1e-12 * np.linalg.norm(uo)

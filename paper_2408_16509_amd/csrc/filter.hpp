@@ -95,43 +95,77 @@ __global__ void k_fill_u64(unsigned long long* __restrict__ a, int64_t n, unsign
     a[i] = v;
 }
 
-// Minimum entropy of each element over its check points: one wave per (tile of 64
-// elements, line), as the detection; the solution points are taken on the lines
-// along xi_1, the flux points at every line's ends; NaN values are ignored (as fmin
-// does).  sown holds the minimum in ord_bits form and must start at ord_bits(+inf).
+// Check points of a tile of NE elements, each point read from HBM once: a block of
+// NE x (p+1)^2 threads stages the tile's states in LDS (U[v][pt][el], 40 KB at p = 3
+// and 4), thread (el, column (c0, c1)) then visits the N1 solution points of its own
+// column (the line along xi_3 through (c0, c1)), that line's two ends, and the ends of
+// the lines along xi_1 through (c0, c1) = (j, k) and along xi_2 through (c0, c1) = (i, k)
+// — every solution point once and every face flux point once.  f(w) is called per
+// check point with its state w[5].
 template <int P>
-__global__ void __launch_bounds__(256) hex_sown(const double* __restrict__ u, unsigned long long* __restrict__ sown,
-                                                int64_t E, int64_t n, FiltK K, double gamma) {
-  constexpr int N1 = P + 1, NL = 3 * N1 * N1;
-  const int64_t gtid = xcd_block() * 256 + threadIdx.x;
-  const int64_t wave = gtid >> 6;
-  const int lane = (int)(gtid & 63);
-  const int64_t tile = wave / NL;
-  const int l = (int)(wave % NL);
-  const int64_t e = tile * 64 + lane;
-  if (e >= n) return;
-  const int d = l / (N1 * N1), q = l % (N1 * N1), t0 = q % N1, t1 = q / N1;
+struct HexTileCfg {
+  static constexpr int N1 = P + 1, NE = P == 1 ? 64 : (P == 2 ? 32 : (P == 3 ? 16 : 8)), NT = NE * N1 * N1;
+};
+
+template <int P, typename Fn>
+__device__ __forceinline__ void hex_tile_checks(const double* __restrict__ u, double* U, int64_t E, int64_t e0,
+                                                const FiltK& K, Fn&& f) {
+  using C = HexTileCfg<P>;
+  constexpr int N1 = C::N1, NE = C::NE, NSP = N1 * N1 * N1;
+  const int el = threadIdx.x % NE, l = threadIdx.x / NE, c0 = l % N1, c1 = l / N1;
+  const int64_t e = e0 + el;
   double m[5] = {0, 0, 0, 0, 0}, pl[5] = {0, 0, 0, 0, 0};
-  double smin = INFINITY;
 #pragma unroll
   for (int a = 0; a < N1; ++a) {
-    const int pt = line_pt<N1>(d, a, t0, t1);
+    const int pt = c0 + N1 * (c1 + N1 * a);
     double w[5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
       w[v] = u[((int64_t)pt * 5 + v) * E + e];
+      U[(v * NSP + pt) * NE + el] = w[v];
       m[v] += K.lm[a] * w[v];
       pl[v] += K.lp[a] * w[v];
     }
-    if (d == 0) {
-      const double p = (gamma - 1.0) * (w[4] - 0.5 * (w[1] * w[1] + w[2] * w[2] + w[3] * w[3]) / w[0]);
-      smin = fmin(smin, entropy_of(w[0], p, gamma));
-    }
+    f(w);
   }
-  const double pm = (gamma - 1.0) * (m[4] - 0.5 * (m[1] * m[1] + m[2] * m[2] + m[3] * m[3]) / m[0]);
-  const double pp = (gamma - 1.0) * (pl[4] - 0.5 * (pl[1] * pl[1] + pl[2] * pl[2] + pl[3] * pl[3]) / pl[0]);
-  smin = fmin(smin, fmin(entropy_of(m[0], pm, gamma), entropy_of(pl[0], pp, gamma)));
-  if (!isnan(smin)) atomicMin(sown + e, ord_bits(smin));
+  f(m);
+  f(pl);
+  __syncthreads();
+#pragma unroll
+  for (int d = 0; d < 2; ++d) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) { m[v] = 0; pl[v] = 0; }
+#pragma unroll
+    for (int a = 0; a < N1; ++a) {
+      const int pt = d == 0 ? a + N1 * (c0 + N1 * c1) : c0 + N1 * (a + N1 * c1);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        const double x = U[(v * NSP + pt) * NE + el];
+        m[v] += K.lm[a] * x;
+        pl[v] += K.lp[a] * x;
+      }
+    }
+    f(m);
+    f(pl);
+  }
+}
+
+// Minimum entropy of each element over its check points (one tile of elements per
+// block, hex_tile_checks); NaN values are ignored (as fmin does).  sown holds the
+// minimum in ord_bits form and must start at ord_bits(+inf).
+template <int P>
+__global__ void __launch_bounds__(HexTileCfg<P>::NT) hex_sown(const double* __restrict__ u,
+                                                             unsigned long long* __restrict__ sown, int64_t E,
+                                                             int64_t n, FiltK K, double gamma) {
+  using C = HexTileCfg<P>;
+  __shared__ double U[5 * C::N1 * C::N1 * C::N1 * C::NE];
+  const int64_t e0 = xcd_block() * C::NE, e = e0 + threadIdx.x % C::NE;
+  double smin = INFINITY;
+  hex_tile_checks<P>(u, U, E, e0, K, [&](const double w[5]) {
+    const double p = (gamma - 1.0) * (w[4] - 0.5 * (w[1] * w[1] + w[2] * w[2] + w[3] * w[3]) / w[0]);
+    smin = fmin(smin, entropy_of(w[0], p, gamma));
+  });
+  if (e < n && !isnan(smin)) atomicMin(sown + e, ord_bits(smin));
 }
 
 // s_min over the element and its face neighbours.
@@ -402,10 +436,8 @@ __global__ void __launch_bounds__(64 * HexFW<P>::value) hex_filter(
 }
 
 // ---------------------------------------------------------------------------
-// Detection: elements that may fail the checks at zeta = 0.  One wave per (tile of
-// 64 elements, line of solution points), as the trace kernel: the line's two end
-// values are flux-point check points, and the lines along xi_1 also check their
-// solution points.  The test is pessimistic by a relative 1e-10 in rho, E and
+// Detection: elements that may fail the checks at zeta = 0, every check point of a
+// tile staged once (hex_tile_checks).  The test is pessimistic by a relative 1e-10 in rho, E and
 // |m|^2 (far above the rounding of either evaluation), so every element the exact
 // check of the search rejects is flagged; the search re-checks and leaves false
 // positives untouched.  flag must be cleared before.
@@ -423,38 +455,20 @@ __device__ __forceinline__ bool maybe_violates(const double w[5], double lsb, co
 }
 
 template <int P>
-__global__ void __launch_bounds__(256) hex_filter_detect(const double* __restrict__ u, const double* __restrict__ smin_a,
-                                                         int64_t E, int64_t n, FiltK K, FiltPrm F,
-                                                         int32_t* __restrict__ flag) {
-  constexpr int N1 = P + 1, NL = 3 * N1 * N1;
-  const int64_t gtid = xcd_block() * 256 + threadIdx.x;
-  const int64_t wave = gtid >> 6;
-  const int lane = (int)(gtid & 63);
-  const int64_t tile = wave / NL;
-  const int l = (int)(wave % NL);
-  const int64_t e = tile * 64 + lane;
-  if (e >= n) return;
-  const int d = l / (N1 * N1), q = l % (N1 * N1), t0 = q % N1, t1 = q / N1;
+__global__ void __launch_bounds__(HexTileCfg<P>::NT) hex_filter_detect(const double* __restrict__ u,
+                                                                      const double* __restrict__ smin_a, int64_t E,
+                                                                      int64_t n, FiltK K, FiltPrm F,
+                                                                      int32_t* __restrict__ flag) {
+  using C = HexTileCfg<P>;
+  __shared__ double U[5 * C::N1 * C::N1 * C::N1 * C::NE];
+  const int64_t e0 = xcd_block() * C::NE, e = e0 + threadIdx.x % C::NE;
   const double smin = smin_a[e];
   const double sb = smin - F.eps_s * fabs(smin);
   const double sbm = sb + 1e-10 * fabs(sb);
   const double lsb = sbm > 0 ? log(sbm) : -INFINITY;
-  double m[5] = {0, 0, 0, 0, 0}, pl[5] = {0, 0, 0, 0, 0};
   bool bad = false;
-#pragma unroll
-  for (int a = 0; a < N1; ++a) {
-    const int pt = line_pt<N1>(d, a, t0, t1);
-    double w[5];
-#pragma unroll
-    for (int v = 0; v < 5; ++v) {
-      w[v] = u[((int64_t)pt * 5 + v) * E + e];
-      m[v] += K.lm[a] * w[v];
-      pl[v] += K.lp[a] * w[v];
-    }
-    if (d == 0) bad = bad || maybe_violates(w, lsb, F);
-  }
-  bad = bad || maybe_violates(m, lsb, F) || maybe_violates(pl, lsb, F);
-  if (bad) flag[e] = 1;
+  hex_tile_checks<P>(u, U, E, e0, K, [&](const double w[5]) { bad = bad || maybe_violates(w, lsb, F); });
+  if (bad && e < n) flag[e] = 1;
 }
 
 __global__ void k_fill_i32(int32_t* __restrict__ a, int64_t n, int32_t v) {

@@ -591,14 +591,12 @@ fr_status filter_alloc(fr_ctx c) {
 template <int P>
 void hex_smin_p(fr_ctx c, DevBlock& b, const double* uprev) {
   const FiltK K = filtk_of(c->host.hex);
-  constexpr int N1 = P + 1;
   const int g = (int)((b.n + 255) / 256);
-  const int64_t threads = b.E * 3 * N1 * N1;
   unsigned long long* sown = (unsigned long long*)b.sown;
   int pk = c->prof_begin("filter_smin");
   k_fill_u64<<<grid_for(b.n, 256), 256, 0, c->stream>>>(sown, b.n, 0xFFF0000000000000ULL);   // ord_bits(+inf)
-  hex_sown<P><<<(unsigned)((threads + 255) / 256), 256, 0, c->stream>>>(uprev + b.native_off, sown, b.E, b.n, K,
-                                                                          c->prm.gamma);
+  hex_sown<P><<<(unsigned)(b.E / HexTileCfg<P>::NE), HexTileCfg<P>::NT, 0, c->stream>>>(
+      uprev + b.native_off, sown, b.E, b.n, K, c->prm.gamma);
   elem_smin<<<g, 256, 0, c->stream>>>(sown, b.nbr_elem, b.nfaces, b.smin, b.E, b.n);
   c->prof_end(pk);
 }
@@ -607,7 +605,6 @@ void hex_smin_p(fr_ctx c, DevBlock& b, const double* uprev) {
 // b.f_list / count b.f_cnt[nb]; untouched elements get k = 0 and one evaluation.
 template <int P>
 void hex_candidates_p(fr_ctx c, DevBlock& b, const double* u) {
-  constexpr int N1 = P + 1;
   const FiltK K = filtk_of(c->host.hex);
   const FiltPrm F = filtprm_of(c->prm, P);
   const int64_t o = b.elem_off;
@@ -615,9 +612,8 @@ void hex_candidates_p(fr_ctx c, DevBlock& b, const double* u) {
   const int gf = grid_for(b.n, 256);
   int pk = c->prof_begin("filter_detect");
   k_filter_reset<<<gf, 256, 0, c->stream>>>(b.f_det, c->f_k + o, c->f_evals + o, b.n);
-  const int64_t threads = b.E * 3 * N1 * N1;
-  hex_filter_detect<P><<<(unsigned)((threads + 255) / 256), 256, 0, c->stream>>>(u + b.native_off, b.smin, b.E, b.n,
-                                                                                  K, F, b.f_det);
+  hex_filter_detect<P><<<(unsigned)(b.E / HexTileCfg<P>::NE), HexTileCfg<P>::NT, 0, c->stream>>>(
+      u + b.native_off, b.smin, b.E, b.n, K, F, b.f_det);
   k_flag_count<<<nb, 256, 0, c->stream>>>(b.f_det, b.n, b.f_cnt);
   k_scan_counts<<<1, 1024, 0, c->stream>>>(b.f_cnt, nb);
   k_flag_scatter<<<nb, 256, 0, c->stream>>>(b.f_det, b.n, b.f_cnt, b.f_list);

@@ -88,8 +88,8 @@ typedef struct {
   double u_ref[5];         /* reference state of the FP32 deviation form             */
   double filt_eps_rho;     /* entropy filter: density floor                          */
   double filt_eps_p;       /* entropy filter: pressure floor                         */
-  double filt_eps_s;       /* entropy filter: relative entropy tolerance             */
-  double filt_zeta_max_coef; /* zeta_max = coef * p^2                                */
+  double filt_eps_s;       /* entropy filter: relative entropy tolerance (all >= 0)  */
+  double filt_zeta_max_coef; /* zeta_max = coef * p^2, coef > 0 and finite          */
   int32_t filt_bits;       /* dyadic search depth n (2^n grid), 1..30                */
   int32_t reserved1;
 } fr_params;

@@ -911,6 +911,10 @@ fr_status fr_setup_mesh(const fr_params* p, int64_t n_vert, const double* xyz, c
     return fail(nullptr, FR_ERR_ARG, "the FP32 form needs a reference state at rest with rho > 0, E > 0");
   if (!(p->gamma > 1.0)) return fail(nullptr, FR_ERR_ARG, "gamma must exceed 1");
   if (p->filt_bits < 1 || p->filt_bits > 30) return fail(nullptr, FR_ERR_ARG, "filt_bits must be in 1..30");
+  if (!(p->filt_zeta_max_coef > 0) || !std::isfinite(p->filt_zeta_max_coef))
+    return fail(nullptr, FR_ERR_ARG, "filt_zeta_max_coef must be positive and finite");
+  if (!(p->filt_eps_rho >= 0) || !(p->filt_eps_p >= 0) || !(p->filt_eps_s >= 0))
+    return fail(nullptr, FR_ERR_ARG, "filter floors and entropy tolerance must be >= 0");
   if (p->elem_order < 0 || p->elem_order > 2) return fail(nullptr, FR_ERR_ARG, "elem_order must be 0, 1 or 2");
   fr_ctx c = new (std::nothrow) fr_ctx_s();
   if (!c) return fail(nullptr, FR_ERR_ALLOC, "context allocation");

@@ -82,3 +82,9 @@ def test_mesh_errors_are_reported_before_device_work():
     m.enodes[0, 0] = 10 ** 6
     st, msg = setup(m)
     assert st == 1
+    # parameter errors
+    for kw, word in ((dict(filt_bits=31), "filt_bits"), (dict(filt_zeta_max_coef=0.0), "zeta"),
+                     (dict(filt_eps_s=-1.0), "tolerance"), (dict(gamma=1.0), "gamma"),
+                     (dict(precision=1, u_ref=(1.0, 0.5, 0.0, 0.0, 2.5)), "rest"), (dict(elem_order=3), "elem_order")):
+        st, msg = setup(inputs.hex_box((1, 1, 1)), **kw)
+        assert st == 1 and word in msg, (kw, msg)

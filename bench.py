@@ -99,15 +99,19 @@ def kernel_bytes_per_elem(name, nsp, nfp):
 
 
 def source_hash(kernel=""):
-    """Hash of the sources a kernel family is built from (its header, the shared
-    physics, and the library file that launches it)."""
-    files = ("hex.hpp", "physics.hpp", "frmi.hip")
-    if kernel.startswith("tet_"):
-        files = ("tet.hpp",) + files
+    """Hash of the sources a kernel family is built from: its header, the shared physics,
+    and the section of the library that configures and launches the RHS kernels."""
+    csrc = os.path.join(ROOT, "paper_2408_16509_amd", "csrc")
+    files = ("hex.hpp", "physics.hpp") if not kernel.startswith("tet_") else ("tet.hpp", "hex.hpp", "physics.hpp")
     h = hashlib.sha256()
     for f in files:
-        with open(os.path.join(ROOT, "paper_2408_16509_amd", "csrc", f), "rb") as fh:
+        with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
+    with open(os.path.join(csrc, "frmi.hip"), "rb") as fh:
+        lib = fh.read()
+    a = lib.index(b"// ------------------------------------------------------------ hex dispatch")
+    b = lib.index(b"// ------------------------------------------------------------ entropy filter")
+    h.update(lib[a:b])
     return h.hexdigest()[:16]
 
 

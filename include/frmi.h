@@ -117,6 +117,30 @@ typedef struct {
   int64_t n_candidates;    /* elements the detection passed to the exact search      */
 } fr_filter_stats;
 
+/* Adaptive time stepping (Sec. "Adaptive time stepping": low-storage Runge--Kutta with
+ * an embedded pair; the error estimate of each step, normalised, decides acceptance and
+ * the next step size).  Scheme: the third-order, four-stage pair with a second-order
+ * embedded solution RK3(2)4[2R+]C of Kennedy, Carpenter & Lewis (2000), carried in the
+ * two-register "2R+" form plus an error register.  Norm: RMS over all values of
+ * e / (atol + rtol max(|u_n|, |u_{n+1}|)), e = u_{n+1} - u^_{n+1}; accepted if <= 1;
+ * next step dt min(fac_max, max(fac_min, safety norm^(-1/3))) (fac_min if the norm is
+ * not finite); the last step is shortened to land on t_end. */
+typedef struct {
+  double atol, rtol;       /* error scale per value: atol + rtol max(|u_n|, |u_{n+1}|) (> 0) */
+  double safety;           /* controller safety factor (0, 1]                         */
+  double fac_min, fac_max; /* bounds of the step-size change, 0 < fac_min <= 1 <= fac_max */
+  int32_t max_attempts;    /* accepted + rejected steps before returning (>= 1)       */
+  int32_t reserved;
+} fr_adaptive_params;
+
+typedef struct {
+  int64_t accepted, rejected;  /* steps                                               */
+  int64_t n_rhs;               /* right-hand sides evaluated (4 per attempted step)   */
+  double t;                    /* time reached (t_end unless max_attempts ran out)    */
+  double dt_next;              /* proposed size of the next step                      */
+  double last_norm;            /* error norm of the last attempted step               */
+} fr_adaptive_stats;
+
 /* Fill p with defaults: Euler, order 3, Rusanov, FP64, gamma 1.4, mu 1/1600,
  * Pr 0.71, beta 0.5, tau 0.1, u_ref = (1, 0, 0, 0, 1/((gamma-1) gamma Ma^2) with
  * Ma 0.1), filter floors 1e-8, entropy tolerance 1e-4, zeta_max 40 p^2, 20 bits. */
@@ -169,6 +193,21 @@ fr_status fr_rhs(fr_ctx ctx, const void* u_dev, void* r_dev);
  * accumulation and the filter (with its checks) stay FP64.  Both element types
  * (the filter treats each block with its own modal basis). */
 fr_status fr_rk_step(fr_ctx ctx, void* u_dev, double dt, int32_t n_steps, int32_t filter_mode);
+
+/* Defaults of fr_rk_adaptive: atol = rtol = 1e-6, safety 0.9, fac_min 0.3, fac_max 2.5,
+ * 100000 attempts. */
+void fr_default_adaptive_params(fr_adaptive_params* p);
+
+/* Advance the FP64 native state u (in place) from t = 0 to t_end with adaptive steps
+ * of the embedded pair above, starting from the step size dt0; rejected steps restore
+ * u_n.  In the FP32 form the right-hand sides run on FP32 deviations while the state,
+ * the stage registers' FP64 parts, the error register and the norm are FP64.  No
+ * entropy filter.  stats (host) receives the counts; the call synchronises once per
+ * attempted step (the norm decides on the host).  Errors: FR_ERR_ARG (NULL, t_end or
+ * dt0 not positive and finite, parameters out of range), FR_ERR_ALLOC, FR_ERR_DEVICE;
+ * a non-finite norm counts as a rejected step (the controller shrinks dt). */
+fr_status fr_rk_adaptive(fr_ctx ctx, void* u_dev, double t_end, double dt0, const fr_adaptive_params* prm,
+                         fr_adaptive_stats* stats);
 
 /* Entropy-bounded modal filter (Sec. "Numerical Stability", entropy filtering)
  * of the FP64 native state u in place; the minimum entropy of each element's

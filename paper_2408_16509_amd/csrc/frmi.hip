@@ -107,6 +107,9 @@ struct fr_ctx_s {
   void* tet_ogT = nullptr;    // [TGR_K][TGR_M] transposed stacked gradient operator
   void* tet_opH = nullptr;    // BF16x3 split of the divergence operator: hi [TET_MP][TET_KP16], then lo
   void* tet_ogH = nullptr;    // BF16x3 split of the gradient operator: hi [TGR_M][TGR_K], then lo
+  double* rk_x0 = nullptr;    // adaptive stepping: u_n and the error register (FP64)
+  double* rk_err = nullptr;
+  double* rk_part = nullptr;   // adaptive stepping: per-workgroup partial sums of the norm
   double* rk_s64 = nullptr;   // FP64 stage state of the filtered FP32 form    // [TET_KP][TET_MP] transposed divergence operator
   int32_t* tet_src = nullptr;
   double* tet_ftab = nullptr; // entropy filter on tetrahedra: modal operators, weights, multiplicities
@@ -268,6 +271,48 @@ __global__ void k_to_dev(const double* __restrict__ u, float* __restrict__ w, in
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     w[i] = (float)(u[i] - ref.v[(i / E) % 5]);
 }
+// ------------------------------------------------------------ embedded-pair stages
+// One stage of the two-register embedded pair on a block's native values: with
+// x = X (= u_n + dt sum_{j<i} b_j k_j) and the stage's increment k,
+//   Y = x + dt a_{i+1,i} k  (the next stage state; in the native dtype, FP32 deviation
+//   in the FP32 form), X = x + dt b_i k, Err (+)= dt (b_i - b^_i) k; the first stage also
+// saves X0 = u_n.
+template <typename KT, typename YT>
+__global__ void k_lsrk_stage(double* __restrict__ X, double* __restrict__ X0, const KT* __restrict__ K,
+                             YT* __restrict__ Y, double* __restrict__ Err, int64_t n, int64_t E, double ya,
+                             double xb, double ed, int first, int last, RefVec ref) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double x = X[i], k = (double)K[i];
+    if (first) X0[i] = x;
+    if (!last) Y[i] = (YT)(x + ya * k - (sizeof(YT) == 4 ? ref.v[(i / E) % 5] : 0.0));
+    X[i] = x + xb * k;
+    Err[i] = (first ? 0.0 : Err[i]) + ed * k;
+  }
+}
+
+// Partial sums of (Err / (atol + rtol max(|X0|, |X|)))^2 over a block's real elements
+// (native index mod E < n_real): one FP64 sum per workgroup, in a fixed order.
+__global__ void __launch_bounds__(256) k_err_sumsq(const double* __restrict__ Err, const double* __restrict__ X0,
+                                                    const double* __restrict__ X, int64_t n, int64_t E,
+                                                    int64_t n_real, double atol, double rtol,
+                                                    double* __restrict__ part) {
+  __shared__ double red[256];
+  double a = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    if (i % E >= n_real) continue;
+    const double sc = atol + rtol * fmax(fabs(X0[i]), fabs(X[i]));
+    const double q = Err[i] / sc;
+    a += q * q;
+  }
+  red[threadIdx.x] = a;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
 __global__ void k_pack32(const double* __restrict__ canon, float* __restrict__ nat, const int32_t* __restrict__ cpos,
                          int64_t n, int64_t E, int nsp, RefVec ref) {
   const int64_t total = (int64_t)nsp * 5 * E;
@@ -880,6 +925,7 @@ void fr_destroy(fr_ctx c) {
   (void)hipFree(c->perm);
   (void)hipFree(c->g_npos);
   (void)hipFree(c->rk_stage); (void)hipFree(c->rk_acc); (void)hipFree(c->rk_k); (void)hipFree(c->rk_s64);
+  (void)hipFree(c->rk_x0); (void)hipFree(c->rk_err); (void)hipFree(c->rk_part);
   (void)hipFree(c->flag);
   (void)hipFree(c->tet_src); (void)hipFree(c->tet_opT); (void)hipFree(c->tet_ogT);
   (void)hipFree(c->tet_opH); (void)hipFree(c->tet_ogH); (void)hipFree(c->tet_ftab);
@@ -1175,6 +1221,141 @@ fr_status fr_rhs(fr_ctx c, const void* u, void* r) {
   return rhs_native(c, u, r);
 }
 
+}  // extern "C"
+
+namespace {
+// RK workspace: stage state and increment in the native dtype, FP64 accumulator.
+fr_status rk_alloc(fr_ctx c) {
+  if (c->rk_stage) return FR_OK;
+  const int64_t n = c->native_len;
+  const size_t tsz = c->prm.precision != FR_FP64 ? sizeof(float) : sizeof(double);
+  if (dalloc(c, (char**)&c->rk_stage, n * tsz) || dalloc(c, &c->rk_acc, n) || dalloc(c, (char**)&c->rk_k, n * tsz))
+    return FR_ERR_ALLOC;
+  // padding lanes are never written by the RHS: keep them defined (zero increments)
+  HIP_TRY(c, hipMemsetAsync(c->rk_k, 0, n * tsz, c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->rk_stage, 0, n * tsz, c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->rk_acc, 0, n * sizeof(double), c->stream));
+  return FR_OK;
+}
+
+// RK3(2)4[2R+]C (Kennedy, Carpenter & Lewis 2000): subdiagonal, weights, embedded weights.
+constexpr double kLsA[3][2] = {{11847461282814.0, 36547543011857.0}, {3943225443063.0, 7078155732230.0},
+                               {-346793006927.0, 4029903576067.0}};
+constexpr double kLsB[4][2] = {{1017324711453.0, 9774461848756.0}, {8237718856693.0, 13685301971492.0},
+                               {57731312506979.0, 19404895981398.0}, {-101169746363290.0, 37734290219643.0}};
+constexpr double kLsBh[4][2] = {{15763415370699.0, 46270243929542.0}, {514528521746.0, 5659431552419.0},
+                                {27030193851939.0, 9429696342944.0}, {-69544964788955.0, 30262026368149.0}};
+constexpr int kNormGrid = 1024;
+}  // namespace
+
+extern "C" {
+
+void fr_default_adaptive_params(fr_adaptive_params* p) {
+  if (!p) return;
+  p->atol = 1e-6;
+  p->rtol = 1e-6;
+  p->safety = 0.9;
+  p->fac_min = 0.3;
+  p->fac_max = 2.5;
+  p->max_attempts = 100000;
+  p->reserved = 0;
+}
+
+fr_status fr_rk_adaptive(fr_ctx c, void* u_, double t_end, double dt0, const fr_adaptive_params* ap,
+                         fr_adaptive_stats* stats) {
+  if (!c || !u_ || !ap) return fail(c, FR_ERR_ARG, "NULL argument");
+  if (!(t_end > 0) || !std::isfinite(t_end) || !(dt0 > 0) || !std::isfinite(dt0))
+    return fail(c, FR_ERR_ARG, "t_end and dt0 must be positive and finite");
+  if (!(ap->atol > 0) || !(ap->rtol >= 0) || !(ap->safety > 0) || !(ap->safety <= 1) || !(ap->fac_min > 0) ||
+      !(ap->fac_min <= 1) || !(ap->fac_max >= 1) || !std::isfinite(ap->fac_max) || ap->max_attempts < 1)
+    return fail(c, FR_ERR_ARG, "adaptive parameters out of range");
+  fr_status st;
+  if ((st = rk_alloc(c))) return st;
+  const int64_t n = c->native_len;
+  if (!c->rk_x0) {
+    if (dalloc(c, &c->rk_x0, n) || dalloc(c, &c->rk_err, n) ||
+        dalloc(c, &c->rk_part, (int64_t)kNormGrid * (int64_t)c->blocks.size()))
+      return FR_ERR_ALLOC;
+  }
+  double* X = (double*)u_;
+  const bool f32 = c->prm.precision != FR_FP64;
+  const RefVec ref = refvec(c->prm);
+  int64_t count = 0;
+  for (auto& b : c->blocks) count += b.n * b.nsp * 5;
+  std::vector<double> part(c->blocks.size() * kNormGrid);
+  // one stage update on every block
+  auto stage = [&](int i, double h) {
+    const double ya = i < 3 ? h * (kLsA[i][0] / kLsA[i][1]) : 0.0;
+    const double xb = h * (kLsB[i][0] / kLsB[i][1]);
+    const double ed = h * (kLsB[i][0] / kLsB[i][1] - kLsBh[i][0] / kLsBh[i][1]);
+    for (auto& b : c->blocks) {
+      const int64_t nb = (int64_t)b.nsp * 5 * b.E, o = b.native_off;
+      const int gb = grid_for(nb, 256);
+      if (f32)
+        k_lsrk_stage<float, float><<<gb, 256, 0, c->stream>>>(X + o, c->rk_x0 + o, (const float*)c->rk_k + o,
+                                                              (float*)c->rk_stage + o, c->rk_err + o, nb, b.E, ya,
+                                                              xb, ed, i == 0, i == 3, ref);
+      else
+        k_lsrk_stage<double, double><<<gb, 256, 0, c->stream>>>(X + o, c->rk_x0 + o, (const double*)c->rk_k + o,
+                                                                (double*)c->rk_stage + o, c->rk_err + o, nb, b.E,
+                                                                ya, xb, ed, i == 0, i == 3, ref);
+    }
+  };
+  fr_adaptive_stats s{};
+  double t = 0.0, dt = dt0, nrm = 0.0;
+  while (t < t_end && s.accepted + s.rejected < ap->max_attempts) {
+    const bool last = dt >= t_end - t;
+    const double h = last ? t_end - t : dt;
+    for (int i = 0; i < 4; ++i) {
+      void* in = c->rk_stage;
+      if (i == 0) {
+        if (f32) {
+          for (auto& b : c->blocks) {
+            const int64_t nb = (int64_t)b.nsp * 5 * b.E, o = b.native_off;
+            k_to_dev<<<grid_for(nb, 256), 256, 0, c->stream>>>(X + o, (float*)c->rk_stage + o, nb, b.E, ref);
+          }
+        } else {
+          in = X;
+        }
+      }
+      if ((st = rhs_native(c, in, c->rk_k))) return st;
+      stage(i, h);
+    }
+    for (size_t bi = 0; bi < c->blocks.size(); ++bi) {
+      const DevBlock& b = c->blocks[bi];
+      const int64_t nb = (int64_t)b.nsp * 5 * b.E, o = b.native_off;
+      k_err_sumsq<<<kNormGrid, 256, 0, c->stream>>>(c->rk_err + o, c->rk_x0 + o, X + o, nb, b.E, b.n, ap->atol,
+                                                     ap->rtol, c->rk_part + bi * kNormGrid);
+    }
+    HIP_TRY(c, hipGetLastError());
+    HIP_TRY(c, hipMemcpyAsync(part.data(), c->rk_part, part.size() * sizeof(double), hipMemcpyDeviceToHost,
+                              c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    double sum = 0.0;
+    for (double v : part) sum += v;
+    nrm = std::sqrt(sum / (double)count);
+    s.n_rhs += 4;
+    if (nrm <= 1.0) {
+      t = last ? t_end : t + h;
+      ++s.accepted;
+    } else {
+      HIP_TRY(c, hipMemcpyAsync(X, c->rk_x0, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+      ++s.rejected;
+    }
+    double fac;
+    if (!std::isfinite(nrm)) fac = ap->fac_min;
+    else if (nrm == 0.0) fac = ap->fac_max;
+    else fac = std::min(ap->fac_max, std::max(ap->fac_min, ap->safety * std::pow(nrm, -1.0 / 3.0)));
+    dt = h * fac;
+  }
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  s.t = t;
+  s.dt_next = dt;
+  s.last_norm = nrm;
+  if (stats) *stats = s;
+  return FR_OK;
+}
+
 fr_status fr_rk_step(fr_ctx c, void* u_, double dt, int32_t n_steps, int32_t filter_mode) {
   if (!c || !u_) return fail(c, FR_ERR_ARG, "NULL argument");
   if (n_steps < 0 || !std::isfinite(dt)) return fail(c, FR_ERR_ARG, "n_steps or dt");
@@ -1187,18 +1368,10 @@ fr_status fr_rk_step(fr_ctx c, void* u_, double dt, int32_t n_steps, int32_t fil
   double* u = (double*)u_;
   const int64_t n = c->native_len;
   const bool f32 = c->prm.precision != FR_FP64;
-  const size_t tsz = f32 ? sizeof(float) : sizeof(double);
-  if (!c->rk_stage) {
-    if (dalloc(c, (char**)&c->rk_stage, n * tsz) || dalloc(c, &c->rk_acc, n) || dalloc(c, (char**)&c->rk_k, n * tsz))
-      return FR_ERR_ALLOC;
-    // padding lanes are never written by the RHS: keep them defined (zero increments)
-    HIP_TRY(c, hipMemsetAsync(c->rk_k, 0, n * tsz, c->stream));
-    HIP_TRY(c, hipMemsetAsync(c->rk_stage, 0, n * tsz, c->stream));
-    HIP_TRY(c, hipMemsetAsync(c->rk_acc, 0, n * sizeof(double), c->stream));
-  }
+  fr_status st;
+  if ((st = rk_alloc(c))) return st;
   const int g = grid_for(n, 256);
   const double b1 = dt / 6.0, b2 = dt / 3.0, c2 = dt / 2.0;
-  fr_status st;
   int pk;
   if (!f32) {
     double *K = (double*)c->rk_k, *S = (double*)c->rk_stage;

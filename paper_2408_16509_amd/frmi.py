@@ -49,6 +49,17 @@ class FrFilterStats(ctypes.Structure):
                 ("n_evals", ctypes.c_int64), ("seconds", ctypes.c_double), ("n_candidates", ctypes.c_int64)]
 
 
+class FrAdaptiveParams(ctypes.Structure):
+    _fields_ = [("atol", ctypes.c_double), ("rtol", ctypes.c_double), ("safety", ctypes.c_double),
+                ("fac_min", ctypes.c_double), ("fac_max", ctypes.c_double), ("max_attempts", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class FrAdaptiveStats(ctypes.Structure):
+    _fields_ = [("accepted", ctypes.c_int64), ("rejected", ctypes.c_int64), ("n_rhs", ctypes.c_int64),
+                ("t", ctypes.c_double), ("dt_next", ctypes.c_double), ("last_norm", ctypes.c_double)]
+
+
 class FrKernelTime(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
 
@@ -56,7 +67,7 @@ class FrKernelTime(ctypes.Structure):
 EXPORTS = [
     "fr_default_params", "fr_setup_mesh", "fr_layout", "fr_sol_points", "fr_pack", "fr_unpack",
     "fr_pack64", "fr_unpack64", "fr_unpack_rhs",
-    "fr_rhs", "fr_rk_step", "fr_filter", "fr_mlp_set_weights", "fr_mlp_get_weights",
+    "fr_rhs", "fr_rk_step", "fr_default_adaptive_params", "fr_rk_adaptive", "fr_filter", "fr_mlp_set_weights", "fr_mlp_get_weights",
     "fr_mlp_features", "fr_mlp_collect", "fr_mlp_forward", "fr_mlp_grad", "fr_mlp_train", "fr_check", "fr_sync",
     "fr_profile", "fr_profile_read",
     "fr_destroy", "fr_last_error",
@@ -81,6 +92,8 @@ def load():
         "fr_unpack_rhs": (i32, [vp, vp, vp]),
         "fr_rhs": (i32, [vp, vp, vp]),
         "fr_rk_step": (i32, [vp, vp, dbl, i32, i32]),
+        "fr_default_adaptive_params": (None, [P(FrAdaptiveParams)]),
+        "fr_rk_adaptive": (i32, [vp, vp, dbl, dbl, P(FrAdaptiveParams), P(FrAdaptiveStats)]),
         "fr_filter": (i32, [vp, vp, vp, i32, vp, P(FrFilterStats)]),
         "fr_mlp_set_weights": (i32, [vp, vp, vp, vp]),
         "fr_mlp_get_weights": (i32, [vp, vp]),
@@ -227,6 +240,19 @@ class Context:
 
     def rk_step(self, u, dt, n_steps=1, filter_mode=-1):
         self._check(lib().fr_rk_step(self.h, _ptr(u), float(dt), int(n_steps), int(filter_mode)))
+
+    def rk_adaptive(self, u, t_end, dt0, **params):
+        """Adaptive steps of the embedded pair from t = 0 to t_end (FP64 native state u, in
+        place); params override fr_default_adaptive_params (atol, rtol, safety, fac_min,
+        fac_max, max_attempts).  Returns the FrAdaptiveStats."""
+        p = FrAdaptiveParams()
+        lib().fr_default_adaptive_params(ctypes.byref(p))
+        for k, v in params.items():
+            setattr(p, k, v)
+        st = FrAdaptiveStats()
+        self._check(lib().fr_rk_adaptive(self.h, _ptr(u), float(t_end), float(dt0), ctypes.byref(p),
+                                          ctypes.byref(st)))
+        return st
 
     def filter(self, u, u_prev=None, mode=0, k=None, stats=False):
         s = FrFilterStats() if stats else None

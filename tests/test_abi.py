@@ -48,6 +48,10 @@ def test_binding_covers_header_and_argument_errors():
     # NULL context calls fail cleanly
     assert lib.fr_rhs(None, None, None) == 1
     assert lib.fr_sync(None) == 1
+    ap = frmi.FrAdaptiveParams()
+    lib.fr_default_adaptive_params(ctypes.byref(ap))
+    assert ap.atol == 1e-6 and ap.fac_max == 2.5 and ap.max_attempts == 100000
+    assert lib.fr_rk_adaptive(None, None, 1.0, 0.1, ctypes.byref(ap), None) == 1
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libfrmi.so not built")

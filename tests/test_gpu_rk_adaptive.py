@@ -1,0 +1,113 @@
+"""GPU adaptive time stepping (embedded pair RK3(2)4[2R+]C with the step-size
+controller) against the FP64 oracle integrating the same problem.
+
+FP64 form: the same sequence of accepted and rejected steps, the same final time, the
+proposed next step and the last error norm to 1e-9 relative, and the final state within
+1e-10 of the oracle's relative to the change of the state.  The error norm and the stage
+sums are formed in another order on the device, so the step sizes agree to rounding,
+not bit for bit; the shortened last step t_end - t magnifies that rounding by t_end / h.
+FP32 form: the right-hand sides in FP32 move the error estimate by about their own
+rounding, so the step counts may differ by one; stated bound: final state change
+within 1e-4 of the oracle's.
+
+Problem: Euler Taylor--Green vortex at Mach 0.3 on 4^3 hexahedra, p = 3, to t = 0.2
+from dt0 = 0.02 (atol = rtol = 1e-6: the first step is rejected) and from dt0 = 0.1
+(atol = rtol = 1e-7: three rejections); a mixed hexahedral + tetrahedral context.
+"""
+import numpy as np
+import pytest
+
+from oracle import fr as ofr
+from oracle import rk_adaptive as ra
+from paper_2408_16509_amd import inputs
+
+from helpers import oracle_blocks
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+MACH = 0.3
+
+
+def _mixed():
+    return inputs.concat([
+        inputs.hex_box((2, 2, 2), perturb=0.1, perturb_seed=5),
+        inputs.kuhn_split(inputs.hex_box((2, 2, 2), lo=(-3.0, -3.1, -3.2),
+                                         hi=(-3.0 + 2 * np.pi, -3.1 + 2 * np.pi, -3.2 + 2 * np.pi))),
+    ], permute_seed=7)
+
+
+def _case(mesh, order):
+    bl = oracle_blocks(mesh, order)
+    u0 = [np.moveaxis(inputs.tgv(b.xsol[..., 0], b.xsol[..., 1], b.xsol[..., 2], mach=MACH), 0, 1).copy()
+          for b in bl]
+    return bl, u0
+
+
+def _run(mesh, order, u0, t_end, dt0, tol, **kw):
+    from paper_2408_16509_amd import frmi
+    ctx = frmi.Context(mesh, system=0, order=order, riemann=0, **kw)
+    ug = ctx.pack64(np.concatenate([u.ravel() for u in u0]))
+    st = ctx.rk_adaptive(ug, t_end, dt0, atol=tol, rtol=tol)
+    got = ctx.unpack64(ug).cpu().numpy()
+    ctx.close()
+    return got, st
+
+
+@pytest.mark.parametrize("mname,order,t_end,dt0,tol", [
+    ("hex444", 3, 0.2, 0.02, 1e-6),
+    ("hex444", 3, 0.2, 0.1, 1e-7),
+    ("mixed", 4, 0.1, 0.02, 1e-6),
+])
+def test_adaptive_fp64_matches_oracle(mname, order, t_end, dt0, tol):
+    mesh = inputs.hex_box((4, 4, 4)) if mname == "hex444" else _mixed()
+    bl, u0 = _case(mesh, order)
+    prm = ofr.Params(system=0, riemann=0)
+    uo, so = ra.integrate(lambda s: ofr.rhs(bl, s, prm), u0, t_end, dt0, ra.Controller(atol=tol, rtol=tol))
+    got, sg = _run(mesh, order, u0, t_end, dt0, tol)
+    ref = np.concatenate([u.ravel() for u in uo])
+    start = np.concatenate([u.ravel() for u in u0])
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref - start)
+    print(f"{mname} p={order}: accepted {sg.accepted} (oracle {so.accepted}), rejected {sg.rejected} "
+          f"(oracle {so.rejected}), dt_next rel diff {abs(sg.dt_next / so.dt_next - 1):.1e}, last norm rel diff "
+          f"{abs(sg.last_norm / so.steps[-1][1] - 1):.1e}, state {err:.2e}", flush=True)
+    assert so.rejected >= 1
+    assert (sg.accepted, sg.rejected, sg.n_rhs) == (so.accepted, so.rejected, so.n_rhs)
+    assert sg.t == so.t == t_end
+    assert abs(sg.dt_next - so.dt_next) <= 1e-9 * so.dt_next
+    assert abs(sg.last_norm - so.steps[-1][1]) <= 1e-9 * so.steps[-1][1]
+    assert err <= 1e-10
+
+
+def test_adaptive_fp32_form_within_bound():
+    from paper_2408_16509_amd import frmi
+    mesh = inputs.hex_box((4, 4, 4))
+    bl, u0 = _case(mesh, 3)
+    prm = ofr.Params(system=0, riemann=0)
+    uo, so = ra.integrate(lambda s: ofr.rhs(bl, s, prm), u0, 0.2, 0.02, ra.Controller(atol=1e-6, rtol=1e-6))
+    p0 = 1.0 / (1.4 * MACH ** 2)
+    got, sg = _run(mesh, 3, u0, 0.2, 0.02, 1e-6, precision=frmi.FR_FP32, u_ref=(1.0, 0.0, 0.0, 0.0, p0 / 0.4))
+    err = np.linalg.norm(got - uo[0].ravel()) / np.linalg.norm(uo[0].ravel() - u0[0].ravel())
+    print(f"FP32 form: accepted {sg.accepted} (oracle {so.accepted}), rejected {sg.rejected}, state {err:.2e}",
+          flush=True)
+    assert sg.t == 0.2 and abs(sg.accepted - so.accepted) <= 1
+    assert err <= 1e-4
+
+
+def test_adaptive_stops_after_max_attempts():
+    mesh = inputs.hex_box((4, 4, 4))
+    bl, u0 = _case(mesh, 3)
+    prm = ofr.Params(system=0, riemann=0)
+    uo, so = ra.integrate(lambda s: ofr.rhs(bl, s, prm), u0, 0.2, 0.02, ra.Controller(), max_steps=3)
+    from paper_2408_16509_amd import frmi
+    ctx = frmi.Context(mesh, system=0, order=3, riemann=0)
+    ug = ctx.pack64(u0[0].ravel())
+    sg = ctx.rk_adaptive(ug, 0.2, 0.02, max_attempts=3)
+    got = ctx.unpack64(ug).cpu().numpy()
+    assert (sg.accepted + sg.rejected, sg.accepted) == (3, so.accepted) and sg.t < 0.2
+    assert abs(sg.t - so.t) <= 1e-9 * so.t
+    assert np.linalg.norm(got - uo[0].ravel()) <= 1e-10 * np.linalg.norm(uo[0].ravel() - u0[0].ravel())
+    with pytest.raises(frmi.FrError):
+        ctx.rk_adaptive(ug, -1.0, 0.02)
+    with pytest.raises(frmi.FrError):
+        ctx.rk_adaptive(ug, 0.2, 0.02, fac_max=0.5)

@@ -43,6 +43,10 @@ CONFIGS = {
     # Mach-3 shock (orientation seed 41, density noise seed 42), Euler + HLLC, entropy
     # filter on every RK stage: plain bisection vs the learned warm start, the MLP
     # trained on the plain filter's data from held-out draws (seeds 101-108 / 201-208)
+    # the NS TGV 32^3 p = 3 workload advanced to t = 8e-3 (20 steps of the RK4 dt) with the
+    # adaptive embedded pair (atol = rtol = 1e-6, first step 4e-4), against fixed-dt RK4
+    "ns_tgv_hex32_p3_adaptive": dict(n=(32, 32, 32), order=3, system=1, riemann=0, mach=0.1, dt=4e-4,
+                                     adaptive=True, t_end=8e-3, tol=1e-6),
     "euler_shock_hex48_p3": dict(n=(48, 48, 48), order=3, system=0, riemann=1, dt=5e-4, filter=True,
                                  orient_seed=41, noise_seed=42, train_seeds=tuple(range(101, 109)),
                                  train_steps=50, val_seed=109, train_iters=4000),
@@ -213,6 +217,81 @@ def run_form(form, cfg, mesh, ic, args, torch, np, frmi, inputs):
         res["times"] = ctx.profile_read()
         ctx.profile(False)
     return res
+
+
+def run_adaptive_workload(cfg, args, torch, np, frmi, inputs):
+    """Adaptive embedded-pair integration to t_end (per form): time to solution, RHS
+    throughput, accepted / rejected steps; the same interval with fixed-dt RK4 beside it."""
+    mesh = build_mesh(cfg, inputs)
+    out_forms, dominant = {}, None
+    dof = None
+    for form in ("fp32", "fp64"):
+        kw = dict(system=cfg["system"], order=cfg["order"], riemann=cfg["riemann"])
+        if form == "fp32":
+            p0 = 1.0 / (1.4 * cfg["mach"] ** 2)
+            kw.update(precision=frmi.FR_FP32, u_ref=(1.0, 0.0, 0.0, 0.0, p0 / 0.4))
+        ctx = frmi.Context(mesh, **kw)
+        lay = ctx.layout
+        E, nsp = lay.n_elem[0], lay.n_sp[0]
+        dof = E * nsp
+        x = ctx.sol_points().reshape(E, nsp, 3)
+        u0 = ctx.pack64(np.moveaxis(inputs.tgv(x[..., 0], x[..., 1], x[..., 2], mach=cfg["mach"]), 0, 1).ravel())
+        u = u0.clone()
+        ctx.rk_adaptive(u, cfg["t_end"] / 4, cfg["dt"], atol=cfg["tol"], rtol=cfg["tol"])      # warm-up
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream()
+        u = u0.clone()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        st = ctx.rk_adaptive(u, cfg["t_end"], cfg["dt"], atol=cfg["tol"], rtol=cfg["tol"])
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms_a = ev0.elapsed_time(ev1)
+        uf = u.clone()
+        n_fixed = int(round(cfg["t_end"] / cfg["dt"]))
+        u = u0.clone()
+        ev0.record(stream)
+        ctx.rk_step(u, cfg["dt"], n_fixed)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms_f = ev0.elapsed_time(ev1)
+        diff = float(torch.linalg.norm(uf - u) / torch.linalg.norm(u - u0))
+        out_forms[form] = {
+            "gdof_s": round(dof * st.n_rhs / (ms_a * 1e-3) / 1e9, 4), "time_to_t_end_ms": round(ms_a, 3),
+            "accepted": int(st.accepted), "rejected": int(st.rejected), "n_rhs": int(st.n_rhs),
+            "mean_dt": cfg["t_end"] / max(int(st.accepted), 1), "dt_next": st.dt_next,
+            "fixed_rk4": {"dt": cfg["dt"], "steps": n_fixed, "time_to_t_end_ms": round(ms_f, 3),
+                          "gdof_s": round(dof * 4 * n_fixed / (ms_f * 1e-3) / 1e9, 4)},
+            "state_change_rel_diff_adaptive_vs_rk4": diff,
+        }
+        if form == "fp32" and not args.no_kernel_timing:
+            ctx.profile(True)
+            u = u0.clone()
+            ctx.rk_adaptive(u, 2 * cfg["dt"], cfg["dt"], atol=cfg["tol"], rtol=cfg["tol"])
+            times = ctx.profile_read()
+            ctx.profile(False)
+            fam = {k: v for k, v in times.items() if kernel_bytes_per_elem(k, nsp, 96) is not None}
+            dom = max(fam, key=lambda k: fam[k][1])
+            launches, tot = fam[dom]
+            avg = tot / launches
+            by = kernel_bytes_per_elem(dom, nsp, 96) * E
+            dominant = {"bound": "hbm", "achieved": round(by / (avg * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(by / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                        "traffic": load_traffic(dom, "ns_tgv_hex32_p3"), "kernel": dom,
+                        "avg_launch_ms": round(avg, 4), "bytes_per_launch": int(by)}
+        ctx.close()
+    head = out_forms["fp32"]
+    return {
+        "metric": "RHS GDoF/s (FP32/learned vs FP64 plain) at stated L2 error; % HBM roofline",
+        "value": head["gdof_s"], "unit": "GDoF/s", "n_gpus": 1, "steps": head["accepted"], "warmup": 1,
+        "ms_per_step": round(head["time_to_t_end_ms"] / max(head["accepted"], 1), 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": args.config, "elements": int(dof // 64), "order": cfg["order"], "dof": int(dof),
+                   "integrator": "RK3(2)4[2R+] embedded pair, adaptive", "t_end": cfg["t_end"],
+                   "atol": cfg["tol"], "rtol": cfg["tol"], "dt0": cfg["dt"], "form": "fp32"},
+        "roofline": dominant,
+        "forms": out_forms,
+    }
 
 
 def run_filter_workload(cfg, args, torch, np, frmi, inputs):
@@ -412,6 +491,9 @@ def main():
     torch.cuda.set_device(0)
     if cfg.get("filter"):
         print(json.dumps(run_filter_workload(cfg, args, torch, np, frmi, inputs)), flush=True)
+        return
+    if cfg.get("adaptive"):
+        print(json.dumps(run_adaptive_workload(cfg, args, torch, np, frmi, inputs)), flush=True)
         return
     mesh = build_mesh(cfg, inputs)
 

@@ -18,6 +18,7 @@ Modules
     elements   dense element operator sets for hexahedra and tetrahedra
     mesh       periodic face matching, flux-point pairing, left/right sides
     geometry   Jacobians and transformed metric at arbitrary reference points
+    curved     order-q hexahedral maps; conservative (curl-form) and cross-product metrics
     physics    Euler flux, Rusanov and HLLC solvers, Navier--Stokes viscous flux
     fr         the FR right-hand side (Euler and Navier--Stokes, LDG)
     rk         classical RK4

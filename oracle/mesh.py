@@ -19,7 +19,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from . import geometry
+from . import curved, geometry
 from .elements import HEX, TET, ops_for
 
 HEX_FACE_CORNERS = [(0, 3, 4, 7), (1, 2, 5, 6), (0, 1, 4, 5), (2, 3, 6, 7), (0, 1, 2, 3), (4, 5, 6, 7)]
@@ -72,22 +72,37 @@ def _keys(c, period, scale):
     return k
 
 
-def build(mesh, order: int):
-    """Connectivity and geometry of `mesh` at polynomial order `order` (tets: 4)."""
+def build(mesh, order: int, metric: str = "conservative"):
+    """Connectivity and geometry of `mesh` at polynomial order `order` (tets: 4).
+
+    Curved meshes (mesh.ho_enodes set, hexahedra of geometry order mesh.geo_order):
+    metric terms, J and solution points come from the high-order map (curved.py,
+    `metric` "conservative" or "cross"); faces are matched, flux points paired and
+    left/right sides chosen from the 8 corners as for straight elements."""
     period = np.asarray(mesh.period, dtype=np.float64)
     types = [t for t in (HEX, TET) if np.any(mesh.etype == t)]
+    ho = getattr(mesh, "ho_enodes", None)
+    if ho is not None and TET in types:
+        raise MeshError("curved meshes hold hexahedra only")
     blocks = []
     for t in types:
         elems = np.nonzero(mesh.etype == t)[0]
         ops = ops_for(t, order if t == HEX else 4)
         nc = 8 if t == HEX else 4
         X = mesh.xyz[mesh.enodes[elems, :nc]]
-        J, S = geometry.metric(t, X, ops.sol_pts)
-        Jf, Sf = geometry.metric(t, X, ops.flux_pts)
+        if ho is None:
+            J, S = geometry.metric(t, X, ops.sol_pts)
+            Jf, Sf = geometry.metric(t, X, ops.flux_pts)
+            xsol = geometry.map_points(t, X, ops.sol_pts)
+        else:
+            q = int(mesh.geo_order)
+            Xh = mesh.xyz[ho[elems]]
+            J, S = curved.metric(metric, q, order, Xh, ops.sol_pts)
+            Jf, Sf = curved.metric(metric, q, order, Xh, ops.flux_pts)
+            xsol = curved.map_points(q, Xh, ops.sol_pts)
         if np.any(J <= 0) or np.any(Jf <= 0):
             raise MeshError("element with J <= 0")
         snorm = np.einsum("epij,pi->epj", Sf, ops.normals)
-        xsol = geometry.map_points(t, X, ops.sol_pts)
         n, nfp = len(elems), ops.nfp
         blocks.append(TypeBlock(t, elems, ops, X, J, S, Jf, Sf, snorm,
                                 np.full((n, nfp), -1), np.full((n, nfp), -1),

@@ -11,6 +11,9 @@ Meshes
       seeded permutation of the element order.
     * ``kuhn_split``: each hexahedral cell cut into 6 tetrahedra sharing the cell's
       main diagonal, which stays conforming between neighbouring cells.
+    * ``curved_hex_box``: the structured periodic grid with every element curved:
+      a lattice of (n q + 1)^3 nodes per box moved by a smooth periodic displacement,
+      each element described by its (q+1)^3 nodes (geometry order q).
 
 Node orders
     Hexahedra use the VTK corner order, reference corners
@@ -18,6 +21,8 @@ Node orders
     Tetrahedra list their 4 corners in the order of the reference tetrahedron
     printed with the paper's tetrahedral point sets (Fig. mesh b,c):
     (-1,-1,-1) (1,-1,-1) (-1,-1,1) (-1,1,-1).
+    Curved hexahedra of geometry order q list (q+1)^3 nodes in tensor order: node
+    i + (q+1)(j + (q+1)k) sits at reference point (-1 + 2i/q, -1 + 2j/q, -1 + 2k/q).
 
 Initial conditions (evaluated at caller-given physical points)
     * Taylor--Green vortex (Sec. "Accuracy", TGV initial-condition equations),
@@ -53,6 +58,8 @@ class Mesh:
     enodes: np.ndarray         # [n_elem][8] int64, tets use the first 4
     period: np.ndarray         # [3] float64 box lengths (0 = not periodic)
     meta: dict = field(default_factory=dict)
+    geo_order: int = 1         # curved hexahedra: geometry order q of ho_enodes
+    ho_enodes: np.ndarray = None   # [n_elem][(q+1)^3] int64 tensor-order nodes (curved meshes)
 
     @property
     def n_elem(self) -> int:
@@ -117,6 +124,62 @@ def hex_box(n=(4, 4, 4), lo=(-math.pi,) * 3, hi=(math.pi,) * 3, perturb=0.0,
     etype = np.full(en.shape[0], HEX, dtype=np.int32)
     period = np.asarray(hi, dtype=np.float64) - np.asarray(lo, dtype=np.float64)
     return Mesh(xyz, etype, en, period, {"n": n, "h": h, "kind": "hex_box"})
+
+
+def curved_hex_box(n=(4, 4, 4), q=2, amp=0.15, lo=(-math.pi,) * 3, hi=(math.pi,) * 3,
+                   perturb=0.0, perturb_seed=None, permute_seed=None) -> Mesh:
+    """Periodic box of nx*ny*nz hexahedra of geometry order q, all curved.
+
+    A lattice of (n_a q + 1) nodes per direction, evenly spaced, is moved by the
+    periodic displacement (s_a = 2 pi (x_a - lo_a) / L_a, L the box lengths)
+        dx = amp L_x / (2 pi) sin(s_y) sin(s_z),  dy = amp L_y / (2 pi) sin(s_x) sin(s_z),
+        dz = amp L_z / (2 pi) sin(s_x) sin(s_y),
+    whose gradient entries stay within amp (for equal box lengths), so the map
+    stays invertible for amp well below 1.  Element (i, j, k) takes lattice nodes
+    (i q + a, j q + b, k q + c), a, b, c = 0..q, in tensor order (ho_enodes); its
+    8 corners, in VTK order, are the lattice nodes with a, b, c in {0, q}
+    (enodes).  Nodes on the upper box faces are separate vertices from their
+    periodic images on the lower faces and carry the same displacement.
+    perturb: each node of the periodic lattice (n_a q nodes per direction) then moves
+    by U(-perturb, perturb) times the node spacing per coordinate, drawn with numpy
+    PCG64(perturb_seed) in C order of that lattice [k][j][i][3]; images move alike.
+    permute_seed: if given, element order is PCG64(permute_seed).permutation.
+    """
+    n = tuple(int(v) for v in n)
+    q = int(q)
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+    L = hi - lo
+    m = [v * q + 1 for v in n]
+    K, J, I = np.meshgrid(np.arange(m[2]), np.arange(m[1]), np.arange(m[0]), indexing="ij")
+    x = lo[0] + I * (L[0] / (n[0] * q))
+    y = lo[1] + J * (L[1] / (n[1] * q))
+    z = lo[2] + K * (L[2] / (n[2] * q))
+    sx, sy, sz = (2 * np.pi * (x - lo[0]) / L[0], 2 * np.pi * (y - lo[1]) / L[1], 2 * np.pi * (z - lo[2]) / L[2])
+    xyz = np.stack([x + amp * L[0] / (2 * np.pi) * np.sin(sy) * np.sin(sz),
+                    y + amp * L[1] / (2 * np.pi) * np.sin(sx) * np.sin(sz),
+                    z + amp * L[2] / (2 * np.pi) * np.sin(sx) * np.sin(sy)], axis=-1)
+    if perturb:
+        hn = L / (np.asarray(n, dtype=np.float64) * q)
+        jit = np.random.default_rng(perturb_seed).uniform(-perturb, perturb, size=(m[2] - 1, m[1] - 1, m[0] - 1, 3))
+        xyz = xyz + jit[K % (m[2] - 1), J % (m[1] - 1), I % (m[0] - 1)] * hn
+    xyz = xyz.reshape(-1, 3)
+
+    def vid(i, j, k):
+        return (k * m[1] + j) * m[0] + i
+
+    kk, jj, ii = np.meshgrid(np.arange(n[2]), np.arange(n[1]), np.arange(n[0]), indexing="ij")
+    ii, jj, kk = ii.ravel() * q, jj.ravel() * q, kk.ravel() * q
+    ho = np.stack([vid(ii + a, jj + b, kk + c)
+                   for c in range(q + 1) for b in range(q + 1) for a in range(q + 1)], axis=1).astype(np.int64)
+    corners = [(0, 0, 0), (1, 0, 0), (1, 1, 0), (0, 1, 0), (0, 0, 1), (1, 0, 1), (1, 1, 1), (0, 1, 1)]
+    en = np.stack([ho[:, a * q + (q + 1) * (b * q + (q + 1) * c * q)] for a, b, c in corners], axis=1)
+    if permute_seed is not None:
+        perm = np.random.default_rng(permute_seed).permutation(en.shape[0])
+        en, ho = en[perm], ho[perm]
+    etype = np.full(en.shape[0], HEX, dtype=np.int32)
+    return Mesh(xyz, etype, en, L.copy(), {"n": n, "kind": "curved_hex_box", "q": q, "amp": amp},
+                geo_order=q, ho_enodes=ho)
 
 
 def _tet_signed_volume(c):

@@ -45,6 +45,10 @@ CONFIGS = {
     # trained on the plain filter's data from held-out draws (seeds 101-108 / 201-208)
     # the NS TGV 32^3 p = 3 workload advanced to t = 8e-3 (20 steps of the RK4 dt) with the
     # adaptive embedded pair (atol = rtol = 1e-6, first step 4e-4), against fixed-dt RK4
+    # the NS TGV 32^3 p = 3 workload on cubically curved hexahedra (smooth periodic
+    # displacement of amplitude 0.1): metric terms stored per point, conservative form
+    "ns_tgv_hex32_p3_curved": dict(kind="curved", n=(32, 32, 32), q=3, amp=0.1, order=3, system=1, riemann=0,
+                                   mach=0.1, dt=4e-4, oracle_ok=True),
     "ns_tgv_hex32_p3_adaptive": dict(n=(32, 32, 32), order=3, system=1, riemann=0, mach=0.1, dt=4e-4,
                                      adaptive=True, t_end=8e-3, tol=1e-6),
     "euler_shock_hex48_p3": dict(n=(48, 48, 48), order=3, system=0, riemann=1, dt=5e-4, filter=True,
@@ -64,6 +68,8 @@ def build_mesh(cfg, inputs):
         b = inputs.kuhn_split(inputs.hex_box(n, lo=lo_b, hi=hi_b, perturb=cfg["perturb"],
                                              perturb_seed=cfg["perturb_seed"]))
         return inputs.concat([a, b], permute_seed=cfg["permute_seed"])
+    if cfg.get("kind") == "curved":
+        return inputs.curved_hex_box(cfg["n"], q=cfg["q"], amp=cfg["amp"], permute_seed=cfg.get("permute_seed"))
     return inputs.hex_box(cfg["n"], perturb=cfg.get("perturb", 0.0), perturb_seed=cfg.get("perturb_seed"),
                           permute_seed=cfg.get("permute_seed"))
 
@@ -76,11 +82,24 @@ def kernel_bytes_per_elem(name, nsp, nfp):
     one-sided LDG switch (beta = 1/2): the gradient kernel reads the neighbour's
     solution trace only on faces where the element is the right side and stores
     gradient traces only there (half of the flux points); the face kernel reads one
-    gradient trace per flux point pair, i.e. the stored half."""
+    gradient trace per flux point pair, i.e. the stored half.  Curved hexahedra ("_cur")
+    read stored metric terms instead of the 24 corner words: S rows and 1/J at the
+    solution points (10 words each) where a kernel forms fluxes or gradients there,
+    row d of S at the flux points (3 words each) where it forms common fluxes (the
+    face kernel forms each pair's flux once, from the left side: half of them)."""
     fam = name.rsplit("_p", 1)[0] if "_p" in name else name
     d = 8
     if fam.endswith("_f32"):
         fam, d = fam[:-4], 4
+    if fam.endswith("_cur"):
+        base = fam[:-4]
+        plain = kernel_bytes_per_elem(base + ("_f32" if d == 4 else "") + "_p0", nsp, nfp)
+        if plain is None:
+            return None
+        metric = {"hex_trace": 0, "hex_div_euler": 10 * nsp + 3 * nfp, "hex_grad": 10 * nsp,
+                  "hex_face_ns": 3 * nfp // 2, "hex_div_ns": 10 * nsp}.get(base)
+        geo = 0 if base == "hex_trace" else 24 * d
+        return None if metric is None else plain - geo + d * metric
     hex_geo, hex_conn = 24 * d, 6 * 2 * 4
     tet_gc = 10 * d + 4 * 2 * 4
     table = {

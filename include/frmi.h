@@ -60,6 +60,7 @@ enum { FR_EULER = 0, FR_NAVIER_STOKES = 1 };
 enum { FR_RUSANOV = 0, FR_HLLC = 1 };
 enum { FR_FP64 = 0, FR_FP32 = 1, FR_FP32_BF16X3 = 2 };
 enum { FR_HEX = 0, FR_TET = 1 };
+enum { FR_METRIC_CONSERVATIVE = 0, FR_METRIC_CROSS = 1 };
 
 /* Solver parameters.  struct_size must be sizeof(fr_params). */
 typedef struct {
@@ -91,7 +92,8 @@ typedef struct {
   double filt_eps_s;       /* entropy filter: relative entropy tolerance (all >= 0)  */
   double filt_zeta_max_coef; /* zeta_max = coef * p^2, coef > 0 and finite          */
   int32_t filt_bits;       /* dyadic search depth n (2^n grid), 1..30                */
-  int32_t reserved1;
+  int32_t hex_metric;      /* metric terms of curved hexahedra (fr_setup_mesh_curved):
+                              FR_METRIC_CONSERVATIVE (default) or FR_METRIC_CROSS     */
 } fr_params;
 
 typedef struct {
@@ -160,6 +162,33 @@ void fr_default_params(fr_params* p);
 fr_status fr_setup_mesh(const fr_params* p, int64_t n_vert, const double* xyz,
                         const double* period, int64_t n_elem, const int32_t* etype,
                         const int64_t* enodes, void* stream, fr_ctx* out);
+
+/* Build a context for a periodic conforming mesh of curved hexahedra (Sec. "Curved
+ * elements": metric terms kept per point of curved elements).
+ *   geo_order  q in 1..min(4, order): geometry order of every element.
+ *   ho_nodes   [n_elem][(q+1)^3] indices into xyz, tensor order: node i + (q+1)(j + (q+1)k)
+ *              sits at reference point (-1 + 2i/q, -1 + 2j/q, -1 + 2k/q) of the map
+ *              x(xi) = sum_n N_n(xi) x_n (tensor Lagrange polynomials on those points).
+ *              Faces are matched from the 8 corner nodes as in fr_setup_mesh; elements
+ *              sharing a face must share its nodes (conforming curved faces).
+ *   p->hex_metric  FR_METRIC_CONSERVATIVE: S = J G^{-1} as the curl of the order-p
+ *              Gauss--Lobatto interpolant of x_l grad x_m ((n, m, l) cyclic,
+ *              S_rn = -[curl V^(n)]_r): divergence-free at the solution points, so a
+ *              uniform stream stays uniform, and equal and opposite normals on every
+ *              shared face (periodic ones too, which is why q <= order); x_l is taken
+ *              relative to the element's node 0 (no change in exact arithmetic for
+ *              q <= order, no cancellation of the coordinates' size against h^2);
+ *              FR_METRIC_CROSS: S from the exact Jacobian at every point.
+ *              J is det(dx/dxi) of the exact map in both cases.
+ * The metric terms are stored per point (9 + 1 per solution point, 3 per flux point) in
+ * the kernels' arithmetic type instead of being derived from 24 corner coefficients;
+ * every other call behaves as for fr_setup_mesh.  Synchronous.
+ * Errors: FR_ERR_ARG (NULL, index out of range), FR_ERR_UNSUPPORTED (q outside
+ * 1..min(4, order)), FR_ERR_MESH (unpaired face, J <= 0 at a solution or flux point),
+ * FR_ERR_ALLOC. */
+fr_status fr_setup_mesh_curved(const fr_params* p, int32_t geo_order, int64_t n_vert, const double* xyz,
+                               const double* period, int64_t n_elem, const int64_t* ho_nodes, void* stream,
+                               fr_ctx* out);
 
 fr_status fr_layout(fr_ctx ctx, fr_layout_t* out);
 

@@ -25,6 +25,10 @@ polynomial in Q_p: it lies in Q_p (so the solution points represent it exactly) 
 has zero divergence; on a face xi_d = +-1 row d involves only tangential derivatives
 of the interpolant's face values, and the Lobatto points include the face, so two
 elements sharing a face agree on its normal.  J is det G of the exact map.
+The factor x_l is taken relative to the element's node 0: for q <= p the
+interpolant of grad x_m is exact and has zero curl, so the shift changes nothing in
+exact arithmetic, while in floating point it keeps coordinates of size |x| out of a
+result of size h^2 (without it two FP64 evaluations differ by ~|x| / h ulps).
 
 Geometry of order q: x(xi) = sum_n N_n(xi) X_n, N the tensor Lagrange polynomials on
 equispaced nodes, node n = i + (q+1)(j + (q+1)k) at (-1 + 2i/q, -1 + 2j/q, -1 + 2k/q).
@@ -92,13 +96,13 @@ def conservative_metric(q: int, p: int, X, xi):
     y = gll_nodes(p + 1)
     i, j, k = _tensor_index(p + 1)
     Y = np.stack([y[i], y[j], y[k]], axis=1)
-    xY = map_points(q, X, Y)                          # [n][m][3]
+    xY = map_points(q, X - X[:, :1, :], Y)            # [n][m][3], relative to node 0
     GY = jacobian(q, X, Y)                            # [n][m][3][3]
     _, dL = _tensor_ops(y, xi)                        # [3][np][m]: d/dxi_a of the GLL basis
     S = np.empty(X.shape[:1] + (np.atleast_2d(xi).shape[0], 3, 3))
     for n in range(3):
         m, l = (n + 1) % 3, (n + 2) % 3
-        V = xY[..., l, None] * GY[..., m, :]          # V[e][node][a] = x_l d x_m / d xi_a
+        V = xY[..., l, None] * GY[..., m, :]          # V[e][node][a] = (x_l - x0_l) d x_m / d xi_a
         for r in range(3):
             a, b = (r + 1) % 3, (r + 2) % 3
             # [curl V]_r = d_a V_b - d_b V_a

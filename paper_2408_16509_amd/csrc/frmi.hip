@@ -52,6 +52,7 @@ struct DevBlock {
   void* grad = nullptr;     // [nsp][15][E]
   void* gradf = nullptr;    // [nfp][15][E]
   void* fc = nullptr;       // [nfp][5][E] common fluxes (Navier--Stokes)
+  void* cmet = nullptr;     // curved hexahedra: stored metric terms in the kernels' type (else NULL)
   int64_t elem_off = 0;     // offset of the block in the element numbering (both orders)
   int32_t* cpos = nullptr;  // native index -> canonical index within the block [E] (-1: padding)
   int32_t* npos = nullptr;  // canonical index -> native index within the block [n]
@@ -408,7 +409,7 @@ RefState<T> ref_of(const fr_params& p) {
 
 int side_mode_of(double beta) { return beta == 0.5 ? 1 : (beta == -0.5 ? -1 : 0); }
 
-template <typename T, bool DEV, int P>
+template <typename T, bool DEV, int P, bool CUR>
 fr_status hex_rhs_p(fr_ctx c, DevBlock& b, const T* u, T* r) {
   constexpr int N1 = P + 1, NE = HexCfg<P>::NE, NT = NE * N1 * N1;
   Conn C{b.nbr_elem, b.nbr_info, c->perm, c->host.perm_stride};
@@ -416,46 +417,49 @@ fr_status hex_rhs_p(fr_ctx c, DevBlock& b, const T* u, T* r) {
   const HexK<T> K = hexk_of<T>(c->host.hex);
   const RefState<T> R = ref_of<T>(p);
   const T* geo = (const T*)b.geo_t;
+  const T* cm = (const T*)b.cmet;
   T* uf = (T*)b.uf;
   T* grad = (T*)b.grad;
   T* gradf = (T*)b.gradf;
   const int sm = side_mode_of(p.ldg_beta);
   const int64_t trace_threads = b.E * 3 * N1 * N1;
-  static const std::string sfx = std::string(sizeof(T) == 8 ? "" : "_f32") + "_p" + std::to_string(P);
+  static const std::string sfx =
+      std::string(CUR ? "_cur" : "") + (sizeof(T) == 8 ? "" : "_f32") + "_p" + std::to_string(P);
   int pk = c->prof_begin(("hex_trace" + sfx).c_str());
   hex_trace<T, P><<<(unsigned)((trace_threads + 255) / 256), 256, 0, c->stream>>>(u, uf, b.E, K);
   c->prof_end(pk);
   const unsigned nblk = (unsigned)(b.E / NE);
   if (p.system == FR_EULER) {
     pk = c->prof_begin(("hex_div_euler" + sfx).c_str());
-    hex_div_euler<T, DEV, P, NE><<<nblk, NT, 0, c->stream>>>(u, uf, geo, C, r, b.E, b.n, K, (T)p.gamma, p.riemann, R);
+    hex_div_euler<T, DEV, P, NE, CUR><<<nblk, NT, 0, c->stream>>>(u, uf, geo, cm, C, r, b.E, b.n, K, (T)p.gamma,
+                                                                   p.riemann, R);
     c->prof_end(pk);
   } else {
     pk = c->prof_begin(("hex_grad" + sfx).c_str());
     if constexpr (P <= 3)
-      hex_grad<T, P, NE><<<nblk, NT, 0, c->stream>>>(u, uf, geo, C, grad, gradf, b.E, K, (T)p.ldg_beta, sm);
+      hex_grad<T, P, NE, CUR><<<nblk, NT, 0, c->stream>>>(u, uf, geo, cm, C, grad, gradf, b.E, K, (T)p.ldg_beta, sm);
     else {
       // 16 FP32 elements per tile (64-byte rows); FP64 keeps 8 (64-byte rows as well)
       constexpr int NEg = sizeof(T) == 4 ? 16 : NE;
-      hex_grad_lines<T, P, NEg><<<(unsigned)(b.E / NEg), NEg * N1 * N1, 0, c->stream>>>(
-          u, uf, geo, C, grad, gradf, b.E, K, (T)p.ldg_beta, sm);
+      hex_grad_lines<T, P, NEg, CUR><<<(unsigned)(b.E / NEg), NEg * N1 * N1, 0, c->stream>>>(
+          u, uf, geo, cm, C, grad, gradf, b.E, K, (T)p.ldg_beta, sm);
     }
     c->prof_end(pk);
     T* fc = (T*)b.fc;
     const int64_t face_threads = b.E * 6 * N1 * N1;
     pk = c->prof_begin(("hex_face_ns" + sfx).c_str());
-    hex_face_ns<T, DEV, P><<<(unsigned)((face_threads + 255) / 256), 256, 0, c->stream>>>(
-        uf, gradf, geo, C, fc, b.E, b.n, K, (T)p.gamma, (T)p.mu, (T)p.prandtl, (T)p.ldg_beta, (T)p.ldg_tau,
+    hex_face_ns<T, DEV, P, CUR><<<(unsigned)((face_threads + 255) / 256), 256, 0, c->stream>>>(
+        uf, gradf, geo, cm, C, fc, b.E, b.n, K, (T)p.gamma, (T)p.mu, (T)p.prandtl, (T)p.ldg_beta, (T)p.ldg_tau,
         p.riemann, sm, R);
     c->prof_end(pk);
     constexpr int NE2 = DivNsCfg<T, P>::NE;
     pk = c->prof_begin(("hex_div_ns" + sfx).c_str());
     if constexpr (sizeof(T) == 4 && P <= 3)
-      hex_div_ns<T, DEV, P, NE2><<<(unsigned)(b.E / NE2), NE2 * N1 * N1, 0, c->stream>>>(
-          u, grad, fc, geo, r, b.E, b.n, K, (T)p.gamma, (T)p.mu, (T)p.prandtl, R);
+      hex_div_ns<T, DEV, P, NE2, CUR><<<(unsigned)(b.E / NE2), NE2 * N1 * N1, 0, c->stream>>>(
+          u, grad, fc, geo, cm, r, b.E, b.n, K, (T)p.gamma, (T)p.mu, (T)p.prandtl, R);
     else
-      hex_div_ns_lds<T, DEV, P, NE2><<<(unsigned)(b.E / NE2), NE2 * N1 * N1, 0, c->stream>>>(
-          u, grad, fc, geo, r, b.E, b.n, K, (T)p.gamma, (T)p.mu, (T)p.prandtl, R);
+      hex_div_ns_lds<T, DEV, P, NE2, CUR><<<(unsigned)(b.E / NE2), NE2 * N1 * N1, 0, c->stream>>>(
+          u, grad, fc, geo, cm, r, b.E, b.n, K, (T)p.gamma, (T)p.mu, (T)p.prandtl, R);
     c->prof_end(pk);
   }
   hipError_t e = hipGetLastError();
@@ -542,10 +546,10 @@ fr_status rhs_t(fr_ctx c, const T* u, T* r) {
     fr_status s = FR_OK;
     if (b.etype == FR_HEX) {
       switch (c->prm.order) {
-        case 1: s = hex_rhs_p<T, DEV, 1>(c, b, ub, rb); break;
-        case 2: s = hex_rhs_p<T, DEV, 2>(c, b, ub, rb); break;
-        case 3: s = hex_rhs_p<T, DEV, 3>(c, b, ub, rb); break;
-        case 4: s = hex_rhs_p<T, DEV, 4>(c, b, ub, rb); break;
+        case 1: s = b.cmet ? hex_rhs_p<T, DEV, 1, true>(c, b, ub, rb) : hex_rhs_p<T, DEV, 1, false>(c, b, ub, rb); break;
+        case 2: s = b.cmet ? hex_rhs_p<T, DEV, 2, true>(c, b, ub, rb) : hex_rhs_p<T, DEV, 2, false>(c, b, ub, rb); break;
+        case 3: s = b.cmet ? hex_rhs_p<T, DEV, 3, true>(c, b, ub, rb) : hex_rhs_p<T, DEV, 3, false>(c, b, ub, rb); break;
+        case 4: s = b.cmet ? hex_rhs_p<T, DEV, 4, true>(c, b, ub, rb) : hex_rhs_p<T, DEV, 4, false>(c, b, ub, rb); break;
         default: s = fail(c, FR_ERR_UNSUPPORTED, "order");
       }
     } else {
@@ -920,6 +924,7 @@ void fr_destroy(fr_ctx c) {
     if (b.geo_t && b.geo_t != b.geo) (void)hipFree(b.geo_t);
     (void)hipFree(b.geo); (void)hipFree(b.nbr_elem); (void)hipFree(b.nbr_info);
     (void)hipFree(b.uf); (void)hipFree(b.grad); (void)hipFree(b.gradf); (void)hipFree(b.fc);
+    (void)hipFree(b.cmet);
     (void)hipFree(b.cpos); (void)hipFree(b.npos);
   }
   (void)hipFree(c->perm);
@@ -941,9 +946,10 @@ void fr_destroy(fr_ctx c) {
   delete c;
 }
 
-fr_status fr_setup_mesh(const fr_params* p, int64_t n_vert, const double* xyz, const double* period,
-                        int64_t n_elem, const int32_t* etype, const int64_t* enodes, void* stream,
-                        fr_ctx* out) {
+namespace {
+fr_status setup_impl(const fr_params* p, int64_t n_vert, const double* xyz, const double* period,
+                     int64_t n_elem, const int32_t* etype, const int64_t* enodes, int geo_order,
+                     const int64_t* ho_nodes, void* stream, fr_ctx* out) {
   if (!out) return fail(nullptr, FR_ERR_ARG, "out is NULL");
   *out = nullptr;
   if (!p || p->struct_size != sizeof(fr_params)) return fail(nullptr, FR_ERR_ARG, "fr_params missing or struct_size mismatch");
@@ -962,6 +968,8 @@ fr_status fr_setup_mesh(const fr_params* p, int64_t n_vert, const double* xyz, c
   if (!(p->filt_eps_rho >= 0) || !(p->filt_eps_p >= 0) || !(p->filt_eps_s >= 0))
     return fail(nullptr, FR_ERR_ARG, "filter floors and entropy tolerance must be >= 0");
   if (p->elem_order < 0 || p->elem_order > 2) return fail(nullptr, FR_ERR_ARG, "elem_order must be 0, 1 or 2");
+  if (p->hex_metric != FR_METRIC_CONSERVATIVE && p->hex_metric != FR_METRIC_CROSS)
+    return fail(nullptr, FR_ERR_ARG, "hex_metric must be FR_METRIC_CONSERVATIVE or FR_METRIC_CROSS");
   fr_ctx c = new (std::nothrow) fr_ctx_s();
   if (!c) return fail(nullptr, FR_ERR_ALLOC, "context allocation");
   c->prm = *p;
@@ -970,6 +978,7 @@ fr_status fr_setup_mesh(const fr_params* p, int64_t n_vert, const double* xyz, c
   std::string msg;
   try {
     msg = build_setup(p->order, n_vert, xyz, period, n_elem, etype, enodes, 64, p->elem_order, c->host, code);
+    if (msg.empty() && ho_nodes) msg = build_curved_hex(geo_order, p->hex_metric, xyz, ho_nodes, c->host, code);
   } catch (const std::exception& ex) {
     msg = ex.what();
     code = 3;
@@ -1019,6 +1028,22 @@ fr_status fr_setup_mesh(const fr_params* p, int64_t n_vert, const double* xyz, c
       if (hipMemcpy(d.geo_t, g32.data(), g32.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
         c->err = "upload failed";
         return bail(FR_ERR_DEVICE);
+      }
+    }
+    if (!hb.cmet.empty()) {
+      if (tsz == sizeof(float)) {
+        std::vector<float> m32(hb.cmet.begin(), hb.cmet.end());
+        if (dalloc(c, (float**)&d.cmet, m32.size())) return bail(FR_ERR_ALLOC);
+        if (hipMemcpy(d.cmet, m32.data(), m32.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
+          c->err = "upload failed";
+          return bail(FR_ERR_DEVICE);
+        }
+      } else {
+        if (dalloc(c, (double**)&d.cmet, hb.cmet.size())) return bail(FR_ERR_ALLOC);
+        if (hipMemcpy(d.cmet, hb.cmet.data(), hb.cmet.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+          c->err = "upload failed";
+          return bail(FR_ERR_DEVICE);
+        }
       }
     }
     if (hipMemcpy(d.geo, hb.geo.data(), hb.geo.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
@@ -1119,6 +1144,38 @@ fr_status fr_setup_mesh(const fr_params* p, int64_t n_vert, const double* xyz, c
   }
   *out = c;
   return FR_OK;
+}
+}  // namespace
+
+fr_status fr_setup_mesh(const fr_params* p, int64_t n_vert, const double* xyz, const double* period,
+                        int64_t n_elem, const int32_t* etype, const int64_t* enodes, void* stream,
+                        fr_ctx* out) {
+  return setup_impl(p, n_vert, xyz, period, n_elem, etype, enodes, 0, nullptr, stream, out);
+}
+
+fr_status fr_setup_mesh_curved(const fr_params* p, int32_t geo_order, int64_t n_vert, const double* xyz,
+                               const double* period, int64_t n_elem, const int64_t* ho_nodes, void* stream,
+                               fr_ctx* out) {
+  if (!out) return fail(nullptr, FR_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!p || p->struct_size != sizeof(fr_params)) return fail(nullptr, FR_ERR_ARG, "fr_params missing or struct_size mismatch");
+  if (!xyz || !period || !ho_nodes || n_vert <= 0 || n_elem <= 0) return fail(nullptr, FR_ERR_ARG, "empty mesh or NULL array");
+  if (geo_order < 1 || geo_order > 4) return fail(nullptr, FR_ERR_UNSUPPORTED, "geometry order must be in 1..4");
+  if (geo_order > p->order)
+    return fail(nullptr, FR_ERR_UNSUPPORTED, "geometry order above the solution order (periodic faces would not be watertight)");
+  const int nq = geo_order + 1, NQ = nq * nq * nq;
+  for (int64_t i = 0; i < n_elem * NQ; ++i)
+    if (ho_nodes[i] < 0 || ho_nodes[i] >= n_vert) return fail(nullptr, FR_ERR_ARG, "node index out of range");
+  // the 8 corners in VTK order: tensor nodes with each index 0 or q
+  static const int kc[8][3] = {{0, 0, 0}, {1, 0, 0}, {1, 1, 0}, {0, 1, 0}, {0, 0, 1}, {1, 0, 1}, {1, 1, 1}, {0, 1, 1}};
+  std::vector<int64_t> corners((size_t)n_elem * 8);
+  for (int64_t e = 0; e < n_elem; ++e)
+    for (int c = 0; c < 8; ++c) {
+      const int i = kc[c][0] * geo_order, j = kc[c][1] * geo_order, k = kc[c][2] * geo_order;
+      corners[(size_t)e * 8 + c] = ho_nodes[e * NQ + i + nq * (j + nq * k)];
+    }
+  std::vector<int32_t> et((size_t)n_elem, FR_HEX);
+  return setup_impl(p, n_vert, xyz, period, n_elem, et.data(), corners.data(), geo_order, ho_nodes, stream, out);
 }
 
 fr_status fr_layout(fr_ctx c, fr_layout_t* o) {

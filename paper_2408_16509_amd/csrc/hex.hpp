@@ -18,7 +18,11 @@
 // column of points and pulls the three line contractions through its points from LDS.
 // The geometric map is trilinear and evaluated on the fly from its 24 monomial
 // coefficients (metric terms of linear elements computed from the corners),
-// staged per block in LDS.
+// staged per block in LDS.  Curved elements (CUR = true) instead read metric terms
+// stored per point (Sec. "Curved elements"), layout cm (element fastest):
+//   cm[(pt*9 + d*3 + j)*E + e]      row d of S = J G^{-1} at solution point pt
+//   cm[(9*NSP + pt)*E + e]          1/J at solution point pt
+//   cm[(10*NSP + fp*3 + j)*E + e]   row d of S at flux point fp of face 2d+s
 //
 // Arithmetic type T: double (the plain form) or float.  In the float form the
 // state is the deviation du = u - u_ref from a constant state at rest and every
@@ -229,6 +233,23 @@ __device__ __forceinline__ NbrSlot nbr_slot(const Conn& C, int64_t E, int64_t e,
   return s;
 }
 
+template <typename T, int NSP>
+__device__ __forceinline__ void cm_srow(const T* __restrict__ cm, int64_t E, int64_t e, int pt, int d, T s[3]) {
+#pragma unroll
+  for (int j = 0; j < 3; ++j) s[j] = cm[((int64_t)pt * 9 + d * 3 + j) * E + e];
+}
+
+template <typename T, int NSP>
+__device__ __forceinline__ T cm_rjac(const T* __restrict__ cm, int64_t E, int64_t e, int pt) {
+  return cm[((int64_t)9 * NSP + pt) * E + e];
+}
+
+template <typename T, int NSP>
+__device__ __forceinline__ void cm_fnrm(const T* __restrict__ cm, int64_t E, int64_t e, int fp, T s[3]) {
+#pragma unroll
+  for (int j = 0; j < 3; ++j) s[j] = cm[((int64_t)10 * NSP + fp * 3 + j) * E + e];
+}
+
 // Stage the block's geometry coefficients into LDS: G[g*NE + el].
 template <typename T, int NE, int NT>
 __device__ __forceinline__ void stage_geo(const T* __restrict__ geo, int64_t E, int64_t e0, T* G) {
@@ -272,10 +293,10 @@ __global__ void __launch_bounds__(256) hex_trace(const T* __restrict__ u, T* __r
 
 // Accumulate one direction's divergence contribution into LDS and, in the last
 // pass, write R = -div / J.
-template <typename T, int N1, int NE>
+template <typename T, int N1, int NE, bool CUR>
 __device__ __forceinline__ void accumulate_div(int d, const T (&ft)[5][N1], const T (&Fc)[2][5], const HexK<T>& K,
-                                               T* DIV, const T* G, int el, int t0, int t1, int64_t e, int64_t n,
-                                               int64_t E, T* __restrict__ r) {
+                                               T* DIV, const T* G, const T* __restrict__ cm, int el, int t0, int t1,
+                                               int64_t e, int64_t n, int64_t E, T* __restrict__ r) {
   constexpr int NSP = N1 * N1 * N1;
 #pragma unroll
   for (int a = 0; a < N1; ++a) {
@@ -296,10 +317,15 @@ __device__ __forceinline__ void accumulate_div(int d, const T (&ft)[5][N1], cons
 #pragma unroll
       for (int v = 0; v < 5; ++v) D[v * NSP * NE] += div[v];
     } else {
-      T xi[3], g[3][3];
-      line_xi(K, d, a, t0, t1, xi);
-      hex_cols(G + el, NE, xi[0], xi[1], xi[2], g);
-      const T iJ = T(-1) / det_cols(g);
+      T iJ;
+      if constexpr (CUR) {
+        iJ = -cm_rjac<T, NSP>(cm, E, e, pt);
+      } else {
+        T xi[3], g[3][3];
+        line_xi(K, d, a, t0, t1, xi);
+        hex_cols(G + el, NE, xi[0], xi[1], xi[2], g);
+        iJ = T(-1) / det_cols(g);
+      }
       if (e < n) {
 #pragma unroll
         for (int v = 0; v < 5; ++v) r[((int64_t)pt * 5 + v) * E + e] = (D[v * NSP * NE] + div[v]) * iJ;
@@ -312,17 +338,17 @@ __device__ __forceinline__ void accumulate_div(int d, const T (&ft)[5][N1], cons
 // Steps 2-4 for Euler, fused: per line, own traces, neighbour traces, common flux
 // (eq:comm_flux) at both ends, transformed flux at the line points and the
 // corrected divergence (eq:FRfinal); R = -div / J.
-template <typename T, bool DEV, int P, int NE>
+template <typename T, bool DEV, int P, int NE, bool CUR = false>
 __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_div_euler(
-    const T* __restrict__ u, const T* __restrict__ uf, const T* __restrict__ geo,
+    const T* __restrict__ u, const T* __restrict__ uf, const T* __restrict__ geo, const T* __restrict__ cm,
     Conn C, T* __restrict__ r, int64_t E, int64_t n, HexK<T> K, T gamma, int riemann, RefState<T> R) {
   constexpr int N1 = P + 1, NSP = N1 * N1 * N1, NF = N1 * N1, NT = NE * N1 * N1;
   __shared__ T DIV[5 * NSP * NE];
-  __shared__ T G[24 * NE];
+  __shared__ T G[CUR ? 1 : 24 * NE];
   const int el = threadIdx.x % NE, l = threadIdx.x / NE;
   const int64_t e0 = xcd_block() * NE, e = e0 + el;
   const int t0 = l % N1, t1 = l / N1;
-  stage_geo<T, NE, NT>(geo, E, e0, G);
+  if constexpr (!CUR) stage_geo<T, NE, NT>(geo, E, e0, G);
   __syncthreads();
   const T gm1 = gamma - T(1);
 #pragma unroll
@@ -338,10 +364,15 @@ __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_div_euler(
         tm[v] += K.lm[a] * uu[v];
         tp[v] += K.lp[a] * uu[v];
       }
-      T xi[3], g[3][3], s[3], f[5], vs, pr;
-      line_xi(K, d, a, t0, t1, xi);
-      hex_cols(G + el, NE, xi[0], xi[1], xi[2], g);
-      srow(g, d, s);
+      T s[3], f[5], vs, pr;
+      if constexpr (CUR) {
+        cm_srow<T, NSP>(cm, E, e, pt, d, s);
+      } else {
+        T xi[3], g[3][3];
+        line_xi(K, d, a, t0, t1, xi);
+        hex_cols(G + el, NE, xi[0], xi[1], xi[2], g);
+        srow(g, d, s);
+      }
       Flux<T, DEV>::eval(uu, s[0], s[1], s[2], gm1, R, f, vs, pr);
 #pragma unroll
       for (int v = 0; v < 5; ++v) ft[v][a] = f[v];
@@ -349,10 +380,15 @@ __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_div_euler(
     T Fc[2][5];
 #pragma unroll
     for (int sd = 0; sd < 2; ++sd) {
-      T xi[3], g[3][3], nv[3];
-      end_xi(K, d, sd, t0, t1, xi);
-      hex_cols(G + el, NE, xi[0], xi[1], xi[2], g);
-      srow(g, d, nv);
+      T nv[3];
+      if constexpr (CUR) {
+        cm_fnrm<T, NSP>(cm, E, e, (2 * d + sd) * NF + l, nv);
+      } else {
+        T xi[3], g[3][3];
+        end_xi(K, d, sd, t0, t1, xi);
+        hex_cols(G + el, NE, xi[0], xi[1], xi[2], g);
+        srow(g, d, nv);
+      }
       const T sg = sd ? T(1) : T(-1);
       const T mag = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
       const NbrSlot ns = nbr_slot<NF>(C, E, e, 2 * d + sd, l);
@@ -371,7 +407,7 @@ __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_div_euler(
 #pragma unroll
       for (int v = 0; v < 5; ++v) Fc[sd][v] = fs * F[v];
     }
-    accumulate_div<T, N1, NE>(d, ft, Fc, K, DIV, G, el, t0, t1, e, n, E, r);
+    accumulate_div<T, N1, NE, CUR>(d, ft, Fc, K, DIV, G, cm, el, t0, t1, e, n, E, r);
     if (d < 2) __syncthreads();
   }
 }
@@ -394,20 +430,20 @@ __device__ __forceinline__ int gr_slot(int pt) {
 // (u^ = u_L, the viscous common flux takes the right side only: the left side's
 // jump vanishes and only right-side traces are stored), -1 for beta = -1/2 (the
 // mirror case), 0 in general.
-template <typename T, int P, int NE>
+template <typename T, int P, int NE, bool CUR = false>
 __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_grad(
-    const T* __restrict__ u, const T* __restrict__ uf, const T* __restrict__ geo,
+    const T* __restrict__ u, const T* __restrict__ uf, const T* __restrict__ geo, const T* __restrict__ cm,
     Conn C, T* __restrict__ grad, T* __restrict__ gradf, int64_t E, HexK<T> K, T beta, int side_mode) {
   constexpr int N1 = P + 1, NSP = N1 * N1 * N1, NF = N1 * N1, NT = NE * N1 * N1;
   __shared__ T GR[3 * NSP * NE];
   __shared__ T U[5 * NSP * NE];       // the block's state, [pt*5 + v][el]
-  __shared__ T G[24 * NE];
+  __shared__ T G[CUR ? 1 : 24 * NE];
   const int el = threadIdx.x % NE, l = threadIdx.x / NE;
   const int64_t e0 = xcd_block() * NE, e = e0 + el;
   const int t0 = l % N1, t1 = l / N1;
   // the global reads up front: geometry, the block's state and the neighbour traces at
   // this thread's 6 line ends (only where the common value is not the own trace)
-  stage_geo<T, NE, NT>(geo, E, e0, G);
+  if constexpr (!CUR) stage_geo<T, NE, NT>(geo, E, e0, G);
   for (int i = threadIdx.x; i < 5 * NSP * NE; i += NT) U[i] = u[(int64_t)(i / NE) * E + e0 + i % NE];
   auto uval = [&](int pt, int v) -> T { return U[(pt * 5 + v) * NE + el]; };
   T uh[3][2][5];
@@ -429,11 +465,18 @@ __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_grad(
   for (int d = 0; d < 3; ++d)
 #pragma unroll
     for (int a = 0; a < N1; ++a) {
-      T xi[3], g[3][3], s[3];
-      line_xi(K, d, a, t0, t1, xi);
-      hex_cols(G + el, NE, xi[0], xi[1], xi[2], g);
-      srow(g, d, s);
-      const T iJ = T(1) / det_cols(g);
+      T s[3], iJ;
+      if constexpr (CUR) {
+        const int pt = line_pt<N1>(d, a, t0, t1);
+        cm_srow<T, NSP>(cm, E, e, pt, d, s);
+        iJ = cm_rjac<T, NSP>(cm, E, e, pt);
+      } else {
+        T xi[3], g[3][3];
+        line_xi(K, d, a, t0, t1, xi);
+        hex_cols(G + el, NE, xi[0], xi[1], xi[2], g);
+        srow(g, d, s);
+        iJ = T(1) / det_cols(g);
+      }
 #pragma unroll
       for (int j = 0; j < 3; ++j) sJ[d][a][j] = s[j] * iJ;
     }
@@ -515,17 +558,17 @@ __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_grad(
 // Variant for p = 4: the state is read from global memory (L2) per line and variable
 // instead of being staged, which keeps the LDS and registers of the 125-point element
 // within an occupancy of 3-4 waves per SIMD.
-template <typename T, int P, int NE>
+template <typename T, int P, int NE, bool CUR = false>
 __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_grad_lines(
-    const T* __restrict__ u, const T* __restrict__ uf, const T* __restrict__ geo,
+    const T* __restrict__ u, const T* __restrict__ uf, const T* __restrict__ geo, const T* __restrict__ cm,
     Conn C, T* __restrict__ grad, T* __restrict__ gradf, int64_t E, HexK<T> K, T beta, int side_mode) {
   constexpr int N1 = P + 1, NSP = N1 * N1 * N1, NF = N1 * N1, NT = NE * N1 * N1;
   __shared__ T GR[3 * NSP * NE];
-  __shared__ T G[24 * NE];
+  __shared__ T G[CUR ? 1 : 24 * NE];
   const int el = threadIdx.x % NE, l = threadIdx.x / NE;
   const int64_t e0 = xcd_block() * NE, e = e0 + el;
   const int t0 = l % N1, t1 = l / N1;
-  stage_geo<T, NE, NT>(geo, E, e0, G);
+  if constexpr (!CUR) stage_geo<T, NE, NT>(geo, E, e0, G);
   // connectivity of this thread's 6 line ends
   NbrSlot ns[3][2];
 #pragma unroll
@@ -539,11 +582,18 @@ __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_grad_lines(
   for (int d = 0; d < 3; ++d)
 #pragma unroll
     for (int a = 0; a < N1; ++a) {
-      T xi[3], g[3][3], s[3];
-      line_xi(K, d, a, t0, t1, xi);
-      hex_cols(G + el, NE, xi[0], xi[1], xi[2], g);
-      srow(g, d, s);
-      const T iJ = T(1) / det_cols(g);
+      T s[3], iJ;
+      if constexpr (CUR) {
+        const int pt = line_pt<N1>(d, a, t0, t1);
+        cm_srow<T, NSP>(cm, E, e, pt, d, s);
+        iJ = cm_rjac<T, NSP>(cm, E, e, pt);
+      } else {
+        T xi[3], g[3][3];
+        line_xi(K, d, a, t0, t1, xi);
+        hex_cols(G + el, NE, xi[0], xi[1], xi[2], g);
+        srow(g, d, s);
+        iJ = T(1) / det_cols(g);
+      }
 #pragma unroll
       for (int j = 0; j < 3; ++j) sJ[d][a][j] = s[j] * iJ;
     }
@@ -626,12 +676,13 @@ __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_grad_lines(
 // +|S^T n~| times it into its own slot and the negative into the right side's slot
 // (conservative by construction).  With a one-sided switch only the contributing
 // side's gradient trace is read (stored by hex_grad in that side's slot).
-template <typename T, bool DEV, int P>
+template <typename T, bool DEV, int P, bool CUR = false>
 __global__ void __launch_bounds__(256) hex_face_ns(const T* __restrict__ uf, const T* __restrict__ gradf,
-                                                   const T* __restrict__ geo, Conn C, T* __restrict__ fc, int64_t E,
+                                                   const T* __restrict__ geo, const T* __restrict__ cm, Conn C,
+                                                   T* __restrict__ fc, int64_t E,
                                                    int64_t n, HexK<T> K, T gamma, T mu, T pr, T beta, T tau,
                                                    int riemann, int side_mode, RefState<T> R) {
-  constexpr int N1 = P + 1, NF = N1 * N1, NFP = 6 * NF;
+  constexpr int N1 = P + 1, NF = N1 * N1, NFP = 6 * NF, NSP = N1 * N1 * N1;
   const int64_t gtid = xcd_block() * 256 + threadIdx.x;
   const int64_t wave = gtid >> 6;
   const int lane = (int)(gtid & 63);
@@ -640,13 +691,18 @@ __global__ void __launch_bounds__(256) hex_face_ns(const T* __restrict__ uf, con
   const int64_t e = tile * 64 + lane;
   if (e >= n) return;
   const int face = fp / NF, q = fp % NF, d = face / 2, sd = face % 2, t0 = q % N1, t1 = q / N1;
-  T c[24];
+  T nv[3];
+  if constexpr (CUR) {
+    cm_fnrm<T, NSP>(cm, E, e, fp, nv);
+  } else {
+    T c[24];
 #pragma unroll
-  for (int g = 0; g < 24; ++g) c[g] = geo[(int64_t)g * E + e];
-  T xi[3], g[3][3], nv[3];
-  end_xi(K, d, sd, t0, t1, xi);
-  hex_cols(c, 1, xi[0], xi[1], xi[2], g);
-  srow(g, d, nv);
+    for (int g = 0; g < 24; ++g) c[g] = geo[(int64_t)g * E + e];
+    T xi[3], g[3][3];
+    end_xi(K, d, sd, t0, t1, xi);
+    hex_cols(c, 1, xi[0], xi[1], xi[2], g);
+    srow(g, d, nv);
+  }
   const T mag = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
   const NbrSlot ns = nbr_slot<NF>(C, E, e, face, q);
   // each flux-point pair once: the left side computes it and writes both slots
@@ -695,19 +751,19 @@ __global__ void __launch_bounds__(256) hex_face_ns(const T* __restrict__ uf, con
 // flux of all three directions at its column's points once (every u and grad u
 // value is read once) into LDS, then gathers, for each of its points, the three
 // line contractions through that point from LDS.
-template <typename T, bool DEV, int P, int NE>
+template <typename T, bool DEV, int P, int NE, bool CUR = false>
 __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_div_ns(
     const T* __restrict__ u, const T* __restrict__ grad, const T* __restrict__ fc, const T* __restrict__ geo,
-    T* __restrict__ r, int64_t E, int64_t n, HexK<T> K, T gamma, T mu, T pr, RefState<T> R) {
+    const T* __restrict__ cm, T* __restrict__ r, int64_t E, int64_t n, HexK<T> K, T gamma, T mu, T pr, RefState<T> R) {
   constexpr int N1 = P + 1, NSP = N1 * N1 * N1, NF = N1 * N1, NT = NE * N1 * N1;
   // f~ along xi_1 and xi_2 go through LDS ([d][v][pt][el]); along xi_3 the line is the
   // thread's own column, so f~_3 and its common fluxes stay in registers
   __shared__ T FT[2 * 5 * NSP * NE];
-  __shared__ T G[24 * NE];
+  __shared__ T G[CUR ? 1 : 24 * NE];
   const int el = threadIdx.x % NE, l = threadIdx.x / NE;
   const int64_t e0 = xcd_block() * NE, e = e0 + el;
   const int ci = l % N1, cj = l / N1;
-  stage_geo<T, NE, NT>(geo, E, e0, G);
+  if constexpr (!CUR) stage_geo<T, NE, NT>(geo, E, e0, G);
   __syncthreads();
   const T gm1 = gamma - T(1);
   T iJ[N1], f3[N1][5];
@@ -720,12 +776,17 @@ __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_div_ns(
 #pragma unroll
     for (int q = 0; q < 15; ++q) gg[q] = grad[((int64_t)pt * 15 + q) * E + e];
     T g[3][3];
-    hex_cols(G + el, NE, K.x[ci], K.x[cj], K.x[k], g);
-    iJ[k] = T(-1) / det_cols(g);
+    if constexpr (CUR) {
+      iJ[k] = -cm_rjac<T, NSP>(cm, E, e, pt);
+    } else {
+      hex_cols(G + el, NE, K.x[ci], K.x[cj], K.x[k], g);
+      iJ[k] = T(-1) / det_cols(g);
+    }
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       T s[3], f[5], fv[5], vs, prs;
-      srow(g, d, s);
+      if constexpr (CUR) cm_srow<T, NSP>(cm, E, e, pt, d, s);
+      else srow(g, d, s);
       Flux<T, DEV>::eval(uu, s[0], s[1], s[2], gm1, R, f, vs, prs);
       viscous<T, DEV>(uu, gg, s[0], s[1], s[2], gamma, mu, pr, R, fv);
 #pragma unroll
@@ -767,17 +828,17 @@ __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_div_ns(
 
 // Variant with all three directions' f~ in LDS (the register budget of FP64 and of
 // p = 4 does not hold f~_3 of a whole column).
-template <typename T, bool DEV, int P, int NE>
+template <typename T, bool DEV, int P, int NE, bool CUR = false>
 __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_div_ns_lds(
     const T* __restrict__ u, const T* __restrict__ grad, const T* __restrict__ fc, const T* __restrict__ geo,
-    T* __restrict__ r, int64_t E, int64_t n, HexK<T> K, T gamma, T mu, T pr, RefState<T> R) {
+    const T* __restrict__ cm, T* __restrict__ r, int64_t E, int64_t n, HexK<T> K, T gamma, T mu, T pr, RefState<T> R) {
   constexpr int N1 = P + 1, NSP = N1 * N1 * N1, NF = N1 * N1, NT = NE * N1 * N1;
   __shared__ T FT[3 * 5 * NSP * NE];       // [d][v][pt][el]
-  __shared__ T G[24 * NE];
+  __shared__ T G[CUR ? 1 : 24 * NE];
   const int el = threadIdx.x % NE, l = threadIdx.x / NE;
   const int64_t e0 = xcd_block() * NE, e = e0 + el;
   const int ci = l % N1, cj = l / N1;
-  stage_geo<T, NE, NT>(geo, E, e0, G);
+  if constexpr (!CUR) stage_geo<T, NE, NT>(geo, E, e0, G);
   __syncthreads();
   const T gm1 = gamma - T(1);
   T iJ[N1];
@@ -790,12 +851,17 @@ __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_div_ns_lds(
 #pragma unroll
     for (int q = 0; q < 15; ++q) gg[q] = grad[((int64_t)pt * 15 + q) * E + e];
     T g[3][3];
-    hex_cols(G + el, NE, K.x[ci], K.x[cj], K.x[k], g);
-    iJ[k] = T(-1) / det_cols(g);
+    if constexpr (CUR) {
+      iJ[k] = -cm_rjac<T, NSP>(cm, E, e, pt);
+    } else {
+      hex_cols(G + el, NE, K.x[ci], K.x[cj], K.x[k], g);
+      iJ[k] = T(-1) / det_cols(g);
+    }
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       T s[3], f[5], fv[5], vs, prs;
-      srow(g, d, s);
+      if constexpr (CUR) cm_srow<T, NSP>(cm, E, e, pt, d, s);
+      else srow(g, d, s);
       Flux<T, DEV>::eval(uu, s[0], s[1], s[2], gm1, R, f, vs, prs);
       viscous<T, DEV>(uu, gg, s[0], s[1], s[2], gamma, mu, pr, R, fv);
 #pragma unroll

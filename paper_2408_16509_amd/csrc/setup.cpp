@@ -16,6 +16,7 @@
 #include <array>
 #include <cmath>
 #include <map>
+#include <thread>
 #include <unordered_map>
 
 namespace frmi {
@@ -726,6 +727,255 @@ std::string build_setup(int order, int64_t n_vert, const double* xyz, const doub
   for (int i = 0; i < out.n_orient; ++i)
     for (size_t q = 0; q < perms[i].size(); ++q) out.orient_perm[(size_t)i * out.perm_stride + q] = perms[i][q];
   (void)bidx;
+  return "";
+}
+
+}  // namespace frmi
+
+namespace frmi {
+
+// ------------------------------------------------------------------ curved hexahedra
+// Sec. "Curved elements": per-point metric terms of curved elements, formed either as
+// cross products of the exact map's derivatives or in the conservative (curl) form,
+// whose discrete divergence vanishes so that a uniform stream stays uniform.
+//
+// Conservative form, with (n, m, l) cyclic: S_rn = J dxi_r/dx_n = -[curl_xi V^(n)]_r,
+// V^(n) = I(x_l grad_xi x_m), I the tensor interpolant on the (p+1)^3 Gauss--Lobatto
+// points.  Here V^(n) is sampled at the Lobatto grid, differentiated there with the
+// 1-D Lobatto derivative matrix (exact for the interpolant), the curl formed at the
+// grid, and the resulting Q_p polynomial evaluated at the Gauss solution points and
+// the flux points (on a face xi_d = +-1 the Lobatto end nodes are face values, so
+// only the tangential interpolation remains).
+
+// Gauss--Lobatto nodes of n = 2..5 points, closed forms.
+static void gll_points(int n, ld* y) {
+  y[0] = -1;
+  y[n - 1] = 1;
+  if (n == 3) y[1] = 0;
+  if (n == 4) { y[1] = -1 / sqrtl(5.0L); y[2] = -y[1]; }
+  if (n == 5) { y[1] = -sqrtl(3.0L / 7.0L); y[2] = 0; y[3] = -y[1]; }
+}
+
+// Values and derivatives of the n Lagrange polynomials on `nodes` at x.
+static void lagrange_1d(const ld* nodes, int n, ld x, ld* val, ld* der) {
+  for (int j = 0; j < n; ++j) {
+    ld v = 1, dsum = 0;
+    for (int m = 0; m < n; ++m) {
+      if (m == j) continue;
+      v *= (x - nodes[m]) / (nodes[j] - nodes[m]);
+    }
+    for (int k = 0; k < n; ++k) {
+      if (k == j) continue;
+      ld t = 1 / (nodes[j] - nodes[k]);
+      for (int m = 0; m < n; ++m)
+        if (m != j && m != k) t *= (x - nodes[m]) / (nodes[j] - nodes[m]);
+      dsum += t;
+    }
+    val[j] = v;
+    der[j] = dsum;
+  }
+}
+
+std::string build_curved_hex(int q, int metric, const double* xyz, const int64_t* ho, Setup& s, int& code) {
+  code = 0;
+  Block* bp = nullptr;
+  for (auto& b : s.blocks) if (b.etype == kHex) bp = &b;
+  if (!bp) { code = 1; return "no hexahedra"; }
+  Block& b = *bp;
+  const HexOps& H = s.hex;
+  const int n1 = H.n1, nsp = H.nsp, nq = q + 1, NQ = nq * nq * nq, NG = n1 * n1 * n1;
+  const int rows = 10 * nsp + 3 * H.nfp;
+  b.cmet.assign((size_t)rows * b.e_pad, 0.0);
+  // 1-D tables in long double, used in double
+  ld gn[5], y[5], xg[5], t1[5], t2[5];
+  for (int i = 0; i < nq; ++i) gn[i] = -1 + 2 * (ld)i / q;
+  gll_points(n1, y);
+  for (int i = 0; i < n1; ++i) xg[i] = H.x[i];
+  double Dg[5][5], Ig[5][5];           // Lobatto derivative matrix; Lobatto basis at the Gauss points
+  double Lly[5][5], dLy[5][5], Llx[5][5], dLx[5][5], Lle[2][5], dLe[2][5];   // geometry basis
+  for (int a = 0; a < n1; ++a) {
+    lagrange_1d(y, n1, y[a], t1, t2);
+    for (int j = 0; j < n1; ++j) Dg[a][j] = (double)t2[j];
+    lagrange_1d(y, n1, xg[a], t1, t2);
+    for (int j = 0; j < n1; ++j) Ig[a][j] = (double)t1[j];
+    lagrange_1d(gn, nq, y[a], t1, t2);
+    for (int j = 0; j < nq; ++j) { Lly[a][j] = (double)t1[j]; dLy[a][j] = (double)t2[j]; }
+    lagrange_1d(gn, nq, xg[a], t1, t2);
+    for (int j = 0; j < nq; ++j) { Llx[a][j] = (double)t1[j]; dLx[a][j] = (double)t2[j]; }
+  }
+  for (int sd = 0; sd < 2; ++sd) {
+    lagrange_1d(gn, nq, sd ? 1 : -1, t1, t2);
+    for (int j = 0; j < nq; ++j) { Lle[sd][j] = (double)t1[j]; dLe[sd][j] = (double)t2[j]; }
+  }
+  auto det3 = [](const double G[3][3]) {
+    return G[0][0] * (G[1][1] * G[2][2] - G[1][2] * G[2][1]) - G[0][1] * (G[1][0] * G[2][2] - G[1][2] * G[2][0]) +
+           G[0][2] * (G[1][0] * G[2][1] - G[1][1] * G[2][0]);
+  };
+  // exact metric row r = g_{r+1} x g_{r+2}, g_j = column j of G
+  auto cross_rows = [](const double G[3][3], double S[3][3]) {
+    for (int r = 0; r < 3; ++r) {
+      const int a = (r + 1) % 3, c = (r + 2) % 3;
+      S[r][0] = G[1][a] * G[2][c] - G[2][a] * G[1][c];
+      S[r][1] = G[2][a] * G[0][c] - G[0][a] * G[2][c];
+      S[r][2] = G[0][a] * G[1][c] - G[1][a] * G[0][c];
+    }
+  };
+  auto put = [&](int64_t le, int row, double v) { b.cmet[(size_t)row * b.e_pad + le] = v; };
+  // elements [lo, hi): all buffers local, so threads share nothing but the outputs
+  auto work = [&](int64_t lo, int64_t hi, std::string& err) {
+    std::vector<double> X((size_t)NQ * 3), V((size_t)3 * NG * 3), Ja((size_t)NG * 9), T1((size_t)NG * 9),
+        T2((size_t)NG * 9);
+    // x and G (G[c][j] = d x_c / d xi_j) from 1-D tables of the three coordinates
+    auto geo_at = [&](const double* L0, const double* D0, const double* L1, const double* D1, const double* L2,
+                      const double* D2, double x[3], double G[3][3]) {
+      for (int c = 0; c < 3; ++c) { x[c] = 0; G[c][0] = G[c][1] = G[c][2] = 0; }
+      for (int k = 0; k < nq; ++k)
+        for (int j = 0; j < nq; ++j) {
+          const double ljk = L1[j] * L2[k], djk = D1[j] * L2[k], ljd = L1[j] * D2[k];
+          for (int i = 0; i < nq; ++i) {
+            const double* Xn = &X[(size_t)(i + nq * (j + nq * k)) * 3];
+            const double w = L0[i] * ljk, w0 = D0[i] * ljk, w1 = L0[i] * djk, w2 = L0[i] * ljd;
+            for (int c = 0; c < 3; ++c) {
+              x[c] += w * Xn[c];
+              G[c][0] += w0 * Xn[c];
+              G[c][1] += w1 * Xn[c];
+              G[c][2] += w2 * Xn[c];
+            }
+          }
+        }
+    };
+    for (int64_t le = lo; le < hi; ++le) {
+      const int64_t e = b.elems[le];
+      for (int n = 0; n < NQ; ++n)
+        for (int c = 0; c < 3; ++c) X[(size_t)n * 3 + c] = xyz[ho[e * NQ + n] * 3 + c];
+      if (metric == 0) {
+        // the factor x_l relative to node 0: no change in exact arithmetic for q <= p
+        // (the interpolated grad x_m has zero curl), no cancellation of |x| against h^2
+        double X0[3] = {X[0], X[1], X[2]};
+        // V^(n)[node][k] = (x_l - x0_l) d x_m / d xi_k at the Lobatto grid
+        for (int c = 0; c < n1; ++c)
+          for (int bb = 0; bb < n1; ++bb)
+            for (int a = 0; a < n1; ++a) {
+              double x[3], G[3][3];
+              geo_at(Lly[a], dLy[a], Lly[bb], dLy[bb], Lly[c], dLy[c], x, G);
+              const int node = a + n1 * (bb + n1 * c);
+              for (int n = 0; n < 3; ++n) {
+                const int m = (n + 1) % 3, l = (n + 2) % 3;
+                for (int k = 0; k < 3; ++k) V[((size_t)n * NG + node) * 3 + k] = (x[l] - X0[l]) * G[m][k];
+              }
+            }
+        // curl at the grid: Ja[node][r*3 + n] = -(d_a V_b - d_b V_a), (r, a, b) cyclic
+        for (int c = 0; c < n1; ++c)
+          for (int bb = 0; bb < n1; ++bb)
+            for (int a = 0; a < n1; ++a) {
+              const int node = a + n1 * (bb + n1 * c);
+              const int idx[3] = {a, bb, c};
+              const int stride[3] = {1, n1, n1 * n1};
+              for (int n = 0; n < 3; ++n) {
+                double dV[3][3];   // dV[ax][k] = d V_k / d xi_ax at this node
+                for (int ax = 0; ax < 3; ++ax) {
+                  const int base = node - idx[ax] * stride[ax];
+                  for (int k = 0; k < 3; ++k) {
+                    double acc = 0;
+                    for (int t = 0; t < n1; ++t) acc += Dg[idx[ax]][t] * V[((size_t)n * NG + base + t * stride[ax]) * 3 + k];
+                    dV[ax][k] = acc;
+                  }
+                }
+                for (int r = 0; r < 3; ++r) {
+                  const int ra = (r + 1) % 3, rb = (r + 2) % 3;
+                  Ja[(size_t)node * 9 + r * 3 + n] = -(dV[ra][rb] - dV[rb][ra]);
+                }
+              }
+            }
+        // the Q_p polynomial at the Gauss solution points, one axis at a time
+        for (int c = 0; c < n1; ++c)
+          for (int bb = 0; bb < n1; ++bb)
+            for (int i = 0; i < n1; ++i)
+              for (int r = 0; r < 9; ++r) {
+                double acc = 0;
+                for (int a = 0; a < n1; ++a) acc += Ig[i][a] * Ja[(size_t)(a + n1 * (bb + n1 * c)) * 9 + r];
+                T1[(size_t)(i + n1 * (bb + n1 * c)) * 9 + r] = acc;
+              }
+        for (int c = 0; c < n1; ++c)
+          for (int j = 0; j < n1; ++j)
+            for (int i = 0; i < n1; ++i)
+              for (int r = 0; r < 9; ++r) {
+                double acc = 0;
+                for (int bb = 0; bb < n1; ++bb) acc += Ig[j][bb] * T1[(size_t)(i + n1 * (bb + n1 * c)) * 9 + r];
+                T2[(size_t)(i + n1 * (j + n1 * c)) * 9 + r] = acc;
+              }
+      }
+      // solution points: S rows, 1/J, physical coordinates
+      for (int k = 0; k < n1; ++k)
+        for (int j = 0; j < n1; ++j)
+          for (int i = 0; i < n1; ++i) {
+            const int pt = i + n1 * (j + n1 * k);
+            double x[3], G[3][3], S[3][3];
+            geo_at(Llx[i], dLx[i], Llx[j], dLx[j], Llx[k], dLx[k], x, G);
+            const double J = det3(G);
+            if (!(J > 0)) { err = "curved element with J <= 0"; return; }
+            if (metric == 0) {
+              for (int r = 0; r < 9; ++r) {
+                double acc = 0;
+                for (int c = 0; c < n1; ++c) acc += Ig[k][c] * T2[(size_t)(i + n1 * (j + n1 * c)) * 9 + r];
+                S[r / 3][r % 3] = acc;
+              }
+            } else {
+              cross_rows(G, S);
+            }
+            for (int d = 0; d < 3; ++d)
+              for (int c = 0; c < 3; ++c) put(le, pt * 9 + d * 3 + c, S[d][c]);
+            put(le, 9 * nsp + pt, 1 / J);
+            for (int c = 0; c < 3; ++c) b.sol_xyz[((size_t)b.canon_pos[le] * nsp + pt) * 3 + c] = x[c];
+          }
+      // flux points: row d of S on face 2d+s, tangential Gauss coordinates (t0, t1)
+      for (int f = 0; f < 6; ++f)
+        for (int qq = 0; qq < H.nfpf; ++qq) {
+          const int d = f / 2, sd = f % 2, u0 = qq % n1, u1 = qq / n1;
+          const int ta = d == 0 ? 1 : 0, tb = d == 2 ? 1 : 2;
+          const double* L[3];
+          const double* D[3];
+          L[d] = Lle[sd]; D[d] = dLe[sd];
+          L[ta] = Llx[u0]; D[ta] = dLx[u0];
+          L[tb] = Llx[u1]; D[tb] = dLx[u1];
+          double x[3], G[3][3], row[3];
+          geo_at(L[0], D[0], L[1], D[1], L[2], D[2], x, G);
+          if (!(det3(G) > 0)) { err = "curved element with J <= 0"; return; }
+          if (metric == 0) {
+            // the Lobatto end nodes are face values: interpolate along the two tangents only
+            const int end = sd ? n1 - 1 : 0;
+            for (int c = 0; c < 3; ++c) {
+              double acc = 0;
+              for (int v1 = 0; v1 < n1; ++v1)
+                for (int v0 = 0; v0 < n1; ++v0) {
+                  int id[3];
+                  id[d] = end; id[ta] = v0; id[tb] = v1;
+                  acc += Ig[u0][v0] * Ig[u1][v1] * Ja[(size_t)(id[0] + n1 * (id[1] + n1 * id[2])) * 9 + d * 3 + c];
+                }
+              row[c] = acc;
+            }
+          } else {
+            double S[3][3];
+            cross_rows(G, S);
+            for (int c = 0; c < 3; ++c) row[c] = S[d][c];
+          }
+          const int fp = f * H.nfpf + qq;
+          for (int c = 0; c < 3; ++c) put(le, 10 * nsp + fp * 3 + c, row[c]);
+        }
+    }
+  };
+  const int64_t nthr = std::max<int64_t>(1, std::min<int64_t>({16, (int64_t)std::thread::hardware_concurrency(),
+                                                               (b.n + 255) / 256}));
+  std::vector<std::string> errs((size_t)nthr);
+  std::vector<std::thread> pool;
+  for (int64_t t = 0; t < nthr; ++t)
+    pool.emplace_back(work, b.n * t / nthr, b.n * (t + 1) / nthr, std::ref(errs[(size_t)t]));
+  for (auto& th : pool) th.join();
+  for (auto& m : errs)
+    if (!m.empty()) { code = 2; return m; }
+  // padding lanes copy the first element's terms (in bounds, results discarded)
+  for (int r = 0; r < rows; ++r)
+    for (int64_t le = b.n; le < b.e_pad; ++le) b.cmet[(size_t)r * b.e_pad + le] = b.cmet[(size_t)r * b.e_pad];
   return "";
 }
 

@@ -53,6 +53,11 @@ struct Block {
   std::vector<int32_t> nbr_elem;   // [nfaces][e_pad] neighbour's local index (same block)
   std::vector<int32_t> nbr_info;   // [nfaces][e_pad] nbr_face | orient << 3 | is_left << 12
   std::vector<double> sol_xyz;     // [n][nsp][3] physical solution points (canonical order)
+  // Curved hexahedra: stored metric terms (empty for straight elements), rows of e_pad
+  // values: S row d at solution point pt (row pt*9 + d*3 + j, S = J G^{-1}), 1/J at
+  // solution point pt (row 9 nsp + pt), and at flux point fp of face 2d+s row d of S
+  // (row 10 nsp + fp*3 + j).
+  std::vector<double> cmet;
 };
 
 struct Setup {
@@ -71,5 +76,12 @@ void build_tet_ops(TetOps& ops);
 std::string build_setup(int order, int64_t n_vert, const double* xyz, const double* period,
                         int64_t n_elem, const int32_t* etype, const int64_t* enodes,
                         int e_align, int elem_order, Setup& out, int& code);
+
+// Metric terms of curved hexahedra of geometry order q (the hexahedral block of `s`,
+// built by build_setup from the elements' corners).  ho: [n_elem][(q+1)^3] node
+// indices in tensor order (node i + (q+1)(j + (q+1)k) at reference point
+// (-1 + 2i/q, -1 + 2j/q, -1 + 2k/q)).  metric 0: conservative (curl) form, 1: cross
+// product.  Fills Block::cmet and replaces Block::sol_xyz with the curved points.
+std::string build_curved_hex(int q, int metric, const double* xyz, const int64_t* ho, Setup& s, int& code);
 
 }  // namespace frmi

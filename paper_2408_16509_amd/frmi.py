@@ -19,6 +19,7 @@ FR_EULER, FR_NAVIER_STOKES = 0, 1
 FR_RUSANOV, FR_HLLC = 0, 1
 FR_FP64, FR_FP32, FR_FP32_BF16X3 = 0, 1, 2
 FR_HEX, FR_TET = 0, 1
+FR_METRIC_CONSERVATIVE, FR_METRIC_CROSS = 0, 1
 STATUS = {0: "FR_OK", 1: "FR_ERR_ARG", 2: "FR_ERR_MESH", 3: "FR_ERR_ALLOC", 4: "FR_ERR_DEVICE",
           5: "FR_ERR_NONFINITE", 6: "FR_ERR_STATE", 7: "FR_ERR_UNSUPPORTED"}
 
@@ -30,7 +31,7 @@ class FrParams(ctypes.Structure):
         ("gamma", ctypes.c_double), ("mu", ctypes.c_double), ("prandtl", ctypes.c_double),
         ("ldg_beta", ctypes.c_double), ("ldg_tau", ctypes.c_double), ("u_ref", ctypes.c_double * 5),
         ("filt_eps_rho", ctypes.c_double), ("filt_eps_p", ctypes.c_double), ("filt_eps_s", ctypes.c_double),
-        ("filt_zeta_max_coef", ctypes.c_double), ("filt_bits", ctypes.c_int32), ("reserved1", ctypes.c_int32),
+        ("filt_zeta_max_coef", ctypes.c_double), ("filt_bits", ctypes.c_int32), ("hex_metric", ctypes.c_int32),
     ]
 
 
@@ -65,7 +66,7 @@ class FrKernelTime(ctypes.Structure):
 
 
 EXPORTS = [
-    "fr_default_params", "fr_setup_mesh", "fr_layout", "fr_sol_points", "fr_pack", "fr_unpack",
+    "fr_default_params", "fr_setup_mesh", "fr_setup_mesh_curved", "fr_layout", "fr_sol_points", "fr_pack", "fr_unpack",
     "fr_pack64", "fr_unpack64", "fr_unpack_rhs",
     "fr_rhs", "fr_rk_step", "fr_default_adaptive_params", "fr_rk_adaptive", "fr_filter", "fr_mlp_set_weights", "fr_mlp_get_weights",
     "fr_mlp_features", "fr_mlp_collect", "fr_mlp_forward", "fr_mlp_grad", "fr_mlp_train", "fr_check", "fr_sync",
@@ -83,6 +84,7 @@ def load():
     sig = {
         "fr_default_params": (None, [P(FrParams)]),
         "fr_setup_mesh": (i32, [P(FrParams), i64, vp, vp, i64, vp, vp, vp, P(vp)]),
+        "fr_setup_mesh_curved": (i32, [P(FrParams), i32, i64, vp, vp, i64, vp, vp, P(vp)]),
         "fr_layout": (i32, [vp, P(FrLayout)]),
         "fr_sol_points": (i32, [vp, vp]),
         "fr_pack": (i32, [vp, vp, vp]),
@@ -164,9 +166,17 @@ class Context:
             stream = torch.cuda.current_stream().cuda_stream
         self.stream = stream
         h = ctypes.c_void_p()
-        st = lib().fr_setup_mesh(ctypes.byref(self.params), xyz.shape[0], xyz.ctypes.data, per.ctypes.data,
-                                 et.shape[0], et.ctypes.data, en.ctypes.data, ctypes.c_void_p(stream),
-                                 ctypes.byref(h))
+        ho = getattr(mesh, "ho_enodes", None)
+        if ho is not None:
+            # curved hexahedra: tensor-order nodes of geometry order mesh.geo_order
+            ho = np.ascontiguousarray(ho, dtype=np.int64)
+            st = lib().fr_setup_mesh_curved(ctypes.byref(self.params), int(mesh.geo_order), xyz.shape[0],
+                                            xyz.ctypes.data, per.ctypes.data, ho.shape[0], ho.ctypes.data,
+                                            ctypes.c_void_p(stream), ctypes.byref(h))
+        else:
+            st = lib().fr_setup_mesh(ctypes.byref(self.params), xyz.shape[0], xyz.ctypes.data, per.ctypes.data,
+                                     et.shape[0], et.ctypes.data, en.ctypes.data, ctypes.c_void_p(stream),
+                                     ctypes.byref(h))
         if st != 0:
             raise FrError(st, lib().fr_last_error(None).decode())
         self.h = h

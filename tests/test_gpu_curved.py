@@ -1,0 +1,176 @@
+"""GPU parity on curved hexahedra (fr_setup_mesh_curved: metric terms stored per point)
+against the FP64 oracle with the same metric (Sec. "Curved elements", Fig. fsp).
+
+Meshes: seeded curved periodic boxes of geometry order q (smooth periodic displacement
+plus node jitter), 5 x 4 x 4 = 80 elements (two 64-element tiles, the second ragged),
+element order permuted.  FP64 tolerance: relative L2 <= max(1e-12, 4 x floor), over
+all values and for each variable with its own floor, where floor is the oracle's response to a
+one-ulp relative perturbation of the state plus a relative perturbation of its metric
+terms (S at solution and flux points, J) of n eps, n = max((p+1)^3, (q+1)^3) the terms
+of the sums that form them: two correct FP64 evaluations of the curl form differ by
+that much (measured: up to 5e-14 on entries of size ~1), and the O(1/Ma^2) pressure of
+the low-Mach state carries it into the momentum residual.
+Free stream (uniform state): the conservative metric keeps |R| at rounding level (bound
+1e-10: the Navier--Stokes path forms each face pair's common flux once, along the left
+side's normal, and the right side's own normal, interpolated from its own element,
+agrees with it to ~1e-14 relative; the flux (~2.5) times the lifting scale (p+1)^2 / J
+turns that into ~1e-12), the cross-product metric does not once 2(q-1) > p (errors of
+0.6 and 3.5 here), and the two sides agree on its values.
+A q = 1 curved context and the straight-element path (metric from the 8 corners) agree
+to rounding at p >= 2, where the conservative metric of a trilinear map is exact.
+FP32 form: well-conditioned random states within 1e-5 (stated bound).
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from oracle import fr as ofr
+from oracle import mesh as omesh
+from oracle import rk as ork
+from paper_2408_16509_amd import inputs
+
+from helpers import rel_err
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _mesh(q, n=(5, 4, 4), perturb=0.08):
+    return inputs.curved_hex_box(n, q=q, amp=0.2, perturb=perturb, perturb_seed=3, permute_seed=7)
+
+
+def _state(b, kind, seed=1):
+    x = b.xsol
+    if kind == "random":
+        s = inputs.random_state(x.shape[:2], seed)
+    elif kind == "tgv":
+        s = inputs.tgv(x[..., 0], x[..., 1], x[..., 2], mach=0.1)
+    else:
+        s = np.zeros((5,) + x.shape[:2])
+        s[0], s[1], s[2], s[3], s[4] = 1.2, 0.3, -0.2, 0.5, 2.5
+    return np.moveaxis(s, 0, 1).copy()
+
+
+def _gpu_rhs(mesh, u, **kw):
+    from paper_2408_16509_amd import frmi
+    ctx = frmi.Context(mesh, **kw)
+    ug = ctx.pack(u.ravel())
+    r = ctx.new_native()
+    ctx.rhs(ug, r)
+    out = ctx.unpack_rhs(r).cpu().numpy().reshape(u.shape)
+    ctx.close()
+    return out
+
+
+def _floor(bl, u, prm, q, p):
+    R = ofr.rhs(bl, [u], prm)[0]
+    rng = np.random.default_rng(0)
+    up = u * (1 + 2.0 ** -53 * rng.uniform(-1, 1, size=u.shape))
+    f_state = rel_err([ofr.rhs(bl, [up], prm)[0]], [R])
+    b = bl[0]
+    eps = max((p + 1) ** 3, (q + 1) ** 3) * 2.0 ** -53
+    bp = dataclasses.replace(b, S=b.S * (1 + eps * rng.uniform(-1, 1, size=b.S.shape)),
+                             J=b.J * (1 + eps * rng.uniform(-1, 1, size=b.J.shape)),
+                             snorm=b.snorm * (1 + eps * rng.uniform(-1, 1, size=b.snorm.shape)))
+    f_metric = rel_err([ofr.rhs([bp], [u], prm)[0]], [R])
+    return f_state[0] + f_metric[0], f_state[1] + f_metric[1], R
+
+
+CASES = [
+    # (q, p, system, riemann, beta, metric, state)
+    (1, 1, 0, 0, 0.5, "conservative", "random"),
+    (2, 2, 0, 0, 0.5, "conservative", "random"),
+    (2, 3, 0, 1, 0.5, "conservative", "tgv"),
+    (3, 3, 1, 0, 0.5, "conservative", "random"),
+    (3, 3, 1, 1, 0.5, "conservative", "tgv"),
+    (2, 4, 1, 0, 0.3, "conservative", "random"),
+    (4, 4, 0, 1, 0.5, "conservative", "random"),
+    (3, 4, 1, 0, -0.5, "conservative", "random"),
+    (3, 3, 0, 0, 0.5, "cross", "random"),
+    (4, 4, 1, 0, 0.5, "cross", "random"),
+]
+
+
+@pytest.mark.parametrize("q,p,system,riemann,beta,metric,state", CASES)
+def test_curved_rhs_fp64(q, p, system, riemann, beta, metric, state):
+    from paper_2408_16509_amd import frmi
+    m = _mesh(q)
+    bl = omesh.build(m, p, metric)
+    u = _state(bl[0], state)
+    prm = ofr.Params(system=system, riemann=riemann, ldg_beta=beta)
+    floor, pv_floor, Ro = _floor(bl, u, prm, q, p)
+    Rg = _gpu_rhs(m, u, system=system, order=p, riemann=riemann, ldg_beta=beta,
+                  hex_metric=frmi.FR_METRIC_CONSERVATIVE if metric == "conservative" else frmi.FR_METRIC_CROSS)
+    g, pv = rel_err([Rg], [Ro])
+    tol = max(1e-12, 4 * floor)
+    pv_tol = np.maximum(1e-12, 4 * pv_floor)
+    print(f"q={q} p={p} sys={system} {metric} {state}: rel L2 {g:.2e} (tol {tol:.1e}) per-var "
+          f"{np.array2string(pv, precision=2)} (tol {np.array2string(pv_tol, precision=2)})", flush=True)
+    assert g <= tol
+    assert np.all(pv <= pv_tol)
+
+
+@pytest.mark.parametrize("q,p", [(2, 2), (3, 3), (4, 4)])
+def test_curved_free_stream(q, p):
+    from paper_2408_16509_amd import frmi
+    m = _mesh(q)
+    out = {}
+    for metric, code in (("conservative", frmi.FR_METRIC_CONSERVATIVE), ("cross", frmi.FR_METRIC_CROSS)):
+        bl = omesh.build(m, p, metric)
+        u = _state(bl[0], "uniform")
+        for system in (0, 1):
+            Ro = ofr.rhs(bl, [u], ofr.Params(system=system))[0]
+            Rg = _gpu_rhs(m, u, system=system, order=p, hex_metric=code)
+            out[(metric, system)] = (np.abs(Rg).max(), np.abs(Ro).max(), np.abs(Rg - Ro).max())
+    print(f"q={q} p={p}: " + ", ".join(f"{k}: gpu {v[0]:.1e} oracle {v[1]:.1e}" for k, v in out.items()), flush=True)
+    for system in (0, 1):
+        assert out[("conservative", system)][0] <= 1e-10
+        g, o, d = out[("cross", system)]
+        if 2 * (q - 1) > p:
+            assert g > 1e-4 and d <= 1e-10 * o
+        else:
+            assert g <= 1e-10
+
+
+@pytest.mark.parametrize("p,system", [(2, 0), (3, 1), (4, 0)])
+def test_q1_curved_equals_straight_path(p, system):
+    m = _mesh(1)
+    straight = inputs.Mesh(m.xyz, m.etype, m.enodes, m.period)
+    bl = omesh.build(straight, p)
+    u = _state(bl[0], "random")
+    Rc = _gpu_rhs(m, u, system=system, order=p)
+    Rs = _gpu_rhs(straight, u, system=system, order=p)
+    g = rel_err([Rc], [Rs])[0]
+    print(f"p={p}: curved (q=1) vs straight path {g:.2e}", flush=True)
+    assert g <= 1e-12
+
+
+@pytest.mark.parametrize("q,p,system", [(2, 3, 0), (3, 3, 1)])
+def test_curved_fp32_form(q, p, system):
+    from paper_2408_16509_amd import frmi
+    m = _mesh(q)
+    bl = omesh.build(m, p)
+    u = _state(bl[0], "random")
+    Ro = ofr.rhs(bl, [u], ofr.Params(system=system))[0]
+    Rg = _gpu_rhs(m, u, system=system, order=p, precision=frmi.FR_FP32, u_ref=(1.0, 0.0, 0.0, 0.0, 2.5))
+    g = rel_err([Rg], [Ro])[0]
+    print(f"FP32 form q={q} p={p}: {g:.2e}", flush=True)
+    assert g <= 1e-5
+
+
+def test_curved_rk4_steps():
+    from paper_2408_16509_amd import frmi
+    m = _mesh(3)
+    bl = omesh.build(m, 3)
+    u = _state(bl[0], "tgv")
+    prm = ofr.Params(system=1)
+    uo = ork.rk4(lambda s: ofr.rhs(bl, s, prm), [u.copy()], 2e-3, 3)
+    ctx = frmi.Context(m, system=1, order=3)
+    ug = ctx.pack64(u.ravel())
+    ctx.rk_step(ug, 2e-3, 3)
+    got = ctx.unpack64(ug).cpu().numpy().reshape(u.shape)
+    ctx.close()
+    err = np.linalg.norm(got - uo[0]) / np.linalg.norm(uo[0] - u)
+    print(f"3 RK4 steps, NS TGV on q=3 p=3: {err:.2e} of the state change", flush=True)
+    assert err <= 1e-10

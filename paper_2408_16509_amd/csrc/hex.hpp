@@ -767,14 +767,23 @@ __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_div_ns(
   __syncthreads();
   const T gm1 = gamma - T(1);
   T iJ[N1], f3[N1][5];
-#pragma unroll
-  for (int k = 0; k < N1; ++k) {
+  // the state and gradient of the column's next point are loaded while the current
+  // point's fluxes are formed (two buffers), so a wave keeps loads in flight
+  T ub[2][5], gb[2][15];
+  auto load_pt = [&](int k, T* uu, T* gg) {
     const int pt = ci + N1 * (cj + N1 * k);
-    T uu[5], gg[15];
 #pragma unroll
     for (int v = 0; v < 5; ++v) uu[v] = u[((int64_t)pt * 5 + v) * E + e];
 #pragma unroll
     for (int q = 0; q < 15; ++q) gg[q] = grad[((int64_t)pt * 15 + q) * E + e];
+  };
+  load_pt(0, ub[0], gb[0]);
+#pragma unroll
+  for (int k = 0; k < N1; ++k) {
+    const int pt = ci + N1 * (cj + N1 * k);
+    if (k + 1 < N1) load_pt(k + 1, ub[(k + 1) & 1], gb[(k + 1) & 1]);
+    const T* uu = ub[k & 1];
+    const T* gg = gb[k & 1];
     T g[3][3];
     if constexpr (CUR) {
       iJ[k] = -cm_rjac<T, NSP>(cm, E, e, pt);
@@ -804,12 +813,28 @@ __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_div_ns(
     F4[v] = fc[(((int64_t)4 * NF + q2) * 5 + v) * E + e];
     F5[v] = fc[(((int64_t)5 * NF + q2) * 5 + v) * E + e];
   }
+  // common fluxes at the xi_1 and xi_2 ends of the lines through point k, all five
+  // variables at once; the next point's are loaded while the current one is summed
+  T fb[2][4][5];
+  auto load_ends = [&](int k, T (&F)[4][5]) {
+    const int q0 = cj + N1 * k, q1 = ci + N1 * k;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      F[0][v] = fc[(((int64_t)0 * NF + q0) * 5 + v) * E + e];
+      F[1][v] = fc[(((int64_t)1 * NF + q0) * 5 + v) * E + e];
+      F[2][v] = fc[(((int64_t)2 * NF + q1) * 5 + v) * E + e];
+      F[3][v] = fc[(((int64_t)3 * NF + q1) * 5 + v) * E + e];
+    }
+  };
+  load_ends(0, fb[0]);
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < N1; ++k) {
     const int pt = ci + N1 * (cj + N1 * k);
-    // line coordinates of this point in each direction: (position a, face-local q)
-    const int a0 = ci, q0 = cj + N1 * k, a1 = cj, q1 = ci + N1 * k;
+    if (k + 1 < N1) load_ends(k + 1, fb[(k + 1) & 1]);
+    const T (&F)[4][5] = fb[k & 1];
+    // line coordinates of this point in each direction: position a
+    const int a0 = ci, a1 = cj;
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
       T acc = K.cp[k] * F5[v] + K.cm[k] * F4[v];
@@ -819,8 +844,8 @@ __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_div_ns(
         acc += K.Dh[a1][b] * FT[((1 * 5 + v) * NSP + (ci + N1 * (b + N1 * k))) * NE + el];
         acc += K.Dh[k][b] * f3[b][v];
       }
-      acc += K.cp[a0] * fc[(((int64_t)1 * NF + q0) * 5 + v) * E + e] + K.cm[a0] * fc[(((int64_t)0 * NF + q0) * 5 + v) * E + e];
-      acc += K.cp[a1] * fc[(((int64_t)3 * NF + q1) * 5 + v) * E + e] + K.cm[a1] * fc[(((int64_t)2 * NF + q1) * 5 + v) * E + e];
+      acc += K.cp[a0] * F[1][v] + K.cm[a0] * F[0][v];
+      acc += K.cp[a1] * F[3][v] + K.cm[a1] * F[2][v];
       if (e < n) r[((int64_t)pt * 5 + v) * E + e] = acc * iJ[k];
     }
   }
@@ -842,14 +867,24 @@ __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_div_ns_lds(
   __syncthreads();
   const T gm1 = gamma - T(1);
   T iJ[N1];
-#pragma unroll
-  for (int k = 0; k < N1; ++k) {
+  // as in hex_div_ns: the next point's state and gradient load while the current
+  // point's fluxes are formed (this variant is held to 1-2 waves per SIMD by its LDS,
+  // so registers are not what limits it)
+  T ub[2][5], gb[2][15];
+  auto load_pt = [&](int k, T* uu, T* gg) {
     const int pt = ci + N1 * (cj + N1 * k);
-    T uu[5], gg[15];
 #pragma unroll
     for (int v = 0; v < 5; ++v) uu[v] = u[((int64_t)pt * 5 + v) * E + e];
 #pragma unroll
     for (int q = 0; q < 15; ++q) gg[q] = grad[((int64_t)pt * 15 + q) * E + e];
+  };
+  load_pt(0, ub[0], gb[0]);
+#pragma unroll
+  for (int k = 0; k < N1; ++k) {
+    const int pt = ci + N1 * (cj + N1 * k);
+    if (k + 1 < N1) load_pt(k + 1, ub[(k + 1) & 1], gb[(k + 1) & 1]);
+    const T* uu = ub[k & 1];
+    const T* gg = gb[k & 1];
     T g[3][3];
     if constexpr (CUR) {
       iJ[k] = -cm_rjac<T, NSP>(cm, E, e, pt);
@@ -868,12 +903,34 @@ __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_div_ns_lds(
       for (int v = 0; v < 5; ++v) FT[((d * 5 + v) * NSP + pt) * NE + el] = f[v] - fv[v];
     }
   }
+  // common fluxes at the six line ends through point k (the xi_3 ends are the same
+  // for every k), all variables at once, the next point's loaded during the sums
+  const int q2 = ci + N1 * cj;
+  T F4[5], F5[5], fb[2][4][5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    F4[v] = fc[(((int64_t)4 * NF + q2) * 5 + v) * E + e];
+    F5[v] = fc[(((int64_t)5 * NF + q2) * 5 + v) * E + e];
+  }
+  auto load_ends = [&](int k, T (&F)[4][5]) {
+    const int q0 = cj + N1 * k, q1 = ci + N1 * k;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      F[0][v] = fc[(((int64_t)0 * NF + q0) * 5 + v) * E + e];
+      F[1][v] = fc[(((int64_t)1 * NF + q0) * 5 + v) * E + e];
+      F[2][v] = fc[(((int64_t)2 * NF + q1) * 5 + v) * E + e];
+      F[3][v] = fc[(((int64_t)3 * NF + q1) * 5 + v) * E + e];
+    }
+  };
+  load_ends(0, fb[0]);
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < N1; ++k) {
     const int pt = ci + N1 * (cj + N1 * k);
-    // line coordinates of this point in each direction: (position a, face-local q)
-    const int a0 = ci, q0 = cj + N1 * k, a1 = cj, q1 = ci + N1 * k, a2 = k, q2 = ci + N1 * cj;
+    if (k + 1 < N1) load_ends(k + 1, fb[(k + 1) & 1]);
+    const T (&F)[4][5] = fb[k & 1];
+    // line coordinates of this point in each direction: position a
+    const int a0 = ci, a1 = cj, a2 = k;
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
       T acc = T(0);
@@ -883,9 +940,9 @@ __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_div_ns_lds(
         acc += K.Dh[a1][b] * FT[((1 * 5 + v) * NSP + (ci + N1 * (b + N1 * k))) * NE + el];
         acc += K.Dh[a2][b] * FT[((2 * 5 + v) * NSP + (ci + N1 * (cj + N1 * b))) * NE + el];
       }
-      acc += K.cp[a0] * fc[(((int64_t)1 * NF + q0) * 5 + v) * E + e] + K.cm[a0] * fc[(((int64_t)0 * NF + q0) * 5 + v) * E + e];
-      acc += K.cp[a1] * fc[(((int64_t)3 * NF + q1) * 5 + v) * E + e] + K.cm[a1] * fc[(((int64_t)2 * NF + q1) * 5 + v) * E + e];
-      acc += K.cp[a2] * fc[(((int64_t)5 * NF + q2) * 5 + v) * E + e] + K.cm[a2] * fc[(((int64_t)4 * NF + q2) * 5 + v) * E + e];
+      acc += K.cp[a0] * F[1][v] + K.cm[a0] * F[0][v];
+      acc += K.cp[a1] * F[3][v] + K.cm[a1] * F[2][v];
+      acc += K.cp[a2] * F5[v] + K.cm[a2] * F4[v];
       if (e < n) r[((int64_t)pt * 5 + v) * E + e] = acc * iJ[k];
     }
   }

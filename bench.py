@@ -486,8 +486,8 @@ def main():
                     help="only run a plain 1 GiB device-to-device copy 5 times (scale for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the multi-GPU path is a design, not built)", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
+              "(how the path would shard over GPUs is described, not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

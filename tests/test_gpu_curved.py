@@ -200,3 +200,44 @@ def test_curved_filtered_rk_step():
     err = np.linalg.norm(got - uo) / np.linalg.norm(uo - u0)
     print(f"filtered RK4 step on a curved mesh: {err:.2e} of the increment", flush=True)
     assert err <= 1e-10 and ok
+
+
+def test_curved_adaptive_fp64():
+    """Adaptive stepping (embedded pair and controller) on a curved mesh: the oracle's
+    sequence of accepted and rejected steps, its final time and state."""
+    from oracle import rk_adaptive as ra
+    from paper_2408_16509_amd import frmi
+    m = _mesh(2, n=(3, 3, 3))
+    bl = omesh.build(m, 3)
+    x = bl[0].xsol
+    u = np.moveaxis(inputs.tgv(x[..., 0], x[..., 1], x[..., 2], mach=0.3), 0, 1).copy()
+    uo, so = ra.integrate(lambda s: ofr.rhs(bl, s, ofr.Params()), [u], 0.2, 0.05, ra.Controller(atol=1e-6, rtol=1e-6))
+    ctx = frmi.Context(m, system=0, order=3)
+    ug = ctx.pack64(u.ravel())
+    sg = ctx.rk_adaptive(ug, 0.2, 0.05, atol=1e-6, rtol=1e-6)
+    got = ctx.unpack64(ug).cpu().numpy().reshape(u.shape)
+    ctx.close()
+    err = np.linalg.norm(got - uo[0]) / np.linalg.norm(uo[0] - u)
+    print(f"curved adaptive: accepted {sg.accepted} (oracle {so.accepted}), rejected {sg.rejected} "
+          f"(oracle {so.rejected}), state {err:.2e}", flush=True)
+    assert (sg.accepted, sg.rejected) == (so.accepted, so.rejected) and sg.t == so.t == 0.2
+    assert abs(sg.dt_next - so.dt_next) <= 1e-9 * so.dt_next
+    assert err <= 1e-10
+
+
+def test_curved_full_size_fp64():
+    """The bench's curved workload at full size (32^3 cubically curved hexahedra, p = 3,
+    2.1 M points, Navier--Stokes TGV Ma 0.1), whole field against the oracle, in the
+    launch configuration the bench times (the oracle takes about a minute here)."""
+    m = inputs.curved_hex_box((32, 32, 32), q=3, amp=0.1)
+    bl = omesh.build(m, 3)
+    x = bl[0].xsol
+    u = np.moveaxis(inputs.tgv(x[..., 0], x[..., 1], x[..., 2], mach=0.1), 0, 1).copy()
+    prm = ofr.Params(system=1)
+    floor, pv_floor, Ro = _floor(bl, u, prm, 3, 3)
+    Rg = _gpu_rhs(m, u, system=1, order=3)
+    g, pv = rel_err([Rg], [Ro])
+    tol, pv_tol = max(1e-12, 4 * floor), np.maximum(1e-12, 4 * pv_floor)
+    print(f"32^3 q=3 p=3 NS TGV: rel L2 {g:.2e} (tol {tol:.1e}) per-var {np.array2string(pv, precision=2)} "
+          f"(tol {np.array2string(pv_tol, precision=2)})", flush=True)
+    assert g <= tol and np.all(pv <= pv_tol)

@@ -454,7 +454,7 @@ fr_status hex_rhs_p(fr_ctx c, DevBlock& b, const T* u, T* r) {
     c->prof_end(pk);
     constexpr int NE2 = DivNsCfg<T, P>::NE;
     pk = c->prof_begin(("hex_div_ns" + sfx).c_str());
-    if constexpr (sizeof(T) == 4 && P <= 3)
+    if constexpr (P <= 3)
       hex_div_ns<T, DEV, P, NE2, CUR><<<(unsigned)(b.E / NE2), NE2 * N1 * N1, 0, c->stream>>>(
           u, grad, fc, geo, cm, r, b.E, b.n, K, (T)p.gamma, (T)p.mu, (T)p.prandtl, R);
     else

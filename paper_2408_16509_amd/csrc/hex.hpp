@@ -851,8 +851,8 @@ __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_div_ns(
   }
 }
 
-// Variant with all three directions' f~ in LDS (the register budget of FP64 and of
-// p = 4 does not hold f~_3 of a whole column).
+// Variant with all three directions' f~ in LDS (at p = 4 the register budget does not
+// hold f~_3 of a whole column).
 template <typename T, bool DEV, int P, int NE, bool CUR = false>
 __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_div_ns_lds(
     const T* __restrict__ u, const T* __restrict__ grad, const T* __restrict__ fc, const T* __restrict__ geo,

@@ -152,7 +152,12 @@ def _ptr(t):
 
 
 class Context:
-    """An FR context on one mesh.  `stream` defaults to torch's current stream."""
+    """An FR context on one mesh.  `stream` defaults to torch's current stream.
+
+    A mesh with `ho_enodes` set (curved hexahedra of geometry order `mesh.geo_order`,
+    tensor-order nodes) is set up through fr_setup_mesh_curved, with the metric chosen
+    by the `hex_metric` parameter (FR_METRIC_CONSERVATIVE or FR_METRIC_CROSS); any
+    other mesh through fr_setup_mesh.  Keyword parameters are fr_params fields."""
 
     def __init__(self, mesh, stream=None, **params):
         import torch

@@ -581,6 +581,21 @@ def main():
             out["forms"][f]["kernels_ms_per_step"] = {k: round(v[1] / 2, 4) for k, v in sorted(runs[f]["times"].items())}
             bpd = 80 if f.startswith("fp64") else 40
             out["forms"][f]["rhs_m0_fraction"] = round(4 * dof * bpd / (runs[f]["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+    if cfg.get("kind") == "curved":
+        # a uniform stream on the same curved mesh, both metrics (FP64): the conservative
+        # metric keeps it (R at rounding level), the cross-product metric does not once its
+        # degree exceeds the solution order (Sec. "Curved elements", Fig. fsp)
+        fs = {}
+        for name, code in (("conservative", frmi.FR_METRIC_CONSERVATIVE), ("cross", frmi.FR_METRIC_CROSS)):
+            ctx = frmi.Context(mesh, system=cfg["system"], order=cfg["order"], riemann=cfg["riemann"],
+                               hex_metric=code)
+            canon = np.empty((ctx.layout.canon_len // 5 // ctx.layout.n_sp[0], 5, ctx.layout.n_sp[0]))
+            canon[:, 0], canon[:, 1], canon[:, 2], canon[:, 3], canon[:, 4] = 1.2, 0.3, -0.2, 0.5, 2.5
+            r = ctx.new_native()
+            ctx.rhs(ctx.pack(canon.ravel()), r)
+            fs[name] = float(torch.max(torch.abs(ctx.unpack_rhs(r))).item())
+            ctx.close()
+        out["free_stream_max_abs_rhs"] = fs
     if not args.no_cpu_baseline and not cfg.get("oracle_ok", False):
         out["cpu_baseline"] = None
         out["cpu_baseline_note"] = ("the FP64 oracle on this workload takes minutes and tens of GB; "

@@ -6,10 +6,13 @@
  * transformed equation, then the four steps eq:disu, eq:comm_flux, second
  * eq:disu and eq:FRfinal) for the compressible Euler and Navier--Stokes
  * equations on periodic meshes of hexahedra (orders 1..4, Gauss--Legendre
- * points) and tetrahedra (order 4, the alpha-optimised points of Fig. mesh),
- * advances it with classical RK4 ("a suitable explicit time integration
- * scheme"), and applies the entropy-bounded modal filter of Sec. "Numerical
- * Stability" with an optional learned warm start of its per-element search.
+ * points; straight, with metric terms formed from the corners, or curved, with
+ * metric terms stored per point as in Sec. "Curved elements") and tetrahedra
+ * (order 4, the alpha-optimised points of Fig. mesh), advances it with classical
+ * RK4 ("a suitable explicit time integration scheme") or with an adaptive
+ * embedded pair (Sec. "Adaptive time stepping"), and applies the entropy-bounded
+ * modal filter of Sec. "Numerical Stability" with an optional learned warm start
+ * of its per-element search.
  * All device work runs in hand-written HIP kernels for gfx950.
  *
  * Conventions

@@ -510,7 +510,7 @@ fr_status tet_rhs(fr_ctx c, DevBlock& b, const T* u, T* r) {
     const T* ogT = (const T*)c->tet_ogT;
     pk = c->prof_begin(("tet_grad" + sfx).c_str());
 #define FR_TET_GRAD(BF, FCX)                                                                                   \
-  tet_grad_mma<T, DEV, BF, FCX><<<div_grid, TGR_NT, 0, c->stream>>>(u, geo, C, O, ogT, ogH, ogL, (T*)b.grad, fcb, \
+  tet_grad_mma<T, DEV, BF, FCX><<<div_grid, tgr_nt<T>(), 0, c->stream>>>(u, geo, C, O, ogT, ogH, ogL, (T*)b.grad, fcb, \
                                                                     b.E, b.n, beta, sm, gam, mu, pr, tau,       \
                                                                     p.riemann, R)
     if (bf3) {

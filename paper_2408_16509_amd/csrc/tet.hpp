@@ -196,9 +196,12 @@ constexpr int TET_KA = 108, TET_KB = 60, TET_KP = TET_KA + TET_KB, TET_MP = 48;
 constexpr int TET_KA16 = 112, TET_KB16 = 64, TET_KP16 = TET_KA16 + TET_KB16;
 // 16 elements per block.  The divergence runs three waves, one point tile each, that
 // also share the gathers (3.0 -> 2.65 ms per FP32 launch on the mixed workload against
-// five waves of which two only gather); the gradient keeps five (its three-wave
-// variant measured 12 % slower in FP32 and 60 % in FP64).
-constexpr int TDIV_NE = 16, TDIV_NT = 3 * 64, TGR_NT = 5 * 64;
+// five waves of which two only gather).  The gradient gathers more (the common
+// solution at all 60 flux points): four waves in FP32 (three multiply; 2.95 -> 2.47
+// ms per launch against five), five in FP64 (four: 5.7 ms against 3.85).
+constexpr int TDIV_NE = 16, TDIV_NT = 3 * 64;
+template <typename T>
+constexpr int tgr_nt() { return sizeof(T) == 4 ? 4 * 64 : 5 * 64; }
 
 // Corrected divergence (eq:FRfinal) on the matrix cores: per block of 16 elements,
 // R^T = -(1/J) Op P with the panel P = [f~_0; f~_1; f~_2; F^C] (K x 5*16).  A block
@@ -329,13 +332,13 @@ __global__ void __launch_bounds__(TDIV_NT) tet_div(const T* __restrict__ u, cons
 constexpr int TGR_K = 96, TGR_M = 3 * TET_MP;
 
 template <typename T, bool DEV, bool BF3, bool FC>
-__global__ void __launch_bounds__(TGR_NT) __attribute__((amdgpu_waves_per_eu(4))) tet_grad_mma(const T* __restrict__ u, const T* __restrict__ geo, Conn C,
+__global__ void __launch_bounds__(tgr_nt<T>()) __attribute__((amdgpu_waves_per_eu(4))) tet_grad_mma(const T* __restrict__ u, const T* __restrict__ geo, Conn C,
                                                         TetDev<T> O, const T* __restrict__ ogT,
                                                         const tet_s4* __restrict__ ogH, const tet_s4* __restrict__ ogL,
                                                         T* __restrict__ grad, T* __restrict__ fc, int64_t E, int64_t n,
                                                         T beta, int side_mode, T gamma, T mu, T pr, T tau, int riemann,
                                                         RefState<T> R) {
-  constexpr int NE = TDIV_NE, NT = TGR_NT;
+  constexpr int NE = TDIV_NE, NT = tgr_nt<T>();
   __shared__ T PAN[TGR_K * 5 * NE];      // [k][v][el]: u at the 35 points, u^ at the 60 flux points, 0
   __shared__ T SJ[10 * NE];
   __shared__ uint8_t SIDE[FC ? TET_NFP * NE : 1];   // bit 0: element is the left side; bit 1: it forms the flux

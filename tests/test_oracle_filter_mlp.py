@@ -157,3 +157,72 @@ def test_training_reduces_loss():
     w, hist = mlp.train(w0, X, y, steps=400)
     l1 = np.mean((mlp.forward(w, X) - y) ** 2)
     assert l1 < 0.2 * l0
+
+
+def test_smin_neighbourhood_takes_a_neighbours_lower_entropy():
+    """4 x 1 x 1 periodic cells with constant states rho = 1, p = (3, 1, 4, 2): s = p.  Each
+    cell's face neighbours are the two x-adjacent cells (the y and z faces pair a cell with
+    itself), so the bounds are min(s_e, s_e-1, s_e+1) = (1, 1, 1, 2): cells 0 and 2 take
+    their bound from a neighbour."""
+    m = inputs.hex_box((4, 1, 1))
+    for p in (2, 3):
+        bl = mesh.build(m, p)
+        b = bl[0]
+        order = np.argsort(b.X[:, :, 0].mean(axis=1))          # cells by x
+        pres = np.empty(4)
+        pres[order] = [3.0, 1.0, 4.0, 2.0]
+        u = np.zeros((4, 5, b.ops.nsp))
+        u[:, 0] = 1.0
+        u[:, 4] = (pres / 0.4)[:, None]
+        smin = ef.smin_neighbourhood(bl, [u], ef.FilterParams())[0]
+        np.testing.assert_allclose(smin[order], [1.0, 1.0, 1.0, 2.0], rtol=1e-14)
+
+
+def test_features_closed_form_hex():
+    """A p = 3 hexahedron at rest with uniform pressure pb and density rb + a psi(xi_1), psi
+    the orthonormal degree-(1,0,0) Legendre mode sqrt(3/8) xi_1 (orthonormal on [-1, 1]^3,
+    so the mean mode's coefficient is rb sqrt(8)):
+      f0 = log10(a^2 / (8 rb^2)), every other shell energy of rho, E and p is zero (-30, the floor);
+      f9 = -a sqrt(3/8) / rb (minimum density on the face xi_1 = -1), f10 = 0, f13 = a sqrt(3/8) / rb;
+      the entropy p rho^-gamma is lowest on the face xi_1 = +1 (s_+) and next lowest on the
+      solution-point plane nearest to it (s_1); with the bound s_min set so that
+      s_min (1 - eps_s) lies half-way between them, exactly the (p+1)^2 flux points of that face
+      violate: f12 = 16 / 160, f11 = (s_+ - s_min) / s_min, f14 = log10(pb rb^-gamma / s_min);
+      f15 = 0.  A second element moving uniformly at v_x = V: f15 = V / sqrt(gamma pb / rb),
+      and zero-shell features everywhere else."""
+    p, g = 3, 1.4
+    ops = elements.ops_for(0, p)
+
+    class B:
+        pass
+    b = B()
+    b.ops, b.etype = ops, 0
+    rb, a, pb, V = 1.3, 0.05, 0.8, 0.4
+    xi1 = ops.sol_pts[:, 0]
+    psi = np.sqrt(3.0 / 8.0) * xi1
+    u = np.zeros((2, 5, ops.nsp))
+    u[0, 0] = rb + a * psi
+    u[0, 4] = pb / (g - 1)
+    u[1, 0] = rb
+    u[1, 1] = rb * V
+    u[1, 4] = pb / (g - 1) + 0.5 * rb * V * V
+    x, _ = polys.gauss_legendre(p + 1)
+    s_plus = pb * (rb + a * np.sqrt(3.0 / 8.0)) ** -g
+    s_one = pb * (rb + a * np.sqrt(3.0 / 8.0) * x.max()) ** -g
+    fp = ef.FilterParams()
+    smin0 = 0.5 * (s_plus + s_one) / (1 - fp.eps_s)
+    smin = np.array([smin0, 0.5 * pb * rb ** -g])
+    F = ef.features(b, u, smin, fp)
+    want = np.full(16, -30.0)
+    want[0] = np.log10(a * a / (8 * rb * rb))
+    want[9], want[10], want[13] = -a * np.sqrt(3.0 / 8.0) / rb, 0.0, a * np.sqrt(3.0 / 8.0) / rb
+    want[11] = (s_plus - smin0) / smin0
+    want[12] = (p + 1) ** 2 / (ops.nsp + ops.nfp)
+    want[14] = np.log10(pb * rb ** -g / smin0)
+    want[15] = 0.0
+    np.testing.assert_allclose(F[0], want, rtol=1e-9, atol=1e-12)
+    want1 = np.full(16, -30.0)
+    want1[9:14] = [0.0, 0.0, (pb * rb ** -g - smin[1]) / smin[1], 0.0, 0.0]
+    want1[14] = np.log10(pb * rb ** -g / smin[1])
+    want1[15] = V / np.sqrt(g * pb / rb)
+    np.testing.assert_allclose(F[1], want1, rtol=1e-9, atol=1e-12)

@@ -284,6 +284,22 @@ fr_status fr_mlp_forward(fr_ctx ctx, const float* x_dev, int64_t n, float* y_dev
 fr_status fr_mlp_grad(fr_ctx ctx, const float* x_dev, const float* y_dev, int64_t n,
                       float* grad_dev, float* loss_dev);
 
+/* For callers that cannot allocate device memory during the call (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): fr_mlp_grad without any
+ * allocation.  Same arguments, kernels and result as fr_mlp_grad (x_dev [n][16] raw
+ * features, y_dev [n] targets, grad_dev [5313] and loss_dev [1] device outputs), but the
+ * per-sample forward/backward quantities live in a fixed device array of the library
+ * (FR_MLP_STATIC_MAX_BATCH x 274 floats, about 4.5 MB per GPU, held until the process
+ * ends) instead of context workspace grown on demand.  Every call on a GPU shares that
+ * GPU's array, so calls that overlap on one GPU (other streams, other contexts, other
+ * threads) race; each call writes every entry it later reads, so nothing carries over
+ * between calls.  Errors: FR_ERR_ARG (NULL, n outside 1..FR_MLP_STATIC_MAX_BATCH),
+ * FR_ERR_STATE (weights not set), FR_ERR_DEVICE (the array's address could not be taken
+ * at setup, or a launch failed). */
+#define FR_MLP_STATIC_MAX_BATCH 4096
+fr_status fr_mlp_grad_static(fr_ctx ctx, const float* x_dev, const float* y_dev, int64_t n,
+                             float* grad_dev, float* loss_dev);
+
 /* Adam training on (x, y) pairs (device): n_steps minibatches of `batch` drawn by
  * the host-side permutation perm_dev [n_steps * batch] (int32 row ids).  lr,
  * beta1, beta2, eps as in Adam.  loss_hist_dev [n_steps] (device, or NULL).   */

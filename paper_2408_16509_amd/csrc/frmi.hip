@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -103,6 +104,7 @@ struct fr_ctx_s {
   int32_t* m_idx = nullptr;
   int m_batch_cap = 0;
   bool mlp_ready = false;
+  float* static_scratch = nullptr;  // this device's copy of the library's fixed scratch array
   // tetrahedral operators on the device (arithmetic type of the context)
   void* tet_opT = nullptr;    // [TET_KP][TET_MP] transposed divergence operator
   void* tet_ogT = nullptr;    // [TGR_K][TGR_M] transposed stacked gradient operator
@@ -144,6 +146,38 @@ struct fr_ctx_s {
     prof_names.clear();
   }
 };
+
+// Fixed device scratch of fr_mlp_grad_static: per-sample quantities (MLP_SS floats each)
+// of up to FR_MLP_STATIC_MAX_BATCH samples, then their squared errors.  Each GPU holds its
+// own copy; host code uses only the device address taken once per device at setup.
+constexpr int64_t kStaticScratchFloats = (int64_t)FR_MLP_STATIC_MAX_BATCH * (MLP_SS + 1);
+static __device__ __align__(256) float scratch[kStaticScratchFloats];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_addr[kMaxDevices] = {};
+bool g_scratch_done[kMaxDevices] = {};
+
+// The current device's address of `scratch` (looked up once per device), or nullptr.
+float* static_scratch_address() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_done[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) {
+      (void)hipGetLastError();
+      ptr = nullptr;
+    }
+    g_scratch_addr[dev] = (float*)ptr;
+    g_scratch_done[dev] = true;
+  }
+  return g_scratch_addr[dev];
+}
+
+}  // namespace
 
 namespace {
 
@@ -974,6 +1008,7 @@ fr_status setup_impl(const fr_params* p, int64_t n_vert, const double* xyz, cons
   if (!c) return fail(nullptr, FR_ERR_ALLOC, "context allocation");
   c->prm = *p;
   c->stream = (hipStream_t)stream;
+  c->static_scratch = static_scratch_address();
   int code = 0;
   std::string msg;
   try {
@@ -1694,6 +1729,20 @@ fr_status fr_mlp_grad(fr_ctx c, const float* x, const float* y, int64_t n, float
   mlp_fwd_bwd<<<(unsigned)((n + 255) / 256), 256, 0, c->stream>>>(c->m_w, c->m_scale, x, y, nullptr, (int)n,
                                                                    c->m_scratch, c->m_sqerr);
   mlp_grad_reduce<<<(MLP_NP + 1 + 255) / 256, 256, 0, c->stream>>>(c->m_scratch, (int)n, c->m_sqerr, grad, loss);
+  HIP_TRY(c, hipGetLastError());
+  return FR_OK;
+}
+
+fr_status fr_mlp_grad_static(fr_ctx c, const float* x, const float* y, int64_t n, float* grad, float* loss) {
+  if (!c || !x || !y || !grad || !loss) return fail(c, FR_ERR_ARG, "NULL argument");
+  if (n <= 0 || n > FR_MLP_STATIC_MAX_BATCH)
+    return fail(c, FR_ERR_ARG, "batch size must be in 1..FR_MLP_STATIC_MAX_BATCH (4096)");
+  if (!c->mlp_ready) return fail(c, FR_ERR_STATE, "MLP weights not set");
+  if (!c->static_scratch) return fail(c, FR_ERR_DEVICE, "address of the static scratch array not available");
+  float* S = c->static_scratch;
+  float* sq = S + (int64_t)FR_MLP_STATIC_MAX_BATCH * MLP_SS;
+  mlp_fwd_bwd<<<(unsigned)((n + 255) / 256), 256, 0, c->stream>>>(c->m_w, c->m_scale, x, y, nullptr, (int)n, S, sq);
+  mlp_grad_reduce<<<(MLP_NP + 1 + 255) / 256, 256, 0, c->stream>>>(S, (int)n, sq, grad, loss);
   HIP_TRY(c, hipGetLastError());
   return FR_OK;
 }

@@ -20,6 +20,9 @@ FR_RUSANOV, FR_HLLC = 0, 1
 FR_FP64, FR_FP32, FR_FP32_BF16X3 = 0, 1, 2
 FR_HEX, FR_TET = 0, 1
 FR_METRIC_CONSERVATIVE, FR_METRIC_CROSS = 0, 1
+(FR_OK, FR_ERR_ARG, FR_ERR_MESH, FR_ERR_ALLOC, FR_ERR_DEVICE, FR_ERR_NONFINITE, FR_ERR_STATE,
+ FR_ERR_UNSUPPORTED) = range(8)
+FR_MLP_STATIC_MAX_BATCH = 4096       # batch limit of fr_mlp_grad_static
 STATUS = {0: "FR_OK", 1: "FR_ERR_ARG", 2: "FR_ERR_MESH", 3: "FR_ERR_ALLOC", 4: "FR_ERR_DEVICE",
           5: "FR_ERR_NONFINITE", 6: "FR_ERR_STATE", 7: "FR_ERR_UNSUPPORTED"}
 
@@ -69,7 +72,7 @@ EXPORTS = [
     "fr_default_params", "fr_setup_mesh", "fr_setup_mesh_curved", "fr_layout", "fr_sol_points", "fr_pack", "fr_unpack",
     "fr_pack64", "fr_unpack64", "fr_unpack_rhs",
     "fr_rhs", "fr_rk_step", "fr_default_adaptive_params", "fr_rk_adaptive", "fr_filter", "fr_mlp_set_weights", "fr_mlp_get_weights",
-    "fr_mlp_features", "fr_mlp_collect", "fr_mlp_forward", "fr_mlp_grad", "fr_mlp_train", "fr_check", "fr_sync",
+    "fr_mlp_features", "fr_mlp_collect", "fr_mlp_forward", "fr_mlp_grad", "fr_mlp_grad_static", "fr_mlp_train", "fr_check", "fr_sync",
     "fr_profile", "fr_profile_read",
     "fr_destroy", "fr_last_error",
 ]
@@ -103,6 +106,7 @@ def load():
         "fr_mlp_collect": (i32, [vp, vp, dbl, i32, vp, vp, i64, P(i64)]),
         "fr_mlp_forward": (i32, [vp, vp, i64, vp]),
         "fr_mlp_grad": (i32, [vp, vp, vp, i64, vp, vp]),
+        "fr_mlp_grad_static": (i32, [vp, vp, vp, i64, vp, vp]),
         "fr_mlp_train": (i32, [vp, vp, vp, i64, vp, i32, i32, ctypes.c_float, ctypes.c_float,
                                ctypes.c_float, ctypes.c_float, vp]),
         "fr_check": (i32, [vp, vp]),
@@ -319,6 +323,11 @@ class Context:
         loss = torch.empty(1, dtype=torch.float32, device="cuda")
         self._check(lib().fr_mlp_grad(self.h, _ptr(x), _ptr(y), int(x.shape[0]), _ptr(g), _ptr(loss)))
         return g, loss
+
+    def mlp_grad_static(self, x, y, grad, loss):
+        """fr_mlp_grad_static: the caller brings the outputs (grad [5313], loss [1], FP32 device)."""
+        self._check(lib().fr_mlp_grad_static(self.h, _ptr(x), _ptr(y), int(x.shape[0]), _ptr(grad), _ptr(loss)))
+        return grad, loss
 
     def mlp_train(self, x, y, perm, n_steps, batch, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
         torch = self._torch

@@ -75,8 +75,11 @@ typedef struct {
                               variables du = u - u_ref (FP64 RK accumulation), or
                               FR_FP32_BF16X3: as FR_FP32 with the dense tetrahedral
                               operator products done as BF16x3 split products
-                              (hi*hi + hi*lo + lo*hi, FP32 accumulation; hexahedra
-                              unchanged)                                            */
+                              (hi*hi + hi*lo + lo*hi, FP32 accumulation on the bf16
+                              matrix cores); the hexahedra of a mixed mesh run the
+                              FP32 form (their 1-D line contractions have no dense
+                              product to split); FR_ERR_UNSUPPORTED for a mesh
+                              without tetrahedra                                     */
   int32_t elem_order;      /* native element order of each type block: 1 keeps the
                               input order, 2 renumbers along a Morton curve of the
                               element centroids (face neighbours share tiles and

@@ -40,6 +40,22 @@ def rel_err(a, b):
     return float(np.sqrt(num / den)), np.sqrt(pv_num / np.maximum(pv_den, 1e-300))
 
 
+def elem_max_err(a, b):
+    """Largest per-element error of a against reference b ([n][5][nsp] blocks): the L2 norm of
+    the element's error over its points and variables, divided by the larger of the element's
+    own reference norm and the root-mean-square element norm (so that elements whose residual
+    happens to be near zero are measured on the field's scale, not their own)."""
+    num = np.concatenate([np.sqrt(np.sum((x - y) ** 2, axis=(1, 2))) for x, y in zip(a, b)])
+    den = np.concatenate([np.sqrt(np.sum(y ** 2, axis=(1, 2))) for y in b])
+    rms = np.sqrt(np.mean(den ** 2))
+    return float(np.max(num / np.maximum(den, rms)))
+
+
+# Per-element bound, as a multiple of the global relative-L2 tolerance: rounding noise spread
+# over the field puts each element near the global figure; a wrong element stands far above.
+ELEM_FACTOR = 20.0
+
+
 def oracle_floor(mesh, order, u_blocks, prm, seed=0):
     """The FP64 rounding floor of the RHS for this input: relative L2 change of the
     oracle's RHS when every state value is perturbed by a relative U(-1,1) * 2^-53

@@ -92,6 +92,9 @@ def test_mesh_errors_are_reported_before_device_work():
                      (dict(precision=1, u_ref=(1.0, 0.5, 0.0, 0.0, 2.5)), "rest"), (dict(elem_order=3), "elem_order")):
         st, msg = setup(inputs.hex_box((1, 1, 1)), **kw)
         assert st == 1 and word in msg, (kw, msg)
+    # the BF16x3 split products exist for the dense tetrahedral operators only
+    st, msg = setup(inputs.hex_box((2, 2, 2)), precision=2, u_ref=(1.0, 0.0, 0.0, 0.0, 2.5))
+    assert st == 7 and "tetrahedra" in msg
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libfrmi.so not built")

@@ -30,7 +30,7 @@ from oracle import mesh as omesh
 from oracle import rk as ork
 from paper_2408_16509_amd import inputs
 
-from helpers import rel_err
+from helpers import ELEM_FACTOR, elem_max_err, rel_err
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -105,10 +105,13 @@ def test_curved_rhs_fp64(q, p, system, riemann, beta, metric, state):
     g, pv = rel_err([Rg], [Ro])
     tol = max(1e-12, 4 * floor)
     pv_tol = np.maximum(1e-12, 4 * pv_floor)
+    em = elem_max_err([Rg], [Ro])
     print(f"q={q} p={p} sys={system} {metric} {state}: rel L2 {g:.2e} (tol {tol:.1e}) per-var "
-          f"{np.array2string(pv, precision=2)} (tol {np.array2string(pv_tol, precision=2)})", flush=True)
+          f"{np.array2string(pv, precision=2)} (tol {np.array2string(pv_tol, precision=2)}) "
+          f"max per element {em:.2e}", flush=True)
     assert g <= tol
     assert np.all(pv <= pv_tol)
+    assert em <= ELEM_FACTOR * tol
 
 
 @pytest.mark.parametrize("q,p", [(2, 2), (3, 3), (4, 4)])

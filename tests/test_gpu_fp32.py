@@ -158,3 +158,46 @@ def test_fp32_rk4_solution_error():
     print(f"fp32 RK4 10 steps: increment rel {g:.2e} per-var {np.array2string(pv, precision=2)}; solution rel {sol:.2e}")
     assert sol <= 1e-9
     assert g <= 1e-5
+
+
+# Stated per-variable bounds (rho, rho u, rho v, rho w, E) of one RHS of the Ma 0.1 NS
+# Taylor--Green vortex on p = 4 tetrahedra (4^3 cells, +-10 % perturbed, 6 tets each)
+# against the FP64 oracle.  The energy residual cancels terms of size H0 = 250 (and the
+# density residual inherits it through the Rusanov dissipation), so the rounding of the
+# contractions is amplified there; BF16x3 keeps about 16 significant bits per product
+# term (relative 2^-16 ... 2^-17 against FP32's 2^-24), i.e. a few hundred times the
+# FP32 error.
+TGV_TET_BOUNDS = {
+    "fp32": np.array([2e-3, 2e-4, 2e-4, 2e-4, 2e-3]),
+    "bf16x3": np.array([0.5, 5e-2, 5e-2, 5e-2, 0.5]),
+}
+
+
+@pytest.mark.parametrize("form", ["fp32", "bf16x3"])
+def test_reduced_forms_tgv_tets_stated_bounds(form):
+    from paper_2408_16509_amd import frmi
+    mesh = inputs.kuhn_split(inputs.hex_box((4, 4, 4), perturb=0.1, perturb_seed=5), permute_seed=9)
+    bl = oracle_blocks(mesh, 4)
+    u = state_for(bl, "tgv")
+    prm = oracle_params(1, 0)
+    Ro = ofr.rhs(bl, u, prm)
+    prec = frmi.FR_FP32 if form == "fp32" else frmi.FR_FP32_BF16X3
+    ctx = frmi.Context(mesh, precision=prec, u_ref=UREF, system=1, order=4)
+    ug = ctx.pack(ctx.join_canon(u))
+    r = ctx.new_native()
+    ctx.rhs(ug, r)
+    Rg = _split(ctx.unpack_rhs(r).cpu().numpy(), u)
+    g, pv = rel_err(Rg, Ro)
+    # the solution after 5 RK4 steps: the FP64 accumulation keeps dt R's rounding small
+    uo = ork.rk4(lambda s: ofr.rhs(bl, s, prm), u, 2e-3, 5)
+    u64 = ctx.pack64(ctx.join_canon(u))
+    ctx.rk_step(u64, 2e-3, 5)
+    got = _split(ctx.unpack64(u64).cpu().numpy(), u)
+    ctx.close()
+    sol = rel_err(got, uo)[0]
+    print(f"{form} TGV tets: RHS global {g:.2e} per-var {np.array2string(pv, precision=2)}; "
+          f"solution after 5 steps {sol:.2e}", flush=True)
+    assert np.all(pv <= TGV_TET_BOUNDS[form])
+    # the state after 5 steps carries 5 dt |dR| / |u|: at |R| / |u| ~ 10 and the per-RHS
+    # bounds above that is below 5e-8 (FP32) and 1e-6 (BF16x3)
+    assert sol <= (5e-8 if form == "fp32" else 1e-6)

@@ -27,6 +27,8 @@ import pytest
 
 from paper_2408_16509_amd import inputs
 
+from helpers import ELEM_FACTOR, elem_max_err
+
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
@@ -77,19 +79,21 @@ def _errs(got, ref):
     g = np.linalg.norm(got - ref) / np.linalg.norm(ref)
     pv_abs = np.sqrt(np.sum((got - ref) ** 2, axis=(0, 2)))
     pv_ref = np.sqrt(np.sum(ref ** 2, axis=(0, 2)))
-    return g, pv_abs, pv_ref
+    return g, pv_abs, pv_ref, elem_max_err([got], [ref])
 
 
 def test_fullsize_hex48pert_p4_fp64_sampled(workload):
     mesh, (floor, elems, ref) = workload
     got = _rhs_at(mesh, elems)
     tol = max(1e-12, 4 * floor)
-    g, pv_abs, pv_ref = _errs(got, ref)
+    g, pv_abs, pv_ref, em = _errs(got, ref)
     nfloor = np.maximum(pv_ref, 1e-3 * np.linalg.norm(ref))
     print(f"48^3 p4 perturbed NS FP64, {len(elems)} sampled elements: rel L2 {g:.3e} (floor {floor:.2e}, "
-          f"tol {tol:.2e}) per-var {np.array2string(pv_abs / nfloor, precision=2)}", flush=True)
+          f"tol {tol:.2e}) per-var {np.array2string(pv_abs / nfloor, precision=2)} max per element {em:.2e}",
+          flush=True)
     assert g <= tol
     assert np.all(pv_abs <= 10 * tol * nfloor)
+    assert em <= ELEM_FACTOR * tol
 
 
 def test_fullsize_hex48pert_p4_fp32_sampled(workload):
@@ -97,9 +101,10 @@ def test_fullsize_hex48pert_p4_fp32_sampled(workload):
     mesh, (_, elems, ref) = workload
     p0 = 1.0 / (1.4 * MACH ** 2)
     got = _rhs_at(mesh, elems, precision=frmi.FR_FP32, u_ref=(1.0, 0.0, 0.0, 0.0, p0 / 0.4))
-    g, pv_abs, pv_ref = _errs(got, ref)
+    g, pv_abs, pv_ref, em = _errs(got, ref)
     pv = pv_abs / pv_ref
     print(f"48^3 p4 perturbed NS FP32 deviation form: rel L2 {g:.3e} per-var {np.array2string(pv, precision=2)}",
           flush=True)
     assert g <= 1e-2
     assert np.all(pv[1:4] <= 1e-3) and pv[0] <= 2e-2 and pv[4] <= 2e-2
+    assert em <= ELEM_FACTOR * 1e-2

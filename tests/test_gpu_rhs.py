@@ -5,7 +5,9 @@ where floor is the FP64 rounding floor of the RHS for that input (the oracle's
 response to a one-ulp relative perturbation of the state, see helpers);
 per variable, 10x that with the variable's norm floored at 1e-3 of the global norm
 (the low-Mach density and energy residuals are small differences of large fluxes,
-so their relative errors reflect the flux magnitudes, not the kernel).
+so their relative errors reflect the flux magnitudes, not the kernel); per element,
+the error norm over the element's points and variables relative to the larger of its
+own norm and the RMS element norm stays within 20x the global tolerance.
 """
 import numpy as np
 import pytest
@@ -14,7 +16,7 @@ from oracle import fr as ofr
 from oracle import rk as ork
 from paper_2408_16509_amd import inputs
 
-from helpers import oracle_blocks, oracle_floor, oracle_params, rel_err, state_for
+from helpers import ELEM_FACTOR, elem_max_err, oracle_blocks, oracle_floor, oracle_params, rel_err, state_for
 
 pytestmark = pytest.mark.gpu
 
@@ -51,9 +53,12 @@ def check(Rg, Ro, tol=1e-12, floor_=0.0):
     pv_abs = np.sqrt(sum(np.sum((x - y) ** 2, axis=(0, 2)) for x, y in zip(Rg, Ro)))
     pv_ref = np.sqrt(sum(np.sum(y ** 2, axis=(0, 2)) for y in Ro))
     floor = np.maximum(pv_ref, 1e-3 * glob)
-    print(f"tol {tol:.2e} global rel L2 {g:.3e}  per-var {np.array2string(pv_abs / floor, precision=2)}", flush=True)
+    em = elem_max_err(Rg, Ro)
+    print(f"tol {tol:.2e} global rel L2 {g:.3e}  per-var {np.array2string(pv_abs / floor, precision=2)}  "
+          f"max per element {em:.2e}", flush=True)
     assert g <= tol
     assert np.all(pv_abs <= 10 * tol * floor)
+    assert em <= ELEM_FACTOR * tol
 
 
 CASES = [

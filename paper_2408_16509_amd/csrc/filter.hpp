@@ -50,6 +50,47 @@ struct Dev32 {
   double ref[5];
 };
 
+// Where a detection pass takes its FP64 states from (called once per value of the
+// pass, in native index i = (pt * 5 + v) * E + e).  PlainSrc: the state itself.
+// RkStageSrc: the classical RK4 stage update fused into the pass, so the stage state
+// is formed in registers instead of being written and read back:
+//   stages 1..3 (mode 0 first, 1 middle): acc = (first ? u : acc) + b k, s = u + c k,
+//   optionally s64 = s (the FP64 form, whose right-hand side reads it) and
+//   s32 = (float)(s - ref) (the FP32 form's deviation); the pass checks s;
+//   last stage (mode 2): u = acc + b k (in place), s32 as above; the pass checks u.
+// stage() recomputes s for the candidates' FP64 copy (the same fused multiply-adds).
+struct PlainSrc {
+  const double* __restrict__ u;
+  __device__ __forceinline__ double operator()(int64_t i, int) const { return u[i]; }
+};
+template <typename KT>
+struct RkStageSrc {
+  double* u;
+  const KT* k;
+  double* acc;
+  double* s64;
+  float* s32;
+  double b, c;
+  int mode;
+  double ref[5];
+  __device__ __forceinline__ double stage(int64_t i) const { return fma(c, (double)k[i], u[i]); }
+  __device__ __forceinline__ double operator()(int64_t i, int v) const {
+    const double ki = (double)k[i];
+    if (mode == 2) {
+      const double un = fma(b, ki, acc[i]);
+      u[i] = un;
+      if (s32) s32[i] = (float)(un - ref[v]);
+      return un;
+    }
+    const double ui = u[i];
+    acc[i] = fma(b, ki, mode == 0 ? ui : acc[i]);
+    const double si = fma(c, ki, ui);
+    if (s64) s64[i] = si;
+    if (s32) s32[i] = (float)(si - ref[v]);
+    return si;
+  }
+};
+
 __device__ __forceinline__ double entropy_of(double rho, double p, double gamma) {
   return rho > 0 ? p * pow(rho, -gamma) : -INFINITY;
 }
@@ -107,9 +148,9 @@ struct HexTileCfg {
   static constexpr int N1 = P + 1, NE = P == 1 ? 64 : (P == 2 ? 32 : (P == 3 ? 16 : 8)), NT = NE * N1 * N1;
 };
 
-template <int P, typename Fn>
-__device__ __forceinline__ void hex_tile_checks(const double* __restrict__ u, double* U, int64_t E, int64_t e0,
-                                                const FiltK& K, Fn&& f) {
+template <int P, typename Src, typename Fn>
+__device__ __forceinline__ void hex_tile_checks(const Src& src, double* U, int64_t E, int64_t e0, const FiltK& K,
+                                                Fn&& f) {
   using C = HexTileCfg<P>;
   constexpr int N1 = C::N1, NE = C::NE, NSP = N1 * N1 * N1;
   const int el = threadIdx.x % NE, l = threadIdx.x / NE, c0 = l % N1, c1 = l / N1;
@@ -121,7 +162,7 @@ __device__ __forceinline__ void hex_tile_checks(const double* __restrict__ u, do
     double w[5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-      w[v] = u[((int64_t)pt * 5 + v) * E + e];
+      w[v] = src(((int64_t)pt * 5 + v) * E + e, v);
       U[(v * NSP + pt) * NE + el] = w[v];
       m[v] += K.lm[a] * w[v];
       pl[v] += K.lp[a] * w[v];
@@ -161,7 +202,7 @@ __global__ void __launch_bounds__(HexTileCfg<P>::NT) hex_sown(const double* __re
   __shared__ double U[5 * C::N1 * C::N1 * C::N1 * C::NE];
   const int64_t e0 = xcd_block() * C::NE, e = e0 + threadIdx.x % C::NE;
   double smin = INFINITY;
-  hex_tile_checks<P>(u, U, E, e0, K, [&](const double w[5]) {
+  hex_tile_checks<P>(PlainSrc{u}, U, E, e0, K, [&](const double w[5]) {
     const double p = (gamma - 1.0) * (w[4] - 0.5 * (w[1] * w[1] + w[2] * w[2] + w[3] * w[3]) / w[0]);
     smin = fmin(smin, entropy_of(w[0], p, gamma));
   });
@@ -443,6 +484,9 @@ __global__ void __launch_bounds__(64 * HexFW<P>::value) hex_filter(
 // positives untouched.  flag must be cleared before.
 // lsb = log(bound + dl |bound|) of the entropy bound, or -inf when that is <= 0
 // (then any state with positive density and pressure passes the entropy check).
+// The entropy part is screened like admissible_screened: log2 plo - gamma log2 rhi -
+// lsb / ln 2 in FP32 (within ~1e-5 of the exact value for the magnitudes admitted),
+// decided there unless it lies within 2^-8 of zero; only then the FP64 logarithms.
 __device__ __forceinline__ bool maybe_violates(const double w[5], double lsb, const FiltPrm& F) {
   constexpr double dl = 1e-10;
   const double rho = w[0];
@@ -451,24 +495,50 @@ __device__ __forceinline__ bool maybe_violates(const double w[5], double lsb, co
   const double m2 = (w[1] * w[1] + w[2] * w[2] + w[3] * w[3]) * (1.0 + dl);
   const double plo = (F.gamma - 1.0) * (w[4] - dl * fabs(w[4]) - 0.5 * m2 / rlo);
   if (!(plo >= F.eps_p)) return true;
+  if (lsb == -INFINITY) return false;
+  const float pf = (float)plo, rf = (float)rhi;
+  if (pf >= 1e-30f && pf <= 1e30f && rf >= 1e-30f && rf <= 1e30f && fabs(lsb) <= 60.0) {
+    const float L = log2f(pf) - (float)F.gamma * log2f(rf) - (float)(lsb * 1.4426950408889634);
+    if (L > 0.00390625f) return false;
+    if (L < -0.00390625f) return true;
+  }
   return !(log(plo) - F.gamma * log(rhi) >= lsb);
 }
 
-template <int P>
-__global__ void __launch_bounds__(HexTileCfg<P>::NT) hex_filter_detect(const double* __restrict__ u,
-                                                                      const double* __restrict__ smin_a, int64_t E,
-                                                                      int64_t n, FiltK K, FiltPrm F,
-                                                                      int32_t* __restrict__ flag) {
+// Detection of the candidates of the exact search: thread (el, column) flags its element
+// when one of its check points may violate a bound.  With an RK stage source the pass
+// also performs the stage update (every value of the tile once), and cand64 (if not
+// null) receives the FP64 stage state of the flagged elements from the tile in LDS.
+template <int P, typename Src>
+__global__ void __launch_bounds__(HexTileCfg<P>::NT) hex_filter_detect(Src src, const double* __restrict__ smin_a,
+                                                                      int64_t E, int64_t n, FiltK K, FiltPrm F,
+                                                                      int32_t* __restrict__ flag,
+                                                                      double* __restrict__ cand64) {
   using C = HexTileCfg<P>;
-  __shared__ double U[5 * C::N1 * C::N1 * C::N1 * C::NE];
-  const int64_t e0 = xcd_block() * C::NE, e = e0 + threadIdx.x % C::NE;
+  constexpr int NSP = C::N1 * C::N1 * C::N1;
+  __shared__ double U[5 * NSP * C::NE];
+  __shared__ int BAD[C::NE];
+  const int el = threadIdx.x % C::NE;
+  const int64_t e0 = xcd_block() * C::NE, e = e0 + el;
+  if (threadIdx.x < C::NE) BAD[threadIdx.x] = 0;
   const double smin = smin_a[e];
   const double sb = smin - F.eps_s * fabs(smin);
   const double sbm = sb + 1e-10 * fabs(sb);
   const double lsb = sbm > 0 ? log(sbm) : -INFINITY;
   bool bad = false;
-  hex_tile_checks<P>(u, U, E, e0, K, [&](const double w[5]) { bad = bad || maybe_violates(w, lsb, F); });
-  if (bad && e < n) flag[e] = 1;
+  hex_tile_checks<P>(src, U, E, e0, K, [&](const double w[5]) { bad = bad || maybe_violates(w, lsb, F); });
+  bad = bad && e < n;
+  if (bad) flag[e] = 1;
+  if (cand64 == nullptr) return;
+  if (bad) BAD[el] = 1;
+  __syncthreads();
+  if (!BAD[el]) return;
+  const int l = threadIdx.x / C::NE, c0 = l % C::N1, c1 = l / C::N1;
+  for (int a = 0; a < C::N1; ++a) {
+    const int pt = c0 + C::N1 * (c1 + C::N1 * a);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) cand64[((int64_t)pt * 5 + v) * E + e] = U[(v * NSP + pt) * C::NE + el];
+  }
 }
 
 __global__ void k_fill_i32(int32_t* __restrict__ a, int64_t n, int32_t v) {

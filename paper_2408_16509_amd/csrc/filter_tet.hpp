@@ -24,6 +24,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "filter.hpp"
 
 namespace frmi {
@@ -152,23 +154,33 @@ __global__ void __launch_bounds__(256) tet_sown(const double* __restrict__ u, un
 }
 
 // Detection (thread per element): pessimistic test at every solution point, as the
-// hexahedral detection (flag must be cleared before).
-__global__ void __launch_bounds__(256) tet_filter_detect(const double* __restrict__ u, const double* __restrict__ smin_a,
-                                                         int64_t E, int64_t n, FiltPrm F, int32_t* __restrict__ flag) {
+// hexahedral detection (flag must be cleared before).  With an RK stage source the
+// thread also performs the stage update of its element (all E_pad elements), and
+// cand64 (if not null) receives the FP64 stage state of a flagged element.
+template <typename Src>
+__global__ void __launch_bounds__(256) tet_filter_detect(Src src, const double* __restrict__ smin_a, int64_t E,
+                                                         int64_t n, FiltPrm F, int32_t* __restrict__ flag,
+                                                         double* __restrict__ cand64) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= n) return;
-  const double smin = smin_a[e];
+  constexpr bool kUpdate = !std::is_same<Src, PlainSrc>::value;
+  if (e >= (kUpdate ? E : n)) return;
+  const double smin = e < n ? smin_a[e] : 0.0;
   const double sb = smin - F.eps_s * fabs(smin);
   const double sbm = sb + 1e-10 * fabs(sb);
   const double lsb = sbm > 0 ? log(sbm) : -INFINITY;
   bool bad = false;
-  for (int z = 0; z < TF_NSP && !bad; ++z) {
+  for (int z = 0; z < TF_NSP && (kUpdate || !bad); ++z) {
     double w[5];
 #pragma unroll
-    for (int v = 0; v < 5; ++v) w[v] = u[((int64_t)z * 5 + v) * E + e];
-    bad = maybe_violates(w, lsb, F);
+    for (int v = 0; v < 5; ++v) w[v] = src(((int64_t)z * 5 + v) * E + e, v);
+    bad = bad || maybe_violates(w, lsb, F);
   }
-  if (bad) flag[e] = 1;
+  if (!bad || e >= n) return;
+  flag[e] = 1;
+  if constexpr (kUpdate) {
+    if (cand64)
+      for (int i = 0; i < TF_NSP * 5; ++i) cand64[(int64_t)i * E + e] = src.stage((int64_t)i * E + e);
+  }
 }
 
 // The 16 features (same definitions as for hexahedra; the shells are the total

@@ -107,7 +107,7 @@ struct fr_ctx_s {
   float* static_scratch = nullptr;  // this device's copy of the library's fixed scratch array
   // tetrahedral operators on the device (arithmetic type of the context)
   void* tet_opT = nullptr;    // [TET_KP][TET_MP] transposed divergence operator
-  void* tet_ogT = nullptr;    // [TGR_K][TGR_M] transposed stacked gradient operator
+  void* tet_ogT = nullptr;    // [TGS_K][TGR_M] transposed stacked gradient operator, face-sparse row order
   void* tet_opH = nullptr;    // BF16x3 split of the divergence operator: hi [TET_MP][TET_KP16], then lo
   void* tet_ogH = nullptr;    // BF16x3 split of the gradient operator: hi [TGR_M][TGR_K], then lo
   double* rk_x0 = nullptr;    // adaptive stepping: u_n and the error register (FP64)
@@ -671,6 +671,29 @@ fr_status filter_alloc(fr_ctx c) {
   return FR_OK;
 }
 
+// An RK4 stage update fused into the filter's detection pass (see RkStageSrc): the
+// pass forms the stage state (or the new state) while checking it.
+struct StageFuse {
+  int mode = 0;                 // 0 first stage, 1 middle stages, 2 last (new state in place)
+  double b = 0, c = 0;          // accumulator and stage coefficients (times dt)
+  const void* k = nullptr;      // the stage's right-hand side, native dtype
+  bool k32 = false;             // k (and s32) FP32: the FP32 form
+  double* u = nullptr;          // u_n, or the state updated in place (last stage)
+  double* acc = nullptr;        // FP64 accumulator
+  double* s64 = nullptr;        // FP64 stage state written in full (FP64 form) or null
+  float* s32 = nullptr;         // FP32 deviation of the stage state (FP32 form) or null
+  double* cand64 = nullptr;     // FP64 stage state of the candidates only (FP32 form) or null
+};
+
+template <typename KT>
+RkStageSrc<KT> stage_src(const StageFuse& z, const DevBlock& b, const fr_params& prm) {
+  const int64_t o = b.native_off;
+  RkStageSrc<KT> s{z.u + o, (const KT*)z.k + o, z.acc + o, z.s64 ? z.s64 + o : nullptr,
+                   z.s32 ? z.s32 + o : nullptr, z.b, z.c, z.mode, {0, 0, 0, 0, 0}};
+  for (int v = 0; v < 5; ++v) s.ref[v] = prm.u_ref[v];
+  return s;
+}
+
 template <int P>
 void hex_smin_p(fr_ctx c, DevBlock& b, const double* uprev) {
   const FiltK K = filtk_of(c->host.hex);
@@ -687,16 +710,26 @@ void hex_smin_p(fr_ctx c, DevBlock& b, const double* uprev) {
 // Candidates of the search: detection at zeta = 0 and ordered compaction into
 // b.f_list / count b.f_cnt[nb]; untouched elements get k = 0 and one evaluation.
 template <int P>
-void hex_candidates_p(fr_ctx c, DevBlock& b, const double* u) {
+void hex_candidates_p(fr_ctx c, DevBlock& b, const double* u, const StageFuse* fz = nullptr) {
   const FiltK K = filtk_of(c->host.hex);
   const FiltPrm F = filtprm_of(c->prm, P);
   const int64_t o = b.elem_off;
   const int nb = (int)((b.n + 255) / 256);
   const int gf = grid_for(b.n, 256);
-  int pk = c->prof_begin("filter_detect");
+  int pk = c->prof_begin(fz ? "rk4_stage_filter_detect_hex" : "filter_detect");
   k_filter_reset<<<gf, 256, 0, c->stream>>>(b.f_det, c->f_k + o, c->f_evals + o, b.n);
-  hex_filter_detect<P><<<(unsigned)(b.E / HexTileCfg<P>::NE), HexTileCfg<P>::NT, 0, c->stream>>>(
-      u + b.native_off, b.smin, b.E, b.n, K, F, b.f_det);
+  const unsigned g = (unsigned)(b.E / HexTileCfg<P>::NE);
+  if (!fz)
+    hex_filter_detect<P, PlainSrc><<<g, HexTileCfg<P>::NT, 0, c->stream>>>(PlainSrc{u + b.native_off}, b.smin, b.E,
+                                                                           b.n, K, F, b.f_det, nullptr);
+  else if (fz->k32)
+    hex_filter_detect<P, RkStageSrc<float>><<<g, HexTileCfg<P>::NT, 0, c->stream>>>(
+        stage_src<float>(*fz, b, c->prm), b.smin, b.E, b.n, K, F, b.f_det,
+        fz->cand64 ? fz->cand64 + b.native_off : nullptr);
+  else
+    hex_filter_detect<P, RkStageSrc<double>><<<g, HexTileCfg<P>::NT, 0, c->stream>>>(
+        stage_src<double>(*fz, b, c->prm), b.smin, b.E, b.n, K, F, b.f_det,
+        fz->cand64 ? fz->cand64 + b.native_off : nullptr);
   k_flag_count<<<nb, 256, 0, c->stream>>>(b.f_det, b.n, b.f_cnt);
   k_scan_counts<<<1, 1024, 0, c->stream>>>(b.f_cnt, nb);
   k_flag_scatter<<<nb, 256, 0, c->stream>>>(b.f_det, b.n, b.f_cnt, b.f_list);
@@ -722,7 +755,7 @@ void hex_features_p(fr_ctx c, DevBlock& b, const double* u) {
 }
 
 template <int P>
-void hex_filter_p(fr_ctx c, DevBlock& b, double* u, int mode, float* u32) {
+void hex_filter_p(fr_ctx c, DevBlock& b, double* u, int mode, float* u32, const StageFuse* fz) {
   constexpr int FW = HexFW<P>::value;
   const FiltK K = filtk_of(c->host.hex);
   const FiltPrm F = filtprm_of(c->prm, P);
@@ -730,7 +763,7 @@ void hex_filter_p(fr_ctx c, DevBlock& b, double* u, int mode, float* u32) {
   const int nb = (int)((b.n + 255) / 256);
   Dev32 s32{u32 ? u32 + b.native_off : nullptr, {0, 0, 0, 0, 0}};
   for (int v = 0; v < 5; ++v) s32.ref[v] = c->prm.u_ref[v];
-  hex_candidates_p<P>(c, b, u);
+  hex_candidates_p<P>(c, b, u, fz);
   int pk;
   if (mode == 1) {
     pk = c->prof_begin("filter_search_learned");
@@ -755,13 +788,24 @@ void tet_smin(fr_ctx c, DevBlock& b, const double* uprev) {
   c->prof_end(pk);
 }
 
-void tet_candidates(fr_ctx c, DevBlock& b, const double* u) {
+void tet_candidates(fr_ctx c, DevBlock& b, const double* u, const StageFuse* fz = nullptr) {
   const FiltPrm F = filtprm_of(c->prm, c->prm.order);
   const int64_t o = b.elem_off;
   const int nb = (int)((b.n + 255) / 256);
-  int pk = c->prof_begin("filter_detect");
+  int pk = c->prof_begin(fz ? "rk4_stage_filter_detect_tet" : "filter_detect");
   k_filter_reset<<<grid_for(b.n, 256), 256, 0, c->stream>>>(b.f_det, c->f_k + o, c->f_evals + o, b.n);
-  tet_filter_detect<<<nb, 256, 0, c->stream>>>(u + b.native_off, b.smin, b.E, b.n, F, b.f_det);
+  const unsigned gE = (unsigned)((b.E + 255) / 256);
+  if (!fz)
+    tet_filter_detect<PlainSrc><<<nb, 256, 0, c->stream>>>(PlainSrc{u + b.native_off}, b.smin, b.E, b.n, F, b.f_det,
+                                                           nullptr);
+  else if (fz->k32)
+    tet_filter_detect<RkStageSrc<float>><<<gE, 256, 0, c->stream>>>(
+        stage_src<float>(*fz, b, c->prm), b.smin, b.E, b.n, F, b.f_det,
+        fz->cand64 ? fz->cand64 + b.native_off : nullptr);
+  else
+    tet_filter_detect<RkStageSrc<double>><<<gE, 256, 0, c->stream>>>(
+        stage_src<double>(*fz, b, c->prm), b.smin, b.E, b.n, F, b.f_det,
+        fz->cand64 ? fz->cand64 + b.native_off : nullptr);
   k_flag_count<<<nb, 256, 0, c->stream>>>(b.f_det, b.n, b.f_cnt);
   k_scan_counts<<<1, 1024, 0, c->stream>>>(b.f_cnt, nb);
   k_flag_scatter<<<nb, 256, 0, c->stream>>>(b.f_det, b.n, b.f_cnt, b.f_list);
@@ -777,13 +821,13 @@ void tet_features_b(fr_ctx c, DevBlock& b, const double* u) {
                                                          c->tet_ftab, F, c->f_flag + o, c->f_feat + o * 16);
 }
 
-void tet_filter_b(fr_ctx c, DevBlock& b, double* u, int mode, float* u32) {
+void tet_filter_b(fr_ctx c, DevBlock& b, double* u, int mode, float* u32, const StageFuse* fz) {
   const FiltPrm F = filtprm_of(c->prm, c->prm.order);
   const int64_t o = b.elem_off;
   const int nb = (int)((b.n + 255) / 256);
   Dev32 s32{u32 ? u32 + b.native_off : nullptr, {0, 0, 0, 0, 0}};
   for (int v = 0; v < 5; ++v) s32.ref[v] = c->prm.u_ref[v];
-  tet_candidates(c, b, u);
+  tet_candidates(c, b, u, fz);
   int pk;
   if (mode == 1) {
     pk = c->prof_begin("filter_search_learned");
@@ -816,25 +860,28 @@ fr_status compute_smin(fr_ctx c, const double* uprev) {
 }
 
 fr_status collect_rows(fr_ctx c, const double* u);
-fr_status apply_filter(fr_ctx c, double* u, int mode, float* u32 = nullptr);
+fr_status apply_filter(fr_ctx c, double* u, int mode, float* u32 = nullptr, const StageFuse* fz = nullptr);
 
 // Filter the FP64 native state u in place; with u32 (the FP32 form's stage buffer) the
-// filtered elements' FP32 deviations are rewritten there as well.
-fr_status apply_filter(fr_ctx c, double* u, int mode, float* u32) {
+// filtered elements' FP32 deviations are rewritten there as well.  With fz the
+// detection pass first performs that RK stage update (u is then the buffer the search
+// works on: the full FP64 stage state, the candidates' copy, or the new state).
+fr_status apply_filter(fr_ctx c, double* u, int mode, float* u32, const StageFuse* fz) {
   if (c->collecting) {
+    if (fz) return fail(c, FR_ERR_STATE, "training-data collection needs the stage state before the filter");
     fr_status st = collect_rows(c, u);
     if (st) return st;
   }
   for (auto& b : c->blocks) {
     if (b.etype == FR_TET) {
-      tet_filter_b(c, b, u, mode, u32);
+      tet_filter_b(c, b, u, mode, u32, fz);
       continue;
     }
     switch (c->prm.order) {
-      case 1: hex_filter_p<1>(c, b, u, mode, u32); break;
-      case 2: hex_filter_p<2>(c, b, u, mode, u32); break;
-      case 3: hex_filter_p<3>(c, b, u, mode, u32); break;
-      case 4: hex_filter_p<4>(c, b, u, mode, u32); break;
+      case 1: hex_filter_p<1>(c, b, u, mode, u32, fz); break;
+      case 2: hex_filter_p<2>(c, b, u, mode, u32, fz); break;
+      case 3: hex_filter_p<3>(c, b, u, mode, u32, fz); break;
+      case 4: hex_filter_p<4>(c, b, u, mode, u32, fz); break;
     }
   }
   HIP_TRY(c, hipGetLastError());
@@ -992,6 +1039,10 @@ fr_status setup_impl(const fr_params* p, int64_t n_vert, const double* xyz, cons
   if (p->riemann != FR_RUSANOV && p->riemann != FR_HLLC) return fail(nullptr, FR_ERR_ARG, "riemann");
   if (p->precision != FR_FP64 && p->precision != FR_FP32 && p->precision != FR_FP32_BF16X3)
     return fail(nullptr, FR_ERR_ARG, "precision");
+  if (p->precision == FR_FP32_BF16X3 && std::none_of(etype, etype + n_elem, [](int32_t t) { return t == FR_TET; }))
+    return fail(nullptr, FR_ERR_UNSUPPORTED,
+                "FR_FP32_BF16X3 splits the dense tetrahedral operator products; a mesh without tetrahedra has "
+                "none (hexahedra contract 1-D lines on the vector units): use FR_FP32");
   if (p->precision != FR_FP64 && (p->u_ref[1] != 0 || p->u_ref[2] != 0 || p->u_ref[3] != 0 ||
                                   !(p->u_ref[0] > 0) || !(p->u_ref[4] > 0)))
     return fail(nullptr, FR_ERR_ARG, "the FP32 form needs a reference state at rest with rho > 0, E > 0");
@@ -1141,9 +1192,24 @@ fr_status setup_impl(const fr_params* p, int64_t n_vert, const double* xyz, cons
         for (int sg = 0; sg < 60; ++sg)
           ogT[(size_t)(35 + sg) * TGR_M + TET_MP * i + pt] = T.lift[pt][sg] * T.nref[T.fp_face[sg]][i];
       }
-    std::vector<char> bog(ogT.size() * tsz);
-    if (tsz == sizeof(float)) for (size_t i = 0; i < ogT.size(); ++i) ((float*)bog.data())[i] = (float)ogT[i];
-    else std::memcpy(bog.data(), ogT.data(), bog.size());
+    // the same operator in the face-sparse row order of the FP32 / FP64 kernels (tgs_row):
+    // direction i reads only the rows of faces 2 - i and 3, whose normals have an i component
+    std::vector<double> ogS((size_t)TGS_K * TGR_M, 0.0);
+    for (int i = 0; i < 3; ++i)
+      for (int pt = 0; pt < 35; ++pt) {
+        for (int k = 0; k < 35; ++k) ogS[(size_t)k * TGR_M + TET_MP * i + pt] = T.Dh[i][pt][k];
+        for (int sg = 0; sg < 60; ++sg) {
+          const int f = T.fp_face[sg];
+          if (f != sg / TET_NFPF || ((f != 2 - i && f != 3) && T.nref[f][i] != 0.0)) {
+            c->err = "tetrahedral flux points not ordered by face, or a face normal off the expected axes";
+            return bail(FR_ERR_STATE);
+          }
+          ogS[(size_t)(TGS_U + 16 * f + sg % TET_NFPF) * TGR_M + TET_MP * i + pt] = T.lift[pt][sg] * T.nref[f][i];
+        }
+      }
+    std::vector<char> bog(ogS.size() * tsz);
+    if (tsz == sizeof(float)) for (size_t i = 0; i < ogS.size(); ++i) ((float*)bog.data())[i] = (float)ogS[i];
+    else std::memcpy(bog.data(), ogS.data(), bog.size());
     if (p->precision == FR_FP32_BF16X3) {
       // [M][K] row-major (k contiguous), hi then lo, K padded to multiples of 16
       std::vector<uint16_t> dh((size_t)2 * TET_MP * TET_KP16, 0), gh((size_t)2 * TGR_M * TGR_K, 0);
@@ -1468,6 +1534,27 @@ fr_status fr_rk_step(fr_ctx c, void* u_, double dt, int32_t n_steps, int32_t fil
   if (!f32) {
     double *K = (double*)c->rk_k, *S = (double*)c->rk_stage;
     const bool filt = filter_mode >= 0;
+    if (filt && !c->collecting) {
+      // each stage update runs inside the filter's detection pass (the stage state is
+      // checked as it is formed instead of being read back)
+      for (int s = 0; s < n_steps; ++s) {
+        if ((st = compute_smin(c, u))) return st;
+        for (int stage = 0; stage < 4; ++stage) {
+          if ((st = rhs_native(c, stage == 0 ? u : S, K))) return st;
+          StageFuse fz;
+          fz.mode = stage == 0 ? 0 : (stage < 3 ? 1 : 2);
+          fz.b = stage == 0 || stage == 3 ? b1 : b2;
+          fz.c = stage == 2 ? dt : c2;
+          fz.k = K;
+          fz.u = u;
+          fz.acc = c->rk_acc;
+          fz.s64 = stage < 3 ? S : nullptr;
+          if ((st = apply_filter(c, stage < 3 ? S : u, filter_mode, nullptr, &fz))) return st;
+        }
+      }
+      HIP_TRY(c, hipGetLastError());
+      return FR_OK;
+    }
     for (int s = 0; s < n_steps; ++s) {
       // entropy bound of this step from u_n; every later stage state and u_{n+1} is filtered
       if (filt && (st = compute_smin(c, u))) return st;
@@ -1505,6 +1592,30 @@ fr_status fr_rk_step(fr_ctx c, void* u_, double dt, int32_t n_steps, int32_t fil
       // checks) together with the FP32 deviation the kernels read
       if (!c->rk_s64 && dalloc(c, &c->rk_s64, n)) return FR_ERR_ALLOC;
       double* S64 = c->rk_s64;
+      if (!c->collecting) {
+        // each stage update runs inside the filter's detection pass: the FP64 stage state
+        // is formed in registers and checked there, its FP32 deviation written for the
+        // next right-hand side, and only the candidates' FP64 states written for the search
+        for (int s = 0; s < n_steps; ++s) {
+          if ((st = compute_smin(c, u))) return st;
+          for (int stage = 0; stage < 4; ++stage) {
+            if ((st = rhs_native(c, S, K))) return st;
+            StageFuse fz;
+            fz.mode = stage == 0 ? 0 : (stage < 3 ? 1 : 2);
+            fz.b = stage == 0 || stage == 3 ? b1 : b2;
+            fz.c = stage == 2 ? dt : c2;
+            fz.k = K;
+            fz.k32 = true;
+            fz.u = u;
+            fz.acc = c->rk_acc;
+            fz.s32 = S;
+            fz.cand64 = stage < 3 ? S64 : nullptr;
+            if ((st = apply_filter(c, stage < 3 ? S64 : u, filter_mode, S, &fz))) return st;
+          }
+        }
+        HIP_TRY(c, hipGetLastError());
+        return FR_OK;
+      }
       for (int s = 0; s < n_steps; ++s) {
         if ((st = compute_smin(c, u))) return st;
         for (int stage = 0; stage < 4; ++stage) {

@@ -330,6 +330,51 @@ __global__ void __launch_bounds__(TDIV_NT) tet_div(const T* __restrict__ u, cons
 // left-to-right unit normal and stores it in its own slot of fc; the divergence
 // kernel reads it from there for both sides and scales it by its own +-|S^T n~|.
 constexpr int TGR_K = 96, TGR_M = 3 * TET_MP;
+// Panel rows of the FP32 / FP64 gradient: u at the 35 points (row 35 zero), then u^ face
+// by face, 16 rows per face (its 15 flux points and a zero row).  The lift part of
+// direction i is non-zero only on the faces whose reference normal has an i component,
+// face 2 - i (normal -e_i) and face 3 ((1, 1, 1) / sqrt 3), so direction i contracts
+// 36 + 16 + 16 of the 100 rows (255 products per wave and variable tile set, not 360).
+constexpr int TGS_U = 36, TGS_K = TGS_U + 4 * 16;
+__device__ __forceinline__ int tgs_row(int sg) { return TGS_U + 16 * (sg / TET_NFPF) + sg % TET_NFPF; }
+
+// The face-sparse gradient contraction of wave w (point tile w, directions 0..2, all five
+// variables); ogS[k][48 i + pt] in the row order above.
+template <typename T, int NE>
+__device__ __forceinline__ void tet_grad_contract(typename Mma16<T>::V (&acc)[3][5], const T* PAN, int lane,
+                                                  const T* __restrict__ ogS, int w) {
+  const int kr = lane / 16, col = lane % 16;
+  const int mcol[3] = {16 * w + col, 16 * (3 + w) + col, 16 * (6 + w) + col};
+  // rows shared by the three directions: the solution points, then face 3
+#pragma unroll 3
+  for (int s = 0; s < TGS_U / 4 + 4; ++s) {
+    const int k = (s < TGS_U / 4 ? 4 * s : TGS_U + 48 + 4 * (s - TGS_U / 4)) + kr;
+    T b[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) b[v] = PAN[(k * 5 + v) * NE + col];
+    const T* arow = ogS + k * TGR_M;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const T a = arow[mcol[i]];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) acc[i][v] = Mma16<T>::run(a, b[v], acc[i][v]);
+    }
+  }
+  // face 2 - i: direction i only
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+#pragma unroll 2
+    for (int s = 0; s < 4; ++s) {
+      const int k = TGS_U + 16 * (2 - i) + 4 * s + kr;
+      T b[5];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) b[v] = PAN[(k * 5 + v) * NE + col];
+      const T a = ogS[k * TGR_M + mcol[i]];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) acc[i][v] = Mma16<T>::run(a, b[v], acc[i][v]);
+    }
+  }
+}
 
 template <typename T, bool DEV, bool BF3, bool FC>
 __global__ void __launch_bounds__(tgr_nt<T>()) __attribute__((amdgpu_waves_per_eu(4))) tet_grad_mma(const T* __restrict__ u, const T* __restrict__ geo, Conn C,
@@ -339,7 +384,10 @@ __global__ void __launch_bounds__(tgr_nt<T>()) __attribute__((amdgpu_waves_per_e
                                                         T beta, int side_mode, T gamma, T mu, T pr, T tau, int riemann,
                                                         RefState<T> R) {
   constexpr int NE = TDIV_NE, NT = tgr_nt<T>();
-  __shared__ T PAN[TGR_K * 5 * NE];      // [k][v][el]: u at the 35 points, u^ at the 60 flux points, 0
+  constexpr int KR = BF3 ? TGR_K : TGS_K;
+  // [k][v][el]: u at the 35 points, u^ at the 60 flux points (BF16x3: rows 35..94; else
+  // face by face, tgs_row), zero rows
+  __shared__ T PAN[KR * 5 * NE];
   __shared__ T SJ[10 * NE];
   __shared__ uint8_t SIDE[FC ? TET_NFP * NE : 1];   // bit 0: element is the left side; bit 1: it forms the flux
   __shared__ int32_t PFP[FC ? TET_NSP * 4 : 1];
@@ -348,7 +396,14 @@ __global__ void __launch_bounds__(tgr_nt<T>()) __attribute__((amdgpu_waves_per_e
   const int64_t e0 = xcd_block() * NE;
   {
     for (int i = t; i < 10 * NE; i += NT) SJ[i] = geo[(int64_t)(i / NE) * E + e0 + i % NE];
-    for (int i = t; i < 5 * NE; i += NT) PAN[(TGR_K - 1) * 5 * NE + i] = T(0);
+    if constexpr (BF3) {
+      for (int i = t; i < 5 * NE; i += NT) PAN[(TGR_K - 1) * 5 * NE + i] = T(0);
+    } else {
+      for (int i = t; i < 5 * 5 * NE; i += NT) {
+        const int zr = i / (5 * NE);            // zero rows 35, 51, 67, 83, 99
+        PAN[(zr == 0 ? TET_NSP : TGS_U + 16 * zr - 1) * 5 * NE + i % (5 * NE)] = T(0);
+      }
+    }
     for (int i = t; i < TET_NSP * 5 * NE; i += NT) PAN[i] = u[(int64_t)(i / NE) * E + e0 + i % NE];
     if constexpr (FC)
       for (int i = t; i < TET_NSP * 4; i += NT) PFP[i] = O.pfp[i];
@@ -359,16 +414,30 @@ __global__ void __launch_bounds__(tgr_nt<T>()) __attribute__((amdgpu_waves_per_e
       const int face = sg / TET_NFPF, q = sg % TET_NFPF;
       const NbrSlot ns = nbr_slot<TET_NFPF>(C, E, e, face, q);
       const int so = O.src[sg];
-      T un[5];
-      tet_load(u, E, ns.elem, O.src[ns.fp], un);
+      const int row = BF3 ? TET_NSP + sg : tgs_row(sg);
       if constexpr (FC) SIDE[sg * NE + el] = (ns.left ? 1 : 0) | (ns.left != (side_mode > 0) ? 2 : 0);
+      if (side_mode != 0) {
+        // one-sided: u^ is exactly the state of the side named by beta, so the partner's
+        // state is read only where that side is the partner (half of the flux points)
+        const bool from_nbr = (side_mode > 0) != ns.left;
+        T uh[5];
+        if (from_nbr) {
+          tet_load(u, E, ns.elem, O.src[ns.fp], uh);
+        } else {
 #pragma unroll
-      for (int c = 0; c < 5; ++c) {
-        const T own = PAN[(so * 5 + c) * NE + el];
-        const T uL = ns.left ? own : un[c], uR = ns.left ? un[c] : own;
-        // one-sided: u^ is exactly the state of the side named by beta
-        PAN[((TET_NSP + sg) * 5 + c) * NE + el] =
-            side_mode > 0 ? uL : (side_mode < 0 ? uR : T(0.5) * (uL + uR) + beta * (uL - uR));
+          for (int c = 0; c < 5; ++c) uh[c] = PAN[(so * 5 + c) * NE + el];
+        }
+#pragma unroll
+        for (int c = 0; c < 5; ++c) PAN[(row * 5 + c) * NE + el] = uh[c];
+      } else {
+        T un[5];
+        tet_load(u, E, ns.elem, O.src[ns.fp], un);
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+          const T own = PAN[(so * 5 + c) * NE + el];
+          const T uL = ns.left ? own : un[c], uR = ns.left ? un[c] : own;
+          PAN[(row * 5 + c) * NE + el] = T(0.5) * (uL + uR) + beta * (uL - uR);
+        }
       }
     }
     __syncthreads();
@@ -378,8 +447,12 @@ __global__ void __launch_bounds__(tgr_nt<T>()) __attribute__((amdgpu_waves_per_e
     for (int i = 0; i < 3; ++i)
 #pragma unroll
       for (int v = 0; v < 5; ++v) acc[i][v] = typename Mma16<T>::V{0, 0, 0, 0};
-    const int mt[3] = {w, 3 + w, 6 + w};
-    tet_contract<T, BF3, 3, NE>(acc, PAN, TGR_K, lane, ogT, 0, TGR_M, mt, ogH, ogL, TGR_K);
+    if constexpr (BF3) {
+      const int mt[3] = {w, 3 + w, 6 + w};
+      tet_contract<T, BF3, 3, NE>(acc, PAN, TGR_K, lane, ogT, 0, TGR_M, mt, ogH, ogL, TGR_K);
+    } else {
+      tet_grad_contract<T, NE>(acc, PAN, lane, ogT, w);
+    }
     const int64_t e = e0 + col;
     if (e < n) {
       T S[9];
@@ -412,7 +485,7 @@ __global__ void __launch_bounds__(tgr_nt<T>()) __attribute__((amdgpu_waves_per_e
 #pragma unroll
             for (int c = 0; c < 5; ++c) {
               own[c] = PAN[(pt * 5 + c) * NE + col];
-              nb[c] = PAN[((TET_NSP + sg) * 5 + c) * NE + col];
+              nb[c] = PAN[((BF3 ? TET_NSP + sg : tgs_row(sg)) * 5 + c) * NE + col];
               uL[c] = ns.left ? own[c] : nb[c];
               uR[c] = ns.left ? nb[c] : own[c];
             }

@@ -1,17 +1,26 @@
 #!/usr/bin/env python3
 """Throughput of the FR right-hand side on one MI355X.
 
-Default workload: compressible Navier--Stokes Taylor--Green vortex (Re 1600,
-Ma 0.1, Pr 0.71) on a periodic 32^3 mesh of straight hexahedra at p = 3
-(64 Gauss--Legendre points per element, 2,097,152 points), LDG viscous terms,
-Rusanov inviscid flux, FP64.  A step is one classical RK4 step (4 right-hand
-sides + the stage updates) on the device-resident state; the metric counts
-right-hand-side degrees of freedom (elements x solution points, the paper's DoF)
-per second: GDoF/s = 4 * E * N_sp * steps / time / 1e9.
+Default workload (the headline): compressible Navier--Stokes Taylor--Green vortex
+(Re 1600, Ma 0.1, Pr 0.71, LDG viscous terms, Rusanov inviscid flux) on the mixed
+mesh of p = 4 hexahedra and p = 4 tetrahedra: two periodic 32 x 64 x 64 boxes of
++-10 % perturbed cells, one kept as 131,072 hexahedra (125 points each), the other
+cut into 786,432 tetrahedra (35 points each), element order permuted: 917,504
+elements, 43,909,120 points.  Two forms are timed: FP32 operators and fluxes on
+FP32 deviations with FP64 RK accumulation and the entropy filter on every stage
+with the learned warm start (the headline), and FP64 with the plain filter.
+A step is one classical RK4 step (4 right-hand sides, stage updates, filter) on
+the device-resident state; the metric counts right-hand-side degrees of freedom
+(elements x solution points, the paper's DoF) per second:
+GDoF/s = 4 * sum_e N_sp(e) * steps / time / 1e9.
 
-Also reported: the dominant kernel's achieved bandwidth (algorithmic bytes per
-launch / HIP-event-measured launch time on the library's stream) against the
-8 TB/s HBM peak, and the FP64 CPU oracle timed on the host on one full RHS.
+Also reported: the dominant kernel against the 8 TB/s HBM peak (bytes of the
+algorithmic minimum of the right-hand side, read u and write R once, for the
+points that kernel processes; the kernel's own compulsory traffic beside it),
+each reduced form's error against the FP64 form per variable, the FP64 CPU
+oracle timed on the host on a bounded sample of the same workload, and two more
+workloads (the 32^3 p = 3 hexahedral NS TGV, and the 48^3 Mach-3 shock with the
+trained learned filter against the plain one) under "extra_workloads".
 """
 from __future__ import annotations
 
@@ -39,7 +48,13 @@ CONFIGS = {
     # timed forms: FP32 + learned filter (headline), FP64 + plain filter, and both unfiltered
     "ns_tgv_mixed_c5split_p4": dict(kind="mixed", n=(32, 64, 64), order=4, system=1, riemann=0, mach=0.1,
                                     dt=7.5e-5, perturb=0.1, perturb_seed=51, permute_seed=53,
-                                    forms="fp32:learned,fp64:plain,fp32,bf16x3:learned,fp64"),
+                                    forms="fp32:learned,fp64:plain",
+                                    # the warm-start MLP of the learned form, trained on the plain filter's
+                                    # rows from a small mixed-mesh Mach-3 shock (NS, p = 4, both element types)
+                                    mlp_train=dict(n=(4, 8, 8), seeds=(101, 102, 103), steps=20, dt=5e-4,
+                                                   iters=2000),
+                                    # oracle timing sample: the same two boxes at 8 x 8 x 8 cells each
+                                    oracle_sample=(8, 8, 8)),
     # Mach-3 shock (orientation seed 41, density noise seed 42), Euler + HLLC, entropy
     # filter on every RK stage: plain bisection vs the learned warm start, the MLP
     # trained on the plain filter's data from held-out draws (seeds 101-108 / 201-208)
@@ -181,8 +196,7 @@ FILTER_MODES = {"": -1, "plain": 0, "learned": 1}
 def run_form(form, cfg, mesh, ic, args, torch, np, frmi, inputs):
     """Time `args.steps` RK4 steps of one form "<precision>[:plain|:learned]" (the suffix
     turns the entropy filter on every stage state and new state on); per-kernel event
-    timing.  The learned filter uses the initial (Glorot, seed 43) MLP with identity
-    input scaling unless trained weights are given."""
+    timing.  The learned filter uses the trained weights in args.mlp_weights."""
     prec, _, fmode = form.partition(":")
     filter_mode = FILTER_MODES[fmode]
     kw = dict(system=cfg["system"], order=cfg["order"], riemann=cfg["riemann"])
@@ -201,7 +215,10 @@ def run_form(form, cfg, mesh, ic, args, torch, np, frmi, inputs):
         blocks["hex" if lay.etype[i] == frmi.FR_HEX else "tet"] = (int(n), int(s), int(lay.n_fp[i]))
     u0 = ctx.pack64(np.concatenate(canon))
     if filter_mode == 1:
-        ctx.mlp_set_weights(inputs.mlp_glorot(43), np.zeros(16), np.ones(16))
+        w = getattr(args, "mlp_weights", None)
+        if w is None:
+            raise RuntimeError("the learned form needs trained MLP weights")
+        ctx.mlp_set_weights(*w)
     u = u0.clone()
     stream = torch.cuda.current_stream()
     # the warm-up and the timed steps each as one call advancing several steps (the FP32
@@ -471,17 +488,241 @@ def _per_var_err(a, b, blocks, torch):
     return [float(v) for v in torch.sqrt(num / den).cpu()]
 
 
+M0_BYTES_PER_DOF = {"f64": 80, "f32": 40}      # read u + write R once per RHS (FP64 / FP32 form)
+M1_BYTES_PER_DOF = {"f64": 320, "f32": 160}    # NS fused in two phases: the gradient round trip added
+ERR_TARGET_PER_RHS = 1e-5
+
+
+def train_mixed_mlp(cfg, torch, np, frmi, inputs):
+    """Warm-start MLP for the mixed workload: the plain filter's (features, dyadic index)
+    rows of a few filtered RK4 steps of a Mach-3 shock on a small mixed mesh of the same
+    element types, orders and equations (FP64 context), then Adam on the device."""
+    tr = cfg["mlp_train"]
+    t0 = time.perf_counter()
+    small = dict(cfg, n=tr["n"])
+    mesh = build_mesh(small, inputs)
+    ctx = frmi.Context(mesh, system=cfg["system"], order=cfg["order"], riemann=frmi.FR_HLLC)
+    lay = ctx.layout
+    x = ctx.sol_points()
+    xs, ks = [], []
+    for sd in tr["seeds"]:
+        canon, off = [], 0
+        for i in range(lay.n_types):
+            n, sp = lay.n_elem[i], lay.n_sp[i]
+            xx = x[off:off + n * sp].reshape(n, sp, 3)
+            s_ = inputs.shock(xx[..., 0], xx[..., 1], xx[..., 2], orient_seed=sd, noise_seed=sd + 100)
+            canon.append(np.moveaxis(s_, 0, 1).ravel())
+            off += n * sp
+        u = ctx.pack64(np.concatenate(canon))
+        ctx.filter(u, u, mode=0)
+        X, K = ctx.mlp_collect(u, tr["dt"], tr["steps"], cap=2_000_000)
+        xs.append(X[K > 0])
+        ks.append(K[K > 0])
+    X = torch.cat(xs).contiguous()
+    y = (torch.log2(torch.cat(ks).double()) / 20.0).float().contiguous()
+    Xn = X.double()
+    mean, std = Xn.mean(0).cpu().numpy(), (Xn.std(0) + 1e-6).cpu().numpy()
+    ctx.mlp_set_weights(inputs.mlp_glorot(43), mean, std)
+    rows = torch.tensor(inputs.minibatch_rows(X.shape[0], 256, tr["iters"], 44), device="cuda")
+    hist = ctx.mlp_train(X, y, rows, tr["iters"], 256).cpu().numpy()
+    w = ctx.mlp_get_weights()
+    ctx.close()
+    info = {"rows": int(X.shape[0]), "iters": tr["iters"], "seconds": round(time.perf_counter() - t0, 2),
+            "loss_first_last": [float(hist[:20].mean()), float(hist[-20:].mean())],
+            "data": f"Mach-3 shock on two {tr['n'][0]}x{tr['n'][1]}x{tr['n'][2]} boxes (hex p=4, tet p=4), "
+                    f"orientation seeds {list(tr['seeds'])}, {tr['steps']} filtered RK4 steps each"}
+    return (w, mean, std), info
+
+
+def oracle_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return int(max([t.get("num_threads", 1) for t in threadpool_info()] or [1]))
+    except Exception:
+        return int(os.cpu_count() or 1)
+
+
+def cpu_baseline_sample(cfg, inputs):
+    """The FP64 oracle on a bounded sample of the workload: the same construction (element
+    types, orders, perturbation, permutation, equations, initial condition) at the sample's
+    cell counts; median of 5 right-hand sides after one untimed, mesh setup excluded."""
+    import numpy as np
+    from oracle import fr as ofr
+    from oracle import mesh as omesh
+    small = dict(cfg, n=cfg["oracle_sample"])
+    mesh = build_mesh(small, inputs)
+    bl = omesh.build(mesh, cfg["order"])
+    u = [np.moveaxis(inputs.tgv(b.xsol[..., 0], b.xsol[..., 1], b.xsol[..., 2], mach=cfg["mach"]), 0, 1).copy()
+         for b in bl]
+    prm = ofr.Params(system=cfg["system"], riemann=cfg["riemann"])
+    ofr.rhs(bl, u, prm)
+    ts = []
+    for _ in range(5):
+        t0 = time.perf_counter()
+        ofr.rhs(bl, u, prm)
+        ts.append(time.perf_counter() - t0)
+    t = float(np.median(ts))
+    dof = sum(b.J.size for b in bl)
+    n = cfg["oracle_sample"]
+    kinds = ", ".join(f"{len(b.elems)} {'hexahedra' if b.etype == 0 else 'tetrahedra'}" for b in bl)
+    return {"value": dof / t / 1e9, "unit": "GDoF/s", "cores": oracle_threads(), "kind": "oracle",
+            "sample": f"FP64 oracle RHS on the workload built at {n[0]}x{n[1]}x{n[2]} cells per box ({kinds}, "
+                      f"{dof} points), median of 5 ({t:.2f} s each), mesh setup excluded"}
+
+
+def roofline_for(times, blocks, form):
+    """Dominant kernel (most time per step) of a form: the algorithmic-minimum bytes of the
+    right-hand side (read u, write R once; SURVEY-style model M0) for the points of the
+    element block it processes, per launch, against the HBM peak; the kernel's own
+    compulsory bytes (this implementation's decomposition) as separate fields."""
+    dtype = "f64" if form.split(":")[0] == "fp64" else "f32"
+
+    def block_of(k):
+        return blocks.get(k.split("_", 1)[0])
+    fam = {k: v for k, v in times.items() if block_of(k) is not None
+           and kernel_bytes_per_elem(k, block_of(k)[1], block_of(k)[2]) is not None}
+    dom = max(fam, key=lambda k: fam[k][1])
+    launches, tot = fam[dom]
+    avg_ms = tot / launches
+    n, nsp, nfp = block_of(dom)
+    m0 = M0_BYTES_PER_DOF[dtype] * n * nsp
+    impl = kernel_bytes_per_elem(dom, nsp, nfp) * n
+    ach = m0 / (avg_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+            "avg_launch_ms": round(avg_ms, 4), "bytes_per_launch_m0": int(m0),
+            "kernel_model_bytes_per_launch": int(impl),
+            "kernel_model_achieved_gbs": round(impl / (avg_ms * 1e-3) / 1e9, 1),
+            "kernel_model_frac": round(impl / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
+def run_tgv_workload(name, cfg, forms, args, torch, np, frmi, inputs, with_cpu=True):
+    """Time the forms of a Taylor--Green workload; errors of each reduced form against the FP64
+    form; dominant-kernel roofline; optionally the oracle on a sample (or the full mesh)."""
+    mesh = build_mesh(cfg, inputs)
+
+    def ic(xsol):
+        s_ = inputs.tgv(xsol[..., 0], xsol[..., 1], xsol[..., 2], mach=cfg["mach"])
+        return np.moveaxis(s_, 0, 1).copy()
+
+    mlp_info = None
+    if any(f.endswith(":learned") for f in forms):
+        args.mlp_weights, mlp_info = train_mixed_mlp(cfg, torch, np, frmi, inputs)
+    runs = {f: run_form(f, cfg, mesh, ic, args, torch, np, frmi, inputs) for f in forms}
+    head = runs[forms[0]]
+    blocks = head["blocks"]
+    E = sum(b[0] for b in blocks.values())
+    dof = sum(b[0] * b[1] for b in blocks.values())
+    gdofs = {f: 4 * dof / (r["ms"] * 1e-3) / 1e9 for f, r in runs.items()}
+    dt0 = forms[0].split(":")[0]
+    out = {
+        "metric": "RHS GDoF/s (FP32/learned vs FP64 plain) at stated L2 error; % HBM roofline",
+        "value": round(gdofs[forms[0]], 4), "unit": "GDoF/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(head["ms"], 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": {"fp32": "f32", "bf16x3": "f32+bf16x3"}.get(dt0, "f64"),
+        "data": "synthetic",
+        "config": {"workload": name, "elements": int(E), "order": cfg["order"],
+                   "blocks": {k: {"elements": v[0], "points_per_elem": v[1]} for k, v in blocks.items()},
+                   "dof": int(dof), "rhs_per_step": 4, "form": forms[0],
+                   "rk_accumulation": "f64", "state_finite_after": bool(head["finite"]),
+                   "wall_s_timed": round(head["wall"], 3)},
+        "forms": {f: {"gdof_s": round(gdofs[f], 4), "ms_per_step": round(runs[f]["ms"], 4),
+                      "timed_s": round(runs[f]["ms"] * args.steps * 1e-3, 3)} for f in forms},
+    }
+    fp64_forms = [f for f in forms if f.split(":")[0] == "fp64"]
+    if fp64_forms and forms[0] != fp64_forms[0]:
+        out["speedup_vs_" + fp64_forms[0].replace(":", "_")] = round(gdofs[forms[0]] / gdofs[fp64_forms[0]], 4)
+    if mlp_info is not None:
+        out["mlp_training"] = mlp_info
+    for f in forms:
+        if "filter" in runs[f]:
+            fs = dict(runs[f]["filter"])
+            fs["state"] = ("idle: no element of this smooth state fails the checks, so the timed cost is the "
+                           "entropy-bound and detection passes" if fs["candidates"] == 0 else "active")
+            out["forms"][f]["filter_on_final_state"] = fs
+    # each reduced-precision form against the first FP64 form of the same run (the FP64 form
+    # is the one the parity tests pin to the oracle): the RHS of the initial state per
+    # variable against the 1e-5 target, and the solution after the same number of RK4 steps
+    ref = fp64_forms[0] if fp64_forms else None
+    if ref is not None:
+        r64, u64 = runs[ref]["rhs0"], runs[ref]["u_final"]
+        for f in forms:
+            if f.split(":")[0] == "fp64":
+                continue
+            rr, uu = runs[f]["rhs0"], runs[f]["u_final"]
+            pv = _per_var_err(rr, r64, runs[f]["blocks"], torch)
+            o = out["forms"][f]
+            o["rhs_rel_l2_vs_fp64_form"] = float(torch.linalg.norm(rr - r64) / torch.linalg.norm(r64))
+            o["rhs_rel_l2_vs_fp64_form_per_var"] = pv
+            o["rhs_meets_1e-5_per_var"] = [v <= ERR_TARGET_PER_RHS for v in pv]
+            bound = STATED_RHS_BOUND.get((name, f.split(":")[0]))
+            if bound is not None:
+                o["rhs_stated_bound_per_var"] = bound
+                o["rhs_within_stated_bound"] = bool(all(v <= b for v, b in zip(pv, bound)))
+            o["solution_rel_l2_vs_fp64_form"] = {
+                "against": ref, "steps": runs[f]["steps_total"],
+                "value": float(torch.linalg.norm(uu - u64) / torch.linalg.norm(u64))}
+    if not args.no_kernel_timing:
+        out["roofline"] = roofline_for(head["times"], blocks, forms[0])
+        out["roofline"]["traffic"] = load_traffic(out["roofline"]["kernel"], name)
+        for f in forms:
+            out["forms"][f]["kernels_ms_per_step"] = {k: round(v[1] / 2, 4)
+                                                       for k, v in sorted(runs[f]["times"].items())}
+            dtype = "f64" if f.startswith("fp64") else "f32"
+            rate = 4 * dof / (runs[f]["ms"] * 1e-3) / 1e9
+            out["forms"][f]["rhs_m0_fraction"] = round(rate * M0_BYTES_PER_DOF[dtype] / HBM_PEAK_GBS, 4)
+            if cfg["system"] == 1:
+                out["forms"][f]["rhs_m1_fraction"] = round(rate * M1_BYTES_PER_DOF[dtype] / HBM_PEAK_GBS, 4)
+            if f != forms[0]:
+                out["forms"][f]["roofline"] = roofline_for(runs[f]["times"], blocks, f)
+    if with_cpu and not args.no_cpu_baseline:
+        if cfg.get("oracle_sample"):
+            out["cpu_baseline"] = cpu_baseline_sample(cfg, inputs)
+        elif cfg.get("oracle_ok", False):
+            base, uo, Ro = cpu_baseline(mesh, cfg, ic)
+            out["cpu_baseline"] = base
+            for f in forms:
+                ctx = runs[f]["ctx"]
+                rg = ctx.new_native()
+                ctx.rhs(ctx.pack(uo[0].ravel()), rg)
+                got = ctx.unpack_rhs(rg).cpu().numpy().reshape(Ro[0].shape)
+                err = np.sqrt(((got - Ro[0]) ** 2).sum(axis=(0, 2)) / (Ro[0] ** 2).sum(axis=(0, 2)))
+                out["forms"][f]["rhs_rel_l2_vs_oracle"] = float(np.linalg.norm(got - Ro[0]) / np.linalg.norm(Ro[0]))
+                out["forms"][f]["rhs_rel_l2_per_var"] = [float(v) for v in err]
+        else:
+            out["cpu_baseline"] = None
+    for r in runs.values():
+        r["ctx"].close()
+    return out, mesh
+
+
+# Stated per-variable bounds (rho, rho u, rho v, rho w, E) of the reduced forms' RHS against
+# the FP64 form on the Ma 0.1 Taylor--Green workloads: the low-Mach residual cancels terms
+# of size H0 = 250 in the energy (and through it in the density), so rho and E sit far
+# above the 1e-5 target while the momentum stays near the arithmetic's own level.
+STATED_RHS_BOUND = {
+    ("ns_tgv_mixed_c5split_p4", "fp32"): [5e-2, 2e-3, 2e-3, 2e-3, 5e-2],
+    ("ns_tgv_mixed_c5split_p4", "bf16x3"): [1.0, 5e-2, 5e-2, 5e-2, 1.0],
+    ("ns_tgv_hex32_p3", "fp32"): [5e-3, 5e-4, 5e-4, 5e-4, 5e-3],
+}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="ns_tgv_hex32_p3", choices=sorted(CONFIGS))
+    ap.add_argument("--config", default="ns_tgv_mixed_c5split_p4", choices=sorted(CONFIGS))
     ap.add_argument("--forms", default=None,
                     help="forms to time: fp32, fp64 or bf16x3, each optionally with :plain or :learned "
                          "(entropy filter on); the first is the headline (default: the workload's own)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the extra workloads of the default run (32^3 p=3 hexahedra, 48^3 shock)")
+    ap.add_argument("--stream-probe", action="store_true",
+                    help="only measure the HBM streaming ceiling: read-only, write-only, copy and 2:1 passes "
+                         "(hand-written kernels in libfrprobe.so, 1 GiB buffers, several grid sizes)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (scale for the HBM byte counters)")
     args = ap.parse_args()
@@ -493,6 +734,24 @@ def main():
     import numpy as np
     import torch
 
+    if args.stream_probe:
+        import ctypes
+        torch.cuda.set_device(0)
+        lib = ctypes.CDLL(os.path.join(ROOT, "paper_2408_16509_amd", "libfrprobe.so"))
+        lib.frprobe_stream.restype = ctypes.c_int
+        lib.frprobe_stream.argtypes = [ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+        res = {}
+        for grid in (1024, 2048, 4096, 8192, 16384):
+            out = (ctypes.c_double * 5)()
+            rc = lib.frprobe_stream(1 << 30, 5, grid, out)
+            if rc != 0:
+                raise RuntimeError(f"stream probe failed with HIP error {rc}")
+            res[grid] = {"read_gbs": round(out[0], 1), "write_gbs": round(out[1], 1), "copy_gbs": round(out[2], 1),
+                         "read2_write1_gbs": round(out[3], 1)}
+        best = {k: max(r[k] for r in res.values()) for k in ("read_gbs", "write_gbs", "copy_gbs", "read2_write1_gbs")}
+        print(json.dumps({"stream_probe": {"buffer_bytes": 1 << 30, "by_grid": res, "best": best,
+                                           "peak_gbs": HBM_PEAK_GBS}}), flush=True)
+        return
     if args.copy_calibration:
         torch.cuda.set_device(0)
         n = 1 << 28
@@ -514,73 +773,8 @@ def main():
     if cfg.get("adaptive"):
         print(json.dumps(run_adaptive_workload(cfg, args, torch, np, frmi, inputs)), flush=True)
         return
-    mesh = build_mesh(cfg, inputs)
-
-    def ic(xsol):
-        s = inputs.tgv(xsol[..., 0], xsol[..., 1], xsol[..., 2], mach=cfg["mach"])
-        return np.moveaxis(s, 0, 1).copy()
-
     forms = [f.strip() for f in (args.forms or cfg.get("forms", "fp32,fp64")).split(",") if f.strip()]
-    runs = {f: run_form(f, cfg, mesh, ic, args, torch, np, frmi, inputs) for f in forms}
-    head = runs[forms[0]]
-    blocks = head["blocks"]
-    E = sum(b[0] for b in blocks.values())
-    dof = sum(b[0] * b[1] for b in blocks.values())
-    nsp = blocks["hex"][1] if "hex" in blocks else blocks["tet"][1]
-
-    def kbytes(k):
-        b = blocks.get(k.split("_", 1)[0])
-        if b is None:
-            return None
-        per = kernel_bytes_per_elem(k, b[1], b[2])
-        return None if per is None else per * b[0]
-    gdofs = {f: 4 * dof / (r["ms"] * 1e-3) / 1e9 for f, r in runs.items()}
-    out = {
-        "metric": "RHS GDoF/s (FP32/learned vs FP64 plain) at stated L2 error; % HBM roofline",
-        "value": round(gdofs[forms[0]], 4), "unit": "GDoF/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(head["ms"], 4), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": {"fp32": "f32", "bf16x3": "f32+bf16x3"}.get(forms[0].split(":")[0], "f64"), "data": "synthetic",
-        "config": {"workload": args.config, "elements": int(E), "order": cfg["order"],
-                   "blocks": {k: {"elements": v[0], "points_per_elem": v[1]} for k, v in blocks.items()},
-                   "dof": int(dof), "rhs_per_step": 4, "form": forms[0],
-                   "rk_accumulation": "f64", "state_finite_after": bool(head["finite"]),
-                   "wall_s_timed": round(head["wall"], 3)},
-        "forms": {f: {"gdof_s": round(gdofs[f], 4), "ms_per_step": round(runs[f]["ms"], 4)} for f in forms},
-    }
-    for f in forms:
-        if "filter" in runs[f]:
-            out["forms"][f]["filter_on_final_state"] = runs[f]["filter"]
-    # each reduced-precision form against the first FP64 form of the same run (the FP64 form
-    # is the one the parity tests pin to the oracle): the RHS of the initial state, and the
-    # solution after the same number of RK4 steps
-    ref = next((f for f in forms if f.split(":")[0] == "fp64"), None)
-    if ref is not None:
-        r64, u64 = runs[ref]["rhs0"], runs[ref]["u_final"]
-        for f in forms:
-            if f.split(":")[0] == "fp64":
-                continue
-            rr, uu = runs[f]["rhs0"], runs[f]["u_final"]
-            out["forms"][f]["rhs_rel_l2_vs_fp64_form"] = float(torch.linalg.norm(rr - r64) / torch.linalg.norm(r64))
-            out["forms"][f]["rhs_rel_l2_vs_fp64_form_per_var"] = _per_var_err(rr, r64, runs[f]["blocks"], torch)
-            out["forms"][f]["solution_rel_l2_vs_fp64_form"] = {
-                "against": ref, "steps": runs[f]["steps_total"],
-                "value": float(torch.linalg.norm(uu - u64) / torch.linalg.norm(u64))}
-    if not args.no_kernel_timing:
-        times = head["times"]
-        fam = {k: v for k, v in times.items() if kbytes(k) is not None}
-        dom = max(fam, key=lambda k: fam[k][1])
-        launches, tot = fam[dom]
-        avg_ms = tot / launches
-        by = kbytes(dom)
-        achieved = by / (avg_ms * 1e-3) / 1e9
-        traffic = load_traffic(dom, args.config)
-        out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                           "kernel": dom, "avg_launch_ms": round(avg_ms, 4), "bytes_per_launch": int(by)}
-        for f in forms:
-            out["forms"][f]["kernels_ms_per_step"] = {k: round(v[1] / 2, 4) for k, v in sorted(runs[f]["times"].items())}
-            bpd = 80 if f.startswith("fp64") else 40
-            out["forms"][f]["rhs_m0_fraction"] = round(4 * dof * bpd / (runs[f]["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+    out, mesh = run_tgv_workload(args.config, cfg, forms, args, torch, np, frmi, inputs)
     if cfg.get("kind") == "curved":
         # a uniform stream on the same curved mesh, both metrics (FP64): the conservative
         # metric keeps it (R at rounding level), the cross-product metric does not once its
@@ -596,22 +790,21 @@ def main():
             fs[name] = float(torch.max(torch.abs(ctx.unpack_rhs(r))).item())
             ctx.close()
         out["free_stream_max_abs_rhs"] = fs
-    if not args.no_cpu_baseline and not cfg.get("oracle_ok", False):
-        out["cpu_baseline"] = None
-        out["cpu_baseline_note"] = ("the FP64 oracle on this workload takes minutes and tens of GB; "
-                                    "it is timed on the default workload")
-    elif not args.no_cpu_baseline:
-        base, uo, Ro = cpu_baseline(mesh, cfg, ic)
-        out["cpu_baseline"] = base
-        for f in forms:
-            ctx = runs[f]["ctx"]
-            ug = ctx.pack(uo[0].ravel())
-            rg = ctx.new_native()
-            ctx.rhs(ug, rg)
-            got = ctx.unpack_rhs(rg).cpu().numpy().reshape(Ro[0].shape)
-            err = np.sqrt(((got - Ro[0]) ** 2).sum(axis=(0, 2)) / (Ro[0] ** 2).sum(axis=(0, 2)))
-            out["forms"][f]["rhs_rel_l2_vs_oracle"] = float(np.linalg.norm(got - Ro[0]) / np.linalg.norm(Ro[0]))
-            out["forms"][f]["rhs_rel_l2_per_var"] = [float(v) for v in err]
+    del mesh
+    if args.config == "ns_tgv_mixed_c5split_p4" and not args.no_extras and args.forms is None:
+        # the other two headline-adjacent workloads, each with its own forms, as extra keys
+        extras = {}
+        sub = argparse.Namespace(**vars(args))
+        sub.steps, sub.warmup = max(args.steps, 20), min(args.warmup, 3)
+        c2 = CONFIGS["ns_tgv_hex32_p3"]
+        extras["ns_tgv_hex32_p3"] = run_tgv_workload("ns_tgv_hex32_p3", c2, ["fp32", "fp64"], sub, torch, np,
+                                                     frmi, inputs, with_cpu=False)[0]
+        extras["euler_shock_hex48_p3"] = run_filter_workload(CONFIGS["euler_shock_hex48_p3"], sub, torch, np,
+                                                             frmi, inputs)
+        for v in extras.values():
+            for k in ("metric", "n_gpus", "higher_is_better", "scaling", "vs_baseline", "data", "unit"):
+                v.pop(k, None)
+        out["extra_workloads"] = extras
     print(json.dumps(out), flush=True)
 
 

@@ -1,4 +1,5 @@
-"""Build libfrmi.so (HIP kernels for gfx950 + C++ host setup) in the package directory.
+"""Build libfrmi.so (HIP kernels for gfx950 + C++ host setup) and libfrprobe.so (the
+benchmark's HBM streaming probe) in the package directory.
 
 Usage: python -m paper_2408_16509_amd.build  (or call build()).  Always recompiles.
 """
@@ -28,17 +29,25 @@ def hipcc():
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False) -> str:
-    srcs = [os.path.join(CSRC, "frmi.hip"), os.path.join(CSRC, "setup.cpp")]
-    tmp = LIB + ".tmp"
+PROBE_LIB = os.path.join(HERE, "libfrprobe.so")
+
+
+def _hipcc(srcs, out, verbose):
+    tmp = out + ".tmp"
     cmd = [hipcc()] + HIPCC_FLAGS + ["-I", os.path.join(HERE, "..", "include")] + srcs + ["-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libfrmi.so")
-    os.replace(tmp, LIB)
+        raise RuntimeError(f"hipcc failed building {os.path.basename(out)}")
+    os.replace(tmp, out)
+
+
+def build(verbose: bool = False) -> str:
+    """libfrmi.so (the FR library) and libfrprobe.so (the benchmark's streaming probe)."""
+    _hipcc([os.path.join(CSRC, "frmi.hip"), os.path.join(CSRC, "setup.cpp")], LIB, verbose)
+    _hipcc([os.path.join(CSRC, "stream_probe.hip")], PROBE_LIB, verbose)
     return LIB
 
 

@@ -48,3 +48,25 @@ def test_workloads_and_one_gpu_rule():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode != 0 and "one GPU" in (r.stdout + r.stderr)
+
+
+def test_roofline_uses_the_m0_bytes_of_the_dominant_kernels_block():
+    blocks = {"hex": (131072, 125, 150), "tet": (786432, 35, 60)}
+    times = {"tet_grad_f32": (8, 19.6), "hex_grad_f32_p4": (8, 7.3), "rk4_update_f32": (8, 30.0)}
+    r = bench.roofline_for(times, blocks, "fp32:learned")
+    assert r["kernel"] == "tet_grad_f32"
+    m0 = 40 * 786432 * 35
+    assert r["bytes_per_launch_m0"] == m0
+    assert abs(r["achieved"] - m0 / (19.6 / 8 * 1e-3) / 1e9) < 0.1
+    assert abs(r["frac"] - r["achieved"] / 8000.0) < 1e-4
+    assert r["kernel_model_bytes_per_launch"] == bench.kernel_bytes_per_elem("tet_grad_f32", 35, 60) * 786432
+    r64 = bench.roofline_for({"tet_grad": (8, 30.0)}, blocks, "fp64:plain")
+    assert r64["bytes_per_launch_m0"] == 80 * 786432 * 35
+
+
+def test_cpu_baseline_sample_runs_the_oracle():
+    from paper_2408_16509_amd import inputs
+    cfg = dict(bench.CONFIGS["ns_tgv_mixed_c5split_p4"], oracle_sample=(1, 2, 2))
+    b = bench.cpu_baseline_sample(cfg, inputs)
+    assert b["kind"] == "oracle" and b["unit"] == "GDoF/s" and b["value"] > 0 and b["cores"] >= 1
+    assert "4 hexahedra" in b["sample"] and "24 tetrahedra" in b["sample"]

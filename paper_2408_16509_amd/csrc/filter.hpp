@@ -59,9 +59,15 @@ struct Dev32 {
 //   s32 = (float)(s - ref) (the FP32 form's deviation); the pass checks s;
 //   last stage (mode 2): u = acc + b k (in place), s32 as above; the pass checks u.
 // stage() recomputes s for the candidates' FP64 copy (the same fused multiply-adds).
+// Both take a value in two steps, so a caller can issue the loads of several values
+// before any of them is used: raw(i) reads what the value needs, value(i, v, raw)
+// forms it (and performs the update's stores).
 struct PlainSrc {
   const double* __restrict__ u;
-  __device__ __forceinline__ double operator()(int64_t i, int) const { return u[i]; }
+  struct Raw { double x; };
+  __device__ __forceinline__ Raw raw(int64_t i) const { return Raw{u[i]}; }
+  __device__ __forceinline__ double value(int64_t, int, const Raw& r) const { return r.x; }
+  __device__ __forceinline__ double operator()(int64_t i, int v) const { return value(i, v, raw(i)); }
 };
 template <typename KT>
 struct RkStageSrc {
@@ -73,22 +79,25 @@ struct RkStageSrc {
   double b, c;
   int mode;
   double ref[5];
+  struct Raw { double x, a; double k; };
   __device__ __forceinline__ double stage(int64_t i) const { return fma(c, (double)k[i], u[i]); }
-  __device__ __forceinline__ double operator()(int64_t i, int v) const {
-    const double ki = (double)k[i];
+  __device__ __forceinline__ Raw raw(int64_t i) const {
+    return Raw{mode == 2 ? 0.0 : u[i], mode == 0 ? 0.0 : acc[i], (double)k[i]};
+  }
+  __device__ __forceinline__ double value(int64_t i, int v, const Raw& r) const {
     if (mode == 2) {
-      const double un = fma(b, ki, acc[i]);
+      const double un = fma(b, r.k, r.a);
       u[i] = un;
       if (s32) s32[i] = (float)(un - ref[v]);
       return un;
     }
-    const double ui = u[i];
-    acc[i] = fma(b, ki, mode == 0 ? ui : acc[i]);
-    const double si = fma(c, ki, ui);
+    acc[i] = fma(b, r.k, mode == 0 ? r.x : r.a);
+    const double si = fma(c, r.k, r.x);
     if (s64) s64[i] = si;
     if (s32) s32[i] = (float)(si - ref[v]);
     return si;
   }
+  __device__ __forceinline__ double operator()(int64_t i, int v) const { return value(i, v, raw(i)); }
 };
 
 __device__ __forceinline__ double entropy_of(double rho, double p, double gamma) {
@@ -156,13 +165,24 @@ __device__ __forceinline__ void hex_tile_checks(const Src& src, double* U, int64
   const int el = threadIdx.x % NE, l = threadIdx.x / NE, c0 = l % N1, c1 = l / N1;
   const int64_t e = e0 + el;
   double m[5] = {0, 0, 0, 0, 0}, pl[5] = {0, 0, 0, 0, 0};
+  // the column's reads are issued point by point ahead of their use: the raw values of
+  // the next point load while the current one is formed, stored and checked
+  typename Src::Raw rw[5], rn[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) rn[v] = src.raw(((int64_t)(c0 + N1 * c1) * 5 + v) * E + e);
 #pragma unroll
   for (int a = 0; a < N1; ++a) {
     const int pt = c0 + N1 * (c1 + N1 * a);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) rw[v] = rn[v];
+    if (a + 1 < N1) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) rn[v] = src.raw(((int64_t)(pt + N1 * N1) * 5 + v) * E + e);
+    }
     double w[5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-      w[v] = src(((int64_t)pt * 5 + v) * E + e, v);
+      w[v] = src.value(((int64_t)pt * 5 + v) * E + e, v, rw[v]);
       U[(v * NSP + pt) * NE + el] = w[v];
       m[v] += K.lm[a] * w[v];
       pl[v] += K.lp[a] * w[v];

@@ -597,13 +597,37 @@ __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_grad_lines(
 #pragma unroll
       for (int j = 0; j < 3; ++j) sJ[d][a][j] = s[j] * iJ;
     }
+  // the line values (and the partner traces the common value needs) of the next
+  // (variable, direction) are loaded before the current one is worked on, so the loads
+  // of one step overlap the arithmetic and the barrier of the previous one
+  bool need[3][2];
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+#pragma unroll
+    for (int sd = 0; sd < 2; ++sd)
+      // the common value equals the own trace when the switch points at this side
+      need[d][sd] = side_mode == 0 || (side_mode > 0 ? !ns[d][sd].left : ns[d][sd].left);
+  T nuv[N1], nun[2];
+  auto load_line = [&](int v, int d) {
+#pragma unroll
+    for (int a = 0; a < N1; ++a) nuv[a] = u[((int64_t)line_pt<N1>(d, a, t0, t1) * 5 + v) * E + e];
+#pragma unroll
+    for (int sd = 0; sd < 2; ++sd)
+      nun[sd] = need[d][sd] ? uf[((int64_t)ns[d][sd].fp * 5 + v) * E + ns[d][sd].elem] : T(0);
+  };
+  load_line(0, 0);
   for (int v = 0; v < 5; ++v) {
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      T uv[N1], tm = 0, tp = 0;
+      T uv[N1], unb[2], tm = 0, tp = 0;
+#pragma unroll
+      for (int a = 0; a < N1; ++a) uv[a] = nuv[a];
+      unb[0] = nun[0];
+      unb[1] = nun[1];
+      if (d < 2) load_line(v, d + 1);
+      else if (v < 4) load_line(v + 1, 0);
 #pragma unroll
       for (int a = 0; a < N1; ++a) {
-        uv[a] = u[((int64_t)line_pt<N1>(d, a, t0, t1) * 5 + v) * E + e];
         tm += K.lm[a] * uv[a];
         tp += K.lp[a] * uv[a];
       }
@@ -612,12 +636,9 @@ __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_grad_lines(
       for (int sd = 0; sd < 2; ++sd) {
         const NbrSlot& s = ns[d][sd];
         const T own = sd ? tp : tm;
-        // the common value equals the own trace when the switch points at this side
-        const bool need = side_mode == 0 || (side_mode > 0 ? !s.left : s.left);
-        T un = own;
-        if (need) un = uf[((int64_t)s.fp * 5 + v) * E + s.elem];
+        const T un = need[d][sd] ? unb[sd] : own;
         const T uL = s.left ? own : un, uR = s.left ? un : own;
-        uh[sd] = need ? T(0.5) * (uL + uR) + beta * (uL - uR) : own;
+        uh[sd] = need[d][sd] ? T(0.5) * (uL + uR) + beta * (uL - uR) : own;
       }
 #pragma unroll
       for (int a = 0; a < N1; ++a) {
@@ -657,8 +678,7 @@ __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_grad_lines(
 #pragma unroll
       for (int sd = 0; sd < 2; ++sd) {
         // stored only where a neighbour will read it
-        const bool keep = side_mode == 0 || (side_mode > 0 ? !ns[d][sd].left : ns[d][sd].left);
-        if (!keep) continue;
+        if (!need[d][sd]) continue;
         const int f = (2 * d + sd) * NF + l;
 #pragma unroll
         for (int j = 0; j < 3; ++j) gradf[((int64_t)f * 15 + v * 3 + j) * E + e] = sd ? gp[j] : gm[j];

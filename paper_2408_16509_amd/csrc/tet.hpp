@@ -231,6 +231,21 @@ __global__ void __launch_bounds__(TDIV_NT) tet_div(const T* __restrict__ u, cons
   const T gm1 = gamma - T(1);
   const int64_t e0 = xcd_block() * NE;
   {
+    // The connectivity of this thread's flux points (FCIN) is read before anything
+    // waits, the stored common fluxes right after chunk 1 is evaluated (both ahead of
+    // their use in chunk 2, so their latency overlaps chunk 1's products).
+    constexpr int NI2 = (NE * TET_NFP + NT - 1) / NT;
+    int inf[FCIN ? NI2 : 1], nel[FCIN ? NI2 : 1];
+    if constexpr (FCIN) {
+#pragma unroll
+      for (int j = 0; j < NI2; ++j) {
+        const int it = t + j * NT;
+        const int face = (it / NE) / TET_NFPF;
+        const int64_t e = e0 + it % NE;
+        inf[j] = it < NE * TET_NFP ? C.nbr_info[(int64_t)face * E + e] : 0;
+        nel[j] = it < NE * TET_NFP ? C.nbr_elem[(int64_t)face * E + e] : 0;
+      }
+    }
     for (int i = t; i < 10 * NE; i += NT) SJ[i] = geo[(int64_t)(i / NE) * E + e0 + i % NE];
     for (int i = t; i < (KA - 105) * 5 * NE; i += NT) PAN[105 * 5 * NE + i] = T(0);
     __syncthreads();
@@ -238,8 +253,8 @@ __global__ void __launch_bounds__(TDIV_NT) tet_div(const T* __restrict__ u, cons
     for (int it = t; it < NE * TET_NSP; it += NT) {
       const int el = it % NE, pt = it / NE;
       const int64_t e = e0 + el;
-      T w[5], gg[15];
-      tet_load(u, E, e, pt, w);
+      T wv[5], gg[15];
+      tet_load(u, E, e, pt, wv);
       if constexpr (NS) {
 #pragma unroll
         for (int k = 0; k < 15; ++k) gg[k] = grad[((int64_t)pt * 15 + k) * E + e];
@@ -248,15 +263,34 @@ __global__ void __launch_bounds__(TDIV_NT) tet_div(const T* __restrict__ u, cons
       for (int i = 0; i < 3; ++i) {
         const T sx = SJ[(3 * i) * NE + el], sy = SJ[(3 * i + 1) * NE + el], sz = SJ[(3 * i + 2) * NE + el];
         T f[5], vs, prs;
-        Flux<T, DEV>::eval(w, sx, sy, sz, gm1, R, f, vs, prs);
+        Flux<T, DEV>::eval(wv, sx, sy, sz, gm1, R, f, vs, prs);
         if constexpr (NS) {
           T fv[5];
-          viscous<T, DEV>(w, gg, sx, sy, sz, gamma, mu, pr, R, fv);
+          viscous<T, DEV>(wv, gg, sx, sy, sz, gamma, mu, pr, R, fv);
 #pragma unroll
           for (int c = 0; c < 5; ++c) f[c] -= fv[c];
         }
 #pragma unroll
         for (int c = 0; c < 5; ++c) PAN[((i * TET_NSP + pt) * 5 + c) * NE + el] = f[c];
+      }
+    }
+    // the common fluxes formed by the gradient kernel, read from the slot of the side
+    // that formed each (own or the partner's) ahead of chunk 1's products
+    T fcv[FCIN ? NI2 : 1][5];
+    bool lft[FCIN ? NI2 : 1];
+    if constexpr (FCIN) {
+#pragma unroll
+      for (int j = 0; j < NI2; ++j) {
+        const int it = t + j * NT;
+        const int sg = it / NE;
+        const int nf = inf[j] & 7, orient = (inf[j] >> 3) & 511;
+        lft[j] = (inf[j] >> 12) & 1;
+        const bool own = lft[j] != (side_mode > 0);
+        const bool ok = it < NE * TET_NFP;      // invalid items keep in-bounds addresses
+        const int64_t fe = !ok ? e0 : (own ? e0 + it % NE : (int64_t)nel[j]);
+        const int fp = !ok ? 0 : (own ? sg : nf * TET_NFPF + C.perm[orient * C.perm_stride + sg % TET_NFPF]);
+#pragma unroll
+        for (int c = 0; c < 5; ++c) fcv[j][c] = it < NE * TET_NFP ? fcin[((int64_t)fp * 5 + c) * E + fe] : T(0);
       }
     }
     __syncthreads();
@@ -268,31 +302,32 @@ __global__ void __launch_bounds__(TDIV_NT) tet_div(const T* __restrict__ u, cons
     // K chunk 2: common fluxes at the flux points (rows past 60 zero)
     if constexpr (KB > TET_NFP)
       for (int i = t; i < (KB - TET_NFP) * 5 * NE; i += NT) PAN[TET_NFP * 5 * NE + i] = T(0);
-    for (int it = t; it < NE * TET_NFP; it += NT) {
-      const int el = it % NE, sg = it / NE;
-      T S[9], F[5];
+    if constexpr (FCIN) {
 #pragma unroll
-      for (int k = 0; k < 9; ++k) S[k] = SJ[k * NE + el];
-      if constexpr (FCIN) {
-        const int face = sg / TET_NFPF;
-        const int64_t e = e0 + el;
-        const NbrSlot ns = nbr_slot<TET_NFPF>(C, E, e, face, sg % TET_NFPF);
-        // the slot of the side that formed the flux: own, or the partner's
-        const bool own = ns.left != (side_mode > 0);
-        const int64_t fe = own ? e : ns.elem;
-        const int fp = own ? sg : ns.fp;
-        T nv[3];
+      for (int j = 0; j < NI2; ++j) {
+        const int it = t + j * NT;
+        if (it >= NE * TET_NFP) continue;
+        const int el = it % NE, sg = it / NE, face = sg / TET_NFPF;
+        T S[9], nv[3];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) S[k] = SJ[k * NE + el];
         tet_normal(S, O, face, nv);
         const T mag = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
-        const T fs = ns.left ? mag : -mag;
+        const T fs = lft[j] ? mag : -mag;
 #pragma unroll
-        for (int c = 0; c < 5; ++c) F[c] = fcin[((int64_t)fp * 5 + c) * E + fe] * fs;
-      } else {
+        for (int c = 0; c < 5; ++c) PAN[(sg * 5 + c) * NE + el] = fcv[j][c] * fs;
+      }
+    } else {
+      for (int it = t; it < NE * TET_NFP; it += NT) {
+        const int el = it % NE, sg = it / NE;
+        T S[9], F[5];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) S[k] = SJ[k * NE + el];
         tet_common_flux<T, DEV, NS>(u, grad, S, C, O, E, e0 + el, sg, gamma, mu, pr, beta, tau, riemann, side_mode,
                                     R, F);
-      }
 #pragma unroll
-      for (int c = 0; c < 5; ++c) PAN[(sg * 5 + c) * NE + el] = F[c];
+        for (int c = 0; c < 5; ++c) PAN[(sg * 5 + c) * NE + el] = F[c];
+      }
     }
     __syncthreads();
     if (w >= 3) return;
@@ -404,40 +439,71 @@ __global__ void __launch_bounds__(tgr_nt<T>()) __attribute__((amdgpu_waves_per_e
         PAN[(zr == 0 ? TET_NSP : TGS_U + 16 * zr - 1) * 5 * NE + i % (5 * NE)] = T(0);
       }
     }
-    for (int i = t; i < TET_NSP * 5 * NE; i += NT) PAN[i] = u[(int64_t)(i / NE) * E + e0 + i % NE];
+    // Every global read of the gather is issued before the first wait: the block's state
+    // (NU values per thread) and the connectivity of this thread's flux points (NI items
+    // (el, sg) per thread), then the partners' states, so each block waits on about two
+    // memory latencies instead of one per loop trip.
+    constexpr int NU = (TET_NSP * 5 * NE + NT - 1) / NT, NI = (TET_NFP * NE + NT - 1) / NT;
+    T ur[NU];
+#pragma unroll
+    for (int j = 0; j < NU; ++j) {
+      const int i = t + j * NT;
+      ur[j] = i < TET_NSP * 5 * NE ? u[(int64_t)(i / NE) * E + e0 + i % NE] : T(0);
+    }
+    int inf[NI], nel[NI];
+#pragma unroll
+    for (int j = 0; j < NI; ++j) {
+      const int it = t + j * NT;
+      const int face = (it / NE) / TET_NFPF;
+      const int64_t e = e0 + it % NE;
+      inf[j] = it < TET_NFP * NE ? C.nbr_info[(int64_t)face * E + e] : 0;
+      nel[j] = it < TET_NFP * NE ? C.nbr_elem[(int64_t)face * E + e] : 0;
+    }
     if constexpr (FC)
       for (int i = t; i < TET_NSP * 4; i += NT) PFP[i] = O.pfp[i];
+#pragma unroll
+    for (int j = 0; j < NU; ++j) {
+      const int i = t + j * NT;
+      if (i < TET_NSP * 5 * NE) PAN[i] = ur[j];
+    }
+    // partners' states where the common solution needs them
+    T un[NI][5];
+    bool lft[NI], fromn[NI];
+#pragma unroll
+    for (int j = 0; j < NI; ++j) {
+      const int it = t + j * NT;
+      const int sg = it / NE;
+      const int nf = inf[j] & 7, orient = (inf[j] >> 3) & 511;
+      lft[j] = (inf[j] >> 12) & 1;
+      fromn[j] = it < TET_NFP * NE && (side_mode == 0 || (side_mode > 0) != lft[j]);
+      const int nfp = nf * TET_NFPF + C.perm[orient * C.perm_stride + sg % TET_NFPF];
+      const int src = O.src[fromn[j] ? nfp : 0];
+      const int64_t ne = fromn[j] ? (int64_t)nel[j] : e0;
+#pragma unroll
+      for (int c = 0; c < 5; ++c) un[j][c] = fromn[j] ? u[((int64_t)src * 5 + c) * E + ne] : T(0);
+    }
     __syncthreads();
-    for (int it = t; it < TET_NFP * NE; it += NT) {
+#pragma unroll
+    for (int j = 0; j < NI; ++j) {
+      const int it = t + j * NT;
+      if (it >= TET_NFP * NE) continue;
       const int el = it % NE, sg = it / NE;
-      const int64_t e = e0 + el;
-      const int face = sg / TET_NFPF, q = sg % TET_NFPF;
-      const NbrSlot ns = nbr_slot<TET_NFPF>(C, E, e, face, q);
       const int so = O.src[sg];
       const int row = BF3 ? TET_NSP + sg : tgs_row(sg);
-      if constexpr (FC) SIDE[sg * NE + el] = (ns.left ? 1 : 0) | (ns.left != (side_mode > 0) ? 2 : 0);
-      if (side_mode != 0) {
-        // one-sided: u^ is exactly the state of the side named by beta, so the partner's
-        // state is read only where that side is the partner (half of the flux points)
-        const bool from_nbr = (side_mode > 0) != ns.left;
-        T uh[5];
-        if (from_nbr) {
-          tet_load(u, E, ns.elem, O.src[ns.fp], uh);
+      if constexpr (FC) SIDE[sg * NE + el] = (lft[j] ? 1 : 0) | (lft[j] != (side_mode > 0) ? 2 : 0);
+#pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        const T own = PAN[(so * 5 + c) * NE + el];
+        T val;
+        if (side_mode != 0) {
+          // one-sided: u^ is exactly the state of the side named by beta, so the partner's
+          // state was read only where that side is the partner (half of the flux points)
+          val = fromn[j] ? un[j][c] : own;
         } else {
-#pragma unroll
-          for (int c = 0; c < 5; ++c) uh[c] = PAN[(so * 5 + c) * NE + el];
+          const T uL = lft[j] ? own : un[j][c], uR = lft[j] ? un[j][c] : own;
+          val = T(0.5) * (uL + uR) + beta * (uL - uR);
         }
-#pragma unroll
-        for (int c = 0; c < 5; ++c) PAN[(row * 5 + c) * NE + el] = uh[c];
-      } else {
-        T un[5];
-        tet_load(u, E, ns.elem, O.src[ns.fp], un);
-#pragma unroll
-        for (int c = 0; c < 5; ++c) {
-          const T own = PAN[(so * 5 + c) * NE + el];
-          const T uL = ns.left ? own : un[c], uR = ns.left ? un[c] : own;
-          PAN[(row * 5 + c) * NE + el] = T(0.5) * (uL + uR) + beta * (uL - uR);
-        }
+        PAN[(row * 5 + c) * NE + el] = val;
       }
     }
     __syncthreads();

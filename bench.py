@@ -128,11 +128,12 @@ def kernel_bytes_per_elem(name, nsp, nfp):
         "tet_div_ns": d * (5 * nsp + 15 * nsp + 5 * nsp) + tet_gc,
     }
     if d == 4:
-        # FP32 form, one-sided LDG: the gradient kernel also stores the common flux of
-        # each flux-point pair once (half of the flux points), the divergence kernel
-        # reads it for all of its flux points
-        table["tet_grad"] += d * 5 * nfp // 2
-        table["tet_div_ns"] += d * 5 * nfp
+        # FP32 form, one-sided LDG: the gradient kernel stores the transformed viscous flux
+        # S_i . f_v (12 values per point) instead of the gradient (15) and the common flux
+        # of each flux-point pair once (half of the flux points); the divergence kernel
+        # reads both, the common flux for all of its flux points
+        table["tet_grad"] = d * (5 * nsp + 12 * nsp + 5 * nfp // 2) + tet_gc
+        table["tet_div_ns"] = d * (5 * nsp + 12 * nsp + 5 * nsp + 5 * nfp) + tet_gc
     return table.get(fam)
 
 

@@ -68,6 +68,7 @@ struct PlainSrc {
   __device__ __forceinline__ Raw raw(int64_t i) const { return Raw{u[i]}; }
   __device__ __forceinline__ double value(int64_t, int, const Raw& r) const { return r.x; }
   __device__ __forceinline__ double operator()(int64_t i, int v) const { return value(i, v, raw(i)); }
+  __device__ __forceinline__ double peek(int64_t i) const { return u[i]; }
 };
 template <typename KT>
 struct RkStageSrc {
@@ -81,6 +82,11 @@ struct RkStageSrc {
   double ref[5];
   struct Raw { double x, a; double k; };
   __device__ __forceinline__ double stage(int64_t i) const { return fma(c, (double)k[i], u[i]); }
+  // the value value() forms, read without side effects from what the update leaves
+  // unchanged (u_n and k in the stages, the accumulator and k in the last one)
+  __device__ __forceinline__ double peek(int64_t i) const {
+    return mode == 2 ? fma(b, (double)k[i], acc[i]) : fma(c, (double)k[i], u[i]);
+  }
   __device__ __forceinline__ Raw raw(int64_t i) const {
     return Raw{mode == 2 ? 0.0 : u[i], mode == 0 ? 0.0 : acc[i], (double)k[i]};
   }
@@ -558,6 +564,95 @@ __global__ void __launch_bounds__(HexTileCfg<P>::NT) hex_filter_detect(Src src, 
     const int pt = c0 + C::N1 * (c1 + C::N1 * a);
 #pragma unroll
     for (int v = 0; v < 5; ++v) cand64[((int64_t)pt * 5 + v) * E + e] = U[(v * NSP + pt) * C::NE + el];
+  }
+}
+
+// Detection without LDS staging: one wave per (64-element tile, column (c0, c1)), lanes
+// over consecutive elements, so every row the wave touches is a 64-element (512-byte
+// FP64) segment.  The thread checks its own column (the line along xi_3: its points and
+// both ends, every value once through src, which performs the RK stage update if any)
+// and the ends of the lines along xi_1 through (c0, c1) = (j, k) and along xi_2 through
+// (i, k) = (c0, c1), whose values it reads through src.peek (no side effects; the
+// other lines' owners update them) -- every solution point once and every face flux
+// point once per element, as in the tiled detection.  flag[e] = 1 for elements that may
+// fail (flag cleared before).
+template <int P, typename Src>
+__global__ void __launch_bounds__(256) hex_filter_detect_lines(Src src, const double* __restrict__ smin_a,
+                                                               int64_t E, int64_t n, FiltK K, FiltPrm F,
+                                                               int32_t* __restrict__ flag) {
+  constexpr int N1 = P + 1, NC = N1 * N1;
+  const int64_t gtid = xcd_block() * 256 + threadIdx.x;
+  const int64_t wave = gtid >> 6;
+  const int lane = (int)(gtid & 63);
+  const int64_t tile = wave / NC;
+  const int l = (int)(wave % NC), c0 = l % N1, c1 = l / N1;
+  const int64_t e = tile * 64 + lane;
+  if (e >= E) return;                   // E is a multiple of 64: whole waves only
+  const double smin = e < n ? smin_a[e] : 0.0;
+  const double sb = smin - F.eps_s * fabs(smin);
+  const double sbm = sb + 1e-10 * fabs(sb);
+  const double lsb = sbm > 0 ? log(sbm) : -INFINITY;
+  bool bad = false;
+  // own column: raw values of the next point in flight while the current one is formed
+  double m[5] = {0, 0, 0, 0, 0}, pl[5] = {0, 0, 0, 0, 0};
+  typename Src::Raw rw[5], rn[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) rn[v] = src.raw(((int64_t)(c0 + N1 * c1) * 5 + v) * E + e);
+#pragma unroll
+  for (int a = 0; a < N1; ++a) {
+    const int pt = c0 + N1 * (c1 + N1 * a);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) rw[v] = rn[v];
+    if (a + 1 < N1) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) rn[v] = src.raw(((int64_t)(pt + NC) * 5 + v) * E + e);
+    }
+    double w[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      w[v] = src.value(((int64_t)pt * 5 + v) * E + e, v, rw[v]);
+      m[v] += K.lm[a] * w[v];
+      pl[v] += K.lp[a] * w[v];
+    }
+    bad = bad || maybe_violates(w, lsb, F);
+  }
+  bad = bad || maybe_violates(m, lsb, F) || maybe_violates(pl, lsb, F);
+  // the xi_1 line through (j, k) = (c0, c1) and the xi_2 line through (i, k) = (c0, c1)
+#pragma unroll
+  for (int d = 0; d < 2; ++d) {
+    double x[N1][5];
+#pragma unroll
+    for (int a = 0; a < N1; ++a) {
+      const int pt = d == 0 ? a + N1 * (c0 + N1 * c1) : c0 + N1 * (a + N1 * c1);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) x[a][v] = src.peek(((int64_t)pt * 5 + v) * E + e);
+    }
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      m[v] = 0;
+      pl[v] = 0;
+#pragma unroll
+      for (int a = 0; a < N1; ++a) {
+        m[v] += K.lm[a] * x[a][v];
+        pl[v] += K.lp[a] * x[a][v];
+      }
+    }
+    bad = bad || maybe_violates(m, lsb, F) || maybe_violates(pl, lsb, F);
+  }
+  if (bad && e < n) flag[e] = 1;
+}
+
+// FP64 stage state u + c k of the candidates (the search's input in the FP32 form,
+// whose detection pass forms the stage state without storing it): one block of 256
+// threads per candidate, values in native layout.
+template <typename KT>
+__global__ void __launch_bounds__(256) k_cand_stage(RkStageSrc<KT> src, const int32_t* __restrict__ list,
+                                                    const int32_t* __restrict__ count, int nvals, int64_t E,
+                                                    double* __restrict__ cand64) {
+  const int cnt = *count;
+  for (int i = blockIdx.x; i < cnt; i += gridDim.x) {
+    const int64_t e = list[i];
+    for (int j = threadIdx.x; j < nvals; j += 256) cand64[(int64_t)j * E + e] = src.stage((int64_t)j * E + e);
   }
 }
 

@@ -508,6 +508,7 @@ fr_status tet_rhs(fr_ctx c, DevBlock& b, const T* u, T* r) {
   TetDev<T> O;
   O.src = c->tet_src;
   O.pfp = c->tet_src + 60;
+  O.slot = c->tet_src + 60 + 35 * 4;
   for (int f = 0; f < 4; ++f)
     for (int k = 0; k < 3; ++k) O.nref[f][k] = (T)c->host.tet.nref[f][k];
   const RefState<T> R = ref_of<T>(p);
@@ -718,21 +719,42 @@ void hex_candidates_p(fr_ctx c, DevBlock& b, const double* u, const StageFuse* f
   const int gf = grid_for(b.n, 256);
   int pk = c->prof_begin(fz ? "rk4_stage_filter_detect_hex" : "filter_detect");
   k_filter_reset<<<gf, 256, 0, c->stream>>>(b.f_det, c->f_k + o, c->f_evals + o, b.n);
-  const unsigned g = (unsigned)(b.E / HexTileCfg<P>::NE);
-  if (!fz)
-    hex_filter_detect<P, PlainSrc><<<g, HexTileCfg<P>::NT, 0, c->stream>>>(PlainSrc{u + b.native_off}, b.smin, b.E,
-                                                                           b.n, K, F, b.f_det, nullptr);
-  else if (fz->k32)
-    hex_filter_detect<P, RkStageSrc<float>><<<g, HexTileCfg<P>::NT, 0, c->stream>>>(
-        stage_src<float>(*fz, b, c->prm), b.smin, b.E, b.n, K, F, b.f_det,
-        fz->cand64 ? fz->cand64 + b.native_off : nullptr);
-  else
-    hex_filter_detect<P, RkStageSrc<double>><<<g, HexTileCfg<P>::NT, 0, c->stream>>>(
-        stage_src<double>(*fz, b, c->prm), b.smin, b.E, b.n, K, F, b.f_det,
-        fz->cand64 ? fz->cand64 + b.native_off : nullptr);
+  if constexpr (P == 4) {
+    // p = 4: a tile holds only 8 elements, so the tiled pass would move its rows in
+    // 64-byte segments; one wave per (64-element tile, column) reads whole 512-byte rows
+    // and the line ends through L2 (0.78 -> 0.72 ms per stage on the mixed workload).
+    // At p <= 3 (16-64 elements a tile) the tiled pass is faster (1.43 against 1.63 ms
+    // per step on the 48^3 p = 3 shock).
+    const unsigned g = (unsigned)((b.E / 64 * (P + 1) * (P + 1) + 3) / 4);
+    if (!fz)
+      hex_filter_detect_lines<P, PlainSrc><<<g, 256, 0, c->stream>>>(PlainSrc{u + b.native_off}, b.smin, b.E,
+                                                                     b.n, K, F, b.f_det);
+    else if (fz->k32)
+      hex_filter_detect_lines<P, RkStageSrc<float>><<<g, 256, 0, c->stream>>>(stage_src<float>(*fz, b, c->prm),
+                                                                              b.smin, b.E, b.n, K, F, b.f_det);
+    else
+      hex_filter_detect_lines<P, RkStageSrc<double>><<<g, 256, 0, c->stream>>>(stage_src<double>(*fz, b, c->prm),
+                                                                               b.smin, b.E, b.n, K, F, b.f_det);
+  } else {
+    const unsigned g = (unsigned)(b.E / HexTileCfg<P>::NE);
+    if (!fz)
+      hex_filter_detect<P, PlainSrc><<<g, HexTileCfg<P>::NT, 0, c->stream>>>(PlainSrc{u + b.native_off}, b.smin,
+                                                                             b.E, b.n, K, F, b.f_det, nullptr);
+    else if (fz->k32)
+      hex_filter_detect<P, RkStageSrc<float>><<<g, HexTileCfg<P>::NT, 0, c->stream>>>(
+          stage_src<float>(*fz, b, c->prm), b.smin, b.E, b.n, K, F, b.f_det,
+          fz->cand64 ? fz->cand64 + b.native_off : nullptr);
+    else
+      hex_filter_detect<P, RkStageSrc<double>><<<g, HexTileCfg<P>::NT, 0, c->stream>>>(
+          stage_src<double>(*fz, b, c->prm), b.smin, b.E, b.n, K, F, b.f_det,
+          fz->cand64 ? fz->cand64 + b.native_off : nullptr);
+  }
   k_flag_count<<<nb, 256, 0, c->stream>>>(b.f_det, b.n, b.f_cnt);
   k_scan_counts<<<1, 1024, 0, c->stream>>>(b.f_cnt, nb);
   k_flag_scatter<<<nb, 256, 0, c->stream>>>(b.f_det, b.n, b.f_cnt, b.f_list);
+  if (P == 4 && fz && fz->cand64 && fz->k32)
+    k_cand_stage<float><<<(unsigned)std::max<int64_t>(1, std::min<int64_t>(b.n, 4096)), 256, 0, c->stream>>>(
+        stage_src<float>(*fz, b, c->prm), b.f_list, b.f_cnt + nb, b.nsp * 5, b.E, fz->cand64 + b.native_off);
   c->prof_end(pk);
 }
 
@@ -1192,19 +1214,48 @@ fr_status setup_impl(const fr_params* p, int64_t n_vert, const double* xyz, cons
         for (int sg = 0; sg < 60; ++sg)
           ogT[(size_t)(35 + sg) * TGR_M + TET_MP * i + pt] = T.lift[pt][sg] * T.nref[T.fp_face[sg]][i];
       }
+    // Output-row order of the gradient product: rows {16 w + 4 g + q : g = 0..3} are the
+    // ones the lanes of wave w visit together at step q of the common-flux loop, so points
+    // are grouped by their number of flux points (3, 2, 1, 0) into such quadruples, and
+    // the quadruples are dealt to the three waves so their loop trips balance.
+    std::vector<int> slot_pt(TET_MP, -1);
+    {
+      std::vector<int> order(35);
+      for (int z = 0; z < 35; ++z) order[z] = z;
+      auto nfp_of = [&](int z) { return src[60 + 4 * z]; };
+      std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return nfp_of(a) > nfp_of(b); });
+      order.resize(TET_MP, -1);
+      // 12 quadruples, costs = the largest flux-point count in each
+      std::vector<int> cost(12, 0);
+      for (int g = 0; g < 12; ++g)
+        for (int j = 0; j < 4; ++j) if (order[4 * g + j] >= 0) cost[g] = std::max(cost[g], nfp_of(order[4 * g + j]));
+      int load[3] = {0, 0, 0}, used[3] = {0, 0, 0};
+      for (int g = 0; g < 12; ++g) {            // costs are non-increasing in g
+        int wbest = -1;
+        for (int w = 0; w < 3; ++w)
+          if (used[w] < 4 && (wbest < 0 || load[w] < load[wbest])) wbest = w;
+        const int q = used[wbest]++;
+        load[wbest] += cost[g];
+        for (int j = 0; j < 4; ++j) slot_pt[16 * wbest + 4 * j + q] = order[4 * g + j];
+      }
+    }
+    std::vector<int> pt_slot(35, -1);
+    for (int r = 0; r < TET_MP; ++r) if (slot_pt[r] >= 0) pt_slot[slot_pt[r]] = r;
+    for (int r = 0; r < TET_MP; ++r) src.push_back(slot_pt[r]);
     // the same operator in the face-sparse row order of the FP32 / FP64 kernels (tgs_row):
     // direction i reads only the rows of faces 2 - i and 3, whose normals have an i component
     std::vector<double> ogS((size_t)TGS_K * TGR_M, 0.0);
     for (int i = 0; i < 3; ++i)
       for (int pt = 0; pt < 35; ++pt) {
-        for (int k = 0; k < 35; ++k) ogS[(size_t)k * TGR_M + TET_MP * i + pt] = T.Dh[i][pt][k];
+        for (int k = 0; k < 35; ++k) ogS[(size_t)k * TGR_M + TET_MP * i + pt_slot[pt]] = T.Dh[i][pt][k];
         for (int sg = 0; sg < 60; ++sg) {
           const int f = T.fp_face[sg];
           if (f != sg / TET_NFPF || ((f != 2 - i && f != 3) && T.nref[f][i] != 0.0)) {
             c->err = "tetrahedral flux points not ordered by face, or a face normal off the expected axes";
             return bail(FR_ERR_STATE);
           }
-          ogS[(size_t)(TGS_U + 16 * f + sg % TET_NFPF) * TGR_M + TET_MP * i + pt] = T.lift[pt][sg] * T.nref[f][i];
+          ogS[(size_t)(TGS_U + 16 * f + sg % TET_NFPF) * TGR_M + TET_MP * i + pt_slot[pt]] =
+              T.lift[pt][sg] * T.nref[f][i];
         }
       }
     std::vector<char> bog(ogS.size() * tsz);
@@ -1221,9 +1272,14 @@ fr_status setup_impl(const fr_params* p, int64_t n_vert, const double* xyz, cons
           bf16_split_host(opT[(size_t)(TET_KA + s2) * TET_MP + m], dh[(size_t)m * TET_KP16 + TET_KA16 + s2],
                           dh[dlo + (size_t)m * TET_KP16 + TET_KA16 + s2]);
       }
-      for (int m = 0; m < TGR_M; ++m)
-        for (int k = 0; k < TGR_K; ++k)
-          bf16_split_host(ogT[(size_t)k * TGR_M + m], gh[(size_t)m * TGR_K + k], gh[glo + (size_t)m * TGR_K + k]);
+      for (int i = 0; i < 3; ++i)
+        for (int r = 0; r < TET_MP; ++r) {
+          const int m = TET_MP * i + r, pt = slot_pt[r];
+          if (pt < 0) continue;
+          for (int k = 0; k < TGR_K; ++k)
+            bf16_split_host(ogT[(size_t)k * TGR_M + TET_MP * i + pt], gh[(size_t)m * TGR_K + k],
+                            gh[glo + (size_t)m * TGR_K + k]);
+        }
       if (dalloc(c, (char**)&c->tet_opH, dh.size() * 2) || dalloc(c, (char**)&c->tet_ogH, gh.size() * 2) ||
           hipMemcpy(c->tet_opH, dh.data(), dh.size() * 2, hipMemcpyHostToDevice) != hipSuccess ||
           hipMemcpy(c->tet_ogH, gh.data(), gh.size() * 2, hipMemcpyHostToDevice) != hipSuccess) {

@@ -156,6 +156,88 @@ __device__ __forceinline__ void viscous(const T w[5], const T g[15], T sx, T sy,
   viscous_dir(u, g, sx, sy, sz, gamma, mu, pr, fv);
 }
 
+// Navier--Stokes flux of one solution point along several directions s:
+// (f_inv - f_v).s.  The velocity, (deviation) pressure and enthalpy, the viscous stress
+// tau and the energy flux vector tau v + kappa grad e are formed once per point (the same
+// formulas as Flux::eval and viscous_dir); each direction then costs a few products.
+template <typename T, bool DEV>
+struct PointFluxNS {
+  T m[3], vx, vy, vz, dp, h;       // momentum, velocity, (deviation) pressure, (deviation) H v factor
+  T tau[6], qe[3];                 // tau_xx, tau_yy, tau_zz, tau_xy, tau_xz, tau_yz; energy flux vector
+  __device__ __forceinline__ PointFluxNS(const T w[5], const T g[15], T gamma, T mu, T pr, const RefState<T>& R) {
+    const T gm1 = gamma - T(1);
+    const T rho = DEV ? R.rho0 + w[0] : w[0];
+    const T Et = DEV ? R.E0 + w[4] : w[4];
+    const T ir = T(1) / rho;
+    m[0] = w[1]; m[1] = w[2]; m[2] = w[3];
+    vx = w[1] * ir; vy = w[2] * ir; vz = w[3] * ir;
+    dp = gm1 * (w[4] - T(0.5) * (w[1] * vx + w[2] * vy + w[3] * vz));
+    // DEV: (H0 + dE + dp) multiplies v.s (f(u).s - f(u_ref).s); else (E + p)
+    h = DEV ? R.H0 + w[4] + dp : w[4] + dp;
+    const T v[3] = {vx, vy, vz};
+    T gv[3][3];                                   // gv[i][j] = d v_i / d x_j
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) gv[i][j] = (g[(1 + i) * 3 + j] - v[i] * g[j]) * ir;
+    const T Er = Et * ir;
+    T ge[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      ge[j] = (g[12 + j] - Er * g[j] - (w[1] * gv[0][j] + w[2] * gv[1][j] + w[3] * gv[2][j])) * ir;
+    const T div = gv[0][0] + gv[1][1] + gv[2][2];
+    const T d23 = T(2.0 / 3.0) * div;
+    tau[0] = mu * (T(2) * gv[0][0] - d23);
+    tau[1] = mu * (T(2) * gv[1][1] - d23);
+    tau[2] = mu * (T(2) * gv[2][2] - d23);
+    tau[3] = mu * (gv[0][1] + gv[1][0]);
+    tau[4] = mu * (gv[0][2] + gv[2][0]);
+    tau[5] = mu * (gv[1][2] + gv[2][1]);
+    const T kappa = mu * gamma / pr;
+    qe[0] = tau[0] * vx + tau[3] * vy + tau[4] * vz + kappa * ge[0];
+    qe[1] = tau[3] * vx + tau[1] * vy + tau[5] * vz + kappa * ge[1];
+    qe[2] = tau[4] * vx + tau[5] * vy + tau[2] * vz + kappa * ge[2];
+  }
+  __device__ __forceinline__ void dir(T sx, T sy, T sz, T f[5]) const {
+    const T vs = vx * sx + vy * sy + vz * sz;
+    f[0] = DEV ? m[0] * sx + m[1] * sy + m[2] * sz : (m[0] * sx + m[1] * sy + m[2] * sz);
+    f[1] = m[0] * vs + dp * sx - (tau[0] * sx + tau[3] * sy + tau[4] * sz);
+    f[2] = m[1] * vs + dp * sy - (tau[3] * sx + tau[1] * sy + tau[5] * sz);
+    f[3] = m[2] * vs + dp * sz - (tau[4] * sx + tau[5] * sy + tau[2] * sz);
+    f[4] = h * vs - (qe[0] * sx + qe[1] * sy + qe[2] * sz);
+  }
+  // the viscous part alone, f_v.s, without its zero mass component (4 values)
+  __device__ __forceinline__ void visc(T sx, T sy, T sz, T fv[4]) const {
+    fv[0] = tau[0] * sx + tau[3] * sy + tau[4] * sz;
+    fv[1] = tau[3] * sx + tau[1] * sy + tau[5] * sz;
+    fv[2] = tau[4] * sx + tau[5] * sy + tau[2] * sz;
+    fv[3] = qe[0] * sx + qe[1] * sy + qe[2] * sz;
+  }
+};
+
+// The inviscid part of PointFluxNS: f_inv.s along several directions of one point.
+template <typename T, bool DEV>
+struct PointInv {
+  T m[3], vx, vy, vz, dp, h;
+  __device__ __forceinline__ PointInv(const T w[5], T gamma, const RefState<T>& R) {
+    const T gm1 = gamma - T(1);
+    const T rho = DEV ? R.rho0 + w[0] : w[0];
+    const T ir = T(1) / rho;
+    m[0] = w[1]; m[1] = w[2]; m[2] = w[3];
+    vx = w[1] * ir; vy = w[2] * ir; vz = w[3] * ir;
+    dp = gm1 * (w[4] - T(0.5) * (w[1] * vx + w[2] * vy + w[3] * vz));
+    h = DEV ? R.H0 + w[4] + dp : w[4] + dp;
+  }
+  __device__ __forceinline__ void dir(T sx, T sy, T sz, T f[5]) const {
+    const T vs = vx * sx + vy * sy + vz * sz;
+    f[0] = m[0] * sx + m[1] * sy + m[2] * sz;
+    f[1] = m[0] * vs + dp * sx;
+    f[2] = m[1] * vs + dp * sy;
+    f[3] = m[2] * vs + dp * sz;
+    f[4] = h * vs;
+  }
+};
+
 // Columns of G = dx/dxi at reference point (a, b, d) of a trilinear map with
 // monomial coefficients c[comp*8 + S], S in {1, a, b, d, ab, ad, bd, abd}; c is
 // read through the stride `cs` (LDS staging).
@@ -811,17 +893,17 @@ __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_div_ns(
       hex_cols(G + el, NE, K.x[ci], K.x[cj], K.x[k], g);
       iJ[k] = T(-1) / det_cols(g);
     }
+    const PointFluxNS<T, DEV> pf(uu, gg, gamma, mu, pr, R);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      T s[3], f[5], fv[5], vs, prs;
+      T s[3], f[5];
       if constexpr (CUR) cm_srow<T, NSP>(cm, E, e, pt, d, s);
       else srow(g, d, s);
-      Flux<T, DEV>::eval(uu, s[0], s[1], s[2], gm1, R, f, vs, prs);
-      viscous<T, DEV>(uu, gg, s[0], s[1], s[2], gamma, mu, pr, R, fv);
+      pf.dir(s[0], s[1], s[2], f);
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
-        if (d < 2) FT[((d * 5 + v) * NSP + pt) * NE + el] = f[v] - fv[v];
-        else f3[k][v] = f[v] - fv[v];
+        if (d < 2) FT[((d * 5 + v) * NSP + pt) * NE + el] = f[v];
+        else f3[k][v] = f[v];
       }
     }
   }
@@ -912,15 +994,15 @@ __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_div_ns_lds(
       hex_cols(G + el, NE, K.x[ci], K.x[cj], K.x[k], g);
       iJ[k] = T(-1) / det_cols(g);
     }
+    const PointFluxNS<T, DEV> pf(uu, gg, gamma, mu, pr, R);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      T s[3], f[5], fv[5], vs, prs;
+      T s[3], f[5];
       if constexpr (CUR) cm_srow<T, NSP>(cm, E, e, pt, d, s);
       else srow(g, d, s);
-      Flux<T, DEV>::eval(uu, s[0], s[1], s[2], gm1, R, f, vs, prs);
-      viscous<T, DEV>(uu, gg, s[0], s[1], s[2], gamma, mu, pr, R, fv);
+      pf.dir(s[0], s[1], s[2], f);
 #pragma unroll
-      for (int v = 0; v < 5; ++v) FT[((d * 5 + v) * NSP + pt) * NE + el] = f[v] - fv[v];
+      for (int v = 0; v < 5; ++v) FT[((d * 5 + v) * NSP + pt) * NE + el] = f[v];
     }
   }
   // common fluxes at the six line ends through point k (the xi_3 ends are the same

@@ -26,6 +26,7 @@ template <typename T>
 struct TetDev {
   const int32_t* src;   // [60] collocated solution point of each flux point
   const int32_t* pfp;   // [35][4]: number of flux points at solution point z (0..3), then their indices
+  const int32_t* slot;  // [48]: solution point of each output row of the gradient product (-1: padding)
   T nref[4][3];         // unit outward reference normals of the faces
 };
 
@@ -255,23 +256,43 @@ __global__ void __launch_bounds__(TDIV_NT) tet_div(const T* __restrict__ u, cons
       const int64_t e = e0 + el;
       T wv[5], gg[15];
       tet_load(u, E, e, pt, wv);
+      if constexpr (NS && FCIN) {
+        // the gradient kernel stored S_i . f_v (12 values) instead of the gradient
+        T fvs[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) fvs[k] = grad[((int64_t)pt * 12 + k) * E + e];
+        const PointInv<T, DEV> pin(wv, gamma, R);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          T f[5];
+          pin.dir(SJ[(3 * i) * NE + el], SJ[(3 * i + 1) * NE + el], SJ[(3 * i + 2) * NE + el], f);
+#pragma unroll
+          for (int c = 0; c < 5; ++c) PAN[((i * TET_NSP + pt) * 5 + c) * NE + el] = c == 0 ? f[0] : f[c] - fvs[4 * i + c - 1];
+        }
+        continue;
+      }
       if constexpr (NS) {
 #pragma unroll
         for (int k = 0; k < 15; ++k) gg[k] = grad[((int64_t)pt * 15 + k) * E + e];
       }
+      if constexpr (NS) {
+        const PointFluxNS<T, DEV> pf(wv, gg, gamma, mu, pr, R);
 #pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        const T sx = SJ[(3 * i) * NE + el], sy = SJ[(3 * i + 1) * NE + el], sz = SJ[(3 * i + 2) * NE + el];
-        T f[5], vs, prs;
-        Flux<T, DEV>::eval(wv, sx, sy, sz, gm1, R, f, vs, prs);
-        if constexpr (NS) {
-          T fv[5];
-          viscous<T, DEV>(wv, gg, sx, sy, sz, gamma, mu, pr, R, fv);
+        for (int i = 0; i < 3; ++i) {
+          T f[5];
+          pf.dir(SJ[(3 * i) * NE + el], SJ[(3 * i + 1) * NE + el], SJ[(3 * i + 2) * NE + el], f);
 #pragma unroll
-          for (int c = 0; c < 5; ++c) f[c] -= fv[c];
+          for (int c = 0; c < 5; ++c) PAN[((i * TET_NSP + pt) * 5 + c) * NE + el] = f[c];
         }
+      } else {
 #pragma unroll
-        for (int c = 0; c < 5; ++c) PAN[((i * TET_NSP + pt) * 5 + c) * NE + el] = f[c];
+        for (int i = 0; i < 3; ++i) {
+          const T sx = SJ[(3 * i) * NE + el], sy = SJ[(3 * i + 1) * NE + el], sz = SJ[(3 * i + 2) * NE + el];
+          T f[5], vs, prs;
+          Flux<T, DEV>::eval(wv, sx, sy, sz, gm1, R, f, vs, prs);
+#pragma unroll
+          for (int c = 0; c < 5; ++c) PAN[((i * TET_NSP + pt) * 5 + c) * NE + el] = f[c];
+        }
       }
     }
     // the common fluxes formed by the gradient kernel, read from the slot of the side
@@ -348,6 +369,11 @@ __global__ void __launch_bounds__(TDIV_NT) tet_div(const T* __restrict__ u, cons
 }
 
 // ---------------------------------------------------------------------------
+// Output rows of the gradient product (per direction 48 = 3 point tiles of 16) hold the
+// solution points in an order chosen at setup (TetDev::slot): the points that carry the
+// same number of flux points share the rows a wave's lanes visit together, so the
+// common-flux loop of the one-sided form diverges less.
+//
 // Navier--Stokes gradient on the matrix cores.  Per element and variable the
 // reference gradient is gt_i = Dh_i u + L diag(n~_i) u^ (i = 0, 1, 2): one product of
 // the stacked operator G = [[Dh_0, L n~_0], [Dh_1, L n~_1], [Dh_2, L n~_2]] (3 x 35 rows
@@ -426,6 +452,7 @@ __global__ void __launch_bounds__(tgr_nt<T>()) __attribute__((amdgpu_waves_per_e
   __shared__ T SJ[10 * NE];
   __shared__ uint8_t SIDE[FC ? TET_NFP * NE : 1];   // bit 0: element is the left side; bit 1: it forms the flux
   __shared__ int32_t PFP[FC ? TET_NSP * 4 : 1];
+  __shared__ int32_t SLOT[TET_MP];
   const int t = threadIdx.x;
   const int w = t / 64, lane = t % 64, col = lane % 16;
   const int64_t e0 = xcd_block() * NE;
@@ -461,6 +488,7 @@ __global__ void __launch_bounds__(tgr_nt<T>()) __attribute__((amdgpu_waves_per_e
     }
     if constexpr (FC)
       for (int i = t; i < TET_NSP * 4; i += NT) PFP[i] = O.pfp[i];
+    for (int i = t; i < TET_MP; i += NT) SLOT[i] = O.slot[i];
 #pragma unroll
     for (int j = 0; j < NU; ++j) {
       const int i = t + j * NT;
@@ -527,8 +555,8 @@ __global__ void __launch_bounds__(tgr_nt<T>()) __attribute__((amdgpu_waves_per_e
       const T iJ = T(1) / SJ[9 * NE + col];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int pt = w * 16 + Mma16<T>::row(lane, q);
-        if (pt >= TET_NSP) continue;
+        const int pt = SLOT[w * 16 + Mma16<T>::row(lane, q)];
+        if (pt < 0) continue;
         T gp[15];
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
@@ -536,7 +564,23 @@ __global__ void __launch_bounds__(tgr_nt<T>()) __attribute__((amdgpu_waves_per_e
 #pragma unroll
           for (int j = 0; j < 3; ++j) {
             gp[v * 3 + j] = (S[j] * g0 + S[3 + j] * g1 + S[6 + j] * g2) * iJ;
-            grad[((int64_t)pt * 15 + v * 3 + j) * E + e] = gp[v * 3 + j];
+            if constexpr (!FC) grad[((int64_t)pt * 15 + v * 3 + j) * E + e] = gp[v * 3 + j];
+          }
+        }
+        if constexpr (FC) {
+          // the divergence kernel needs the gradient only through the transformed viscous
+          // flux at the solution points: S_i . f_v for i = 0, 1, 2 (momentum and energy,
+          // the mass component is zero), 12 values instead of 15
+          T own[5];
+#pragma unroll
+          for (int c = 0; c < 5; ++c) own[c] = PAN[(pt * 5 + c) * NE + col];
+          const PointFluxNS<T, DEV> pf(own, gp, gamma, mu, pr, R);
+#pragma unroll
+          for (int i = 0; i < 3; ++i) {
+            T fv[4];
+            pf.visc(S[3 * i], S[3 * i + 1], S[3 * i + 2], fv);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) grad[((int64_t)pt * 12 + i * 4 + c) * E + e] = fv[c];
           }
         }
         if constexpr (FC) {

@@ -173,7 +173,9 @@ def test_filtered_rk_step_fp32_form():
 
 def test_warm_start_gain_after_training():
     """Train the MLP on plain-filter data from held-out shock draws, then filter an
-    unseen draw: identical k, fewer constraint evaluations per troubled element."""
+    unseen draw: identical k and fewer constraint evaluations per troubled element than the
+    plain bisection.  Control arm: the same bracketed search from a constant prediction
+    (the training targets' median); evaluations and call times of the three are printed."""
     from paper_2408_16509_amd import frmi
     mesh = inputs.hex_box((6, 6, 6))
     ctx = _ctx(mesh)
@@ -213,13 +215,38 @@ def test_warm_start_gain_after_training():
     u_prev = u.clone()
     ctx.rk_step(u, 5e-3, 1, filter_mode=-1)          # unfiltered step: creates troubled elements
     assert ctx.check(u)
-    res = {}
-    for mode in (0, 1):
+    trained = ctx.mlp_get_weights()
+    # control arm: the same bracketed search from a constant prediction, the training
+    # targets' median (zero weights, last bias = median), so the comparison isolates
+    # what the network's per-element prediction adds to any bracketed warm start
+    const = np.zeros_like(trained)
+    const[-1] = float(np.median(y.cpu().numpy()))
+    stream = torch.cuda.current_stream()
+
+    def run(mode, weights=None):
+        if weights is not None:
+            ctx.mlp_set_weights(weights, xm, xsd)
         uu = u.clone()
         k = torch.zeros(lay.n_elem[0], dtype=torch.int32, device="cuda")
-        st = ctx.filter(uu, u_prev, mode=mode, k=k, stats=True)
-        res[mode] = (k.cpu().numpy(), st.n_evals / max(st.n_troubled, 1), st.n_troubled)
-    print(f"troubled {res[0][2]}: evals per troubled element plain {res[0][1]:.2f}, warm {res[1][1]:.2f}")
-    assert res[0][2] > 0
-    assert np.array_equal(res[0][0], res[1][0])
-    assert res[1][1] < res[0][1]
+        ctx.filter(u.clone(), u_prev, mode=mode)                      # warm-up
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        ctx.filter(uu, u_prev, mode=mode, k=k)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        st = ctx.filter(u.clone(), u_prev, mode=mode, stats=True)
+        return k.cpu().numpy(), st.n_evals / max(st.n_troubled, 1), st.n_troubled, ev0.elapsed_time(ev1)
+
+    res = {"plain": run(0), "constant": run(1, const), "learned": run(1, trained)}
+    print(f"troubled {res['plain'][2]}: evaluations per troubled element / call ms: "
+          + ", ".join(f"{n} {r[1]:.2f} / {r[3]:.3f}" for n, r in res.items()), flush=True)
+    assert res["plain"][2] > 0
+    assert np.array_equal(res["plain"][0], res["learned"][0])
+    assert res["learned"][1] < res["plain"][1]
+    assert np.array_equal(res["plain"][0], res["constant"][0])
+    # The control arm is reported, not asserted against: on these shock draws the
+    # strengths cluster so tightly that the median alone starts the bracketed search
+    # about as well as the network (measured 13.6 against 14.6 evaluations per troubled
+    # element on 49 elements); both need far fewer than the full-range bisection.
+    assert res["constant"][1] < res["plain"][1]

@@ -641,7 +641,7 @@ __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_grad(
 // instead of being staged, which keeps the LDS and registers of the 125-point element
 // within an occupancy of 3-4 waves per SIMD.
 template <typename T, int P, int NE, bool CUR = false>
-__global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_grad_lines(
+__global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1))) hex_grad_lines(
     const T* __restrict__ u, const T* __restrict__ uf, const T* __restrict__ geo, const T* __restrict__ cm,
     Conn C, T* __restrict__ grad, T* __restrict__ gradf, int64_t E, HexK<T> K, T beta, int side_mode) {
   constexpr int N1 = P + 1, NSP = N1 * N1 * N1, NF = N1 * N1, NT = NE * N1 * N1;

@@ -385,11 +385,18 @@ __global__ void __launch_bounds__(TDIV_NT) tet_div(const T* __restrict__ u, cons
 //
 // FC (one-sided LDG, beta = +-1/2, side_mode = sign of beta): the common flux of
 // every flux-point pair is formed here, once, by the element whose gradient the
-// viscous part takes (the right side for beta = 1/2).  That lane holds the full
-// gradient at the collocated solution point, its own state, and (as u^) the partner's
-// state, so it evaluates eq:comm_flux with the LDG viscous part and penalty in the
-// left-to-right unit normal and stores it in its own slot of fc; the divergence
-// kernel reads it from there for both sides and scales it by its own +-|S^T n~|.
+// viscous part takes (the right side for beta = 1/2), and stored in that element's
+// slot of fc; the divergence kernel reads it from there for both sides and scales it
+// by its own +-|S^T n~|.  The lane that holds the gradient at a solution point stages
+// the viscous flux along the left-to-right unit normal of each collocated flux point
+// in LDS (over the flux-point rows of the panel, free once the products are done).
+// Whether an element forms the fluxes of a face is a property of the face, so the
+// formed (flux point, element) pairs of the block -- about half of them -- are then
+// listed face by face and spread over all waves of the block, which evaluate
+// eq:comm_flux (inviscid solver, staged viscous part, penalty) with the partner's
+// state read again from memory (still in cache).  Evaluated per solution point
+// instead, a wave would run the flux once for every flux point any of its lanes has,
+// formed or not.
 constexpr int TGR_K = 96, TGR_M = 3 * TET_MP;
 // Panel rows of the FP32 / FP64 gradient: u at the 35 points (row 35 zero), then u^ face
 // by face, 16 rows per face (its 15 flux points and a zero row).  The lift part of
@@ -450,7 +457,16 @@ __global__ void __launch_bounds__(tgr_nt<T>()) __attribute__((amdgpu_waves_per_e
   // face by face, tgs_row), zero rows
   __shared__ T PAN[KR * 5 * NE];
   __shared__ T SJ[10 * NE];
-  __shared__ uint8_t SIDE[FC ? TET_NFP * NE : 1];   // bit 0: element is the left side; bit 1: it forms the flux
+  // FC: per (face, element) the partner element and connectivity word and the unit
+  // normal from the left to the right side; per formed (flux point, element) the
+  // solution point of the partner's collocated value; per face the formed elements in
+  // ascending order (FEL) and, bit 16 f + el, the block's formed mask (FMASK)
+  static_assert(!FC || (NE == 16 && NT >= 4 * NE), "face tables assume 16-element tiles");
+  __shared__ int32_t NBE[FC ? 4 * NE : 1], NBF[FC ? 4 * NE : 1];
+  __shared__ T NRM[FC ? 12 * NE : 1];
+  __shared__ uint8_t PSRC[FC ? TET_NFP * NE : 1];
+  __shared__ uint8_t FEL[FC ? 4 * NE : 1];
+  __shared__ uint32_t FMASK[2];
   __shared__ int32_t PFP[FC ? TET_NSP * 4 : 1];
   __shared__ int32_t SLOT[TET_MP];
   const int t = threadIdx.x;
@@ -509,8 +525,40 @@ __global__ void __launch_bounds__(tgr_nt<T>()) __attribute__((amdgpu_waves_per_e
       const int64_t ne = fromn[j] ? (int64_t)nel[j] : e0;
 #pragma unroll
       for (int c = 0; c < 5; ++c) un[j][c] = fromn[j] ? u[((int64_t)src * 5 + c) * E + ne] : T(0);
+      if constexpr (FC) {
+        if (it < TET_NFP * NE) {
+          const int el = it % NE;
+          if (fromn[j]) PSRC[sg * NE + el] = (uint8_t)src;
+          if (sg % TET_NFPF == 0) {
+            NBF[(sg / TET_NFPF) * NE + el] = inf[j];
+            NBE[(sg / TET_NFPF) * NE + el] = nel[j];
+          }
+        }
+      }
     }
     __syncthreads();
+    if constexpr (FC) {
+      // wave 0, lane = 16 f + el: the face tables (after the wait: SJ and NBF are in LDS)
+      if (w == 0) {
+        const int f = lane / NE, el = lane % NE;
+        const bool left = (NBF[f * NE + el] >> 12) & 1;
+        const bool formed = left != (side_mode > 0) && e0 + el < n;
+        T S[9], nv[3];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) S[k] = SJ[k * NE + el];
+        tet_normal(S, O, f, nv);
+        const T sl = (left ? T(1) : T(-1)) / sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) NRM[(f * 3 + k) * NE + el] = nv[k] * sl;
+        const uint64_t m = __ballot(formed);
+        const uint32_t mf = (uint32_t)(m >> (16 * f)) & 0xffffu;
+        if (formed) FEL[f * NE + __popc(mf & ((1u << el) - 1u))] = (uint8_t)el;
+        if (lane == 0) {
+          FMASK[0] = (uint32_t)m;
+          FMASK[1] = (uint32_t)(m >> 32);
+        }
+      }
+    }
 #pragma unroll
     for (int j = 0; j < NI; ++j) {
       const int it = t + j * NT;
@@ -518,7 +566,6 @@ __global__ void __launch_bounds__(tgr_nt<T>()) __attribute__((amdgpu_waves_per_e
       const int el = it % NE, sg = it / NE;
       const int so = O.src[sg];
       const int row = BF3 ? TET_NSP + sg : tgs_row(sg);
-      if constexpr (FC) SIDE[sg * NE + el] = (lft[j] ? 1 : 0) | (lft[j] != (side_mode > 0) ? 2 : 0);
 #pragma unroll
       for (int c = 0; c < 5; ++c) {
         const T own = PAN[(so * 5 + c) * NE + el];
@@ -535,20 +582,28 @@ __global__ void __launch_bounds__(tgr_nt<T>()) __attribute__((amdgpu_waves_per_e
       }
     }
     __syncthreads();
-    if (w >= 3) return;
+    if constexpr (!FC) {
+      if (w >= 3) return;
+    }
     typename Mma16<T>::V acc[3][5];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
       for (int v = 0; v < 5; ++v) acc[i][v] = typename Mma16<T>::V{0, 0, 0, 0};
-    if constexpr (BF3) {
-      const int mt[3] = {w, 3 + w, 6 + w};
-      tet_contract<T, BF3, 3, NE>(acc, PAN, TGR_K, lane, ogT, 0, TGR_M, mt, ogH, ogL, TGR_K);
-    } else {
-      tet_grad_contract<T, NE>(acc, PAN, lane, ogT, w);
+    if (w < 3) {
+      if constexpr (BF3) {
+        const int mt[3] = {w, 3 + w, 6 + w};
+        tet_contract<T, BF3, 3, NE>(acc, PAN, TGR_K, lane, ogT, 0, TGR_M, mt, ogH, ogL, TGR_K);
+      } else {
+        tet_grad_contract<T, NE>(acc, PAN, lane, ogT, w);
+      }
     }
+    // FC: the flux-point rows of the panel take the staged viscous fluxes below
+    if constexpr (FC) __syncthreads();
+    constexpr int FVB = (BF3 ? TET_NSP : TGS_U) * 5 * NE;   // FVN[(sg * 4 + c) * NE + el] at PAN + FVB
+    static_assert(!FC || FVB + TET_NFP * 4 * NE <= KR * 5 * NE, "staged viscous fluxes exceed the panel");
     const int64_t e = e0 + col;
-    if (e < n) {
+    if (w < 3 && e < n) {
       T S[9];
 #pragma unroll
       for (int k = 0; k < 9; ++k) S[k] = SJ[k * NE + col];
@@ -582,37 +637,75 @@ __global__ void __launch_bounds__(tgr_nt<T>()) __attribute__((amdgpu_waves_per_e
 #pragma unroll
             for (int c = 0; c < 4; ++c) grad[((int64_t)pt * 12 + i * 4 + c) * E + e] = fv[c];
           }
-        }
-        if constexpr (FC) {
+          // the viscous flux along the left-to-right unit normal at each collocated flux
+          // point (the flux phase reads only those of formed faces)
           const int nf = PFP[pt * 4];
           for (int i = 0; i < nf; ++i) {
             const int sg = PFP[pt * 4 + 1 + i];
-            const int face = sg / TET_NFPF;
-            const int side = SIDE[sg * NE + col];
-            if (!(side & 2)) continue;                      // the partner's gradient contributes
-            const NbrSlot ns{0, 0, (side & 1) != 0};
-            T own[5], nb[5], uL[5], uR[5], nv[3], nL[3], F[5], fv[5];
+            const int f = sg / TET_NFPF;
+            T fv[4];
+            pf.visc(NRM[(f * 3) * NE + col], NRM[(f * 3 + 1) * NE + col], NRM[(f * 3 + 2) * NE + col], fv);
 #pragma unroll
-            for (int c = 0; c < 5; ++c) {
-              own[c] = PAN[(pt * 5 + c) * NE + col];
-              nb[c] = PAN[((BF3 ? TET_NSP + sg : tgs_row(sg)) * 5 + c) * NE + col];
-              uL[c] = ns.left ? own[c] : nb[c];
-              uR[c] = ns.left ? nb[c] : own[c];
-            }
-            tet_normal(S, O, face, nv);
-            const T mag = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
-            const T sl = (ns.left ? T(1) : T(-1)) / mag;
-#pragma unroll
-            for (int k = 0; k < 3; ++k) nL[k] = nv[k] * sl;
-            common_inviscid<T, DEV>(riemann, uL, uR, nL, gamma, R, F);
-            viscous<T, DEV>(own, gp, nL[0], nL[1], nL[2], gamma, mu, pr, R, fv);
-#pragma unroll
-            for (int c = 0; c < 5; ++c) {
-              F[c] = (F[c] - fv[c]) + tau * (uL[c] - uR[c]);
-              fc[((int64_t)sg * 5 + c) * E + e] = F[c];
-            }
+            for (int c = 0; c < 4; ++c) PAN[FVB + (sg * 4 + c) * NE + col] = fv[c];
           }
         }
+      }
+    }
+    if constexpr (FC) {
+      __syncthreads();
+      // The formed pairs, face by face (15 flux points x the face's formed elements in
+      // ascending order), dealt to all threads of the block; each thread first issues the
+      // reads of its pairs' partner states, then evaluates the fluxes.
+      const uint64_t m = ((uint64_t)FMASK[1] << 32) | FMASK[0];
+      const int c0 = __popcll(m & 0xffffull), c1 = __popcll((m >> 16) & 0xffffull);
+      const int c2 = __popcll((m >> 32) & 0xffffull), c3 = __popcll(m >> 48);
+      const int o1 = TET_NFPF * c0, o2 = o1 + TET_NFPF * c1, o3 = o2 + TET_NFPF * c2, total = o3 + TET_NFPF * c3;
+      constexpr int ND = (TET_NFP * NE + NT - 1) / NT;
+      T nb[ND][5];
+      int psg[ND], pel[ND], pso[ND];
+#pragma unroll
+      for (int j = 0; j < ND; ++j) {
+        const int i = t + j * NT;
+        const bool ok = i < total;
+        const int f = (i >= o1) + (i >= o2) + (i >= o3);
+        const int of = f == 0 ? 0 : f == 1 ? o1 : f == 2 ? o2 : o3;
+        const int cf = f == 0 ? c0 : f == 1 ? c1 : f == 2 ? c2 : c3;
+        const int r = ok ? i - of : 0;
+        // r = 15 k + position among the face's formed elements; k = floor((r + 1/2) / cf),
+        // whose fraction lies in [1/32, 31/32], far from the reciprocal's rounding
+        const int k = ok ? (int)((T(r) + T(0.5)) * __builtin_amdgcn_rcpf((float)cf)) : 0;
+        const int el = ok ? FEL[f * NE + (r - k * cf)] : 0;
+        const int sg = f * TET_NFPF + k;
+        psg[j] = ok ? sg : -1;
+        pel[j] = el;
+        pso[j] = ok ? O.src[sg] : 0;
+        const int src = ok ? PSRC[sg * NE + el] : 0;
+        const int64_t ne = ok ? (int64_t)NBE[f * NE + el] : e0;
+#pragma unroll
+        for (int c = 0; c < 5; ++c) nb[j][c] = ok ? u[((int64_t)src * 5 + c) * E + ne] : T(0);
+      }
+      // formed pairs have the element on the side that beta does not name
+      const bool left = side_mode < 0;
+#pragma unroll
+      for (int j = 0; j < ND; ++j) {
+        const int sg = psg[j], el = pel[j];
+        if (sg < 0) continue;
+        const int f = sg / TET_NFPF;
+        T own[5], uL[5], uR[5], nL[3], F[5];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+          own[c] = PAN[(pso[j] * 5 + c) * NE + el];
+          uL[c] = left ? own[c] : nb[j][c];
+          uR[c] = left ? nb[j][c] : own[c];
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) nL[k] = NRM[(f * 3 + k) * NE + el];
+        common_inviscid<T, DEV>(riemann, uL, uR, nL, gamma, R, F);
+        F[0] += tau * (uL[0] - uR[0]);
+#pragma unroll
+        for (int c = 1; c < 5; ++c) F[c] = (F[c] - PAN[FVB + (sg * 4 + c - 1) * NE + el]) + tau * (uL[c] - uR[c]);
+#pragma unroll
+        for (int c = 0; c < 5; ++c) fc[((int64_t)sg * 5 + c) * E + e0 + el] = F[c];
       }
     }
   }

@@ -76,7 +76,7 @@ struct Flux {
       flux_dir(w, sx, sy, sz, gm1, f, vs, p_full);
     } else {
       const T rho = R.rho0 + w[0];
-      const T ir = T(1) / rho;
+      const T ir = rcp(rho);
       const T vx = w[1] * ir, vy = w[2] * ir, vz = w[3] * ir;
       const T dp = gm1 * (w[4] - T(0.5) * (w[1] * vx + w[2] * vy + w[3] * vz));
       vs = vx * sx + vy * sy + vz * sz;
@@ -105,7 +105,7 @@ __device__ __forceinline__ void common_inviscid(int kind, const T uL[5], const T
   Flux<T, DEV>::eval(uL, n[0], n[1], n[2], gm1, R, fL, vnL, pL);
   Flux<T, DEV>::eval(uR, n[0], n[1], n[2], gm1, R, fR, vnR, pR);
   const T rL = Flux<T, DEV>::rho(uL, R), rR = Flux<T, DEV>::rho(uR, R);
-  const T cL = sqrt(gamma * pL / rL), cR = sqrt(gamma * pR / rR);
+  const T cL = fsqrt(fdiv(gamma * pL, rL)), cR = fsqrt(fdiv(gamma * pR, rR));
   if (kind != 1) {
     const T lam = fmax(fabs(vnL) + cL, fabs(vnR) + cR);
 #pragma unroll
@@ -116,7 +116,7 @@ __device__ __forceinline__ void common_inviscid(int kind, const T uL[5], const T
   const T SR = fmax(vnL + cL, vnR + cR);
   // pR - pL from the deviation pressures in the float form (same value in exact arithmetic)
   const T dpLR = pR - pL;
-  const T Ss = (dpLR + rL * vnL * (SL - vnL) - rR * vnR * (SR - vnR)) / (rL * (SL - vnL) - rR * (SR - vnR));
+  const T Ss = fdiv(dpLR + rL * vnL * (SL - vnL) - rR * vnR * (SR - vnR), rL * (SL - vnL) - rR * (SR - vnR));
   if (T(0) <= SL) {
 #pragma unroll
     for (int v = 0; v < 5; ++v) F[v] = fL[v];
@@ -134,8 +134,8 @@ __device__ __forceinline__ void common_inviscid(int kind, const T uL[5], const T
   // U*_K - U_K written without forming U*_K (no cancellation of the total energy):
   //   mass: r (Ss - vn)/(S - Ss); momentum: that times v + fac (Ss - vn) n;
   //   energy: (Ss - vn)/(S - Ss) [r (S - vn) Ss + p + E]
-  const T fac = r * (S - vn) / (S - Ss);
-  const T q = (Ss - vn) / (S - Ss);
+  const T fac = fdiv(r * (S - vn), S - Ss);
+  const T q = fdiv(Ss - vn, S - Ss);
   const T E = DEV ? R.E0 + wK[4] : wK[4];
   T dU[5];
   dU[0] = r * q;
@@ -168,7 +168,7 @@ struct PointFluxNS {
     const T gm1 = gamma - T(1);
     const T rho = DEV ? R.rho0 + w[0] : w[0];
     const T Et = DEV ? R.E0 + w[4] : w[4];
-    const T ir = T(1) / rho;
+    const T ir = rcp(rho);
     m[0] = w[1]; m[1] = w[2]; m[2] = w[3];
     vx = w[1] * ir; vy = w[2] * ir; vz = w[3] * ir;
     dp = gm1 * (w[4] - T(0.5) * (w[1] * vx + w[2] * vy + w[3] * vz));
@@ -193,7 +193,7 @@ struct PointFluxNS {
     tau[3] = mu * (gv[0][1] + gv[1][0]);
     tau[4] = mu * (gv[0][2] + gv[2][0]);
     tau[5] = mu * (gv[1][2] + gv[2][1]);
-    const T kappa = mu * gamma / pr;
+    const T kappa = fdiv(mu * gamma, pr);
     qe[0] = tau[0] * vx + tau[3] * vy + tau[4] * vz + kappa * ge[0];
     qe[1] = tau[3] * vx + tau[1] * vy + tau[5] * vz + kappa * ge[1];
     qe[2] = tau[4] * vx + tau[5] * vy + tau[2] * vz + kappa * ge[2];
@@ -222,7 +222,7 @@ struct PointInv {
   __device__ __forceinline__ PointInv(const T w[5], T gamma, const RefState<T>& R) {
     const T gm1 = gamma - T(1);
     const T rho = DEV ? R.rho0 + w[0] : w[0];
-    const T ir = T(1) / rho;
+    const T ir = rcp(rho);
     m[0] = w[1]; m[1] = w[2]; m[2] = w[3];
     vx = w[1] * ir; vy = w[2] * ir; vz = w[3] * ir;
     dp = gm1 * (w[4] - T(0.5) * (w[1] * vx + w[2] * vy + w[3] * vz));
@@ -406,7 +406,7 @@ __device__ __forceinline__ void accumulate_div(int d, const T (&ft)[5][N1], cons
         T xi[3], g[3][3];
         line_xi(K, d, a, t0, t1, xi);
         hex_cols(G + el, NE, xi[0], xi[1], xi[2], g);
-        iJ = T(-1) / det_cols(g);
+        iJ = -rcp(det_cols(g));
       }
       if (e < n) {
 #pragma unroll
@@ -472,7 +472,7 @@ __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_div_euler(
         srow(g, d, nv);
       }
       const T sg = sd ? T(1) : T(-1);
-      const T mag = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+      const T mag = fsqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
       const NbrSlot ns = nbr_slot<NF>(C, E, e, 2 * d + sd, l);
       T un[5];
 #pragma unroll
@@ -481,7 +481,7 @@ __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_div_euler(
       T uL[5], uR[5], nL[3], F[5];
 #pragma unroll
       for (int v = 0; v < 5; ++v) { uL[v] = ns.left ? own[v] : un[v]; uR[v] = ns.left ? un[v] : own[v]; }
-      const T sl = (ns.left ? sg : -sg) / mag;
+      const T sl = fdiv(ns.left ? sg : -sg, mag);
 #pragma unroll
       for (int k = 0; k < 3; ++k) nL[k] = nv[k] * sl;
       common_inviscid<T, DEV>(riemann, uL, uR, nL, gamma, R, F);
@@ -557,7 +557,7 @@ __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_grad(
         line_xi(K, d, a, t0, t1, xi);
         hex_cols(G + el, NE, xi[0], xi[1], xi[2], g);
         srow(g, d, s);
-        iJ = T(1) / det_cols(g);
+        iJ = rcp(det_cols(g));
       }
 #pragma unroll
       for (int j = 0; j < 3; ++j) sJ[d][a][j] = s[j] * iJ;
@@ -674,7 +674,7 @@ __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) __attribute__((amdgpu_wave
         line_xi(K, d, a, t0, t1, xi);
         hex_cols(G + el, NE, xi[0], xi[1], xi[2], g);
         srow(g, d, s);
-        iJ = T(1) / det_cols(g);
+        iJ = rcp(det_cols(g));
       }
 #pragma unroll
       for (int j = 0; j < 3; ++j) sJ[d][a][j] = s[j] * iJ;
@@ -805,7 +805,7 @@ __global__ void __launch_bounds__(256) hex_face_ns(const T* __restrict__ uf, con
     hex_cols(c, 1, xi[0], xi[1], xi[2], g);
     srow(g, d, nv);
   }
-  const T mag = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+  const T mag = fsqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
   const NbrSlot ns = nbr_slot<NF>(C, E, e, face, q);
   // each flux-point pair once: the left side computes it and writes both slots
   if (!ns.left) return;
@@ -816,7 +816,7 @@ __global__ void __launch_bounds__(256) hex_face_ns(const T* __restrict__ uf, con
     un[v] = uf[((int64_t)ns.fp * 5 + v) * E + ns.elem];
   }
   const T sg = sd ? T(1) : T(-1);
-  const T sl = (ns.left ? sg : -sg) / mag;
+  const T sl = fdiv(ns.left ? sg : -sg, mag);
 #pragma unroll
   for (int k = 0; k < 3; ++k) nL[k] = nv[k] * sl;
 #pragma unroll
@@ -891,7 +891,7 @@ __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_div_ns(
       iJ[k] = -cm_rjac<T, NSP>(cm, E, e, pt);
     } else {
       hex_cols(G + el, NE, K.x[ci], K.x[cj], K.x[k], g);
-      iJ[k] = T(-1) / det_cols(g);
+      iJ[k] = -rcp(det_cols(g));
     }
     const PointFluxNS<T, DEV> pf(uu, gg, gamma, mu, pr, R);
 #pragma unroll
@@ -992,7 +992,7 @@ __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_div_ns_lds(
       iJ[k] = -cm_rjac<T, NSP>(cm, E, e, pt);
     } else {
       hex_cols(G + el, NE, K.x[ci], K.x[cj], K.x[k], g);
-      iJ[k] = T(-1) / det_cols(g);
+      iJ[k] = -rcp(det_cols(g));
     }
     const PointFluxNS<T, DEV> pf(uu, gg, gamma, mu, pr, R);
 #pragma unroll

@@ -67,8 +67,8 @@ __device__ __forceinline__ void tet_common_flux(const T* __restrict__ u, const T
   tet_load(u, E, e, so, own);
   tet_load(u, E, ns.elem, sn, un);
   tet_normal(S, O, face, nv);
-  const T mag = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
-  const T sl = (ns.left ? T(1) : T(-1)) / mag;
+  const T mag = fsqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+  const T sl = fdiv(ns.left ? T(1) : T(-1), mag);
 #pragma unroll
   for (int k = 0; k < 3; ++k) nL[k] = nv[k] * sl;
 #pragma unroll
@@ -333,7 +333,7 @@ __global__ void __launch_bounds__(TDIV_NT) tet_div(const T* __restrict__ u, cons
 #pragma unroll
         for (int k = 0; k < 9; ++k) S[k] = SJ[k * NE + el];
         tet_normal(S, O, face, nv);
-        const T mag = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+        const T mag = fsqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
         const T fs = lft[j] ? mag : -mag;
 #pragma unroll
         for (int c = 0; c < 5; ++c) PAN[(sg * 5 + c) * NE + el] = fcv[j][c] * fs;
@@ -354,7 +354,7 @@ __global__ void __launch_bounds__(TDIV_NT) tet_div(const T* __restrict__ u, cons
     if (w >= 3) return;
     tet_contract<T, BF3, 1, NE>(acc, PAN, KB, lane, opT, BF3 ? TET_KA16 : TET_KA, TET_MP, mt, opH, opL, TET_KP16);
     const int64_t e = e0 + col;
-    const T iJ = T(-1) / SJ[9 * NE + col];
+    const T iJ = -rcp(SJ[9 * NE + col]);
     if (e < n) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -547,7 +547,7 @@ __global__ void __launch_bounds__(tgr_nt<T>()) __attribute__((amdgpu_waves_per_e
 #pragma unroll
         for (int k = 0; k < 9; ++k) S[k] = SJ[k * NE + el];
         tet_normal(S, O, f, nv);
-        const T sl = (left ? T(1) : T(-1)) / sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+        const T sl = fdiv(left ? T(1) : T(-1), fsqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]));
 #pragma unroll
         for (int k = 0; k < 3; ++k) NRM[(f * 3 + k) * NE + el] = nv[k] * sl;
         const uint64_t m = __ballot(formed);
@@ -607,7 +607,7 @@ __global__ void __launch_bounds__(tgr_nt<T>()) __attribute__((amdgpu_waves_per_e
       T S[9];
 #pragma unroll
       for (int k = 0; k < 9; ++k) S[k] = SJ[k * NE + col];
-      const T iJ = T(1) / SJ[9 * NE + col];
+      const T iJ = rcp(SJ[9 * NE + col]);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int pt = SLOT[w * 16 + Mma16<T>::row(lane, q)];

@@ -488,7 +488,8 @@ fr_status hex_rhs_p(fr_ctx c, DevBlock& b, const T* u, T* r) {
     c->prof_end(pk);
     constexpr int NE2 = DivNsCfg<T, P>::NE;
     pk = c->prof_begin(("hex_div_ns" + sfx).c_str());
-    if constexpr (P <= 3)
+    // f~_3 of a column in registers except for FP64 at p = 4 (all of f~ in LDS there)
+    if constexpr (P <= 3 || sizeof(T) == 4)
       hex_div_ns<T, DEV, P, NE2, CUR><<<(unsigned)(b.E / NE2), NE2 * N1 * N1, 0, c->stream>>>(
           u, grad, fc, geo, cm, r, b.E, b.n, K, (T)p.gamma, (T)p.mu, (T)p.prandtl, R);
     else

@@ -953,8 +953,11 @@ __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_div_ns(
   }
 }
 
-// Variant with all three directions' f~ in LDS (at p = 4 the register budget does not
-// hold f~_3 of a whole column).
+// Variant with all three directions' f~ in LDS, for FP64 at p = 4, where f~_3 of a
+// whole column in registers does not fit beside the rest.  (In FP32 it does, at 166
+// VGPRs: 3 waves per SIMD and 40 KB of LDS per 8 elements, three blocks per CU, where
+// this variant's 60 KB allow two; bounding the register kernel to 128 VGPRs for a
+// fourth block spills and is slower.)
 template <typename T, bool DEV, int P, int NE, bool CUR = false>
 __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) hex_div_ns_lds(
     const T* __restrict__ u, const T* __restrict__ grad, const T* __restrict__ fc, const T* __restrict__ geo,

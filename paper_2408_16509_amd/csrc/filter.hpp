@@ -80,7 +80,7 @@ struct RkStageSrc {
   double b, c;
   int mode;
   double ref[5];
-  struct Raw { double x, a; double k; };
+  struct Raw { double x, a; KT k; };
   __device__ __forceinline__ double stage(int64_t i) const { return fma(c, (double)k[i], u[i]); }
   // the value value() forms, read without side effects from what the update leaves
   // unchanged (u_n and k in the stages, the accumulator and k in the last one)
@@ -88,17 +88,18 @@ struct RkStageSrc {
     return mode == 2 ? fma(b, (double)k[i], acc[i]) : fma(c, (double)k[i], u[i]);
   }
   __device__ __forceinline__ Raw raw(int64_t i) const {
-    return Raw{mode == 2 ? 0.0 : u[i], mode == 0 ? 0.0 : acc[i], (double)k[i]};
+    return Raw{mode == 2 ? 0.0 : u[i], mode == 0 ? 0.0 : acc[i], k[i]};
   }
   __device__ __forceinline__ double value(int64_t i, int v, const Raw& r) const {
+    const double rk = (double)r.k;
     if (mode == 2) {
-      const double un = fma(b, r.k, r.a);
+      const double un = fma(b, rk, r.a);
       u[i] = un;
       if (s32) s32[i] = (float)(un - ref[v]);
       return un;
     }
-    acc[i] = fma(b, r.k, mode == 0 ? r.x : r.a);
-    const double si = fma(c, r.k, r.x);
+    acc[i] = fma(b, rk, mode == 0 ? r.x : r.a);
+    const double si = fma(c, rk, r.x);
     if (s64) s64[i] = si;
     if (s32) s32[i] = (float)(si - ref[v]);
     return si;
@@ -593,17 +594,25 @@ __global__ void __launch_bounds__(256) hex_filter_detect_lines(Src src, const do
   const double sbm = sb + 1e-10 * fabs(sb);
   const double lsb = sbm > 0 ? log(sbm) : -INFINITY;
   bool bad = false;
-  // own column: raw values of the next point in flight while the current one is formed
+  // own column: raw values of the next point in flight while the current one is formed.
+  // The xi_1 line through (j, k) = (c0, c1) and the xi_2 line through (i, k) = (c0, c1)
+  // both lie at height c1, so they are read in the iteration a = c1, when the waves that
+  // own those columns read the same height: the values are then still in L2 (read a
+  // column later, most of them had to come from HBM again).
   double m[5] = {0, 0, 0, 0, 0}, pl[5] = {0, 0, 0, 0, 0};
   typename Src::Raw rw[5], rn[5];
 #pragma unroll
   for (int v = 0; v < 5; ++v) rn[v] = src.raw(((int64_t)(c0 + N1 * c1) * 5 + v) * E + e);
-#pragma unroll
+  // not unrolled: one copy of the lines' block (the height a is wave-uniform)
+#pragma unroll 1
   for (int a = 0; a < N1; ++a) {
     const int pt = c0 + N1 * (c1 + N1 * a);
 #pragma unroll
     for (int v = 0; v < 5; ++v) rw[v] = rn[v];
-    if (a + 1 < N1) {
+    // the next point's loads: issued before this point is formed, except in the
+    // iteration of the two lines, where they follow the lines' reads (keeping them
+    // apart keeps the registers of the two sets apart)
+    if (a + 1 < N1 && a != c1) {        // wave-uniform
 #pragma unroll
       for (int v = 0; v < 5; ++v) rn[v] = src.raw(((int64_t)(pt + NC) * 5 + v) * E + e);
     }
@@ -615,30 +624,30 @@ __global__ void __launch_bounds__(256) hex_filter_detect_lines(Src src, const do
       pl[v] += K.lp[a] * w[v];
     }
     bad = bad || maybe_violates(w, lsb, F);
-  }
-  bad = bad || maybe_violates(m, lsb, F) || maybe_violates(pl, lsb, F);
-  // the xi_1 line through (j, k) = (c0, c1) and the xi_2 line through (i, k) = (c0, c1)
+    if (a == c1) {
+#pragma unroll 1
+      for (int d = 0; d < 2; ++d) {
+        // point b of the line: (b, c0, c1) along xi_1, (c0, b, c1) along xi_2
+        const int q0 = d == 0 ? N1 * (c0 + N1 * c1) : c0 + N1 * N1 * c1, qs = d == 0 ? 1 : N1;
+        double lm[5] = {0, 0, 0, 0, 0}, lp[5] = {0, 0, 0, 0, 0};
 #pragma unroll
-  for (int d = 0; d < 2; ++d) {
-    double x[N1][5];
+        for (int b = 0; b < N1; ++b) {
 #pragma unroll
-    for (int a = 0; a < N1; ++a) {
-      const int pt = d == 0 ? a + N1 * (c0 + N1 * c1) : c0 + N1 * (a + N1 * c1);
+          for (int v = 0; v < 5; ++v) {
+            const double x = src.peek(((int64_t)(q0 + qs * b) * 5 + v) * E + e);
+            lm[v] += K.lm[b] * x;
+            lp[v] += K.lp[b] * x;
+          }
+        }
+        bad = bad || maybe_violates(lm, lsb, F) || maybe_violates(lp, lsb, F);
+      }
+      if (a + 1 < N1) {
 #pragma unroll
-      for (int v = 0; v < 5; ++v) x[a][v] = src.peek(((int64_t)pt * 5 + v) * E + e);
-    }
-#pragma unroll
-    for (int v = 0; v < 5; ++v) {
-      m[v] = 0;
-      pl[v] = 0;
-#pragma unroll
-      for (int a = 0; a < N1; ++a) {
-        m[v] += K.lm[a] * x[a][v];
-        pl[v] += K.lp[a] * x[a][v];
+        for (int v = 0; v < 5; ++v) rn[v] = src.raw(((int64_t)(pt + NC) * 5 + v) * E + e);
       }
     }
-    bad = bad || maybe_violates(m, lsb, F) || maybe_violates(pl, lsb, F);
   }
+  bad = bad || maybe_violates(m, lsb, F) || maybe_violates(pl, lsb, F);
   if (bad && e < n) flag[e] = 1;
 }
 

@@ -235,6 +235,39 @@ def test_tet_filtered_rk_step_fp32_form(case):
     assert ok.all()
 
 
+@pytest.fixture(scope="module")
+def mixed_case():
+    mesh = mixed_mesh()
+    bl, u0, _ = shock_states(mesh, 4, shifts=[0.0, MIXED_SHIFT])
+    return mesh, bl, u0
+
+
+@pytest.mark.parametrize("form", ["fp64", "fp32"])
+def test_mixed_filtered_rk_step_matches_oracle(mixed_case, form):
+    """One RK4 step of a hexahedral + tetrahedral context at p = 4 with the plain filter
+    on every stage state and on the new state: the detection passes that perform the
+    stage updates (for hexahedra at p = 4 one wave per 64-element tile and column) on
+    both blocks, against the oracle.  Bounds on the increment as for the single-type
+    steps (FP64 1e-10, FP32 form 1e-4), every check point within the entropy and
+    positivity bounds."""
+    from paper_2408_16509_amd import frmi
+    mesh, bl, u0 = mixed_case
+    smin0 = ef.smin_neighbourhood(bl, u0, FP)
+    post = lambda s: [ef.filter_block(b, ss, sm, FP)[0] for b, ss, sm in zip(bl, s, smin0)]
+    uo = ork.rk4_step(lambda s: ofr.rhs(bl, s, ofr.Params(riemann=1)), u0, DT, stage_post=post)
+    kw = {} if form == "fp64" else dict(precision=frmi.FR_FP32, u_ref=(1.0, 0.0, 0.0, 0.0, 1.0 / 0.4))
+    ctx = _ctx(mesh, **kw)
+    ug = ctx.pack64(_flat(u0))
+    ctx.rk_step(ug, DT, 1, filter_mode=0)
+    got = _split(ctx.unpack64(ug).cpu().numpy(), uo)
+    for name, g, o, a, b, sm in zip(("hex", "tet"), got, uo, u0, bl, smin0):
+        err = np.linalg.norm(g - o) / np.linalg.norm(o - a)
+        print(f"mixed filtered RK4 step, {form}, {name}: relative error of the increment {err:.2e}", flush=True)
+        assert err <= (1e-10 if form == "fp64" else 1e-4)
+        assert ef.admissible(b, g, sm, FP)[0].all()
+    assert ctx.check(ug)
+
+
 def test_mixed_context_filter_matches_oracle():
     """Both blocks of a hexahedral + tetrahedral context filtered in one call."""
     mesh = mixed_mesh()

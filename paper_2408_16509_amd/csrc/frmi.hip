@@ -528,11 +528,11 @@ fr_status tet_rhs(fr_ctx c, DevBlock& b, const T* u, T* r) {
   if (p.system == FR_EULER) {
     pk = c->prof_begin(("tet_div_euler" + sfx).c_str());
     if (bf3)
-      tet_div<T, DEV, false, can_bf3, false><<<div_grid, TDIV_NT, 0, c->stream>>>(
+      tet_div<T, DEV, false, can_bf3, false><<<div_grid, tdiv_nt<T>(), 0, c->stream>>>(
           u, nullptr, nullptr, geo, C, O, opT, opH, opL, r, b.E, b.n, (T)p.gamma, zero, zero, zero, zero, p.riemann, 0,
           R);
     else
-      tet_div<T, DEV, false, false, false><<<div_grid, TDIV_NT, 0, c->stream>>>(
+      tet_div<T, DEV, false, false, false><<<div_grid, tdiv_nt<T>(), 0, c->stream>>>(
           u, nullptr, nullptr, geo, C, O, opT, opH, opL, r, b.E, b.n, (T)p.gamma, zero, zero, zero, zero, p.riemann, 0,
           R);
     c->prof_end(pk);
@@ -558,7 +558,7 @@ fr_status tet_rhs(fr_ctx c, DevBlock& b, const T* u, T* r) {
     c->prof_end(pk);
     pk = c->prof_begin(("tet_div_ns" + sfx).c_str());
 #define FR_TET_DIV(BF, FCX)                                                                                     \
-  tet_div<T, DEV, true, BF, FCX><<<div_grid, TDIV_NT, 0, c->stream>>>(u, (const T*)b.grad, fcb, geo, C, O, opT, opH, \
+  tet_div<T, DEV, true, BF, FCX><<<div_grid, tdiv_nt<T>(), 0, c->stream>>>(u, (const T*)b.grad, fcb, geo, C, O, opT, opH, \
                                                                      opL, r, b.E, b.n, gam, mu, pr, beta, tau,   \
                                                                      p.riemann, sm, R)
     if (bf3) {

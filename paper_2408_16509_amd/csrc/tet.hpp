@@ -195,12 +195,16 @@ __device__ __forceinline__ void tet_contract(typename Mma16<T>::V (&acc)[NW][5],
 constexpr int TET_KA = 108, TET_KB = 60, TET_KP = TET_KA + TET_KB, TET_MP = 48;
 // the BF16x3 path pads both K chunks to multiples of 16: [0, 112) and [112, 176)
 constexpr int TET_KA16 = 112, TET_KB16 = 64, TET_KP16 = TET_KA16 + TET_KB16;
-// 16 elements per block.  The divergence runs three waves, one point tile each, that
+// 16 elements per block.  The divergence runs one wave per point tile (three), which
 // also share the gathers (3.0 -> 2.65 ms per FP32 launch on the mixed workload against
-// five waves of which two only gather).  The gradient gathers more (the common
-// solution at all 60 flux points): four waves in FP32 (three multiply; 2.95 -> 2.47
-// ms per launch against five), five in FP64 (four: 5.7 ms against 3.85).
-constexpr int TDIV_NE = 16, TDIV_NT = 3 * 64;
+// five waves of which two only gather); in FP32 a fourth wave joins the gathers and the
+// flux evaluation (four blocks per CU either way, set by LDS: 1.286 -> 1.246 ms).  The
+// gradient gathers more (the common solution at all 60 flux points): four waves in
+// FP32 (three multiply; 2.95 -> 2.47 ms per launch against five), five in FP64 (four:
+// 5.7 ms against 3.85).
+constexpr int TDIV_NE = 16;
+template <typename T>
+constexpr int tdiv_nt() { return sizeof(T) == 4 ? 4 * 64 : 3 * 64; }
 template <typename T>
 constexpr int tgr_nt() { return sizeof(T) == 4 ? 4 * 64 : 5 * 64; }
 
@@ -215,14 +219,14 @@ constexpr int tgr_nt() { return sizeof(T) == 4 ? 4 * 64 : 5 * 64; }
 // side that formed them; here each flux point reads its pair's value and scales it by
 // the element's own +-|S^T n~|.
 template <typename T, bool DEV, bool NS, bool BF3, bool FCIN>
-__global__ void __launch_bounds__(TDIV_NT) tet_div(const T* __restrict__ u, const T* __restrict__ grad,
+__global__ void __launch_bounds__(tdiv_nt<T>()) tet_div(const T* __restrict__ u, const T* __restrict__ grad,
                                                    const T* __restrict__ fcin,
                                                    const T* __restrict__ geo, Conn C, TetDev<T> O,
                                                    const T* __restrict__ opT, const tet_s4* __restrict__ opH,
                                                    const tet_s4* __restrict__ opL, T* __restrict__ r, int64_t E,
                                                    int64_t n, T gamma, T mu, T pr, T beta, T tau, int riemann,
                                                    int side_mode, RefState<T> R) {
-  constexpr int NE = TDIV_NE, NT = TDIV_NT;
+  constexpr int NE = TDIV_NE, NT = tdiv_nt<T>();
   constexpr int KA = BF3 ? TET_KA16 : TET_KA, KB = BF3 ? TET_KB16 : TET_KB;
   __shared__ T PAN[KA * 5 * NE];          // [k][v][el]; the second K chunk reuses it
   __shared__ T SJ[10 * NE];
@@ -468,6 +472,7 @@ __global__ void __launch_bounds__(tgr_nt<T>()) __attribute__((amdgpu_waves_per_e
   __shared__ uint8_t FEL[FC ? 4 * NE : 1];
   __shared__ uint32_t FMASK[2];
   __shared__ int32_t PFP[FC ? TET_NSP * 4 : 1];
+  __shared__ uint8_t SRCT[FC ? TET_NFP : 1];        // FC: collocated solution point of each flux point
   __shared__ int32_t SLOT[TET_MP];
   const int t = threadIdx.x;
   const int w = t / 64, lane = t % 64, col = lane % 16;
@@ -504,6 +509,8 @@ __global__ void __launch_bounds__(tgr_nt<T>()) __attribute__((amdgpu_waves_per_e
     }
     if constexpr (FC)
       for (int i = t; i < TET_NSP * 4; i += NT) PFP[i] = O.pfp[i];
+    if constexpr (FC)
+      for (int i = t; i < TET_NFP; i += NT) SRCT[i] = (uint8_t)O.src[i];
     for (int i = t; i < TET_MP; i += NT) SLOT[i] = O.slot[i];
 #pragma unroll
     for (int j = 0; j < NU; ++j) {
@@ -582,130 +589,171 @@ __global__ void __launch_bounds__(tgr_nt<T>()) __attribute__((amdgpu_waves_per_e
       }
     }
     __syncthreads();
+    // the formed pairs of the one-sided common flux, face by face (15 flux points x the
+    // face's formed elements in ascending order): item i -> face f, flux point sg, element el
+    [[maybe_unused]] int c0 = 0, c1 = 0, c2 = 0, c3 = 0, o1 = 0, o2 = 0, o3 = 0, total = 0;
+    if constexpr (FC) {
+      const uint64_t m = ((uint64_t)FMASK[1] << 32) | FMASK[0];
+      c0 = __popcll(m & 0xffffull);
+      c1 = __popcll((m >> 16) & 0xffffull);
+      c2 = __popcll((m >> 32) & 0xffffull);
+      c3 = __popcll(m >> 48);
+      o1 = TET_NFPF * c0;
+      o2 = o1 + TET_NFPF * c1;
+      o3 = o2 + TET_NFPF * c2;
+      total = o3 + TET_NFPF * c3;
+    }
+    [[maybe_unused]] auto decode = [&](int i, int& f, int& sg, int& el) {
+      f = (i >= o1) + (i >= o2) + (i >= o3);
+      const int of = f == 0 ? 0 : f == 1 ? o1 : f == 2 ? o2 : o3;
+      const int cf = f == 0 ? c0 : f == 1 ? c1 : f == 2 ? c2 : c3;
+      const int r = i - of;
+      // r = 15 k + position among the face's formed elements; k = floor((r + 1/2) / cf),
+      // whose fraction lies in [1/32, 31/32], far from the reciprocal's rounding
+      const int k = (int)((float(r) + 0.5f) * __builtin_amdgcn_rcpf((float)cf));
+      el = FEL[f * NE + (r - k * cf)];
+      sg = f * TET_NFPF + k;
+    };
+    // formed pairs have the element on the side that beta does not name
+    [[maybe_unused]] const bool left = side_mode < 0;
+    constexpr int FVB = (BF3 ? TET_NSP : TGS_U) * 5 * NE;   // FVN[(sg * 4 + c) * NE + el] at PAN + FVB
+    static_assert(!FC || FVB + TET_NFP * 4 * NE <= KR * 5 * NE, "staged viscous fluxes exceed the panel");
     if constexpr (!FC) {
       if (w >= 3) return;
     }
-    typename Mma16<T>::V acc[3][5];
+    static_assert(!FC || NT == 4 * 64, "the FC roles assume waves 0-2 multiplying and wave 3");
+    constexpr int JW = 10;                           // FC: pairs per lane of wave 3
+    if (FC && w == 3) {
+      // wave 3, idle during the products: the inviscid flux and the penalty of the first
+      // 64 JW pairs from the panel (read-only until barrier 1), kept in registers until
+      // the viscous part is staged.  The two wave roles pass the same two block barriers,
+      // (1) and (2), each in its own branch; a barrier counts the waves of the block
+      // that reach one.
+      T fw[JW][4];
+      int iw[JW];
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < JW; ++j) {
+        const int i = lane + 64 * j;
+        iw[j] = -1;
+        if (i >= total) continue;
+        int f, sg, el;
+        decode(i, f, sg, el);
+        const int so = SRCT[sg], row = BF3 ? TET_NSP + sg : tgs_row(sg);
+        T uL[5], uR[5], nL[3], F[5];
 #pragma unroll
-      for (int v = 0; v < 5; ++v) acc[i][v] = typename Mma16<T>::V{0, 0, 0, 0};
-    if (w < 3) {
+        for (int c = 0; c < 5; ++c) {
+          const T own = PAN[(so * 5 + c) * NE + el], nb = PAN[(row * 5 + c) * NE + el];
+          uL[c] = left ? own : nb;
+          uR[c] = left ? nb : own;
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) nL[k] = NRM[(f * 3 + k) * NE + el];
+        common_inviscid<T, DEV>(riemann, uL, uR, nL, gamma, R, F);
+        fc[((int64_t)sg * 5) * E + e0 + el] = F[0] + tau * (uL[0] - uR[0]);
+#pragma unroll
+        for (int c = 1; c < 5; ++c) fw[j][c - 1] = F[c] + tau * (uL[c] - uR[c]);
+        iw[j] = sg * NE + el;
+      }
+      __syncthreads();                             // (1)
+      __syncthreads();                             // (2)
+#pragma unroll
+      for (int j = 0; j < JW; ++j) {
+        if (iw[j] < 0) continue;
+        const int sg = iw[j] / NE, el = iw[j] % NE;
+#pragma unroll
+        for (int c = 1; c < 5; ++c)
+          fc[((int64_t)sg * 5 + c) * E + e0 + el] = fw[j][c - 1] - PAN[FVB + (sg * 4 + c - 1) * NE + el];
+      }
+    } else {
+      // waves 0-2: the products, then the gradient epilogue (FC: with the staged viscous
+      // normal fluxes, written over the panel's trace rows once all products are done)
+      typename Mma16<T>::V acc[3][5];
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int v = 0; v < 5; ++v) acc[i][v] = typename Mma16<T>::V{0, 0, 0, 0};
       if constexpr (BF3) {
         const int mt[3] = {w, 3 + w, 6 + w};
         tet_contract<T, BF3, 3, NE>(acc, PAN, TGR_K, lane, ogT, 0, TGR_M, mt, ogH, ogL, TGR_K);
       } else {
         tet_grad_contract<T, NE>(acc, PAN, lane, ogT, w);
       }
-    }
-    // FC: the flux-point rows of the panel take the staged viscous fluxes below
-    if constexpr (FC) __syncthreads();
-    constexpr int FVB = (BF3 ? TET_NSP : TGS_U) * 5 * NE;   // FVN[(sg * 4 + c) * NE + el] at PAN + FVB
-    static_assert(!FC || FVB + TET_NFP * 4 * NE <= KR * 5 * NE, "staged viscous fluxes exceed the panel");
-    const int64_t e = e0 + col;
-    if (w < 3 && e < n) {
-      T S[9];
+      if constexpr (FC) __syncthreads();           // (1) every wave's products are done
+      const int64_t e = e0 + col;
+      if (e < n) {
+        T S[9];
 #pragma unroll
-      for (int k = 0; k < 9; ++k) S[k] = SJ[k * NE + col];
-      const T iJ = rcp(SJ[9 * NE + col]);
+        for (int k = 0; k < 9; ++k) S[k] = SJ[k * NE + col];
+        const T iJ = rcp(SJ[9 * NE + col]);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int pt = SLOT[w * 16 + Mma16<T>::row(lane, q)];
-        if (pt < 0) continue;
-        T gp[15];
+        for (int q = 0; q < 4; ++q) {
+          const int pt = SLOT[w * 16 + Mma16<T>::row(lane, q)];
+          if (pt < 0) continue;
+          T gp[15];
 #pragma unroll
-        for (int v = 0; v < 5; ++v) {
-          const T g0 = acc[0][v][q], g1 = acc[1][v][q], g2 = acc[2][v][q];
+          for (int v = 0; v < 5; ++v) {
+            const T g0 = acc[0][v][q], g1 = acc[1][v][q], g2 = acc[2][v][q];
 #pragma unroll
-          for (int j = 0; j < 3; ++j) {
-            gp[v * 3 + j] = (S[j] * g0 + S[3 + j] * g1 + S[6 + j] * g2) * iJ;
-            if constexpr (!FC) grad[((int64_t)pt * 15 + v * 3 + j) * E + e] = gp[v * 3 + j];
+            for (int j = 0; j < 3; ++j) {
+              gp[v * 3 + j] = (S[j] * g0 + S[3 + j] * g1 + S[6 + j] * g2) * iJ;
+              if constexpr (!FC) grad[((int64_t)pt * 15 + v * 3 + j) * E + e] = gp[v * 3 + j];
+            }
           }
-        }
-        if constexpr (FC) {
-          // the divergence kernel needs the gradient only through the transformed viscous
-          // flux at the solution points: S_i . f_v for i = 0, 1, 2 (momentum and energy,
-          // the mass component is zero), 12 values instead of 15
-          T own[5];
+          if constexpr (FC) {
+            // the divergence kernel needs the gradient only through the transformed viscous
+            // flux at the solution points: S_i . f_v for i = 0, 1, 2 (momentum and energy,
+            // the mass component is zero), 12 values instead of 15
+            T own[5];
 #pragma unroll
-          for (int c = 0; c < 5; ++c) own[c] = PAN[(pt * 5 + c) * NE + col];
-          const PointFluxNS<T, DEV> pf(own, gp, gamma, mu, pr, R);
+            for (int c = 0; c < 5; ++c) own[c] = PAN[(pt * 5 + c) * NE + col];
+            const PointFluxNS<T, DEV> pf(own, gp, gamma, mu, pr, R);
 #pragma unroll
-          for (int i = 0; i < 3; ++i) {
-            T fv[4];
-            pf.visc(S[3 * i], S[3 * i + 1], S[3 * i + 2], fv);
+            for (int i = 0; i < 3; ++i) {
+              T fv[4];
+              pf.visc(S[3 * i], S[3 * i + 1], S[3 * i + 2], fv);
 #pragma unroll
-            for (int c = 0; c < 4; ++c) grad[((int64_t)pt * 12 + i * 4 + c) * E + e] = fv[c];
-          }
-          // the viscous flux along the left-to-right unit normal at each collocated flux
-          // point (the flux phase reads only those of formed faces)
-          const int nf = PFP[pt * 4];
-          for (int i = 0; i < nf; ++i) {
-            const int sg = PFP[pt * 4 + 1 + i];
-            const int f = sg / TET_NFPF;
-            T fv[4];
-            pf.visc(NRM[(f * 3) * NE + col], NRM[(f * 3 + 1) * NE + col], NRM[(f * 3 + 2) * NE + col], fv);
+              for (int c = 0; c < 4; ++c) grad[((int64_t)pt * 12 + i * 4 + c) * E + e] = fv[c];
+            }
+            // the viscous flux along the left-to-right unit normal at each collocated flux
+            // point (the flux phase reads only those of formed faces)
+            const int nf = PFP[pt * 4];
+            for (int i = 0; i < nf; ++i) {
+              const int sg = PFP[pt * 4 + 1 + i];
+              const int f = sg / TET_NFPF;
+              T fv[4];
+              pf.visc(NRM[(f * 3) * NE + col], NRM[(f * 3 + 1) * NE + col], NRM[(f * 3 + 2) * NE + col], fv);
 #pragma unroll
-            for (int c = 0; c < 4; ++c) PAN[FVB + (sg * 4 + c) * NE + col] = fv[c];
+              for (int c = 0; c < 4; ++c) PAN[FVB + (sg * 4 + c) * NE + col] = fv[c];
+            }
           }
         }
       }
+      if constexpr (FC) __syncthreads();           // (2) the viscous normal fluxes are staged
     }
     if constexpr (FC) {
-      __syncthreads();
-      // The formed pairs, face by face (15 flux points x the face's formed elements in
-      // ascending order), dealt to all threads of the block; each thread first issues the
-      // reads of its pairs' partner states, then evaluates the fluxes.
-      const uint64_t m = ((uint64_t)FMASK[1] << 32) | FMASK[0];
-      const int c0 = __popcll(m & 0xffffull), c1 = __popcll((m >> 16) & 0xffffull);
-      const int c2 = __popcll((m >> 32) & 0xffffull), c3 = __popcll(m >> 48);
-      const int o1 = TET_NFPF * c0, o2 = o1 + TET_NFPF * c1, o3 = o2 + TET_NFPF * c2, total = o3 + TET_NFPF * c3;
-      constexpr int ND = (TET_NFP * NE + NT - 1) / NT;
-      T nb[ND][5];
-      int psg[ND], pel[ND], pso[ND];
-#pragma unroll
-      for (int j = 0; j < ND; ++j) {
-        const int i = t + j * NT;
-        const bool ok = i < total;
-        const int f = (i >= o1) + (i >= o2) + (i >= o3);
-        const int of = f == 0 ? 0 : f == 1 ? o1 : f == 2 ? o2 : o3;
-        const int cf = f == 0 ? c0 : f == 1 ? c1 : f == 2 ? c2 : c3;
-        const int r = ok ? i - of : 0;
-        // r = 15 k + position among the face's formed elements; k = floor((r + 1/2) / cf),
-        // whose fraction lies in [1/32, 31/32], far from the reciprocal's rounding
-        const int k = ok ? (int)((T(r) + T(0.5)) * __builtin_amdgcn_rcpf((float)cf)) : 0;
-        const int el = ok ? FEL[f * NE + (r - k * cf)] : 0;
-        const int sg = f * TET_NFPF + k;
-        psg[j] = ok ? sg : -1;
-        pel[j] = el;
-        pso[j] = ok ? O.src[sg] : 0;
-        const int src = ok ? PSRC[sg * NE + el] : 0;
-        const int64_t ne = ok ? (int64_t)NBE[f * NE + el] : e0;
-#pragma unroll
-        for (int c = 0; c < 5; ++c) nb[j][c] = ok ? u[((int64_t)src * 5 + c) * E + ne] : T(0);
-      }
-      // formed pairs have the element on the side that beta does not name
-      const bool left = side_mode < 0;
-#pragma unroll
-      for (int j = 0; j < ND; ++j) {
-        const int sg = psg[j], el = pel[j];
-        if (sg < 0) continue;
-        const int f = sg / TET_NFPF;
-        T own[5], uL[5], uR[5], nL[3], F[5];
+      // pairs past 64 JW (more than 640 formed pairs in the block, rare): all waves, the
+      // partner's state read again from memory (the panel's trace rows hold the staged
+      // viscous fluxes by now)
+      for (int i = 64 * JW + t; i < total; i += NT) {
+        int f, sg, el;
+        decode(i, f, sg, el);
+        const int so = SRCT[sg], src = PSRC[sg * NE + el];
+        const int64_t ne = NBE[f * NE + el];
+        T uL[5], uR[5], nL[3], F[5];
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
-          own[c] = PAN[(pso[j] * 5 + c) * NE + el];
-          uL[c] = left ? own[c] : nb[j][c];
-          uR[c] = left ? nb[j][c] : own[c];
+          const T own = PAN[(so * 5 + c) * NE + el], nb = u[((int64_t)src * 5 + c) * E + ne];
+          uL[c] = left ? own : nb;
+          uR[c] = left ? nb : own;
         }
 #pragma unroll
         for (int k = 0; k < 3; ++k) nL[k] = NRM[(f * 3 + k) * NE + el];
         common_inviscid<T, DEV>(riemann, uL, uR, nL, gamma, R, F);
-        F[0] += tau * (uL[0] - uR[0]);
+        fc[((int64_t)sg * 5) * E + e0 + el] = F[0] + tau * (uL[0] - uR[0]);
 #pragma unroll
-        for (int c = 1; c < 5; ++c) F[c] = (F[c] - PAN[FVB + (sg * 4 + c - 1) * NE + el]) + tau * (uL[c] - uR[c]);
-#pragma unroll
-        for (int c = 0; c < 5; ++c) fc[((int64_t)sg * 5 + c) * E + e0 + el] = F[c];
+        for (int c = 1; c < 5; ++c)
+          fc[((int64_t)sg * 5 + c) * E + e0 + el] =
+              (F[c] + tau * (uL[c] - uR[c])) - PAN[FVB + (sg * 4 + c - 1) * NE + el];
       }
     }
   }

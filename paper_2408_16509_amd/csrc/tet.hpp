@@ -203,6 +203,16 @@ constexpr int TET_KA16 = 112, TET_KB16 = 64, TET_KP16 = TET_KA16 + TET_KB16;
 // FP32 (three multiply; 2.95 -> 2.47 ms per launch against five), five in FP64 (four:
 // 5.7 ms against 3.85).
 constexpr int TDIV_NE = 16;
+// Layout of the transformed viscous fluxes S_i . f_v that the FP32 gradient kernel stores
+// for the divergence kernel (12 rows per solution point): tile by tile of NE elements,
+// [tile][pt * 12 + k][el], so the rows of one tile are contiguous and the two halves of
+// every 128-byte line are written by the same wave in consecutive stores (in the
+// element-fastest layout of the state each 16-element row is half a line, whose other
+// half another block writes).  Both kernels walk the same tiles.
+template <int NE>
+__device__ __forceinline__ int64_t tet_fv_index(int64_t e0, int row, int el) {
+  return e0 * (12 * TET_NSP) + (int64_t)row * NE + el;
+}
 template <typename T>
 constexpr int tdiv_nt() { return sizeof(T) == 4 ? 4 * 64 : 3 * 64; }
 template <typename T>
@@ -261,10 +271,11 @@ __global__ void __launch_bounds__(tdiv_nt<T>()) tet_div(const T* __restrict__ u,
       T wv[5], gg[15];
       tet_load(u, E, e, pt, wv);
       if constexpr (NS && FCIN) {
-        // the gradient kernel stored S_i . f_v (12 values) instead of the gradient
+        // the gradient kernel stored S_i . f_v (12 values) instead of the gradient, tile by
+        // tile (tet_fv_index)
         T fvs[12];
 #pragma unroll
-        for (int k = 0; k < 12; ++k) fvs[k] = grad[((int64_t)pt * 12 + k) * E + e];
+        for (int k = 0; k < 12; ++k) fvs[k] = grad[tet_fv_index<NE>(e0, pt * 12 + k, el)];
         const PointInv<T, DEV> pin(wv, gamma, R);
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
@@ -712,7 +723,7 @@ __global__ void __launch_bounds__(tgr_nt<T>()) __attribute__((amdgpu_waves_per_e
               T fv[4];
               pf.visc(S[3 * i], S[3 * i + 1], S[3 * i + 2], fv);
 #pragma unroll
-              for (int c = 0; c < 4; ++c) grad[((int64_t)pt * 12 + i * 4 + c) * E + e] = fv[c];
+              for (int c = 0; c < 4; ++c) grad[tet_fv_index<NE>(e0, pt * 12 + i * 4 + c, col)] = fv[c];
             }
             // the viscous flux along the left-to-right unit normal at each collocated flux
             // point (the flux phase reads only those of formed faces)

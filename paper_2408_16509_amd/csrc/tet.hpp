@@ -213,6 +213,13 @@ template <int NE>
 __device__ __forceinline__ int64_t tet_fv_index(int64_t e0, int row, int el) {
   return e0 * (12 * TET_NSP) + (int64_t)row * NE + el;
 }
+// The same for the pair-once common fluxes of the FP32 one-sided form (5 rows per flux
+// point, [tile][sg * 5 + c][el]); the divergence kernel also reads the partner's slot,
+// at element e of any tile.
+template <int NE>
+__device__ __forceinline__ int64_t tet_fc_index(int64_t e, int row) {
+  return (e / NE) * (NE * 5 * TET_NFP) + (int64_t)row * NE + e % NE;
+}
 template <typename T>
 constexpr int tdiv_nt() { return sizeof(T) == 4 ? 4 * 64 : 3 * 64; }
 template <typename T>
@@ -326,7 +333,7 @@ __global__ void __launch_bounds__(tdiv_nt<T>()) tet_div(const T* __restrict__ u,
         const int64_t fe = !ok ? e0 : (own ? e0 + it % NE : (int64_t)nel[j]);
         const int fp = !ok ? 0 : (own ? sg : nf * TET_NFPF + C.perm[orient * C.perm_stride + sg % TET_NFPF]);
 #pragma unroll
-        for (int c = 0; c < 5; ++c) fcv[j][c] = it < NE * TET_NFP ? fcin[((int64_t)fp * 5 + c) * E + fe] : T(0);
+        for (int c = 0; c < 5; ++c) fcv[j][c] = it < NE * TET_NFP ? fcin[tet_fc_index<NE>(fe, fp * 5 + c)] : T(0);
       }
     }
     __syncthreads();
@@ -660,7 +667,7 @@ __global__ void __launch_bounds__(tgr_nt<T>()) __attribute__((amdgpu_waves_per_e
 #pragma unroll
         for (int k = 0; k < 3; ++k) nL[k] = NRM[(f * 3 + k) * NE + el];
         common_inviscid<T, DEV>(riemann, uL, uR, nL, gamma, R, F);
-        fc[((int64_t)sg * 5) * E + e0 + el] = F[0] + tau * (uL[0] - uR[0]);
+        fc[tet_fc_index<NE>(e0 + el, sg * 5)] = F[0] + tau * (uL[0] - uR[0]);
 #pragma unroll
         for (int c = 1; c < 5; ++c) fw[j][c - 1] = F[c] + tau * (uL[c] - uR[c]);
         iw[j] = sg * NE + el;
@@ -673,7 +680,7 @@ __global__ void __launch_bounds__(tgr_nt<T>()) __attribute__((amdgpu_waves_per_e
         const int sg = iw[j] / NE, el = iw[j] % NE;
 #pragma unroll
         for (int c = 1; c < 5; ++c)
-          fc[((int64_t)sg * 5 + c) * E + e0 + el] = fw[j][c - 1] - PAN[FVB + (sg * 4 + c - 1) * NE + el];
+          fc[tet_fc_index<NE>(e0 + el, sg * 5 + c)] = fw[j][c - 1] - PAN[FVB + (sg * 4 + c - 1) * NE + el];
       }
     } else {
       // waves 0-2: the products, then the gradient epilogue (FC: with the staged viscous
@@ -760,10 +767,10 @@ __global__ void __launch_bounds__(tgr_nt<T>()) __attribute__((amdgpu_waves_per_e
 #pragma unroll
         for (int k = 0; k < 3; ++k) nL[k] = NRM[(f * 3 + k) * NE + el];
         common_inviscid<T, DEV>(riemann, uL, uR, nL, gamma, R, F);
-        fc[((int64_t)sg * 5) * E + e0 + el] = F[0] + tau * (uL[0] - uR[0]);
+        fc[tet_fc_index<NE>(e0 + el, sg * 5)] = F[0] + tau * (uL[0] - uR[0]);
 #pragma unroll
         for (int c = 1; c < 5; ++c)
-          fc[((int64_t)sg * 5 + c) * E + e0 + el] =
+          fc[tet_fc_index<NE>(e0 + el, sg * 5 + c)] =
               (F[c] + tau * (uL[c] - uR[c])) - PAN[FVB + (sg * 4 + c - 1) * NE + el];
       }
     }

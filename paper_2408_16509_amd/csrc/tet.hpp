@@ -510,20 +510,27 @@ __global__ void __launch_bounds__(tgr_nt<T>()) __attribute__((amdgpu_waves_per_e
     // (el, sg) per thread), then the partners' states, so each block waits on about two
     // memory latencies instead of one per loop trip.
     constexpr int NU = (TET_NSP * 5 * NE + NT - 1) / NT, NI = (TET_NFP * NE + NT - 1) / NT;
+    // item i = t + j NT is row i / NE, element i % NE = t % NE (NT a multiple of NE): one
+    // base address per thread and a uniform stride of NT / NE rows
+    static_assert(NT % NE == 0, "rows per pass");
+    const int tr = t / NE, tel = t % NE;
     T ur[NU];
+    {
+      const T* ub = u + (int64_t)tr * E + e0 + tel;
+      const int64_t us = (int64_t)(NT / NE) * E;
 #pragma unroll
-    for (int j = 0; j < NU; ++j) {
-      const int i = t + j * NT;
-      ur[j] = i < TET_NSP * 5 * NE ? u[(int64_t)(i / NE) * E + e0 + i % NE] : T(0);
+      for (int j = 0; j < NU; ++j)
+        ur[j] = (j + 1 < NU || t + j * NT < TET_NSP * 5 * NE) ? ub[j * us] : T(0);
     }
     int inf[NI], nel[NI];
 #pragma unroll
     for (int j = 0; j < NI; ++j) {
       const int it = t + j * NT;
-      const int face = (it / NE) / TET_NFPF;
-      const int64_t e = e0 + it % NE;
-      inf[j] = it < TET_NFP * NE ? C.nbr_info[(int64_t)face * E + e] : 0;
-      nel[j] = it < TET_NFP * NE ? C.nbr_elem[(int64_t)face * E + e] : 0;
+      const int face = (tr + j * (NT / NE)) / TET_NFPF;
+      const int64_t o = (int64_t)face * E + e0 + tel;
+      const bool ok = j + 1 < NI || it < TET_NFP * NE;
+      inf[j] = ok ? C.nbr_info[o] : 0;
+      nel[j] = ok ? C.nbr_elem[o] : 0;
     }
     if constexpr (FC)
       for (int i = t; i < TET_NSP * 4; i += NT) PFP[i] = O.pfp[i];
@@ -541,18 +548,18 @@ __global__ void __launch_bounds__(tgr_nt<T>()) __attribute__((amdgpu_waves_per_e
 #pragma unroll
     for (int j = 0; j < NI; ++j) {
       const int it = t + j * NT;
-      const int sg = it / NE;
+      const int sg = tr + j * (NT / NE);
       const int nf = inf[j] & 7, orient = (inf[j] >> 3) & 511;
       lft[j] = (inf[j] >> 12) & 1;
       fromn[j] = it < TET_NFP * NE && (side_mode == 0 || (side_mode > 0) != lft[j]);
       const int nfp = nf * TET_NFPF + C.perm[orient * C.perm_stride + sg % TET_NFPF];
       const int src = O.src[fromn[j] ? nfp : 0];
-      const int64_t ne = fromn[j] ? (int64_t)nel[j] : e0;
+      const T* pb = u + (int64_t)src * 5 * E + (fromn[j] ? (int64_t)nel[j] : e0);
 #pragma unroll
-      for (int c = 0; c < 5; ++c) un[j][c] = fromn[j] ? u[((int64_t)src * 5 + c) * E + ne] : T(0);
+      for (int c = 0; c < 5; ++c) un[j][c] = fromn[j] ? pb[(int64_t)c * E] : T(0);
       if constexpr (FC) {
         if (it < TET_NFP * NE) {
-          const int el = it % NE;
+          const int el = tel;
           if (fromn[j]) PSRC[sg * NE + el] = (uint8_t)src;
           if (sg % TET_NFPF == 0) {
             NBF[(sg / TET_NFPF) * NE + el] = inf[j];

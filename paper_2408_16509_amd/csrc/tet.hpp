@@ -257,23 +257,26 @@ __global__ void __launch_bounds__(tdiv_nt<T>()) tet_div(const T* __restrict__ u,
     // waits, the stored common fluxes right after chunk 1 is evaluated (both ahead of
     // their use in chunk 2, so their latency overlaps chunk 1's products).
     constexpr int NI2 = (NE * TET_NFP + NT - 1) / NT;
+    // item it = t + j NT is row t / NE + j NT / NE of element t % NE (NT a multiple of NE)
+    static_assert(NT % NE == 0, "rows per pass");
+    const int tr = t / NE, tel = t % NE;
     int inf[FCIN ? NI2 : 1], nel[FCIN ? NI2 : 1];
     if constexpr (FCIN) {
 #pragma unroll
       for (int j = 0; j < NI2; ++j) {
-        const int it = t + j * NT;
-        const int face = (it / NE) / TET_NFPF;
-        const int64_t e = e0 + it % NE;
-        inf[j] = it < NE * TET_NFP ? C.nbr_info[(int64_t)face * E + e] : 0;
-        nel[j] = it < NE * TET_NFP ? C.nbr_elem[(int64_t)face * E + e] : 0;
+        const int face = (tr + j * (NT / NE)) / TET_NFPF;
+        const int64_t o = (int64_t)face * E + e0 + tel;
+        const bool ok = j + 1 < NI2 || t + j * NT < NE * TET_NFP;
+        inf[j] = ok ? C.nbr_info[o] : 0;
+        nel[j] = ok ? C.nbr_elem[o] : 0;
       }
     }
     for (int i = t; i < 10 * NE; i += NT) SJ[i] = geo[(int64_t)(i / NE) * E + e0 + i % NE];
     for (int i = t; i < (KA - 105) * 5 * NE; i += NT) PAN[105 * 5 * NE + i] = T(0);
     __syncthreads();
     // K chunk 1: transformed fluxes at the solution points
-    for (int it = t; it < NE * TET_NSP; it += NT) {
-      const int el = it % NE, pt = it / NE;
+    for (int pt = tr; pt < TET_NSP; pt += NT / NE) {
+      const int el = tel;
       const int64_t e = e0 + el;
       T wv[5], gg[15];
       tet_load(u, E, e, pt, wv);
@@ -325,12 +328,12 @@ __global__ void __launch_bounds__(tdiv_nt<T>()) tet_div(const T* __restrict__ u,
 #pragma unroll
       for (int j = 0; j < NI2; ++j) {
         const int it = t + j * NT;
-        const int sg = it / NE;
+        const int sg = tr + j * (NT / NE);
         const int nf = inf[j] & 7, orient = (inf[j] >> 3) & 511;
         lft[j] = (inf[j] >> 12) & 1;
         const bool own = lft[j] != (side_mode > 0);
         const bool ok = it < NE * TET_NFP;      // invalid items keep in-bounds addresses
-        const int64_t fe = !ok ? e0 : (own ? e0 + it % NE : (int64_t)nel[j]);
+        const int64_t fe = !ok ? e0 : (own ? e0 + tel : (int64_t)nel[j]);
         const int fp = !ok ? 0 : (own ? sg : nf * TET_NFPF + C.perm[orient * C.perm_stride + sg % TET_NFPF]);
 #pragma unroll
         for (int c = 0; c < 5; ++c) fcv[j][c] = it < NE * TET_NFP ? fcin[tet_fc_index<NE>(fe, fp * 5 + c)] : T(0);
@@ -348,9 +351,8 @@ __global__ void __launch_bounds__(tdiv_nt<T>()) tet_div(const T* __restrict__ u,
     if constexpr (FCIN) {
 #pragma unroll
       for (int j = 0; j < NI2; ++j) {
-        const int it = t + j * NT;
-        if (it >= NE * TET_NFP) continue;
-        const int el = it % NE, sg = it / NE, face = sg / TET_NFPF;
+        if (t + j * NT >= NE * TET_NFP) continue;
+        const int el = tel, sg = tr + j * (NT / NE), face = sg / TET_NFPF;
         T S[9], nv[3];
 #pragma unroll
         for (int k = 0; k < 9; ++k) S[k] = SJ[k * NE + el];

@@ -800,6 +800,7 @@ def main():
         c2 = CONFIGS["ns_tgv_hex32_p3"]
         extras["ns_tgv_hex32_p3"] = run_tgv_workload("ns_tgv_hex32_p3", c2, ["fp32", "fp64"], sub, torch, np,
                                                      frmi, inputs, with_cpu=False)[0]
+        sub.config = "euler_shock_hex48_p3"          # the workload the traffic records are keyed by
         extras["euler_shock_hex48_p3"] = run_filter_workload(CONFIGS["euler_shock_hex48_p3"], sub, torch, np,
                                                              frmi, inputs)
         for v in extras.values():

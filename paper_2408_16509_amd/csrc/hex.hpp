@@ -793,6 +793,11 @@ __global__ void __launch_bounds__(256) hex_face_ns(const T* __restrict__ uf, con
   const int64_t e = tile * 64 + lane;
   if (e >= n) return;
   const int face = fp / NF, q = fp % NF, d = face / 2, sd = face % 2, t0 = q % N1, t1 = q / N1;
+  const NbrSlot ns = nbr_slot<NF>(C, E, e, face, q);
+  // each flux-point pair once: the left side computes it and writes both slots (decided
+  // before the geometry is read: which side is left is a property of the face, so the
+  // waves of the right sides' faces leave at once)
+  if (!ns.left) return;
   T nv[3];
   if constexpr (CUR) {
     cm_fnrm<T, NSP>(cm, E, e, fp, nv);
@@ -806,9 +811,6 @@ __global__ void __launch_bounds__(256) hex_face_ns(const T* __restrict__ uf, con
     srow(g, d, nv);
   }
   const T mag = fsqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
-  const NbrSlot ns = nbr_slot<NF>(C, E, e, face, q);
-  // each flux-point pair once: the left side computes it and writes both slots
-  if (!ns.left) return;
   T own[5], un[5], uL[5], uR[5], nL[3], F[5];
 #pragma unroll
   for (int v = 0; v < 5; ++v) {

@@ -645,7 +645,10 @@ __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) __attribute__((amdgpu_wave
     const T* __restrict__ u, const T* __restrict__ uf, const T* __restrict__ geo, const T* __restrict__ cm,
     Conn C, T* __restrict__ grad, T* __restrict__ gradf, int64_t E, HexK<T> K, T beta, int side_mode) {
   constexpr int N1 = P + 1, NSP = N1 * N1 * N1, NF = N1 * N1, NT = NE * N1 * N1;
-  __shared__ T GR[3 * NSP * NE];
+  // the physical gradient's contributions of the three line directions, one slot per
+  // direction ([d][j][pt][el]): every value has one writer, so the three directions of a
+  // variable run without a barrier between them, and the output phase adds the slots
+  __shared__ T GR[9 * NSP * NE];
   __shared__ T G[CUR ? 1 : 24 * NE];
   const int el = threadIdx.x % NE, l = threadIdx.x / NE;
   const int64_t e0 = xcd_block() * NE, e = e0 + el;
@@ -728,21 +731,22 @@ __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) __attribute__((amdgpu_wave
 #pragma unroll
         for (int b = 0; b < N1; ++b) gt += K.Dh[a][b] * uv[b];
         const int pt = line_pt<N1>(d, a, t0, t1);
-        T* Gp = GR + (gr_slot<T, N1, NE>(pt) * NE + el);
+        T* Gp = GR + d * 3 * NSP * NE + (gr_slot<T, N1, NE>(pt) * NE + el);
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-          if (d == 0) Gp[j * NSP * NE] = sJ[d][a][j] * gt;
-          else Gp[j * NSP * NE] += sJ[d][a][j] * gt;
-        }
+        for (int j = 0; j < 3; ++j) Gp[j * NSP * NE] = sJ[d][a][j] * gt;
       }
-      __syncthreads();
     }
+    __syncthreads();
+    auto gsum = [&](int j, int pt) {
+      const int o = (j * NSP + gr_slot<T, N1, NE>(pt)) * NE + el;
+      return (GR[o] + GR[3 * NSP * NE + o]) + GR[6 * NSP * NE + o];
+    };
 #pragma unroll
     for (int a = 0; a < N1; ++a) {
       const int pt = line_pt<N1>(2, a, t0, t1);
 #pragma unroll
       for (int j = 0; j < 3; ++j)
-        grad[((int64_t)pt * 15 + v * 3 + j) * E + e] = GR[(j * NSP + gr_slot<T, N1, NE>(pt)) * NE + el];
+        grad[((int64_t)pt * 15 + v * 3 + j) * E + e] = gsum(j, pt);
     }
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -752,7 +756,7 @@ __global__ void __launch_bounds__(NE*(P + 1)*(P + 1)) __attribute__((amdgpu_wave
         const int pt = line_pt<N1>(d, a, t0, t1);
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-          const T val = GR[(j * NSP + gr_slot<T, N1, NE>(pt)) * NE + el];
+          const T val = gsum(j, pt);
           gm[j] += K.lm[a] * val;
           gp[j] += K.lp[a] * val;
         }

@@ -1,4 +1,5 @@
-"""Curved hexahedra: the high-order geometric map and its metric terms (oracle, FP64).
+"""Curved hexahedra and tetrahedra: the high-order geometric map and its metric terms
+(oracle, FP64).
 
 TEST INFRASTRUCTURE: only tests/, the smoke check and the benchmark's CPU leg use it.
 
@@ -32,6 +33,18 @@ result of size h^2 (without it two FP64 evaluations differ by ~|x| / h ulps).
 
 Geometry of order q: x(xi) = sum_n N_n(xi) X_n, N the tensor Lagrange polynomials on
 equispaced nodes, node n = i + (q+1)(j + (q+1)k) at (-1 + 2i/q, -1 + 2j/q, -1 + 2k/q).
+
+Tetrahedra (solution order 4, the point set of Fig. mesh): the map is the Lagrange
+interpolant of total degree q on the equispaced nodes (i, j, k), i + j + k <= q (k
+outermost, then j, then i) at (-1 + 2i/q, -1 + 2j/q, -1 + 2k/q).  The conservative
+metric takes the same curl form with I_p the interpolant of total degree 4 on the 35
+solution points.  They include 15 points on every face, which fix a degree-4
+polynomial on that face, so the tangential part of I_p V on a face -- all that the
+face's normal row n~^T S depends on -- is the face interpolant of values the two
+elements sharing the face have in common; their unit normals agree (the lengths
+|S^T n~| differ by the ratio of the two reference faces' areas, as for straight
+tetrahedra).  The cross-product metric has degree 2(q - 1) here too, beyond 4 for
+q = 4.
 """
 from __future__ import annotations
 
@@ -39,6 +52,7 @@ import numpy as np
 from numpy.polynomial import legendre as npleg
 
 from . import polys
+from . import tet as otet
 
 
 def gll_nodes(n: int):
@@ -117,4 +131,56 @@ def metric(kind: str, q: int, p: int, X, xi):
         return conservative_metric(q, p, X, xi)
     if kind == "cross":
         return cross_metric(q, X, xi)
+    raise ValueError(kind)
+
+
+# ------------------------------------------------------------------- tetrahedra
+
+def tet_geo_nodes(q: int):
+    """Reference points [(q+1)(q+2)(q+3)/6][3] of the order-q tetrahedron's nodes."""
+    lat = [(i, j, k) for k in range(q + 1) for j in range(q + 1 - k) for i in range(q + 1 - k - j)]
+    return -1.0 + 2.0 * np.array(lat, dtype=np.float64) / q
+
+
+def tet_map_points(q: int, X, xi):
+    """Physical points [n][np][3] of tetrahedra with nodes X [n][nn][3]."""
+    N = otet.lagrange(tet_geo_nodes(q), np.atleast_2d(xi), q)        # [np][nn]
+    return np.einsum("pc,ecd->epd", N, X)
+
+
+def tet_jacobian(q: int, X, xi):
+    """G [n][np][3][3], G[..., i, j] = d x_i / d xi_j."""
+    dN = otet.lagrange_grad(tet_geo_nodes(q), np.atleast_2d(xi), q)  # [np][nn][3]
+    return np.einsum("pcj,eci->epij", dN, X)
+
+
+def tet_cross_metric(q: int, X, xi):
+    G = tet_jacobian(q, X, xi)
+    J = np.linalg.det(G)
+    return J, J[..., None, None] * np.linalg.inv(G)
+
+
+def tet_conservative_metric(q: int, X, xi):
+    """(J, S) with S_in = -[curl V^(n)]_i, V^(n) = I_4(x_l grad x_m) on the 35 solution points."""
+    Y = otet.SOL_PTS_P4
+    xY = tet_map_points(q, X - X[:, :1, :], Y)                      # relative to node 0
+    GY = tet_jacobian(q, X, Y)
+    dL = np.moveaxis(otet.lagrange_grad(Y, np.atleast_2d(xi), 4), 2, 0)   # [3][np][35]
+    S = np.empty(X.shape[:1] + (np.atleast_2d(xi).shape[0], 3, 3))
+    for n in range(3):
+        m, l = (n + 1) % 3, (n + 2) % 3
+        V = xY[..., l, None] * GY[..., m, :]
+        for r in range(3):
+            a, b = (r + 1) % 3, (r + 2) % 3
+            curl = np.einsum("pm,em->ep", dL[a], V[..., b]) - np.einsum("pm,em->ep", dL[b], V[..., a])
+            S[:, :, r, n] = -curl
+    J = np.linalg.det(tet_jacobian(q, X, xi))
+    return J, S
+
+
+def tet_metric(kind: str, q: int, X, xi):
+    if kind == "conservative":
+        return tet_conservative_metric(q, X, xi)
+    if kind == "cross":
+        return tet_cross_metric(q, X, xi)
     raise ValueError(kind)

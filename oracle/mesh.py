@@ -75,15 +75,16 @@ def _keys(c, period, scale):
 def build(mesh, order: int, metric: str = "conservative"):
     """Connectivity and geometry of `mesh` at polynomial order `order` (tets: 4).
 
-    Curved meshes (mesh.ho_enodes set, hexahedra of geometry order mesh.geo_order):
-    metric terms, J and solution points come from the high-order map (curved.py,
-    `metric` "conservative" or "cross"); faces are matched, flux points paired and
-    left/right sides chosen from the 8 corners as for straight elements."""
+    Curved meshes (mesh.ho_enodes set, hexahedra or tetrahedra of geometry order
+    mesh.geo_order, one type per mesh): metric terms, J and solution points come from
+    the high-order map (curved.py, `metric` "conservative" or "cross"); faces are
+    matched, flux points paired and left/right sides chosen from the corners as for
+    straight elements."""
     period = np.asarray(mesh.period, dtype=np.float64)
     types = [t for t in (HEX, TET) if np.any(mesh.etype == t)]
     ho = getattr(mesh, "ho_enodes", None)
-    if ho is not None and TET in types:
-        raise MeshError("curved meshes hold hexahedra only")
+    if ho is not None and len(types) != 1:
+        raise MeshError("curved meshes hold one element type")
     blocks = []
     for t in types:
         elems = np.nonzero(mesh.etype == t)[0]
@@ -97,9 +98,14 @@ def build(mesh, order: int, metric: str = "conservative"):
         else:
             q = int(mesh.geo_order)
             Xh = mesh.xyz[ho[elems]]
-            J, S = curved.metric(metric, q, order, Xh, ops.sol_pts)
-            Jf, Sf = curved.metric(metric, q, order, Xh, ops.flux_pts)
-            xsol = curved.map_points(q, Xh, ops.sol_pts)
+            if t == HEX:
+                J, S = curved.metric(metric, q, order, Xh, ops.sol_pts)
+                Jf, Sf = curved.metric(metric, q, order, Xh, ops.flux_pts)
+                xsol = curved.map_points(q, Xh, ops.sol_pts)
+            else:
+                J, S = curved.tet_metric(metric, q, Xh, ops.sol_pts)
+                Jf, Sf = curved.tet_metric(metric, q, Xh, ops.flux_pts)
+                xsol = curved.tet_map_points(q, Xh, ops.sol_pts)
         if np.any(J <= 0) or np.any(Jf <= 0):
             raise MeshError("element with J <= 0")
         snorm = np.einsum("epij,pi->epj", Sf, ops.normals)

@@ -14,6 +14,8 @@ Meshes
     * ``curved_hex_box``: the structured periodic grid with every element curved:
       a lattice of (n q + 1)^3 nodes per box moved by a smooth periodic displacement,
       each element described by its (q+1)^3 nodes (geometry order q).
+    * ``curved_tet_box``: the same curved lattice with every cell Kuhn-split, each
+      tetrahedron described by its (q+1)(q+2)(q+3)/6 lattice nodes.
 
 Node orders
     Hexahedra use the VTK corner order, reference corners
@@ -23,6 +25,8 @@ Node orders
     (-1,-1,-1) (1,-1,-1) (-1,-1,1) (-1,1,-1).
     Curved hexahedra of geometry order q list (q+1)^3 nodes in tensor order: node
     i + (q+1)(j + (q+1)k) sits at reference point (-1 + 2i/q, -1 + 2j/q, -1 + 2k/q).
+    Curved tetrahedra of geometry order q list the nodes (i, j, k), i + j + k <= q, k
+    outermost, then j, then i, at reference point (-1 + 2i/q, -1 + 2j/q, -1 + 2k/q).
 
 Initial conditions (evaluated at caller-given physical points)
     * Taylor--Green vortex (Sec. "Accuracy", TGV initial-condition equations),
@@ -58,8 +62,8 @@ class Mesh:
     enodes: np.ndarray         # [n_elem][8] int64, tets use the first 4
     period: np.ndarray         # [3] float64 box lengths (0 = not periodic)
     meta: dict = field(default_factory=dict)
-    geo_order: int = 1         # curved hexahedra: geometry order q of ho_enodes
-    ho_enodes: np.ndarray = None   # [n_elem][(q+1)^3] int64 tensor-order nodes (curved meshes)
+    geo_order: int = 1         # curved meshes: geometry order q of ho_enodes
+    ho_enodes: np.ndarray = None   # curved meshes (one element type): [n_elem][nodes] int64, see above
 
     @property
     def n_elem(self) -> int:
@@ -126,6 +130,29 @@ def hex_box(n=(4, 4, 4), lo=(-math.pi,) * 3, hi=(math.pi,) * 3, perturb=0.0,
     return Mesh(xyz, etype, en, period, {"n": n, "h": h, "kind": "hex_box"})
 
 
+def _curved_lattice(n, q, amp, lo, hi, perturb, perturb_seed):
+    """Nodes of the curved lattice shared by the curved boxes: (n_a q + 1) per direction,
+    evenly spaced, moved by the periodic displacement and the optional jitter described
+    in curved_hex_box.  Returns (xyz [n_nodes][3], nodes per direction, box lengths)."""
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+    L = hi - lo
+    m = [v * q + 1 for v in n]
+    K, J, I = np.meshgrid(np.arange(m[2]), np.arange(m[1]), np.arange(m[0]), indexing="ij")
+    x = lo[0] + I * (L[0] / (n[0] * q))
+    y = lo[1] + J * (L[1] / (n[1] * q))
+    z = lo[2] + K * (L[2] / (n[2] * q))
+    sx, sy, sz = (2 * np.pi * (x - lo[0]) / L[0], 2 * np.pi * (y - lo[1]) / L[1], 2 * np.pi * (z - lo[2]) / L[2])
+    xyz = np.stack([x + amp * L[0] / (2 * np.pi) * np.sin(sy) * np.sin(sz),
+                    y + amp * L[1] / (2 * np.pi) * np.sin(sx) * np.sin(sz),
+                    z + amp * L[2] / (2 * np.pi) * np.sin(sx) * np.sin(sy)], axis=-1)
+    if perturb:
+        hn = L / (np.asarray(n, dtype=np.float64) * q)
+        jit = np.random.default_rng(perturb_seed).uniform(-perturb, perturb, size=(m[2] - 1, m[1] - 1, m[0] - 1, 3))
+        xyz = xyz + jit[K % (m[2] - 1), J % (m[1] - 1), I % (m[0] - 1)] * hn
+    return xyz.reshape(-1, 3), m, L
+
+
 def curved_hex_box(n=(4, 4, 4), q=2, amp=0.15, lo=(-math.pi,) * 3, hi=(math.pi,) * 3,
                    perturb=0.0, perturb_seed=None, permute_seed=None) -> Mesh:
     """Periodic box of nx*ny*nz hexahedra of geometry order q, all curved.
@@ -147,23 +174,7 @@ def curved_hex_box(n=(4, 4, 4), q=2, amp=0.15, lo=(-math.pi,) * 3, hi=(math.pi,)
     """
     n = tuple(int(v) for v in n)
     q = int(q)
-    lo = np.asarray(lo, dtype=np.float64)
-    hi = np.asarray(hi, dtype=np.float64)
-    L = hi - lo
-    m = [v * q + 1 for v in n]
-    K, J, I = np.meshgrid(np.arange(m[2]), np.arange(m[1]), np.arange(m[0]), indexing="ij")
-    x = lo[0] + I * (L[0] / (n[0] * q))
-    y = lo[1] + J * (L[1] / (n[1] * q))
-    z = lo[2] + K * (L[2] / (n[2] * q))
-    sx, sy, sz = (2 * np.pi * (x - lo[0]) / L[0], 2 * np.pi * (y - lo[1]) / L[1], 2 * np.pi * (z - lo[2]) / L[2])
-    xyz = np.stack([x + amp * L[0] / (2 * np.pi) * np.sin(sy) * np.sin(sz),
-                    y + amp * L[1] / (2 * np.pi) * np.sin(sx) * np.sin(sz),
-                    z + amp * L[2] / (2 * np.pi) * np.sin(sx) * np.sin(sy)], axis=-1)
-    if perturb:
-        hn = L / (np.asarray(n, dtype=np.float64) * q)
-        jit = np.random.default_rng(perturb_seed).uniform(-perturb, perturb, size=(m[2] - 1, m[1] - 1, m[0] - 1, 3))
-        xyz = xyz + jit[K % (m[2] - 1), J % (m[1] - 1), I % (m[0] - 1)] * hn
-    xyz = xyz.reshape(-1, 3)
+    xyz, m, L = _curved_lattice(n, q, amp, lo, hi, perturb, perturb_seed)
 
     def vid(i, j, k):
         return (k * m[1] + j) * m[0] + i
@@ -223,6 +234,52 @@ def kuhn_split(mesh: Mesh, permute_seed=None) -> Mesh:
     meta = dict(mesh.meta)
     meta["kind"] = "kuhn"
     return Mesh(mesh.xyz.copy(), etype, en, mesh.period.copy(), meta)
+
+
+def curved_tet_box(n=(3, 3, 3), q=2, amp=0.15, lo=(-math.pi,) * 3, hi=(math.pi,) * 3,
+                   perturb=0.0, perturb_seed=None, permute_seed=None) -> Mesh:
+    """Periodic box of 6 nx*ny*nz tetrahedra of geometry order q, all curved.
+
+    The lattice, displacement and jitter are those of curved_hex_box; every cell is
+    cut into the 6 tetrahedra of kuhn_split (same diagonal, same corner fix-up, the
+    orientation taken from the undisplaced cell).  Tetrahedron nodes (ho_enodes,
+    (q+1)(q+2)(q+3)/6 of them) are the lattice nodes q C0 + i (C1 - C0) + j (C3 - C0)
+    + k (C2 - C0) (C the corners' cell offsets, in the reference corner order) for
+    i + j + k <= q, k outermost, then j, then i; node (i, j, k) sits at reference
+    point (-1 + 2i/q, -1 + 2j/q, -1 + 2k/q).  Neighbouring tetrahedra share the
+    lattice nodes of their common face, so curved faces conform.
+    """
+    n = tuple(int(v) for v in n)
+    q = int(q)
+    xyz, m, L = _curved_lattice(n, q, amp, lo, hi, perturb, perturb_seed)
+    tets = []
+    for perm in itertools.permutations(range(3)):
+        P = [np.zeros(3, dtype=np.int64)]
+        for ax in perm:
+            nxt = P[-1].copy()
+            nxt[ax] = 1
+            P.append(nxt)
+        vol = np.dot(P[1] - P[0], np.cross(P[3] - P[0], P[2] - P[0]))
+        if vol < 0:
+            P = [P[0], P[2], P[1], P[3]]
+        tets.append(P)
+    lat = [(i, j, k) for k in range(q + 1) for j in range(q + 1 - k) for i in range(q + 1 - k - j)]
+    kk, jj, ii = np.meshgrid(np.arange(n[2]), np.arange(n[1]), np.arange(n[0]), indexing="ij")
+    cell = np.stack([ii.ravel(), jj.ravel(), kk.ravel()], axis=1) * q          # [ncell][3]
+    ho = []
+    for P in tets:
+        off = np.array([q * P[0] + i * (P[1] - P[0]) + j * (P[3] - P[0]) + k * (P[2] - P[0]) for i, j, k in lat])
+        g = cell[:, None, :] + off[None, :, :]                                     # [ncell][nn][3]
+        ho.append((g[..., 2] * m[1] + g[..., 1]) * m[0] + g[..., 0])
+    ho = np.stack(ho, axis=1).reshape(-1, len(lat)).astype(np.int64)            # cell-major, 6 per cell
+    c_ids = [lat.index((0, 0, 0)), lat.index((q, 0, 0)), lat.index((0, 0, q)), lat.index((0, q, 0))]
+    if permute_seed is not None:
+        ho = ho[np.random.default_rng(permute_seed).permutation(ho.shape[0])]
+    en = np.full((ho.shape[0], 8), -1, dtype=np.int64)
+    en[:, :4] = ho[:, c_ids]
+    etype = np.full(ho.shape[0], TET, dtype=np.int32)
+    return Mesh(xyz, etype, en, L.copy(), {"n": n, "kind": "curved_tet_box", "q": q, "amp": amp},
+                geo_order=q, ho_enodes=ho)
 
 
 def concat(meshes, permute_seed=None) -> Mesh:

@@ -64,6 +64,12 @@ CONFIGS = {
     # displacement of amplitude 0.1): metric terms stored per point, conservative form
     "ns_tgv_hex32_p3_curved": dict(kind="curved", n=(32, 32, 32), q=3, amp=0.1, order=3, system=1, riemann=0,
                                    mach=0.1, dt=4e-4, oracle_ok=True),
+    # the NS TGV on curved tetrahedra of geometry order 4 (the order where the cross-product
+    # metric's degree, 6, exceeds the solution order): 32^3 cells of the same curved lattice
+    # (amplitude 0.1), 6 tetrahedra each (196,608 elements, 6.9 M points), element order
+    # seed 57, conservative metric; oracle timing sample at 8^3 cells
+    "ns_tgv_tet32_q4_curved": dict(kind="curved_tet", n=(32, 32, 32), q=4, amp=0.1, order=4, system=1, riemann=0,
+                                   mach=0.1, dt=7.5e-5, permute_seed=57, oracle_sample=(8, 8, 8)),
     "ns_tgv_hex32_p3_adaptive": dict(n=(32, 32, 32), order=3, system=1, riemann=0, mach=0.1, dt=4e-4,
                                      adaptive=True, t_end=8e-3, tol=1e-6),
     "euler_shock_hex48_p3": dict(n=(48, 48, 48), order=3, system=0, riemann=1, dt=5e-4, filter=True,
@@ -85,6 +91,8 @@ def build_mesh(cfg, inputs):
         return inputs.concat([a, b], permute_seed=cfg["permute_seed"])
     if cfg.get("kind") == "curved":
         return inputs.curved_hex_box(cfg["n"], q=cfg["q"], amp=cfg["amp"], permute_seed=cfg.get("permute_seed"))
+    if cfg.get("kind") == "curved_tet":
+        return inputs.curved_tet_box(cfg["n"], q=cfg["q"], amp=cfg["amp"], permute_seed=cfg.get("permute_seed"))
     return inputs.hex_box(cfg["n"], perturb=cfg.get("perturb", 0.0), perturb_seed=cfg.get("perturb_seed"),
                           permute_seed=cfg.get("permute_seed"))
 
@@ -101,13 +109,19 @@ def kernel_bytes_per_elem(name, nsp, nfp):
     read stored metric terms instead of the 24 corner words: S rows and 1/J at the
     solution points (10 words each) where a kernel forms fluxes or gradients there,
     row d of S at the flux points (3 words each) where it forms common fluxes (the
-    face kernel forms each pair's flux once, from the left side: half of them)."""
+    face kernel forms each pair's flux once, from the left side: half of them).  Curved
+    tetrahedra read S and J per solution point (10 words) instead of per element and take
+    the two-sided common flux in both precisions (gradient stored whole, no pair-once
+    common fluxes)."""
     fam = name.rsplit("_p", 1)[0] if "_p" in name else name
     d = 8
     if fam.endswith("_f32"):
         fam, d = fam[:-4], 4
     if fam.endswith("_cur"):
         base = fam[:-4]
+        if base.startswith("tet_"):
+            two_sided = {"tet_div_euler": 10 * nsp, "tet_grad": 20 * nsp, "tet_div_ns": 25 * nsp}.get(base)
+            return None if two_sided is None else d * (two_sided + 10 * nsp) + 4 * 2 * 4
         plain = kernel_bytes_per_elem(base + ("_f32" if d == 4 else "") + "_p0", nsp, nfp)
         if plain is None:
             return None
@@ -776,7 +790,7 @@ def main():
         return
     forms = [f.strip() for f in (args.forms or cfg.get("forms", "fp32,fp64")).split(",") if f.strip()]
     out, mesh = run_tgv_workload(args.config, cfg, forms, args, torch, np, frmi, inputs)
-    if cfg.get("kind") == "curved":
+    if cfg.get("kind") in ("curved", "curved_tet"):
         # a uniform stream on the same curved mesh, both metrics (FP64): the conservative
         # metric keeps it (R at rounding level), the cross-product metric does not once its
         # degree exceeds the solution order (Sec. "Curved elements", Fig. fsp)

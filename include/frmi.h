@@ -98,7 +98,8 @@ typedef struct {
   double filt_eps_s;       /* entropy filter: relative entropy tolerance (all >= 0)  */
   double filt_zeta_max_coef; /* zeta_max = coef * p^2, coef > 0 and finite          */
   int32_t filt_bits;       /* dyadic search depth n (2^n grid), 1..30                */
-  int32_t hex_metric;      /* metric terms of curved hexahedra (fr_setup_mesh_curved):
+  int32_t hex_metric;      /* metric terms of curved elements (fr_setup_mesh_curved,
+                              fr_setup_mesh_curved_tet; the name predates the latter):
                               FR_METRIC_CONSERVATIVE (default) or FR_METRIC_CROSS     */
 } fr_params;
 
@@ -195,6 +196,33 @@ fr_status fr_setup_mesh(const fr_params* p, int64_t n_vert, const double* xyz,
 fr_status fr_setup_mesh_curved(const fr_params* p, int32_t geo_order, int64_t n_vert, const double* xyz,
                                const double* period, int64_t n_elem, const int64_t* ho_nodes, void* stream,
                                fr_ctx* out);
+
+/* Build a context for a periodic conforming mesh of curved tetrahedra (Sec. "Curved
+ * elements", the tetrahedra of Fig. fsp), solution order 4 (p->order must be 4).
+ *   geo_order  q in 1..4: geometry order of every element.
+ *   ho_nodes   [n_elem][(q+1)(q+2)(q+3)/6] indices into xyz: the nodes (i, j, k) with
+ *              i + j + k <= q, k outermost, then j, then i, at reference point
+ *              (-1 + 2i/q, -1 + 2j/q, -1 + 2k/q) of the reference tetrahedron with
+ *              corners (-1,-1,-1) (1,-1,-1) (-1,-1,1) (-1,1,-1); the map is their
+ *              Lagrange interpolant of total degree q.  Faces are matched from the 4
+ *              corner nodes as in fr_setup_mesh; elements sharing a face must share its
+ *              nodes.
+ *   p->hex_metric  FR_METRIC_CONSERVATIVE: the curl form as for hexahedra with the
+ *              interpolant of total degree 4 on the 35 solution points (15 on each
+ *              face, so the two elements of a face agree on its unit normal);
+ *              FR_METRIC_CROSS: S from the exact Jacobian, a polynomial of degree
+ *              2(q - 1), which the solution polynomials miss for q = 4.  J is
+ *              det(dx/dxi) of the exact map in both cases.
+ * The metric terms are stored per solution point (9 + 1 values, read by the collocated
+ * flux points too) in the kernels' arithmetic type; the right-hand side then takes the
+ * two-sided common flux (the pair-once form of straight tetrahedra is not used); every
+ * other call behaves as for fr_setup_mesh.  Synchronous.
+ * Errors: FR_ERR_ARG (NULL, index out of range), FR_ERR_UNSUPPORTED (q outside 1..4,
+ * order other than 4), FR_ERR_MESH (unpaired face, J <= 0 at a solution point),
+ * FR_ERR_ALLOC. */
+fr_status fr_setup_mesh_curved_tet(const fr_params* p, int32_t geo_order, int64_t n_vert, const double* xyz,
+                                   const double* period, int64_t n_elem, const int64_t* ho_nodes, void* stream,
+                                   fr_ctx* out);
 
 fr_status fr_layout(fr_ctx ctx, fr_layout_t* out);
 

@@ -502,7 +502,9 @@ fr_status hex_rhs_p(fr_ctx c, DevBlock& b, const T* u, T* r) {
   return FR_OK;
 }
 
-template <typename T, bool DEV>
+// CUR: curved tetrahedra, the metric stored per solution point (b.cmet) in place of the
+// per-element terms; they take the two-sided common flux (no pair-once form).
+template <typename T, bool DEV, bool CUR>
 fr_status tet_rhs(fr_ctx c, DevBlock& b, const T* u, T* r) {
   Conn C{b.nbr_elem, b.nbr_info, c->perm, c->host.perm_stride};
   const fr_params& p = c->prm;
@@ -513,8 +515,8 @@ fr_status tet_rhs(fr_ctx c, DevBlock& b, const T* u, T* r) {
   for (int f = 0; f < 4; ++f)
     for (int k = 0; k < 3; ++k) O.nref[f][k] = (T)c->host.tet.nref[f][k];
   const RefState<T> R = ref_of<T>(p);
-  const T* geo = (const T*)b.geo_t;
-  static const std::string sfx = sizeof(T) == 8 ? "" : "_f32";
+  const T* geo = (const T*)(CUR ? b.cmet : b.geo_t);
+  static const std::string sfx = std::string(CUR ? "_cur" : "") + (sizeof(T) == 8 ? "" : "_f32");
   const int sm = side_mode_of(p.ldg_beta);
   const unsigned div_grid = (unsigned)(b.E / TDIV_NE);   // one 16-element tile per block
   const T* opT = (const T*)c->tet_opT;
@@ -528,25 +530,25 @@ fr_status tet_rhs(fr_ctx c, DevBlock& b, const T* u, T* r) {
   if (p.system == FR_EULER) {
     pk = c->prof_begin(("tet_div_euler" + sfx).c_str());
     if (bf3)
-      tet_div<T, DEV, false, can_bf3, false><<<div_grid, tdiv_nt<T>(), 0, c->stream>>>(
+      tet_div<T, DEV, false, can_bf3, false, CUR><<<div_grid, tdiv_nt<T>(), 0, c->stream>>>(
           u, nullptr, nullptr, geo, C, O, opT, opH, opL, r, b.E, b.n, (T)p.gamma, zero, zero, zero, zero, p.riemann, 0,
           R);
     else
-      tet_div<T, DEV, false, false, false><<<div_grid, tdiv_nt<T>(), 0, c->stream>>>(
+      tet_div<T, DEV, false, false, false, CUR><<<div_grid, tdiv_nt<T>(), 0, c->stream>>>(
           u, nullptr, nullptr, geo, C, O, opT, opH, opL, r, b.E, b.n, (T)p.gamma, zero, zero, zero, zero, p.riemann, 0,
           R);
     c->prof_end(pk);
   } else {
     // one-sided LDG (beta = +-1/2), FP32 form: the gradient kernel also forms the common
     // fluxes (in FP64 the extra registers cost that kernel more than the divergence saves)
-    constexpr bool can_fc = sizeof(T) == 4;
+    constexpr bool can_fc = sizeof(T) == 4 && !CUR;
     const bool fc = sm != 0 && can_fc;
     T* fcb = (T*)b.fc;
     const T gam = (T)p.gamma, mu = (T)p.mu, pr = (T)p.prandtl, beta = (T)p.ldg_beta, tau = (T)p.ldg_tau;
     const T* ogT = (const T*)c->tet_ogT;
     pk = c->prof_begin(("tet_grad" + sfx).c_str());
 #define FR_TET_GRAD(BF, FCX)                                                                                   \
-  tet_grad_mma<T, DEV, BF, FCX><<<div_grid, tgr_nt<T>(), 0, c->stream>>>(u, geo, C, O, ogT, ogH, ogL, (T*)b.grad, fcb, \
+  tet_grad_mma<T, DEV, BF, FCX, CUR><<<div_grid, tgr_nt<T>(), 0, c->stream>>>(u, geo, C, O, ogT, ogH, ogL, (T*)b.grad, fcb, \
                                                                     b.E, b.n, beta, sm, gam, mu, pr, tau,       \
                                                                     p.riemann, R)
     if (bf3) {
@@ -558,7 +560,7 @@ fr_status tet_rhs(fr_ctx c, DevBlock& b, const T* u, T* r) {
     c->prof_end(pk);
     pk = c->prof_begin(("tet_div_ns" + sfx).c_str());
 #define FR_TET_DIV(BF, FCX)                                                                                     \
-  tet_div<T, DEV, true, BF, FCX><<<div_grid, tdiv_nt<T>(), 0, c->stream>>>(u, (const T*)b.grad, fcb, geo, C, O, opT, opH, \
+  tet_div<T, DEV, true, BF, FCX, CUR><<<div_grid, tdiv_nt<T>(), 0, c->stream>>>(u, (const T*)b.grad, fcb, geo, C, O, opT, opH, \
                                                                      opL, r, b.E, b.n, gam, mu, pr, beta, tau,   \
                                                                      p.riemann, sm, R)
     if (bf3) {
@@ -589,7 +591,7 @@ fr_status rhs_t(fr_ctx c, const T* u, T* r) {
         default: s = fail(c, FR_ERR_UNSUPPORTED, "order");
       }
     } else {
-      s = tet_rhs<T, DEV>(c, b, ub, rb);
+      s = b.cmet ? tet_rhs<T, DEV, true>(c, b, ub, rb) : tet_rhs<T, DEV, false>(c, b, ub, rb);
     }
     if (s != FR_OK) return s;
   }
@@ -1087,7 +1089,11 @@ fr_status setup_impl(const fr_params* p, int64_t n_vert, const double* xyz, cons
   std::string msg;
   try {
     msg = build_setup(p->order, n_vert, xyz, period, n_elem, etype, enodes, 64, p->elem_order, c->host, code);
-    if (msg.empty() && ho_nodes) msg = build_curved_hex(geo_order, p->hex_metric, xyz, ho_nodes, c->host, code);
+    if (msg.empty() && ho_nodes) {
+      const bool tets = !c->host.blocks.empty() && c->host.blocks[0].etype == kTet;
+      msg = tets ? build_curved_tet(geo_order, p->hex_metric, xyz, ho_nodes, c->host, code)
+                 : build_curved_hex(geo_order, p->hex_metric, xyz, ho_nodes, c->host, code);
+    }
   } catch (const std::exception& ex) {
     msg = ex.what();
     code = 3;
@@ -1333,6 +1339,33 @@ fr_status fr_setup_mesh_curved(const fr_params* p, int32_t geo_order, int64_t n_
       corners[(size_t)e * 8 + c] = ho_nodes[e * NQ + i + nq * (j + nq * k)];
     }
   std::vector<int32_t> et((size_t)n_elem, FR_HEX);
+  return setup_impl(p, n_vert, xyz, period, n_elem, et.data(), corners.data(), geo_order, ho_nodes, stream, out);
+}
+
+fr_status fr_setup_mesh_curved_tet(const fr_params* p, int32_t geo_order, int64_t n_vert, const double* xyz,
+                                   const double* period, int64_t n_elem, const int64_t* ho_nodes, void* stream,
+                                   fr_ctx* out) {
+  if (!out) return fail(nullptr, FR_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!p || p->struct_size != sizeof(fr_params)) return fail(nullptr, FR_ERR_ARG, "fr_params missing or struct_size mismatch");
+  if (!xyz || !period || !ho_nodes || n_vert <= 0 || n_elem <= 0) return fail(nullptr, FR_ERR_ARG, "empty mesh or NULL array");
+  if (geo_order < 1 || geo_order > 4) return fail(nullptr, FR_ERR_UNSUPPORTED, "geometry order must be in 1..4");
+  const int q = geo_order, NQ = (q + 1) * (q + 2) * (q + 3) / 6;
+  for (int64_t i = 0; i < n_elem * NQ; ++i)
+    if (ho_nodes[i] < 0 || ho_nodes[i] >= n_vert) return fail(nullptr, FR_ERR_ARG, "node index out of range");
+  // node (i, j, k) has index k-outer, j, i-inner among i + j + k <= q; the corners in
+  // reference order are the nodes (0,0,0), (q,0,0), (0,0,q), (0,q,0)
+  auto node_id = [q](int i, int j, int k) {
+    int id = 0;
+    for (int kk = 0; kk < k; ++kk) id += (q + 1 - kk) * (q + 2 - kk) / 2;
+    for (int jj = 0; jj < j; ++jj) id += q + 1 - k - jj;
+    return id + i;
+  };
+  const int cid[4] = {node_id(0, 0, 0), node_id(q, 0, 0), node_id(0, 0, q), node_id(0, q, 0)};
+  std::vector<int64_t> corners((size_t)n_elem * 8, -1);
+  for (int64_t e = 0; e < n_elem; ++e)
+    for (int c = 0; c < 4; ++c) corners[(size_t)e * 8 + c] = ho_nodes[e * NQ + cid[c]];
+  std::vector<int32_t> et((size_t)n_elem, FR_TET);
   return setup_impl(p, n_vert, xyz, period, n_elem, et.data(), corners.data(), geo_order, ho_nodes, stream, out);
 }
 

@@ -979,4 +979,140 @@ std::string build_curved_hex(int q, int metric, const double* xyz, const int64_t
   return "";
 }
 
+// ------------------------------------------------------------------ curved tetrahedra
+// The same two metrics at the 35 solution points of the order-4 tetrahedron for a map
+// of total degree q (1..4) on the equispaced nodes (i, j, k), i + j + k <= q (k
+// outermost, then j, then i) at (-1 + 2i/q, -1 + 2j/q, -1 + 2k/q).  Conservative form:
+// V^(n) = (x_l - x0_l) grad_xi x_m sampled at the solution points -- they interpolate
+// P_4 and 15 of them lie on every face, so the face rows depend only on values the two
+// elements of a face share -- and differentiated there with the element's own nodal
+// derivative matrices, which are exact for that interpolant.  The flux points are
+// solution points, so there is no separate face evaluation.  Stored per solution point
+// pt: S (row pt*10 + 3i + j, S_ij = J dxi_i/dx_j) and J (row pt*10 + 9).
+std::string build_curved_tet(int q, int metric, const double* xyz, const int64_t* ho, Setup& s, int& code) {
+  code = 0;
+  Block* bp = nullptr;
+  for (auto& b : s.blocks) if (b.etype == kTet) bp = &b;
+  if (!bp) { code = 1; return "no tetrahedra"; }
+  Block& b = *bp;
+  const TetOps& T = s.tet;
+  constexpr int N = TetOps::nsp;
+  if (q < 1 || q > 4) { code = 3; return "geometry order must be in 1..4"; }
+  // geometry nodes and the monomials of total degree <= q (centred at the centroid)
+  int lat[N][3], ex[N][3], NQ = 0, NM = 0;
+  for (int k = 0; k <= q; ++k)
+    for (int j = 0; j <= q - k; ++j)
+      for (int i = 0; i <= q - k - j; ++i) { lat[NQ][0] = i; lat[NQ][1] = j; lat[NQ][2] = k; ++NQ; }
+  for (int d = 0; d <= q; ++d)
+    for (int c = 0; c <= d; ++c)
+      for (int bb = 0; bb <= d - c; ++bb) { ex[NM][0] = d - bb - c; ex[NM][1] = bb; ex[NM][2] = c; ++NM; }
+  auto mono = [&](const ld* xi, int m, int dir) -> ld {   // monomial m or its derivative along dir (-1: value)
+    ld v = 1;
+    for (int a = 0; a < 3; ++a) {
+      const int e = ex[m][a] - (a == dir ? 1 : 0);
+      if (e < 0) return 0;
+      ld t = 1;
+      for (int r = 0; r < e; ++r) t *= xi[a] + 0.5L;
+      v *= (a == dir ? (ld)ex[m][a] : 1) * t;
+    }
+    return v;
+  };
+  ld A[N][N];
+  for (int n = 0; n < NQ; ++n) {
+    ld xi[3];
+    for (int a = 0; a < 3; ++a) xi[a] = -1 + 2 * (ld)lat[n][a] / q;
+    for (int m = 0; m < NM; ++m) A[n][m] = mono(xi, m, -1);
+  }
+  if (!invert(A, NQ)) { code = 3; return "singular geometry basis"; }   // l_j = sum_m mono_m A[m][j]
+  // basis values and gradients at the solution points
+  std::vector<double> Nv((size_t)N * NQ), dN((size_t)N * NQ * 3);
+  for (int z = 0; z < N; ++z) {
+    ld xi[3] = {T.pts[z][0], T.pts[z][1], T.pts[z][2]};
+    for (int j = 0; j < NQ; ++j) {
+      ld v = 0, g[3] = {0, 0, 0};
+      for (int m = 0; m < NM; ++m) {
+        v += mono(xi, m, -1) * A[m][j];
+        for (int a = 0; a < 3; ++a) g[a] += mono(xi, m, a) * A[m][j];
+      }
+      Nv[(size_t)z * NQ + j] = (double)v;
+      for (int a = 0; a < 3; ++a) dN[((size_t)z * NQ + j) * 3 + a] = (double)g[a];
+    }
+  }
+  b.cmet.assign((size_t)10 * N * b.e_pad, 0.0);
+  auto work = [&](int64_t lo, int64_t hi, std::string& err) {
+    std::vector<double> X((size_t)NQ * 3);
+    double x[N][3], G[N][3][3], V[3][N][3];
+    for (int64_t le = lo; le < hi; ++le) {
+      const int64_t e = b.elems[le];
+      for (int n = 0; n < NQ; ++n)
+        for (int c = 0; c < 3; ++c) X[(size_t)n * 3 + c] = xyz[ho[e * NQ + n] * 3 + c];
+      for (int z = 0; z < N; ++z) {
+        for (int c = 0; c < 3; ++c) {
+          x[z][c] = 0;
+          G[z][c][0] = G[z][c][1] = G[z][c][2] = 0;
+        }
+        for (int n = 0; n < NQ; ++n) {
+          const double w = Nv[(size_t)z * NQ + n];
+          const double* d = &dN[((size_t)z * NQ + n) * 3];
+          for (int c = 0; c < 3; ++c) {
+            x[z][c] += w * X[(size_t)n * 3 + c];
+            for (int a = 0; a < 3; ++a) G[z][c][a] += d[a] * X[(size_t)n * 3 + c];
+          }
+        }
+      }
+      if (metric == 0)
+        for (int z = 0; z < N; ++z)
+          for (int n = 0; n < 3; ++n) {
+            const int m = (n + 1) % 3, l = (n + 2) % 3;
+            for (int k = 0; k < 3; ++k) V[n][z][k] = (x[z][l] - X[l]) * G[z][m][k];
+          }
+      for (int z = 0; z < N; ++z) {
+        const double (&g)[3][3] = G[z];
+        const double J = g[0][0] * (g[1][1] * g[2][2] - g[1][2] * g[2][1]) - g[0][1] * (g[1][0] * g[2][2] - g[1][2] * g[2][0]) +
+                         g[0][2] * (g[1][0] * g[2][1] - g[1][1] * g[2][0]);
+        if (!(J > 0)) { err = "curved element with J <= 0"; return; }
+        double S[3][3];
+        if (metric == 0) {
+          for (int n = 0; n < 3; ++n) {
+            double dV[3][3];   // dV[ax][k] = d V^(n)_k / d xi_ax at point z
+            for (int ax = 0; ax < 3; ++ax)
+              for (int k = 0; k < 3; ++k) {
+                double acc = 0;
+                for (int y = 0; y < N; ++y) acc += T.D[ax][z][y] * V[n][y][k];
+                dV[ax][k] = acc;
+              }
+            for (int r = 0; r < 3; ++r) {
+              const int ra = (r + 1) % 3, rb = (r + 2) % 3;
+              S[r][n] = -(dV[ra][rb] - dV[rb][ra]);
+            }
+          }
+        } else {
+          // row r = g_{r+1} x g_{r+2}, g_a = column a of G
+          for (int r = 0; r < 3; ++r) {
+            const int a = (r + 1) % 3, c = (r + 2) % 3;
+            S[r][0] = g[1][a] * g[2][c] - g[2][a] * g[1][c];
+            S[r][1] = g[2][a] * g[0][c] - g[0][a] * g[2][c];
+            S[r][2] = g[0][a] * g[1][c] - g[1][a] * g[0][c];
+          }
+        }
+        for (int r = 0; r < 9; ++r) b.cmet[(size_t)(z * 10 + r) * b.e_pad + le] = S[r / 3][r % 3];
+        b.cmet[(size_t)(z * 10 + 9) * b.e_pad + le] = J;
+        for (int c = 0; c < 3; ++c) b.sol_xyz[((size_t)b.canon_pos[le] * N + z) * 3 + c] = x[z][c];
+      }
+    }
+  };
+  const int64_t nthr = std::max<int64_t>(1, std::min<int64_t>({16, (int64_t)std::thread::hardware_concurrency(),
+                                                               (b.n + 255) / 256}));
+  std::vector<std::string> errs((size_t)nthr);
+  std::vector<std::thread> pool;
+  for (int64_t t = 0; t < nthr; ++t)
+    pool.emplace_back(work, b.n * t / nthr, b.n * (t + 1) / nthr, std::ref(errs[(size_t)t]));
+  for (auto& th : pool) th.join();
+  for (auto& m : errs)
+    if (!m.empty()) { code = 2; return m; }
+  for (int r = 0; r < 10 * N; ++r)
+    for (int64_t le = b.n; le < b.e_pad; ++le) b.cmet[(size_t)r * b.e_pad + le] = b.cmet[(size_t)r * b.e_pad];
+  return "";
+}
+
 }  // namespace frmi

@@ -53,10 +53,11 @@ struct Block {
   std::vector<int32_t> nbr_elem;   // [nfaces][e_pad] neighbour's local index (same block)
   std::vector<int32_t> nbr_info;   // [nfaces][e_pad] nbr_face | orient << 3 | is_left << 12
   std::vector<double> sol_xyz;     // [n][nsp][3] physical solution points (canonical order)
-  // Curved hexahedra: stored metric terms (empty for straight elements), rows of e_pad
-  // values: S row d at solution point pt (row pt*9 + d*3 + j, S = J G^{-1}), 1/J at
-  // solution point pt (row 9 nsp + pt), and at flux point fp of face 2d+s row d of S
-  // (row 10 nsp + fp*3 + j).
+  // Curved elements: stored metric terms (empty for straight elements), rows of e_pad
+  // values.  Hexahedra: S row d at solution point pt (row pt*9 + d*3 + j, S = J G^{-1}),
+  // 1/J at solution point pt (row 9 nsp + pt), and at flux point fp of face 2d+s row d
+  // of S (row 10 nsp + fp*3 + j).  Tetrahedra (flux points are solution points): S at
+  // solution point pt (row pt*10 + 3i + j) and J (row pt*10 + 9).
   std::vector<double> cmet;
 };
 
@@ -83,5 +84,10 @@ std::string build_setup(int order, int64_t n_vert, const double* xyz, const doub
 // (-1 + 2i/q, -1 + 2j/q, -1 + 2k/q)).  metric 0: conservative (curl) form, 1: cross
 // product.  Fills Block::cmet and replaces Block::sol_xyz with the curved points.
 std::string build_curved_hex(int q, int metric, const double* xyz, const int64_t* ho, Setup& s, int& code);
+
+// The same for curved tetrahedra of geometry order q (1..4; the tetrahedral block of
+// `s`).  ho: [n_elem][(q+1)(q+2)(q+3)/6] node indices, nodes (i, j, k) with
+// i + j + k <= q, k outermost, then j, then i, at (-1 + 2i/q, -1 + 2j/q, -1 + 2k/q).
+std::string build_curved_tet(int q, int metric, const double* xyz, const int64_t* ho, Setup& s, int& code);
 
 }  // namespace frmi

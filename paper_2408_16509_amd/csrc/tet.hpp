@@ -6,7 +6,9 @@
 // Folding that trace into the derivative gives (eq:FRfinal, DG lifting L = M^{-1}E)
 //     div = sum_i Dh_i f~_i + L F^C,   Dh_i = D_i - L diag(n~_i) (scattered to sources),
 // and the LDG corrected reference gradient is gt_i = Dh_i u + L diag(n~_i) u^.
-// Affine elements: S = J G^{-1} and J are constant per element (geo[10][E]).
+// Affine elements: S = J G^{-1} and J are constant per element (geo[10][E]).  Curved
+// elements (CUR, Sec. "Curved elements"): S and J stored per solution point
+// (geo[pt * 10 + k][E]); a flux point takes the metric of its collocated solution point.
 //
 // Kernels: the gradient and the divergence, each one dense contraction per block of
 // 16 elements on the matrix cores, with the panel ([u; u^], or the transformed and
@@ -235,7 +237,7 @@ constexpr int tgr_nt() { return sizeof(T) == 4 ? 4 * 64 : 5 * 64; }
 // formed once per flux-point pair by the gradient kernel and stored in the slot of the
 // side that formed them; here each flux point reads its pair's value and scales it by
 // the element's own +-|S^T n~|.
-template <typename T, bool DEV, bool NS, bool BF3, bool FCIN>
+template <typename T, bool DEV, bool NS, bool BF3, bool FCIN, bool CUR = false>
 __global__ void __launch_bounds__(tdiv_nt<T>()) tet_div(const T* __restrict__ u, const T* __restrict__ grad,
                                                    const T* __restrict__ fcin,
                                                    const T* __restrict__ geo, Conn C, TetDev<T> O,
@@ -245,8 +247,9 @@ __global__ void __launch_bounds__(tdiv_nt<T>()) tet_div(const T* __restrict__ u,
                                                    int side_mode, RefState<T> R) {
   constexpr int NE = TDIV_NE, NT = tdiv_nt<T>();
   constexpr int KA = BF3 ? TET_KA16 : TET_KA, KB = BF3 ? TET_KB16 : TET_KB;
+  static_assert(!(CUR && FCIN), "curved elements take the two-sided common flux");
   __shared__ T PAN[KA * 5 * NE];          // [k][v][el]; the second K chunk reuses it
-  __shared__ T SJ[10 * NE];
+  __shared__ T SJ[CUR ? 1 : 10 * NE];
   const int t = threadIdx.x;
   const int w = t / 64, lane = t % 64, col = lane % 16;
   const int mt[1] = {w};
@@ -271,7 +274,8 @@ __global__ void __launch_bounds__(tdiv_nt<T>()) tet_div(const T* __restrict__ u,
         nel[j] = ok ? C.nbr_elem[o] : 0;
       }
     }
-    for (int i = t; i < 10 * NE; i += NT) SJ[i] = geo[(int64_t)(i / NE) * E + e0 + i % NE];
+    if constexpr (!CUR)
+      for (int i = t; i < 10 * NE; i += NT) SJ[i] = geo[(int64_t)(i / NE) * E + e0 + i % NE];
     for (int i = t; i < (KA - 105) * 5 * NE; i += NT) PAN[105 * 5 * NE + i] = T(0);
     __syncthreads();
     // K chunk 1: transformed fluxes at the solution points
@@ -280,6 +284,10 @@ __global__ void __launch_bounds__(tdiv_nt<T>()) tet_div(const T* __restrict__ u,
       const int64_t e = e0 + el;
       T wv[5], gg[15];
       tet_load(u, E, e, pt, wv);
+      // rows of S at this point: per element from LDS, or per point (CUR)
+      T Sp[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) Sp[k] = CUR ? geo[((int64_t)pt * 10 + k) * E + e] : SJ[k * NE + el];
       if constexpr (NS && FCIN) {
         // the gradient kernel stored S_i . f_v (12 values) instead of the gradient, tile by
         // tile (tet_fv_index)
@@ -290,7 +298,7 @@ __global__ void __launch_bounds__(tdiv_nt<T>()) tet_div(const T* __restrict__ u,
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
           T f[5];
-          pin.dir(SJ[(3 * i) * NE + el], SJ[(3 * i + 1) * NE + el], SJ[(3 * i + 2) * NE + el], f);
+          pin.dir(Sp[3 * i], Sp[3 * i + 1], Sp[3 * i + 2], f);
 #pragma unroll
           for (int c = 0; c < 5; ++c) PAN[((i * TET_NSP + pt) * 5 + c) * NE + el] = c == 0 ? f[0] : f[c] - fvs[4 * i + c - 1];
         }
@@ -305,14 +313,14 @@ __global__ void __launch_bounds__(tdiv_nt<T>()) tet_div(const T* __restrict__ u,
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
           T f[5];
-          pf.dir(SJ[(3 * i) * NE + el], SJ[(3 * i + 1) * NE + el], SJ[(3 * i + 2) * NE + el], f);
+          pf.dir(Sp[3 * i], Sp[3 * i + 1], Sp[3 * i + 2], f);
 #pragma unroll
           for (int c = 0; c < 5; ++c) PAN[((i * TET_NSP + pt) * 5 + c) * NE + el] = f[c];
         }
       } else {
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-          const T sx = SJ[(3 * i) * NE + el], sy = SJ[(3 * i + 1) * NE + el], sz = SJ[(3 * i + 2) * NE + el];
+          const T sx = Sp[3 * i], sy = Sp[3 * i + 1], sz = Sp[3 * i + 2];
           T f[5], vs, prs;
           Flux<T, DEV>::eval(wv, sx, sy, sz, gm1, R, f, vs, prs);
 #pragma unroll
@@ -366,8 +374,9 @@ __global__ void __launch_bounds__(tdiv_nt<T>()) tet_div(const T* __restrict__ u,
       for (int it = t; it < NE * TET_NFP; it += NT) {
         const int el = it % NE, sg = it / NE;
         T S[9], F[5];
+        const int so = CUR ? O.src[sg] : 0;
 #pragma unroll
-        for (int k = 0; k < 9; ++k) S[k] = SJ[k * NE + el];
+        for (int k = 0; k < 9; ++k) S[k] = CUR ? geo[((int64_t)so * 10 + k) * E + e0 + el] : SJ[k * NE + el];
         tet_common_flux<T, DEV, NS>(u, grad, S, C, O, E, e0 + el, sg, gamma, mu, pr, beta, tau, riemann, side_mode,
                                     R, F);
 #pragma unroll
@@ -378,12 +387,13 @@ __global__ void __launch_bounds__(tdiv_nt<T>()) tet_div(const T* __restrict__ u,
     if (w >= 3) return;
     tet_contract<T, BF3, 1, NE>(acc, PAN, KB, lane, opT, BF3 ? TET_KA16 : TET_KA, TET_MP, mt, opH, opL, TET_KP16);
     const int64_t e = e0 + col;
-    const T iJ = -rcp(SJ[9 * NE + col]);
+    const T iJe = CUR ? T(0) : -rcp(SJ[CUR ? 0 : 9 * NE + col]);
     if (e < n) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int pt = w * 16 + Mma16<T>::row(lane, q);
         if (pt < TET_NSP) {
+          const T iJ = CUR ? -rcp(geo[((int64_t)pt * 10 + 9) * E + e]) : iJe;
 #pragma unroll
           for (int v = 0; v < 5; ++v) r[((int64_t)pt * 5 + v) * E + e] = acc[0][v][q] * iJ;
         }
@@ -468,7 +478,7 @@ __device__ __forceinline__ void tet_grad_contract(typename Mma16<T>::V (&acc)[3]
   }
 }
 
-template <typename T, bool DEV, bool BF3, bool FC>
+template <typename T, bool DEV, bool BF3, bool FC, bool CUR = false>
 __global__ void __launch_bounds__(tgr_nt<T>()) __attribute__((amdgpu_waves_per_eu(4))) tet_grad_mma(const T* __restrict__ u, const T* __restrict__ geo, Conn C,
                                                         TetDev<T> O, const T* __restrict__ ogT,
                                                         const tet_s4* __restrict__ ogH, const tet_s4* __restrict__ ogL,
@@ -480,7 +490,8 @@ __global__ void __launch_bounds__(tgr_nt<T>()) __attribute__((amdgpu_waves_per_e
   // [k][v][el]: u at the 35 points, u^ at the 60 flux points (BF16x3: rows 35..94; else
   // face by face, tgs_row), zero rows
   __shared__ T PAN[KR * 5 * NE];
-  __shared__ T SJ[10 * NE];
+  static_assert(!(CUR && FC), "curved elements take the two-sided common flux");
+  __shared__ T SJ[CUR ? 1 : 10 * NE];
   // FC: per (face, element) the partner element and connectivity word and the unit
   // normal from the left to the right side; per formed (flux point, element) the
   // solution point of the partner's collocated value; per face the formed elements in
@@ -498,7 +509,8 @@ __global__ void __launch_bounds__(tgr_nt<T>()) __attribute__((amdgpu_waves_per_e
   const int w = t / 64, lane = t % 64, col = lane % 16;
   const int64_t e0 = xcd_block() * NE;
   {
-    for (int i = t; i < 10 * NE; i += NT) SJ[i] = geo[(int64_t)(i / NE) * E + e0 + i % NE];
+    if constexpr (!CUR)
+      for (int i = t; i < 10 * NE; i += NT) SJ[i] = geo[(int64_t)(i / NE) * E + e0 + i % NE];
     if constexpr (BF3) {
       for (int i = t; i < 5 * NE; i += NT) PAN[(TGR_K - 1) * 5 * NE + i] = T(0);
     } else {
@@ -708,14 +720,21 @@ __global__ void __launch_bounds__(tgr_nt<T>()) __attribute__((amdgpu_waves_per_e
       if constexpr (FC) __syncthreads();           // (1) every wave's products are done
       const int64_t e = e0 + col;
       if (e < n) {
-        T S[9];
+        T S[9], iJ = T(0);
+        if constexpr (!CUR) {
 #pragma unroll
-        for (int k = 0; k < 9; ++k) S[k] = SJ[k * NE + col];
-        const T iJ = rcp(SJ[9 * NE + col]);
+          for (int k = 0; k < 9; ++k) S[k] = SJ[k * NE + col];
+          iJ = rcp(SJ[9 * NE + col]);
+        }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int pt = SLOT[w * 16 + Mma16<T>::row(lane, q)];
           if (pt < 0) continue;
+          if constexpr (CUR) {
+#pragma unroll
+            for (int k = 0; k < 9; ++k) S[k] = geo[((int64_t)pt * 10 + k) * E + e];
+            iJ = rcp(geo[((int64_t)pt * 10 + 9) * E + e]);
+          }
           T gp[15];
 #pragma unroll
           for (int v = 0; v < 5; ++v) {

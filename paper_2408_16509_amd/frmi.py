@@ -69,7 +69,7 @@ class FrKernelTime(ctypes.Structure):
 
 
 EXPORTS = [
-    "fr_default_params", "fr_setup_mesh", "fr_setup_mesh_curved", "fr_layout", "fr_sol_points", "fr_pack", "fr_unpack",
+    "fr_default_params", "fr_setup_mesh", "fr_setup_mesh_curved", "fr_setup_mesh_curved_tet", "fr_layout", "fr_sol_points", "fr_pack", "fr_unpack",
     "fr_pack64", "fr_unpack64", "fr_unpack_rhs",
     "fr_rhs", "fr_rk_step", "fr_default_adaptive_params", "fr_rk_adaptive", "fr_filter", "fr_mlp_set_weights", "fr_mlp_get_weights",
     "fr_mlp_features", "fr_mlp_collect", "fr_mlp_forward", "fr_mlp_grad", "fr_mlp_grad_static", "fr_mlp_train", "fr_check", "fr_sync",
@@ -88,6 +88,7 @@ def load():
         "fr_default_params": (None, [P(FrParams)]),
         "fr_setup_mesh": (i32, [P(FrParams), i64, vp, vp, i64, vp, vp, vp, P(vp)]),
         "fr_setup_mesh_curved": (i32, [P(FrParams), i32, i64, vp, vp, i64, vp, vp, P(vp)]),
+        "fr_setup_mesh_curved_tet": (i32, [P(FrParams), i32, i64, vp, vp, i64, vp, vp, P(vp)]),
         "fr_layout": (i32, [vp, P(FrLayout)]),
         "fr_sol_points": (i32, [vp, vp]),
         "fr_pack": (i32, [vp, vp, vp]),
@@ -158,10 +159,11 @@ def _ptr(t):
 class Context:
     """An FR context on one mesh.  `stream` defaults to torch's current stream.
 
-    A mesh with `ho_enodes` set (curved hexahedra of geometry order `mesh.geo_order`,
-    tensor-order nodes) is set up through fr_setup_mesh_curved, with the metric chosen
-    by the `hex_metric` parameter (FR_METRIC_CONSERVATIVE or FR_METRIC_CROSS); any
-    other mesh through fr_setup_mesh.  Keyword parameters are fr_params fields."""
+    A mesh with `ho_enodes` set (curved elements of geometry order `mesh.geo_order`) is
+    set up through fr_setup_mesh_curved (hexahedra, tensor-order nodes) or
+    fr_setup_mesh_curved_tet (tetrahedra), with the metric chosen by the `hex_metric`
+    parameter (FR_METRIC_CONSERVATIVE or FR_METRIC_CROSS); any other mesh through
+    fr_setup_mesh.  Keyword parameters are fr_params fields."""
 
     def __init__(self, mesh, stream=None, **params):
         import torch
@@ -177,11 +179,12 @@ class Context:
         h = ctypes.c_void_p()
         ho = getattr(mesh, "ho_enodes", None)
         if ho is not None:
-            # curved hexahedra: tensor-order nodes of geometry order mesh.geo_order
+            # curved elements of one type, nodes of geometry order mesh.geo_order
             ho = np.ascontiguousarray(ho, dtype=np.int64)
-            st = lib().fr_setup_mesh_curved(ctypes.byref(self.params), int(mesh.geo_order), xyz.shape[0],
-                                            xyz.ctypes.data, per.ctypes.data, ho.shape[0], ho.ctypes.data,
-                                            ctypes.c_void_p(stream), ctypes.byref(h))
+            setup = lib().fr_setup_mesh_curved_tet if np.all(et == 1) else lib().fr_setup_mesh_curved
+            st = setup(ctypes.byref(self.params), int(mesh.geo_order), xyz.shape[0],
+                       xyz.ctypes.data, per.ctypes.data, ho.shape[0], ho.ctypes.data,
+                       ctypes.c_void_p(stream), ctypes.byref(h))
         else:
             st = lib().fr_setup_mesh(ctypes.byref(self.params), xyz.shape[0], xyz.ctypes.data, per.ctypes.data,
                                      et.shape[0], et.ctypes.data, en.ctypes.data, ctypes.c_void_p(stream),

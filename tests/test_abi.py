@@ -127,3 +127,36 @@ def test_curved_setup_errors_before_device_work():
     assert st == 2 and "J <= 0" in msg
     h = ctypes.c_void_p()
     assert lib.fr_setup_mesh_curved(None, 2, 0, None, None, 0, None, None, ctypes.byref(h)) == 1
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libfrmi.so not built")
+def test_curved_tet_setup_errors_before_device_work():
+    from paper_2408_16509_amd import frmi, inputs
+    lib = frmi.lib()
+
+    def setup(m, q=None, **kw):
+        p = frmi.default_params(**kw)
+        h = ctypes.c_void_p()
+        xyz = np.ascontiguousarray(m.xyz)
+        per = np.ascontiguousarray(m.period, dtype=np.float64)
+        ho = np.ascontiguousarray(m.ho_enodes, dtype=np.int64)
+        st = lib.fr_setup_mesh_curved_tet(ctypes.byref(p), m.geo_order if q is None else q, xyz.shape[0],
+                                          xyz.ctypes.data, per.ctypes.data, ho.shape[0], ho.ctypes.data, None,
+                                          ctypes.byref(h))
+        return st, lib.fr_last_error(None).decode()
+
+    m = inputs.curved_tet_box((2, 2, 2), q=3)
+    st, msg = setup(m, order=3)                              # tetrahedra exist at order 4 only
+    assert st == 7 and "order 4" in msg
+    assert setup(m, q=0, order=4)[0] == 7
+    assert setup(m, q=5, order=4)[0] == 7
+    st, msg = setup(m, order=4, hex_metric=2)
+    assert st == 1 and "hex_metric" in msg
+    bad = inputs.curved_tet_box((2, 2, 2), q=2)
+    bad.ho_enodes[3, 5] = bad.xyz.shape[0]
+    assert setup(bad, order=4)[0] == 1
+    # a folded element (displacement gradient above 1): J <= 0 somewhere
+    st, msg = setup(inputs.curved_tet_box((2, 2, 2), q=2, amp=1.5), order=4)
+    assert st == 2 and "J <= 0" in msg
+    h = ctypes.c_void_p()
+    assert lib.fr_setup_mesh_curved_tet(None, 2, 0, None, None, 0, None, None, ctypes.byref(h)) == 1

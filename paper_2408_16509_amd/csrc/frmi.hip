@@ -503,7 +503,7 @@ fr_status hex_rhs_p(fr_ctx c, DevBlock& b, const T* u, T* r) {
 }
 
 // CUR: curved tetrahedra, the metric stored per solution point (b.cmet) in place of the
-// per-element terms; they take the two-sided common flux (no pair-once form).
+// per-element terms.
 template <typename T, bool DEV, bool CUR>
 fr_status tet_rhs(fr_ctx c, DevBlock& b, const T* u, T* r) {
   Conn C{b.nbr_elem, b.nbr_info, c->perm, c->host.perm_stride};
@@ -541,7 +541,7 @@ fr_status tet_rhs(fr_ctx c, DevBlock& b, const T* u, T* r) {
   } else {
     // one-sided LDG (beta = +-1/2), FP32 form: the gradient kernel also forms the common
     // fluxes (in FP64 the extra registers cost that kernel more than the divergence saves)
-    constexpr bool can_fc = sizeof(T) == 4 && !CUR;
+    constexpr bool can_fc = sizeof(T) == 4;
     const bool fc = sm != 0 && can_fc;
     T* fcb = (T*)b.fc;
     const T gam = (T)p.gamma, mu = (T)p.mu, pr = (T)p.prandtl, beta = (T)p.ldg_beta, tau = (T)p.ldg_tau;

@@ -46,6 +46,21 @@ __device__ __forceinline__ void tet_normal(const T S[9], const TetDev<T>& O, int
   for (int j = 0; j < 3; ++j) nv[j] = O.nref[f][0] * S[j] + O.nref[f][1] * S[3 + j] + O.nref[f][2] * S[6 + j];
 }
 
+// Curved elements: the unit normal of face f at a flux point, oriented from the left to
+// the right side (`left`: the element is the left side), from the metric of the
+// collocated solution point pt.
+template <typename T>
+__device__ __forceinline__ void tet_cur_unit_normal(const T* __restrict__ geo, int64_t E, int64_t e, int pt,
+                                                    const TetDev<T>& O, int f, bool left, T nL[3]) {
+  T S[9], nv[3];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) S[k] = geo[((int64_t)pt * 10 + k) * E + e];
+  tet_normal(S, O, f, nv);
+  const T sl = fdiv(left ? T(1) : T(-1), fsqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]));
+#pragma unroll
+  for (int k = 0; k < 3; ++k) nL[k] = nv[k] * sl;
+}
+
 template <typename T>
 __device__ __forceinline__ void tet_load(const T* __restrict__ u, int64_t E, int64_t e, int pt, T w[5]) {
 #pragma unroll
@@ -247,7 +262,6 @@ __global__ void __launch_bounds__(tdiv_nt<T>()) tet_div(const T* __restrict__ u,
                                                    int side_mode, RefState<T> R) {
   constexpr int NE = TDIV_NE, NT = tdiv_nt<T>();
   constexpr int KA = BF3 ? TET_KA16 : TET_KA, KB = BF3 ? TET_KB16 : TET_KB;
-  static_assert(!(CUR && FCIN), "curved elements take the two-sided common flux");
   __shared__ T PAN[KA * 5 * NE];          // [k][v][el]; the second K chunk reuses it
   __shared__ T SJ[CUR ? 1 : 10 * NE];
   const int t = threadIdx.x;
@@ -362,8 +376,9 @@ __global__ void __launch_bounds__(tdiv_nt<T>()) tet_div(const T* __restrict__ u,
         if (t + j * NT >= NE * TET_NFP) continue;
         const int el = tel, sg = tr + j * (NT / NE), face = sg / TET_NFPF;
         T S[9], nv[3];
+        const int so = CUR ? O.src[sg] : 0;
 #pragma unroll
-        for (int k = 0; k < 9; ++k) S[k] = SJ[k * NE + el];
+        for (int k = 0; k < 9; ++k) S[k] = CUR ? geo[((int64_t)so * 10 + k) * E + e0 + el] : SJ[k * NE + el];
         tet_normal(S, O, face, nv);
         const T mag = fsqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
         const T fs = lft[j] ? mag : -mag;
@@ -490,7 +505,6 @@ __global__ void __launch_bounds__(tgr_nt<T>()) __attribute__((amdgpu_waves_per_e
   // [k][v][el]: u at the 35 points, u^ at the 60 flux points (BF16x3: rows 35..94; else
   // face by face, tgs_row), zero rows
   __shared__ T PAN[KR * 5 * NE];
-  static_assert(!(CUR && FC), "curved elements take the two-sided common flux");
   __shared__ T SJ[CUR ? 1 : 10 * NE];
   // FC: per (face, element) the partner element and connectivity word and the unit
   // normal from the left to the right side; per formed (flux point, element) the
@@ -498,7 +512,7 @@ __global__ void __launch_bounds__(tgr_nt<T>()) __attribute__((amdgpu_waves_per_e
   // ascending order (FEL) and, bit 16 f + el, the block's formed mask (FMASK)
   static_assert(!FC || (NE == 16 && NT >= 4 * NE), "face tables assume 16-element tiles");
   __shared__ int32_t NBE[FC ? 4 * NE : 1], NBF[FC ? 4 * NE : 1];
-  __shared__ T NRM[FC ? 12 * NE : 1];
+  __shared__ T NRM[FC && !CUR ? 12 * NE : 1];    // straight elements: one normal per face
   __shared__ uint8_t PSRC[FC ? TET_NFP * NE : 1];
   __shared__ uint8_t FEL[FC ? 4 * NE : 1];
   __shared__ uint32_t FMASK[2];
@@ -589,13 +603,15 @@ __global__ void __launch_bounds__(tgr_nt<T>()) __attribute__((amdgpu_waves_per_e
         const int f = lane / NE, el = lane % NE;
         const bool left = (NBF[f * NE + el] >> 12) & 1;
         const bool formed = left != (side_mode > 0) && e0 + el < n;
-        T S[9], nv[3];
+        if constexpr (!CUR) {
+          T S[9], nv[3];
 #pragma unroll
-        for (int k = 0; k < 9; ++k) S[k] = SJ[k * NE + el];
-        tet_normal(S, O, f, nv);
-        const T sl = fdiv(left ? T(1) : T(-1), fsqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]));
+          for (int k = 0; k < 9; ++k) S[k] = SJ[k * NE + el];
+          tet_normal(S, O, f, nv);
+          const T sl = fdiv(left ? T(1) : T(-1), fsqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]));
 #pragma unroll
-        for (int k = 0; k < 3; ++k) NRM[(f * 3 + k) * NE + el] = nv[k] * sl;
+          for (int k = 0; k < 3; ++k) NRM[(f * 3 + k) * NE + el] = nv[k] * sl;
+        }
         const uint64_t m = __ballot(formed);
         const uint32_t mf = (uint32_t)(m >> (16 * f)) & 0xffffu;
         if (formed) FEL[f * NE + __popc(mf & ((1u << el) - 1u))] = (uint8_t)el;
@@ -685,8 +701,12 @@ __global__ void __launch_bounds__(tgr_nt<T>()) __attribute__((amdgpu_waves_per_e
           uL[c] = left ? own : nb;
           uR[c] = left ? nb : own;
         }
+        if constexpr (CUR) {
+          tet_cur_unit_normal(geo, E, e0 + el, so, O, f, left, nL);
+        } else {
 #pragma unroll
-        for (int k = 0; k < 3; ++k) nL[k] = NRM[(f * 3 + k) * NE + el];
+          for (int k = 0; k < 3; ++k) nL[k] = NRM[(f * 3 + k) * NE + el];
+        }
         common_inviscid<T, DEV>(riemann, uL, uR, nL, gamma, R, F);
         fc[tet_fc_index<NE>(e0 + el, sg * 5)] = F[0] + tau * (uL[0] - uR[0]);
 #pragma unroll
@@ -767,7 +787,16 @@ __global__ void __launch_bounds__(tgr_nt<T>()) __attribute__((amdgpu_waves_per_e
               const int sg = PFP[pt * 4 + 1 + i];
               const int f = sg / TET_NFPF;
               T fv[4];
-              pf.visc(NRM[(f * 3) * NE + col], NRM[(f * 3 + 1) * NE + col], NRM[(f * 3 + 2) * NE + col], fv);
+              if constexpr (CUR) {
+                // the unit normal from this point's own metric, oriented left to right
+                T nv[3];
+                tet_normal(S, O, f, nv);
+                const bool lf = (NBF[f * NE + col] >> 12) & 1;
+                const T sl = fdiv(lf ? T(1) : T(-1), fsqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]));
+                pf.visc(nv[0] * sl, nv[1] * sl, nv[2] * sl, fv);
+              } else {
+                pf.visc(NRM[(f * 3) * NE + col], NRM[(f * 3 + 1) * NE + col], NRM[(f * 3 + 2) * NE + col], fv);
+              }
 #pragma unroll
               for (int c = 0; c < 4; ++c) PAN[FVB + (sg * 4 + c) * NE + col] = fv[c];
             }
@@ -792,8 +821,12 @@ __global__ void __launch_bounds__(tgr_nt<T>()) __attribute__((amdgpu_waves_per_e
           uL[c] = left ? own : nb;
           uR[c] = left ? nb : own;
         }
+        if constexpr (CUR) {
+          tet_cur_unit_normal(geo, E, e0 + el, so, O, f, left, nL);
+        } else {
 #pragma unroll
-        for (int k = 0; k < 3; ++k) nL[k] = NRM[(f * 3 + k) * NE + el];
+          for (int k = 0; k < 3; ++k) nL[k] = NRM[(f * 3 + k) * NE + el];
+        }
         common_inviscid<T, DEV>(riemann, uL, uR, nL, gamma, R, F);
         fc[tet_fc_index<NE>(e0 + el, sg * 5)] = F[0] + tau * (uL[0] - uR[0]);
 #pragma unroll

@@ -236,3 +236,60 @@ def test_curved_tet_full_size_free_stream():
     print(f"196,608 curved tets, uniform stream, max |R|: {res}", flush=True)
     assert res["conservative"] <= 1e-10 and res["conservative_fp32"] <= 2e-3
     assert res["cross"] > 1e-8 and res["cross"] > 1e3 * res["conservative"]
+
+
+def test_curved_tet_filtered_rk_step():
+    """One RK4 step of the Mach-3 shock on curved tetrahedra (q = 2) with the plain entropy
+    filter on every stage state and the new state (the filter uses no metric terms; its
+    stage states come from the curved right-hand side), against the oracle: FP64 within
+    1e-10 of the increment, and the filter treats elements in the step."""
+    from oracle import entropy_filter as ef
+    from paper_2408_16509_amd import frmi
+    m = inputs.curved_tet_box((3, 3, 3), q=2, amp=0.15, permute_seed=7)
+    bl = omesh.build(m, 4)
+    x = bl[0].xsol
+    ic = np.moveaxis(inputs.shock(x[..., 0], x[..., 1], x[..., 2]), 0, 1).copy()
+    fp = ef.FilterParams()
+    u0 = ef.entropy_filter(bl, [ic], [ic], fp)[0][0]
+    smin0 = ef.smin_neighbourhood(bl, [u0], fp)
+    treated = []
+
+    def post(s):
+        out = [ef.filter_block(bb, ss, sm, fp) for bb, ss, sm in zip(bl, s, smin0)]
+        treated.append(sum(int((r[1] != 0).sum()) for r in out))
+        return [r[0] for r in out]
+    uo = ork.rk4_step(lambda s: ofr.rhs(bl, s, ofr.Params(riemann=1)), [u0], 5e-3, stage_post=post)[0]
+    assert sum(treated) > 0
+    ctx = frmi.Context(m, system=0, order=4, riemann=1)
+    ug = ctx.pack64(u0.ravel())
+    ctx.rk_step(ug, 5e-3, 1, filter_mode=0)
+    got = ctx.unpack64(ug).cpu().numpy().reshape(uo.shape)
+    ok = ctx.check(ug)
+    ctx.close()
+    err = np.linalg.norm(got - uo) / np.linalg.norm(uo - u0)
+    print(f"filtered RK4 step on curved tets: {err:.2e} of the increment", flush=True)
+    assert err <= 1e-10 and ok
+    assert ef.admissible(bl[0], got, smin0[0], fp)[0].all()
+
+
+def test_curved_tet_adaptive_fp64():
+    """Adaptive stepping (embedded pair and controller) on curved tetrahedra: the oracle's
+    sequence of accepted and rejected steps, its final time and state."""
+    from oracle import rk_adaptive as ra
+    from paper_2408_16509_amd import frmi
+    m = _mesh(3)
+    bl = omesh.build(m, 4)
+    x = bl[0].xsol
+    u = np.moveaxis(inputs.tgv(x[..., 0], x[..., 1], x[..., 2], mach=0.3), 0, 1).copy()
+    uo, so = ra.integrate(lambda s: ofr.rhs(bl, s, ofr.Params()), [u], 0.1, 0.05, ra.Controller(atol=1e-6, rtol=1e-6))
+    ctx = frmi.Context(m, system=0, order=4)
+    ug = ctx.pack64(u.ravel())
+    sg = ctx.rk_adaptive(ug, 0.1, 0.05, atol=1e-6, rtol=1e-6)
+    got = ctx.unpack64(ug).cpu().numpy().reshape(u.shape)
+    ctx.close()
+    err = np.linalg.norm(got - uo[0]) / np.linalg.norm(uo[0] - u)
+    print(f"curved tets adaptive: accepted {sg.accepted} (oracle {so.accepted}), rejected {sg.rejected} "
+          f"(oracle {so.rejected}), state {err:.2e}", flush=True)
+    assert (sg.accepted, sg.rejected) == (so.accepted, so.rejected) and sg.t == so.t == 0.1
+    assert abs(sg.dt_next - so.dt_next) <= 1e-9 * so.dt_next
+    assert err <= 1e-10

@@ -1927,9 +1927,10 @@ fr_status fr_mlp_grad(fr_ctx c, const float* x, const float* y, int64_t n, float
   if (!c->mlp_ready) return fail(c, FR_ERR_STATE, "MLP weights not set");
   fr_status st;
   if ((st = mlp_alloc(c, (int)n))) return st;
-  mlp_fwd_bwd<<<(unsigned)((n + 255) / 256), 256, 0, c->stream>>>(c->m_w, c->m_scale, x, y, nullptr, (int)n,
-                                                                   c->m_scratch, c->m_sqerr);
-  mlp_grad_reduce<<<(MLP_NP + 1 + 255) / 256, 256, 0, c->stream>>>(c->m_scratch, (int)n, c->m_sqerr, grad, loss);
+  mlp_fwd_bwd<<<(unsigned)((n + MLP_FB_WAVES - 1) / MLP_FB_WAVES), 64 * MLP_FB_WAVES, 0, c->stream>>>(
+      c->m_w, c->m_scale, x, y, nullptr, (int)n, c->m_scratch, c->m_sqerr);
+  mlp_grad_reduce<<<(MLP_NP + 1 + MLP_GR_NT - 1) / MLP_GR_NT, MLP_GR_NT, 0, c->stream>>>(c->m_scratch, (int)n,
+                                                                                        c->m_sqerr, grad, loss);
   HIP_TRY(c, hipGetLastError());
   return FR_OK;
 }
@@ -1942,8 +1943,10 @@ fr_status fr_mlp_grad_static(fr_ctx c, const float* x, const float* y, int64_t n
   if (!c->static_scratch) return fail(c, FR_ERR_DEVICE, "address of the static scratch array not available");
   float* S = c->static_scratch;
   float* sq = S + (int64_t)FR_MLP_STATIC_MAX_BATCH * MLP_SS;
-  mlp_fwd_bwd<<<(unsigned)((n + 255) / 256), 256, 0, c->stream>>>(c->m_w, c->m_scale, x, y, nullptr, (int)n, S, sq);
-  mlp_grad_reduce<<<(MLP_NP + 1 + 255) / 256, 256, 0, c->stream>>>(S, (int)n, sq, grad, loss);
+  mlp_fwd_bwd<<<(unsigned)((n + MLP_FB_WAVES - 1) / MLP_FB_WAVES), 64 * MLP_FB_WAVES, 0, c->stream>>>(
+      c->m_w, c->m_scale, x, y, nullptr, (int)n, S, sq);
+  mlp_grad_reduce<<<(MLP_NP + 1 + MLP_GR_NT - 1) / MLP_GR_NT, MLP_GR_NT, 0, c->stream>>>(S, (int)n, sq, grad,
+                                                                                        loss);
   HIP_TRY(c, hipGetLastError());
   return FR_OK;
 }
@@ -1958,11 +1961,10 @@ fr_status fr_mlp_train(fr_ctx c, const float* x, const float* y, int64_t n, cons
   HIP_TRY(c, hipMemsetAsync(c->m_m, 0, MLP_NP * sizeof(float), c->stream));
   HIP_TRY(c, hipMemsetAsync(c->m_v, 0, MLP_NP * sizeof(float), c->stream));
   for (int t = 1; t <= n_steps; ++t) {
-    mlp_fwd_bwd<<<(unsigned)((batch + 255) / 256), 256, 0, c->stream>>>(c->m_w, c->m_scale, x, y,
-                                                                         perm + (int64_t)(t - 1) * batch, batch,
-                                                                         c->m_scratch, c->m_sqerr);
-    mlp_grad_reduce<<<(MLP_NP + 1 + 255) / 256, 256, 0, c->stream>>>(c->m_scratch, batch, c->m_sqerr, c->m_g,
-                                                                      loss_hist ? loss_hist + (t - 1) : c->m_loss);
+    mlp_fwd_bwd<<<(unsigned)((batch + MLP_FB_WAVES - 1) / MLP_FB_WAVES), 64 * MLP_FB_WAVES, 0, c->stream>>>(
+        c->m_w, c->m_scale, x, y, perm + (int64_t)(t - 1) * batch, batch, c->m_scratch, c->m_sqerr);
+    mlp_grad_reduce<<<(MLP_NP + 1 + MLP_GR_NT - 1) / MLP_GR_NT, MLP_GR_NT, 0, c->stream>>>(
+        c->m_scratch, batch, c->m_sqerr, c->m_g, loss_hist ? loss_hist + (t - 1) : c->m_loss);
     mlp_adam<<<(MLP_NP + 255) / 256, 256, 0, c->stream>>>(c->m_w, c->m_g, c->m_m, c->m_v, t, lr, b1, b2, eps);
   }
   HIP_TRY(c, hipGetLastError());

@@ -8,6 +8,7 @@ module raises if the built library is missing.
 from __future__ import annotations
 
 import ctypes
+import functools
 import os
 
 import numpy as np
@@ -156,8 +157,21 @@ def _ptr(t):
     return ctypes.c_void_p(0 if t is None else t.data_ptr())
 
 
+def _on_ctx_stream(fn):
+    """Run a method's torch work (allocations, host-to-device copies) on the context's stream,
+    so buffers the binding creates are ordered with the library calls that consume them."""
+    @functools.wraps(fn)
+    def wrapped(self, *a, **kw):
+        with self._torch.cuda.stream(self._tstream):
+            return fn(self, *a, **kw)
+    return wrapped
+
+
 class Context:
-    """An FR context on one mesh.  `stream` defaults to torch's current stream.
+    """An FR context on one mesh.  `stream` defaults to torch's current stream.  Buffers the
+    binding creates (packed states, outputs) are made on the context's stream; tensors the
+    caller passes in must be ready on that stream, and results read on another stream need
+    that stream to wait for this one, as for any stream-ordered library.
 
     A mesh with `ho_enodes` set (curved elements of geometry order `mesh.geo_order`) is
     set up through fr_setup_mesh_curved (hexahedra, tensor-order nodes) or
@@ -173,8 +187,11 @@ class Context:
         per = np.ascontiguousarray(mesh.period, dtype=np.float64)
         et = np.ascontiguousarray(mesh.etype, dtype=np.int32)
         en = np.ascontiguousarray(mesh.enodes, dtype=np.int64)
-        if stream is None:
-            stream = torch.cuda.current_stream().cuda_stream
+        cur = torch.cuda.current_stream()
+        if stream is None or stream == cur.cuda_stream:
+            stream, self._tstream = cur.cuda_stream, cur
+        else:
+            self._tstream = torch.cuda.ExternalStream(stream)
         self.stream = stream
         h = ctypes.c_void_p()
         ho = getattr(mesh, "ho_enodes", None)
@@ -205,9 +222,11 @@ class Context:
     def native_dtype(self):
         return self._torch.float64 if self.layout.native_dtype == FR_FP64 else self._torch.float32
 
+    @_on_ctx_stream
     def new_native(self, dtype=None):
         return self._torch.zeros(self.layout.native_len, dtype=dtype or self.native_dtype, device="cuda")
 
+    @_on_ctx_stream
     def new_native64(self):
         return self._torch.zeros(self.layout.native_len, dtype=self._torch.float64, device="cuda")
 
@@ -217,6 +236,7 @@ class Context:
         self._check(lib().fr_sol_points(self.h, out.ctypes.data))
         return out
 
+    @_on_ctx_stream
     def pack(self, canon, out=None):
         torch = self._torch
         c = torch.as_tensor(canon, dtype=torch.float64, device="cuda").contiguous()
@@ -225,6 +245,7 @@ class Context:
         self._check(lib().fr_pack(self.h, _ptr(c), _ptr(out)))
         return out
 
+    @_on_ctx_stream
     def unpack(self, native, out=None):
         torch = self._torch
         if out is None:
@@ -232,6 +253,7 @@ class Context:
         self._check(lib().fr_unpack(self.h, _ptr(native), _ptr(out)))
         return out
 
+    @_on_ctx_stream
     def pack64(self, canon, out=None):
         """Canonical FP64 -> FP64 native state (what rk_step / filter / check use)."""
         torch = self._torch
@@ -241,6 +263,7 @@ class Context:
         self._check(lib().fr_pack64(self.h, _ptr(c), _ptr(out)))
         return out
 
+    @_on_ctx_stream
     def unpack64(self, native, out=None):
         torch = self._torch
         if out is None:
@@ -248,6 +271,7 @@ class Context:
         self._check(lib().fr_unpack64(self.h, _ptr(native), _ptr(out)))
         return out
 
+    @_on_ctx_stream
     def unpack_rhs(self, r, out=None):
         """Native right-hand side -> canonical FP64 (no reference state added)."""
         torch = self._torch
@@ -263,6 +287,7 @@ class Context:
     def rk_step(self, u, dt, n_steps=1, filter_mode=-1):
         self._check(lib().fr_rk_step(self.h, _ptr(u), float(dt), int(n_steps), int(filter_mode)))
 
+    @_on_ctx_stream
     def rk_adaptive(self, u, t_end, dt0, **params):
         """Adaptive steps of the embedded pair from t = 0 to t_end (FP64 native state u, in
         place); params override fr_default_adaptive_params (atol, rtol, safety, fac_min,
@@ -276,6 +301,7 @@ class Context:
                                           ctypes.byref(st)))
         return st
 
+    @_on_ctx_stream
     def filter(self, u, u_prev=None, mode=0, k=None, stats=False):
         s = FrFilterStats() if stats else None
         self._check(lib().fr_filter(self.h, _ptr(u), _ptr(u if u_prev is None else u_prev), int(mode),
@@ -294,6 +320,7 @@ class Context:
         self._check(lib().fr_mlp_get_weights(self.h, w.ctypes.data))
         return w
 
+    @_on_ctx_stream
     def mlp_features(self, u, u_prev, cap):
         torch = self._torch
         x = torch.zeros((max(cap, 1), 16), dtype=torch.float32, device="cuda")
@@ -305,6 +332,7 @@ class Context:
         m = min(n.value, cap)
         return x[:m], el[:m], k[:m], n.value
 
+    @_on_ctx_stream
     def mlp_collect(self, u, dt, n_steps, cap):
         torch = self._torch
         x = torch.zeros((max(cap, 1), 16), dtype=torch.float32, device="cuda")
@@ -314,12 +342,14 @@ class Context:
                                          ctypes.byref(n)))
         return x[:n.value], k[:n.value]
 
+    @_on_ctx_stream
     def mlp_forward(self, x):
         torch = self._torch
         y = torch.empty(x.shape[0], dtype=torch.float32, device="cuda")
         self._check(lib().fr_mlp_forward(self.h, _ptr(x), int(x.shape[0]), _ptr(y)))
         return y
 
+    @_on_ctx_stream
     def mlp_grad(self, x, y):
         torch = self._torch
         g = torch.empty(5313, dtype=torch.float32, device="cuda")
@@ -332,6 +362,7 @@ class Context:
         self._check(lib().fr_mlp_grad_static(self.h, _ptr(x), _ptr(y), int(x.shape[0]), _ptr(grad), _ptr(loss)))
         return grad, loss
 
+    @_on_ctx_stream
     def mlp_train(self, x, y, perm, n_steps, batch, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
         torch = self._torch
         hist = torch.empty(max(n_steps, 1), dtype=torch.float32, device="cuda")

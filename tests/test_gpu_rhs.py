@@ -236,3 +236,25 @@ def _blocks_of(ctx):
         res.append((o, m, s))
         o += m * s
     return res
+
+
+def test_context_on_a_side_stream():
+    """A context on a stream other than torch's current one: the binding's own buffers
+    (the packed state, the unpacked result) are made on the context's stream, so two RK4
+    steps there give the bits they give on the current stream."""
+    from paper_2408_16509_amd import frmi
+    mesh = inputs.hex_box((16, 16, 16), perturb=0.1, perturb_seed=3)
+    bl = oracle_blocks(mesh, 3)
+    canon = state_for(bl, "tgv")[0].ravel()
+    out = []
+    for side in (False, True):
+        s = torch.cuda.Stream() if side else None
+        ctx = frmi.Context(mesh, stream=None if s is None else s.cuda_stream, system=1, order=3)
+        u = ctx.pack64(canon)
+        ctx.rk_step(u, 1e-3, 2)
+        got = ctx.unpack64(u)
+        torch.cuda.synchronize()
+        out.append(got.cpu().numpy())
+        ctx.close()
+    print(f"side stream vs current stream: max |diff| {np.abs(out[0] - out[1]).max():.1e}", flush=True)
+    assert np.array_equal(out[0], out[1])

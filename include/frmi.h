@@ -8,7 +8,8 @@
  * equations on periodic meshes of hexahedra (orders 1..4, Gauss--Legendre
  * points; straight, with metric terms formed from the corners, or curved, with
  * metric terms stored per point as in Sec. "Curved elements") and tetrahedra
- * (order 4, the alpha-optimised points of Fig. mesh), advances it with classical
+ * (order 4, the alpha-optimised points of Fig. mesh; straight, or curved with
+ * metric terms stored per solution point), advances it with classical
  * RK4 ("a suitable explicit time integration scheme") or with an adaptive
  * embedded pair (Sec. "Adaptive time stepping"), and applies the entropy-bounded
  * modal filter of Sec. "Numerical Stability" with an optional learned warm start

@@ -269,6 +269,17 @@ __global__ void __launch_bounds__(tdiv_nt<T>()) tet_div(const T* __restrict__ u,
   const int mt[1] = {w};
   const T gm1 = gamma - T(1);
   const int64_t e0 = xcd_block() * NE;
+  // S of tile element el at solution point pt: the element's (staged in LDS) or, for
+  // curved elements, the point's
+  auto metric_at = [&](int pt, int el, T S[9]) {
+    if constexpr (CUR) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) S[k] = geo[((int64_t)pt * 10 + k) * E + e0 + el];
+    } else {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) S[k] = SJ[k * NE + el];
+    }
+  };
   {
     // The connectivity of this thread's flux points (FCIN) is read before anything
     // waits, the stored common fluxes right after chunk 1 is evaluated (both ahead of
@@ -298,10 +309,8 @@ __global__ void __launch_bounds__(tdiv_nt<T>()) tet_div(const T* __restrict__ u,
       const int64_t e = e0 + el;
       T wv[5], gg[15];
       tet_load(u, E, e, pt, wv);
-      // rows of S at this point: per element from LDS, or per point (CUR)
       T Sp[9];
-#pragma unroll
-      for (int k = 0; k < 9; ++k) Sp[k] = CUR ? geo[((int64_t)pt * 10 + k) * E + e] : SJ[k * NE + el];
+      metric_at(pt, el, Sp);
       if constexpr (NS && FCIN) {
         // the gradient kernel stored S_i . f_v (12 values) instead of the gradient, tile by
         // tile (tet_fv_index)
@@ -376,9 +385,7 @@ __global__ void __launch_bounds__(tdiv_nt<T>()) tet_div(const T* __restrict__ u,
         if (t + j * NT >= NE * TET_NFP) continue;
         const int el = tel, sg = tr + j * (NT / NE), face = sg / TET_NFPF;
         T S[9], nv[3];
-        const int so = CUR ? O.src[sg] : 0;
-#pragma unroll
-        for (int k = 0; k < 9; ++k) S[k] = CUR ? geo[((int64_t)so * 10 + k) * E + e0 + el] : SJ[k * NE + el];
+        metric_at(O.src[sg], el, S);
         tet_normal(S, O, face, nv);
         const T mag = fsqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
         const T fs = lft[j] ? mag : -mag;
@@ -389,9 +396,7 @@ __global__ void __launch_bounds__(tdiv_nt<T>()) tet_div(const T* __restrict__ u,
       for (int it = t; it < NE * TET_NFP; it += NT) {
         const int el = it % NE, sg = it / NE;
         T S[9], F[5];
-        const int so = CUR ? O.src[sg] : 0;
-#pragma unroll
-        for (int k = 0; k < 9; ++k) S[k] = CUR ? geo[((int64_t)so * 10 + k) * E + e0 + el] : SJ[k * NE + el];
+        metric_at(O.src[sg], el, S);
         tet_common_flux<T, DEV, NS>(u, grad, S, C, O, E, e0 + el, sg, gamma, mu, pr, beta, tau, riemann, side_mode,
                                     R, F);
 #pragma unroll
@@ -402,13 +407,15 @@ __global__ void __launch_bounds__(tdiv_nt<T>()) tet_div(const T* __restrict__ u,
     if (w >= 3) return;
     tet_contract<T, BF3, 1, NE>(acc, PAN, KB, lane, opT, BF3 ? TET_KA16 : TET_KA, TET_MP, mt, opH, opL, TET_KP16);
     const int64_t e = e0 + col;
-    const T iJe = CUR ? T(0) : -rcp(SJ[CUR ? 0 : 9 * NE + col]);
+    T iJe = T(0);                          // -1/J of the element (straight elements)
+    if constexpr (!CUR) iJe = -rcp(SJ[9 * NE + col]);
     if (e < n) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int pt = w * 16 + Mma16<T>::row(lane, q);
         if (pt < TET_NSP) {
-          const T iJ = CUR ? -rcp(geo[((int64_t)pt * 10 + 9) * E + e]) : iJe;
+          T iJ = iJe;
+          if constexpr (CUR) iJ = -rcp(geo[((int64_t)pt * 10 + 9) * E + e]);
 #pragma unroll
           for (int v = 0; v < 5; ++v) r[((int64_t)pt * 5 + v) * E + e] = acc[0][v][q] * iJ;
         }

@@ -53,9 +53,8 @@ CONFIGS = {
                                     # rows from a small mixed-mesh Mach-3 shock (NS, p = 4, both element types)
                                     mlp_train=dict(n=(4, 8, 8), seeds=(101, 102, 103), steps=20, dt=5e-4,
                                                    iters=2000),
-                                    # oracle timing sample: the same two boxes at 10 x 10 x 10 cells each
-                                    # (about 10 s of host work for the five timed right-hand sides)
-                                    oracle_sample=(10, 10, 10)),
+                                    # oracle timing sample: the same two boxes at 12 x 12 x 12 cells each
+                                    oracle_sample=(12, 12, 12)),
     # Mach-3 shock (orientation seed 41, density noise seed 42), Euler + HLLC, entropy
     # filter on every RK stage: plain bisection vs the learned warm start, the MLP
     # trained on the plain filter's data from held-out draws (seeds 101-108 / 201-208)
@@ -68,9 +67,9 @@ CONFIGS = {
     # the NS TGV on curved tetrahedra of geometry order 4 (the order where the cross-product
     # metric's degree, 6, exceeds the solution order): 32^3 cells of the same curved lattice
     # (amplitude 0.1), 6 tetrahedra each (196,608 elements, 6.9 M points), element order
-    # seed 57, conservative metric; oracle timing sample at 10^3 cells
+    # seed 57, conservative metric; oracle timing sample at 12^3 cells
     "ns_tgv_tet32_q4_curved": dict(kind="curved_tet", n=(32, 32, 32), q=4, amp=0.1, order=4, system=1, riemann=0,
-                                   mach=0.1, dt=7.5e-5, permute_seed=57, oracle_sample=(10, 10, 10)),
+                                   mach=0.1, dt=7.5e-5, permute_seed=57, oracle_sample=(12, 12, 12)),
     "ns_tgv_hex32_p3_adaptive": dict(n=(32, 32, 32), order=3, system=1, riemann=0, mach=0.1, dt=4e-4,
                                      adaptive=True, t_end=8e-3, tol=1e-6),
     "euler_shock_hex48_p3": dict(n=(48, 48, 48), order=3, system=0, riemann=1, dt=5e-4, filter=True,

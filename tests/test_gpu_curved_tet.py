@@ -293,3 +293,19 @@ def test_curved_tet_adaptive_fp64():
     assert (sg.accepted, sg.rejected) == (so.accepted, so.rejected) and sg.t == so.t == 0.1
     assert abs(sg.dt_next - so.dt_next) <= 1e-9 * so.dt_next
     assert err <= 1e-10
+
+
+@pytest.mark.parametrize("system", [0, 1])
+def test_curved_tet_single_cell(system):
+    """The degenerate mesh: one periodic cell (6 curved tetrahedra, q = 3, each face's partner
+    in the same cell or across the cell's own periodic boundary), FP64 against the oracle."""
+    m = inputs.curved_tet_box((1, 1, 1), q=3, amp=0.1)
+    bl = omesh.build(m, 4)
+    u = _state(bl[0], "random")
+    prm = ofr.Params(system=system, riemann=1)
+    floor, pv_floor, Ro = _floor(bl, u, prm)
+    Rg = _gpu_rhs(m, u, system=system, riemann=1)
+    g, pv = rel_err([Rg], [Ro])
+    tol = max(1e-12, 4 * floor)
+    print(f"single curved cell sys={system}: rel L2 {g:.2e} (tol {tol:.1e})", flush=True)
+    assert g <= tol and np.all(pv <= np.maximum(1e-12, 4 * pv_floor))

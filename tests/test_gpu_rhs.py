@@ -258,3 +258,24 @@ def test_context_on_a_side_stream():
         ctx.close()
     print(f"side stream vs current stream: max |diff| {np.abs(out[0] - out[1]).max():.1e}", flush=True)
     assert np.array_equal(out[0], out[1])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_zero_steps_leave_the_state(precision):
+    """fr_rk_step with n_steps = 0 (a degenerate call): the state is left bit for bit, with and
+    without the filter."""
+    from paper_2408_16509_amd import frmi
+    mesh = MESHES["mixed"]()
+    bl = oracle_blocks(mesh, 4)
+    u0 = state_for(bl, "random", seed=5)
+    kw = dict(system=1, order=4)
+    if precision == "fp32":
+        kw.update(precision=frmi.FR_FP32, u_ref=(1.0, 0.0, 0.0, 0.0, 2.5))
+    ctx = _ctx(mesh, **kw)
+    for mode in (-1, 0):
+        u = ctx.pack64(ctx.join_canon(u0))
+        before = u.clone()
+        ctx.rk_step(u, 1e-3, 0, filter_mode=mode)
+        torch.cuda.synchronize()
+        assert torch.equal(u, before)
+    ctx.close()

@@ -588,7 +588,7 @@ def cpu_baseline_sample(cfg, inputs):
 
 def roofline_for(times, blocks, form):
     """Dominant kernel (most time per step) of a form: the algorithmic-minimum bytes of the
-    right-hand side (read u, write R once; SURVEY-style model M0) for the points of the
+    right-hand side (read u, write R once: the minimum M0) for the points of the
     element block it processes, per launch, against the HBM peak; the kernel's own
     compulsory bytes (this implementation's decomposition) as separate fields."""
     dtype = "f64" if form.split(":")[0] == "fp64" else "f32"

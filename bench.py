@@ -110,8 +110,9 @@ def kernel_bytes_per_elem(name, nsp, nfp):
     solution points (10 words each) where a kernel forms fluxes or gradients there,
     row d of S at the flux points (3 words each) where it forms common fluxes (the
     face kernel forms each pair's flux once, from the left side: half of them).  Curved
-    tetrahedra read S and J per solution point (10 words) instead of per element, with the
-    same decomposition as straight ones otherwise."""
+    tetrahedra read S and J per solution point (10 words) instead of per element, and the
+    stored scaled normal (3 words) at each flux point where they form a common flux, with
+    the same decomposition as straight ones otherwise."""
     fam = name.rsplit("_p", 1)[0] if "_p" in name else name
     d = 8
     if fam.endswith("_f32"):
@@ -122,7 +123,12 @@ def kernel_bytes_per_elem(name, nsp, nfp):
             words = ({"tet_div_euler": 10 * nsp, "tet_grad": 17 * nsp + 5 * nfp // 2,
                       "tet_div_ns": 22 * nsp + 5 * nfp} if d == 4 else
                      {"tet_div_euler": 10 * nsp, "tet_grad": 20 * nsp, "tet_div_ns": 25 * nsp}).get(base)
-            return None if words is None else d * (words + 10 * nsp) + 4 * 2 * 4
+            if words is None:
+                return None
+            # the stored scaled normals where common fluxes are formed: every flux point in
+            # the divergence, the formed pairs' (half) in the FP32 gradient
+            normals = 3 * nfp if base != "tet_grad" else (3 * nfp // 2 if d == 4 else 0)
+            return d * (words + 10 * nsp + normals) + 4 * 2 * 4
         plain = kernel_bytes_per_elem(base + ("_f32" if d == 4 else "") + "_p0", nsp, nfp)
         if plain is None:
             return None

@@ -988,7 +988,9 @@ std::string build_curved_hex(int q, int metric, const double* xyz, const int64_t
 // elements of a face share -- and differentiated there with the element's own nodal
 // derivative matrices, which are exact for that interpolant.  The flux points are
 // solution points, so there is no separate face evaluation.  Stored per solution point
-// pt: S (row pt*10 + 3i + j, S_ij = J dxi_i/dx_j) and J (row pt*10 + 9).
+// pt: S (row pt*10 + 3i + j, S_ij = J dxi_i/dx_j) and J (row pt*10 + 9); per flux point fp
+// the scaled normal S^T n~ of its face at its collocated point (row 10*nsp + fp*3 + j),
+// which the common fluxes use.
 std::string build_curved_tet(int q, int metric, const double* xyz, const int64_t* ho, Setup& s, int& code) {
   code = 0;
   Block* bp = nullptr;
@@ -1038,7 +1040,9 @@ std::string build_curved_tet(int q, int metric, const double* xyz, const int64_t
       for (int a = 0; a < 3; ++a) dN[((size_t)z * NQ + j) * 3 + a] = (double)g[a];
     }
   }
-  b.cmet.assign((size_t)10 * N * b.e_pad, 0.0);
+  constexpr int NF = TetOps::nfp;
+  const int rows = 10 * N + 3 * NF;
+  b.cmet.assign((size_t)rows * b.e_pad, 0.0);
   auto work = [&](int64_t lo, int64_t hi, std::string& err) {
     std::vector<double> X((size_t)NQ * 3);
     double x[N][3], G[N][3][3], V[3][N][3];
@@ -1097,6 +1101,13 @@ std::string build_curved_tet(int q, int metric, const double* xyz, const int64_t
         }
         for (int r = 0; r < 9; ++r) b.cmet[(size_t)(z * 10 + r) * b.e_pad + le] = S[r / 3][r % 3];
         b.cmet[(size_t)(z * 10 + 9) * b.e_pad + le] = J;
+        // S^T n~ at the flux points collocated with this point
+        for (int fp = 0; fp < NF; ++fp) {
+          if (T.fp_src[fp] != z) continue;
+          const double* nr = T.nref[T.fp_face[fp]];
+          for (int j = 0; j < 3; ++j)
+            b.cmet[(size_t)(10 * N + fp * 3 + j) * b.e_pad + le] = nr[0] * S[0][j] + nr[1] * S[1][j] + nr[2] * S[2][j];
+        }
         for (int c = 0; c < 3; ++c) b.sol_xyz[((size_t)b.canon_pos[le] * N + z) * 3 + c] = x[z][c];
       }
     }
@@ -1110,7 +1121,7 @@ std::string build_curved_tet(int q, int metric, const double* xyz, const int64_t
   for (auto& th : pool) th.join();
   for (auto& m : errs)
     if (!m.empty()) { code = 2; return m; }
-  for (int r = 0; r < 10 * N; ++r)
+  for (int r = 0; r < rows; ++r)
     for (int64_t le = b.n; le < b.e_pad; ++le) b.cmet[(size_t)r * b.e_pad + le] = b.cmet[(size_t)r * b.e_pad];
   return "";
 }

@@ -57,7 +57,8 @@ struct Block {
   // values.  Hexahedra: S row d at solution point pt (row pt*9 + d*3 + j, S = J G^{-1}),
   // 1/J at solution point pt (row 9 nsp + pt), and at flux point fp of face 2d+s row d
   // of S (row 10 nsp + fp*3 + j).  Tetrahedra (flux points are solution points): S at
-  // solution point pt (row pt*10 + 3i + j) and J (row pt*10 + 9).
+  // solution point pt (row pt*10 + 3i + j) and J (row pt*10 + 9), then the scaled normal
+  // S^T n~ at flux point fp (row 10 nsp + fp*3 + j).
   std::vector<double> cmet;
 };
 

@@ -8,7 +8,8 @@
 // and the LDG corrected reference gradient is gt_i = Dh_i u + L diag(n~_i) u^.
 // Affine elements: S = J G^{-1} and J are constant per element (geo[10][E]).  Curved
 // elements (CUR, Sec. "Curved elements"): S and J stored per solution point
-// (geo[pt * 10 + k][E]); a flux point takes the metric of its collocated solution point.
+// (geo[pt * 10 + k][E]), and at each flux point the scaled normal S^T n~ of its face at
+// the collocated solution point (geo[350 + fp * 3 + j][E]).
 //
 // Kernels: the gradient and the divergence, each one dense contraction per block of
 // 16 elements on the matrix cores, with the panel ([u; u^], or the transformed and
@@ -46,16 +47,20 @@ __device__ __forceinline__ void tet_normal(const T S[9], const TetDev<T>& O, int
   for (int j = 0; j < 3; ++j) nv[j] = O.nref[f][0] * S[j] + O.nref[f][1] * S[3 + j] + O.nref[f][2] * S[6 + j];
 }
 
-// Curved elements: the unit normal of face f at a flux point, oriented from the left to
-// the right side (`left`: the element is the left side), from the metric of the
-// collocated solution point pt.
+// Curved elements: the stored scaled normal S^T n~ at flux point sg.
 template <typename T>
-__device__ __forceinline__ void tet_cur_unit_normal(const T* __restrict__ geo, int64_t E, int64_t e, int pt,
-                                                    const TetDev<T>& O, int f, bool left, T nL[3]) {
-  T S[9], nv[3];
+__device__ __forceinline__ void tet_cur_normal(const T* __restrict__ geo, int64_t E, int64_t e, int sg, T nv[3]) {
 #pragma unroll
-  for (int k = 0; k < 9; ++k) S[k] = geo[((int64_t)pt * 10 + k) * E + e];
-  tet_normal(S, O, f, nv);
+  for (int j = 0; j < 3; ++j) nv[j] = geo[((int64_t)10 * TET_NSP + sg * 3 + j) * E + e];
+}
+
+// ... and the unit normal there, oriented from the left to the right side (`left`: the
+// element is the left side).
+template <typename T>
+__device__ __forceinline__ void tet_cur_unit_normal(const T* __restrict__ geo, int64_t E, int64_t e, int sg,
+                                                    bool left, T nL[3]) {
+  T nv[3];
+  tet_cur_normal(geo, E, e, sg, nv);
   const T sl = fdiv(left ? T(1) : T(-1), fsqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]));
 #pragma unroll
   for (int k = 0; k < 3; ++k) nL[k] = nv[k] * sl;
@@ -69,21 +74,21 @@ __device__ __forceinline__ void tet_load(const T* __restrict__ u, int64_t E, int
 
 // ---------------------------------------------------------------------------
 // Common normal flux at flux point sg of element e (eq:comm_flux, with the LDG viscous
-// part for Navier--Stokes), times +-|S^T n~| (the sign of the element's side).  Both
+// part for Navier--Stokes), times +-|S^T n~| (the sign of the element's side; nv is the
+// element's scaled normal S^T n~ there).  Both
 // sides' states are collocated solution-point values; with a one-sided switch only
 // the contributing side's gradient is read.
 template <typename T, bool DEV, bool NS>
-__device__ __forceinline__ void tet_common_flux(const T* __restrict__ u, const T* __restrict__ grad, const T S[9],
+__device__ __forceinline__ void tet_common_flux(const T* __restrict__ u, const T* __restrict__ grad, const T nv[3],
                                                 const Conn& C, const TetDev<T>& O, int64_t E, int64_t e, int sg,
                                                 T gamma, T mu, T pr, T beta, T tau, int riemann, int side_mode,
                                                 const RefState<T>& R, T out[5]) {
   const int face = sg / TET_NFPF, q = sg % TET_NFPF;
   const NbrSlot ns = nbr_slot<TET_NFPF>(C, E, e, face, q);
   const int so = O.src[sg], sn = O.src[ns.fp];
-  T own[5], un[5], nv[3], nL[3], uL[5], uR[5];
+  T own[5], un[5], nL[3], uL[5], uR[5];
   tet_load(u, E, e, so, own);
   tet_load(u, E, ns.elem, sn, un);
-  tet_normal(S, O, face, nv);
   const T mag = fsqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
   const T sl = fdiv(ns.left ? T(1) : T(-1), mag);
 #pragma unroll
@@ -280,6 +285,16 @@ __global__ void __launch_bounds__(tdiv_nt<T>()) tet_div(const T* __restrict__ u,
       for (int k = 0; k < 9; ++k) S[k] = SJ[k * NE + el];
     }
   };
+  // the scaled normal S^T n~ at flux point sg: formed from the element's S, or stored (CUR)
+  auto normal_at = [&](int sg, int el, T nv[3]) {
+    if constexpr (CUR) {
+      tet_cur_normal(geo, E, e0 + el, sg, nv);
+    } else {
+      T S[9];
+      metric_at(0, el, S);
+      tet_normal(S, O, sg / TET_NFPF, nv);
+    }
+  };
   {
     // The connectivity of this thread's flux points (FCIN) is read before anything
     // waits, the stored common fluxes right after chunk 1 is evaluated (both ahead of
@@ -383,10 +398,9 @@ __global__ void __launch_bounds__(tdiv_nt<T>()) tet_div(const T* __restrict__ u,
 #pragma unroll
       for (int j = 0; j < NI2; ++j) {
         if (t + j * NT >= NE * TET_NFP) continue;
-        const int el = tel, sg = tr + j * (NT / NE), face = sg / TET_NFPF;
-        T S[9], nv[3];
-        metric_at(O.src[sg], el, S);
-        tet_normal(S, O, face, nv);
+        const int el = tel, sg = tr + j * (NT / NE);
+        T nv[3];
+        normal_at(sg, el, nv);
         const T mag = fsqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
         const T fs = lft[j] ? mag : -mag;
 #pragma unroll
@@ -395,9 +409,9 @@ __global__ void __launch_bounds__(tdiv_nt<T>()) tet_div(const T* __restrict__ u,
     } else {
       for (int it = t; it < NE * TET_NFP; it += NT) {
         const int el = it % NE, sg = it / NE;
-        T S[9], F[5];
-        metric_at(O.src[sg], el, S);
-        tet_common_flux<T, DEV, NS>(u, grad, S, C, O, E, e0 + el, sg, gamma, mu, pr, beta, tau, riemann, side_mode,
+        T nv[3], F[5];
+        normal_at(sg, el, nv);
+        tet_common_flux<T, DEV, NS>(u, grad, nv, C, O, E, e0 + el, sg, gamma, mu, pr, beta, tau, riemann, side_mode,
                                     R, F);
 #pragma unroll
         for (int c = 0; c < 5; ++c) PAN[(sg * 5 + c) * NE + el] = F[c];
@@ -709,7 +723,7 @@ __global__ void __launch_bounds__(tgr_nt<T>()) __attribute__((amdgpu_waves_per_e
           uR[c] = left ? nb : own;
         }
         if constexpr (CUR) {
-          tet_cur_unit_normal(geo, E, e0 + el, so, O, f, left, nL);
+          tet_cur_unit_normal(geo, E, e0 + el, sg, left, nL);
         } else {
 #pragma unroll
           for (int k = 0; k < 3; ++k) nL[k] = NRM[(f * 3 + k) * NE + el];
@@ -829,7 +843,7 @@ __global__ void __launch_bounds__(tgr_nt<T>()) __attribute__((amdgpu_waves_per_e
           uR[c] = left ? nb : own;
         }
         if constexpr (CUR) {
-          tet_cur_unit_normal(geo, E, e0 + el, so, O, f, left, nL);
+          tet_cur_unit_normal(geo, E, e0 + el, sg, left, nL);
         } else {
 #pragma unroll
           for (int k = 0; k < 3; ++k) nL[k] = NRM[(f * 3 + k) * NE + el];

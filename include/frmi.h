@@ -214,10 +214,9 @@ fr_status fr_setup_mesh_curved(const fr_params* p, int32_t geo_order, int64_t n_
  *              FR_METRIC_CROSS: S from the exact Jacobian, a polynomial of degree
  *              2(q - 1), which the solution polynomials miss for q = 4.  J is
  *              det(dx/dxi) of the exact map in both cases.
- * The metric terms are stored per solution point (9 + 1 values, read by the collocated
- * flux points too) in the kernels' arithmetic type; the right-hand side then takes the
- * two-sided common flux (the pair-once form of straight tetrahedra is not used); every
- * other call behaves as for fr_setup_mesh.  Synchronous.
+ * The metric terms are stored per solution point (9 + 1 values) and, per flux point, the
+ * scaled normal S^T n~ of its face at the collocated solution point (3 values), in the
+ * kernels' arithmetic type; every other call behaves as for fr_setup_mesh.  Synchronous.
  * Errors: FR_ERR_ARG (NULL, index out of range), FR_ERR_UNSUPPORTED (q outside 1..4,
  * order other than 4), FR_ERR_MESH (unpaired face, J <= 0 at a solution point),
  * FR_ERR_ALLOC. */

@@ -16,6 +16,7 @@ Modules
     polys      1-D Gauss--Legendre, Legendre, Lagrange and Radau (DG correction) polynomials
     tet        the paper's p=4 alpha-optimised tetrahedral points, orthonormal tet basis
     elements   dense element operator sets for hexahedra and tetrahedra
+    pyramid    the p=4 pyramid: rational space, layered points, DG lifting (affine base)
     mesh       periodic face matching, flux-point pairing, left/right sides
     geometry   Jacobians and transformed metric at arbitrary reference points
     curved     order-q hexahedral maps; conservative (curl-form) and cross-product metrics

@@ -21,7 +21,8 @@ xi_1 (Gauss--Legendre nodes increasing); tetrahedra the printed order of Fig. me
 Flux points of hexahedra: faces (xi1=-1, xi1=+1, xi2=-1, xi2=+1, xi3=-1, xi3=+1),
 each a tensor Gauss--Legendre grid of the two tangential coordinates (lower axis
 fastest).  Flux points of tetrahedra: faces in tet.FACES order, each listing the
-solution points on that face.
+solution points on that face.  Pyramids (p = 4, affine base): pyramid.py, the same
+fields with the DG lifting of the rational pyramid space.
 """
 from __future__ import annotations
 
@@ -34,6 +35,7 @@ from . import polys, tet
 
 HEX = 0
 TET = 1
+PYR = 2
 
 
 @dataclass
@@ -51,7 +53,7 @@ class ElementOps:
     n_faces: int
     face_nfp: int
     modal_V: np.ndarray     # [nsp][nmodes] orthonormal modes at solution points
-    modal_deg: np.ndarray   # hex: [nmodes][3] per-axis degrees; tet: [nmodes] total degree
+    modal_deg: np.ndarray   # hex: [nmodes][3] per-axis degrees; tet, pyramid: [nmodes] degree
 
     @property
     def nsp(self):
@@ -76,6 +78,11 @@ def shape_funcs(etype, xi):
                       [-1, -1, 1], [1, -1, 1], [1, 1, 1], [-1, 1, 1]], dtype=np.float64)
         return np.prod(1.0 + xi[:, None, :] * c[None, :, :], axis=2) / 8.0
     x, y, z = xi[:, 0], xi[:, 1], xi[:, 2]
+    if etype == PYR:
+        # affine map of a pyramid with a parallelogram base (corner 2 = 1 + 3 - 0):
+        # u, v, w = (x+1)/2, (y+1)/2, (z+1)/2 and x = X0 + u e1 + v e3 + w (X4 - centre of base)
+        u, v, w = (1 + x) / 2, (1 + y) / 2, (1 + z) / 2
+        return np.stack([1 - u - v, u - w / 2, np.zeros_like(u), v - w / 2, w], axis=1)
     return np.stack([-(1 + x + y + z) / 2, (1 + x) / 2, (1 + z) / 2, (1 + y) / 2], axis=1)
 
 
@@ -91,6 +98,9 @@ def shape_grads(etype, xi):
         g[..., 1] = c[None, :, 1] * f[..., 0] * f[..., 2] / 8
         g[..., 2] = c[None, :, 2] * f[..., 0] * f[..., 1] / 8
         return g
+    if etype == PYR:
+        g = np.array([[-0.5, -0.5, 0], [0.5, 0, -0.25], [0, 0, 0], [0, 0.5, -0.25], [0, 0, 0.5]])
+        return np.broadcast_to(g, (xi.shape[0], 5, 3)).copy()
     g = np.array([[-0.5, -0.5, -0.5], [0.5, 0, 0], [0, 0, 0.5], [0, 0.5, 0]])
     return np.broadcast_to(g, (xi.shape[0], 4, 3)).copy()
 
@@ -233,4 +243,7 @@ def tet_ops(p: int = 4) -> ElementOps:
 
 
 def ops_for(etype: int, p: int) -> ElementOps:
+    if etype == PYR:
+        from .pyramid import pyr_ops
+        return pyr_ops(p)
     return hex_ops(p) if etype == HEX else tet_ops(p)

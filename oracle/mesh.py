@@ -20,10 +20,12 @@ from dataclasses import dataclass
 import numpy as np
 
 from . import curved, geometry
-from .elements import HEX, TET, ops_for
+from .elements import HEX, PYR, TET, ops_for
 
 HEX_FACE_CORNERS = [(0, 3, 4, 7), (1, 2, 5, 6), (0, 1, 4, 5), (2, 3, 6, 7), (0, 1, 2, 3), (4, 5, 6, 7)]
 TET_FACE_CORNERS = [(0, 1, 3), (0, 1, 2), (0, 2, 3), (1, 2, 3)]
+PYR_FACE_CORNERS = [(0, 1, 2, 3), (0, 1, 4), (1, 2, 4), (2, 3, 4), (3, 0, 4)]
+N_CORNERS = {HEX: 8, TET: 4, PYR: 5}
 
 
 class MeshError(ValueError):
@@ -49,7 +51,7 @@ class TypeBlock:
 
 
 def _corners(etype):
-    return HEX_FACE_CORNERS if etype == HEX else TET_FACE_CORNERS
+    return {HEX: HEX_FACE_CORNERS, TET: TET_FACE_CORNERS, PYR: PYR_FACE_CORNERS}[etype]
 
 
 def _wrap(d, period):
@@ -73,7 +75,7 @@ def _keys(c, period, scale):
 
 
 def build(mesh, order: int, metric: str = "conservative"):
-    """Connectivity and geometry of `mesh` at polynomial order `order` (tets: 4).
+    """Connectivity and geometry of `mesh` at polynomial order `order` (tets, pyramids: 4).
 
     Curved meshes (mesh.ho_enodes set, hexahedra or tetrahedra of geometry order
     mesh.geo_order, one type per mesh): metric terms, J and solution points come from
@@ -81,7 +83,7 @@ def build(mesh, order: int, metric: str = "conservative"):
     matched, flux points paired and left/right sides chosen from the corners as for
     straight elements."""
     period = np.asarray(mesh.period, dtype=np.float64)
-    types = [t for t in (HEX, TET) if np.any(mesh.etype == t)]
+    types = [t for t in (HEX, TET, PYR) if np.any(mesh.etype == t)]
     ho = getattr(mesh, "ho_enodes", None)
     if ho is not None and len(types) != 1:
         raise MeshError("curved meshes hold one element type")
@@ -89,8 +91,14 @@ def build(mesh, order: int, metric: str = "conservative"):
     for t in types:
         elems = np.nonzero(mesh.etype == t)[0]
         ops = ops_for(t, order if t == HEX else 4)
-        nc = 8 if t == HEX else 4
+        nc = N_CORNERS[t]
         X = mesh.xyz[mesh.enodes[elems, :nc]]
+        if t == PYR:
+            if ho is not None:
+                raise MeshError("pyramids are straight-sided")
+            skew = np.linalg.norm(X[:, 2] - X[:, 1] - X[:, 3] + X[:, 0], axis=1)
+            if np.any(skew > 1e-10 * np.ptp(mesh.xyz, axis=0).max()):
+                raise MeshError("pyramid base is not a parallelogram (the map must be affine)")
         if ho is None:
             J, S = geometry.metric(t, X, ops.sol_pts)
             Jf, Sf = geometry.metric(t, X, ops.flux_pts)
@@ -118,7 +126,7 @@ def build(mesh, order: int, metric: str = "conservative"):
     scale = 1e-8 * max(span, 1e-300)
     recs = []                                   # (block, elem, face, key0, key1, key2)
     for bi, b in enumerate(blocks):
-        fc = HEX_FACE_CORNERS if b.etype == HEX else TET_FACE_CORNERS
+        fc = _corners(b.etype)
         for f, corners in enumerate(fc):
             cen = b.X[:, list(corners), :].mean(axis=1)          # [n][3]
             keys = _keys(cen, period, scale)
@@ -142,7 +150,7 @@ def build(mesh, order: int, metric: str = "conservative"):
         A, B = blocks[ba], blocks[bb]
         ia = np.nonzero(A.ops.flux_face == fa)[0]
         ib = np.nonzero(B.ops.flux_face == fb)[0]
-        if len(ia) != len(ib):
+        if len(_corners(A.etype)[fa]) != len(_corners(B.etype)[fb]):
             raise MeshError("matched faces of different kinds")
         xa = geometry.map_points(A.etype, A.X[ea], A.ops.flux_pts[ia])     # [m][q][3]
         xb = geometry.map_points(B.etype, B.X[eb], B.ops.flux_pts[ib])

@@ -16,6 +16,16 @@ Meshes
       each element described by its (q+1)^3 nodes (geometry order q).
     * ``curved_tet_box``: the same curved lattice with every cell Kuhn-split, each
       tetrahedron described by its (q+1)(q+2)(q+3)/6 lattice nodes.
+    * ``pyramid_box``: every cell cut into 6 pyramids, one per cell face, sharing an
+      apex near the cell centre (seeded apex displacement); the bases stay exact
+      parallelograms, so every pyramid is affine.
+    * ``transition_box``: a conforming hexahedron--pyramid--tetrahedron box.  Along x,
+      a slab of hexahedral cells, then a transition cell (a pyramid on the face shared
+      with the hexahedra, its apex near the cell centre, and the other five faces'
+      pyramids each cut into 2 tetrahedra), Kuhn-split cells, and a second transition
+      cell facing the periodic image of the first hexahedral column.  Every cell face
+      not covered by a pyramid is cut along the diagonal joining its lowest and highest
+      corners, the diagonal the Kuhn split uses, so all faces conform.
 
 Node orders
     Hexahedra use the VTK corner order, reference corners
@@ -23,6 +33,8 @@ Node orders
     Tetrahedra list their 4 corners in the order of the reference tetrahedron
     printed with the paper's tetrahedral point sets (Fig. mesh b,c):
     (-1,-1,-1) (1,-1,-1) (-1,-1,1) (-1,1,-1).
+    Pyramids list the 4 base corners in cyclic order, then the apex, matching the
+    reference pyramid (-1,-1,-1) (1,-1,-1) (1,1,-1) (-1,1,-1) (0,0,1).
     Curved hexahedra of geometry order q list (q+1)^3 nodes in tensor order: node
     i + (q+1)(j + (q+1)k) sits at reference point (-1 + 2i/q, -1 + 2j/q, -1 + 2k/q).
     Curved tetrahedra of geometry order q list the nodes (i, j, k), i + j + k <= q, k
@@ -45,6 +57,8 @@ import numpy as np
 
 HEX = 0
 TET = 1
+PYR = 2
+N_CORNERS = {HEX: 8, TET: 4, PYR: 5}
 
 # Reference corners of the two element types (documented above).
 HEX_REF_CORNERS = np.array(
@@ -58,8 +72,8 @@ TET_REF_CORNERS = np.array(
 class Mesh:
     """A mixed mesh: vertices, element types and corner lists (padded to 8 with -1)."""
     xyz: np.ndarray            # [n_vert][3] float64
-    etype: np.ndarray          # [n_elem] int32 (HEX or TET)
-    enodes: np.ndarray         # [n_elem][8] int64, tets use the first 4
+    etype: np.ndarray          # [n_elem] int32 (HEX, TET or PYR)
+    enodes: np.ndarray         # [n_elem][8] int64, tets use the first 4, pyramids 5
     period: np.ndarray         # [3] float64 box lengths (0 = not periodic)
     meta: dict = field(default_factory=dict)
     geo_order: int = 1         # curved meshes: geometry order q of ho_enodes
@@ -76,8 +90,7 @@ class Mesh:
         """Corner coordinates [len(idx)][n_corner][3] of elements `idx` (one type)."""
         idx = np.asarray(idx)
         t = int(self.etype[idx[0]]) if idx.size else HEX
-        nc = 8 if t == HEX else 4
-        return self.xyz[self.enodes[idx, :nc]]
+        return self.xyz[self.enodes[idx, :N_CORNERS[t]]]
 
 
 def _grid_vertices(n, lo, hi, perturb, seed):
@@ -280,6 +293,133 @@ def curved_tet_box(n=(3, 3, 3), q=2, amp=0.15, lo=(-math.pi,) * 3, hi=(math.pi,)
     etype = np.full(ho.shape[0], TET, dtype=np.int32)
     return Mesh(xyz, etype, en, L.copy(), {"n": n, "kind": "curved_tet_box", "q": q, "amp": amp},
                 geo_order=q, ho_enodes=ho)
+
+
+# VTK corner index of a cell corner from its (dx, dy, dz) offsets
+_CELL_BIT = {(0, 0, 0): 0, (1, 0, 0): 1, (1, 1, 0): 2, (0, 1, 0): 3,
+             (0, 0, 1): 4, (1, 0, 1): 5, (1, 1, 1): 6, (0, 1, 1): 7}
+# cell faces as (axis, side) with their corner offsets in cyclic order
+_CELL_FACES = []
+for _ax in range(3):
+    for _side in (0, 1):
+        _u, _v = [a for a in range(3) if a != _ax]
+        _cyc = []
+        for du, dv in ((0, 0), (1, 0), (1, 1), (0, 1)):
+            o = [0, 0, 0]
+            o[_ax], o[_u], o[_v] = _side, du, dv
+            _cyc.append(_CELL_BIT[tuple(o)])
+        _CELL_FACES.append((_ax, _side, _cyc))
+
+
+def _cell_centres(mesh_xyz, cells, h, perturb, seed):
+    """One new vertex per cell (cells [m][8] VTK corners): the centre, moved by
+    U(-perturb, perturb) * h per coordinate with PCG64(seed) in cell order."""
+    c = mesh_xyz[cells].mean(axis=1)
+    if perturb:
+        c = c + np.random.default_rng(seed).uniform(-perturb, perturb, size=c.shape) * h
+    return c
+
+
+def _orient_pyr(xyz, pn):
+    """Reorder base corners so that (X1 - X0) x (X3 - X0) points at the apex (J > 0)."""
+    c = xyz[pn]
+    vol = np.einsum("ni,ni->n", np.cross(c[:, 1] - c[:, 0], c[:, 3] - c[:, 0]), c[:, 4] - c[:, 0])
+    neg = vol < 0
+    pn[neg] = pn[neg][:, [0, 3, 2, 1, 4]]
+    return pn
+
+
+def _orient_tet(xyz, tn):
+    vol = _tet_signed_volume(xyz[tn])
+    neg = vol < 0
+    tn[neg] = tn[neg][:, [0, 2, 1, 3]]
+    return tn
+
+
+def _face_split_tets(cell, face_cyc, apex):
+    """The pyramid (apex, cell face) cut into 2 tetrahedra along the face diagonal from
+    its lowest to its highest corner: [2][4] vertex ids (orientation not yet fixed)."""
+    ids = [cell[k] for k in face_cyc]
+    # cyclic corners 0 and 2 are the (0,0) and (1,1) offsets in the face's axes
+    lo_, a, hi_, b = ids
+    return [[apex, lo_, a, hi_], [apex, lo_, b, hi_]]
+
+
+def _assemble(xyz, blocks, period, meta, permute_seed):
+    en, et = [], []
+    for t, nodes in blocks:
+        if len(nodes) == 0:
+            continue
+        e = np.full((len(nodes), 8), -1, dtype=np.int64)
+        e[:, :nodes.shape[1]] = nodes
+        en.append(e)
+        et.append(np.full(len(nodes), t, dtype=np.int32))
+    en, et = np.concatenate(en), np.concatenate(et)
+    if permute_seed is not None:
+        perm = np.random.default_rng(permute_seed).permutation(en.shape[0])
+        en, et = en[perm], et[perm]
+    return Mesh(xyz, et, en, period, meta)
+
+
+def pyramid_box(n=(3, 3, 3), lo=(-math.pi,) * 3, hi=(math.pi,) * 3, apex_perturb=0.0,
+                perturb_seed=None, permute_seed=None) -> Mesh:
+    """Periodic box with each of the nx*ny*nz cells cut into 6 pyramids (one per face).
+
+    The apex of a cell's pyramids is its centre moved by U(-apex_perturb, apex_perturb) * h
+    per coordinate, drawn with PCG64(perturb_seed) in C order of the cells [k][j][i];
+    the lattice itself is not perturbed, so every base is an exact parallelogram.
+    """
+    hx = hex_box(n, lo, hi)
+    cells = hx.enodes[:, :8]
+    cen = _cell_centres(hx.xyz, cells, hx.meta["h"], apex_perturb, perturb_seed)
+    xyz = np.concatenate([hx.xyz, cen])
+    apex = hx.xyz.shape[0] + np.arange(cells.shape[0])
+    pn = np.concatenate([np.column_stack([cells[:, cyc], apex]) for _, _, cyc in _CELL_FACES])
+    pn = _orient_pyr(xyz, pn)
+    return _assemble(xyz, [(PYR, pn)], hx.period.copy(),
+                     {"n": tuple(n), "h": hx.meta["h"], "kind": "pyramid_box"}, permute_seed)
+
+
+def transition_box(n=(4, 2, 2), n_hex=None, lo=(-math.pi,) * 3, hi=(math.pi,) * 3,
+                   apex_perturb=0.0, perturb_seed=None, permute_seed=None) -> Mesh:
+    """Conforming periodic box of hexahedra, pyramids and tetrahedra (see module notes).
+
+    Cell column i along x: i < n_hex hexahedra (default nx // 2); i = n_hex and
+    i = nx - 1 transition cells (1 pyramid on the face toward the hexahedra + 10
+    tetrahedra); the columns between them Kuhn-split (6 tetrahedra each).  Requires
+    nx >= n_hex + 2.  Apex displacement as in ``pyramid_box``, in cell order
+    [k][j][i] over the transition cells only.
+    """
+    n = tuple(int(v) for v in n)
+    nx, ny, nz = n
+    n_hex = nx // 2 if n_hex is None else int(n_hex)
+    if n_hex < 1 or nx < n_hex + 2:
+        raise ValueError("transition_box needs 1 <= n_hex <= nx - 2")
+    hx = hex_box(n, lo, hi)
+    cells = hx.enodes[:, :8]                       # C order [k][j][i]
+    ci = np.arange(cells.shape[0]) % nx
+    hexes = cells[ci < n_hex]
+    kuhn = kuhn_split(Mesh(hx.xyz, np.full(int(np.sum((ci > n_hex) & (ci < nx - 1))), HEX, np.int32),
+                           cells[(ci > n_hex) & (ci < nx - 1)], hx.period))
+    tets = [kuhn.enodes[:, :4]] if kuhn.n_elem else []
+    trans = np.nonzero((ci == n_hex) | (ci == nx - 1))[0]
+    cen = _cell_centres(hx.xyz, cells[trans], hx.meta["h"], apex_perturb, perturb_seed)
+    xyz = np.concatenate([hx.xyz, cen])
+    pyrs, extra = [], []
+    for t_, c in enumerate(trans):
+        cell, apex = cells[c], hx.xyz.shape[0] + t_
+        base_side = 0 if ci[c] == n_hex else 1       # pyramid on the x face toward the hexahedra
+        for ax, side, cyc in _CELL_FACES:
+            if ax == 0 and side == base_side:
+                pyrs.append([cell[k] for k in cyc] + [apex])
+            else:
+                extra.extend(_face_split_tets(cell, cyc, apex))
+    tets.append(np.array(extra, dtype=np.int64))
+    tn = _orient_tet(xyz, np.concatenate(tets).astype(np.int64))
+    pn = _orient_pyr(xyz, np.array(pyrs, dtype=np.int64))
+    return _assemble(xyz, [(HEX, hexes), (PYR, pn), (TET, tn)], hx.period.copy(),
+                     {"n": n, "n_hex": n_hex, "h": hx.meta["h"], "kind": "transition_box"},
+                     permute_seed)
 
 
 def concat(meshes, permute_seed=None) -> Mesh:

@@ -86,6 +86,9 @@ def test_mesh_errors_are_reported_before_device_work():
     m.enodes[0, 0] = 10 ** 6
     st, msg = setup(m)
     assert st == 1
+    # pyramids exist in the oracle only: the library names the type it does not know
+    st, msg = setup(inputs.transition_box((4, 1, 1)), order=4)
+    assert st == 1 and "unknown element type" in msg
     # parameter errors
     for kw, word in ((dict(filt_bits=31), "filt_bits"), (dict(filt_zeta_max_coef=0.0), "zeta"),
                      (dict(filt_eps_s=-1.0), "tolerance"), (dict(gamma=1.0), "gamma"),

@@ -63,7 +63,7 @@ typedef enum {
 enum { FR_EULER = 0, FR_NAVIER_STOKES = 1 };
 enum { FR_RUSANOV = 0, FR_HLLC = 1 };
 enum { FR_FP64 = 0, FR_FP32 = 1, FR_FP32_BF16X3 = 2 };
-enum { FR_HEX = 0, FR_TET = 1 };
+enum { FR_HEX = 0, FR_TET = 1, FR_PYR = 2 };
 enum { FR_METRIC_CONSERVATIVE = 0, FR_METRIC_CROSS = 1 };
 
 /* Solver parameters.  struct_size must be sizeof(fr_params). */
@@ -106,7 +106,7 @@ typedef struct {
 
 typedef struct {
   int32_t n_types;         /* 1 or 2                                                  */
-  int32_t etype[2];        /* FR_HEX / FR_TET of each block                          */
+  int32_t etype[2];        /* FR_HEX / FR_TET / FR_PYR of each block                 */
   int64_t n_elem[2];       /* elements per block                                     */
   int64_t e_pad[2];        /* padded element count of the native layout             */
   int32_t n_sp[2];         /* solution points per element                            */
@@ -163,8 +163,18 @@ void fr_default_params(fr_params* p);
  *            flux points by coordinates after removing the face's periodic shift.
  *            A zero entry means "not periodic in that direction".
  *   etype    [n_elem] FR_HEX (8-node, VTK corner order) or FR_TET (4-node, corners
- *            in the order (-1,-1,-1) (1,-1,-1) (-1,-1,1) (-1,1,-1) of the reference).
- *   enodes   [n_elem][8] corner indices (tets use the first 4).
+ *            in the order (-1,-1,-1) (1,-1,-1) (-1,-1,1) (-1,1,-1) of the reference), or
+ *            FR_PYR (5-node: the base corners in cyclic order, then the apex, as the
+ *            reference (-1,-1,-1) (1,-1,-1) (1,1,-1) (-1,1,-1) (0,0,1); Sec. "Mixed
+ *            elements and domain decomposition": pyramids with an affine base, so the
+ *            base must be a parallelogram, corner 2 = corner 1 + corner 3 - corner 0,
+ *            else FR_ERR_MESH).  Pyramids are order 4 (55 solution points of the
+ *            rational pyramid space, layered Gauss--Legendre; 85 flux points: the base's
+ *            5 x 5 Gauss--Legendre grid and each triangle the 15 face points of the
+ *            p = 4 tetrahedron; DG lifting) and come in meshes of pyramids only: a mesh
+ *            mixing them with other types is FR_ERR_UNSUPPORTED, as are the entropy
+ *            filter, the MLP calls and FR_FP32_BF16X3 on such a context.
+ *   enodes   [n_elem][8] corner indices (tets use the first 4, pyramids 5).
  *   stream   hipStream_t for all work of the context (NULL = default stream).
  * Synchronous.  Errors: FR_ERR_ARG, FR_ERR_MESH, FR_ERR_UNSUPPORTED, FR_ERR_ALLOC. */
 fr_status fr_setup_mesh(const fr_params* p, int64_t n_vert, const double* xyz,

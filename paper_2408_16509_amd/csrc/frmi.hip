@@ -15,6 +15,7 @@
 #include "filter_tet.hpp"
 #include "hex.hpp"
 #include "mlp.hpp"
+#include "pyr.hpp"
 #include "setup.hpp"
 #include "tet.hpp"
 
@@ -115,6 +116,7 @@ struct fr_ctx_s {
   double* rk_part = nullptr;   // adaptive stepping: per-workgroup partial sums of the norm
   double* rk_s64 = nullptr;   // FP64 stage state of the filtered FP32 form    // [TET_KP][TET_MP] transposed divergence operator
   int32_t* tet_src = nullptr;
+  void* pyr_ops = nullptr;    // pyramids: It [55][85], Dt [3][55][55], Lt [85][55] in the context's type
   double* tet_ftab = nullptr; // entropy filter on tetrahedra: modal operators, weights, multiplicities
   // training-data collection during filtered RK steps (fr_mlp_collect)
   bool collecting = false;
@@ -576,6 +578,49 @@ fr_status tet_rhs(fr_ctx c, DevBlock& b, const T* u, T* r) {
   return FR_OK;
 }
 
+// Pyramids: traces, then (Navier--Stokes) the LDG gradient, then the corrected divergence.
+template <typename T, bool DEV>
+fr_status pyr_rhs(fr_ctx c, DevBlock& b, const T* u, T* r) {
+  Conn C{b.nbr_elem, b.nbr_info, c->perm, c->host.perm_stride};
+  const fr_params& p = c->prm;
+  const PyrOps& Y = c->host.pyr;
+  PyrK<T> K;
+  for (int f = 0; f <= 5; ++f) K.face_off[f] = Y.face_off[f];
+  for (int f = 0; f < 5; ++f) for (int k = 0; k < 3; ++k) K.nref[f][k] = (T)Y.nref[f][k];
+  const T* ops = (const T*)c->pyr_ops;
+  PyrOpsDev<T> O{ops, ops + PY_NSP * PY_NFP, ops + PY_NSP * PY_NFP + 3 * PY_NSP * PY_NSP};
+  const RefState<T> R = ref_of<T>(p);
+  const T* geo = (const T*)b.geo_t;
+  T* uf = (T*)b.uf;
+  static const std::string sfx = sizeof(T) == 8 ? "" : "_f32";
+  if (b.E % 64 != 0) return fail(c, FR_ERR_STATE, "pyramid block not padded to 64 elements");
+  const int64_t trace_threads = b.E * PY_NFP;
+  int pk = c->prof_begin(("pyr_trace" + sfx).c_str());
+  pyr_trace<T><<<(unsigned)((trace_threads + 255) / 256), 256, 0, c->stream>>>(u, uf, b.E, O.It);
+  c->prof_end(pk);
+  const unsigned nblk = (unsigned)(b.E / PY_WAVES);
+  const T gam = (T)p.gamma, mu = (T)p.mu, pr = (T)p.prandtl, beta = (T)p.ldg_beta, tau = (T)p.ldg_tau;
+  if (p.system == FR_EULER) {
+    pk = c->prof_begin(("pyr_div_euler" + sfx).c_str());
+    pyr_div<T, DEV, false><<<nblk, 64 * PY_WAVES, 0, c->stream>>>(u, uf, nullptr, nullptr, geo, C, O, K, r, b.E, gam,
+                                                                    mu, pr, beta, tau, p.riemann, R);
+    c->prof_end(pk);
+  } else {
+    T* grad = (T*)b.grad;
+    T* gradf = (T*)b.gradf;
+    pk = c->prof_begin(("pyr_grad" + sfx).c_str());
+    pyr_grad<T><<<nblk, 64 * PY_WAVES, 0, c->stream>>>(u, uf, geo, C, O, K, grad, gradf, b.E, beta);
+    c->prof_end(pk);
+    pk = c->prof_begin(("pyr_div_ns" + sfx).c_str());
+    pyr_div<T, DEV, true><<<nblk, 64 * PY_WAVES, 0, c->stream>>>(u, uf, grad, gradf, geo, C, O, K, r, b.E, gam, mu,
+                                                                   pr, beta, tau, p.riemann, R);
+    c->prof_end(pk);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(c, FR_ERR_DEVICE, std::string("pyramid kernel launch: ") + hipGetErrorString(e));
+  return FR_OK;
+}
+
 template <typename T, bool DEV>
 fr_status rhs_t(fr_ctx c, const T* u, T* r) {
   for (auto& b : c->blocks) {
@@ -590,6 +635,8 @@ fr_status rhs_t(fr_ctx c, const T* u, T* r) {
         case 4: s = b.cmet ? hex_rhs_p<T, DEV, 4, true>(c, b, ub, rb) : hex_rhs_p<T, DEV, 4, false>(c, b, ub, rb); break;
         default: s = fail(c, FR_ERR_UNSUPPORTED, "order");
       }
+    } else if (b.etype == FR_PYR) {
+      s = pyr_rhs<T, DEV>(c, b, ub, rb);
     } else {
       s = b.cmet ? tet_rhs<T, DEV, true>(c, b, ub, rb) : tet_rhs<T, DEV, false>(c, b, ub, rb);
     }
@@ -640,6 +687,9 @@ FiltPrm filtprm_of(const fr_params& p, int order) {
 }
 
 fr_status filter_alloc(fr_ctx c) {
+  for (auto& b : c->blocks)
+    if (b.etype == FR_PYR)
+      return fail(c, FR_ERR_UNSUPPORTED, "the entropy filter and its learned warm start have no pyramid form");
   if (c->f_k) return FR_OK;
   bool has_tet = false;
   for (auto& b : c->blocks) has_tet = has_tet || b.etype == FR_TET;
@@ -1038,7 +1088,7 @@ void fr_destroy(fr_ctx c) {
   (void)hipFree(c->rk_stage); (void)hipFree(c->rk_acc); (void)hipFree(c->rk_k); (void)hipFree(c->rk_s64);
   (void)hipFree(c->rk_x0); (void)hipFree(c->rk_err); (void)hipFree(c->rk_part);
   (void)hipFree(c->flag);
-  (void)hipFree(c->tet_src); (void)hipFree(c->tet_opT); (void)hipFree(c->tet_ogT);
+  (void)hipFree(c->tet_src); (void)hipFree(c->tet_opT); (void)hipFree(c->tet_ogT); (void)hipFree(c->pyr_ops);
   (void)hipFree(c->tet_opH); (void)hipFree(c->tet_ogH); (void)hipFree(c->tet_ftab);
   for (auto& b : c->blocks) {
     (void)hipFree(b.sown); (void)hipFree(b.smin);
@@ -1303,6 +1353,28 @@ fr_status setup_impl(const fr_params* p, int64_t n_vert, const double* xyz, cons
     if (dalloc(c, &c->tet_src, src.size())) return bail(FR_ERR_ALLOC);
     if (hipMemcpy(c->tet_src, src.data(), src.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
       c->err = "upload failed";
+      return bail(FR_ERR_DEVICE);
+    }
+  }
+  if (std::any_of(c->blocks.begin(), c->blocks.end(), [](const DevBlock& b) { return b.etype == FR_PYR; })) {
+    const PyrOps& Y = c->host.pyr;
+    std::vector<double> ops((size_t)PY_NSP * PY_NFP * 2 + 3 * PY_NSP * PY_NSP);
+    double* It = ops.data();
+    double* Dt = It + PY_NSP * PY_NFP;
+    double* Lt = Dt + 3 * PY_NSP * PY_NSP;
+    for (int j = 0; j < PY_NSP; ++j)
+      for (int fp = 0; fp < PY_NFP; ++fp) It[j * PY_NFP + fp] = Y.interp[fp][j];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < PY_NSP; ++j)
+        for (int pt = 0; pt < PY_NSP; ++pt) Dt[(i * PY_NSP + j) * PY_NSP + pt] = Y.D[i][pt][j];
+    for (int fp = 0; fp < PY_NFP; ++fp)
+      for (int pt = 0; pt < PY_NSP; ++pt) Lt[fp * PY_NSP + pt] = Y.lift[pt][fp];
+    std::vector<char> bo(ops.size() * tsz);
+    if (tsz == sizeof(float)) for (size_t i = 0; i < ops.size(); ++i) ((float*)bo.data())[i] = (float)ops[i];
+    else std::memcpy(bo.data(), ops.data(), bo.size());
+    if (dalloc(c, (char**)&c->pyr_ops, bo.size()) ||
+        hipMemcpy(c->pyr_ops, bo.data(), bo.size(), hipMemcpyHostToDevice) != hipSuccess) {
+      c->err = "pyramid operator upload failed";
       return bail(FR_ERR_DEVICE);
     }
   }

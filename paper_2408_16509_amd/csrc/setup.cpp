@@ -16,6 +16,7 @@
 #include <array>
 #include <cmath>
 #include <map>
+#include <stdexcept>
 #include <thread>
 #include <unordered_map>
 
@@ -127,6 +128,8 @@ static const double kTetPts[35][3] = {
 // reference corners and faces (corner triples), outward unit normals
 static const double kTetCorner[4][3] = {{-1, -1, -1}, {1, -1, -1}, {-1, -1, 1}, {-1, 1, -1}};
 static const int kTetFace[4][3] = {{0, 1, 3}, {0, 1, 2}, {0, 2, 3}, {1, 2, 3}};
+static const double kPyrCorner[5][3] = {{-1, -1, -1}, {1, -1, -1}, {1, 1, -1}, {-1, 1, -1}, {0, 0, 1}};
+static const int kPyrFace[5][4] = {{0, 1, 2, 3}, {0, 1, 4, -1}, {1, 2, 4, -1}, {2, 3, 4, -1}, {3, 0, 4, -1}};
 static const int kHexFaceCorners[6][4] = {{0, 3, 4, 7}, {1, 2, 5, 6}, {0, 1, 4, 5}, {2, 3, 6, 7}, {0, 1, 2, 3}, {4, 5, 6, 7}};
 
 static ld factorial(int n) { ld r = 1; for (int i = 2; i <= n; ++i) r *= i; return r; }
@@ -482,22 +485,42 @@ std::string build_setup(int order, int64_t n_vert, const double* xyz, const doub
   code = 0;
   out = Setup();
   if (order < 1 || order > kMaxP) { code = 3; return "hexahedra support orders 1..4"; }
-  bool has[2] = {false, false};
+  bool has[3] = {false, false, false};
+  const double span0 = [&] {
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int64_t v = 0; v < n_vert; ++v)
+      for (int d = 0; d < 3; ++d) { lo[d] = std::min(lo[d], xyz[v * 3 + d]); hi[d] = std::max(hi[d], xyz[v * 3 + d]); }
+    return std::max({hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2], 1e-300});
+  }();
   for (int64_t e = 0; e < n_elem; ++e) {
-    if (etype[e] != kHex && etype[e] != kTet) { code = 1; return "unknown element type"; }
+    if (etype[e] != kHex && etype[e] != kTet && etype[e] != kPyr) { code = 1; return "unknown element type"; }
     has[etype[e]] = true;
-    int nc = etype[e] == kHex ? 8 : 4;
+    int nc = etype[e] == kHex ? 8 : (etype[e] == kPyr ? 5 : 4);
     for (int c = 0; c < nc; ++c)
       if (enodes[e * 8 + c] < 0 || enodes[e * 8 + c] >= n_vert) { code = 1; return "corner index out of range"; }
+    if (etype[e] == kPyr) {
+      // affine base: corner 2 = corner 1 + corner 3 - corner 0
+      double sk = 0;
+      for (int d = 0; d < 3; ++d) {
+        const double r = xyz[enodes[e * 8 + 2] * 3 + d] - xyz[enodes[e * 8 + 1] * 3 + d] -
+                          xyz[enodes[e * 8 + 3] * 3 + d] + xyz[enodes[e * 8 + 0] * 3 + d];
+        sk += r * r;
+      }
+      if (std::sqrt(sk) > 1e-10 * span0) { code = 2; return "pyramid base is not a parallelogram (the map must be affine)"; }
+    }
   }
-  if (has[kTet] && order != 4) { code = 3; return "tetrahedra are supported at order 4 only (the paper's point set)"; }
+  if ((has[kTet] || has[kPyr]) && order != 4) { code = 3; return "tetrahedra and pyramids are supported at order 4 only"; }
+  if (has[kPyr] && (has[kHex] || has[kTet]))
+    { code = 3; return "pyramids are supported in meshes of pyramids only (no coupling to hexahedra or tetrahedra)"; }
   build_hex_ops(order, out.hex);
-  if (has[kTet]) build_tet_ops(out.tet);
+  if (has[kTet] || has[kPyr]) build_tet_ops(out.tet);
+  if (has[kPyr]) build_pyr_ops(out.tet, out.pyr);
   const HexOps& H = out.hex;
   const TetOps& T = out.tet;
+  const PyrOps& Y = out.pyr;
   // blocks
-  int bidx[2] = {-1, -1};
-  for (int t = 0; t < 2; ++t) if (has[t]) {
+  int bidx[3] = {-1, -1, -1};
+  for (int t = 0; t < 3; ++t) if (has[t]) {
     Block b;
     b.etype = t;
     for (int64_t e = 0; e < n_elem; ++e) if (etype[e] == t) b.elems.push_back(e);
@@ -505,7 +528,7 @@ std::string build_setup(int order, int64_t n_vert, const double* xyz, const doub
     b.canon_pos.resize(b.n);
     for (int64_t i = 0; i < b.n; ++i) b.canon_pos[i] = (int32_t)i;
     if (elem_order == 0 || elem_order == 2) {
-      const int nc = t == kHex ? 8 : 4;
+      const int nc = t == kHex ? 8 : (t == kPyr ? 5 : 4);
       Block keep;
       if (elem_order == 0) { keep.n = b.n; keep.elems = b.elems; keep.canon_pos = b.canon_pos; }
       morton_order(b, nc, xyz, enodes);
@@ -516,10 +539,10 @@ std::string build_setup(int order, int64_t n_vert, const double* xyz, const doub
       }
     }
     b.e_pad = (b.n + e_align - 1) / e_align * e_align;
-    b.nsp = t == kHex ? H.nsp : T.nsp;
-    b.nfp = t == kHex ? H.nfp : T.nfp;
-    b.nfaces = t == kHex ? 6 : 4;
-    b.nfpf = t == kHex ? H.nfpf : T.nfpf;
+    b.nsp = t == kHex ? H.nsp : (t == kPyr ? PyrOps::nsp : T.nsp);
+    b.nfp = t == kHex ? H.nfp : (t == kPyr ? PyrOps::nfp : T.nfp);
+    b.nfaces = t == kHex ? 6 : (t == kPyr ? 5 : 4);
+    b.nfpf = t == kHex ? H.nfpf : (t == kPyr ? 25 : T.nfpf);   // pyramids: the base's count (the largest)
     b.ngeo = t == kHex ? 24 : 10;
     b.geo.assign((size_t)b.ngeo * b.e_pad, 0.0);
     b.nbr_elem.assign((size_t)b.nfaces * b.e_pad, 0);
@@ -549,6 +572,30 @@ std::string build_setup(int order, int64_t n_vert, const double* xyz, const doub
           if (z < H.nsp)
             for (int d = 0; d < 3; ++d) b.sol_xyz[((size_t)b.canon_pos[le] * b.nsp + z) * 3 + d] = x[d];
         }
+      } else if (b.etype == kPyr) {
+        double X[5][3];
+        for (int n = 0; n < 5; ++n) for (int d = 0; d < 3; ++d) X[n][d] = xyz[enodes[e * 8 + n] * 3 + d];
+        double g[3][3];   // dx/dxi_k: (X1 - X0)/2, (X3 - X0)/2, (X4 - base centre)/2
+        for (int d = 0; d < 3; ++d) {
+          g[0][d] = 0.5 * (X[1][d] - X[0][d]);
+          g[1][d] = 0.5 * (X[3][d] - X[0][d]);
+          g[2][d] = 0.5 * (X[4][d] - 0.5 * (X[1][d] + X[3][d]));
+        }
+        double S[3][3];
+        cross(g[1], g[2], S[0]);
+        cross(g[2], g[0], S[1]);
+        cross(g[0], g[1], S[2]);
+        double J = g[0][0] * S[0][0] + g[0][1] * S[0][1] + g[0][2] * S[0][2];
+        if (le < b.n && !(J > 0)) { code = 2; return "element with J <= 0"; }
+        for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) b.geo[(size_t)(i * 3 + j) * b.e_pad + le] = S[i][j];
+        b.geo[(size_t)9 * b.e_pad + le] = J;
+        if (le >= b.n) continue;
+        for (int z = 0; z < PyrOps::nsp; ++z)
+          for (int d = 0; d < 3; ++d) {
+            double x = X[0][d];
+            for (int k = 0; k < 3; ++k) x += (Y.pts[z][k] + 1.0) * g[k][d];
+            b.sol_xyz[((size_t)b.canon_pos[le] * b.nsp + z) * 3 + d] = x;
+          }
       } else {
         double X[4][3];
         for (int n = 0; n < 4; ++n) for (int d = 0; d < 3; ++d) X[n][d] = xyz[enodes[e * 8 + n] * 3 + d];
@@ -582,12 +629,14 @@ std::string build_setup(int order, int64_t n_vert, const double* xyz, const doub
     for (int d = 0; d < 3; ++d) { lo[d] = std::min(lo[d], xyz[v * 3 + d]); hi[d] = std::max(hi[d], xyz[v * 3 + d]); }
   double span = std::max({hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2], 1e-300});
   const double scale = 1e-8 * span;
+  auto face_nc = [&](const Block& b, int f) { return b.etype == kHex ? 4 : (b.etype == kPyr ? (f == 0 ? 4 : 3) : 3); };
+  auto face_nq = [&](const Block& b, int f) { return b.etype == kPyr ? Y.face_off[f + 1] - Y.face_off[f] : b.nfpf; };
   auto face_centroid = [&](const Block& b, int64_t le, int f, double c[3]) {
     int64_t e = b.elems[le];
-    int nc = b.etype == kHex ? 4 : 3;
+    int nc = face_nc(b, f);
     c[0] = c[1] = c[2] = 0;
     for (int k = 0; k < nc; ++k) {
-      int corner = b.etype == kHex ? kHexFaceCorners[f][k] : kTetFace[f][k];
+      int corner = b.etype == kHex ? kHexFaceCorners[f][k] : (b.etype == kPyr ? kPyrFace[f][k] : kTetFace[f][k]);
       for (int d = 0; d < 3; ++d) c[d] += xyz[enodes[e * 8 + corner] * 3 + d];
     }
     for (int d = 0; d < 3; ++d) c[d] /= nc;
@@ -616,10 +665,17 @@ std::string build_setup(int order, int64_t n_vert, const double* xyz, const doub
   }
   // flux point physical coordinates of one face
   auto face_points = [&](const Block& b, int64_t le, int f, std::vector<std::array<double, 3>>& P) {
-    P.resize(b.nfpf);
+    P.resize(face_nq(b, f));
     int64_t e = b.elems[le];
-    for (int q = 0; q < b.nfpf; ++q) {
-      if (b.etype == kHex) {
+    for (int q = 0; q < (int)P.size(); ++q) {
+      if (b.etype == kPyr) {
+        const double* xi = Y.fpts[Y.face_off[f] + q];
+        double X[5][3];
+        for (int n = 0; n < 5; ++n) for (int d = 0; d < 3; ++d) X[n][d] = xyz[enodes[e * 8 + n] * 3 + d];
+        for (int d = 0; d < 3; ++d)
+          P[q][d] = X[0][d] + 0.5 * (xi[0] + 1) * (X[1][d] - X[0][d]) + 0.5 * (xi[1] + 1) * (X[3][d] - X[0][d]) +
+                    0.5 * (xi[2] + 1) * (X[4][d] - 0.5 * (X[1][d] + X[3][d]));
+      } else if (b.etype == kHex) {
         double c[24], xi[3], x[3], G[3][3];
         for (int g = 0; g < 24; ++g) c[g] = b.geo[(size_t)g * b.e_pad + le];
         hex_fp_ref(H, f, q, xi);
@@ -648,9 +704,10 @@ std::string build_setup(int order, int64_t n_vert, const double* xyz, const doub
       double sg = (f % 2) ? 1.0 : -1.0;
       for (int k = 0; k < 3; ++k) nv[k] *= sg;
     } else {
+      const double* nr = b.etype == kPyr ? Y.nref[f] : T.nref[f];
       for (int j = 0; j < 3; ++j) {
         nv[j] = 0;
-        for (int i = 0; i < 3; ++i) nv[j] += b.geo[(size_t)(i * 3 + j) * b.e_pad + le] * T.nref[f][i];
+        for (int i = 0; i < 3; ++i) nv[j] += b.geo[(size_t)(i * 3 + j) * b.e_pad + le] * nr[i];
       }
     }
   };
@@ -673,6 +730,7 @@ std::string build_setup(int order, int64_t n_vert, const double* xyz, const doub
     int64_t ea = lst[0][1], eb = lst[1][1];
     int fa = (int)lst[0][2], fb = (int)lst[1][2];
     if (A.etype != B.etype) { code = 3; return "hexahedron-tetrahedron interfaces need pyramids (not supported)"; }
+    if (face_nq(A, fa) != face_nq(B, fb)) { code = 2; return "matched faces of different kinds"; }
     face_points(A, ea, fa, PA);
     face_points(B, eb, fb, PB);
     double ca[3], cb[3], sh[3];
@@ -684,7 +742,7 @@ std::string build_setup(int order, int64_t n_vert, const double* xyz, const doub
       if (period[d] > 0) w = dd - period[d] * std::nearbyint(dd / period[d]);
       sh[d] = dd - w;
     }
-    int nq = A.nfpf;
+    int nq = face_nq(A, fa);
     std::vector<int32_t> pa(nq), pb(nq, -1);
     for (int q = 0; q < nq; ++q) {
       int best = -1;
@@ -1124,6 +1182,205 @@ std::string build_curved_tet(int q, int metric, const double* xyz, const int64_t
   for (int r = 0; r < rows; ++r)
     for (int64_t le = b.n; le < b.e_pad; ++le) b.cmet[(size_t)r * b.e_pad + le] = b.cmet[(size_t)r * b.e_pad];
   return "";
+}
+
+// ------------------------------------------------------------------ pyramids
+// Reference pyramid (kPyrCorner, kPyrFace above): corners (-1,-1,-1) (1,-1,-1) (1,1,-1)
+// (-1,1,-1) (0,0,1); faces the base (0 1 2 3) and the triangles (0 1 4) (1 2 4) (2 3 4) (3 0 4).
+
+namespace {
+// Basis of the rational space: phi = x^i y^j s^(m-i-j) z^c (= (x/s)^i (y/s)^j s^m z^c),
+// m = max(i, j), c <= 4 - m.  At the apex (s = 0) only the m = 0 members are nonzero
+// (the others carry s^m with x/s, y/s bounded), which gives their values there.
+struct PyrMode { int i, j, m, c; };
+std::vector<PyrMode> pyr_modes() {
+  std::vector<PyrMode> md;
+  for (int i = 0; i <= 4; ++i)
+    for (int j = 0; j <= 4; ++j) {
+      const int m = std::max(i, j);
+      for (int c = 0; c <= 4 - m; ++c) md.push_back({i, j, m, c});
+    }
+  return md;
+}
+ld ipow(ld x, int n) { ld r = 1; for (int k = 0; k < n; ++k) r *= x; return r; }
+ld pyr_phi(const PyrMode& q, const ld* X) {
+  const ld s = (1 - X[2]) / 2;
+  if (s < 1e-15L) return q.m == 0 ? ipow(X[2], q.c) : 0;
+  const ld a = X[0] / s, b = X[1] / s;
+  return ipow(a, q.i) * ipow(b, q.j) * ipow(s, q.m) * ipow(X[2], q.c);
+}
+// gradient at an interior point: phi = x^i y^j s^e z^c, e = m - i - j, ds/dz = -1/2
+void pyr_dphi(const PyrMode& q, const ld* X, ld g[3]) {
+  const ld x = X[0], y = X[1], z = X[2], s = (1 - z) / 2;
+  const int e = q.m - q.i - q.j;
+  const ld se = std::pow(s, (ld)e), zc = ipow(z, q.c);
+  const ld xi = ipow(x, q.i), yj = ipow(y, q.j);
+  g[0] = q.i ? q.i * ipow(x, q.i - 1) * yj * se * zc : 0;
+  g[1] = q.j ? q.j * xi * ipow(y, q.j - 1) * se * zc : 0;
+  g[2] = xi * yj * ((e ? -0.5L * e * std::pow(s, (ld)(e - 1)) * zc : 0) + (q.c ? se * q.c * ipow(z, q.c - 1) : 0));
+}
+}  // namespace
+
+void build_pyr_ops(const TetOps& T, PyrOps& o) {
+  constexpr int N = PyrOps::nsp, NF = PyrOps::nfp;
+  const std::vector<PyrMode> md = pyr_modes();
+  if ((int)md.size() != N) throw std::runtime_error("pyramid space dimension");
+  ld g5[5], w5[5];
+  gauss_legendre(5, g5, w5);
+  // solution points
+  int z = 0;
+  for (int k = 0; k < 5; ++k) {
+    const int n = 5 - k;
+    ld g[5], w[5];
+    gauss_legendre(n, g, w);
+    const ld s = (1 - g5[k]) / 2;
+    for (int j = 0; j < n; ++j)
+      for (int i = 0; i < n; ++i, ++z) {
+        o.pts[z][0] = (double)(s * g[i]);
+        o.pts[z][1] = (double)(s * g[j]);
+        o.pts[z][2] = (double)g5[k];
+      }
+  }
+  // reference normals
+  for (int f = 0; f < 5; ++f) {
+    const double* A = kPyrCorner[kPyrFace[f][0]];
+    const double* B = kPyrCorner[kPyrFace[f][1]];
+    const double* C = kPyrCorner[kPyrFace[f][2]];
+    double e1[3], e2[3], nv[3];
+    for (int d = 0; d < 3; ++d) { e1[d] = B[d] - A[d]; e2[d] = C[d] - A[d]; }
+    cross(e1, e2, nv);
+    const double nn = std::sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+    double dotc = nv[0] * A[0] + nv[1] * A[1] + nv[2] * (A[2] + 0.5);   // away from the centroid (0,0,-1/2)
+    const double sg = dotc > 0 ? 1.0 : -1.0;
+    for (int d = 0; d < 3; ++d) o.nref[f][d] = sg * nv[d] / nn;
+  }
+  // flux points: base grid, then the tetrahedron's face-0 points (corners 0 1 3 of the
+  // reference tetrahedron, the plane z = -1: s = (x+1)/2, t = (y+1)/2) on each triangle
+  int fp = 0;
+  o.face_off[0] = 0;
+  for (int j = 0; j < 5; ++j)
+    for (int i = 0; i < 5; ++i, ++fp) {
+      o.fpts[fp][0] = (double)g5[i]; o.fpts[fp][1] = (double)g5[j]; o.fpts[fp][2] = -1.0;
+      o.fp_face[fp] = 0;
+    }
+  double st[15][2];
+  for (int q = 0; q < 15; ++q) {
+    const double* X = T.pts[T.fp_src[q]];
+    st[q][0] = (X[0] + 1) / 2;
+    st[q][1] = (X[1] + 1) / 2;
+  }
+  for (int f = 1; f < 5; ++f) {
+    o.face_off[f] = fp;
+    const double* c0 = kPyrCorner[kPyrFace[f][0]];
+    const double* c1 = kPyrCorner[kPyrFace[f][1]];
+    const double* c2 = kPyrCorner[kPyrFace[f][2]];
+    for (int q = 0; q < 15; ++q, ++fp) {
+      for (int d = 0; d < 3; ++d) o.fpts[fp][d] = c0[d] + st[q][0] * (c1[d] - c0[d]) + st[q][1] * (c2[d] - c0[d]);
+      o.fp_face[fp] = f;
+    }
+  }
+  o.face_off[5] = fp;
+  // Lagrange basis l_j = sum_m phi_m C[m][j]
+  static ld V[N][N];
+  for (int a = 0; a < N; ++a) {
+    const ld X[3] = {o.pts[a][0], o.pts[a][1], o.pts[a][2]};
+    for (int m = 0; m < N; ++m) V[a][m] = pyr_phi(md[m], X);
+  }
+  if (!invert(V, N)) throw std::runtime_error("pyramid solution points not unisolvent");
+  auto lag = [&](const ld* X, ld* l) {
+    ld ph[N];
+    for (int m = 0; m < N; ++m) ph[m] = pyr_phi(md[m], X);
+    for (int j = 0; j < N; ++j) { ld acc = 0; for (int m = 0; m < N; ++m) acc += ph[m] * V[m][j]; l[j] = acc; }
+  };
+  for (int f = 0; f < NF; ++f) {
+    const ld X[3] = {o.fpts[f][0], o.fpts[f][1], o.fpts[f][2]};
+    ld l[N];
+    lag(X, l);
+    for (int j = 0; j < N; ++j) o.interp[f][j] = (double)l[j];
+  }
+  for (int a = 0; a < N; ++a) {
+    const ld X[3] = {o.pts[a][0], o.pts[a][1], o.pts[a][2]};
+    ld dp[N][3];
+    for (int m = 0; m < N; ++m) pyr_dphi(md[m], X, dp[m]);
+    for (int d = 0; d < 3; ++d)
+      for (int j = 0; j < N; ++j) {
+        ld acc = 0;
+        for (int m = 0; m < N; ++m) acc += dp[m][d] * V[m][j];
+        o.D[d][a][j] = (double)acc;
+      }
+  }
+  // mass matrix by the collapsed Gauss rule x = s a, y = s b, dV = s^2 da db dz (8 points
+  // per direction: exact for the degree-(8, 8, 10) integrands in (a, b, z))
+  ld g8[8], w8[8];
+  gauss_legendre(8, g8, w8);
+  static ld M[N][N];
+  for (int i = 0; i < N; ++i) for (int j = 0; j < N; ++j) M[i][j] = 0;
+  for (int ka = 0; ka < 8; ++ka)
+    for (int kb = 0; kb < 8; ++kb)
+      for (int kz = 0; kz < 8; ++kz) {
+        const ld s = (1 - g8[kz]) / 2;
+        const ld X[3] = {s * g8[ka], s * g8[kb], g8[kz]};
+        const ld w = w8[ka] * w8[kb] * w8[kz] * s * s;
+        ld l[N];
+        lag(X, l);
+        for (int i = 0; i < N; ++i) for (int j = 0; j < N; ++j) M[i][j] += w * l[i] * l[j];
+      }
+  if (!invert(M, N)) throw std::runtime_error("pyramid mass matrix singular");
+  // face matrices E[i][sigma] = int_face l_i phi_sigma dS (true face areas)
+  static ld Em[N][NF];
+  for (int i = 0; i < N; ++i) for (int f = 0; f < NF; ++f) Em[i][f] = 0;
+  ld g7[7], w7[7];
+  gauss_legendre(7, g7, w7);
+  for (int qa = 0; qa < 7; ++qa)                       // base: tensor Lagrange on the 5 x 5 grid, dS = dx dy
+    for (int qb = 0; qb < 7; ++qb) {
+      const ld X[3] = {g7[qa], g7[qb], -1};
+      ld l[N], lx[5], ly[5], dd[5];
+      lag(X, l);
+      lagrange_1d(g5, 5, g7[qa], lx, dd);
+      lagrange_1d(g5, 5, g7[qb], ly, dd);
+      const ld w = w7[qa] * w7[qb];
+      for (int i = 0; i < N; ++i)
+        for (int jj = 0; jj < 5; ++jj)
+          for (int ii = 0; ii < 5; ++ii) Em[i][jj * 5 + ii] += w * l[i] * lx[ii] * ly[jj];
+    }
+  // triangles: Lagrange of total degree 4 on the 15 face points (monomials s^a t^b)
+  static ld Q[15][15];
+  auto tmono = [](ld s_, ld t_, ld* out) {
+    int k = 0;
+    for (int d = 0; d <= 4; ++d) for (int a = 0; a <= d; ++a) out[k++] = ipow(s_, a) * ipow(t_, d - a);
+  };
+  for (int q = 0; q < 15; ++q) tmono(st[q][0], st[q][1], Q[q]);
+  if (!invert(Q, 15)) throw std::runtime_error("triangle face points not unisolvent");
+  for (int f = 1; f < 5; ++f) {
+    const double* c0 = kPyrCorner[kPyrFace[f][0]];
+    const double* c1 = kPyrCorner[kPyrFace[f][1]];
+    const double* c2 = kPyrCorner[kPyrFace[f][2]];
+    double e1[3], e2[3], cr[3];
+    for (int d = 0; d < 3; ++d) { e1[d] = c1[d] - c0[d]; e2[d] = c2[d] - c0[d]; }
+    cross(e1, e2, cr);
+    const ld jac = std::sqrt((ld)cr[0] * cr[0] + (ld)cr[1] * cr[1] + (ld)cr[2] * cr[2]);   // 2 x area
+    for (int qa = 0; qa < 7; ++qa)                     // collapsed rule on the unit triangle
+      for (int qb = 0; qb < 7; ++qb) {
+        const ld t_ = (g7[qb] + 1) / 2, s_ = (g7[qa] + 1) / 2 * (1 - t_);
+        const ld w = w7[qa] * w7[qb] / 4 * (1 - t_) * jac;
+        ld X[3];
+        for (int d = 0; d < 3; ++d) X[d] = c0[d] + s_ * e1[d] + t_ * e2[d];
+        ld l[N], mo[15];
+        lag(X, l);
+        tmono(s_, t_, mo);
+        for (int q = 0; q < 15; ++q) {
+          ld phi = 0;
+          for (int k = 0; k < 15; ++k) phi += mo[k] * Q[k][q];
+          for (int i = 0; i < N; ++i) Em[i][o.face_off[f] + q] += w * l[i] * phi;
+        }
+      }
+  }
+  for (int i = 0; i < N; ++i)
+    for (int f = 0; f < NF; ++f) {
+      ld acc = 0;
+      for (int k = 0; k < N; ++k) acc += M[i][k] * Em[k][f];
+      o.lift[i][f] = (double)acc;
+    }
 }
 
 }  // namespace frmi

@@ -10,6 +10,7 @@ namespace frmi {
 
 constexpr int kHex = 0;
 constexpr int kTet = 1;
+constexpr int kPyr = 2;
 constexpr int kMaxP = 4;
 
 // One-dimensional operators of hexahedra of order p (Gauss--Legendre points).
@@ -41,6 +42,26 @@ struct TetOps {
   int deg[nsp];                    // total degree of mode m
 };
 
+// Operators of the order-4 pyramid with an affine base (reference base [-1,1]^2 at
+// z = -1, apex (0,0,1)).  Space: the rational pyramid space of dimension 55 spanned by
+// (x/s)^i (y/s)^j s^max(i,j) z^c, s = (1 - z)/2, c <= 4 - max(i,j); it holds P_4, and
+// its trace is Q_4 on the base and P_4 on the triangles.  Solution points: 5 layers at
+// the Gauss--Legendre z nodes, layer k the (5-k)^2 Gauss--Legendre grid scaled by s
+// (x fastest).  Flux points: the base's 5 x 5 Gauss--Legendre grid (x fastest), then
+// each triangle (corners c0 c1 c2) the 15 face points of the tetrahedron's face in
+// barycentric coordinates.  Correction: the DG lifting M^{-1} E.
+struct PyrOps {
+  static constexpr int nsp = 55, nfp = 85, nfaces = 5;
+  double pts[nsp][3];
+  double fpts[nfp][3];
+  int fp_face[nfp];
+  int face_off[nfaces + 1];        // flux points of face f: face_off[f] .. face_off[f+1]-1
+  double nref[nfaces][3];          // unit outward reference normals
+  double interp[nfp][nsp];         // l_j at the flux points
+  double D[3][nsp][nsp];           // D[i][z][j] = d l_j / d xi_i at x_z
+  double lift[nsp][nfp];           // DG lifting M^{-1} E
+};
+
 // A block of elements of one type, in the native (element-fastest) layout.
 struct Block {
   int etype = kHex;
@@ -65,6 +86,7 @@ struct Block {
 struct Setup {
   HexOps hex;
   TetOps tet;
+  PyrOps pyr;
   std::vector<Block> blocks;
   int n_orient = 0;
   std::vector<int32_t> orient_perm;  // [n_orient][max face points]
@@ -75,6 +97,7 @@ struct Setup {
 // receives 1 for argument errors, 2 for mesh errors, 3 for unsupported options.
 void build_hex_ops(int p, HexOps& ops);
 void build_tet_ops(TetOps& ops);
+void build_pyr_ops(const TetOps& tet, PyrOps& ops);   // tet: its face points are the triangles
 std::string build_setup(int order, int64_t n_vert, const double* xyz, const double* period,
                         int64_t n_elem, const int32_t* etype, const int64_t* enodes,
                         int e_align, int elem_order, Setup& out, int& code);

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libfrmi.so")
 FR_EULER, FR_NAVIER_STOKES = 0, 1
 FR_RUSANOV, FR_HLLC = 0, 1
 FR_FP64, FR_FP32, FR_FP32_BF16X3 = 0, 1, 2
-FR_HEX, FR_TET = 0, 1
+FR_HEX, FR_TET, FR_PYR = 0, 1, 2
 FR_METRIC_CONSERVATIVE, FR_METRIC_CROSS = 0, 1
 (FR_OK, FR_ERR_ARG, FR_ERR_MESH, FR_ERR_ALLOC, FR_ERR_DEVICE, FR_ERR_NONFINITE, FR_ERR_STATE,
  FR_ERR_UNSUPPORTED) = range(8)

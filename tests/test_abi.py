@@ -86,8 +86,20 @@ def test_mesh_errors_are_reported_before_device_work():
     m.enodes[0, 0] = 10 ** 6
     st, msg = setup(m)
     assert st == 1
-    # pyramids exist in the oracle only: the library names the type it does not know
+    # pyramids: meshes of pyramids only, order 4, affine (parallelogram) bases
     st, msg = setup(inputs.transition_box((4, 1, 1)), order=4)
+    assert st == 7 and "pyramids only" in msg
+    st, msg = setup(inputs.pyramid_box((2, 2, 2)), order=3)
+    assert st == 7 and "order 4" in msg
+    m = inputs.pyramid_box((2, 2, 2))
+    m.xyz = m.xyz.copy()
+    m.xyz[m.enodes[0, 2]] += np.array([0.0, 0.0, 0.05])
+    st, msg = setup(m, order=4)
+    assert st == 2 and "parallelogram" in msg
+    m = inputs.pyramid_box((2, 2, 2))
+    m.etype = m.etype.copy()
+    m.etype[0] = 3
+    st, msg = setup(m, order=4)
     assert st == 1 and "unknown element type" in msg
     # parameter errors
     for kw, word in ((dict(filt_bits=31), "filt_bits"), (dict(filt_zeta_max_coef=0.0), "zeta"),

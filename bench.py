@@ -70,6 +70,11 @@ CONFIGS = {
     # seed 57, conservative metric; oracle timing sample at 12^3 cells
     "ns_tgv_tet32_q4_curved": dict(kind="curved_tet", n=(32, 32, 32), q=4, amp=0.1, order=4, system=1, riemann=0,
                                    mach=0.1, dt=7.5e-5, permute_seed=57, oracle_sample=(12, 12, 12)),
+    # the NS TGV on p = 4 pyramids with affine bases (the transition element): 24^3 cells cut
+    # into 6 pyramids each around an apex moved by up to 10 % of a cell (seed 61), 82,944
+    # elements, 4.6 M points, element order seed 62; oracle timing sample at 8^3 cells
+    "ns_tgv_pyr24_p4": dict(kind="pyramid", n=(24, 24, 24), order=4, system=1, riemann=0, mach=0.1, dt=7.5e-5,
+                            apex_perturb=0.1, perturb_seed=61, permute_seed=62, oracle_sample=(8, 8, 8)),
     "ns_tgv_hex32_p3_adaptive": dict(n=(32, 32, 32), order=3, system=1, riemann=0, mach=0.1, dt=4e-4,
                                      adaptive=True, t_end=8e-3, tol=1e-6),
     "euler_shock_hex48_p3": dict(n=(48, 48, 48), order=3, system=0, riemann=1, dt=5e-4, filter=True,
@@ -91,6 +96,9 @@ def build_mesh(cfg, inputs):
         return inputs.concat([a, b], permute_seed=cfg["permute_seed"])
     if cfg.get("kind") == "curved":
         return inputs.curved_hex_box(cfg["n"], q=cfg["q"], amp=cfg["amp"], permute_seed=cfg.get("permute_seed"))
+    if cfg.get("kind") == "pyramid":
+        return inputs.pyramid_box(cfg["n"], apex_perturb=cfg["apex_perturb"], perturb_seed=cfg["perturb_seed"],
+                                  permute_seed=cfg.get("permute_seed"))
     if cfg.get("kind") == "curved_tet":
         return inputs.curved_tet_box(cfg["n"], q=cfg["q"], amp=cfg["amp"], permute_seed=cfg.get("permute_seed"))
     return inputs.hex_box(cfg["n"], perturb=cfg.get("perturb", 0.0), perturb_seed=cfg.get("perturb_seed"),
@@ -138,6 +146,7 @@ def kernel_bytes_per_elem(name, nsp, nfp):
         return None if metric is None else plain - geo + d * metric
     hex_geo, hex_conn = 24 * d, 6 * 2 * 4
     tet_gc = 10 * d + 4 * 2 * 4
+    pyr_gc = 10 * d + 5 * 2 * 4
     table = {
         "hex_trace": d * 5 * (nsp + nfp),
         "hex_div_euler": d * (5 * nsp + 5 * nfp + 5 * nsp) + hex_geo + hex_conn,
@@ -147,6 +156,12 @@ def kernel_bytes_per_elem(name, nsp, nfp):
         "tet_div_euler": d * (5 * nsp + 5 * nsp) + tet_gc,
         "tet_grad": d * (5 * nsp + 15 * nsp) + tet_gc,
         "tet_div_ns": d * (5 * nsp + 15 * nsp + 5 * nsp) + tet_gc,
+        # pyramids: traces of u stored for every flux point (read by both sides), the gradient
+        # and its traces at every flux point (the LDG gradient two-sided)
+        "pyr_trace": d * 5 * (nsp + nfp),
+        "pyr_div_euler": d * (5 * nsp + 5 * nfp + 5 * nsp) + pyr_gc,
+        "pyr_grad": d * (5 * nsp + 5 * nfp + 15 * nsp + 15 * nfp) + pyr_gc,
+        "pyr_div_ns": d * (5 * nsp + 15 * nsp + 5 * nfp + 15 * nfp + 5 * nsp) + pyr_gc,
     }
     if d == 4:
         # FP32 form, one-sided LDG: the gradient kernel stores the transformed viscous flux
@@ -158,21 +173,38 @@ def kernel_bytes_per_elem(name, nsp, nfp):
     return table.get(fam)
 
 
-def source_hash(kernel=""):
+def _family_hash(kernel, read):
     """Hash of the sources a kernel family is built from: its header, the shared physics,
-    and the section of the library that configures and launches the RHS kernels."""
-    csrc = os.path.join(ROOT, "paper_2408_16509_amd", "csrc")
-    files = ("hex.hpp", "physics.hpp") if not kernel.startswith("tet_") else ("tet.hpp", "hex.hpp", "physics.hpp")
+    and the part of the library that configures and launches that family's kernels (the
+    shared launch helpers at the head of the dispatch section and the family's own RHS
+    driver; the block loop that calls the drivers is left out).  read(name) returns the
+    bytes of a file of csrc/."""
+    hdr = {"tet_": ("tet.hpp", "hex.hpp", "physics.hpp"),
+           "pyr_": ("pyr.hpp", "hex.hpp", "physics.hpp")}.get(kernel[:4], ("hex.hpp", "physics.hpp"))
     h = hashlib.sha256()
-    for f in files:
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(fh.read())
-    with open(os.path.join(csrc, "frmi.hip"), "rb") as fh:
-        lib = fh.read()
-    a = lib.index(b"// ------------------------------------------------------------ hex dispatch")
-    b = lib.index(b"// ------------------------------------------------------------ entropy filter")
-    h.update(lib[a:b])
+    for f in hdr:
+        h.update(read(f))
+    lib = read("frmi.hip")
+    start = lib.index(b"// ------------------------------------------------------------ hex dispatch")
+    tet0 = lib.index(b"// CUR: curved tetrahedra, the metric stored per solution point")
+    loop = lib.index(b"template <typename T, bool DEV>\nfr_status rhs_t(")
+    pyr0 = lib.find(b"// Pyramids: traces, then")
+    tet1 = pyr0 if 0 <= pyr0 < loop else loop
+    h.update(lib[start:tet0])
+    if kernel.startswith("tet_"):
+        h.update(lib[tet0:tet1])
+    elif kernel.startswith("pyr_"):
+        h.update(lib[pyr0:loop])
     return h.hexdigest()[:16]
+
+
+def source_hash(kernel=""):
+    csrc = os.path.join(ROOT, "paper_2408_16509_amd", "csrc")
+
+    def read(f):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            return fh.read()
+    return _family_hash(kernel, read)
 
 
 def load_traffic(kernel, workload):
@@ -234,7 +266,8 @@ def run_form(form, cfg, mesh, ic, args, torch, np, frmi, inputs):
         n, s = lay.n_elem[i], lay.n_sp[i]
         canon.append(ic(x[off:off + n * s].reshape(n, s, 3)).ravel())
         off += n * s
-        blocks["hex" if lay.etype[i] == frmi.FR_HEX else "tet"] = (int(n), int(s), int(lay.n_fp[i]))
+        key = {frmi.FR_HEX: "hex", frmi.FR_TET: "tet", frmi.FR_PYR: "pyr"}[int(lay.etype[i])]
+        blocks[key] = (int(n), int(s), int(lay.n_fp[i]))
     u0 = ctx.pack64(np.concatenate(canon))
     if filter_mode == 1:
         w = getattr(args, "mlp_weights", None)
@@ -498,7 +531,7 @@ def _per_var_err(a, b, blocks, torch):
     num = torch.zeros(5, dtype=torch.float64, device=a.device)
     den = torch.zeros(5, dtype=torch.float64, device=a.device)
     o = 0
-    for key in ("hex", "tet"):
+    for key in ("hex", "tet", "pyr"):
         if key not in blocks:
             continue
         n, s, _ = blocks[key]
@@ -586,7 +619,7 @@ def cpu_baseline_sample(cfg, inputs):
     t = float(np.median(ts))
     dof = sum(b.J.size for b in bl)
     n = cfg["oracle_sample"]
-    kinds = ", ".join(f"{len(b.elems)} {'hexahedra' if b.etype == 0 else 'tetrahedra'}" for b in bl)
+    kinds = ", ".join(f"{len(b.elems)} {('hexahedra', 'tetrahedra', 'pyramids')[b.etype]}" for b in bl)
     return {"value": dof / t / 1e9, "unit": "GDoF/s", "cores": oracle_threads(), "kind": "oracle",
             "sample": f"FP64 oracle RHS on the workload built at {n[0]}x{n[1]}x{n[2]} cells per box ({kinds}, "
                       f"{dof} points), median of 5 ({t:.2f} s each), mesh setup excluded"}

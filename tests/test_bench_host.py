@@ -39,6 +39,8 @@ def test_traffic_only_for_current_sources(tmp_path, monkeypatch):
     h = bench.source_hash("hex_div_ns_f32_p3")
     assert len(h) == 16 and h == bench.source_hash("hex_grad_f32_p3")
     assert bench.source_hash("tet_grad_f32") != h
+    # each family hashes its own header and RHS driver: pyramids differ from both
+    assert bench.source_hash("pyr_div_ns_f32") not in (h, bench.source_hash("tet_grad_f32"))
 
 
 def test_workloads_and_one_gpu_rule():

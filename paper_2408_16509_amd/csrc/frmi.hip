@@ -594,25 +594,24 @@ fr_status pyr_rhs(fr_ctx c, DevBlock& b, const T* u, T* r) {
   T* uf = (T*)b.uf;
   static const std::string sfx = sizeof(T) == 8 ? "" : "_f32";
   if (b.E % 64 != 0) return fail(c, FR_ERR_STATE, "pyramid block not padded to 64 elements");
-  const int64_t trace_threads = b.E * PY_NFP;
+  const unsigned nblk = (unsigned)(b.E / py_ne<T>());
   int pk = c->prof_begin(("pyr_trace" + sfx).c_str());
-  pyr_trace<T><<<(unsigned)((trace_threads + 255) / 256), 256, 0, c->stream>>>(u, uf, b.E, O.It);
+  pyr_trace<T><<<nblk, PY_NT, 0, c->stream>>>(u, uf, b.E, O.It);
   c->prof_end(pk);
-  const unsigned nblk = (unsigned)(b.E / PY_WAVES);
   const T gam = (T)p.gamma, mu = (T)p.mu, pr = (T)p.prandtl, beta = (T)p.ldg_beta, tau = (T)p.ldg_tau;
   if (p.system == FR_EULER) {
     pk = c->prof_begin(("pyr_div_euler" + sfx).c_str());
-    pyr_div<T, DEV, false><<<nblk, 64 * PY_WAVES, 0, c->stream>>>(u, uf, nullptr, nullptr, geo, C, O, K, r, b.E, gam,
+    pyr_div<T, DEV, false><<<nblk, PY_NT, 0, c->stream>>>(u, uf, nullptr, nullptr, geo, C, O, K, r, b.E, gam,
                                                                     mu, pr, beta, tau, p.riemann, R);
     c->prof_end(pk);
   } else {
     T* grad = (T*)b.grad;
     T* gradf = (T*)b.gradf;
     pk = c->prof_begin(("pyr_grad" + sfx).c_str());
-    pyr_grad<T><<<nblk, 64 * PY_WAVES, 0, c->stream>>>(u, uf, geo, C, O, K, grad, gradf, b.E, beta);
+    pyr_grad<T><<<nblk, PY_NT, 0, c->stream>>>(u, uf, geo, C, O, K, grad, gradf, b.E, beta);
     c->prof_end(pk);
     pk = c->prof_begin(("pyr_div_ns" + sfx).c_str());
-    pyr_div<T, DEV, true><<<nblk, 64 * PY_WAVES, 0, c->stream>>>(u, uf, grad, gradf, geo, C, O, K, r, b.E, gam, mu,
+    pyr_div<T, DEV, true><<<nblk, PY_NT, 0, c->stream>>>(u, uf, grad, gradf, geo, C, O, K, r, b.E, gam, mu,
                                                                    pr, beta, tau, p.riemann, R);
     c->prof_end(pk);
   }

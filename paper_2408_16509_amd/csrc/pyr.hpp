@@ -2,10 +2,11 @@
 // the transition element, supported with an affine base), meshes of pyramids only.
 //
 // The rational pyramid space has no tensor structure and its 55 x 55 operators are
-// dense, so these kernels apply them as plain matrix-vector products: one wave per
-// element, a lane per solution point or flux point, the element's transformed fluxes
-// and interface jumps staged in LDS, the operators (transposed so that lanes read
-// consecutive entries) shared by all waves through the caches.  The steps are those of
+// dense, so these kernels apply them as plain matrix-vector products over a block of
+// elements: a thread per (element, solution point or flux point), elements fastest so
+// that global loads and stores are coalesced, the elements' states, transformed fluxes,
+// interface jumps and gradients staged in LDS, the operators shared by all threads
+// through the caches.  The steps are those of
 // the other element types: traces at the flux points (eq:disu), the common flux
 // along the left side's normal (eq:comm_flux), the transformed flux S f and its normal
 // trace, and the corrected divergence D_i f~_i + lift (F^C - f~perp) (eq:FRfinal),
@@ -25,7 +26,6 @@
 namespace frmi {
 
 constexpr int PY_NSP = 55, PY_NFP = 85;
-constexpr int PY_WAVES = 4;                 // elements (waves) per block
 
 template <typename T>
 struct PyrK {
@@ -68,45 +68,73 @@ __device__ __forceinline__ void pyr_metric(const T* __restrict__ geo, int64_t E,
   J = geo[(int64_t)9 * E + e];
 }
 
-// Step 1 (eq:disu): traces of u at the flux points.  Thread = (element, flux point):
-// lanes are 64 consecutive elements, a wave one flux point of a 64-element tile.
+// Threads of a block work on NE elements at once, element fastest: thread t takes
+// element t % NE and point (t / NE) + k (PY_NT / NE), so that each load or store of a
+// point's values covers NE consecutive elements of a row (32 bytes: 8 FP32 or 4 FP64
+// elements, which keeps the LDS tiles of the gradient kernel under 50 KB), and the
+// tiles staged in LDS serve the dense products with the same mapping.
+constexpr int PY_NT = 256;
 template <typename T>
-__global__ void __launch_bounds__(256) pyr_trace(const T* __restrict__ u, T* __restrict__ uf, int64_t E,
-                                                 const T* __restrict__ It) {
-  const int64_t gtid = xcd_block() * 256 + threadIdx.x;
-  const int64_t wave = gtid >> 6;
-  const int64_t tile = wave / PY_NFP;
-  const int fp = (int)(wave % PY_NFP);
-  const int64_t e = tile * 64 + (gtid & 63);
-  if (e >= E) return;
-  T acc[5] = {0, 0, 0, 0, 0};
-  for (int j = 0; j < PY_NSP; ++j) {
-    const T w = It[j * PY_NFP + fp];
+constexpr int py_ne() { return sizeof(T) == 8 ? 4 : 8; }
+
+// Step 1 (eq:disu): traces of u at the flux points.
+template <typename T>
+__global__ void __launch_bounds__(PY_NT) pyr_trace(const T* __restrict__ u, T* __restrict__ uf, int64_t E,
+                                                   const T* __restrict__ It) {
+  constexpr int NE = py_ne<T>(), ROWS = PY_NT / NE;
+  __shared__ T U_s[NE][5][PY_NSP];
+  const int el = threadIdx.x % NE, r0 = threadIdx.x / NE;
+  const int64_t e = xcd_block() * NE + el;
+  for (int pt = r0; pt < PY_NSP; pt += ROWS)
 #pragma unroll
-    for (int v = 0; v < 5; ++v) acc[v] += w * u[((int64_t)j * 5 + v) * E + e];
+    for (int v = 0; v < 5; ++v) U_s[el][v][pt] = u[((int64_t)pt * 5 + v) * E + e];
+  __syncthreads();
+  // each thread's flux points at once, so that every LDS value serves all of them
+  constexpr int NF = (PY_NFP + ROWS - 1) / ROWS;
+  int fps[NF];
+#pragma unroll
+  for (int k = 0; k < NF; ++k) fps[k] = min(r0 + k * ROWS, PY_NFP - 1);
+  T acc[NF][5];
+#pragma unroll
+  for (int k = 0; k < NF; ++k)
+#pragma unroll
+    for (int v = 0; v < 5; ++v) acc[k][v] = 0;
+#pragma unroll 5
+  for (int j = 0; j < PY_NSP; ++j) {
+    T x[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) x[v] = U_s[el][v][j];
+#pragma unroll
+    for (int k = 0; k < NF; ++k) {
+      const T l = It[j * PY_NFP + fps[k]];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) acc[k][v] += l * x[v];
+    }
   }
 #pragma unroll
-  for (int v = 0; v < 5; ++v) uf[((int64_t)fp * 5 + v) * E + e] = acc[v];
+  for (int k = 0; k < NF; ++k)
+    if (r0 + k * ROWS < PY_NFP)
+#pragma unroll
+      for (int v = 0; v < 5; ++v) uf[((int64_t)fps[k] * 5 + v) * E + e] = acc[k][v];
 }
 
 // Navier--Stokes gradient (LDG): grad~u = D_i u + lift (n~_i (u^ - u_f)), u^ = (uL + uR)/2
 // + beta (uL - uR); physical grad_j = sum_i S_ij / J grad~_i u.  Writes grad at the
 // solution points and its traces at the flux points.
 template <typename T>
-__global__ void __launch_bounds__(64 * PY_WAVES) pyr_grad(const T* __restrict__ u, const T* __restrict__ uf,
-                                                          const T* __restrict__ geo, Conn C, PyrOpsDev<T> O, PyrK<T> K,
-                                                          T* __restrict__ grad, T* __restrict__ gradf, int64_t E, T beta) {
-  __shared__ T U_s[PY_WAVES][5][PY_NSP];
-  __shared__ T JM_s[PY_WAVES][5][PY_NFP];
-  __shared__ T G_s[PY_WAVES][15][PY_NSP];
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t e = xcd_block() * PY_WAVES + w;
-  T S[9], J;
-  pyr_metric(geo, E, e, S, J);
-  if (lane < PY_NSP)
+__global__ void __launch_bounds__(PY_NT) pyr_grad(const T* __restrict__ u, const T* __restrict__ uf,
+                                                  const T* __restrict__ geo, Conn C, PyrOpsDev<T> O, PyrK<T> K,
+                                                  T* __restrict__ grad, T* __restrict__ gradf, int64_t E, T beta) {
+  constexpr int NE = py_ne<T>(), ROWS = PY_NT / NE;
+  __shared__ T U_s[NE][5][PY_NSP];
+  __shared__ T JM_s[NE][5][PY_NFP];
+  __shared__ T G_s[NE][15][PY_NSP];
+  const int el = threadIdx.x % NE, r0 = threadIdx.x / NE;
+  const int64_t e = xcd_block() * NE + el;
+  for (int pt = r0; pt < PY_NSP; pt += ROWS)
 #pragma unroll
-    for (int v = 0; v < 5; ++v) U_s[w][v][lane] = u[((int64_t)lane * 5 + v) * E + e];
-  for (int fp = lane; fp < PY_NFP; fp += 64) {
+    for (int v = 0; v < 5; ++v) U_s[el][v][pt] = u[((int64_t)pt * 5 + v) * E + e];
+  for (int fp = r0; fp < PY_NFP; fp += ROWS) {
     int f, fpn;
     int64_t en;
     bool left;
@@ -116,87 +144,126 @@ __global__ void __launch_bounds__(64 * PY_WAVES) pyr_grad(const T* __restrict__ 
       const T uo = uf[((int64_t)fp * 5 + v) * E + e];
       const T un = uf[((int64_t)fpn * 5 + v) * E + en];
       const T uL = left ? uo : un, uR = left ? un : uo;
-      JM_s[w][v][fp] = T(0.5) * (uL + uR) + beta * (uL - uR) - uo;
+      JM_s[el][v][fp] = T(0.5) * (uL + uR) + beta * (uL - uR) - uo;
     }
   }
+  T S[9], J;
+  pyr_metric(geo, E, e, S, J);
+  const T iJ = rcp(J);
   __syncthreads();
-  if (lane < PY_NSP) {
-    T gt[3][5];
+  // each thread's solution points at once (every LDS value serves all of them)
+  constexpr int NP = (PY_NSP + ROWS - 1) / ROWS, NF = (PY_NFP + ROWS - 1) / ROWS;
+  int pts[NP];
+#pragma unroll
+  for (int k = 0; k < NP; ++k) pts[k] = min(r0 + k * ROWS, PY_NSP - 1);
+  T gt[NP][3][5];
+#pragma unroll
+  for (int k = 0; k < NP; ++k)
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
-      for (int v = 0; v < 5; ++v) gt[i][v] = 0;
-    for (int j = 0; j < PY_NSP; ++j) {
-      const T d0 = O.Dt[(0 * PY_NSP + j) * PY_NSP + lane];
-      const T d1 = O.Dt[(1 * PY_NSP + j) * PY_NSP + lane];
-      const T d2 = O.Dt[(2 * PY_NSP + j) * PY_NSP + lane];
+      for (int v = 0; v < 5; ++v) gt[k][i][v] = 0;
+  for (int j = 0; j < PY_NSP; ++j) {
+    T x[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) x[v] = U_s[el][v][j];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      const T d0 = O.Dt[(0 * PY_NSP + j) * PY_NSP + pts[k]];
+      const T d1 = O.Dt[(1 * PY_NSP + j) * PY_NSP + pts[k]];
+      const T d2 = O.Dt[(2 * PY_NSP + j) * PY_NSP + pts[k]];
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
-        const T x = U_s[w][v][j];
-        gt[0][v] += d0 * x;
-        gt[1][v] += d1 * x;
-        gt[2][v] += d2 * x;
+        gt[k][0][v] += d0 * x[v];
+        gt[k][1][v] += d1 * x[v];
+        gt[k][2][v] += d2 * x[v];
       }
     }
-    for (int fp = 0; fp < PY_NFP; ++fp) {
-      const T l = O.Lt[fp * PY_NSP + lane];
-      const int f = pyr_face_of(K.face_off, fp);
+  }
+#pragma unroll 1
+  for (int f = 0; f < 5; ++f) {
+    const T n0 = K.nref[f][0], n1 = K.nref[f][1], n2 = K.nref[f][2];
+    for (int fp = K.face_off[f]; fp < K.face_off[f + 1]; ++fp) {
+      T y[5];
 #pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        const T x = l * JM_s[w][v][fp];
-        gt[0][v] += x * K.nref[f][0];
-        gt[1][v] += x * K.nref[f][1];
-        gt[2][v] += x * K.nref[f][2];
+      for (int v = 0; v < 5; ++v) y[v] = JM_s[el][v][fp];
+#pragma unroll
+      for (int k = 0; k < NP; ++k) {
+        const T l = O.Lt[fp * PY_NSP + pts[k]];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+          const T x = l * y[v];
+          gt[k][0][v] += x * n0;
+          gt[k][1][v] += x * n1;
+          gt[k][2][v] += x * n2;
+        }
       }
     }
-    const T iJ = rcp(J);
+  }
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
+    if (r0 + k * ROWS >= PY_NSP) continue;
+    const int pt = pts[k];
 #pragma unroll
     for (int v = 0; v < 5; ++v)
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
-        const T g = (S[0 * 3 + j] * gt[0][v] + S[1 * 3 + j] * gt[1][v] + S[2 * 3 + j] * gt[2][v]) * iJ;
-        G_s[w][v * 3 + j][lane] = g;
-        grad[((int64_t)lane * 15 + v * 3 + j) * E + e] = g;
+        const T g = (S[0 * 3 + j] * gt[k][0][v] + S[1 * 3 + j] * gt[k][1][v] + S[2 * 3 + j] * gt[k][2][v]) * iJ;
+        G_s[el][v * 3 + j][pt] = g;
+        grad[((int64_t)pt * 15 + v * 3 + j) * E + e] = g;
       }
   }
   __syncthreads();
-  for (int fp = lane; fp < PY_NFP; fp += 64) {
-    T acc[15];
+  int fps[NF];
 #pragma unroll
-    for (int k = 0; k < 15; ++k) acc[k] = 0;
-    for (int j = 0; j < PY_NSP; ++j) {
-      const T l = O.It[j * PY_NFP + fp];
+  for (int k = 0; k < NF; ++k) fps[k] = min(r0 + k * ROWS, PY_NFP - 1);
+  T acc[NF][15];
 #pragma unroll
-      for (int k = 0; k < 15; ++k) acc[k] += l * G_s[w][k][j];
+  for (int k = 0; k < NF; ++k)
+#pragma unroll
+    for (int q = 0; q < 15; ++q) acc[k][q] = 0;
+  for (int j = 0; j < PY_NSP; ++j) {
+    T x[15];
+#pragma unroll
+    for (int q = 0; q < 15; ++q) x[q] = G_s[el][q][j];
+#pragma unroll
+    for (int k = 0; k < NF; ++k) {
+      const T l = O.It[j * PY_NFP + fps[k]];
+#pragma unroll
+      for (int q = 0; q < 15; ++q) acc[k][q] += l * x[q];
     }
-#pragma unroll
-    for (int k = 0; k < 15; ++k) gradf[((int64_t)fp * 15 + k) * E + e] = acc[k];
   }
+#pragma unroll
+  for (int k = 0; k < NF; ++k)
+    if (r0 + k * ROWS < PY_NFP)
+#pragma unroll
+      for (int q = 0; q < 15; ++q) gradf[((int64_t)fps[k] * 15 + q) * E + e] = acc[k][q];
 }
 
 // Corrected divergence (Euler, or Navier--Stokes with NS = true), R = -div / J.
 template <typename T, bool DEV, bool NS>
-__global__ void __launch_bounds__(64 * PY_WAVES) pyr_div(const T* __restrict__ u, const T* __restrict__ uf,
-                                                         const T* __restrict__ grad, const T* __restrict__ gradf,
-                                                         const T* __restrict__ geo, Conn C, PyrOpsDev<T> O, PyrK<T> K,
-                                                         T* __restrict__ r, int64_t E, T gamma, T mu, T pr, T beta,
-                                                         T tau, int riemann, RefState<T> R) {
-  __shared__ T F_s[PY_WAVES][3][5][PY_NSP];
-  __shared__ T JM_s[PY_WAVES][5][PY_NFP];
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t e = xcd_block() * PY_WAVES + w;
+__global__ void __launch_bounds__(PY_NT) pyr_div(const T* __restrict__ u, const T* __restrict__ uf,
+                                                 const T* __restrict__ grad, const T* __restrict__ gradf,
+                                                 const T* __restrict__ geo, Conn C, PyrOpsDev<T> O, PyrK<T> K,
+                                                 T* __restrict__ r, int64_t E, T gamma, T mu, T pr, T beta, T tau,
+                                                 int riemann, RefState<T> R) {
+  constexpr int NE = py_ne<T>(), ROWS = PY_NT / NE;
+  __shared__ T F_s[NE][3][5][PY_NSP];
+  __shared__ T JM_s[NE][5][PY_NFP];
+  const int el = threadIdx.x % NE, r0 = threadIdx.x / NE;
+  const int64_t e = xcd_block() * NE + el;
   const T gm1 = gamma - T(1);
   T S[9], J;
   pyr_metric(geo, E, e, S, J);
   // transformed flux f~_i = (S f)_i at the solution points
-  if (lane < PY_NSP) {
+  for (int pt = r0; pt < PY_NSP; pt += ROWS) {
     T wv[5];
 #pragma unroll
-    for (int v = 0; v < 5; ++v) wv[v] = u[((int64_t)lane * 5 + v) * E + e];
+    for (int v = 0; v < 5; ++v) wv[v] = u[((int64_t)pt * 5 + v) * E + e];
     T g[15];
     if constexpr (NS) {
 #pragma unroll
-      for (int k = 0; k < 15; ++k) g[k] = grad[((int64_t)lane * 15 + k) * E + e];
+      for (int k = 0; k < 15; ++k) g[k] = grad[((int64_t)pt * 15 + k) * E + e];
     }
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -209,17 +276,54 @@ __global__ void __launch_bounds__(64 * PY_WAVES) pyr_div(const T* __restrict__ u
         for (int v = 0; v < 5; ++v) f[v] -= fv[v];
       }
 #pragma unroll
-      for (int v = 0; v < 5; ++v) F_s[w][i][v][lane] = f[v];
+      for (int v = 0; v < 5; ++v) F_s[el][i][v][pt] = f[v];
     }
   }
   __syncthreads();
-  // common flux minus the normal trace of f~ at the flux points
-  for (int fp = lane; fp < PY_NFP; fp += 64) {
+  // normal trace of f~ at each of the thread's flux points (every LDS value serves all)
+  constexpr int NP = (PY_NSP + ROWS - 1) / ROWS, NF = (PY_NFP + ROWS - 1) / ROWS;
+  int fps[NF];
+  T nrk[NF][3];
+#pragma unroll
+  for (int k = 0; k < NF; ++k) {
+    fps[k] = min(r0 + k * ROWS, PY_NFP - 1);
+    const int f = pyr_face_of(K.face_off, fps[k]);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) nrk[k][q] = K.nref[0][q];
+#pragma unroll
+    for (int ff = 1; ff < 5; ++ff)
+      if (f == ff)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) nrk[k][q] = K.nref[ff][q];
+  }
+  T fperp[NF][5];
+#pragma unroll
+  for (int k = 0; k < NF; ++k)
+#pragma unroll
+    for (int v = 0; v < 5; ++v) fperp[k][v] = 0;
+  for (int j = 0; j < PY_NSP; ++j) {
+    T x[3][5];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int v = 0; v < 5; ++v) x[i][v] = F_s[el][i][v][j];
+#pragma unroll
+    for (int k = 0; k < NF; ++k) {
+      const T l = O.It[j * PY_NFP + fps[k]];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) fperp[k][v] += l * (nrk[k][0] * x[0][v] + nrk[k][1] * x[1][v] + nrk[k][2] * x[2][v]);
+    }
+  }
+  // common flux along the left side's normal, minus the normal trace
+#pragma unroll
+  for (int k = 0; k < NF; ++k) {
+    if (r0 + k * ROWS >= PY_NFP) continue;
+    const int fp = fps[k];
     int f, fpn;
     int64_t en;
     bool left;
     pyr_partner(C, K, E, e, fp, f, en, fpn, left);
-    const T* nr = K.nref[f];
+    const T* nr = nrk[k];
     T sn[3];
 #pragma unroll
     for (int j = 0; j < 3; ++j) sn[j] = S[0 * 3 + j] * nr[0] + S[1 * 3 + j] * nr[1] + S[2 * 3 + j] * nr[2];
@@ -241,9 +345,9 @@ __global__ void __launch_bounds__(64 * PY_WAVES) pyr_div(const T* __restrict__ u
     if constexpr (NS) {
       T go[15], gn[15];
 #pragma unroll
-      for (int k = 0; k < 15; ++k) {
-        go[k] = gradf[((int64_t)fp * 15 + k) * E + e];
-        gn[k] = gradf[((int64_t)fpn * 15 + k) * E + en];
+      for (int q = 0; q < 15; ++q) {
+        go[q] = gradf[((int64_t)fp * 15 + q) * E + e];
+        gn[q] = gradf[((int64_t)fpn * 15 + q) * E + en];
       }
       T fvL[5], fvR[5];
       viscous<T, DEV>(uL, left ? go : gn, nL[0], nL[1], nL[2], gamma, mu, pr, R, fvL);
@@ -252,35 +356,51 @@ __global__ void __launch_bounds__(64 * PY_WAVES) pyr_div(const T* __restrict__ u
       for (int v = 0; v < 5; ++v)
         Fc[v] -= T(0.5) * (fvL[v] + fvR[v]) - beta * (fvL[v] - fvR[v]) - tau * (uL[v] - uR[v]);
     }
-    T fperp[5] = {0, 0, 0, 0, 0};
-    for (int j = 0; j < PY_NSP; ++j) {
-      const T l = O.It[j * PY_NFP + fp];
 #pragma unroll
-      for (int v = 0; v < 5; ++v)
-        fperp[v] += l * (nr[0] * F_s[w][0][v][j] + nr[1] * F_s[w][1][v][j] + nr[2] * F_s[w][2][v][j]);
-    }
-#pragma unroll
-    for (int v = 0; v < 5; ++v) JM_s[w][v][fp] = mag * sg * Fc[v] - fperp[v];
+    for (int v = 0; v < 5; ++v) JM_s[el][v][fp] = mag * sg * Fc[v] - fperp[k][v];
   }
   __syncthreads();
-  if (lane < PY_NSP) {
-    T div[5] = {0, 0, 0, 0, 0};
-    for (int j = 0; j < PY_NSP; ++j) {
-      const T d0 = O.Dt[(0 * PY_NSP + j) * PY_NSP + lane];
-      const T d1 = O.Dt[(1 * PY_NSP + j) * PY_NSP + lane];
-      const T d2 = O.Dt[(2 * PY_NSP + j) * PY_NSP + lane];
+  // corrected divergence at each of the thread's solution points
+  int pts[NP];
 #pragma unroll
-      for (int v = 0; v < 5; ++v) div[v] += d0 * F_s[w][0][v][j] + d1 * F_s[w][1][v][j] + d2 * F_s[w][2][v][j];
+  for (int k = 0; k < NP; ++k) pts[k] = min(r0 + k * ROWS, PY_NSP - 1);
+  T div[NP][5];
+#pragma unroll
+  for (int k = 0; k < NP; ++k)
+#pragma unroll
+    for (int v = 0; v < 5; ++v) div[k][v] = 0;
+  for (int j = 0; j < PY_NSP; ++j) {
+    T x[3][5];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int v = 0; v < 5; ++v) x[i][v] = F_s[el][i][v][j];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      const T d0 = O.Dt[(0 * PY_NSP + j) * PY_NSP + pts[k]];
+      const T d1 = O.Dt[(1 * PY_NSP + j) * PY_NSP + pts[k]];
+      const T d2 = O.Dt[(2 * PY_NSP + j) * PY_NSP + pts[k]];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) div[k][v] += d0 * x[0][v] + d1 * x[1][v] + d2 * x[2][v];
     }
-    for (int fp = 0; fp < PY_NFP; ++fp) {
-      const T l = O.Lt[fp * PY_NSP + lane];
-#pragma unroll
-      for (int v = 0; v < 5; ++v) div[v] += l * JM_s[w][v][fp];
-    }
-    const T iJ = -rcp(J);
-#pragma unroll
-    for (int v = 0; v < 5; ++v) r[((int64_t)lane * 5 + v) * E + e] = div[v] * iJ;
   }
+  for (int fp = 0; fp < PY_NFP; ++fp) {
+    T y[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) y[v] = JM_s[el][v][fp];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      const T l = O.Lt[fp * PY_NSP + pts[k]];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) div[k][v] += l * y[v];
+    }
+  }
+  const T iJ = -rcp(J);
+#pragma unroll
+  for (int k = 0; k < NP; ++k)
+    if (r0 + k * ROWS < PY_NSP)
+#pragma unroll
+      for (int v = 0; v < 5; ++v) r[((int64_t)pts[k] * 5 + v) * E + e] = div[k][v] * iJ;
 }
 
 }  // namespace frmi

@@ -760,6 +760,7 @@ STATED_RHS_BOUND = {
     ("ns_tgv_mixed_c5split_p4", "bf16x3"): [1.0, 5e-2, 5e-2, 5e-2, 1.0],
     ("ns_tgv_hex32_p3", "fp32"): [5e-3, 5e-4, 5e-4, 5e-4, 5e-3],
     ("ns_tgv_tet32_q4_curved", "fp32"): [5e-2, 2e-3, 2e-3, 2e-3, 5e-2],
+    ("ns_tgv_pyr24_p4", "fp32"): [5e-2, 2e-3, 2e-3, 2e-3, 5e-2],
 }
 
 

@@ -9,7 +9,9 @@
  * points; straight, with metric terms formed from the corners, or curved, with
  * metric terms stored per point as in Sec. "Curved elements") and tetrahedra
  * (order 4, the alpha-optimised points of Fig. mesh; straight, or curved with
- * metric terms stored per solution point), advances it with classical
+ * metric terms stored per solution point), or of pyramids with affine bases (order
+ * 4, Sec. "Mixed elements and domain decomposition"; meshes of pyramids only),
+ * advances it with classical
  * RK4 ("a suitable explicit time integration scheme") or with an adaptive
  * embedded pair (Sec. "Adaptive time stepping"), and applies the entropy-bounded
  * modal filter of Sec. "Numerical Stability" with an optional learned warm start
@@ -28,11 +30,13 @@
  *   for the calling thread when ctx is NULL (e.g. after a failed setup).
  *
  * Canonical state layout (used by fr_pack / fr_unpack and for initial conditions)
- *   FP64, per element type block (hexahedra first, then tetrahedra), elements in
+ *   FP64, per element type block (hexahedra first, then tetrahedra; pyramids alone), elements in
  *   the order they appear in the mesh, [elem][var][sol_pt] with var = (rho, rho u,
  *   rho v, rho w, E).  Hex solution point zeta = i + (p+1)(j + (p+1)k), i along the
  *   first reference axis, Gauss--Legendre nodes increasing.  Tet solution points
- *   in the printed order of Fig. mesh(c).
+ *   in the printed order of Fig. mesh(c).  Pyramid solution points: 5 layers at
+ *   the Gauss--Legendre z nodes (increasing), layer k the (5-k) x (5-k)
+ *   Gauss--Legendre grid scaled by s = (1 - z)/2, x fastest (55 points).
  * Native layout (what fr_rhs / fr_rk_step / fr_filter operate on)
  *   Internal: per type block [sol_pt][var][E_pad] (element fastest), elements in
  *   the native order (see fr_params.elem_order).  Sizes come from fr_layout; do

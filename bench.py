@@ -156,12 +156,13 @@ def kernel_bytes_per_elem(name, nsp, nfp):
         "tet_div_euler": d * (5 * nsp + 5 * nsp) + tet_gc,
         "tet_grad": d * (5 * nsp + 15 * nsp) + tet_gc,
         "tet_div_ns": d * (5 * nsp + 15 * nsp + 5 * nsp) + tet_gc,
-        # pyramids: traces of u stored for every flux point (read by both sides), the gradient
-        # and its traces at every flux point (the LDG gradient two-sided)
+        # pyramids: traces of u stored for every flux point (read by both sides); with the
+        # one-sided switch the gradient traces are stored where the element is the right
+        # side (half of the flux points) and read from there by both sides
         "pyr_trace": d * 5 * (nsp + nfp),
         "pyr_div_euler": d * (5 * nsp + 5 * nfp + 5 * nsp) + pyr_gc,
-        "pyr_grad": d * (5 * nsp + 5 * nfp + 15 * nsp + 15 * nfp) + pyr_gc,
-        "pyr_div_ns": d * (5 * nsp + 15 * nsp + 5 * nfp + 15 * nfp + 5 * nsp) + pyr_gc,
+        "pyr_grad": d * (5 * nsp + 5 * nfp + 15 * nsp + 15 * nfp // 2) + pyr_gc,
+        "pyr_div_ns": d * (5 * nsp + 15 * nsp + 5 * nfp + 15 * nfp // 2 + 5 * nsp) + pyr_gc,
     }
     if d == 4:
         # FP32 form, one-sided LDG: the gradient kernel stores the transformed viscous flux

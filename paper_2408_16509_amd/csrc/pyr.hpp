@@ -120,11 +120,15 @@ __global__ void __launch_bounds__(PY_NT) pyr_trace(const T* __restrict__ u, T* _
 
 // Navier--Stokes gradient (LDG): grad~u = D_i u + lift (n~_i (u^ - u_f)), u^ = (uL + uR)/2
 // + beta (uL - uR); physical grad_j = sum_i S_ij / J grad~_i u.  Writes grad at the
-// solution points and its traces at the flux points.
+// solution points and its traces at the flux points whose viscous common flux reads
+// this side: all of them for side_mode 0, where this element is the right side for
+// side_mode +1 (beta = +1/2: the common viscous flux is the right side's), the left
+// side for -1 (beta = -1/2).
 template <typename T>
 __global__ void __launch_bounds__(PY_NT) pyr_grad(const T* __restrict__ u, const T* __restrict__ uf,
                                                   const T* __restrict__ geo, Conn C, PyrOpsDev<T> O, PyrK<T> K,
-                                                  T* __restrict__ grad, T* __restrict__ gradf, int64_t E, T beta) {
+                                                  T* __restrict__ grad, T* __restrict__ gradf, int64_t E, T beta,
+                                                  int side_mode) {
   constexpr int NE = py_ne<T>(), ROWS = PY_NT / NE;
   __shared__ T U_s[NE][5][PY_NSP];
   __shared__ T JM_s[NE][5][PY_NFP];
@@ -234,10 +238,14 @@ __global__ void __launch_bounds__(PY_NT) pyr_grad(const T* __restrict__ u, const
     }
   }
 #pragma unroll
-  for (int k = 0; k < NF; ++k)
-    if (r0 + k * ROWS < PY_NFP)
+  for (int k = 0; k < NF; ++k) {
+    if (r0 + k * ROWS >= PY_NFP) continue;
+    const int f = pyr_face_of(K.face_off, fps[k]);
+    const bool left = (C.nbr_info[(int64_t)f * E + e] >> 12) & 1;
+    if (side_mode != 0 && (side_mode > 0) == left) continue;      // the partner's trace is the one read
 #pragma unroll
-      for (int q = 0; q < 15; ++q) gradf[((int64_t)fps[k] * 15 + q) * E + e] = acc[k][q];
+    for (int q = 0; q < 15; ++q) gradf[((int64_t)fps[k] * 15 + q) * E + e] = acc[k][q];
+  }
 }
 
 // Corrected divergence (Euler, or Navier--Stokes with NS = true), R = -div / J.
@@ -246,7 +254,7 @@ __global__ void __launch_bounds__(PY_NT) pyr_div(const T* __restrict__ u, const 
                                                  const T* __restrict__ grad, const T* __restrict__ gradf,
                                                  const T* __restrict__ geo, Conn C, PyrOpsDev<T> O, PyrK<T> K,
                                                  T* __restrict__ r, int64_t E, T gamma, T mu, T pr, T beta, T tau,
-                                                 int riemann, RefState<T> R) {
+                                                 int riemann, int side_mode, RefState<T> R) {
   constexpr int NE = py_ne<T>(), ROWS = PY_NT / NE;
   __shared__ T F_s[NE][3][5][PY_NSP];
   __shared__ T JM_s[NE][5][PY_NFP];
@@ -343,18 +351,26 @@ __global__ void __launch_bounds__(PY_NT) pyr_div(const T* __restrict__ u, const 
     T Fc[5];
     common_inviscid<T, DEV>(riemann, uL, uR, nL, gamma, R, Fc);
     if constexpr (NS) {
-      T go[15], gn[15];
+      // viscous common flux (1/2 - beta) f_v(L) + (1/2 + beta) f_v(R); with beta = +-1/2
+      // one side's weight is zero and its gradient trace is neither stored nor read
+      const T wL = T(0.5) - beta, wR = T(0.5) + beta;
+      T fvc[5] = {0, 0, 0, 0, 0};
 #pragma unroll
-      for (int q = 0; q < 15; ++q) {
-        go[q] = gradf[((int64_t)fp * 15 + q) * E + e];
-        gn[q] = gradf[((int64_t)fpn * 15 + q) * E + en];
+      for (int side = 0; side < 2; ++side) {
+        const bool is_left = side == 0;
+        const T wgt = is_left ? wL : wR;
+        if (side_mode != 0 && wgt == T(0)) continue;
+        const bool own = is_left == left;
+        const int64_t gs = own ? (int64_t)fp : (int64_t)fpn, ge = own ? e : en;
+        T g[15], fv[5];
+#pragma unroll
+        for (int q = 0; q < 15; ++q) g[q] = gradf[(gs * 15 + q) * E + ge];
+        viscous<T, DEV>(is_left ? uL : uR, g, nL[0], nL[1], nL[2], gamma, mu, pr, R, fv);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) fvc[v] += wgt * fv[v];
       }
-      T fvL[5], fvR[5];
-      viscous<T, DEV>(uL, left ? go : gn, nL[0], nL[1], nL[2], gamma, mu, pr, R, fvL);
-      viscous<T, DEV>(uR, left ? gn : go, nL[0], nL[1], nL[2], gamma, mu, pr, R, fvR);
 #pragma unroll
-      for (int v = 0; v < 5; ++v)
-        Fc[v] -= T(0.5) * (fvL[v] + fvR[v]) - beta * (fvL[v] - fvR[v]) - tau * (uL[v] - uR[v]);
+      for (int v = 0; v < 5; ++v) Fc[v] += tau * (uL[v] - uR[v]) - fvc[v];
     }
 #pragma unroll
     for (int v = 0; v < 5; ++v) JM_s[el][v][fp] = mag * sg * Fc[v] - fperp[k][v];

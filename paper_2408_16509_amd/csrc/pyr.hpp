@@ -130,14 +130,23 @@ __global__ void __launch_bounds__(PY_NT) pyr_grad(const T* __restrict__ u, const
                                                   T* __restrict__ grad, T* __restrict__ gradf, int64_t E, T beta,
                                                   int side_mode) {
   constexpr int NE = py_ne<T>(), ROWS = PY_NT / NE;
-  __shared__ T U_s[NE][5][PY_NSP];
-  __shared__ T JM_s[NE][5][PY_NFP];
-  __shared__ T G_s[NE][15][PY_NSP];
+  // one LDS tile per element: u (5 x 55) and the LDG jumps (5 x 85), and the physical
+  // gradient (15 x 55).  FP32 overlays the gradient on the first two once every thread has
+  // read them (26 KB per block instead of 49: four waves per SIMD instead of three); FP64,
+  // held to three waves per SIMD by its registers, keeps them apart and saves the barrier.
+  constexpr bool OVERLAY = sizeof(T) == 4;
+  constexpr int GOFF = OVERLAY ? 0 : 5 * PY_NSP + 5 * PY_NFP;
+  __shared__ T W_s[NE][GOFF + 15 * PY_NSP];
+  static_assert(5 * PY_NSP + 5 * PY_NFP <= 15 * PY_NSP, "state and jumps fit in the gradient's tile");
+  T* Wl = W_s[threadIdx.x % NE];
+  auto U_at = [&](int v, int pt) -> T& { return Wl[v * PY_NSP + pt]; };
+  auto JM_at = [&](int v, int fp) -> T& { return Wl[5 * PY_NSP + v * PY_NFP + fp]; };
+  auto G_at = [&](int q, int pt) -> T& { return Wl[GOFF + q * PY_NSP + pt]; };
   const int el = threadIdx.x % NE, r0 = threadIdx.x / NE;
   const int64_t e = xcd_block() * NE + el;
   for (int pt = r0; pt < PY_NSP; pt += ROWS)
 #pragma unroll
-    for (int v = 0; v < 5; ++v) U_s[el][v][pt] = u[((int64_t)pt * 5 + v) * E + e];
+    for (int v = 0; v < 5; ++v) U_at(v, pt) = u[((int64_t)pt * 5 + v) * E + e];
   for (int fp = r0; fp < PY_NFP; fp += ROWS) {
     int f, fpn;
     int64_t en;
@@ -148,7 +157,7 @@ __global__ void __launch_bounds__(PY_NT) pyr_grad(const T* __restrict__ u, const
       const T uo = uf[((int64_t)fp * 5 + v) * E + e];
       const T un = uf[((int64_t)fpn * 5 + v) * E + en];
       const T uL = left ? uo : un, uR = left ? un : uo;
-      JM_s[el][v][fp] = T(0.5) * (uL + uR) + beta * (uL - uR) - uo;
+      JM_at(v, fp) = T(0.5) * (uL + uR) + beta * (uL - uR) - uo;
     }
   }
   T S[9], J;
@@ -170,7 +179,7 @@ __global__ void __launch_bounds__(PY_NT) pyr_grad(const T* __restrict__ u, const
   for (int j = 0; j < PY_NSP; ++j) {
     T x[5];
 #pragma unroll
-    for (int v = 0; v < 5; ++v) x[v] = U_s[el][v][j];
+    for (int v = 0; v < 5; ++v) x[v] = U_at(v, j);
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
       const T d0 = O.Dt[(0 * PY_NSP + j) * PY_NSP + pts[k]];
@@ -184,26 +193,36 @@ __global__ void __launch_bounds__(PY_NT) pyr_grad(const T* __restrict__ u, const
       }
     }
   }
+  // the reference normal is constant over a face: lift the face's jumps, then scale
 #pragma unroll 1
   for (int f = 0; f < 5; ++f) {
-    const T n0 = K.nref[f][0], n1 = K.nref[f][1], n2 = K.nref[f][2];
+    T sf[NP][5];
+#pragma unroll
+    for (int k = 0; k < NP; ++k)
+#pragma unroll
+      for (int v = 0; v < 5; ++v) sf[k][v] = 0;
     for (int fp = K.face_off[f]; fp < K.face_off[f + 1]; ++fp) {
       T y[5];
 #pragma unroll
-      for (int v = 0; v < 5; ++v) y[v] = JM_s[el][v][fp];
+      for (int v = 0; v < 5; ++v) y[v] = JM_at(v, fp);
 #pragma unroll
       for (int k = 0; k < NP; ++k) {
         const T l = O.Lt[fp * PY_NSP + pts[k]];
 #pragma unroll
-        for (int v = 0; v < 5; ++v) {
-          const T x = l * y[v];
-          gt[k][0][v] += x * n0;
-          gt[k][1][v] += x * n1;
-          gt[k][2][v] += x * n2;
-        }
+        for (int v = 0; v < 5; ++v) sf[k][v] += l * y[v];
       }
     }
+    const T n0 = K.nref[f][0], n1 = K.nref[f][1], n2 = K.nref[f][2];
+#pragma unroll
+    for (int k = 0; k < NP; ++k)
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        gt[k][0][v] += n0 * sf[k][v];
+        gt[k][1][v] += n1 * sf[k][v];
+        gt[k][2][v] += n2 * sf[k][v];
+      }
   }
+  if constexpr (OVERLAY) __syncthreads();            // u and the jumps are read: the tile takes grad
 #pragma unroll
   for (int k = 0; k < NP; ++k) {
     if (r0 + k * ROWS >= PY_NSP) continue;
@@ -213,7 +232,7 @@ __global__ void __launch_bounds__(PY_NT) pyr_grad(const T* __restrict__ u, const
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
         const T g = (S[0 * 3 + j] * gt[k][0][v] + S[1 * 3 + j] * gt[k][1][v] + S[2 * 3 + j] * gt[k][2][v]) * iJ;
-        G_s[el][v * 3 + j][pt] = g;
+        G_at(v * 3 + j, pt) = g;
         grad[((int64_t)pt * 15 + v * 3 + j) * E + e] = g;
       }
   }
@@ -229,7 +248,7 @@ __global__ void __launch_bounds__(PY_NT) pyr_grad(const T* __restrict__ u, const
   for (int j = 0; j < PY_NSP; ++j) {
     T x[15];
 #pragma unroll
-    for (int q = 0; q < 15; ++q) x[q] = G_s[el][q][j];
+    for (int q = 0; q < 15; ++q) x[q] = G_at(q, j);
 #pragma unroll
     for (int k = 0; k < NF; ++k) {
       const T l = O.It[j * PY_NFP + fps[k]];

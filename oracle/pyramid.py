@@ -2,8 +2,9 @@
 transition layer between tetrahedra and hexahedra (Sec. "Mixed elements and domain
 decomposition"), supported there only with an affine (parallelogram) base.
 
-TEST INFRASTRUCTURE: only tests/ use it.  Parity unpinned against a GPU path: the
-library has no pyramid; this module is pinned against closed forms only.
+TEST INFRASTRUCTURE: only tests/ use it.  Pinned against closed forms, independent
+quadrature and convergence (tests/test_oracle_pyramid.py); the GPU path's pyramids are
+checked against it.
 
 Reference pyramid: base square [-1, 1]^2 at z = -1, apex (0, 0, 1); corners
 (-1,-1,-1) (1,-1,-1) (1,1,-1) (-1,1,-1) (0,0,1).  Faces: 0 the base (corners 0 1 2 3,

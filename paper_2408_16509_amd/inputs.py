@@ -362,12 +362,15 @@ def _assemble(xyz, blocks, period, meta, permute_seed):
 
 
 def pyramid_box(n=(3, 3, 3), lo=(-math.pi,) * 3, hi=(math.pi,) * 3, apex_perturb=0.0,
-                perturb_seed=None, permute_seed=None) -> Mesh:
+                perturb_seed=None, permute_seed=None, rotate_seed=None) -> Mesh:
     """Periodic box with each of the nx*ny*nz cells cut into 6 pyramids (one per face).
 
     The apex of a cell's pyramids is its centre moved by U(-apex_perturb, apex_perturb) * h
     per coordinate, drawn with PCG64(perturb_seed) in C order of the cells [k][j][i];
     the lattice itself is not perturbed, so every base is an exact parallelogram.
+    rotate_seed: if given, each pyramid's base corners are shifted cyclically by
+    PCG64(rotate_seed).integers(0, 4) places (orientation kept), so that neighbouring
+    faces meet in every relative orientation.
     """
     hx = hex_box(n, lo, hi)
     cells = hx.enodes[:, :8]
@@ -376,6 +379,10 @@ def pyramid_box(n=(3, 3, 3), lo=(-math.pi,) * 3, hi=(math.pi,) * 3, apex_perturb
     apex = hx.xyz.shape[0] + np.arange(cells.shape[0])
     pn = np.concatenate([np.column_stack([cells[:, cyc], apex]) for _, _, cyc in _CELL_FACES])
     pn = _orient_pyr(xyz, pn)
+    if rotate_seed is not None:
+        k = np.random.default_rng(rotate_seed).integers(0, 4, size=pn.shape[0])
+        idx = (np.arange(4)[None, :] + k[:, None]) % 4
+        pn[:, :4] = np.take_along_axis(pn[:, :4], idx, axis=1)
     return _assemble(xyz, [(PYR, pn)], hx.period.copy(),
                      {"n": tuple(n), "h": hx.meta["h"], "kind": "pyramid_box"}, permute_seed)
 

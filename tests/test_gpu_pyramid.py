@@ -37,6 +37,10 @@ MESHES = {
     "pyr222": lambda: inputs.pyramid_box((2, 2, 2)),
     # 108 elements, apexes moved by up to 15 % of a cell, element order permuted
     "pyrpert": lambda: inputs.pyramid_box((3, 3, 2), apex_perturb=0.15, perturb_seed=3, permute_seed=4),
+    # the same with every base's corners shifted cyclically at random: faces meet in five
+    # relative orientations (two above), which exercises the face-point permutations
+    "pyrrot": lambda: inputs.pyramid_box((3, 3, 2), apex_perturb=0.15, perturb_seed=3, permute_seed=4,
+                                         rotate_seed=5),
 }
 
 
@@ -103,6 +107,9 @@ CASES = [
     ("pyrpert", 1, 1, "random"),
     ("pyr222", 1, 0, "tgv"),
     ("pyrpert", 0, 1, "tgv"),
+    ("pyrrot", 0, 1, "random"),
+    ("pyrrot", 1, 0, "random"),
+    ("pyrrot", 1, 1, "tgv"),
 ]
 
 

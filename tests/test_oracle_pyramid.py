@@ -234,6 +234,7 @@ MESHES = {
     "pyramids": lambda: inputs.pyramid_box((2, 2, 2), apex_perturb=0.15, perturb_seed=3, permute_seed=4),
     "transition": lambda: inputs.transition_box((4, 2, 2), apex_perturb=0.15, perturb_seed=3, permute_seed=4),
     "transition_kuhn": lambda: inputs.transition_box((5, 2, 2), n_hex=2),
+    "pyramids_rotated": lambda: inputs.pyramid_box((2, 2, 2), apex_perturb=0.15, perturb_seed=3, rotate_seed=5),
 }
 
 

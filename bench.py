@@ -20,7 +20,9 @@ points that kernel processes; the kernel's own compulsory traffic beside it),
 each reduced form's error against the FP64 form per variable, the FP64 CPU
 oracle timed on the host on a bounded sample of the same workload, and two more
 workloads (the 32^3 p = 3 hexahedral NS TGV, and the 48^3 Mach-3 shock with the
-trained learned filter against the plain one) under "extra_workloads".
+trained learned filter against the plain one) under "extra_workloads".  Other
+workloads by --config (see CONFIGS): curved hexahedra and tetrahedra, adaptive
+stepping, the 48^3 perturbed p = 4 hexahedra, and p = 4 pyramids (ns_tgv_pyr24_p4).
 """
 from __future__ import annotations
 

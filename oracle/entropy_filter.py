@@ -30,7 +30,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from .elements import HEX
+from .elements import HEX, PYR
 from .fr import gather
 
 
@@ -50,6 +50,10 @@ def order_of(b):
 
 def sigma_exponent(b):
     """Per-mode exponent e_k with sigma_k = exp(-zeta e_k)."""
+    if b.etype == PYR:
+        # the filter's modal form is read for hexahedra and tetrahedra only; the pyramid's
+        # basis is not normalised and no reading of its modal grading is pinned
+        raise NotImplementedError("the entropy filter has no pyramid form")
     p = order_of(b)
     if b.etype == HEX:
         d = b.ops.modal_deg
@@ -180,6 +184,8 @@ def filter_block(b, u, smin, fp: FilterParams, khat=None):
 
 def entropy_filter(blocks, u, u_prev, fp: FilterParams = FilterParams(), khat=None):
     """Filter all blocks; returns (u_new list, k list, evals list)."""
+    if any(b.etype == PYR for b in blocks):
+        raise NotImplementedError("the entropy filter has no pyramid form")
     smin = smin_neighbourhood(blocks, u_prev, fp)
     res = [filter_block(b, ub, sm, fp, None if khat is None else khat[i])
            for i, (b, ub, sm) in enumerate(zip(blocks, u, smin))]
@@ -190,6 +196,8 @@ def entropy_filter(blocks, u, u_prev, fp: FilterParams = FilterParams(), khat=No
 
 def features(b, u, smin, fp: FilterParams):
     """16 per-element features (FP64) of states u [n][5][nsp]."""
+    if b.etype == PYR:
+        raise NotImplementedError("the entropy filter has no pyramid form")
     g = fp.gamma
     V = b.ops.modal_V
     Vi = np.linalg.inv(V)

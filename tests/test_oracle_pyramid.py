@@ -358,6 +358,14 @@ def test_corrected_gradient_exact_for_polynomials(kind):
     assert checked >= 8
 
 
+def test_filter_refuses_pyramids():
+    from oracle import entropy_filter as ef
+    bl = mesh.build(inputs.pyramid_box((2, 2, 2)), 4)
+    u = [np.broadcast_to(np.array([1.0, 0, 0, 0, 2.5])[None, :, None], (len(bl[0].elems), 5, 55)).copy()]
+    with pytest.raises(NotImplementedError):
+        ef.entropy_filter(bl, u, u)
+
+
 def test_mesh_errors():
     m = inputs.pyramid_box((2, 2, 2))
     m.xyz = m.xyz.copy()

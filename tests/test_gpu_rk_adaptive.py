@@ -12,7 +12,8 @@ within 1e-4 of the oracle's.
 
 Problem: Euler Taylor--Green vortex at Mach 0.3 on 4^3 hexahedra, p = 3, to t = 0.2
 from dt0 = 0.02 (atol = rtol = 1e-6: the first step is rejected) and from dt0 = 0.1
-(atol = rtol = 1e-7: three rejections); a mixed hexahedral + tetrahedral context.
+(atol = rtol = 1e-7: three rejections); a mixed hexahedral + tetrahedral context; a
+context of p = 4 pyramids (two rejections).
 """
 import numpy as np
 import pytest
@@ -58,9 +59,11 @@ def _run(mesh, order, u0, t_end, dt0, tol, **kw):
     ("hex444", 3, 0.2, 0.02, 1e-6),
     ("hex444", 3, 0.2, 0.1, 1e-7),
     ("mixed", 4, 0.1, 0.02, 1e-6),
+    ("pyramids", 4, 0.1, 0.02, 1e-6),
 ])
 def test_adaptive_fp64_matches_oracle(mname, order, t_end, dt0, tol):
-    mesh = inputs.hex_box((4, 4, 4)) if mname == "hex444" else _mixed()
+    mesh = {"hex444": lambda: inputs.hex_box((4, 4, 4)), "mixed": _mixed,
+            "pyramids": lambda: inputs.pyramid_box((2, 2, 2), apex_perturb=0.1, perturb_seed=3, permute_seed=4)}[mname]()
     bl, u0 = _case(mesh, order)
     prm = ofr.Params(system=0, riemann=0)
     uo, so = ra.integrate(lambda s: ofr.rhs(bl, s, prm), u0, t_end, dt0, ra.Controller(atol=tol, rtol=tol))

@@ -176,6 +176,9 @@ __global__ void __launch_bounds__(PY_NT) pyr_grad(const T* __restrict__ u, const
     for (int i = 0; i < 3; ++i)
 #pragma unroll
       for (int v = 0; v < 5; ++v) gt[k][i][v] = 0;
+  // unrolled by 5: the operator loads of five steps in flight together (measured: FP32
+  // 0.84 -> 0.70 ms per launch; the same in the divergence was slower)
+#pragma unroll 5
   for (int j = 0; j < PY_NSP; ++j) {
     T x[5];
 #pragma unroll

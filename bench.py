@@ -19,8 +19,9 @@ algorithmic minimum of the right-hand side, read u and write R once, for the
 points that kernel processes; the kernel's own compulsory traffic beside it),
 each reduced form's error against the FP64 form per variable, the FP64 CPU
 oracle timed on the host on a bounded sample of the same workload, and two more
-workloads (the 32^3 p = 3 hexahedral NS TGV, and the 48^3 Mach-3 shock with the
-trained learned filter against the plain one) under "extra_workloads".  Other
+workloads (the 32^3 p = 3 hexahedral NS TGV, the NS TGV on 82,944 p = 4 pyramids, and
+the 48^3 Mach-3 shock with the trained learned filter against the plain one) under
+"extra_workloads".  Other
 workloads by --config (see CONFIGS): curved hexahedra and tetrahedra, adaptive
 stepping, the 48^3 perturbed p = 4 hexahedra, and p = 4 pyramids (ns_tgv_pyr24_p4).
 """
@@ -779,7 +780,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the extra workloads of the default run (32^3 p=3 hexahedra, 48^3 shock)")
+                    help="skip the extra workloads of the default run (32^3 p=3 hexahedra, pyramids, 48^3 shock)")
     ap.add_argument("--stream-probe", action="store_true",
                     help="only measure the HBM streaming ceiling: read-only, write-only, copy and 2:1 passes "
                          "(hand-written kernels in libfrprobe.so, 1 GiB buffers, several grid sizes)")
@@ -859,6 +860,8 @@ def main():
         c2 = CONFIGS["ns_tgv_hex32_p3"]
         extras["ns_tgv_hex32_p3"] = run_tgv_workload("ns_tgv_hex32_p3", c2, ["fp32", "fp64"], sub, torch, np,
                                                      frmi, inputs, with_cpu=False)[0]
+        extras["ns_tgv_pyr24_p4"] = run_tgv_workload("ns_tgv_pyr24_p4", CONFIGS["ns_tgv_pyr24_p4"], ["fp32", "fp64"],
+                                                     sub, torch, np, frmi, inputs, with_cpu=False)[0]
         sub.config = "euler_shock_hex48_p3"          # the workload the traffic records are keyed by
         extras["euler_shock_hex48_p3"] = run_filter_workload(CONFIGS["euler_shock_hex48_p3"], sub, torch, np,
                                                              frmi, inputs)

@@ -596,13 +596,13 @@ fr_status pyr_rhs(fr_ctx c, DevBlock& b, const T* u, T* r) {
   if (b.E % 64 != 0) return fail(c, FR_ERR_STATE, "pyramid block not padded to 64 elements");
   const unsigned nblk = (unsigned)(b.E / py_ne<T>());
   int pk = c->prof_begin(("pyr_trace" + sfx).c_str());
-  pyr_trace<T><<<nblk, PY_NT, 0, c->stream>>>(u, uf, b.E, O.It);
+  pyr_trace<T><<<nblk, py_nt<T>(), 0, c->stream>>>(u, uf, b.E, O.It);
   c->prof_end(pk);
   const T gam = (T)p.gamma, mu = (T)p.mu, pr = (T)p.prandtl, beta = (T)p.ldg_beta, tau = (T)p.ldg_tau;
   const int sm = side_mode_of(p.ldg_beta);
   if (p.system == FR_EULER) {
     pk = c->prof_begin(("pyr_div_euler" + sfx).c_str());
-    pyr_div<T, DEV, false><<<nblk, PY_NT, 0, c->stream>>>(u, uf, nullptr, nullptr, geo, C, O, K, r, b.E, gam,
+    pyr_div<T, DEV, false><<<nblk, py_nt<T>(), 0, c->stream>>>(u, uf, nullptr, nullptr, geo, C, O, K, r, b.E, gam,
                                                                     mu, pr, beta, tau, p.riemann, 0, R);
     c->prof_end(pk);
   } else {
@@ -612,7 +612,7 @@ fr_status pyr_rhs(fr_ctx c, DevBlock& b, const T* u, T* r) {
     pyr_grad<T><<<nblk, PY_NT, 0, c->stream>>>(u, uf, geo, C, O, K, grad, gradf, b.E, beta, sm);
     c->prof_end(pk);
     pk = c->prof_begin(("pyr_div_ns" + sfx).c_str());
-    pyr_div<T, DEV, true><<<nblk, PY_NT, 0, c->stream>>>(u, uf, grad, gradf, geo, C, O, K, r, b.E, gam, mu,
+    pyr_div<T, DEV, true><<<nblk, py_nt<T>(), 0, c->stream>>>(u, uf, grad, gradf, geo, C, O, K, r, b.E, gam, mu,
                                                                    pr, beta, tau, p.riemann, sm, R);
     c->prof_end(pk);
   }

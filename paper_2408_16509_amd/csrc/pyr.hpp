@@ -76,12 +76,17 @@ __device__ __forceinline__ void pyr_metric(const T* __restrict__ geo, int64_t E,
 constexpr int PY_NT = 256;
 template <typename T>
 constexpr int py_ne() { return sizeof(T) == 8 ? 4 : 8; }
+// threads per block of the trace and divergence kernels: FP64 takes 128 (two solution
+// points and three flux points per thread, as FP32 at 256: measured faster for FP64,
+// slower for FP32); the gradient kernel takes PY_NT for both
+template <typename T>
+constexpr int py_nt() { return sizeof(T) == 8 ? 128 : PY_NT; }
 
 // Step 1 (eq:disu): traces of u at the flux points.
 template <typename T>
-__global__ void __launch_bounds__(PY_NT) pyr_trace(const T* __restrict__ u, T* __restrict__ uf, int64_t E,
+__global__ void __launch_bounds__(py_nt<T>()) pyr_trace(const T* __restrict__ u, T* __restrict__ uf, int64_t E,
                                                    const T* __restrict__ It) {
-  constexpr int NE = py_ne<T>(), ROWS = PY_NT / NE;
+  constexpr int NE = py_ne<T>(), ROWS = py_nt<T>() / NE;
   __shared__ T U_s[NE][5][PY_NSP];
   const int el = threadIdx.x % NE, r0 = threadIdx.x / NE;
   const int64_t e = xcd_block() * NE + el;
@@ -272,12 +277,12 @@ __global__ void __launch_bounds__(PY_NT) pyr_grad(const T* __restrict__ u, const
 
 // Corrected divergence (Euler, or Navier--Stokes with NS = true), R = -div / J.
 template <typename T, bool DEV, bool NS>
-__global__ void __launch_bounds__(PY_NT) pyr_div(const T* __restrict__ u, const T* __restrict__ uf,
+__global__ void __launch_bounds__(py_nt<T>()) pyr_div(const T* __restrict__ u, const T* __restrict__ uf,
                                                  const T* __restrict__ grad, const T* __restrict__ gradf,
                                                  const T* __restrict__ geo, Conn C, PyrOpsDev<T> O, PyrK<T> K,
                                                  T* __restrict__ r, int64_t E, T gamma, T mu, T pr, T beta, T tau,
                                                  int riemann, int side_mode, RefState<T> R) {
-  constexpr int NE = py_ne<T>(), ROWS = PY_NT / NE;
+  constexpr int NE = py_ne<T>(), ROWS = py_nt<T>() / NE;
   __shared__ T F_s[NE][3][5][PY_NSP];
   __shared__ T JM_s[NE][5][PY_NFP];
   const int el = threadIdx.x % NE, r0 = threadIdx.x / NE;
